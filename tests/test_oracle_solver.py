@@ -1,0 +1,128 @@
+"""Pins of the oracle's LASSO, local ascent/descent, pruning and SFW/BSFW loop. CPU only."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_05473_amd import synth
+
+
+def _columns_problem(seed, k, shape=(16, 16, 16)):
+    rng = np.random.default_rng(seed)
+    psf = synth.gaussian_psf(1.0, 1.5, (9, 7, 7))
+    thetas = synth.random_atoms(rng, k, shape, margin=3.0)[:, 1:6]
+    truth_w = rng.uniform(0.2, 1.5, size=k)
+    A = oracle.lasso_columns(shape, thetas, psf)
+    y = (truth_w @ A).reshape(shape) + 0.05 * rng.standard_normal(shape)
+    return y, psf, thetas, A
+
+
+def test_lasso_single_column_closed_form():
+    y, psf, thetas, A = _columns_problem(20, 1)
+    for lam in (0.01, 0.5, 1e6):
+        w, G, b = oracle.lasso_weights(y, thetas, psf, lam)
+        a = A[0]
+        want = max(0.0, (a @ y.reshape(-1) - lam) / (a @ a))
+        assert w[0] == pytest.approx(want, rel=1e-10, abs=1e-14)
+
+
+@pytest.mark.parametrize("seed,k,lam", [(21, 5, 0.3), (22, 7, 2.0), (23, 4, 0.05)])
+def test_lasso_kkt_and_support_enumeration(seed, k, lam):
+    """The unique minimiser is the only support whose KKT system is feasible."""
+    y, psf, thetas, A = _columns_problem(seed, k)
+    w, G, b = oracle.lasso_weights(y, thetas, psf, lam)
+    grad = G @ w - b + lam
+    scale = np.abs(b).max()
+    on = w > 0
+    assert np.all(np.abs(grad[on]) <= 1e-9 * scale)
+    assert np.all(grad[~on] >= -1e-9 * scale)
+    feasible = []
+    for bits in itertools.product([0, 1], repeat=k):
+        S = np.array(bits, dtype=bool)
+        wS = np.zeros(k)
+        if S.any():
+            wS[S] = np.linalg.solve(G[np.ix_(S, S)], b[S] - lam)
+            if np.any(wS[S] <= 0):
+                continue
+        gS = G @ wS - b + lam
+        if np.all(gS[~S] >= -1e-9 * scale):
+            feasible.append(wS)
+    assert len(feasible) == 1
+    np.testing.assert_allclose(w, feasible[0], rtol=1e-8, atol=1e-12)
+
+
+def test_prune_threshold():
+    a = np.array([[1.0, 0, 0, 0, 1, 2], [0.0, 1, 1, 1, 1, 2], [5e-7, 2, 2, 2, 1, 2], [2e-6, 3, 3, 3, 1, 2]])
+    p = oracle.prune(a)
+    np.testing.assert_array_equal(p[:, 1], [0, 3])
+    assert oracle.prune(np.zeros((0, 6))).shape == (0, 6)
+
+
+def _c1_like(seed=1000, noise=True, n_atoms=None):
+    prob = synth.draw_problem("c1", seed - 1000)
+    atoms = prob.atoms_true if n_atoms is None else prob.atoms_true[:n_atoms]
+    clean = oracle.blur(oracle.render(prob.shape, atoms), prob.psf)
+    y = synth.make_observation(clean, prob.noise_unit, prob.config.noise_rel if noise else 0.0)
+    lam = prob.config.lambda_rel * oracle.max_grid_certificate(y, prob.psf, prob.config.sigma_grid,
+                                                               prob.config.d_grid)
+    return prob, atoms, y, lam
+
+
+def test_ascent_reaches_stationary_point():
+    prob, atoms, y, lam = _c1_like()
+    q = oracle.adjoint(y, prob.psf)
+    eta = oracle.grid_certificate(q, lam, prob.config.sigma_grid, prob.config.d_grid)
+    _, (i, j, z, yy, x) = oracle.grid_argmax(eta)
+    th0 = np.array([x, yy, z, prob.config.sigma_grid[i], prob.config.d_grid[j]], float)
+    th, e = oracle.ascent(q, lam, th0, y.shape, prob.bounds)
+    e0, _ = oracle.eta_point(q, lam, th0)
+    assert e >= e0
+    _, g = oracle.eta_point(q, lam, th)
+    lo = np.array([0, 0, 0, prob.bounds["sigma"][0], prob.bounds["d"][0]])
+    hi = np.array([31, 31, 31, prob.bounds["sigma"][1], prob.bounds["d"][1]])
+    pg = np.where((th <= lo + 1e-9) & (g < 0), 0.0, g)  # projected gradient of an ascent
+    pg = np.where((th >= hi - 1e-9) & (pg > 0), 0.0, pg)
+    assert np.max(np.abs(pg)) <= 1e-4 * e
+
+
+def test_slide_decreases_criterion_to_stationary_point():
+    prob, truth, y, lam = _c1_like()
+    start = synth.perturb(truth, 1000)
+    C0, _ = oracle.criterion(y, start, prob.psf, lam)
+    out = oracle.slide(y, start, prob.psf, lam, prob.bounds)
+    C1, g, _, _ = oracle.criterion_and_grad(y, out, prob.psf, lam)
+    assert C1 < C0
+    nz, ny, nx = y.shape
+    lo = np.array([0.0, 0, 0, 0, prob.bounds["sigma"][0], prob.bounds["d"][0]])
+    hi = np.array([np.inf, nx - 1, ny - 1, nz - 1, prob.bounds["sigma"][1], prob.bounds["d"][1]])
+    pg = np.where((out <= lo + 1e-9) & (g > 0), 0.0, g)  # projected gradient of a descent
+    pg = np.where((out >= hi - 1e-9) & (pg < 0), 0.0, pg)
+    assert np.max(np.abs(pg)) <= 1e-4 * C1
+
+
+@pytest.mark.slow
+def test_bsfw_noiseless_exact_recovery_c1():
+    """Tiny noiseless volume: exactly N atoms, centres within 0.05 voxel of the truth."""
+    prob, truth, y, lam = _c1_like(noise=False)
+    res = oracle.solve(y, prob.psf, lam, prob.config.sigma_grid, prob.config.d_grid, prob.bounds, mode="BSFW")
+    assert res.converged
+    assert res.atoms.shape[0] == truth.shape[0]
+    for t in truth:
+        dist = np.min(np.linalg.norm(res.atoms[:, 1:4] - t[1:4], axis=1))
+        assert dist <= 0.05
+    Cs = [h["C"] for h in res.history] + [res.criterion]
+    assert all(b <= a + 1e-9 * abs(a) for a, b in zip(Cs, Cs[1:]))  # C never increases
+
+
+@pytest.mark.slow
+def test_sfw_and_bsfw_reach_same_criterion_c1():
+    """BSFW reaches almost exactly the criterion of SFW (section 3) on a noisy c1 volume."""
+    prob, truth, y, lam = _c1_like(noise=True)
+    rb = oracle.solve(y, prob.psf, lam, prob.config.sigma_grid, prob.config.d_grid, prob.bounds, mode="BSFW")
+    rs = oracle.solve(y, prob.psf, lam, prob.config.sigma_grid, prob.config.d_grid, prob.bounds, mode="SFW")
+    assert rb.converged and rs.converged
+    assert abs(rb.criterion - rs.criterion) <= 1e-3 * rs.criterion
+    assert rb.atoms.shape[0] == rs.atoms.shape[0] == truth.shape[0]
+    # SFW needs exactly K steps to add K atoms (plus the stopping iteration)
+    assert rs.iterations == truth.shape[0] + 1
