@@ -1,0 +1,188 @@
+/*
+ * sfw.h -- C ABI of the MI355X (gfx950) hot path of the boosted Sliding
+ * Frank-Wolfe solver for gridless 3D deconvolution (Courbot & Colicchio,
+ * "Boosting the Sliding Frank-Wolfe solver for 3D deconvolution",
+ * arXiv:2009.05473).
+ *
+ * Problem (section 1.1): y = H * sum_n G(theta_n, w_n) + eps with atoms
+ *   G(theta, w; s) = w exp(-||m - s||^d / (2 sigma^d)),  theta = (m, sigma, d),
+ * and the criterion (section 1.2)
+ *   C(y, mu, lambda) = 1/2 ||y - Phi mu||^2 + lambda sum_n w_n.
+ *
+ * Conventions shared by every entry point:
+ *   - A volume is float32, C order [nz][ny][nx] (x fastest); voxel centres
+ *     sit at integer coordinates with unit spacing on every axis.
+ *   - The PSF H is float32 [pz][py][px], every size odd, centred at
+ *     ((px-1)/2, (py-1)/2, (pz-1)/2). The library never normalises it.
+ *   - H * f is the zero-padded linear convolution whose output lies on the
+ *     volume grid; Phi^T is its exact adjoint (correlation with H).
+ *   - An atom is sfw_atom (w, mx, my, mz, sigma, d) in voxel units; the
+ *     gradient of C uses the same struct, each field holding dC/d(field).
+ *   - Unless stated otherwise every pointer is DEVICE memory owned by the
+ *     caller. The library never frees caller memory.
+ *   - Operator calls enqueue on the workspace stream and return without a
+ *     host synchronisation; the caller keeps inputs alive until the stream
+ *     reaches that point. sfw_lasso_weights and sfw_solve synchronise.
+ *   - Every call returns an int status (SFW_OK or a negative SFW_E* code).
+ *     On error, sfw_last_error() returns a message for the calling thread.
+ *     No C++ exception crosses this interface. Calls that share a workspace
+ *     must not overlap; distinct workspaces are independent.
+ */
+#ifndef SFW_H
+#define SFW_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SFW_OK = 0,
+  SFW_EINVAL = -1,  /* invalid argument: null required pointer, dims <= 0, even PSF dims,
+                       lambda <= 0 or not finite, n < 0, n > max_atoms, sizes above the
+                       workspace maxima, sigma <= 0 or d <= 0, non-finite y or H (sfw_solve) */
+  SFW_ENOMEM = -2,  /* device or host allocation failed (workspace creation only) */
+  SFW_EHIP = -3,    /* a HIP runtime call failed; the message names it */
+  SFW_ECAP = -4,    /* sfw_solve: more atoms than cap; *n_out holds the needed size */
+  SFW_ENOCONV = -5  /* sfw_solve: iteration cap reached; best measure so far is returned */
+};
+
+enum { SFW_MODE_BSFW = 0, SFW_MODE_SFW = 1 };
+
+#define SFW_MAX_GRID 16
+
+typedef struct { int32_t nx, ny, nz; } sfw_dims;
+
+typedef struct { float w, mx, my, mz, sigma, d; } sfw_atom;
+
+/* Maximum of the grid certificate: value, grid indices (sigma, d) and voxel. */
+typedef struct { float eta; int32_t i_sigma, i_d, x, y, z; } sfw_argmax;
+
+typedef struct sfw_workspace sfw_workspace;
+
+/* Solver options (host memory). sfw_default_options fills the defaults. */
+typedef struct {
+  int32_t mode;                      /* SFW_MODE_BSFW (default) or SFW_MODE_SFW */
+  int32_t n_sigma, n_d;              /* candidate grid sizes (<= SFW_MAX_GRID each) */
+  float sigma_grid[SFW_MAX_GRID];    /* default linspace(1, 2, 4) */
+  float d_grid[SFW_MAX_GRID];        /* default {1.5, 2, 2.5} */
+  float sigma_lo, sigma_hi;          /* box of the domain for sigma, default [0.5, 4] */
+  float d_lo, d_hi;                  /* box for d, default [1.2, 3]; centres are boxed
+                                        to [0, n-1] on each axis */
+  float trunc_T;                     /* grid kernels keep g >= exp(-T) cube, default 12 */
+  double eta_tol;                    /* continue while eta* > 1 + eta_tol, default 1e-3 */
+  double prune_rel;                  /* drop w <= prune_rel * max w, default 1e-6 */
+  double merge_tol;                  /* fuse masses closer than this per coordinate, 2e-2 */
+  int32_t max_iter;                  /* outer iterations, default 200 */
+  int32_t ascent_max_iter;           /* default 200 */
+  int32_t slide_max_iter;            /* default 1000 */
+  double ascent_gtol, slide_gtol;    /* projected-gradient tolerances, default 1e-9 */
+  double ftol;                       /* relative decrease tolerance, default 1e-12 */
+  int32_t lbfgs_memory;              /* curvature pairs kept, default 10 */
+  int32_t check_finite;              /* reject NaN/Inf in y and H, default 1 */
+  int32_t verbose;                   /* print one line per iteration to stderr */
+} sfw_options;
+
+/* Per-solve statistics (host memory). */
+typedef struct {
+  int32_t iterations;        /* outer iterations run */
+  int32_t converged;         /* 1 if stopped on eta* <= 1 + eta_tol */
+  int32_t n_atoms;           /* atoms in the returned measure */
+  int32_t n_eval_cgrad;      /* evaluations of (C, grad C) */
+  int32_t n_eval_eta;        /* evaluations of (eta, grad eta) at a point */
+  int32_t n_certificates;    /* grid certificates computed */
+  int32_t max_support;       /* largest support size reached */
+  double criterion;          /* C of the returned measure */
+  double last_eta;           /* eta* of the last iteration */
+  double seconds_total, seconds_certificate, seconds_ascent, seconds_lasso, seconds_slide;
+} sfw_stats;
+
+/* ---------------------------------------------------------------- lifecycle */
+
+/* Fill *opts with the defaults listed above. opts: host. */
+int sfw_default_options(sfw_options* opts);
+
+/* Create a workspace on the current HIP device for volumes up to vol_max voxels per axis,
+ * PSFs up to psf_max taps per axis and up to max_atoms atoms. All scratch (rendered
+ * volume, residual, adjoint, reduction partials, lookup tables, LASSO columns) is
+ * allocated here once; hot calls allocate nothing. stream: the stream every call of this
+ * workspace enqueues on (0 = the null stream). */
+int sfw_workspace_create(sfw_workspace** ws, sfw_dims vol_max, sfw_dims psf_max,
+                         int max_atoms, hipStream_t stream);
+void sfw_workspace_destroy(sfw_workspace* ws);
+/* Re-point the workspace at another stream of the same device. */
+int sfw_workspace_set_stream(sfw_workspace* ws, hipStream_t stream);
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char* sfw_last_error(void);
+
+/* ---------------------------------------------------------------- operators */
+
+/* Forward model (section 1.1, observation model): phi_mu = H * sum_n w_n g(theta_n),
+ * every atom rendered over every voxel with no truncation.
+ * atoms: device [n]; phi_mu: device [V] or NULL (result kept in the workspace). */
+int sfw_forward(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
+                const sfw_atom* atoms, int n, float* phi_mu);
+
+/* Criterion and its analytic gradient (section 1.2 criterion; section 2 analytic
+ * gradient): r = y - Phi mu, loss = 1/2 sum r^2 + lambda sum w (float64),
+ * grad[n] = dC/d(w, mx, my, mz, sigma, d) of every atom.
+ * y: device [V]; r_out: device [V] or NULL; loss_out: device double [1] or NULL;
+ * grad_out: device [n] or NULL. n may be 0 (then r = y). */
+int sfw_residual_grad(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
+                      const float* y, float lambda, const sfw_atom* atoms, int n,
+                      float* r_out, double* loss_out, sfw_atom* grad_out);
+
+/* Volume adjoint Phi^T on a volume (section 1.2, certificate): q = correlation of r with H.
+ * r: device [V]; q_out: device [V]. */
+int sfw_adjoint(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
+                const float* r, float* q_out);
+
+/* Grid certificate and its maximum (section 1.3 step 1, lookup table of section 2):
+ * eta_ij(m) = (1/lambda) sum_{||t||_inf <= R_ij} g(t; 0, sigma_i, d_j) q(m + t),
+ * q = Phi^T r, R_ij = ceil(sigma_i (2T)^(1/d_j)), T = trunc_T (<= 0 selects 12),
+ * for every voxel centre m. best_out: the maximum of eta (not |eta|) over
+ * (i, j, z, y, x); ties go to the lowest C-order flat index.
+ * r: device [V]; sigma_grid, d_grid: HOST float [ns], [nd] (ns, nd <= SFW_MAX_GRID);
+ * eta_out: device [ns][nd][nz][ny][nx] or NULL; best_out: device [1] or NULL. */
+int sfw_certificate(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
+                    const float* r, float lambda, const float* sigma_grid, int ns,
+                    const float* d_grid, int nd, float trunc_T, float* eta_out,
+                    sfw_argmax* best_out);
+
+/* Certificate at points of the domain and its gradient (section 1.3 step 1, local ascent):
+ * eta(theta) = (1/lambda) sum_s g(s; theta) q(s) with q = Phi^T r from the last
+ * sfw_residual_grad / sfw_adjoint / sfw_certificate call on this workspace (or the
+ * q passed here when not NULL), untruncated.
+ * thetas: HOST float [n][5] = (mx, my, mz, sigma, d); eta_out: HOST double [n];
+ * grad_out: HOST double [n][5] or NULL. Synchronises the stream. */
+int sfw_eta_points(sfw_workspace* ws, sfw_dims vol, const float* q, float lambda,
+                   const float* thetas, int n, double* eta_out, double* grad_out);
+
+/* Weights-only LASSO (section 1.3 step 3): w = argmin_{w >= 0} 1/2 ||y - sum w_n a_n||^2
+ * + lambda sum w_n, a_n = H * g(theta_n) (unit weight). The Gram matrix and A^T y are
+ * accumulated in float64 on the GPU; the non-negative quadratic program is solved in
+ * float64 on the host by an active-set method. The atoms' w fields are ignored.
+ * atoms: device [n]; w_out: device double [n]. Synchronises the stream. */
+int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
+                      const float* y, float lambda, const sfw_atom* atoms, int n,
+                      double* w_out);
+
+/* ---------------------------------------------------------------- solver */
+
+/* SFW (algorithm 1) or BSFW (algorithm 2) from mu = 0: estimate N and the atoms knowing
+ * only y, H and lambda (section 1.1, problem statement).
+ * y, H: device; opts: HOST or NULL (defaults); atoms_out: HOST [cap]; n_out: HOST;
+ * stats: HOST or NULL. Returns SFW_OK, SFW_ENOCONV (cap on iterations, result still
+ * written), SFW_ECAP (more than cap atoms; *n_out = needed) or an error. */
+int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const float* H,
+              sfw_dims psf, float lambda, const sfw_options* opts, sfw_atom* atoms_out,
+              int cap, int* n_out, sfw_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFW_H */

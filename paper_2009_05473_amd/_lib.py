@@ -1,0 +1,293 @@
+"""ctypes binding of libsfw (include/sfw.h): argument marshalling only.
+
+Every entry point of the C ABI is exposed under the same name. Volumes, PSFs and atom
+arrays are torch tensors on the GPU (float32, contiguous); torch supplies device memory
+and the current HIP stream, all arithmetic runs in libsfw's kernels. There is no CPU
+fallback: importing this module without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfw.so")
+
+SFW_OK, SFW_EINVAL, SFW_ENOMEM, SFW_EHIP, SFW_ECAP, SFW_ENOCONV = 0, -1, -2, -3, -4, -5
+SFW_MODE_BSFW, SFW_MODE_SFW = 0, 1
+SFW_MAX_GRID = 16
+
+EXPORTED = (
+    "sfw_default_options", "sfw_workspace_create", "sfw_workspace_destroy",
+    "sfw_workspace_set_stream", "sfw_last_error", "sfw_forward", "sfw_residual_grad",
+    "sfw_adjoint", "sfw_certificate", "sfw_eta_points", "sfw_lasso_weights", "sfw_solve",
+)
+
+
+class SfwDims(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class SfwAtom(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in ("w", "mx", "my", "mz", "sigma", "d")]
+
+
+class SfwArgmax(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_float), ("i_sigma", ctypes.c_int32), ("i_d", ctypes.c_int32),
+                ("x", ctypes.c_int32), ("y", ctypes.c_int32), ("z", ctypes.c_int32)]
+
+
+class SfwOptions(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int32), ("n_sigma", ctypes.c_int32), ("n_d", ctypes.c_int32),
+        ("sigma_grid", ctypes.c_float * SFW_MAX_GRID), ("d_grid", ctypes.c_float * SFW_MAX_GRID),
+        ("sigma_lo", ctypes.c_float), ("sigma_hi", ctypes.c_float),
+        ("d_lo", ctypes.c_float), ("d_hi", ctypes.c_float), ("trunc_T", ctypes.c_float),
+        ("eta_tol", ctypes.c_double), ("prune_rel", ctypes.c_double), ("merge_tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32), ("ascent_max_iter", ctypes.c_int32),
+        ("slide_max_iter", ctypes.c_int32), ("ascent_gtol", ctypes.c_double),
+        ("slide_gtol", ctypes.c_double), ("ftol", ctypes.c_double),
+        ("lbfgs_memory", ctypes.c_int32), ("check_finite", ctypes.c_int32),
+        ("verbose", ctypes.c_int32),
+    ]
+
+
+class SfwStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("n_atoms", ctypes.c_int32),
+        ("n_eval_cgrad", ctypes.c_int32), ("n_eval_eta", ctypes.c_int32),
+        ("n_certificates", ctypes.c_int32), ("max_support", ctypes.c_int32),
+        ("criterion", ctypes.c_double), ("last_eta", ctypes.c_double),
+        ("seconds_total", ctypes.c_double), ("seconds_certificate", ctypes.c_double),
+        ("seconds_ascent", ctypes.c_double), ("seconds_lasso", ctypes.c_double),
+        ("seconds_slide", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SfwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libsfw error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
+    D = SfwDims
+    sig = {
+        "sfw_default_options": (i32, [ctypes.POINTER(SfwOptions)]),
+        "sfw_workspace_create": (i32, [ctypes.POINTER(vp), D, D, i32, vp]),
+        "sfw_workspace_destroy": (None, [vp]),
+        "sfw_workspace_set_stream": (i32, [vp, vp]),
+        "sfw_last_error": (ctypes.c_char_p, []),
+        "sfw_forward": (i32, [vp, vp, D, D, vp, i32, vp]),
+        "sfw_residual_grad": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp, vp, vp]),
+        "sfw_adjoint": (i32, [vp, vp, D, D, vp, vp]),
+        "sfw_certificate": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp, i32, f32, vp, vp]),
+        "sfw_eta_points": (i32, [vp, D, vp, f32, vp, i32, vp, vp]),
+        "sfw_lasso_weights": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp]),
+        "sfw_solve": (i32, [vp, vp, D, vp, D, f32, ctypes.POINTER(SfwOptions), vp, i32,
+                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SfwStats)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return (lib.sfw_last_error() or b"").decode()
+
+
+def check(code: int, allow=()) -> int:
+    if code != SFW_OK and code not in allow:
+        raise SfwError(code, last_error())
+    return code
+
+
+def dims(shape) -> SfwDims:
+    """(nz, ny, nx) -> sfw_dims."""
+    nz, ny, nx = (int(v) for v in shape)
+    return SfwDims(nx, ny, nz)
+
+
+def _dev_ptr(t, dtype_name, what):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: must live on the GPU")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise ValueError(f"{what}: dtype must be {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def default_options(**overrides) -> SfwOptions:
+    o = SfwOptions()
+    check(lib.sfw_default_options(ctypes.byref(o)))
+    for k, v in overrides.items():
+        if k in ("sigma_grid", "d_grid"):
+            vals = list(v)
+            if len(vals) > SFW_MAX_GRID:
+                raise ValueError(f"{k}: at most {SFW_MAX_GRID} values")
+            arr = getattr(o, k)
+            for i, x in enumerate(vals):
+                arr[i] = float(x)
+            setattr(o, "n_sigma" if k == "sigma_grid" else "n_d", len(vals))
+        elif k == "mode" and isinstance(v, str):
+            o.mode = {"BSFW": SFW_MODE_BSFW, "SFW": SFW_MODE_SFW}[v]
+        else:
+            setattr(o, k, v)
+    return o
+
+
+class Workspace:
+    """Owns an sfw_workspace bound to the current device and torch's current stream."""
+
+    def __init__(self, vol_max, psf_max, max_atoms, stream=None):
+        self.handle = ctypes.c_void_p()
+        self.vol_max = tuple(vol_max)
+        self.psf_max = tuple(psf_max)
+        self.max_atoms = int(max_atoms)
+        check(lib.sfw_workspace_create(ctypes.byref(self.handle), dims(vol_max), dims(psf_max),
+                                       int(max_atoms), _stream_handle(stream)))
+
+    def close(self):
+        if self.handle:
+            lib.sfw_workspace_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# ---------------------------------------------------------------- entry points (same names)
+
+def sfw_forward(ws: Workspace, H, atoms, vol_shape, phi_mu=None):
+    import torch
+    n = 0 if atoms is None else int(atoms.shape[0])
+    if phi_mu is None:
+        phi_mu = torch.empty(tuple(vol_shape), dtype=torch.float32, device="cuda")
+    check(lib.sfw_forward(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape), dims(vol_shape),
+                          _dev_ptr(atoms, "float32", "atoms") if n else None, n,
+                          _dev_ptr(phi_mu, "float32", "phi_mu")))
+    return phi_mu
+
+
+def sfw_residual_grad(ws: Workspace, H, y, lam, atoms, r_out=None, want_r=True):
+    """Returns (r, loss[1] float64 tensor, grad[n, 6] tensor)."""
+    import torch
+    n = 0 if atoms is None else int(atoms.shape[0])
+    if want_r and r_out is None:
+        r_out = torch.empty_like(y)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty((max(n, 1), 6), dtype=torch.float32, device="cuda")
+    check(lib.sfw_residual_grad(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape),
+                                dims(y.shape), _dev_ptr(y, "float32", "y"), float(lam),
+                                _dev_ptr(atoms, "float32", "atoms") if n else None, n,
+                                _dev_ptr(r_out, "float32", "r_out") if want_r else None,
+                                _dev_ptr(loss, "float64", "loss"),
+                                _dev_ptr(grad, "float32", "grad")))
+    return r_out, loss, grad[:n]
+
+
+def sfw_adjoint(ws: Workspace, H, r, q_out=None):
+    import torch
+    if q_out is None:
+        q_out = torch.empty_like(r)
+    check(lib.sfw_adjoint(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape), dims(r.shape),
+                          _dev_ptr(r, "float32", "r"), _dev_ptr(q_out, "float32", "q_out")))
+    return q_out
+
+
+def sfw_certificate(ws: Workspace, H, r, lam, sigma_grid, d_grid, trunc_T=12.0, want_eta=False):
+    """Returns (eta [ns, nd, nz, ny, nx] or None, argmax dict)."""
+    import torch
+    sg = (ctypes.c_float * len(sigma_grid))(*[float(v) for v in sigma_grid])
+    dg = (ctypes.c_float * len(d_grid))(*[float(v) for v in d_grid])
+    eta = None
+    if want_eta:
+        eta = torch.empty((len(sigma_grid), len(d_grid)) + tuple(r.shape), dtype=torch.float32,
+                          device="cuda")
+    best = torch.zeros(6, dtype=torch.int32, device="cuda")  # sfw_argmax is 24 bytes
+    check(lib.sfw_certificate(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape),
+                              dims(r.shape), _dev_ptr(r, "float32", "r"), float(lam),
+                              ctypes.cast(sg, ctypes.c_void_p), len(sigma_grid),
+                              ctypes.cast(dg, ctypes.c_void_p), len(d_grid), float(trunc_T),
+                              _dev_ptr(eta, "float32", "eta") if want_eta else None,
+                              _dev_ptr(best, "int32", "best")))
+    b = best.cpu().numpy()
+    return eta, {"eta": float(b[:1].view(np.float32)[0]), "i_sigma": int(b[1]), "i_d": int(b[2]),
+                 "x": int(b[3]), "y": int(b[4]), "z": int(b[5])}
+
+
+def sfw_eta_points(ws: Workspace, vol_shape, q, lam, thetas):
+    """thetas: host array [n, 5]; q: device volume or None (workspace's q). Returns (eta, grad)."""
+    th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float32).reshape(-1, 5))
+    n = th.shape[0]
+    eta = np.zeros(n, dtype=np.float64)
+    grad = np.zeros((n, 5), dtype=np.float64)
+    check(lib.sfw_eta_points(ws.handle, dims(vol_shape),
+                             _dev_ptr(q, "float32", "q") if q is not None else None, float(lam),
+                             th.ctypes.data_as(ctypes.c_void_p), n,
+                             eta.ctypes.data_as(ctypes.c_void_p),
+                             grad.ctypes.data_as(ctypes.c_void_p)))
+    return eta, grad
+
+
+def sfw_lasso_weights(ws: Workspace, H, y, lam, atoms):
+    import torch
+    n = int(atoms.shape[0])
+    w = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
+    check(lib.sfw_lasso_weights(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape),
+                                dims(y.shape), _dev_ptr(y, "float32", "y"), float(lam),
+                                _dev_ptr(atoms, "float32", "atoms"), n, _dev_ptr(w, "float64", "w")))
+    return w[:n]
+
+
+def sfw_solve(ws: Workspace, y, H, lam, opts: SfwOptions | None = None, cap: int | None = None):
+    """Returns (atoms [n, 6] float64 numpy, stats dict, status code)."""
+    cap = ws.max_atoms if cap is None else int(cap)
+    out = (SfwAtom * max(cap, 1))()
+    n_out = ctypes.c_int(0)
+    stats = SfwStats()
+    code = lib.sfw_solve(ws.handle, _dev_ptr(y, "float32", "y"), dims(y.shape),
+                         _dev_ptr(H, "float32", "H"), dims(H.shape), float(lam),
+                         ctypes.byref(opts) if opts is not None else None,
+                         ctypes.cast(out, ctypes.c_void_p), cap, ctypes.byref(n_out),
+                         ctypes.byref(stats))
+    check(code, allow=(SFW_ENOCONV,))
+    n = n_out.value
+    arr = np.array([[a.w, a.mx, a.my, a.mz, a.sigma, a.d] for a in out[:n]], dtype=np.float64)
+    return arr.reshape(-1, 6), stats.as_dict(), code

@@ -1,0 +1,583 @@
+// C ABI of libsfw: workspace lifecycle, argument validation and the operator entry points.
+// The solver loop (sfw_solve) lives in sfw_solver.cpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "sfw_internal.h"
+#include "sfw_ops.h"
+
+namespace sfw {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) +
+                 ") in " + what;
+  return SFW_EHIP;
+}
+
+// ------------------------------------------------------------------ validation
+
+int check_dims(const sfw_dims& d, const char* what) {
+  if (d.nx <= 0 || d.ny <= 0 || d.nz <= 0)
+    return fail(SFW_EINVAL, std::string(what) + ": every size must be positive");
+  if ((long long)d.nx * d.ny * d.nz > (1LL << 31) - 1)
+    return fail(SFW_EINVAL, std::string(what) + ": more than 2^31-1 voxels");
+  return SFW_OK;
+}
+
+int check_psf(const sfw_dims& p) {
+  int rc = check_dims(p, "psf");
+  if (rc) return rc;
+  if (p.nx % 2 == 0 || p.ny % 2 == 0 || p.nz % 2 == 0)
+    return fail(SFW_EINVAL, "psf: every size must be odd (the PSF is centred at (P-1)/2)");
+  return SFW_OK;
+}
+
+int check_ws_fit(const sfw_workspace* ws, const sfw_dims& vol, const sfw_dims* psf, int n) {
+  if (!ws) return fail(SFW_EINVAL, "workspace is NULL");
+  int rc = check_dims(vol, "vol");
+  if (rc) return rc;
+  if (vol.nx > ws->vol_max.nx || vol.ny > ws->vol_max.ny || vol.nz > ws->vol_max.nz)
+    return fail(SFW_EINVAL, "vol exceeds the workspace's vol_max");
+  if (psf) {
+    rc = check_psf(*psf);
+    if (rc) return rc;
+    if (psf->nx > ws->psf_max.nx || psf->ny > ws->psf_max.ny || psf->nz > ws->psf_max.nz)
+      return fail(SFW_EINVAL, "psf exceeds the workspace's psf_max");
+  }
+  if (n < 0) return fail(SFW_EINVAL, "n must be >= 0");
+  if (n > ws->max_atoms) return fail(SFW_EINVAL, "n exceeds the workspace's max_atoms");
+  return SFW_OK;
+}
+
+int check_lambda(float lambda) {
+  if (!(lambda > 0.f) || !std::isfinite(lambda))
+    return fail(SFW_EINVAL, "lambda must be finite and > 0");
+  return SFW_OK;
+}
+
+// ------------------------------------------------------------------ internal operators
+
+PsfPlan plan_psf(const sfw_dims& vol, const sfw_dims& psf) {
+  PsfPlan p;
+  p.psf = psf;
+  p.valu = plan_conv(vol, psf.nx, psf.ny, psf.nz);
+  const char* env = std::getenv("SFW_CONV");
+  const bool force_valu = env && std::strcmp(env, "valu") == 0;
+  p.mfma = !force_valu && mfma_conv_ok(psf.nx, psf.ny, psf.nz);
+  p.nres = p.mfma ? 4 * mfma_conv_blocks(vol) : p.valu.nblocks;
+  return p;
+}
+
+int prep_psf(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool adj) {
+  if (p.mfma) {
+    if (fwd) SFW_HIP(launch_mfma_prep(H, p.psf, false, ws->am_fwd, ws->stream));
+    if (adj) SFW_HIP(launch_mfma_prep(H, p.psf, true, ws->am_adj, ws->stream));
+  } else {
+    if (fwd) SFW_HIP(launch_psf_prep(H, p.psf, p.valu.kzp, false, ws->wt_fwd, ws->stream));
+    if (adj) SFW_HIP(launch_psf_prep(H, p.psf, p.valu.kzp, true, ws->wt_adj, ws->stream));
+  }
+  return SFW_OK;
+}
+
+int conv_psf(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjoint,
+             const float* in, float* out, int epi, const float* yobs) {
+  if (p.mfma)
+    SFW_HIP(launch_conv_mfma(in, adjoint ? ws->am_adj : ws->am_fwd, p.psf, vol, epi, out, yobs,
+                             ws->dpart, ws->stream));
+  else
+    SFW_HIP(launch_conv(p.valu, in, adjoint ? ws->wt_adj : ws->wt_fwd, vol, epi, out, yobs,
+                        ws->dpart, 1.f, 0, nullptr, ws->stream));
+  return SFW_OK;
+}
+
+int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, float* phi) {
+  SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream));
+  return conv_psf(ws, p, vol, false, ws->f, phi, kEpiPlain, nullptr);
+}
+
+int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
+             float lambda, const sfw_atom* atoms_dev, int n, float* r_out, double* loss_out,
+             sfw_atom* grad_out) {
+  float* r = r_out ? r_out : ws->r;
+  SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream));
+  int rc = conv_psf(ws, p, vol, false, ws->f, r, kEpiResidual, y);
+  if (rc) return rc;
+  rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr);
+  if (rc) return rc;
+  ws->q_valid = true;
+  GradPlan gp = plan_grad(vol, n);
+  SFW_HIP(launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream));
+  SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, ws->dpart, p.nres, atoms_dev, lambda,
+                               ws->dres, grad_out, loss_out, ws->stream));
+  return SFW_OK;
+}
+
+int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double lambda,
+                  const double* thetas, int n, double* eta_out, double* grad_out) {
+  // unit-weight atom constants computed on the host in float64, staged through pinned memory
+  AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin);
+  for (int i = 0; i < n; ++i) {
+    const double* t = thetas + 5 * i;
+    AtomK k;
+    k.w = 1.f;
+    k.mx = (float)t[0];
+    k.my = (float)t[1];
+    k.mz = (float)t[2];
+    k.hd = (float)(0.5 * t[4]);
+    k.hdm1 = k.hd - 1.f;
+    k.c = (float)(-t[4] * std::log2(t[3]) - 1.0 + 0.52876637294489772);
+    k.pad = 0.f;
+    hk[i] = k;
+  }
+  SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
+  GradPlan gp = plan_grad(vol, n);
+  SFW_HIP(launch_grad(gp, ws->ak, n, q, vol, ws->gpart, ws->stream));
+  SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, nullptr, 0, nullptr, 0.f, ws->dres,
+                               nullptr, nullptr, ws->stream));
+  double* hs = ws->hpin + 8 * (size_t)ws->max_atoms + 16;
+  SFW_HIP(hipMemcpyAsync(hs, ws->dres, sizeof(double) * 6 * n, hipMemcpyDeviceToHost,
+                         ws->stream));
+  SFW_HIP(hipStreamSynchronize(ws->stream));
+  const double ln2 = 0.69314718055994531;
+  for (int i = 0; i < n; ++i) {
+    const double* S = hs + 6 * i;
+    const double* t = thetas + 5 * i;
+    const double d = t[4], sg = t[3];
+    eta_out[i] = S[0] / lambda;
+    if (grad_out) {
+      double* g = grad_out + 5 * i;
+      g[0] = d * ln2 * S[3] / lambda;
+      g[1] = d * ln2 * S[4] / lambda;
+      g[2] = d * ln2 * S[5] / lambda;
+      g[3] = (d / sg) * ln2 * S[1] / lambda;
+      g[4] = -(0.5 * ln2 * ln2 * S[2] - std::log(sg) * ln2 * S[1]) / lambda;
+    }
+  }
+  return SFW_OK;
+}
+
+static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* dg, int nd,
+                       float T, const sfw_dims& vol) {
+  std::vector<float> key;
+  key.push_back(T);
+  key.push_back((float)ns);
+  key.push_back((float)nd);
+  for (int i = 0; i < ns; ++i) key.push_back(sg[i]);
+  for (int j = 0; j < nd; ++j) key.push_back(dg[j]);
+  if (key == ws->lut_key && ws->lut) return SFW_OK;
+  std::vector<size_t> off;
+  std::vector<int> rad;
+  size_t total = 0;
+  for (int i = 0; i < ns; ++i)
+    for (int j = 0; j < nd; ++j) {
+      const double R = std::ceil((double)sg[i] * std::pow(2.0 * (double)T, 1.0 / (double)dg[j]));
+      const int r = (int)R;
+      if (r > 128) return fail(SFW_EINVAL, "certificate grid kernel radius above 128");
+      const int P = 2 * r + 1;
+      ConvPlan p = plan_conv(vol, P, P, P);
+      if (p.lds_bytes > (size_t)kConvMaxLds)
+        return fail(SFW_EINVAL, "certificate grid kernel too wide for the convolution tile");
+      off.push_back(total);
+      rad.push_back(r);
+      total += (size_t)P * P * p.kzp;
+    }
+  std::vector<float> host(total, 0.f);
+  for (int i = 0; i < ns; ++i)
+    for (int j = 0; j < nd; ++j) {
+      const int s = i * nd + j;
+      const int r = rad[s];
+      const int P = 2 * r + 1;
+      ConvPlan p = plan_conv(vol, P, P, P);
+      const double sig = sg[i], d = dg[j];
+      const double inv = 1.0 / (2.0 * std::pow(sig, d));
+      float* dst = host.data() + off[s];
+      for (int ky = 0; ky < P; ++ky)
+        for (int kx = 0; kx < P; ++kx)
+          for (int kz = 0; kz < P; ++kz) {
+            const double tx = kx - r, ty = ky - r, tz = kz - r;
+            const double rr = std::sqrt(tx * tx + ty * ty + tz * tz);
+            dst[((size_t)ky * P + kx) * p.kzp + kz] = (float)std::exp(-std::pow(rr, d) * inv);
+          }
+    }
+  if (total > ws->lut_cap) {
+    if (ws->lut) SFW_HIP(hipFree(ws->lut));
+    ws->lut = nullptr;
+    ws->lut_cap = 0;
+    SFW_HIP(hipMalloc(&ws->lut, total * sizeof(float)));
+    ws->lut_cap = total;
+  }
+  SFW_HIP(hipMemcpyAsync(ws->lut, host.data(), total * sizeof(float), hipMemcpyHostToDevice,
+                         ws->stream));
+  SFW_HIP(hipStreamSynchronize(ws->stream));
+  ws->lut_off = off;
+  ws->lut_r = rad;
+  ws->lut_key = key;
+  return SFW_OK;
+}
+
+int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float lambda,
+                   const float* sg, int ns, const float* dg, int nd, float T, float* eta_out) {
+  int rc = lut_prepare(ws, sg, ns, dg, nd, T, vol);
+  if (rc) return rc;
+  const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
+  int nb = 0;
+  for (int i = 0; i < ns; ++i)
+    for (int j = 0; j < nd; ++j) {
+      const int s = i * nd + j;
+      const int P = 2 * ws->lut_r[s] + 1;
+      ConvPlan p = plan_conv(vol, P, P, P);
+      nb = p.nblocks;
+      if ((size_t)nb * ns * nd > ws->apart_cap)
+        return fail(SFW_EINVAL, "certificate partial buffer too small");
+      SFW_HIP(launch_conv(p, q, ws->lut + ws->lut_off[s], vol, kEpiArgmax,
+                          eta_out ? eta_out + (size_t)s * V : nullptr, nullptr, nullptr,
+                          1.0f / lambda, (long long)s * (long long)V, ws->apart + (size_t)s * nb,
+                          ws->stream));
+    }
+  SFW_HIP(launch_argmax_final(ws->apart, nb * ns * nd, vol, nd, ws->best, ws->stream));
+  return SFW_OK;
+}
+
+// Columns a_i = H * g(theta_i) (unit weight) for i in [i0, i1) into ws->cols; atoms staged in
+// ws->ak with unit weights.
+int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int i0, int i1) {
+  for (int i = i0; i < i1; ++i) {
+    SFW_HIP(launch_render(ws->ak + i, 1, vol, ws->f, ws->stream));
+    int rc = conv_psf(ws, p, vol, false, ws->f, ws->cols + (size_t)i * ws->vcap, kEpiPlain,
+                      nullptr);
+    if (rc) return rc;
+  }
+  return SFW_OK;
+}
+
+// G[i][0..i] and b[i] for the column i into out (float64, device), k = i + 1 entries + b.
+int op_gram_row(sfw_workspace* ws, const sfw_dims& vol, const float* y, int i, double* out) {
+  const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
+  int nb = (int)std::min<size_t>(256, (V + 255) / 256);
+  if ((size_t)nb * (i + 2) > ws->dpart_cap) return fail(SFW_EINVAL, "dot partial buffer too small");
+  SFW_HIP(launch_dots(ws->cols + (size_t)i * ws->vcap, ws->cols, i + 1, ws->vcap, y, V, ws->dpart,
+                      nb, out, ws->stream));
+  return SFW_OK;
+}
+
+}  // namespace sfw
+
+using namespace sfw;
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* sfw_last_error(void) { return g_last_error.c_str(); }
+
+int sfw_default_options(sfw_options* o) {
+  if (!o) return fail(SFW_EINVAL, "opts is NULL");
+  std::memset(o, 0, sizeof(*o));
+  o->mode = SFW_MODE_BSFW;
+  o->n_sigma = 4;
+  for (int i = 0; i < 4; ++i) o->sigma_grid[i] = 1.0f + i / 3.0f;
+  o->n_d = 3;
+  o->d_grid[0] = 1.5f;
+  o->d_grid[1] = 2.0f;
+  o->d_grid[2] = 2.5f;
+  o->sigma_lo = 0.5f;
+  o->sigma_hi = 4.0f;
+  o->d_lo = 1.2f;
+  o->d_hi = 3.0f;
+  o->trunc_T = 12.0f;
+  o->eta_tol = 1e-3;
+  o->prune_rel = 1e-6;
+  o->merge_tol = 2e-2;
+  o->max_iter = 200;
+  o->ascent_max_iter = 200;
+  o->slide_max_iter = 1000;
+  o->ascent_gtol = 1e-9;
+  o->slide_gtol = 1e-9;
+  o->ftol = 1e-12;
+  o->lbfgs_memory = 10;
+  o->check_finite = 1;
+  o->verbose = 0;
+  return SFW_OK;
+}
+
+void sfw_workspace_destroy(sfw_workspace* ws) {
+  if (!ws) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(ws->device);
+  if (ws->stream) (void)hipStreamSynchronize(ws->stream);
+  float* fbufs[] = {ws->f, ws->phi, ws->r, ws->q, ws->tmpv, ws->wt_fwd, ws->wt_adj, ws->am_fwd,
+                    ws->am_adj, ws->lut, ws->gpart, ws->cols};
+  for (float* b : fbufs)
+    if (b) (void)hipFree(b);
+  if (ws->atoms_dev) (void)hipFree(ws->atoms_dev);
+  if (ws->ak) (void)hipFree(ws->ak);
+  if (ws->dpart) (void)hipFree(ws->dpart);
+  if (ws->dres) (void)hipFree(ws->dres);
+  if (ws->apart) (void)hipFree(ws->apart);
+  if (ws->best) (void)hipFree(ws->best);
+  if (ws->hpin) (void)hipHostFree(ws->hpin);
+  (void)hipSetDevice(cur);
+  delete ws;
+}
+
+int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max, int max_atoms,
+                         hipStream_t stream) {
+  try {
+    if (!out) return fail(SFW_EINVAL, "ws output pointer is NULL");
+    *out = nullptr;
+    int rc = check_dims(vol_max, "vol_max");
+    if (rc) return rc;
+    rc = check_psf(psf_max);
+    if (rc) return rc;
+    if (max_atoms < 1 || max_atoms > 4096)
+      return fail(SFW_EINVAL, "max_atoms must be in [1, 4096]");
+    {
+      // PSF must fit the convolution's LDS tile even with one y tap per pass
+      const int LX = kConvTX + psf_max.nx - 1;
+      if ((size_t)LX * kConvTY * conv_tile_lzp(4) * 4 > (size_t)kConvMaxLds)
+        return fail(SFW_EINVAL, "psf_max.nx too large for the convolution tile");
+    }
+    sfw_workspace* ws = new (std::nothrow) sfw_workspace();
+    if (!ws) return fail(SFW_ENOMEM, "host allocation failed");
+    SFW_HIP(hipGetDevice(&ws->device));
+    ws->stream = stream;
+    ws->vol_max = vol_max;
+    ws->psf_max = psf_max;
+    ws->max_atoms = max_atoms;
+    ws->vcap = (size_t)vol_max.nx * vol_max.ny * vol_max.nz;
+    const size_t V = ws->vcap;
+    const int na = max_atoms + 1;
+    auto dmalloc = [&](void** p, size_t bytes, const char* what) -> int {
+      hipError_t e = hipMalloc(p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SFW_ENOMEM, std::string("device allocation failed: ") + what);
+      }
+      return SFW_OK;
+    };
+#define ALLOC(ptr, bytes, what)                                    \
+  do {                                                             \
+    int rc_ = dmalloc(reinterpret_cast<void**>(&(ptr)), (bytes), what); \
+    if (rc_) {                                                     \
+      sfw_workspace_destroy(ws);                                   \
+      return rc_;                                                  \
+    }                                                              \
+  } while (0)
+    ALLOC(ws->f, V * 4, "f");
+    ALLOC(ws->phi, V * 4, "phi");
+    ALLOC(ws->r, V * 4, "r");
+    ALLOC(ws->q, V * 4, "q");
+    ALLOC(ws->tmpv, V * 4, "tmpv");
+    ws->wt_cap = (size_t)psf_max.nx * psf_max.ny * (psf_max.nz + 15);
+    ALLOC(ws->wt_fwd, ws->wt_cap * 4, "psf copy");
+    ALLOC(ws->wt_adj, ws->wt_cap * 4, "psf copy");
+    ALLOC(ws->am_fwd, 32 * 64 * 4, "psf matrix operands");
+    ALLOC(ws->am_adj, 32 * 64 * 4, "psf matrix operands");
+    ALLOC(ws->atoms_dev, sizeof(sfw_atom) * na, "atoms");
+    ALLOC(ws->ak, sizeof(AtomK) * na, "atom constants");
+    const size_t nxy = (size_t)vol_max.nx * vol_max.ny;
+    const size_t gtiles = ((nxy + kGradThreads - 1) / kGradThreads) * ((vol_max.nz + 15) / 16);
+    ws->gpart_cap = gtiles * na * 6;
+    ALLOC(ws->gpart, ws->gpart_cap * 4, "gradient partials");
+    const size_t cblocks = (size_t)((vol_max.nx + kConvTX - 1) / kConvTX) *
+                           ((vol_max.ny + kConvTY - 1) / kConvTY) *
+                           ((vol_max.nz + kConvRZ - 1) / kConvRZ);
+    const size_t mparts = 4 * (size_t)mfma_conv_blocks(vol_max);
+    ws->dpart_cap = std::max(std::max(cblocks, mparts), (size_t)256 * (na + 2));
+    ALLOC(ws->dpart, ws->dpart_cap * 8, "float64 partials");
+    const size_t dres_n = (size_t)(na + 2) * (na + 2) + 8 * (size_t)(na + 2) + 64;
+    ALLOC(ws->dres, dres_n * 8, "float64 results");
+    ws->apart_cap = cblocks * SFW_MAX_GRID * SFW_MAX_GRID;
+    ALLOC(ws->apart, ws->apart_cap * sizeof(ArgPart), "argmax partials");
+    ALLOC(ws->best, sizeof(sfw_argmax) * 2, "argmax");
+    ALLOC(ws->cols, (size_t)max_atoms * V * 4, "LASSO columns");
+#undef ALLOC
+    ws->hpin_cap = dres_n + 8 * (size_t)(na + 2) + 64;
+    if (hipHostMalloc(reinterpret_cast<void**>(&ws->hpin), ws->hpin_cap * 8, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      sfw_workspace_destroy(ws);
+      return fail(SFW_ENOMEM, "pinned host allocation failed");
+    }
+    *out = ws;
+    return SFW_OK;
+  } catch (const std::exception& e) {
+    return fail(SFW_ENOMEM, std::string("exception: ") + e.what());
+  } catch (...) {
+    return fail(SFW_ENOMEM, "unknown exception");
+  }
+}
+
+int sfw_workspace_set_stream(sfw_workspace* ws, hipStream_t stream) {
+  if (!ws) return fail(SFW_EINVAL, "workspace is NULL");
+  ws->stream = stream;
+  return SFW_OK;
+}
+
+int sfw_forward(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
+                const sfw_atom* atoms, int n, float* phi_mu) {
+  try {
+    int rc = check_ws_fit(ws, vol, &psf, n);
+    if (rc) return rc;
+    if (!H) return fail(SFW_EINVAL, "H is NULL");
+    if (n > 0 && !atoms) return fail(SFW_EINVAL, "atoms is NULL");
+    PsfPlan p = plan_psf(vol, psf);
+    rc = prep_psf(ws, H, p, true, false);
+    if (rc) return rc;
+    SFW_HIP(launch_atom_prep(atoms, n, false, ws->ak, ws->stream));
+    return op_forward(ws, p, vol, n, phi_mu ? phi_mu : ws->phi);
+  } catch (...) {
+    return fail(SFW_EINVAL, "unexpected exception in sfw_forward");
+  }
+}
+
+int sfw_residual_grad(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
+                      const float* y, float lambda, const sfw_atom* atoms, int n, float* r_out,
+                      double* loss_out, sfw_atom* grad_out) {
+  try {
+    int rc = check_ws_fit(ws, vol, &psf, n);
+    if (rc) return rc;
+    if (!H || !y) return fail(SFW_EINVAL, "H or y is NULL");
+    if (n > 0 && !atoms) return fail(SFW_EINVAL, "atoms is NULL");
+    rc = check_lambda(lambda);
+    if (rc) return rc;
+    PsfPlan p = plan_psf(vol, psf);
+    rc = prep_psf(ws, H, p, true, true);
+    if (rc) return rc;
+    SFW_HIP(launch_atom_prep(atoms, n, false, ws->ak, ws->stream));
+    return op_cgrad(ws, p, vol, y, lambda, atoms, n, r_out, loss_out, n > 0 ? grad_out : nullptr);
+  } catch (...) {
+    return fail(SFW_EINVAL, "unexpected exception in sfw_residual_grad");
+  }
+}
+
+int sfw_adjoint(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol, const float* r,
+                float* q_out) {
+  try {
+    int rc = check_ws_fit(ws, vol, &psf, 0);
+    if (rc) return rc;
+    if (!H || !r || !q_out) return fail(SFW_EINVAL, "H, r or q_out is NULL");
+    PsfPlan p = plan_psf(vol, psf);
+    rc = prep_psf(ws, H, p, false, true);
+    if (rc) return rc;
+    return conv_psf(ws, p, vol, true, r, q_out, kEpiPlain, nullptr);
+  } catch (...) {
+    return fail(SFW_EINVAL, "unexpected exception in sfw_adjoint");
+  }
+}
+
+int sfw_certificate(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol, const float* r,
+                    float lambda, const float* sigma_grid, int ns, const float* d_grid, int nd,
+                    float trunc_T, float* eta_out, sfw_argmax* best_out) {
+  try {
+    int rc = check_ws_fit(ws, vol, &psf, 0);
+    if (rc) return rc;
+    if (!H || !r) return fail(SFW_EINVAL, "H or r is NULL");
+    rc = check_lambda(lambda);
+    if (rc) return rc;
+    if (!sigma_grid || !d_grid) return fail(SFW_EINVAL, "sigma_grid or d_grid is NULL");
+    if (ns < 1 || nd < 1 || ns > SFW_MAX_GRID || nd > SFW_MAX_GRID)
+      return fail(SFW_EINVAL, "grid sizes must be in [1, SFW_MAX_GRID]");
+    for (int i = 0; i < ns; ++i)
+      if (!(sigma_grid[i] > 0.f) || !std::isfinite(sigma_grid[i]))
+        return fail(SFW_EINVAL, "sigma_grid values must be finite and > 0");
+    for (int j = 0; j < nd; ++j)
+      if (!(d_grid[j] > 0.f) || !std::isfinite(d_grid[j]))
+        return fail(SFW_EINVAL, "d_grid values must be finite and > 0");
+    const float T = trunc_T > 0.f ? trunc_T : 12.0f;
+    PsfPlan p = plan_psf(vol, psf);
+    rc = prep_psf(ws, H, p, false, true);
+    if (rc) return rc;
+    rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr);
+    if (rc) return rc;
+    ws->q_valid = true;
+    rc = op_certificate(ws, vol, ws->q, lambda, sigma_grid, ns, d_grid, nd, T, eta_out);
+    if (rc) return rc;
+    if (best_out)
+      SFW_HIP(hipMemcpyAsync(best_out, ws->best, sizeof(sfw_argmax), hipMemcpyDeviceToDevice,
+                             ws->stream));
+    return SFW_OK;
+  } catch (...) {
+    return fail(SFW_EINVAL, "unexpected exception in sfw_certificate");
+  }
+}
+
+int sfw_eta_points(sfw_workspace* ws, sfw_dims vol, const float* q, float lambda,
+                   const float* thetas, int n, double* eta_out, double* grad_out) {
+  try {
+    int rc = check_ws_fit(ws, vol, nullptr, n);
+    if (rc) return rc;
+    rc = check_lambda(lambda);
+    if (rc) return rc;
+    if (n == 0) return SFW_OK;
+    if (!thetas || !eta_out) return fail(SFW_EINVAL, "thetas or eta_out is NULL");
+    if (!q && !ws->q_valid) return fail(SFW_EINVAL, "no q given and none computed yet");
+    std::vector<double> th(5 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+      for (int c = 0; c < 5; ++c) th[5 * i + c] = thetas[5 * i + c];
+      if (!(th[5 * i + 3] > 0) || !(th[5 * i + 4] > 0))
+        return fail(SFW_EINVAL, "sigma and d must be > 0");
+    }
+    return op_eta_points(ws, vol, q ? q : ws->q, lambda, th.data(), n, eta_out, grad_out);
+  } catch (...) {
+    return fail(SFW_EINVAL, "unexpected exception in sfw_eta_points");
+  }
+}
+
+int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
+                      const float* y, float lambda, const sfw_atom* atoms, int n, double* w_out) {
+  try {
+    int rc = check_ws_fit(ws, vol, &psf, n);
+    if (rc) return rc;
+    if (!H || !y) return fail(SFW_EINVAL, "H or y is NULL");
+    rc = check_lambda(lambda);
+    if (rc) return rc;
+    if (n == 0) return SFW_OK;
+    if (!atoms || !w_out) return fail(SFW_EINVAL, "atoms or w_out is NULL");
+    PsfPlan p = plan_psf(vol, psf);
+    rc = prep_psf(ws, H, p, true, false);
+    if (rc) return rc;
+    SFW_HIP(launch_atom_prep(atoms, n, true, ws->ak, ws->stream));
+    rc = op_columns(ws, p, vol, 0, n);
+    if (rc) return rc;
+    // row i of the lower triangle: G[i][0..i] then b[i], packed at offset i(i+1)/2 + i
+    for (int i = 0; i < n; ++i) {
+      rc = op_gram_row(ws, vol, y, i, ws->dres + (size_t)i * (i + 1) / 2 + i);
+      if (rc) return rc;
+    }
+    const size_t tot = (size_t)n * (n + 1) / 2 + n;
+    SFW_HIP(hipMemcpyAsync(ws->hpin, ws->dres, tot * 8, hipMemcpyDeviceToHost, ws->stream));
+    SFW_HIP(hipStreamSynchronize(ws->stream));
+    std::vector<double> G((size_t)n * n), c(n), w;
+    for (int i = 0; i < n; ++i) {
+      const double* row = ws->hpin + (size_t)i * (i + 1) / 2 + i;
+      for (int j = 0; j <= i; ++j) G[(size_t)i * n + j] = G[(size_t)j * n + i] = row[j];
+      c[i] = row[i + 1] - (double)lambda;
+    }
+    rc = nnqp(G, c, n, w);
+    if (rc) return rc;
+    SFW_HIP(hipMemcpyAsync(w_out, w.data(), 8 * (size_t)n, hipMemcpyHostToDevice, ws->stream));
+    SFW_HIP(hipStreamSynchronize(ws->stream));
+    return SFW_OK;
+  } catch (...) {
+    return fail(SFW_EINVAL, "unexpected exception in sfw_lasso_weights");
+  }
+}
+
+}  // extern "C"

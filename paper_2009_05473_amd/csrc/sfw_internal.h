@@ -1,0 +1,194 @@
+// Internal declarations of libsfw: workspace layout, per-atom constants, kernel launchers.
+// Not part of the public interface (include/sfw.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sfw.h"
+
+namespace sfw {
+
+// Per-atom constants consumed by the render and reduction kernels. With l = log2(r^2):
+//   u * log2(e) = exp2(hd * l + c)        (u = ||s - m||^d / (2 sigma^d))
+//   u * log2(e) / r^2 = exp2(hdm1 * l + c)
+// where hd = d / 2, hdm1 = hd - 1 and c = -d log2(sigma) - 1 + log2(log2(e)).
+struct AtomK {
+  float w, mx, my, mz, hd, c, hdm1, pad;
+};
+
+// One candidate of the grid-certificate maximum.
+struct ArgPart {
+  float val;
+  int32_t pad;
+  long long idx;
+};
+
+// Fixed tile shapes of the direct convolution (see launch_conv).
+constexpr int kConvTX = 32;
+constexpr int kConvTY = 8;
+constexpr int kConvRZ = 8;
+constexpr int kConvMaxLds = 64 * 1024;
+// Largest (16 + px - 1) x (4 + py - 1) input patch of the matrix-core convolution.
+constexpr int kMfmaPatchMax = 512;
+
+// Voxel columns of the render kernel: 256 threads over the flattened (y, x) plane,
+// kRenderVPT consecutive z per thread.
+constexpr int kRenderVPT = 8;
+// Reduction kernel: 256 threads over the flattened (y, x) plane, VPT z per thread.
+constexpr int kGradThreads = 256;
+constexpr int kGradMaxAtomsPerGroup = 64;
+
+// 2^-100: added to the in-plane squared distance so log2(r^2) stays finite at an atom
+// centre; every derivative term carrying r^2 then vanishes there as in the limit.
+constexpr float kTinyR2 = 7.888609052210118e-31f;
+
+// z stride (floats) of the convolution's staged tile for z-pass size kz (see k_conv).
+constexpr int conv_tile_lzp(int kz) {
+  int l = (kConvRZ + kz - 1 + 3) / 4 * 4;
+  return (l / 4) % 2 == 1 ? l : l + 4;
+}
+
+struct ConvPlan {
+  int px = 1, py = 1, pz = 1;  // kernel taps per axis
+  int kz = 4;                  // z taps per LDS pass (template parameter)
+  int kzp = 4;                 // pz padded to a multiple of kz
+  int kyc = 1;                 // y taps per LDS pass
+  size_t lds_bytes = 0;
+  dim3 grid;
+  int nblocks = 0;
+};
+
+struct GradPlan {
+  int vpt = 16;       // z voxels per thread (template parameter)
+  int ntile_xy = 0;   // blocks over the flattened (y, x) plane
+  int ntile_z = 0;
+  int ntiles = 0;     // ntile_xy * ntile_z
+  int groups = 1;     // atom groups (second grid dimension)
+  int apg = 0;        // atoms per group
+};
+
+}  // namespace sfw
+
+struct sfw_workspace {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  sfw_dims vol_max{0, 0, 0};
+  sfw_dims psf_max{0, 0, 0};
+  int max_atoms = 0;
+  size_t vcap = 0;
+
+  // volumes [vcap]
+  float* f = nullptr;    // rendered sum of atoms
+  float* phi = nullptr;  // H * f
+  float* r = nullptr;    // residual y - H * f
+  float* q = nullptr;    // Phi^T r
+  float* tmpv = nullptr; // LASSO column under construction, misc
+  bool q_valid = false;
+
+  // PSF copies in [ky][kx][kzp] layout: forward (convolution) and adjoint (correlation)
+  float* wt_fwd = nullptr;
+  float* wt_adj = nullptr;
+  size_t wt_cap = 0;
+  // matrix-core A operands of the same two kernels (used when mfma_conv_ok)
+  float* am_fwd = nullptr;
+  float* am_adj = nullptr;
+
+  // lookup table of the grid certificate: concatenated [ky][kx][kzp] kernels
+  float* lut = nullptr;
+  size_t lut_cap = 0;
+  std::vector<size_t> lut_off;
+  std::vector<int> lut_r;
+  std::vector<float> lut_key;  // (T, ns, nd, sigmas..., ds...) of the cached table
+
+  // atoms
+  sfw_atom* atoms_dev = nullptr;  // [max_atoms + 1] staging for host-provided atoms
+  sfw::AtomK* ak = nullptr;       // [max_atoms + 1]
+
+  // reduction partials
+  float* gpart = nullptr;   // [tiles][atoms][6]
+  size_t gpart_cap = 0;     // floats
+  double* dpart = nullptr;  // loss / dot partials
+  size_t dpart_cap = 0;     // doubles
+  double* dres = nullptr;   // [8 * (max_atoms + 2) + 64] float64 results
+  sfw::ArgPart* apart = nullptr;
+  size_t apart_cap = 0;
+  sfw_argmax* best = nullptr;  // [1]
+
+  // LASSO columns a_n = H * g_n, [max_atoms][vcap]
+  float* cols = nullptr;
+
+  // pinned host staging
+  double* hpin = nullptr;
+  size_t hpin_cap = 0;  // doubles
+};
+
+namespace sfw {
+
+// ---- error plumbing (sfw_api.cpp)
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define SFW_HIP(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return sfw::hip_fail(e_, #call); \
+  } while (0)
+
+// ---- launchers (sfw_kernels.hip); each returns a hipError_t from the launch
+ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz);
+GradPlan plan_grad(sfw_dims vol, int n_atoms);
+
+hipError_t launch_psf_prep(const float* H, sfw_dims psf, int kzp, bool flip, float* out,
+                           hipStream_t st);
+hipError_t launch_atom_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* out,
+                            hipStream_t st);
+hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st);
+
+enum ConvEpilogue { kEpiPlain = 0, kEpiResidual = 1, kEpiArgmax = 2 };
+// out = conv(in, W) with W in [ky][kx][kzp] layout (already flipped for a correlation).
+//  kEpiPlain:    out[v] = conv
+//  kEpiResidual: out[v] = yobs[v] - conv; dpart[block] = sum over the block of out^2
+//  kEpiArgmax:   eta = conv * scale; out[v] = eta if out != nullptr;
+//                apart[block] = max of eta over the block, flat index idx_base + v
+hipError_t launch_conv(const ConvPlan& p, const float* in, const float* wt, sfw_dims vol,
+                       int epi, float* out, const float* yobs, double* dpart, float scale,
+                       long long idx_base, ArgPart* apart, hipStream_t st);
+
+// Matrix-core convolution for PSFs with pz <= 16 and px * py <= 128 (see k_conv_mfma).
+// The A operands (per-lane weights) are built by launch_mfma_prep into amat
+// (mfma_steps * 64 floats). kEpiResidual writes one partial per wave: dpart[block * 4 + wave].
+bool mfma_conv_ok(int px, int py, int pz);
+int mfma_steps(int px, int py);
+int mfma_conv_blocks(sfw_dims vol);
+hipError_t launch_mfma_prep(const float* H, sfw_dims psf, bool flip, float* amat, hipStream_t st);
+hipError_t launch_conv_mfma(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
+                            int epi, float* out, const float* yobs, double* dpart,
+                            hipStream_t st);
+
+hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q, sfw_dims vol,
+                       float* gpart, hipStream_t st);
+// Sums partials over tiles in a fixed order (float64). For atom a:
+//   sums[a*6 + 0..5] = (S_g, S_u, S_l, S_mx, S_my, S_mz)
+// with S_g = sum q g, S_u = sum q g u', S_l = sum q g u' log2 r^2,
+// S_m = sum q g u' (s - m) / r^2 and u' = u log2(e). If loss_part != nullptr,
+// sums[6 n] = 1/2 sum of the nloss loss partials. If grad_out != nullptr, also writes the
+// gradient of C (float) using atoms and lambda.
+hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const double* loss_part,
+                                int nloss, const sfw_atom* atoms, float lambda,
+                                double* sums, sfw_atom* grad_out, double* loss_out,
+                                hipStream_t st);
+hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
+                               sfw_argmax* best, hipStream_t st);
+// out[c] = sum_v a[v] * cols[c][v] for c < k, out[k] = sum_v a[v] * y[v] (float64).
+hipError_t launch_dots(const float* a, const float* cols, int k, size_t colstride,
+                       const float* y, size_t nvox, double* dpart, int nblocks, double* out,
+                       hipStream_t st);
+hipError_t launch_any_nonfinite(const float* v, size_t n, int* flag, hipStream_t st);
+
+}  // namespace sfw

@@ -1,0 +1,907 @@
+// gfx950 kernels of the BSFW / SFW hot path (render, PSF convolution, residual, adjoint,
+// gradient reduction, grid certificate and its maximum, LASSO dot products).
+//
+// The paper computes the convolutions in the Fourier domain and parallelises C and grad C
+// across atoms (section 2). Here every operator is a direct, data-parallel kernel:
+// voxel columns for the atom sums, LDS-staged input tiles with register blocking along z
+// for the convolutions, and wavefront DPP reductions for the per-atom gradient sums.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "sfw_internal.h"
+
+namespace sfw {
+
+namespace {
+
+constexpr double kLog2Log2e = 0.52876637294489772;  // log2(log2(e))
+constexpr double kLn2 = 0.69314718055994531;
+
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// DPP row/broadcast controls (GFX9 encoding).
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+template <int CTRL, int ROWMASK, bool BOUND>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                               ROWMASK, 0xf, BOUND));
+}
+
+// Sum of v over the 64 lanes of the wavefront, returned as a wave-uniform value.
+// Requires all 64 lanes active.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f<kRowShr1, 0xf, true>(v);
+  v += dpp_f<kRowShr2, 0xf, true>(v);
+  v += dpp_f<kRowShr4, 0xf, true>(v);
+  v += dpp_f<kRowShr8, 0xf, true>(v);
+  v += dpp_f<kRowBcast15, 0xa, false>(v);
+  v += dpp_f<kRowBcast31, 0xc, false>(v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+__device__ __forceinline__ double shfl_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ bool arg_better(float v, long long i, float bv, long long bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+// ------------------------------------------------------------------ preparation
+
+__global__ void k_atom_prep(const sfw_atom* __restrict__ atoms, int n, int unit_weight,
+                            AtomK* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  sfw_atom a = atoms[i];
+  AtomK k;
+  k.w = unit_weight ? 1.0f : a.w;
+  k.mx = a.mx;
+  k.my = a.my;
+  k.mz = a.mz;
+  k.hd = 0.5f * a.d;
+  k.hdm1 = k.hd - 1.0f;
+  k.c = (float)(-(double)a.d * log2((double)a.sigma) - 1.0 + kLog2Log2e);
+  k.pad = 0.f;
+  out[i] = k;
+}
+
+// W[ky][kx][kz] (kz padded to kzp with zeros) from H[kz][ky][kx]; flip gives the
+// correlation kernel H[pz-1-kz][py-1-ky][px-1-kx].
+__global__ void k_psf_prep(const float* __restrict__ H, int px, int py, int pz, int kzp, int flip,
+                           float* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int total = px * py * kzp;
+  if (i >= total) return;
+  int kz = i % kzp;
+  int kx = (i / kzp) % px;
+  int ky = i / (kzp * px);
+  float v = 0.f;
+  if (kz < pz) {
+    int sz = flip ? pz - 1 - kz : kz;
+    int sy = flip ? py - 1 - ky : ky;
+    int sx = flip ? px - 1 - kx : kx;
+    v = H[((size_t)sz * py + sy) * px + sx];
+  }
+  out[i] = v;
+}
+
+// ------------------------------------------------------------------ render
+
+// f(s) = sum_n w_n exp(-u_n(s)) for every voxel; thread = one (y, x) column, kRenderVPT z.
+__global__ __launch_bounds__(256) void k_render(const AtomK* __restrict__ ak, int n, int nx,
+                                                int ny, int nz, float* __restrict__ f) {
+  constexpr int VPT = kRenderVPT;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int nxy = nx * ny;
+  if (p >= nxy) return;
+  const int y = p / nx;
+  const int x = p - y * nx;
+  const int z0 = blockIdx.y * VPT;
+  const float fx = (float)x, fy = (float)y, fz0 = (float)z0;
+  float acc[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) acc[j] = 0.f;
+  for (int a = 0; a < n; ++a) {
+    const AtomK k = ak[a];
+    const float dx = fx - k.mx;
+    const float dy = fy - k.my;
+    const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
+    const float dz0 = fz0 - k.mz;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const float dz = dz0 + (float)j;
+      const float r2 = fmaf(dz, dz, dxy2);
+      const float l = fast_log2(r2);
+      const float up = fast_exp2(fmaf(k.hd, l, k.c));  // u * log2(e)
+      const float g = fast_exp2(-up);
+      acc[j] = fmaf(k.w, g, acc[j]);
+    }
+  }
+  float* col = f + (size_t)z0 * nxy + p;
+#pragma unroll
+  for (int j = 0; j < VPT; ++j)
+    if (z0 + j < nz) col[(size_t)j * nxy] = acc[j];
+}
+
+// ------------------------------------------------------------------ direct convolution
+
+// z stride of the staged tile: >= RZ + KZ - 1, a multiple of 4 floats (128-bit reads) and an
+// odd multiple of 4 so the 16 lanes of a 128-bit LDS read phase hit distinct banks.
+constexpr int conv_lzp(int rz, int kz) {
+  int l = (rz + kz - 1 + 3) / 4 * 4;
+  return (l / 4) % 2 == 1 ? l : l + 4;
+}
+
+// out[z][y][x] = sum_{kz,ky,kx} W[ky][kx][kz] in[z + cz - kz][y + cy - ky][x + cx - kx],
+// in = 0 outside the volume. Block = TX x TY threads over an output tile TX x TY x RZ; each
+// thread keeps RZ outputs along z in registers. Taps are visited in passes of KZ (z) by kyc
+// (y) by px (x); each pass stages the input sub-tile it needs in LDS as [ly][lx][lz] with a
+// compile-time z stride, then for every (ky, kx) a thread reads one contiguous input column
+// of RZ + KZ - 1 values and does RZ * KZ FMAs with wave-uniform (scalar) weights.
+template <int TX, int TY, int RZ, int KZ, int EPI>
+__global__ __launch_bounds__(TX* TY) void k_conv(
+    const float* __restrict__ in, const float* __restrict__ wt, int px, int py, int pz, int kzp,
+    int kyc, int nx, int ny, int nz, float* __restrict__ out, const float* __restrict__ yobs,
+    double* __restrict__ dpart, float scale, long long idx_base, ArgPart* __restrict__ apart) {
+  extern __shared__ float lds[];
+  constexpr int NT = TX * TY;
+  constexpr int LZ = RZ + KZ - 1;
+  constexpr int LZP = conv_lzp(RZ, KZ);
+  const int tid = threadIdx.x;
+  const int tx = tid % TX;
+  const int ty = tid / TX;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * RZ;
+  const int cx = (px - 1) / 2, cy = (py - 1) / 2, cz = (pz - 1) / 2;
+  const int LX = TX + px - 1;
+  const size_t nxy = (size_t)nx * ny;
+
+  float acc[RZ];
+#pragma unroll
+  for (int j = 0; j < RZ; ++j) acc[j] = 0.f;
+
+  for (int kz0 = 0; kz0 < kzp; kz0 += KZ) {
+    for (int ky0 = 0; ky0 < py; ky0 += kyc) {
+      const int kyn = min(kyc, py - ky0);
+      const int LY = TY + kyn - 1;
+      const int ix0 = x0 + cx - px + 1;
+      const int iy0 = y0 + cy - ky0 - kyn + 1;
+      const int iz0 = z0 + cz - kz0 - KZ + 1;
+      __syncthreads();
+      // stage in[iz0 .. iz0+LZ) x [iy0 .. iy0+LY) x [ix0 .. ix0+LX) (zero outside) as
+      // lds[(ly * LX + lx) * LZP + lz]
+      const int nrows = LY * LZ;
+      for (int row = tid / 64; row < nrows; row += NT / 64) {
+        const int lz = row / LY;
+        const int ly = row - lz * LY;
+        const int gz = iz0 + lz, gy = iy0 + ly;
+        const bool rin = gz >= 0 && gz < nz && gy >= 0 && gy < ny;
+        const float* src = rin ? in + (size_t)gz * nxy + (size_t)gy * nx : in;
+        float* dst = lds + (size_t)ly * LX * LZP + lz;
+        for (int lx = tid & 63; lx < LX; lx += 64) {
+          const int gx = ix0 + lx;
+          dst[lx * LZP] = (rin && gx >= 0 && gx < nx) ? src[gx] : 0.f;
+        }
+      }
+      __syncthreads();
+      // blocked summation: each pass accumulates into fresh partials added to acc at the end
+      float part[RZ];
+#pragma unroll
+      for (int j = 0; j < RZ; ++j) part[j] = 0.f;
+      for (int kk = 0; kk < kyn; ++kk) {
+        const int ky = ky0 + kk;
+        const int ly = ty + kyn - 1 - kk;
+        const float* wrow = wt + (size_t)ky * px * kzp + kz0;
+        const float* lcol = lds + ((size_t)ly * LX + tx + px - 1) * LZP;
+        for (int kx = 0; kx < px; ++kx) {
+          float w[KZ];
+#pragma unroll
+          for (int t = 0; t < KZ; ++t) w[t] = wrow[(size_t)kx * kzp + t];
+          const float4* c4 = reinterpret_cast<const float4*>(lcol - (size_t)kx * LZP);
+          float v[LZP];
+#pragma unroll
+          for (int t = 0; t < LZP / 4; ++t) {
+            const float4 q4 = c4[t];
+            v[4 * t + 0] = q4.x;
+            v[4 * t + 1] = q4.y;
+            v[4 * t + 2] = q4.z;
+            v[4 * t + 3] = q4.w;
+          }
+#pragma unroll
+          for (int t = 0; t < KZ; ++t)
+#pragma unroll
+            for (int j = 0; j < RZ; ++j) part[j] = fmaf(w[t], v[j + KZ - 1 - t], part[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < RZ; ++j) acc[j] += part[j];
+    }
+  }
+
+  const int x = x0 + tx, y = y0 + ty;
+  const bool xy_in = x < nx && y < ny;
+  if (EPI == kEpiPlain) {
+    if (xy_in) {
+#pragma unroll
+      for (int j = 0; j < RZ; ++j)
+        if (z0 + j < nz) out[(size_t)(z0 + j) * nxy + (size_t)y * nx + x] = acc[j];
+    }
+  } else if (EPI == kEpiResidual) {
+    double ss = 0.0;
+    if (xy_in) {
+      float ssf = 0.f;
+#pragma unroll
+      for (int j = 0; j < RZ; ++j) {
+        if (z0 + j < nz) {
+          const size_t v = (size_t)(z0 + j) * nxy + (size_t)y * nx + x;
+          const float rv = yobs[v] - acc[j];
+          out[v] = rv;
+          ssf = fmaf(rv, rv, ssf);
+        }
+      }
+      ss = (double)ssf;
+    }
+    __shared__ double red[NT / 64];
+    ss = shfl_sum_d(ss);
+    if ((tid & 63) == 0) red[tid / 64] = ss;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int i = 0; i < NT / 64; ++i) t += red[i];
+      dpart[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = t;
+    }
+  } else {  // kEpiArgmax
+    float bv = -INFINITY;
+    long long bi = 0x7fffffffffffffffLL;
+    if (xy_in) {
+#pragma unroll
+      for (int j = 0; j < RZ; ++j) {
+        if (z0 + j < nz) {
+          const size_t v = (size_t)(z0 + j) * nxy + (size_t)y * nx + x;
+          const float e = acc[j] * scale;
+          if (out) out[v] = e;
+          const long long gi = idx_base + (long long)v;
+          if (arg_better(e, gi, bv, bi)) {
+            bv = e;
+            bi = gi;
+          }
+        }
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const float ov = __shfl_xor(bv, o, 64);
+      const long long oi = __shfl_xor(bi, o, 64);
+      if (arg_better(ov, oi, bv, bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    __shared__ float rv[NT / 64];
+    __shared__ long long ri[NT / 64];
+    if ((tid & 63) == 0) {
+      rv[tid / 64] = bv;
+      ri[tid / 64] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int i = 1; i < NT / 64; ++i)
+        if (arg_better(rv[i], ri[i], bv, bi)) {
+          bv = rv[i];
+          bi = ri[i];
+        }
+      ArgPart ap;
+      ap.val = bv;
+      ap.pad = 0;
+      ap.idx = bi;
+      apart[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = ap;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ convolution on MFMA
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// A operands of k_conv_mfma: amat[s * 64 + lane] = W[kz = lane % 16][tap k = 4 s + lane / 16]
+// with tap k = ky * px + kx (zero for kz >= pz or k >= px * py). W is H or, for the
+// correlation, H flipped on every axis.
+__global__ void k_mfma_prep(const float* __restrict__ H, int px, int py, int pz, int steps,
+                            int flip, float* __restrict__ amat) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= steps * 64) return;
+  const int lane = i & 63, s = i >> 6;
+  const int kz = lane & 15;
+  const int k = 4 * s + (lane >> 4);
+  float v = 0.f;
+  if (kz < pz && k < px * py) {
+    const int ky = k / px, kx = k - ky * px;
+    const int sz = flip ? pz - 1 - kz : kz;
+    const int sy = flip ? py - 1 - ky : ky;
+    const int sx = flip ? px - 1 - kx : kx;
+    v = H[((size_t)sz * py + sy) * px + sx];
+  }
+  amat[i] = v;
+}
+
+// out[z][y][x] = sum_{kz,ky,kx} W[kz][ky][kx] in[z + cz - kz][y + cy - ky][x + cx - kx] on the
+// matrix cores (pz <= 16, px * py <= 4 * STEPS; amat holds STEPS steps, zero past the taps).
+// A block owns 16 consecutive x of 4 rows y (one wave per row) and streams the input planes
+// zi = 0 .. nz-1. For each plane the in-plane taps form the K dimension of a chain of
+// v_mfma_f32_16x16x4_f32 with A = W[kz][tap] (registers), B[tap][n] =
+// in[zi][y + cy - ky][x0 + n + cx - kx] and accumulator rows indexed by kz: row j holds the
+// partial sum of output plane zi - cz + j. After a plane row 0 is complete and is stored,
+// and the rows roll up by one. The block stages each plane's (16 + px - 1) x (4 + py - 1)
+// input patch (zero outside the volume) in a ring of LDS buffers, with the global loads
+// issued three planes ahead.
+// Accumulator layout (16x16x4 f32): lane l holds rows 4 (l / 16) + 0..3 of column l % 16.
+template <int STEPS, int EPI>
+__global__ __launch_bounds__(256) void k_conv_mfma(
+    const float* __restrict__ in, const float* __restrict__ amat, int px, int py, int pz,
+    int nx, int ny, int nz, float* __restrict__ out, const float* __restrict__ yobs,
+    double* __restrict__ dpart) {
+  constexpr int NBUF = 4;
+  constexpr int PLANE = kMfmaPatchMax;
+  __shared__ float patch[NBUF][PLANE];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int n = lane & 15, g = lane >> 4;
+  const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4;
+  const int y = y0 + wave, x = x0 + n;
+  const int cx = (px - 1) / 2, cy = (py - 1) / 2, cz = (pz - 1) / 2;
+  const size_t nxy = (size_t)nx * ny;
+  const int PW = 16 + px - 1, PH = 4 + py - 1, PN = PW * PH;
+
+  // staging: thread owns patch elements tid and tid + 256 (in-plane offset, -1 = zero)
+  int goff[2];
+  bool lown[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int e = tid + 256 * j;
+    lown[j] = e < PN;
+    goff[j] = -1;
+    if (lown[j]) {
+      const int row = e / PW, col = e - (e / PW) * PW;
+      const int iy = y0 + cy - (py - 1) + row, ix = x0 + cx - (px - 1) + col;
+      if (iy >= 0 && iy < ny && ix >= 0 && ix < nx) goff[j] = iy * nx + ix;
+    }
+  }
+  auto fetch = [&](int plane, int j) -> float {
+    const bool ok = plane < nz && goff[j] >= 0;
+    const float t = in[(size_t)min(plane, nz - 1) * nxy + max(goff[j], 0)];
+    return ok ? t : 0.f;
+  };
+  // B operand addresses inside a plane buffer
+  float a[STEPS];
+  int boff[STEPS];
+#pragma unroll
+  for (int s = 0; s < STEPS; ++s) {
+    a[s] = amat[s * 64 + lane];
+    const int k = 4 * s + g;
+    int o = 0;
+    if (k < px * py) {
+      const int ky = k / px, kx = k - ky * px;
+      o = (wave + py - 1 - ky) * PW + n + px - 1 - kx;
+    }
+    boff[s] = o;
+  }
+  // prologue: planes 0 and 1 in LDS, plane 2 in flight
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+    if (lown[j]) {
+      patch[0][tid + 256 * j] = fetch(0, j);
+      patch[1][tid + 256 * j] = fetch(1, j);
+    }
+  float st1[2] = {fetch(2, 0), fetch(2, 1)};
+  const bool out_lane = g == 0 && x < nx && y < ny;
+  const size_t col = (size_t)min(y, ny - 1) * nx + min(x, nx - 1);
+  float ynext = 0.f;
+  if (EPI == kEpiResidual) ynext = yobs[col];  // plane 0, used when zo = 0
+  __syncthreads();
+
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  float ssf = 0.f;
+  for (int zi = 0; zi < nz + cz; ++zi) {
+    const float st0[2] = {fetch(zi + 3, 0), fetch(zi + 3, 1)};
+    const int zo = zi - cz;
+    float ycur = 0.f;
+    if (EPI == kEpiResidual && zo >= 0) {
+      ycur = ynext;
+      ynext = yobs[(size_t)min(zo + 1, nz - 1) * nxy + col];
+    }
+    if (zi < nz) {
+      const float* buf = patch[zi & (NBUF - 1)];
+      float b[STEPS];
+#pragma unroll
+      for (int s = 0; s < STEPS; ++s) b[s] = buf[boff[s]];
+#pragma unroll
+      for (int s = 0; s < STEPS; ++s)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
+    }
+    if (zo >= 0 && out_lane) {
+      const size_t v = (size_t)zo * nxy + col;
+      if (EPI == kEpiPlain) {
+        out[v] = acc[0];
+      } else {
+        const float rv = ycur - acc[0];
+        out[v] = rv;
+        ssf = fmaf(rv, rv, ssf);
+      }
+    }
+    const float up = __shfl_down(acc[0], 16, 64);
+    acc[0] = acc[1];
+    acc[1] = acc[2];
+    acc[2] = acc[3];
+    acc[3] = g < 3 ? up : 0.f;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (lown[j]) patch[(zi + 2) & (NBUF - 1)][tid + 256 * j] = st1[j];
+    st1[0] = st0[0];
+    st1[1] = st0[1];
+    __syncthreads();
+  }
+  if (EPI == kEpiResidual) {
+    double ss = shfl_sum_d((double)ssf);
+    if (lane == 0) dpart[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + wave] = ss;
+  }
+}
+
+// ------------------------------------------------------------------ gradient sums
+
+// Per-atom sums over a tile of voxels (block = 256 (y, x) columns x VPT z); grid.x = tiles,
+// grid.y = atom groups. Writes gpart[tile][atom][0..5] =
+// (S_g, S_u, S_l, S_mx, S_my, S_mz) of the tile (see launch_grad_finalize).
+template <int VPT>
+__global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__ ak, int n,
+                                                       int apg, const float* __restrict__ q,
+                                                       int nx, int ny, int nz, int ntile_xy,
+                                                       float* __restrict__ gpart) {
+  constexpr int NW = kGradThreads / 64;
+  __shared__ float red[NW][kGradMaxAtomsPerGroup][6];
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int txy = tile % ntile_xy;
+  const int tz = tile / ntile_xy;
+  const int nxy = nx * ny;
+  const int p = txy * kGradThreads + tid;
+  const bool pin = p < nxy;
+  const int pp = pin ? p : 0;
+  const int y = pp / nx;
+  const int x = pp - y * nx;
+  const int z0 = tz * VPT;
+  float qv[VPT];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j)
+    qv[j] = (pin && z0 + j < nz) ? q[(size_t)(z0 + j) * nxy + p] : 0.f;
+  const float fx = (float)x, fy = (float)y, fz0 = (float)z0;
+  const int a0 = blockIdx.y * apg;
+  const int a1 = min(n, a0 + apg);
+  const int wave = tid / 64;
+  for (int a = a0; a < a1; ++a) {
+    const AtomK k = ak[a];
+    const float dx = fx - k.mx;
+    const float dy = fy - k.my;
+    const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
+    const float dz0 = fz0 - k.mz;
+    float sg = 0.f, su = 0.f, sl = 0.f, sc = 0.f, scz = 0.f;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const float dz = dz0 + (float)j;
+      const float r2 = fmaf(dz, dz, dxy2);
+      const float l = fast_log2(r2);
+      const float vp = fast_exp2(fmaf(k.hdm1, l, k.c));  // u log2(e) / r^2
+      const float up = vp * r2;                           // u log2(e)
+      const float g = fast_exp2(-up);
+      const float qg = qv[j] * g;
+      sg += qg;
+      const float qgu = qg * up;
+      su += qgu;
+      sl = fmaf(qgu, l, sl);
+      const float c2 = qg * vp;
+      sc += c2;
+      scz = fmaf(c2, dz, scz);
+    }
+    const float s0 = wave_sum(sg);
+    const float s1 = wave_sum(su);
+    const float s2 = wave_sum(sl);
+    const float s3 = wave_sum(sc * dx);
+    const float s4 = wave_sum(sc * dy);
+    const float s5 = wave_sum(scz);
+    if ((tid & 63) == 0) {
+      float* rr = red[wave][a - a0];
+      rr[0] = s0;
+      rr[1] = s1;
+      rr[2] = s2;
+      rr[3] = s3;
+      rr[4] = s4;
+      rr[5] = s5;
+    }
+  }
+  __syncthreads();
+  const int cnt = (a1 - a0) * 6;
+  for (int i = tid; i < cnt; i += kGradThreads) {
+    const int aa = i / 6, c = i - aa * 6;
+    float t = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += red[w][aa][c];
+    gpart[((size_t)tile * n + a0 + aa) * 6 + c] = t;
+  }
+}
+
+// Block per atom (blockIdx.x < n) plus one block for the loss (blockIdx.x == n).
+__global__ __launch_bounds__(256) void k_grad_finalize(
+    const float* __restrict__ gpart, int ntiles, int n, const double* __restrict__ loss_part,
+    int nloss, const sfw_atom* __restrict__ atoms, float lambda, double* __restrict__ sums,
+    sfw_atom* __restrict__ grad_out, double* __restrict__ loss_out) {
+  __shared__ double red[6][4];
+  const int tid = threadIdx.x;
+  const int a = blockIdx.x;
+  if (a < n) {
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = tid; t < ntiles; t += 256) {
+      const float* g = gpart + ((size_t)t * n + a) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) s[c] += (double)g[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      double v = shfl_sum_d(s[c]);
+      if ((tid & 63) == 0) red[c][tid / 64] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double S[6];
+      for (int c = 0; c < 6; ++c) S[c] = red[c][0] + red[c][1] + red[c][2] + red[c][3];
+      for (int c = 0; c < 6; ++c) sums[(size_t)a * 6 + c] = S[c];
+      if (grad_out) {
+        const sfw_atom at = atoms[a];
+        const double w = at.w, d = at.d, sg = at.sigma;
+        sfw_atom g;
+        g.w = (float)((double)lambda - S[0]);
+        const double fm = -w * d * kLn2;
+        g.mx = (float)(fm * S[3]);
+        g.my = (float)(fm * S[4]);
+        g.mz = (float)(fm * S[5]);
+        g.sigma = (float)(-w * (d / sg) * kLn2 * S[1]);
+        g.d = (float)(w * (0.5 * kLn2 * kLn2 * S[2] - log(sg) * kLn2 * S[1]));
+        grad_out[a] = g;
+      }
+    }
+  } else {
+    double s = 0.0;
+    if (loss_part)
+      for (int t = tid; t < nloss; t += 256) s += loss_part[t];
+    s = shfl_sum_d(s);
+    if ((tid & 63) == 0) red[0][tid / 64] = s;
+    __syncthreads();
+    if (tid == 0) {
+      const double ss = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+      double wsum = 0.0;
+      if (atoms)
+        for (int i = 0; i < n; ++i) wsum += (double)atoms[i].w;
+      const double loss = 0.5 * ss + (double)lambda * wsum;
+      sums[(size_t)n * 6] = loss;
+      sums[(size_t)n * 6 + 1] = 0.5 * ss;
+      if (loss_out) *loss_out = loss;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ certificate maximum
+
+__global__ __launch_bounds__(256) void k_argmax_final(const ArgPart* __restrict__ apart,
+                                                      int nparts, int nx, int ny, int nz, int nd,
+                                                      sfw_argmax* __restrict__ best) {
+  const int tid = threadIdx.x;
+  float bv = -INFINITY;
+  long long bi = 0x7fffffffffffffffLL;
+  for (int i = tid; i < nparts; i += 256) {
+    const ArgPart ap = apart[i];
+    if (arg_better(ap.val, ap.idx, bv, bi)) {
+      bv = ap.val;
+      bi = ap.idx;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const float ov = __shfl_xor(bv, o, 64);
+    const long long oi = __shfl_xor(bi, o, 64);
+    if (arg_better(ov, oi, bv, bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  __shared__ float rv[4];
+  __shared__ long long ri[4];
+  if ((tid & 63) == 0) {
+    rv[tid / 64] = bv;
+    ri[tid / 64] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 1; i < 4; ++i)
+      if (arg_better(rv[i], ri[i], bv, bi)) {
+        bv = rv[i];
+        bi = ri[i];
+      }
+    sfw_argmax b;
+    b.eta = bv;
+    const long long V = (long long)nx * ny * nz;
+    long long v = bi % V;
+    const long long slice = bi / V;
+    b.i_sigma = (int)(slice / nd);
+    b.i_d = (int)(slice % nd);
+    b.z = (int)(v / ((long long)nx * ny));
+    v -= (long long)b.z * nx * ny;
+    b.y = (int)(v / nx);
+    b.x = (int)(v - (long long)b.y * nx);
+    *best = b;
+  }
+}
+
+// ------------------------------------------------------------------ LASSO dot products
+
+// dpart[block][c] = partial sum over the block's voxels of a * cols[c] (c < k), a * y (c = k).
+__global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
+                                              const float* __restrict__ cols, int k,
+                                              size_t colstride, const float* __restrict__ y,
+                                              size_t nvox, double* __restrict__ dpart) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (int c = 0; c <= k; ++c) {
+    const float* b = c < k ? cols + (size_t)c * colstride : y;
+    double s = 0.0;
+    for (size_t v = (size_t)blockIdx.x * 256 + tid; v < nvox; v += stride)
+      s += (double)a[v] * (double)b[v];
+    s = shfl_sum_d(s);
+    if ((tid & 63) == 0) red[tid / 64] = s;
+    __syncthreads();
+    if (tid == 0) dpart[(size_t)blockIdx.x * (k + 1) + c] = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ dpart, int nblocks,
+                                                    int k1, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int b = tid; b < nblocks; b += 256) s += dpart[(size_t)b * k1 + c];
+  s = shfl_sum_d(s);
+  if ((tid & 63) == 0) red[tid / 64] = s;
+  __syncthreads();
+  if (tid == 0) out[c] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_any_nonfinite(const float* __restrict__ v, size_t n,
+                                                       int* __restrict__ flag) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  bool bad = false;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const float x = v[i];
+    bad |= !(x - x == 0.f);  // false for NaN and +-Inf
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz) {
+  ConvPlan p;
+  p.px = px;
+  p.py = py;
+  p.pz = pz;
+  const int LX = kConvTX + px - 1;
+  // z taps per pass: the smallest of 4 / 8 / 16 covering pz, reduced while even a single
+  // y tap per pass would not fit the LDS budget
+  p.kz = pz <= 4 ? 4 : (pz <= 8 ? 8 : 16);
+  while (p.kz > 4 && (size_t)LX * kConvTY * conv_tile_lzp(p.kz) * 4 > (size_t)kConvMaxLds)
+    p.kz /= 2;
+  p.kzp = (pz + p.kz - 1) / p.kz * p.kz;
+  const int LZ = conv_tile_lzp(p.kz);
+  int kyc = py;
+  while (kyc > 1 && (size_t)LX * (kConvTY + kyc - 1) * LZ * 4 > (size_t)kConvMaxLds) --kyc;
+  p.kyc = kyc;
+  p.lds_bytes = (size_t)LX * (kConvTY + kyc - 1) * LZ * 4;
+  p.grid = dim3((vol.nx + kConvTX - 1) / kConvTX, (vol.ny + kConvTY - 1) / kConvTY,
+                (vol.nz + kConvRZ - 1) / kConvRZ);
+  p.nblocks = (int)(p.grid.x * p.grid.y * p.grid.z);
+  return p;
+}
+
+GradPlan plan_grad(sfw_dims vol, int n_atoms) {
+  GradPlan p;
+  p.vpt = vol.nz >= 64 ? 64 : (vol.nz >= 32 ? 32 : 16);
+  const int nxy = vol.nx * vol.ny;
+  p.ntile_xy = (nxy + kGradThreads - 1) / kGradThreads;
+  p.ntile_z = (vol.nz + p.vpt - 1) / p.vpt;
+  p.ntiles = p.ntile_xy * p.ntile_z;
+  const int target_blocks = 512;
+  int groups = (target_blocks + p.ntiles - 1) / p.ntiles;
+  if (groups > n_atoms) groups = n_atoms;
+  if (groups < 1) groups = 1;
+  int apg = (n_atoms + groups - 1) / groups;
+  if (apg > kGradMaxAtomsPerGroup) apg = kGradMaxAtomsPerGroup;
+  if (apg < 1) apg = 1;
+  p.apg = apg;
+  p.groups = (n_atoms + apg - 1) / apg;
+  if (p.groups < 1) p.groups = 1;
+  return p;
+}
+
+hipError_t launch_psf_prep(const float* H, sfw_dims psf, int kzp, bool flip, float* out,
+                           hipStream_t st) {
+  const int total = psf.nx * psf.ny * kzp;
+  hipLaunchKernelGGL(k_psf_prep, dim3((total + 255) / 256), dim3(256), 0, st, H, psf.nx, psf.ny,
+                     psf.nz, kzp, flip ? 1 : 0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_atom_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* out,
+                            hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_atom_prep, dim3((n + 63) / 64), dim3(64), 0, st, atoms, n,
+                     unit_weight ? 1 : 0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st) {
+  const int nxy = vol.nx * vol.ny;
+  dim3 grid((nxy + 255) / 256, (vol.nz + kRenderVPT - 1) / kRenderVPT);
+  hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
+  return hipGetLastError();
+}
+
+template <int KZ, int EPI>
+static hipError_t conv_t(const ConvPlan& p, const float* in, const float* wt, sfw_dims vol,
+                         float* out, const float* yobs, double* dpart, float scale,
+                         long long idx_base, ArgPart* apart, hipStream_t st) {
+  hipLaunchKernelGGL((k_conv<kConvTX, kConvTY, kConvRZ, KZ, EPI>), p.grid,
+                     dim3(kConvTX * kConvTY), p.lds_bytes, st, in, wt, p.px, p.py, p.pz, p.kzp,
+                     p.kyc, vol.nx, vol.ny, vol.nz, out, yobs, dpart, scale, idx_base, apart);
+  return hipGetLastError();
+}
+
+template <int EPI>
+static hipError_t conv_kz(const ConvPlan& p, const float* in, const float* wt, sfw_dims vol,
+                          float* out, const float* yobs, double* dpart, float scale,
+                          long long idx_base, ArgPart* apart, hipStream_t st) {
+  switch (p.kz) {
+    case 4:
+      return conv_t<4, EPI>(p, in, wt, vol, out, yobs, dpart, scale, idx_base, apart, st);
+    case 8:
+      return conv_t<8, EPI>(p, in, wt, vol, out, yobs, dpart, scale, idx_base, apart, st);
+    default:
+      return conv_t<16, EPI>(p, in, wt, vol, out, yobs, dpart, scale, idx_base, apart, st);
+  }
+}
+
+hipError_t launch_conv(const ConvPlan& p, const float* in, const float* wt, sfw_dims vol, int epi,
+                       float* out, const float* yobs, double* dpart, float scale,
+                       long long idx_base, ArgPart* apart, hipStream_t st) {
+  switch (epi) {
+    case kEpiPlain:
+      return conv_kz<kEpiPlain>(p, in, wt, vol, out, yobs, dpart, scale, idx_base, apart, st);
+    case kEpiResidual:
+      return conv_kz<kEpiResidual>(p, in, wt, vol, out, yobs, dpart, scale, idx_base, apart, st);
+    default:
+      return conv_kz<kEpiArgmax>(p, in, wt, vol, out, yobs, dpart, scale, idx_base, apart, st);
+  }
+}
+
+bool mfma_conv_ok(int px, int py, int pz) {
+  return pz <= 16 && px * py <= 4 * 32 && (16 + px - 1) * (4 + py - 1) <= kMfmaPatchMax;
+}
+
+// MFMA steps (4 taps each) actually run: the smallest instantiated count covering px * py.
+int mfma_steps(int px, int py) {
+  const int need = (px * py + 3) / 4;
+  const int counts[] = {1, 3, 7, 13, 21, 32};
+  for (int c : counts)
+    if (need <= c) return c;
+  return 32;
+}
+
+hipError_t launch_mfma_prep(const float* H, sfw_dims psf, bool flip, float* amat, hipStream_t st) {
+  const int steps = mfma_steps(psf.nx, psf.ny);
+  hipLaunchKernelGGL(k_mfma_prep, dim3((steps * 64 + 255) / 256), dim3(256), 0, st, H, psf.nx,
+                     psf.ny, psf.nz, steps, flip ? 1 : 0, amat);
+  return hipGetLastError();
+}
+
+int mfma_conv_blocks(sfw_dims vol) { return ((vol.nx + 15) / 16) * ((vol.ny + 3) / 4); }
+
+template <int STEPS, int EPI>
+static hipError_t mfma_t(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
+                         float* out, const float* yobs, double* dpart, hipStream_t st) {
+  dim3 grid((vol.nx + 15) / 16, (vol.ny + 3) / 4);
+  hipLaunchKernelGGL((k_conv_mfma<STEPS, EPI>), grid, dim3(256), 0, st, in, amat, psf.nx, psf.ny,
+                     psf.nz, vol.nx, vol.ny, vol.nz, out, yobs, dpart);
+  return hipGetLastError();
+}
+
+template <int EPI>
+static hipError_t mfma_e(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
+                         float* out, const float* yobs, double* dpart, hipStream_t st) {
+  switch (mfma_steps(psf.nx, psf.ny)) {
+    case 1: return mfma_t<1, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
+    case 3: return mfma_t<3, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
+    case 7: return mfma_t<7, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
+    case 13: return mfma_t<13, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
+    case 21: return mfma_t<21, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
+    default: return mfma_t<32, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
+  }
+}
+
+hipError_t launch_conv_mfma(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
+                            int epi, float* out, const float* yobs, double* dpart,
+                            hipStream_t st) {
+  if (epi == kEpiResidual) return mfma_e<kEpiResidual>(in, amat, psf, vol, out, yobs, dpart, st);
+  return mfma_e<kEpiPlain>(in, amat, psf, vol, out, yobs, dpart, st);
+}
+
+hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q, sfw_dims vol,
+                       float* gpart, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(p.ntiles, p.groups);
+  switch (p.vpt) {
+    case 64:
+      hipLaunchKernelGGL(k_grad<64>, grid, dim3(kGradThreads), 0, st, ak, n, p.apg, q, vol.nx,
+                         vol.ny, vol.nz, p.ntile_xy, gpart);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_grad<32>, grid, dim3(kGradThreads), 0, st, ak, n, p.apg, q, vol.nx,
+                         vol.ny, vol.nz, p.ntile_xy, gpart);
+      break;
+    default:
+      hipLaunchKernelGGL(k_grad<16>, grid, dim3(kGradThreads), 0, st, ak, n, p.apg, q, vol.nx,
+                         vol.ny, vol.nz, p.ntile_xy, gpart);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const double* loss_part,
+                                int nloss, const sfw_atom* atoms, float lambda, double* sums,
+                                sfw_atom* grad_out, double* loss_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_finalize, dim3(n + 1), dim3(256), 0, st, gpart, ntiles, n, loss_part,
+                     nloss, atoms, lambda, sums, grad_out, loss_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
+                               sfw_argmax* best, hipStream_t st) {
+  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(256), 0, st, apart, nparts, vol.nx, vol.ny,
+                     vol.nz, nd, best);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(const float* a, const float* cols, int k, size_t colstride,
+                       const float* y, size_t nvox, double* dpart, int nblocks, double* out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_dots, dim3(nblocks), dim3(256), 0, st, a, cols, k, colstride, y, nvox,
+                     dpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dots_final, dim3(k + 1), dim3(256), 0, st, dpart, nblocks, k + 1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_any_nonfinite(const float* v, size_t n, int* flag, hipStream_t st) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_any_nonfinite, dim3((unsigned)blocks), dim3(256), 0, st, v, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace sfw

@@ -1,0 +1,50 @@
+// Internal operator layer shared by the C ABI (sfw_api.cpp) and the solver (sfw_solver.cpp).
+#pragma once
+
+#include <vector>
+
+#include "sfw_internal.h"
+
+namespace sfw {
+
+int check_dims(const sfw_dims& d, const char* what);
+int check_psf(const sfw_dims& p);
+int check_ws_fit(const sfw_workspace* ws, const sfw_dims& vol, const sfw_dims* psf, int n);
+int check_lambda(float lambda);
+
+// How the PSF convolutions of one volume shape run: on the matrix cores when the PSF fits
+// k_conv_mfma (pz <= 16, px * py <= 128), else on the LDS-tiled VALU kernel. The environment
+// variable SFW_CONV=valu forces the VALU kernel (used by the tests to cover both).
+struct PsfPlan {
+  sfw_dims psf{1, 1, 1};
+  ConvPlan valu;
+  bool mfma = false;
+  int nres = 0;  // number of loss partials the residual epilogue writes
+};
+PsfPlan plan_psf(const sfw_dims& vol, const sfw_dims& psf);
+// Build the forward (convolution) and / or adjoint (correlation) copies of H.
+int prep_psf(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool adj);
+// out = H * in (adjoint = false) or correlation with H (adjoint = true); epilogue as launch_conv.
+int conv_psf(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjoint,
+             const float* in, float* out, int epi, const float* yobs);
+// ws->ak must hold the n atoms' constants.
+int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, float* phi);
+// r = y - H * f (into r_out or ws->r), q = Phi^T r (ws->q), per-atom sums and loss in ws->dres:
+// dres[6a + c] (see launch_grad_finalize), dres[6n] = C, dres[6n + 1] = 1/2 ||r||^2.
+int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
+             float lambda, const sfw_atom* atoms_dev, int n, float* r_out, double* loss_out,
+             sfw_atom* grad_out);
+// eta and its gradient at n points theta = (mx, my, mz, sigma, d) (host, float64); syncs.
+int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double lambda,
+                  const double* thetas, int n, double* eta_out, double* grad_out);
+// Grid certificate of q; the maximum lands in ws->best (device).
+int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float lambda,
+                   const float* sg, int ns, const float* dg, int nd, float T, float* eta_out);
+// LASSO columns for unit-weight atoms i in [i0, i1) already staged in ws->ak.
+int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int i0, int i1);
+// out[0..i] = <a_i, a_j> (j <= i), out[i + 1] = <a_i, y>, float64 on the device.
+int op_gram_row(sfw_workspace* ws, const sfw_dims& vol, const float* y, int i, double* out);
+// min_{w >= 0} 1/2 w^T G w - c^T w.
+int nnqp(const std::vector<double>& G, const std::vector<double>& c, int k, std::vector<double>& w);
+
+}  // namespace sfw

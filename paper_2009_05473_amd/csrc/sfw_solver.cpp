@@ -1,0 +1,653 @@
+// sfw_solve: SFW (algorithm 1) and BSFW (algorithm 2) driven from the host in float64, with
+// every volume operation (render, blur, residual, adjoint, gradient sums, grid certificate,
+// LASSO columns and Gram entries) on the GPU through the operator layer.
+//
+// Local ascent of eta (step 1) and the sliding descent of C (SFW step 4, BSFW step 2b) use a
+// box-bounded limited-memory BFGS; the weights-only LASSO (step 3) is a non-negative
+// quadratic program solved by a primal active-set method.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <functional>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "sfw_internal.h"
+#include "sfw_ops.h"
+
+namespace sfw {
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double secs(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double>(b - a).count();
+}
+
+// Cholesky of the s x s matrix A (row-major, lower factor in place). False if not SPD.
+bool cholesky(std::vector<double>& A, int s) {
+  for (int j = 0; j < s; ++j) {
+    double d = A[(size_t)j * s + j];
+    for (int k = 0; k < j; ++k) d -= A[(size_t)j * s + k] * A[(size_t)j * s + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    A[(size_t)j * s + j] = d;
+    for (int i = j + 1; i < s; ++i) {
+      double v = A[(size_t)i * s + j];
+      for (int k = 0; k < j; ++k) v -= A[(size_t)i * s + k] * A[(size_t)j * s + k];
+      A[(size_t)i * s + j] = v / d;
+    }
+  }
+  return true;
+}
+
+void chol_solve(const std::vector<double>& L, int s, std::vector<double>& b) {
+  for (int i = 0; i < s; ++i) {
+    double v = b[i];
+    for (int k = 0; k < i; ++k) v -= L[(size_t)i * s + k] * b[k];
+    b[i] = v / L[(size_t)i * s + i];
+  }
+  for (int i = s - 1; i >= 0; --i) {
+    double v = b[i];
+    for (int k = i + 1; k < s; ++k) v -= L[(size_t)k * s + i] * b[k];
+    b[i] = v / L[(size_t)i * s + i];
+  }
+}
+
+// z_P = G_PP^{-1} c_P (ridge added if G_PP is singular, as duplicate atoms make it).
+void solve_passive(const std::vector<double>& G, const std::vector<double>& c, int k,
+                   const std::vector<int>& P, std::vector<double>& z) {
+  const int s = (int)P.size();
+  std::vector<double> A((size_t)s * s), b(s);
+  double tr = 0.0;
+  for (int i = 0; i < s; ++i) {
+    for (int j = 0; j < s; ++j) A[(size_t)i * s + j] = G[(size_t)P[i] * k + P[j]];
+    b[i] = c[P[i]];
+    tr += A[(size_t)i * s + i];
+  }
+  std::vector<double> L = A;
+  if (!cholesky(L, s)) {
+    L = A;
+    const double ridge = 1e-12 * tr / std::max(s, 1);
+    for (int i = 0; i < s; ++i) L[(size_t)i * s + i] += ridge;
+    if (!cholesky(L, s)) {
+      for (int i = 0; i < s; ++i) L[(size_t)i * s + i] += 1e-6 * tr / std::max(s, 1);
+      cholesky(L, s);
+    }
+  }
+  chol_solve(L, s, b);
+  z.assign(k, 0.0);
+  for (int i = 0; i < s; ++i) z[P[i]] = b[i];
+}
+
+}  // namespace
+
+int nnqp(const std::vector<double>& G, const std::vector<double>& c, int k,
+         std::vector<double>& w) {
+  w.assign(k, 0.0);
+  if (k == 0) return SFW_OK;
+  std::vector<char> passive(k, 0);
+  double scale = 0.0;
+  for (int i = 0; i < k; ++i) scale = std::max(scale, std::fabs(c[i]));
+  const double tol = 1e-13 * std::max(scale, 1e-300);
+  std::vector<double> z;
+  for (int outer = 0; outer < 4 * k + 20; ++outer) {
+    // gradient of 1/2 w'Gw - c'w
+    int jbest = -1;
+    double gbest = -tol;
+    for (int i = 0; i < k; ++i) {
+      if (passive[i]) continue;
+      double g = -c[i];
+      for (int j = 0; j < k; ++j) g += G[(size_t)i * k + j] * w[j];
+      if (g < gbest) {
+        gbest = g;
+        jbest = i;
+      }
+    }
+    if (jbest < 0) return SFW_OK;
+    passive[jbest] = 1;
+    for (int inner = 0; inner < 4 * k + 20; ++inner) {
+      std::vector<int> P;
+      for (int i = 0; i < k; ++i)
+        if (passive[i]) P.push_back(i);
+      solve_passive(G, c, k, P, z);
+      bool feasible = true;
+      for (int i : P)
+        if (!(z[i] > 0.0)) feasible = false;
+      if (feasible) {
+        w = z;
+        break;
+      }
+      double alpha = 1.0;
+      for (int i : P)
+        if (!(z[i] > 0.0)) {
+          const double den = w[i] - z[i];
+          const double a = den > 0.0 ? w[i] / den : 0.0;
+          alpha = std::min(alpha, a);
+        }
+      for (int i = 0; i < k; ++i) w[i] += alpha * (z[i] - w[i]);
+      bool moved = false;
+      for (int i : P)
+        if (w[i] <= 1e-15 * std::max(1.0, std::fabs(z[i]))) {
+          passive[i] = 0;
+          w[i] = 0.0;
+          moved = true;
+        }
+      if (!moved) {  // numerically stuck: drop the most negative member
+        int worst = P[0];
+        for (int i : P)
+          if (z[i] < z[worst]) worst = i;
+        passive[worst] = 0;
+        w[worst] = 0.0;
+      }
+    }
+  }
+  return SFW_OK;
+}
+
+namespace {
+
+// ------------------------------------------------------------------ box-bounded L-BFGS
+
+struct MinResult {
+  int iterations = 0;
+  int evaluations = 0;
+  bool converged = false;
+  double f = 0.0;
+  int status = SFW_OK;
+};
+
+using FG = std::function<int(const std::vector<double>&, double&, std::vector<double>&)>;
+
+MinResult minimize_box(const FG& fg, std::vector<double>& x, const std::vector<double>& lo,
+                       const std::vector<double>& hi, int m, double gtol, double ftol,
+                       int maxiter) {
+  MinResult res;
+  const int n = (int)x.size();
+  for (int i = 0; i < n; ++i) x[i] = std::min(std::max(x[i], lo[i]), hi[i]);
+  std::vector<double> g(n), gn(n), xn(n), d(n);
+  double f = 0.0, fnew = 0.0;
+  int rc = fg(x, f, g);
+  res.evaluations = 1;
+  if (rc) {
+    res.status = rc;
+    return res;
+  }
+  std::deque<std::vector<double>> S, Y;
+  std::deque<double> RHO;
+  auto at_lo = [&](int i, const std::vector<double>& gg) { return x[i] <= lo[i] && gg[i] > 0; };
+  auto at_hi = [&](int i, const std::vector<double>& gg) { return x[i] >= hi[i] && gg[i] < 0; };
+  for (int it = 0; it < maxiter; ++it) {
+    double pgmax = 0.0;
+    std::vector<char> freev(n);
+    for (int i = 0; i < n; ++i) {
+      freev[i] = !(at_lo(i, g) || at_hi(i, g));
+      if (freev[i]) pgmax = std::max(pgmax, std::fabs(g[i]));
+    }
+    res.iterations = it;
+    if (pgmax <= gtol) {
+      res.converged = true;
+      break;
+    }
+    // two-loop recursion on the free coordinates
+    for (int i = 0; i < n; ++i) d[i] = freev[i] ? -g[i] : 0.0;
+    const int ms = (int)S.size();
+    std::vector<double> alpha(ms);
+    for (int j = ms - 1; j >= 0; --j) {
+      double a = 0.0;
+      for (int i = 0; i < n; ++i)
+        if (freev[i]) a += S[j][i] * d[i];
+      a *= RHO[j];
+      alpha[j] = a;
+      for (int i = 0; i < n; ++i)
+        if (freev[i]) d[i] -= a * Y[j][i];
+    }
+    if (ms > 0) {
+      double sy = 0.0, yy = 0.0;
+      for (int i = 0; i < n; ++i) {
+        sy += S[ms - 1][i] * Y[ms - 1][i];
+        yy += Y[ms - 1][i] * Y[ms - 1][i];
+      }
+      const double gam = yy > 0 ? sy / yy : 1.0;
+      for (int i = 0; i < n; ++i) d[i] *= gam;
+    }
+    for (int j = 0; j < ms; ++j) {
+      double b = 0.0;
+      for (int i = 0; i < n; ++i)
+        if (freev[i]) b += Y[j][i] * d[i];
+      b *= RHO[j];
+      for (int i = 0; i < n; ++i)
+        if (freev[i]) d[i] += S[j][i] * (alpha[j] - b);
+    }
+    double gd = 0.0, gg = 0.0;
+    for (int i = 0; i < n; ++i) {
+      if (!freev[i]) d[i] = 0.0;
+      gd += g[i] * d[i];
+      if (freev[i]) gg += g[i] * g[i];
+    }
+    if (!(gd < 0.0)) {  // not a descent direction: restart from steepest descent
+      S.clear();
+      Y.clear();
+      RHO.clear();
+      for (int i = 0; i < n; ++i) d[i] = freev[i] ? -g[i] : 0.0;
+      gd = -gg;
+    }
+    double step = 1.0;
+    if (S.empty()) {
+      double dmax = 0.0;
+      for (int i = 0; i < n; ++i) dmax = std::max(dmax, std::fabs(d[i]));
+      step = dmax > 0 ? std::min(1.0, 1.0 / dmax) : 1.0;
+    }
+    bool accepted = false;
+    for (int ls = 0; ls < 40; ++ls) {
+      double dec = 0.0;
+      for (int i = 0; i < n; ++i) {
+        xn[i] = std::min(std::max(x[i] + step * d[i], lo[i]), hi[i]);
+        dec += g[i] * (xn[i] - x[i]);
+      }
+      rc = fg(xn, fnew, gn);
+      res.evaluations++;
+      if (rc) {
+        res.status = rc;
+        return res;
+      }
+      if (std::isfinite(fnew) && fnew <= f + 1e-4 * dec) {
+        accepted = true;
+        break;
+      }
+      step *= (ls < 2 ? 0.5 : 0.25);
+    }
+    if (!accepted) {
+      if (S.empty()) {  // even a steepest-descent step fails: stationary to working precision
+        res.converged = true;
+        break;
+      }
+      S.clear();
+      Y.clear();
+      RHO.clear();
+      continue;
+    }
+    std::vector<double> s(n), yv(n);
+    double sy = 0.0, ss = 0.0, yy = 0.0;
+    for (int i = 0; i < n; ++i) {
+      s[i] = xn[i] - x[i];
+      yv[i] = gn[i] - g[i];
+      sy += s[i] * yv[i];
+      ss += s[i] * s[i];
+      yy += yv[i] * yv[i];
+    }
+    const bool small_dec = (f - fnew) <= ftol * std::max(std::max(std::fabs(f), std::fabs(fnew)), 1.0);
+    x = xn;
+    g = gn;
+    f = fnew;
+    if (sy > 1e-12 * std::sqrt(ss * yy) && sy > 0) {
+      S.push_back(s);
+      Y.push_back(yv);
+      RHO.push_back(1.0 / sy);
+      if ((int)S.size() > m) {
+        S.pop_front();
+        Y.pop_front();
+        RHO.pop_front();
+      }
+    }
+    if (small_dec) {
+      res.iterations = it + 1;
+      res.converged = true;
+      break;
+    }
+    res.iterations = it + 1;
+  }
+  res.f = f;
+  return res;
+}
+
+// ------------------------------------------------------------------ solver state
+
+struct Solver {
+  sfw_workspace* ws;
+  sfw_dims vol;
+  sfw_dims psf;
+  const float* y;
+  const float* H;
+  double lam;
+  sfw_options o;
+  PsfPlan plan;
+  size_t V;
+  sfw_stats st{};
+  // atoms (w, mx, my, mz, sigma, d) in float64
+  std::vector<double> atoms;
+  int k() const { return (int)(atoms.size() / 6); }
+  // LASSO cache: columns valid for indices < ncols_valid, Gram (row-major, max_atoms^2)
+  int ncols_valid = 0;
+  std::vector<double> G, b;
+
+  int upload_atoms(const std::vector<double>& a, bool unit_weight) {
+    const int n = (int)(a.size() / 6);
+    if (n == 0) return SFW_OK;
+    sfw_atom* h = reinterpret_cast<sfw_atom*>(ws->hpin);
+    for (int i = 0; i < n; ++i) {
+      h[i].w = (float)a[6 * i + 0];
+      h[i].mx = (float)a[6 * i + 1];
+      h[i].my = (float)a[6 * i + 2];
+      h[i].mz = (float)a[6 * i + 3];
+      h[i].sigma = (float)a[6 * i + 4];
+      h[i].d = (float)a[6 * i + 5];
+    }
+    SFW_HIP(hipMemcpyAsync(ws->atoms_dev, h, sizeof(sfw_atom) * n, hipMemcpyHostToDevice,
+                           ws->stream));
+    SFW_HIP(launch_atom_prep(ws->atoms_dev, n, unit_weight, ws->ak, ws->stream));
+    // the pinned staging buffer is reused right away by callers: wait for the copy
+    SFW_HIP(hipStreamSynchronize(ws->stream));
+    return SFW_OK;
+  }
+
+  // C and dC/d(atoms) at a (float64 host), r and q left in the workspace.
+  int cgrad(const std::vector<double>& a, double& C, std::vector<double>* grad) {
+    const int n = (int)(a.size() / 6);
+    int rc = upload_atoms(a, false);
+    if (rc) return rc;
+    rc = op_cgrad(ws, plan, vol, y, (float)lam, ws->atoms_dev, n, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    double* hs = ws->hpin + 8 * (size_t)ws->max_atoms + 16;
+    SFW_HIP(hipMemcpyAsync(hs, ws->dres, sizeof(double) * (6 * n + 2), hipMemcpyDeviceToHost,
+                           ws->stream));
+    SFW_HIP(hipStreamSynchronize(ws->stream));
+    st.n_eval_cgrad++;
+    double wsum = 0.0;
+    for (int i = 0; i < n; ++i) wsum += a[6 * i];
+    C = hs[6 * n + 1] + lam * wsum;
+    if (grad) {
+      const double ln2 = 0.69314718055994531;
+      grad->assign(6 * (size_t)n, 0.0);
+      for (int i = 0; i < n; ++i) {
+        const double* S = hs + 6 * i;
+        const double w = a[6 * i], sg = a[6 * i + 4], d = a[6 * i + 5];
+        double* g = grad->data() + 6 * i;
+        g[0] = lam - S[0];
+        g[1] = -w * d * ln2 * S[3];
+        g[2] = -w * d * ln2 * S[4];
+        g[3] = -w * d * ln2 * S[5];
+        g[4] = -w * (d / sg) * ln2 * S[1];
+        g[5] = w * (0.5 * ln2 * ln2 * S[2] - std::log(sg) * ln2 * S[1]);
+      }
+    }
+    return SFW_OK;
+  }
+
+  void theta_bounds(std::vector<double>& lo, std::vector<double>& hi) const {
+    lo = {0.0, 0.0, 0.0, (double)o.sigma_lo, (double)o.d_lo};
+    hi = {vol.nx - 1.0, vol.ny - 1.0, vol.nz - 1.0, (double)o.sigma_hi, (double)o.d_hi};
+  }
+
+  int ascent(std::vector<double>& th, double& eta_star) {
+    std::vector<double> lo, hi;
+    theta_bounds(lo, hi);
+    FG fg = [&](const std::vector<double>& x, double& f, std::vector<double>& g) -> int {
+      double e;
+      g.assign(5, 0.0);
+      int rc = op_eta_points(ws, vol, ws->q, lam, x.data(), 1, &e, g.data());
+      st.n_eval_eta++;
+      f = -e;
+      for (double& v : g) v = -v;
+      return rc;
+    };
+    MinResult r = minimize_box(fg, th, lo, hi, o.lbfgs_memory, o.ascent_gtol, o.ftol,
+                               o.ascent_max_iter);
+    if (r.status) return r.status;
+    std::vector<double> g(5);
+    int rc = op_eta_points(ws, vol, ws->q, lam, th.data(), 1, &eta_star, g.data());
+    st.n_eval_eta++;
+    return rc;
+  }
+
+  int slide() {
+    const int n = k();
+    if (n == 0) return SFW_OK;
+    std::vector<double> lo(6 * (size_t)n), hi(6 * (size_t)n), tl, th;
+    theta_bounds(tl, th);
+    for (int i = 0; i < n; ++i) {
+      lo[6 * i] = 0.0;
+      hi[6 * i] = std::numeric_limits<double>::infinity();
+      for (int c = 0; c < 5; ++c) {
+        lo[6 * i + 1 + c] = tl[c];
+        hi[6 * i + 1 + c] = th[c];
+      }
+    }
+    FG fg = [&](const std::vector<double>& x, double& f, std::vector<double>& g) -> int {
+      return cgrad(x, f, &g);
+    };
+    MinResult r = minimize_box(fg, atoms, lo, hi, o.lbfgs_memory, o.slide_gtol, o.ftol,
+                               o.slide_max_iter);
+    ncols_valid = 0;  // every theta may have moved
+    return r.status;
+  }
+
+  // Weights of the current support by the LASSO (columns cached while theta is unchanged).
+  int lasso() {
+    const int n = k();
+    if (n == 0) return SFW_OK;
+    const int M = ws->max_atoms;
+    if (ncols_valid < n) {
+      int rc = upload_atoms(atoms, true);
+      if (rc) return rc;
+      rc = op_columns(ws, plan, vol, ncols_valid, n);
+      if (rc) return rc;
+      for (int i = ncols_valid; i < n; ++i) {
+        rc = op_gram_row(ws, vol, y, i, ws->dres + (size_t)i * (i + 1) / 2 + i);
+        if (rc) return rc;
+      }
+      const size_t o0 = (size_t)ncols_valid * (ncols_valid + 1) / 2 + ncols_valid;
+      const size_t o1 = (size_t)n * (n + 1) / 2 + n;
+      SFW_HIP(hipMemcpyAsync(ws->hpin + o0, ws->dres + o0, (o1 - o0) * 8, hipMemcpyDeviceToHost,
+                             ws->stream));
+      SFW_HIP(hipStreamSynchronize(ws->stream));
+      G.resize((size_t)M * M);
+      b.resize(M);
+      for (int i = ncols_valid; i < n; ++i) {
+        const double* row = ws->hpin + (size_t)i * (i + 1) / 2 + i;
+        for (int j = 0; j <= i; ++j) G[(size_t)i * M + j] = G[(size_t)j * M + i] = row[j];
+        b[i] = row[i + 1];
+      }
+      ncols_valid = n;
+    }
+    std::vector<double> Gk((size_t)n * n), c(n), w;
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < n; ++j) Gk[(size_t)i * n + j] = G[(size_t)i * M + j];
+      c[i] = b[i] - lam;
+    }
+    int rc = nnqp(Gk, c, n, w);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) atoms[6 * i] = w[i];
+    return SFW_OK;
+  }
+
+  // Remove zero-weighted masses and merge coincident ones; columns of removed or moved atoms
+  // (and of every later index) are invalidated.
+  void prune() {
+    const int n = k();
+    if (n == 0) return;
+    double wmax = 0.0;
+    for (int i = 0; i < n; ++i) wmax = std::max(wmax, atoms[6 * i]);
+    std::vector<double> kept;
+    int first_change = n;
+    int kept_n = 0;
+    for (int i = 0; i < n; ++i) {
+      const double* a = &atoms[6 * i];
+      if (!(wmax > 0.0) || !(a[0] > o.prune_rel * wmax)) {
+        first_change = std::min(first_change, kept_n);
+        continue;
+      }
+      bool merged = false;
+      for (int j = 0; j < kept_n; ++j) {
+        double* bj = &kept[6 * j];
+        double dmax = 0.0;
+        for (int c = 1; c < 6; ++c) dmax = std::max(dmax, std::fabs(a[c] - bj[c]));
+        if (dmax <= o.merge_tol) {
+          const double ws_ = a[0] + bj[0];
+          if (ws_ > 0)
+            for (int c = 1; c < 6; ++c) bj[c] = (bj[0] * bj[c] + a[0] * a[c]) / ws_;
+          bj[0] = ws_;
+          first_change = std::min(first_change, j);
+          merged = true;
+          break;
+        }
+      }
+      if (!merged) {
+        kept.insert(kept.end(), a, a + 6);
+        kept_n++;
+      }
+    }
+    atoms.swap(kept);
+    ncols_valid = std::min(ncols_valid, first_change);
+  }
+};
+
+}  // namespace
+
+}  // namespace sfw
+
+using namespace sfw;
+
+extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const float* H,
+                         sfw_dims psf, float lambda, const sfw_options* opts,
+                         sfw_atom* atoms_out, int cap, int* n_out, sfw_stats* stats) {
+  try {
+    int rc = check_ws_fit(ws, vol, &psf, 0);
+    if (rc) return rc;
+    if (!y || !H) return fail(SFW_EINVAL, "y or H is NULL");
+    if (!n_out) return fail(SFW_EINVAL, "n_out is NULL");
+    if (cap < 0 || (cap > 0 && !atoms_out)) return fail(SFW_EINVAL, "atoms_out/cap invalid");
+    rc = check_lambda(lambda);
+    if (rc) return rc;
+    Solver S;
+    S.ws = ws;
+    S.vol = vol;
+    S.psf = psf;
+    S.y = y;
+    S.H = H;
+    S.lam = lambda;
+    if (opts)
+      S.o = *opts;
+    else
+      sfw_default_options(&S.o);
+    const sfw_options& o = S.o;
+    if (o.mode != SFW_MODE_BSFW && o.mode != SFW_MODE_SFW)
+      return fail(SFW_EINVAL, "opts.mode must be SFW_MODE_BSFW or SFW_MODE_SFW");
+    if (o.n_sigma < 1 || o.n_sigma > SFW_MAX_GRID || o.n_d < 1 || o.n_d > SFW_MAX_GRID)
+      return fail(SFW_EINVAL, "opts grid sizes must be in [1, SFW_MAX_GRID]");
+    if (!(o.sigma_lo > 0) || !(o.sigma_hi >= o.sigma_lo) || !(o.d_lo > 0) || !(o.d_hi >= o.d_lo))
+      return fail(SFW_EINVAL, "opts bounds of sigma / d invalid");
+    for (int i = 0; i < o.n_sigma; ++i)
+      if (!(o.sigma_grid[i] > 0)) return fail(SFW_EINVAL, "opts.sigma_grid must be > 0");
+    for (int j = 0; j < o.n_d; ++j)
+      if (!(o.d_grid[j] > 0)) return fail(SFW_EINVAL, "opts.d_grid must be > 0");
+    if (o.max_iter < 1) return fail(SFW_EINVAL, "opts.max_iter must be >= 1");
+    S.V = (size_t)vol.nx * vol.ny * vol.nz;
+    S.plan = plan_psf(vol, psf);
+    const auto t0 = Clock::now();
+
+    if (o.check_finite) {
+      int* flag = reinterpret_cast<int*>(ws->best + 1);
+      SFW_HIP(hipMemsetAsync(flag, 0, sizeof(int), ws->stream));
+      SFW_HIP(launch_any_nonfinite(y, S.V, flag, ws->stream));
+      SFW_HIP(launch_any_nonfinite(H, (size_t)psf.nx * psf.ny * psf.nz, flag, ws->stream));
+      int hflag = 0;
+      SFW_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, ws->stream));
+      SFW_HIP(hipStreamSynchronize(ws->stream));
+      if (hflag) return fail(SFW_EINVAL, "y or H holds NaN or Inf");
+    }
+    rc = prep_psf(ws, H, S.plan, true, true);
+    if (rc) return rc;
+
+    const float T = o.trunc_T > 0 ? o.trunc_T : 12.0f;
+    bool converged = false;
+    int it = 0;
+    double C = 0.0;
+    for (it = 1; it <= o.max_iter; ++it) {
+      // residual of the current measure, q = Phi^T r, criterion
+      rc = S.cgrad(S.atoms, C, nullptr);
+      if (rc) return rc;
+      // step 1: grid maximum of eta, then local ascent
+      auto tc = Clock::now();
+      rc = op_certificate(ws, vol, ws->q, lambda, o.sigma_grid, o.n_sigma, o.d_grid, o.n_d, T,
+                          nullptr);
+      if (rc) return rc;
+      sfw_argmax best;
+      SFW_HIP(hipMemcpyAsync(&best, ws->best, sizeof(best), hipMemcpyDeviceToHost, ws->stream));
+      SFW_HIP(hipStreamSynchronize(ws->stream));
+      S.st.n_certificates++;
+      auto ta = Clock::now();
+      S.st.seconds_certificate += secs(tc, ta);
+      std::vector<double> th = {(double)best.x, (double)best.y, (double)best.z,
+                                (double)o.sigma_grid[best.i_sigma], (double)o.d_grid[best.i_d]};
+      double eta_star = 0.0;
+      rc = S.ascent(th, eta_star);
+      if (rc) return rc;
+      S.st.seconds_ascent += secs(ta, Clock::now());
+      S.st.last_eta = eta_star;
+      if (o.verbose)
+        std::fprintf(stderr, "[sfw] k=%d C=%.9g grid=%.6g eta*=%.9g atoms=%d\n", it, C, best.eta,
+                     eta_star, S.k());
+      if (eta_star <= 1.0 + o.eta_tol) {
+        if (o.mode == SFW_MODE_BSFW) {  // 2b: final slide, 3b: prune
+          auto ts = Clock::now();
+          rc = S.slide();
+          if (rc) return rc;
+          S.prune();
+          S.st.seconds_slide += secs(ts, Clock::now());
+        }
+        converged = true;
+        break;
+      }
+      // step 2: augment the support
+      if (S.k() + 1 > ws->max_atoms)
+        return fail(SFW_EINVAL, "support grew beyond the workspace's max_atoms");
+      S.atoms.push_back(0.0);
+      S.atoms.insert(S.atoms.end(), th.begin(), th.end());
+      S.st.max_support = std::max(S.st.max_support, S.k());
+      // step 3: weights only
+      auto tl = Clock::now();
+      rc = S.lasso();
+      if (rc) return rc;
+      S.st.seconds_lasso += secs(tl, Clock::now());
+      if (o.mode == SFW_MODE_SFW) {  // step 4: slide all parameters
+        auto ts = Clock::now();
+        rc = S.slide();
+        if (rc) return rc;
+        S.st.seconds_slide += secs(ts, Clock::now());
+      }
+      S.prune();  // SFW step 5 / BSFW step 4
+    }
+    rc = S.cgrad(S.atoms, C, nullptr);
+    if (rc) return rc;
+    const int n = S.k();
+    S.st.iterations = converged ? it : o.max_iter;
+    S.st.converged = converged ? 1 : 0;
+    S.st.n_atoms = n;
+    S.st.criterion = C;
+    S.st.seconds_total = secs(t0, Clock::now());
+    if (stats) *stats = S.st;
+    *n_out = n;
+    if (n > cap) return fail(SFW_ECAP, "more atoms than cap; *n_out holds the count");
+    for (int i = 0; i < n; ++i) {
+      atoms_out[i].w = (float)S.atoms[6 * i + 0];
+      atoms_out[i].mx = (float)S.atoms[6 * i + 1];
+      atoms_out[i].my = (float)S.atoms[6 * i + 2];
+      atoms_out[i].mz = (float)S.atoms[6 * i + 3];
+      atoms_out[i].sigma = (float)S.atoms[6 * i + 4];
+      atoms_out[i].d = (float)S.atoms[6 * i + 5];
+    }
+    if (!converged) return fail(SFW_ENOCONV, "iteration cap reached before eta* <= 1 + eta_tol");
+    return SFW_OK;
+  } catch (const std::exception& e) {
+    return fail(SFW_EINVAL, std::string("exception in sfw_solve: ") + e.what());
+  } catch (...) {
+    return fail(SFW_EINVAL, "unexpected exception in sfw_solve");
+  }
+}

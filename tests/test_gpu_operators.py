@@ -1,0 +1,274 @@
+"""GPU parity of every operator of the C ABI against the FP64 oracle.
+
+Bars (relative L2 unless stated): forward and residual 1e-5, criterion 1e-5 (relative),
+adjoint and grid certificate 1e-5, gradient of C 1e-4 at perturbed (non-stationary)
+parameters, eta at points 1e-5 and its gradient 1e-4, LASSO weights 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_05473_amd import synth
+from tests._common import config_problem, parity_atoms, rel_err, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_05473_amd import _lib
+    return _lib
+
+
+def dev(a, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=dtype))).cuda()
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def say(*msg):
+    print("[case]", *msg, flush=True)
+
+
+CONFIGS = ["c1", "c2", "c3"]
+
+
+@pytest.fixture(params=["auto", "valu"])
+def conv_path(request, monkeypatch):
+    """Run a test on the default PSF convolution (matrix cores when the PSF fits) and on the
+    LDS-tiled VALU kernel."""
+    if request.param == "valu":
+        monkeypatch.setenv("SFW_CONV", "valu")
+    else:
+        monkeypatch.delenv("SFW_CONV", raising=False)
+    return request.param
+
+
+@pytest.fixture(scope="module")
+def ws_big(L):
+    ws = L.Workspace((64, 128, 128), (31, 15, 15), 64)
+    yield ws
+    ws.close()
+
+
+def _problem(name):
+    prob = config_problem(name)
+    atoms = parity_atoms(prob)
+    psf = f32(prob.psf)
+    clean = oracle.blur(oracle.render(prob.shape, prob.atoms_true), psf)
+    y = f32(synth.make_observation(clean, prob.noise_unit, prob.config.noise_rel))
+    return prob, atoms, psf, y
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_forward_parity(L, ws_big, name, conv_path):
+    prob, atoms, psf, _ = _problem(name)
+    say("sfw_forward", name, prob.shape, "atoms", len(atoms), conv_path)
+    phi = L.sfw_forward(ws_big, dev(psf), dev(atoms), prob.shape)
+    torch.cuda.synchronize()
+    want = oracle.blur(oracle.render(prob.shape, atoms), psf)
+    assert rel_l2(phi.cpu().numpy(), want) <= 1e-5
+
+
+EDGE = [
+    # (shape (nz, ny, nx), psf shape, n atoms)
+    ((23, 29, 37), (7, 5, 3), 4),     # ragged in every axis
+    ((8, 8, 8), (15, 9, 9), 3),       # PSF larger than the volume
+    ((5, 70, 33), (1, 1, 1), 5),      # delta PSF: forward equals the render
+    ((1, 1, 1), (3, 3, 3), 1),        # single voxel
+    ((40, 3, 100), (9, 3, 5), 2),     # thin, several ragged x tiles
+    ((17, 16, 16), (17, 1, 1), 2),    # PSF along z only, 17 taps (two z passes)
+]
+
+
+@pytest.mark.parametrize("shape,psf_shape,n", EDGE)
+def test_forward_edge_shapes(L, ws_big, shape, psf_shape, n, conv_path):
+    rng = np.random.default_rng(sum(shape) * 7 + n)
+    psf = f32(np.abs(rng.standard_normal(psf_shape)) + 0.05)
+    atoms = f32(synth.random_atoms(rng, n, shape))
+    atoms[0, 1:4] = np.round(atoms[0, 1:4])  # one centre exactly on a voxel
+    say("sfw_forward edge", shape, psf_shape, n, conv_path)
+    phi = L.sfw_forward(ws_big, dev(psf), dev(atoms), shape)
+    torch.cuda.synchronize()
+    want = oracle.blur(oracle.render(shape, atoms), psf)
+    assert rel_l2(phi.cpu().numpy(), want) <= 1e-5
+    if psf_shape == (1, 1, 1):
+        assert rel_l2(phi.cpu().numpy() / psf[0, 0, 0], oracle.render(shape, atoms)) <= 1e-5
+
+
+def test_forward_no_atoms_is_zero(L, ws_big):
+    psf = f32(synth.gaussian_psf(1.0, 2.0, (15, 9, 9)))
+    say("sfw_forward n=0")
+    phi = L.sfw_forward(ws_big, dev(psf), None, (9, 10, 11))
+    torch.cuda.synchronize()
+    assert np.all(phi.cpu().numpy() == 0.0)
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_residual_grad_parity(L, ws_big, name, conv_path):
+    prob, atoms, psf, y = _problem(name)
+    lam = 0.37 if name != "c3" else 1.3
+    say("sfw_residual_grad", name, prob.shape, "atoms", len(atoms), conv_path)
+    r, loss, grad = L.sfw_residual_grad(ws_big, dev(psf), dev(y), lam, dev(atoms))
+    torch.cuda.synchronize()
+    C, g, r_o, q_o = oracle.criterion_and_grad(y, atoms, psf, lam)
+    assert rel_l2(r.cpu().numpy(), r_o) <= 1e-5
+    assert rel_err(loss.cpu().numpy()[0], C) <= 1e-5
+    gg = grad.cpu().numpy()
+    assert rel_l2(gg, g) <= 1e-4
+    # every parameter block on its own scale
+    for c in range(6):
+        assert rel_l2(gg[:, c], g[:, c]) <= 2e-4, c
+
+
+def test_residual_grad_edge(L, ws_big, conv_path):
+    shape = (23, 29, 37)
+    rng = np.random.default_rng(77)
+    psf = f32(np.abs(rng.standard_normal((9, 5, 7))) + 0.05)
+    psf /= psf.sum()
+    truth = f32(synth.random_atoms(rng, 4, shape, margin=3))
+    y = f32(oracle.blur(oracle.render(shape, truth), psf) + 0.01 * rng.standard_normal(shape))
+    atoms = f32(synth.random_atoms(rng, 4, shape, margin=3))
+    atoms[1, 1:4] = np.round(atoms[1, 1:4])  # centre on a voxel: finite, limit-correct gradient
+    lam = 0.2
+    say("sfw_residual_grad edge", shape)
+    r, loss, grad = L.sfw_residual_grad(ws_big, dev(psf), dev(y), lam, dev(atoms))
+    torch.cuda.synchronize()
+    C, g, r_o, _ = oracle.criterion_and_grad(y, atoms, psf, lam)
+    assert np.all(np.isfinite(grad.cpu().numpy()))
+    assert rel_l2(r.cpu().numpy(), r_o) <= 1e-5
+    assert rel_err(loss.cpu().numpy()[0], C) <= 1e-5
+    assert rel_l2(grad.cpu().numpy(), g) <= 1e-4
+    # no atoms: r = y and C = 1/2 ||y||^2
+    say("sfw_residual_grad n=0")
+    r0, loss0, _ = L.sfw_residual_grad(ws_big, dev(psf), dev(y), lam, None)
+    torch.cuda.synchronize()
+    assert np.array_equal(r0.cpu().numpy(), y.astype(np.float32))
+    assert rel_err(loss0.cpu().numpy()[0], 0.5 * np.sum(y * y)) <= 1e-6
+
+
+def test_adjoint_parity(L, ws_big, conv_path):
+    rng = np.random.default_rng(5)
+    shape = (31, 45, 50)
+    r = f32(rng.standard_normal(shape))
+    psf = f32(rng.standard_normal((15, 9, 9)))
+    say("sfw_adjoint", shape, conv_path)
+    q = L.sfw_adjoint(ws_big, dev(psf), dev(r))
+    torch.cuda.synchronize()
+    assert rel_l2(q.cpu().numpy(), oracle.adjoint(r, psf)) <= 1e-5
+
+
+def test_adjoint_identity_on_gpu(L, ws_big, conv_path):
+    rng = np.random.default_rng(6)
+    shape = (20, 33, 27)
+    f = rng.standard_normal(shape).astype(np.float32)
+    r = rng.standard_normal(shape).astype(np.float32)
+    psf = rng.standard_normal((9, 7, 5)).astype(np.float32)
+    say("adjoint identity", shape)
+    # correlation with flip(H) is the convolution with H, so both sides use sfw_adjoint
+    Hf = L.sfw_adjoint(ws_big, dev(np.ascontiguousarray(psf[::-1, ::-1, ::-1])), dev(f))
+    q = L.sfw_adjoint(ws_big, dev(psf), dev(r))
+    torch.cuda.synchronize()
+    lhs = float(np.sum(Hf.cpu().numpy().astype(np.float64) * r))
+    rhs = float(np.sum(f.astype(np.float64) * q.cpu().numpy()))
+    np.testing.assert_allclose(Hf.cpu().numpy(), oracle.blur(f, psf), rtol=0,
+                               atol=1e-5 * np.abs(psf).sum() * np.abs(f).max())
+    assert abs(lhs - rhs) <= 1e-5 * (np.linalg.norm(f) * np.linalg.norm(r) * np.abs(psf).sum())
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_certificate_parity(L, ws_big, name):
+    prob, atoms, psf, y = _problem(name)
+    lam = 0.9
+    sg, dg = prob.config.sigma_grid, prob.config.d_grid
+    sgf = [float(np.float32(v)) for v in sg]
+    say("sfw_certificate", name, prob.shape)
+    eta, best = L.sfw_certificate(ws_big, dev(psf), dev(y), lam, sgf, dg, want_eta=True)
+    torch.cuda.synchronize()
+    q = oracle.adjoint(y, psf)
+    eta_o = oracle.grid_certificate(q, lam, sgf, dg)
+    e = eta.cpu().numpy()
+    assert rel_l2(e, eta_o) <= 1e-5
+    v_o, idx_o = oracle.grid_argmax(eta_o)
+    assert rel_err(best["eta"], v_o) <= 1e-5
+    idx = (best["i_sigma"], best["i_d"], best["z"], best["y"], best["x"])
+    if idx != idx_o:  # allowed only if the oracle cannot separate the two within the bar
+        assert rel_err(eta_o[idx], v_o) <= 1e-5
+    # the reported maximum is the maximum of the returned grid
+    assert best["eta"] == e.max()
+    assert best["eta"] == e[idx]
+
+
+def test_certificate_argmax_only_matches_grid(L, ws_big):
+    prob, atoms, psf, y = _problem("c1")
+    say("sfw_certificate argmax only")
+    _, b1 = L.sfw_certificate(ws_big, dev(psf), dev(y), 0.5, [1.0, 1.5], [2.0], want_eta=False)
+    eta, b2 = L.sfw_certificate(ws_big, dev(psf), dev(y), 0.5, [1.0, 1.5], [2.0], want_eta=True)
+    torch.cuda.synchronize()
+    assert b1 == b2
+
+
+def test_eta_points_parity(L, ws_big):
+    prob, atoms, psf, y = _problem("c1")
+    lam = 0.8
+    r = f32(y - oracle.blur(oracle.render(prob.shape, atoms[:1]), psf))
+    q = f32(oracle.adjoint(r, psf))
+    rng = np.random.default_rng(9)
+    th = np.zeros((6, 5))
+    th[:, 0:3] = rng.uniform(3, 28, size=(6, 3))
+    th[:, 3] = rng.uniform(0.7, 3.0, size=6)
+    th[:, 4] = rng.uniform(1.3, 2.9, size=6)
+    th[0, 0:3] = np.round(th[0, 0:3])  # on a voxel centre
+    th = f32(th)
+    say("sfw_eta_points", th.shape)
+    eta, grad = L.sfw_eta_points(ws_big, prob.shape, dev(q), lam, th)
+    for i in range(th.shape[0]):
+        e_o, g_o = oracle.eta_point(q, lam, th[i])
+        assert rel_err(eta[i], e_o) <= 1e-5
+        assert rel_l2(grad[i], g_o) <= 1e-4
+
+
+def test_lasso_parity(L, ws_big):
+    prob, _, psf, y = _problem("c1")
+    thetas = f32(prob.atoms_true[:, 1:6])
+    atoms = np.hstack([np.zeros((len(thetas), 1)), thetas])
+    lam = 0.05 * oracle.max_grid_certificate(y, psf, prob.config.sigma_grid, prob.config.d_grid)
+    lam = float(np.float32(lam))
+    say("sfw_lasso_weights c1", len(atoms))
+    w = L.sfw_lasso_weights(ws_big, dev(psf), dev(y), lam, dev(atoms)).cpu().numpy()
+    w_o, G, b = oracle.lasso_weights(y, thetas, psf, lam)
+    assert rel_l2(w, w_o) <= 1e-4
+    grad = G @ w - b + lam
+    assert np.all(np.abs(grad[w > 0]) <= 1e-4 * np.abs(b).max())
+    assert np.all(grad[w == 0] >= -1e-4 * np.abs(b).max())
+
+
+def test_lasso_zero_weight_case(L, ws_big):
+    """A far-off atom with no signal gets weight 0 (KKT lower bound active)."""
+    prob, _, psf, y = _problem("c1")
+    thetas = f32(np.vstack([prob.atoms_true[:, 1:6], [[1.0, 1.0, 30.0, 1.2, 2.0]]]))
+    atoms = np.hstack([np.zeros((len(thetas), 1)), thetas])
+    lam = 3.0
+    say("sfw_lasso_weights zero weight")
+    w = L.sfw_lasso_weights(ws_big, dev(psf), dev(y), lam, dev(atoms)).cpu().numpy()
+    w_o, _, _ = oracle.lasso_weights(y, thetas, psf, lam)
+    assert w_o[-1] == 0.0 and w[-1] == 0.0
+    assert rel_l2(w, w_o) <= 1e-4
+
+
+def test_reductions_are_deterministic(L, ws_big):
+    prob, atoms, psf, y = _problem("c3")
+    say("determinism c3")
+    out = []
+    for _ in range(2):
+        r, loss, grad = L.sfw_residual_grad(ws_big, dev(psf), dev(y), 1.0, dev(atoms))
+        _, best = L.sfw_certificate(ws_big, dev(psf), r, 1.0, [1.0, 2.0], [2.0])
+        torch.cuda.synchronize()
+        out.append((loss.cpu().numpy().tobytes(), grad.cpu().numpy().tobytes(), best))
+    assert out[0] == out[1]
