@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Throughput of the BSFW hot path on one MI355X, against its roofline and the CPU oracle.
+
+Workload: one 128 x 128 x 64 float32 volume with 50 atoms (centres uniform in the interior
+with spacing >= 3 voxels, sigma ~ U[1, 2], d = 2, w ~ U[1, 2]), anisotropic Gaussian PSF
+(sigma_xy = 1, sigma_z = 2, 9 x 9 x 15 taps), Gaussian noise of 0.01 * max(Phi mu*),
+lambda = 0.05 * max of the grid certificate of y, candidate grid = voxel centres x
+linspace(1, 2, 4) sigmas x {1.5, 2, 2.5} exponents. The 50 evaluated atoms are the truth
+perturbed (centres +-0.5, sigma x[0.9, 1.1], d +-0.1, w x[0.8, 1.2]).
+
+One step is one pass over every row of the hot path, as one BSFW iteration runs them:
+  (C, grad C) of the 50 atoms (render, blur, residual and criterion, adjoint, gradient
+  sums), the grid certificate of the residual with its maximum, eta and its gradient at
+  that maximum, and the weights-only LASSO of a 50-atom support whose last atom is new
+  (columns of the other 49 come from the workspace cache, as in BSFW).
+The metric counts the voxel x atom pairs of the (C, grad C) evaluation per step:
+  value = 128 * 128 * 64 * 50 * steps / seconds / 1e9   [GVoxel*atom/s].
+Inputs are built on the GPU before the timed region; every step runs in libsfw's kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_FP32_TFLOPS = 157.3   # vector and matrix FP32, dense
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic ALU work per voxel-atom pair in FMA-slot units (one VALU instruction = 1 slot,
+# one v_exp/v_log/v_rcp = 4 slots: quarter rate, measured), reported as 2 FLOP per slot.
+RENDER_SLOTS_PER_PAIR = 4 + 3 * 4   # 4 VALU + log2, exp2, exp2
+GRAD_SLOTS_PER_PAIR = 12 + 3 * 4    # 12 VALU + log2, exp2, exp2
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def lut_taps(sigmas, ds, T=12.0):
+    t = 0
+    for s in sigmas:
+        for d in ds:
+            R = int(np.ceil(float(np.float32(s)) * (2 * T) ** (1 / float(d))))
+            t += (2 * R + 1) ** 3
+    return t
+
+
+def cpu_baseline(prob, atoms_eval, psf):
+    """The oracle (single thread) on one step of the same workload, from its own inputs."""
+    import oracle
+    from paper_2009_05473_amd import synth
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        clean = oracle.blur(oracle.render(prob.shape, prob.atoms_true), psf)
+        y = synth.make_observation(clean, prob.noise_unit, prob.config.noise_rel)
+        lam = prob.config.lambda_rel * oracle.max_grid_certificate(
+            y, psf, prob.config.sigma_grid, prob.config.d_grid)
+        cols = oracle.lasso_columns(prob.shape, atoms_eval[:-1, 1:6], psf)  # cached in BSFW
+        t0 = time.perf_counter()
+        _, _, _, q = oracle.criterion_and_grad(y, atoms_eval, psf, lam)
+        eta = oracle.grid_certificate(q, lam, prob.config.sigma_grid, prob.config.d_grid)
+        _, (i, j, z, yy, x) = oracle.grid_argmax(eta)
+        oracle.eta_point(q, lam, (x, yy, z, prob.config.sigma_grid[i], prob.config.d_grid[j]))
+        a_new = oracle.lasso_columns(prob.shape, atoms_eval[-1:, 1:6], psf)
+        A = np.vstack([cols, a_new])
+        G = A @ A.T
+        b = A @ y.reshape(-1)
+        from scipy import linalg, optimize
+        L = linalg.cholesky(G, lower=True)
+        optimize.nnls(L.T, linalg.solve_triangular(L, b - lam, lower=True))
+        dt = time.perf_counter() - t0
+    V = int(np.prod(prob.shape))
+    n = atoms_eval.shape[0]
+    return {"value": V * n / dt / 1e9, "unit": "GVoxel*atom/s", "cores": 1, "kind": "oracle",
+            "seconds": dt,
+            "sample": "one full step of the same 128x128x64, 50-atom workload (float64 "
+                      "criterion and gradient, grid certificate and maximum, eta at the "
+                      "maximum, one new LASSO column with its Gram row and the NNLS), "
+                      "single thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2009_05473_amd import synth
+    from paper_2009_05473_amd import _lib as L
+
+    prob = synth.draw_problem("c3")
+    cfg = prob.config
+    shape = prob.shape
+    V = int(np.prod(shape))
+    N = cfg.n_atoms
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    psf = prob.psf.astype(np.float32)
+    H = dev(psf)
+    ws = L.Workspace(shape, psf.shape, 64)
+    sg = [float(np.float32(v)) for v in cfg.sigma_grid]
+    dg = [float(v) for v in cfg.d_grid]
+
+    # inputs: y = Phi mu* + noise on the GPU, lambda from the grid certificate of y
+    clean = L.sfw_forward(ws, H, dev(prob.atoms_true.astype(np.float32)), shape)
+    noise = dev(prob.noise_unit.astype(np.float32))
+    Y = (clean + cfg.noise_rel * clean.max() * noise).contiguous()
+    _, best0 = L.sfw_certificate(ws, H, Y, 1.0, sg, dg)
+    lam = float(np.float32(cfg.lambda_rel * best0["eta"]))
+    atoms_eval = synth.perturb(prob.atoms_true, prob.seed).astype(np.float32)
+    A = dev(atoms_eval)
+    R = torch.empty_like(Y)
+    # one support per step: the 49 first atoms fixed, the last one new each step
+    rng = np.random.default_rng(prob.seed + 900)
+    supports = []
+    for _ in range(args.warmup + args.steps):
+        s = atoms_eval.copy()
+        s[-1, 1:4] += rng.uniform(-1.0, 1.0, size=3).astype(np.float32)
+        supports.append(dev(s))
+
+    def step(k):
+        L.sfw_residual_grad(ws, H, Y, lam, A, r_out=R)                       # a1-a5
+        _, best = L.sfw_certificate(ws, H, None, lam, sg, dg, vol_shape=shape)  # a6-a7
+        th = [[best["x"], best["y"], best["z"], sg[best["i_sigma"]], dg[best["i_d"]]]]
+        L.sfw_eta_points(ws, shape, None, lam, th)                           # a8
+        L.sfw_lasso_weights(ws, H, Y, lam, supports[k])                      # a9
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    L.sfw_profile_begin(ws)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = L.sfw_profile_end(ws)
+    dt = t1 - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = V * N * args.steps / dt / 1e9
+
+    # algorithmic work per launch of each kernel class
+    px, py, pz = psf.shape[2], psf.shape[1], psf.shape[0]
+    taps = px * py * pz
+    cert_taps = lut_taps(sg, dg)
+    work = {
+        "render": ("alu", 2.0 * V * N * RENDER_SLOTS_PER_PAIR, "TFLOP/s"),
+        "grad": ("alu", 2.0 * V * N * GRAD_SLOTS_PER_PAIR, "TFLOP/s"),
+        "conv_residual": ("mfma", 2.0 * V * taps, "TFLOP/s"),
+        "conv_adjoint": ("mfma", 2.0 * V * taps, "TFLOP/s"),
+        "lasso_conv": ("mfma", 2.0 * V * taps, "TFLOP/s"),
+        "cert_conv": ("alu", 2.0 * V * cert_taps / (len(sg) * len(dg)), "TFLOP/s"),
+    }
+    breakdown = {}
+    for name, (launches, ms) in prof.items():
+        e = {"launches": launches, "ms_per_step": ms / args.steps,
+             "us_per_launch": ms / launches * 1e3}
+        if name in work:
+            bound, flops, unit = work[name]
+            achieved = flops / (ms / launches * 1e-3) / 1e12
+            e.update({"bound": bound, "achieved_tflops": achieved,
+                      "frac": achieved / PEAK_FP32_TFLOPS})
+        breakdown[name] = e
+    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    if dom in work:
+        bound, flops, unit = work[dom]
+        avg_s = prof[dom][1] / prof[dom][0] * 1e-3
+        achieved = flops / avg_s / 1e12
+        roofline = {"kernel": dom, "bound": bound, "achieved": achieved,
+                    "peak": PEAK_FP32_TFLOPS, "unit": unit, "frac": achieved / PEAK_FP32_TFLOPS,
+                    "traffic": None}
+    else:
+        roofline = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None,
+                    "frac": None, "traffic": None}
+    fwd_grad_ms = sum(prof.get(k, (0, 0.0))[1] for k in
+                      ("prep", "render", "conv_residual", "conv_adjoint", "grad",
+                       "grad_finalize")) / args.steps
+    breakdown["fwd_grad_GVoxel_atom_per_s"] = V * N / (fwd_grad_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "fwd+grad GVoxel*atom/s (one step = every hot-path row once)",
+        "value": value,
+        "unit": "GVoxel*atom/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "128x128x64 volume, 50 atoms, 9x9x15 Gaussian PSF, 4x3 "
+                               "certificate grid (BSFW iteration)",
+                   "volume": [128, 128, 64], "atoms": N, "psf": [px, py, pz],
+                   "grid": [len(sg), len(dg)], "lambda": lam, "parallelism": "none"},
+        "roofline": roofline,
+        "breakdown": breakdown,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, atoms_eval.astype(np.float64),
+                                           psf.astype(np.float64))
+    print(json.dumps(out), flush=True)
+    ws.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -145,7 +145,9 @@ int sfw_adjoint(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
  * q = Phi^T r, R_ij = ceil(sigma_i (2T)^(1/d_j)), T = trunc_T (<= 0 selects 12),
  * for every voxel centre m. best_out: the maximum of eta (not |eta|) over
  * (i, j, z, y, x); ties go to the lowest C-order flat index.
- * r: device [V]; sigma_grid, d_grid: HOST float [ns], [nd] (ns, nd <= SFW_MAX_GRID);
+ * r: device [V], or NULL to use the q = Phi^T r left by the last sfw_residual_grad /
+ * sfw_certificate on this workspace; sigma_grid, d_grid: HOST float [ns], [nd]
+ * (ns, nd <= SFW_MAX_GRID);
  * eta_out: device [ns][nd][nz][ny][nx] or NULL; best_out: device [1] or NULL. */
 int sfw_certificate(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
                     const float* r, float lambda, const float* sigma_grid, int ns,
@@ -169,6 +171,21 @@ int sfw_eta_points(sfw_workspace* ws, sfw_dims vol, const float* q, float lambda
 int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
                       const float* y, float lambda, const sfw_atom* atoms, int n,
                       double* w_out);
+
+/* ---------------------------------------------------------------- profiling */
+
+/* Per-kernel-class device time recorded with HIP events on the workspace stream between
+ * sfw_profile_begin and sfw_profile_end. Classes: "prep", "render", "conv_residual",
+ * "conv_adjoint", "conv_forward", "grad", "grad_finalize", "cert_conv", "cert_argmax",
+ * "lasso_render", "lasso_conv", "lasso_dots", "hash", "eta_grad". */
+#define SFW_PROF_KINDS 16
+typedef struct { char name[24]; int32_t launches; double ms; } sfw_prof_entry;
+
+/* Start recording (creates the event pool on first use; host call, no device sync). */
+int sfw_profile_begin(sfw_workspace* ws);
+/* Stop, synchronise the stream and write one entry per class with launches > 0 into
+ * out (HOST [SFW_PROF_KINDS]); *n_out = entries written. */
+int sfw_profile_end(sfw_workspace* ws, sfw_prof_entry* out, int* n_out);
 
 /* ---------------------------------------------------------------- solver */
 

@@ -23,7 +23,9 @@ EXPORTED = (
     "sfw_default_options", "sfw_workspace_create", "sfw_workspace_destroy",
     "sfw_workspace_set_stream", "sfw_last_error", "sfw_forward", "sfw_residual_grad",
     "sfw_adjoint", "sfw_certificate", "sfw_eta_points", "sfw_lasso_weights", "sfw_solve",
+    "sfw_profile_begin", "sfw_profile_end",
 )
+SFW_PROF_KINDS = 16
 
 
 class SfwDims(ctypes.Structure):
@@ -69,6 +71,10 @@ class SfwStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class SfwProfEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
 class SfwError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libsfw error {code}: {msg}")
@@ -96,6 +102,8 @@ def _load():
         "sfw_lasso_weights": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp]),
         "sfw_solve": (i32, [vp, vp, D, vp, D, f32, ctypes.POINTER(SfwOptions), vp, i32,
                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SfwStats)]),
+        "sfw_profile_begin": (i32, [vp]),
+        "sfw_profile_end": (i32, [vp, ctypes.POINTER(SfwProfEntry), ctypes.POINTER(ctypes.c_int)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -231,18 +239,22 @@ def sfw_adjoint(ws: Workspace, H, r, q_out=None):
     return q_out
 
 
-def sfw_certificate(ws: Workspace, H, r, lam, sigma_grid, d_grid, trunc_T=12.0, want_eta=False):
-    """Returns (eta [ns, nd, nz, ny, nx] or None, argmax dict)."""
+def sfw_certificate(ws: Workspace, H, r, lam, sigma_grid, d_grid, trunc_T=12.0, want_eta=False,
+                    vol_shape=None):
+    """Returns (eta [ns, nd, nz, ny, nx] or None, argmax dict). r=None reuses the workspace's
+    last q (then vol_shape is required)."""
     import torch
     sg = (ctypes.c_float * len(sigma_grid))(*[float(v) for v in sigma_grid])
     dg = (ctypes.c_float * len(d_grid))(*[float(v) for v in d_grid])
     eta = None
     if want_eta:
-        eta = torch.empty((len(sigma_grid), len(d_grid)) + tuple(r.shape), dtype=torch.float32,
-                          device="cuda")
+        eta = torch.empty((len(sigma_grid), len(d_grid)) + (tuple(r.shape) if r is not None
+                                                             else tuple(vol_shape)),
+                          dtype=torch.float32, device="cuda")
     best = torch.zeros(6, dtype=torch.int32, device="cuda")  # sfw_argmax is 24 bytes
+    vol = tuple(r.shape) if r is not None else tuple(vol_shape)
     check(lib.sfw_certificate(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape),
-                              dims(r.shape), _dev_ptr(r, "float32", "r"), float(lam),
+                              dims(vol), _dev_ptr(r, "float32", "r"), float(lam),
                               ctypes.cast(sg, ctypes.c_void_p), len(sigma_grid),
                               ctypes.cast(dg, ctypes.c_void_p), len(d_grid), float(trunc_T),
                               _dev_ptr(eta, "float32", "eta") if want_eta else None,
@@ -291,3 +303,15 @@ def sfw_solve(ws: Workspace, y, H, lam, opts: SfwOptions | None = None, cap: int
     n = n_out.value
     arr = np.array([[a.w, a.mx, a.my, a.mz, a.sigma, a.d] for a in out[:n]], dtype=np.float64)
     return arr.reshape(-1, 6), stats.as_dict(), code
+
+
+def sfw_profile_begin(ws: Workspace):
+    check(lib.sfw_profile_begin(ws.handle))
+
+
+def sfw_profile_end(ws: Workspace):
+    """Returns {class name: (launches, total ms)}."""
+    arr = (SfwProfEntry * SFW_PROF_KINDS)()
+    n = ctypes.c_int(0)
+    check(lib.sfw_profile_end(ws.handle, arr, ctypes.byref(n)))
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].ms)) for i in range(n.value)}

@@ -84,19 +84,36 @@ PsfPlan plan_psf(const sfw_dims& vol, const sfw_dims& psf) {
   return p;
 }
 
-int prep_psf(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool adj) {
-  if (p.mfma) {
-    if (fwd) SFW_HIP(launch_mfma_prep(H, p.psf, false, ws->am_fwd, ws->stream));
-    if (adj) SFW_HIP(launch_mfma_prep(H, p.psf, true, ws->am_adj, ws->stream));
-  } else {
-    if (fwd) SFW_HIP(launch_psf_prep(H, p.psf, p.valu.kzp, false, ws->wt_fwd, ws->stream));
-    if (adj) SFW_HIP(launch_psf_prep(H, p.psf, p.valu.kzp, true, ws->wt_adj, ws->stream));
-  }
+int prep_all(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool adj,
+             const sfw_atom* atoms, int n, bool unit_weight) {
+  float* of = p.mfma ? ws->am_fwd : ws->wt_fwd;
+  float* oa = p.mfma ? ws->am_adj : ws->wt_adj;
+  ProfScope ps(ws, kProfPrep);
+  SFW_HIP(launch_prep(atoms, atoms ? n : 0, unit_weight, ws->ak, H, p.psf, p.mfma, p.valu.kzp,
+                      fwd, adj, of, oa, ws->stream));
   return SFW_OK;
 }
 
+int prep_psf(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool adj) {
+  return prep_all(ws, H, p, fwd, adj, nullptr, 0, false);
+}
+
+AtomK make_atomk(double w, double mx, double my, double mz, double sigma, double d) {
+  AtomK k;
+  k.w = (float)w;
+  k.mx = (float)mx;
+  k.my = (float)my;
+  k.mz = (float)mz;
+  k.hd = (float)(0.5 * d);
+  k.hdm1 = k.hd - 1.f;
+  k.c = (float)(-d * std::log2(sigma) - 1.0 + 0.52876637294489772);
+  k.pad = 0.f;
+  return k;
+}
+
 int conv_psf(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjoint,
-             const float* in, float* out, int epi, const float* yobs) {
+             const float* in, float* out, int epi, const float* yobs, int kind) {
+  ProfScope ps(ws, kind);
   if (p.mfma)
     SFW_HIP(launch_conv_mfma(in, adjoint ? ws->am_adj : ws->am_fwd, p.psf, vol, epi, out, yobs,
                              ws->dpart, ws->stream));
@@ -107,22 +124,32 @@ int conv_psf(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjo
 }
 
 int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, float* phi) {
-  SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream));
-  return conv_psf(ws, p, vol, false, ws->f, phi, kEpiPlain, nullptr);
+  {
+    ProfScope ps(ws, kProfRender);
+    SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream));
+  }
+  return conv_psf(ws, p, vol, false, ws->f, phi, kEpiPlain, nullptr, kProfConvForward);
 }
 
 int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
              float lambda, const sfw_atom* atoms_dev, int n, float* r_out, double* loss_out,
              sfw_atom* grad_out) {
   float* r = r_out ? r_out : ws->r;
-  SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream));
-  int rc = conv_psf(ws, p, vol, false, ws->f, r, kEpiResidual, y);
+  {
+    ProfScope ps(ws, kProfRender);
+    SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream));
+  }
+  int rc = conv_psf(ws, p, vol, false, ws->f, r, kEpiResidual, y, kProfConvResidual);
   if (rc) return rc;
-  rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr);
+  rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr, kProfConvAdjoint);
   if (rc) return rc;
   ws->q_valid = true;
   GradPlan gp = plan_grad(vol, n);
-  SFW_HIP(launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream));
+  {
+    ProfScope ps(ws, kProfGrad);
+    SFW_HIP(launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream));
+  }
+  ProfScope ps(ws, kProfGradFinalize);
   SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, ws->dpart, p.nres, atoms_dev, lambda,
                                ws->dres, grad_out, loss_out, ws->stream));
   return SFW_OK;
@@ -134,22 +161,16 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
   AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin);
   for (int i = 0; i < n; ++i) {
     const double* t = thetas + 5 * i;
-    AtomK k;
-    k.w = 1.f;
-    k.mx = (float)t[0];
-    k.my = (float)t[1];
-    k.mz = (float)t[2];
-    k.hd = (float)(0.5 * t[4]);
-    k.hdm1 = k.hd - 1.f;
-    k.c = (float)(-t[4] * std::log2(t[3]) - 1.0 + 0.52876637294489772);
-    k.pad = 0.f;
-    hk[i] = k;
+    hk[i] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
   }
   SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
   GradPlan gp = plan_grad(vol, n);
-  SFW_HIP(launch_grad(gp, ws->ak, n, q, vol, ws->gpart, ws->stream));
-  SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, nullptr, 0, nullptr, 0.f, ws->dres,
-                               nullptr, nullptr, ws->stream));
+  {
+    ProfScope ps(ws, kProfEtaGrad);
+    SFW_HIP(launch_grad(gp, ws->ak, n, q, vol, ws->gpart, ws->stream));
+    SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, nullptr, 0, nullptr, 0.f, ws->dres,
+                                 nullptr, nullptr, ws->stream));
+  }
   double* hs = ws->hpin + 8 * (size_t)ws->max_atoms + 16;
   SFW_HIP(hipMemcpyAsync(hs, ws->dres, sizeof(double) * 6 * n, hipMemcpyDeviceToHost,
                          ws->stream));
@@ -245,11 +266,13 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
       nb = p.nblocks;
       if ((size_t)nb * ns * nd > ws->apart_cap)
         return fail(SFW_EINVAL, "certificate partial buffer too small");
+      ProfScope ps(ws, kProfCertConv);
       SFW_HIP(launch_conv(p, q, ws->lut + ws->lut_off[s], vol, kEpiArgmax,
                           eta_out ? eta_out + (size_t)s * V : nullptr, nullptr, nullptr,
                           1.0f / lambda, (long long)s * (long long)V, ws->apart + (size_t)s * nb,
                           ws->stream));
     }
+  ProfScope ps(ws, kProfCertArgmax);
   SFW_HIP(launch_argmax_final(ws->apart, nb * ns * nd, vol, nd, ws->best, ws->stream));
   return SFW_OK;
 }
@@ -258,9 +281,12 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
 // ws->ak with unit weights.
 int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int i0, int i1) {
   for (int i = i0; i < i1; ++i) {
-    SFW_HIP(launch_render(ws->ak + i, 1, vol, ws->f, ws->stream));
+    {
+      ProfScope ps(ws, kProfLassoRender);
+      SFW_HIP(launch_render(ws->ak + i, 1, vol, ws->f, ws->stream));
+    }
     int rc = conv_psf(ws, p, vol, false, ws->f, ws->cols + (size_t)i * ws->vcap, kEpiPlain,
-                      nullptr);
+                      nullptr, kProfLassoConv);
     if (rc) return rc;
   }
   return SFW_OK;
@@ -269,11 +295,94 @@ int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int i0,
 // G[i][0..i] and b[i] for the column i into out (float64, device), k = i + 1 entries + b.
 int op_gram_row(sfw_workspace* ws, const sfw_dims& vol, const float* y, int i, double* out) {
   const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
-  int nb = (int)std::min<size_t>(256, (V + 255) / 256);
+  int nb = (int)std::min<size_t>(1024, (V + 1023) / 1024);
   if ((size_t)nb * (i + 2) > ws->dpart_cap) return fail(SFW_EINVAL, "dot partial buffer too small");
+  ProfScope ps(ws, kProfLassoDots);
   SFW_HIP(launch_dots(ws->cols + (size_t)i * ws->vcap, ws->cols, i + 1, ws->vcap, y, V, ws->dpart,
                       nb, out, ws->stream));
   return SFW_OK;
+}
+
+// Weights-only LASSO for unit-weight atoms thetas [n][5] (host, float32 values as the device
+// sees them); the PSF operands for the forward convolution must already be prepared. Columns
+// and Gram rows of the longest prefix of atoms identical to the workspace's cached list (same
+// y, H, shapes and convolution kind) are reused; the rest are computed on the GPU.
+int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
+             const float* H, double lambda, const float* thetas, int n, std::vector<double>& w) {
+  w.assign(n, 0.0);
+  if (n == 0) return SFW_OK;
+  const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
+  const int M = ws->max_atoms;
+  {
+    ProfScope ps(ws, kProfHash);
+    SFW_HIP(hipMemsetAsync(ws->hashbuf, 0, 2 * sizeof(unsigned long long), ws->stream));
+    SFW_HIP(launch_hash(y, V, ws->hashbuf, ws->stream));
+    SFW_HIP(launch_hash(H, (size_t)p.psf.nx * p.psf.ny * p.psf.nz, ws->hashbuf + 1, ws->stream));
+  }
+  unsigned long long* hh = reinterpret_cast<unsigned long long*>(ws->hpin);
+  SFW_HIP(hipMemcpyAsync(hh, ws->hashbuf, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         ws->stream));
+  SFW_HIP(hipStreamSynchronize(ws->stream));
+  const unsigned long long yh = hh[0], hhv = hh[1];
+  int pre = 0;
+  const bool same = ws->lasso_y == y && ws->lasso_yhash == yh && ws->lasso_hhash == hhv &&
+                    ws->lasso_mfma == p.mfma && ws->lasso_vol.nx == vol.nx &&
+                    ws->lasso_vol.ny == vol.ny && ws->lasso_vol.nz == vol.nz &&
+                    ws->lasso_psf.nx == p.psf.nx && ws->lasso_psf.ny == p.psf.ny &&
+                    ws->lasso_psf.nz == p.psf.nz;
+  if (same) {
+    const int kmax = std::min(ws->lasso_k, n);
+    while (pre < kmax &&
+           std::memcmp(&ws->lasso_thetas[5 * (size_t)pre], thetas + 5 * (size_t)pre,
+                       5 * sizeof(float)) == 0)
+      ++pre;
+  }
+  if ((int)ws->lasso_G.size() != M * M) {
+    ws->lasso_G.assign((size_t)M * M, 0.0);
+    ws->lasso_b.assign(M, 0.0);
+  }
+  if (pre < n) {
+    AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin);
+    for (int i = pre; i < n; ++i) {
+      const float* t = thetas + 5 * (size_t)i;
+      hk[i - pre] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
+    }
+    SFW_HIP(hipMemcpyAsync(ws->ak + pre, hk, sizeof(AtomK) * (n - pre), hipMemcpyHostToDevice,
+                           ws->stream));
+    int rc = op_columns(ws, p, vol, pre, n);
+    if (rc) return rc;
+    for (int i = pre; i < n; ++i) {
+      rc = op_gram_row(ws, vol, y, i, ws->dres + (size_t)i * (i + 1) / 2 + i);
+      if (rc) return rc;
+    }
+    const size_t o0 = (size_t)pre * (pre + 1) / 2 + pre;
+    const size_t o1 = (size_t)n * (n + 1) / 2 + n;
+    // the staged atom constants share the pinned buffer: wait for that copy first
+    SFW_HIP(hipStreamSynchronize(ws->stream));
+    SFW_HIP(hipMemcpyAsync(ws->hpin + o0, ws->dres + o0, (o1 - o0) * 8, hipMemcpyDeviceToHost,
+                           ws->stream));
+    SFW_HIP(hipStreamSynchronize(ws->stream));
+    for (int i = pre; i < n; ++i) {
+      const double* row = ws->hpin + (size_t)i * (i + 1) / 2 + i;
+      for (int j = 0; j <= i; ++j)
+        ws->lasso_G[(size_t)i * M + j] = ws->lasso_G[(size_t)j * M + i] = row[j];
+      ws->lasso_b[i] = row[i + 1];
+    }
+    ws->lasso_thetas.assign(thetas, thetas + 5 * (size_t)n);
+    ws->lasso_k = n;
+    ws->lasso_y = y;
+    ws->lasso_yhash = yh;
+    ws->lasso_hhash = hhv;
+    ws->lasso_vol = vol;
+    ws->lasso_psf = p.psf;
+    ws->lasso_mfma = p.mfma;
+  }
+  std::vector<double> Gk((size_t)n * n), c(n);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) Gk[(size_t)i * n + j] = ws->lasso_G[(size_t)i * M + j];
+    c[i] = ws->lasso_b[i] - lambda;
+  }
+  return nnqp(Gk, c, n, w);
 }
 
 }  // namespace sfw
@@ -332,7 +441,10 @@ void sfw_workspace_destroy(sfw_workspace* ws) {
   if (ws->dres) (void)hipFree(ws->dres);
   if (ws->apart) (void)hipFree(ws->apart);
   if (ws->best) (void)hipFree(ws->best);
+  if (ws->hashbuf) (void)hipFree(ws->hashbuf);
   if (ws->hpin) (void)hipHostFree(ws->hpin);
+  for (hipEvent_t e : ws->prof_start) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ws->prof_stop) (void)hipEventDestroy(e);
   (void)hipSetDevice(cur);
   delete ws;
 }
@@ -400,13 +512,14 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
                            ((vol_max.ny + kConvTY - 1) / kConvTY) *
                            ((vol_max.nz + kConvRZ - 1) / kConvRZ);
     const size_t mparts = 4 * (size_t)mfma_conv_blocks(vol_max);
-    ws->dpart_cap = std::max(std::max(cblocks, mparts), (size_t)256 * (na + 2));
+    ws->dpart_cap = std::max(std::max(cblocks, mparts), (size_t)1024 * (na + 2));
     ALLOC(ws->dpart, ws->dpart_cap * 8, "float64 partials");
     const size_t dres_n = (size_t)(na + 2) * (na + 2) + 8 * (size_t)(na + 2) + 64;
     ALLOC(ws->dres, dres_n * 8, "float64 results");
     ws->apart_cap = cblocks * SFW_MAX_GRID * SFW_MAX_GRID;
     ALLOC(ws->apart, ws->apart_cap * sizeof(ArgPart), "argmax partials");
     ALLOC(ws->best, sizeof(sfw_argmax) * 2, "argmax");
+    ALLOC(ws->hashbuf, 2 * sizeof(unsigned long long), "fingerprints");
     ALLOC(ws->cols, (size_t)max_atoms * V * 4, "LASSO columns");
 #undef ALLOC
     ws->hpin_cap = dres_n + 8 * (size_t)(na + 2) + 64;
@@ -424,6 +537,53 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
   }
 }
 
+int sfw_profile_begin(sfw_workspace* ws) {
+  if (!ws) return fail(SFW_EINVAL, "workspace is NULL");
+  if (ws->prof_start.empty()) {
+    ws->prof_start.resize(kProfPool);
+    ws->prof_stop.resize(kProfPool);
+    ws->prof_kind.resize(kProfPool);
+    for (int i = 0; i < kProfPool; ++i) {
+      SFW_HIP(hipEventCreate(&ws->prof_start[i]));
+      SFW_HIP(hipEventCreate(&ws->prof_stop[i]));
+    }
+  }
+  ws->prof_used = 0;
+  ws->prof_overflow = false;
+  ws->prof_on = true;
+  return SFW_OK;
+}
+
+int sfw_profile_end(sfw_workspace* ws, sfw_prof_entry* out, int* n_out) {
+  if (!ws || !out || !n_out) return fail(SFW_EINVAL, "ws, out or n_out is NULL");
+  static const char* names[kProfCount] = {
+      "prep", "render", "conv_residual", "conv_adjoint", "conv_forward", "grad",
+      "grad_finalize", "cert_conv", "cert_argmax", "lasso_render", "lasso_conv", "lasso_dots",
+      "hash", "eta_grad"};
+  ws->prof_on = false;
+  SFW_HIP(hipStreamSynchronize(ws->stream));
+  double ms[kProfCount] = {0};
+  int cnt[kProfCount] = {0};
+  for (int i = 0; i < ws->prof_used; ++i) {
+    float t = 0.f;
+    SFW_HIP(hipEventElapsedTime(&t, ws->prof_start[i], ws->prof_stop[i]));
+    ms[ws->prof_kind[i]] += t;
+    cnt[ws->prof_kind[i]]++;
+  }
+  int k = 0;
+  for (int i = 0; i < kProfCount && k < SFW_PROF_KINDS; ++i) {
+    if (!cnt[i]) continue;
+    std::memset(&out[k], 0, sizeof(out[k]));
+    std::strncpy(out[k].name, names[i], sizeof(out[k].name) - 1);
+    out[k].launches = cnt[i];
+    out[k].ms = ms[i];
+    ++k;
+  }
+  *n_out = k;
+  if (ws->prof_overflow) return fail(SFW_EINVAL, "profile event pool exhausted; totals partial");
+  return SFW_OK;
+}
+
 int sfw_workspace_set_stream(sfw_workspace* ws, hipStream_t stream) {
   if (!ws) return fail(SFW_EINVAL, "workspace is NULL");
   ws->stream = stream;
@@ -438,9 +598,8 @@ int sfw_forward(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
     if (!H) return fail(SFW_EINVAL, "H is NULL");
     if (n > 0 && !atoms) return fail(SFW_EINVAL, "atoms is NULL");
     PsfPlan p = plan_psf(vol, psf);
-    rc = prep_psf(ws, H, p, true, false);
+    rc = prep_all(ws, H, p, true, false, atoms, n, false);
     if (rc) return rc;
-    SFW_HIP(launch_atom_prep(atoms, n, false, ws->ak, ws->stream));
     return op_forward(ws, p, vol, n, phi_mu ? phi_mu : ws->phi);
   } catch (...) {
     return fail(SFW_EINVAL, "unexpected exception in sfw_forward");
@@ -458,9 +617,8 @@ int sfw_residual_grad(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
     rc = check_lambda(lambda);
     if (rc) return rc;
     PsfPlan p = plan_psf(vol, psf);
-    rc = prep_psf(ws, H, p, true, true);
+    rc = prep_all(ws, H, p, true, true, atoms, n, false);
     if (rc) return rc;
-    SFW_HIP(launch_atom_prep(atoms, n, false, ws->ak, ws->stream));
     return op_cgrad(ws, p, vol, y, lambda, atoms, n, r_out, loss_out, n > 0 ? grad_out : nullptr);
   } catch (...) {
     return fail(SFW_EINVAL, "unexpected exception in sfw_residual_grad");
@@ -476,7 +634,7 @@ int sfw_adjoint(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol, c
     PsfPlan p = plan_psf(vol, psf);
     rc = prep_psf(ws, H, p, false, true);
     if (rc) return rc;
-    return conv_psf(ws, p, vol, true, r, q_out, kEpiPlain, nullptr);
+    return conv_psf(ws, p, vol, true, r, q_out, kEpiPlain, nullptr, kProfConvAdjoint);
   } catch (...) {
     return fail(SFW_EINVAL, "unexpected exception in sfw_adjoint");
   }
@@ -488,7 +646,8 @@ int sfw_certificate(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vo
   try {
     int rc = check_ws_fit(ws, vol, &psf, 0);
     if (rc) return rc;
-    if (!H || !r) return fail(SFW_EINVAL, "H or r is NULL");
+    if (!H) return fail(SFW_EINVAL, "H is NULL");
+    if (!r && !ws->q_valid) return fail(SFW_EINVAL, "r is NULL and no q was computed yet");
     rc = check_lambda(lambda);
     if (rc) return rc;
     if (!sigma_grid || !d_grid) return fail(SFW_EINVAL, "sigma_grid or d_grid is NULL");
@@ -501,12 +660,14 @@ int sfw_certificate(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vo
       if (!(d_grid[j] > 0.f) || !std::isfinite(d_grid[j]))
         return fail(SFW_EINVAL, "d_grid values must be finite and > 0");
     const float T = trunc_T > 0.f ? trunc_T : 12.0f;
-    PsfPlan p = plan_psf(vol, psf);
-    rc = prep_psf(ws, H, p, false, true);
-    if (rc) return rc;
-    rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr);
-    if (rc) return rc;
-    ws->q_valid = true;
+    if (r) {
+      PsfPlan p = plan_psf(vol, psf);
+      rc = prep_psf(ws, H, p, false, true);
+      if (rc) return rc;
+      rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr, kProfConvAdjoint);
+      if (rc) return rc;
+      ws->q_valid = true;
+    }
     rc = op_certificate(ws, vol, ws->q, lambda, sigma_grid, ns, d_grid, nd, T, eta_out);
     if (rc) return rc;
     if (best_out)
@@ -553,24 +714,21 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
     PsfPlan p = plan_psf(vol, psf);
     rc = prep_psf(ws, H, p, true, false);
     if (rc) return rc;
-    SFW_HIP(launch_atom_prep(atoms, n, true, ws->ak, ws->stream));
-    rc = op_columns(ws, p, vol, 0, n);
-    if (rc) return rc;
-    // row i of the lower triangle: G[i][0..i] then b[i], packed at offset i(i+1)/2 + i
-    for (int i = 0; i < n; ++i) {
-      rc = op_gram_row(ws, vol, y, i, ws->dres + (size_t)i * (i + 1) / 2 + i);
-      if (rc) return rc;
-    }
-    const size_t tot = (size_t)n * (n + 1) / 2 + n;
-    SFW_HIP(hipMemcpyAsync(ws->hpin, ws->dres, tot * 8, hipMemcpyDeviceToHost, ws->stream));
+    sfw_atom* ha = reinterpret_cast<sfw_atom*>(ws->hpin);
+    SFW_HIP(hipMemcpyAsync(ha, atoms, sizeof(sfw_atom) * n, hipMemcpyDeviceToHost, ws->stream));
     SFW_HIP(hipStreamSynchronize(ws->stream));
-    std::vector<double> G((size_t)n * n), c(n), w;
+    std::vector<float> th(5 * (size_t)n);
     for (int i = 0; i < n; ++i) {
-      const double* row = ws->hpin + (size_t)i * (i + 1) / 2 + i;
-      for (int j = 0; j <= i; ++j) G[(size_t)i * n + j] = G[(size_t)j * n + i] = row[j];
-      c[i] = row[i + 1] - (double)lambda;
+      th[5 * i + 0] = ha[i].mx;
+      th[5 * i + 1] = ha[i].my;
+      th[5 * i + 2] = ha[i].mz;
+      th[5 * i + 3] = ha[i].sigma;
+      th[5 * i + 4] = ha[i].d;
+      if (!(ha[i].sigma > 0.f) || !(ha[i].d > 0.f))
+        return fail(SFW_EINVAL, "atoms: sigma and d must be > 0");
     }
-    rc = nnqp(G, c, n, w);
+    std::vector<double> w;
+    rc = op_lasso(ws, p, vol, y, H, lambda, th.data(), n, w);
     if (rc) return rc;
     SFW_HIP(hipMemcpyAsync(w_out, w.data(), 8 * (size_t)n, hipMemcpyHostToDevice, ws->stream));
     SFW_HIP(hipStreamSynchronize(ws->stream));

@@ -63,6 +63,13 @@ struct ConvPlan {
   int nblocks = 0;
 };
 
+enum ProfKind {
+  kProfPrep = 0, kProfRender, kProfConvResidual, kProfConvAdjoint, kProfConvForward, kProfGrad,
+  kProfGradFinalize, kProfCertConv, kProfCertArgmax, kProfLassoRender, kProfLassoConv,
+  kProfLassoDots, kProfHash, kProfEtaGrad, kProfCount
+};
+constexpr int kProfPool = 16384;
+
 struct GradPlan {
   int vpt = 16;       // z voxels per thread (template parameter)
   int ntile_xy = 0;   // blocks over the flattened (y, x) plane
@@ -119,13 +126,50 @@ struct sfw_workspace {
   size_t apart_cap = 0;
   sfw_argmax* best = nullptr;  // [1]
 
-  // LASSO columns a_n = H * g_n, [max_atoms][vcap]
+  // LASSO columns a_n = H * g_n, [max_atoms][vcap], valid for the first lasso_k atoms of the
+  // cached theta list, for the y / H fingerprints, shapes and convolution kind below
   float* cols = nullptr;
+  int lasso_k = 0;
+  const float* lasso_y = nullptr;
+  unsigned long long lasso_yhash = 0, lasso_hhash = 0;
+  sfw_dims lasso_vol{0, 0, 0}, lasso_psf{0, 0, 0};
+  bool lasso_mfma = false;
+  std::vector<float> lasso_thetas;  // [lasso_k][5]
+  std::vector<double> lasso_G, lasso_b;  // [max_atoms][max_atoms], [max_atoms]
+  unsigned long long* hashbuf = nullptr;  // [2] device
 
   // pinned host staging
   double* hpin = nullptr;
   size_t hpin_cap = 0;  // doubles
+
+  // optional per-kernel-class event timing (sfw_profile_begin / end)
+  bool prof_on = false;
+  int prof_used = 0;
+  bool prof_overflow = false;
+  std::vector<hipEvent_t> prof_start, prof_stop;
+  std::vector<int> prof_kind;
 };
+
+namespace sfw {
+// Records a start event on construction and a stop event on destruction when profiling is on.
+struct ProfScope {
+  sfw_workspace* ws;
+  int slot = -1;
+  ProfScope(sfw_workspace* w, int kind) : ws(w) {
+    if (!ws->prof_on) return;
+    if (ws->prof_used >= (int)ws->prof_start.size()) {
+      ws->prof_overflow = true;
+      return;
+    }
+    slot = ws->prof_used++;
+    ws->prof_kind[slot] = kind;
+    (void)hipEventRecord(ws->prof_start[slot], ws->stream);
+  }
+  ~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(ws->prof_stop[slot], ws->stream);
+  }
+};
+}  // namespace sfw
 
 namespace sfw {
 
@@ -144,10 +188,13 @@ int hip_fail(hipError_t e, const char* what);
 ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz);
 GradPlan plan_grad(sfw_dims vol, int n_atoms);
 
-hipError_t launch_psf_prep(const float* H, sfw_dims psf, int kzp, bool flip, float* out,
-                           hipStream_t st);
-hipError_t launch_atom_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* out,
-                            hipStream_t st);
+// One launch: atom constants (atoms may be null when n == 0) and the forward / adjoint PSF
+// operands for the matrix-core (mfma) or VALU (kzp) convolution (H may be null).
+hipError_t launch_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* ak, const float* H,
+                       sfw_dims psf, bool mfma, int kzp, bool fwd, bool adj, float* out_fwd,
+                       float* out_adj, hipStream_t st);
+// atomicAdd of the fingerprint of v[0..n) into *out (zero it first).
+hipError_t launch_hash(const float* v, size_t n, unsigned long long* out, hipStream_t st);
 hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st);
 
 enum ConvEpilogue { kEpiPlain = 0, kEpiResidual = 1, kEpiArgmax = 2 };
@@ -161,12 +208,10 @@ hipError_t launch_conv(const ConvPlan& p, const float* in, const float* wt, sfw_
                        long long idx_base, ArgPart* apart, hipStream_t st);
 
 // Matrix-core convolution for PSFs with pz <= 16 and px * py <= 128 (see k_conv_mfma).
-// The A operands (per-lane weights) are built by launch_mfma_prep into amat
-// (mfma_steps * 64 floats). kEpiResidual writes one partial per wave: dpart[block * 4 + wave].
+// The A operands (per-lane weights, mfma_steps * 64 floats) are built by launch_prep. kEpiResidual writes one partial per wave: dpart[block * 4 + wave].
 bool mfma_conv_ok(int px, int py, int pz);
 int mfma_steps(int px, int py);
 int mfma_conv_blocks(sfw_dims vol);
-hipError_t launch_mfma_prep(const float* H, sfw_dims psf, bool flip, float* amat, hipStream_t st);
 hipError_t launch_conv_mfma(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
                             int epi, float* out, const float* yobs, double* dpart,
                             hipStream_t st);

@@ -12,6 +12,8 @@
 
 #include "sfw_internal.h"
 
+#include <algorithm>
+
 namespace sfw {
 
 namespace {
@@ -55,41 +57,76 @@ __device__ __forceinline__ bool arg_better(float v, long long i, float bv, long 
 
 // ------------------------------------------------------------------ preparation
 
-__global__ void k_atom_prep(const sfw_atom* __restrict__ atoms, int n, int unit_weight,
-                            AtomK* __restrict__ out) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  sfw_atom a = atoms[i];
-  AtomK k;
-  k.w = unit_weight ? 1.0f : a.w;
-  k.mx = a.mx;
-  k.my = a.my;
-  k.mz = a.mz;
-  k.hd = 0.5f * a.d;
-  k.hdm1 = k.hd - 1.0f;
-  k.c = (float)(-(double)a.d * log2((double)a.sigma) - 1.0 + kLog2Log2e);
-  k.pad = 0.f;
-  out[i] = k;
+// One launch for everything an evaluation needs before the render: grid.y = 0 computes the
+// atom constants, grid.y = 1 / 2 the forward / adjoint PSF operands (matrix-core A operands
+// when mfma != 0, else the [ky][kx][kzp] copies).
+__global__ void k_prep(const sfw_atom* __restrict__ atoms, int n, int unit_weight,
+                       AtomK* __restrict__ ak, const float* __restrict__ H, int px, int py,
+                       int pz, int mfma, int steps, int kzp, int want_fwd, int want_adj,
+                       float* __restrict__ out_fwd, float* __restrict__ out_adj) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int which = blockIdx.y;
+  if (which == 0) {
+    if (i >= n) return;
+    const sfw_atom a = atoms[i];
+    AtomK k;
+    k.w = unit_weight ? 1.0f : a.w;
+    k.mx = a.mx;
+    k.my = a.my;
+    k.mz = a.mz;
+    k.hd = 0.5f * a.d;
+    k.hdm1 = k.hd - 1.0f;
+    k.c = (float)(-(double)a.d * log2((double)a.sigma) - 1.0 + kLog2Log2e);
+    k.pad = 0.f;
+    ak[i] = k;
+    return;
+  }
+  const int flip = which == 2;
+  if ((flip && !want_adj) || (!flip && !want_fwd)) return;
+  float* out = flip ? out_adj : out_fwd;
+  if (mfma) {
+    if (i >= steps * 64) return;
+    const int lane = i & 63, s = i >> 6;
+    const int kz = lane & 15;
+    const int k = 4 * s + (lane >> 4);
+    float v = 0.f;
+    if (kz < pz && k < px * py) {
+      const int ky = k / px, kx = k - ky * px;
+      const int sz = flip ? pz - 1 - kz : kz;
+      const int sy = flip ? py - 1 - ky : ky;
+      const int sx = flip ? px - 1 - kx : kx;
+      v = H[((size_t)sz * py + sy) * px + sx];
+    }
+    out[i] = v;
+  } else {
+    if (i >= px * py * kzp) return;
+    const int kz = i % kzp;
+    const int kx = (i / kzp) % px;
+    const int ky = i / (kzp * px);
+    float v = 0.f;
+    if (kz < pz) {
+      const int sz = flip ? pz - 1 - kz : kz;
+      const int sy = flip ? py - 1 - ky : ky;
+      const int sx = flip ? px - 1 - kx : kx;
+      v = H[((size_t)sz * py + sy) * px + sx];
+    }
+    out[i] = v;
+  }
 }
 
-// W[ky][kx][kz] (kz padded to kzp with zeros) from H[kz][ky][kx]; flip gives the
-// correlation kernel H[pz-1-kz][py-1-ky][px-1-kx].
-__global__ void k_psf_prep(const float* __restrict__ H, int px, int py, int pz, int kzp, int flip,
-                           float* __restrict__ out) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int total = px * py * kzp;
-  if (i >= total) return;
-  int kz = i % kzp;
-  int kx = (i / kzp) % px;
-  int ky = i / (kzp * px);
-  float v = 0.f;
-  if (kz < pz) {
-    int sz = flip ? pz - 1 - kz : kz;
-    int sy = flip ? py - 1 - ky : ky;
-    int sx = flip ? px - 1 - kx : kx;
-    v = H[((size_t)sz * py + sy) * px + sx];
-  }
-  out[i] = v;
+// Order-independent 64-bit fingerprint of a float array: sum over i of bits(v[i]) * (2 i + 1)
+// (mod 2^64). Used to recognise inputs already seen by cached LASSO columns.
+__global__ __launch_bounds__(256) void k_hash(const float* __restrict__ v, size_t n,
+                                              unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long red[4];
+  const size_t stride = (size_t)gridDim.x * 256;
+  unsigned long long h = 0ull;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+    h += (unsigned long long)__float_as_uint(v[i]) * (2ull * i + 1ull);
+  for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = h;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, red[0] + red[1] + red[2] + red[3]);
 }
 
 // ------------------------------------------------------------------ render
@@ -307,27 +344,6 @@ __global__ __launch_bounds__(TX* TY) void k_conv(
 // ------------------------------------------------------------------ convolution on MFMA
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-// A operands of k_conv_mfma: amat[s * 64 + lane] = W[kz = lane % 16][tap k = 4 s + lane / 16]
-// with tap k = ky * px + kx (zero for kz >= pz or k >= px * py). W is H or, for the
-// correlation, H flipped on every axis.
-__global__ void k_mfma_prep(const float* __restrict__ H, int px, int py, int pz, int steps,
-                            int flip, float* __restrict__ amat) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= steps * 64) return;
-  const int lane = i & 63, s = i >> 6;
-  const int kz = lane & 15;
-  const int k = 4 * s + (lane >> 4);
-  float v = 0.f;
-  if (kz < pz && k < px * py) {
-    const int ky = k / px, kx = k - ky * px;
-    const int sz = flip ? pz - 1 - kz : kz;
-    const int sy = flip ? py - 1 - ky : ky;
-    const int sx = flip ? px - 1 - kx : kx;
-    v = H[((size_t)sz * py + sy) * px + sx];
-  }
-  amat[i] = v;
-}
 
 // out[z][y][x] = sum_{kz,ky,kx} W[kz][ky][kx] in[z + cz - kz][y + cy - ky][x + cx - kx] on the
 // matrix cores (pz <= 16, px * py <= 4 * STEPS; amat holds STEPS steps, zero past the taps).
@@ -646,19 +662,31 @@ __global__ __launch_bounds__(256) void k_argmax_final(const ArgPart* __restrict_
 
 // ------------------------------------------------------------------ LASSO dot products
 
-// dpart[block][c] = partial sum over the block's voxels of a * cols[c] (c < k), a * y (c = k).
+// dpart[block][c] = partial sum over the block's voxels of a * cols[c] (c < k), a * y (c = k):
+// each thread owns 4 consecutive voxels per grid stride (128-bit loads), float32 products,
+// float64 accumulation, fixed-order block reduction.
 __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
                                               const float* __restrict__ cols, int k,
                                               size_t colstride, const float* __restrict__ y,
                                               size_t nvox, double* __restrict__ dpart) {
   __shared__ double red[4];
   const int tid = threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * 256;
+  const size_t stride = (size_t)gridDim.x * 256 * 4;
+  const size_t v0 = ((size_t)blockIdx.x * 256 + tid) * 4;
   for (int c = 0; c <= k; ++c) {
     const float* b = c < k ? cols + (size_t)c * colstride : y;
+    const bool vec = nvox % 4 == 0 && (((uintptr_t)a | (uintptr_t)b) & 15) == 0;
     double s = 0.0;
-    for (size_t v = (size_t)blockIdx.x * 256 + tid; v < nvox; v += stride)
-      s += (double)a[v] * (double)b[v];
+    for (size_t v = v0; v < nvox; v += stride) {
+      if (vec) {
+        const float4 av = *reinterpret_cast<const float4*>(a + v);
+        const float4 bv = *reinterpret_cast<const float4*>(b + v);
+        s += (double)(av.x * bv.x) + (double)(av.y * bv.y) + (double)(av.z * bv.z) +
+             (double)(av.w * bv.w);
+      } else {
+        for (size_t u = v; u < v + 4 && u < nvox; ++u) s += (double)(a[u] * b[u]);
+      }
+    }
     s = shfl_sum_d(s);
     if ((tid & 63) == 0) red[tid / 64] = s;
     __syncthreads();
@@ -738,19 +766,25 @@ GradPlan plan_grad(sfw_dims vol, int n_atoms) {
   return p;
 }
 
-hipError_t launch_psf_prep(const float* H, sfw_dims psf, int kzp, bool flip, float* out,
-                           hipStream_t st) {
-  const int total = psf.nx * psf.ny * kzp;
-  hipLaunchKernelGGL(k_psf_prep, dim3((total + 255) / 256), dim3(256), 0, st, H, psf.nx, psf.ny,
-                     psf.nz, kzp, flip ? 1 : 0, out);
+hipError_t launch_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* ak, const float* H,
+                       sfw_dims psf, bool mfma, int kzp, bool fwd, bool adj, float* out_fwd,
+                       float* out_adj, hipStream_t st) {
+  const int steps = mfma ? mfma_steps(psf.nx, psf.ny) : 0;
+  const int npsf = (H && (fwd || adj)) ? (mfma ? steps * 64 : psf.nx * psf.ny * kzp) : 0;
+  const int count = std::max(n, npsf);
+  if (count <= 0) return hipSuccess;
+  dim3 grid((count + 255) / 256, npsf > 0 ? 3 : 1);
+  hipLaunchKernelGGL(k_prep, grid, dim3(256), 0, st, atoms, n, unit_weight ? 1 : 0, ak, H, psf.nx,
+                     psf.ny, psf.nz, mfma ? 1 : 0, steps, kzp, (fwd && npsf) ? 1 : 0,
+                     (adj && npsf) ? 1 : 0, out_fwd, out_adj);
   return hipGetLastError();
 }
 
-hipError_t launch_atom_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* out,
-                            hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_atom_prep, dim3((n + 63) / 64), dim3(64), 0, st, atoms, n,
-                     unit_weight ? 1 : 0, out);
+hipError_t launch_hash(const float* v, size_t n, unsigned long long* out, hipStream_t st) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 256) blocks = 256;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_hash, dim3((unsigned)blocks), dim3(256), 0, st, v, n, out);
   return hipGetLastError();
 }
 
@@ -809,13 +843,6 @@ int mfma_steps(int px, int py) {
   for (int c : counts)
     if (need <= c) return c;
   return 32;
-}
-
-hipError_t launch_mfma_prep(const float* H, sfw_dims psf, bool flip, float* amat, hipStream_t st) {
-  const int steps = mfma_steps(psf.nx, psf.ny);
-  hipLaunchKernelGGL(k_mfma_prep, dim3((steps * 64 + 255) / 256), dim3(256), 0, st, H, psf.nx,
-                     psf.ny, psf.nz, steps, flip ? 1 : 0, amat);
-  return hipGetLastError();
 }
 
 int mfma_conv_blocks(sfw_dims vol) { return ((vol.nx + 15) / 16) * ((vol.ny + 3) / 4); }

@@ -22,11 +22,19 @@ struct PsfPlan {
   int nres = 0;  // number of loss partials the residual epilogue writes
 };
 PsfPlan plan_psf(const sfw_dims& vol, const sfw_dims& psf);
-// Build the forward (convolution) and / or adjoint (correlation) copies of H.
+// Build the forward (convolution) and / or adjoint (correlation) operands of H and, when atoms
+// is not null, the constants of its n atoms into ws->ak, in one launch.
+int prep_all(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool adj,
+             const sfw_atom* atoms, int n, bool unit_weight);
 int prep_psf(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool adj);
+// Atom constants (see AtomK) from float64 parameters.
+AtomK make_atomk(double w, double mx, double my, double mz, double sigma, double d);
+// Weights-only LASSO with the workspace's column cache (see sfw_api.cpp).
+int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
+             const float* H, double lambda, const float* thetas, int n, std::vector<double>& w);
 // out = H * in (adjoint = false) or correlation with H (adjoint = true); epilogue as launch_conv.
 int conv_psf(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjoint,
-             const float* in, float* out, int epi, const float* yobs);
+             const float* in, float* out, int epi, const float* yobs, int prof_kind);
 // ws->ak must hold the n atoms' constants.
 int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, float* phi);
 // r = y - H * f (into r_out or ws->r), q = Phi^T r (ws->q), per-atom sums and loss in ws->dres:

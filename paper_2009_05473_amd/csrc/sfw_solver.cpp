@@ -323,9 +323,6 @@ struct Solver {
   // atoms (w, mx, my, mz, sigma, d) in float64
   std::vector<double> atoms;
   int k() const { return (int)(atoms.size() / 6); }
-  // LASSO cache: columns valid for indices < ncols_valid, Gram (row-major, max_atoms^2)
-  int ncols_valid = 0;
-  std::vector<double> G, b;
 
   int upload_atoms(const std::vector<double>& a, bool unit_weight) {
     const int n = (int)(a.size() / 6);
@@ -341,7 +338,8 @@ struct Solver {
     }
     SFW_HIP(hipMemcpyAsync(ws->atoms_dev, h, sizeof(sfw_atom) * n, hipMemcpyHostToDevice,
                            ws->stream));
-    SFW_HIP(launch_atom_prep(ws->atoms_dev, n, unit_weight, ws->ak, ws->stream));
+    int rc = prep_all(ws, nullptr, plan, false, false, ws->atoms_dev, n, unit_weight);
+    if (rc) return rc;
     // the pinned staging buffer is reused right away by callers: wait for the copy
     SFW_HIP(hipStreamSynchronize(ws->stream));
     return SFW_OK;
@@ -424,63 +422,35 @@ struct Solver {
     };
     MinResult r = minimize_box(fg, atoms, lo, hi, o.lbfgs_memory, o.slide_gtol, o.ftol,
                                o.slide_max_iter);
-    ncols_valid = 0;  // every theta may have moved
     return r.status;
   }
 
-  // Weights of the current support by the LASSO (columns cached while theta is unchanged).
+  // Weights of the current support by the LASSO (the workspace reuses the columns of the
+  // unchanged prefix of the support).
   int lasso() {
     const int n = k();
     if (n == 0) return SFW_OK;
-    const int M = ws->max_atoms;
-    if (ncols_valid < n) {
-      int rc = upload_atoms(atoms, true);
-      if (rc) return rc;
-      rc = op_columns(ws, plan, vol, ncols_valid, n);
-      if (rc) return rc;
-      for (int i = ncols_valid; i < n; ++i) {
-        rc = op_gram_row(ws, vol, y, i, ws->dres + (size_t)i * (i + 1) / 2 + i);
-        if (rc) return rc;
-      }
-      const size_t o0 = (size_t)ncols_valid * (ncols_valid + 1) / 2 + ncols_valid;
-      const size_t o1 = (size_t)n * (n + 1) / 2 + n;
-      SFW_HIP(hipMemcpyAsync(ws->hpin + o0, ws->dres + o0, (o1 - o0) * 8, hipMemcpyDeviceToHost,
-                             ws->stream));
-      SFW_HIP(hipStreamSynchronize(ws->stream));
-      G.resize((size_t)M * M);
-      b.resize(M);
-      for (int i = ncols_valid; i < n; ++i) {
-        const double* row = ws->hpin + (size_t)i * (i + 1) / 2 + i;
-        for (int j = 0; j <= i; ++j) G[(size_t)i * M + j] = G[(size_t)j * M + i] = row[j];
-        b[i] = row[i + 1];
-      }
-      ncols_valid = n;
-    }
-    std::vector<double> Gk((size_t)n * n), c(n), w;
-    for (int i = 0; i < n; ++i) {
-      for (int j = 0; j < n; ++j) Gk[(size_t)i * n + j] = G[(size_t)i * M + j];
-      c[i] = b[i] - lam;
-    }
-    int rc = nnqp(Gk, c, n, w);
+    std::vector<float> th(5 * (size_t)n);
+    for (int i = 0; i < n; ++i)
+      for (int c = 0; c < 5; ++c) th[5 * i + c] = (float)atoms[6 * i + 1 + c];
+    std::vector<double> w;
+    int rc = op_lasso(ws, plan, vol, y, H, lam, th.data(), n, w);
     if (rc) return rc;
     for (int i = 0; i < n; ++i) atoms[6 * i] = w[i];
     return SFW_OK;
   }
 
-  // Remove zero-weighted masses and merge coincident ones; columns of removed or moved atoms
-  // (and of every later index) are invalidated.
+  // Remove zero-weighted masses and merge coincident ones.
   void prune() {
     const int n = k();
     if (n == 0) return;
     double wmax = 0.0;
     for (int i = 0; i < n; ++i) wmax = std::max(wmax, atoms[6 * i]);
     std::vector<double> kept;
-    int first_change = n;
     int kept_n = 0;
     for (int i = 0; i < n; ++i) {
       const double* a = &atoms[6 * i];
       if (!(wmax > 0.0) || !(a[0] > o.prune_rel * wmax)) {
-        first_change = std::min(first_change, kept_n);
         continue;
       }
       bool merged = false;
@@ -493,7 +463,6 @@ struct Solver {
           if (ws_ > 0)
             for (int c = 1; c < 6; ++c) bj[c] = (bj[0] * bj[c] + a[0] * a[c]) / ws_;
           bj[0] = ws_;
-          first_change = std::min(first_change, j);
           merged = true;
           break;
         }
@@ -504,7 +473,6 @@ struct Solver {
       }
     }
     atoms.swap(kept);
-    ncols_valid = std::min(ncols_valid, first_change);
   }
 };
 
