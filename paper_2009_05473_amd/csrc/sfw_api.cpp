@@ -201,7 +201,12 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
   key.push_back((float)nd);
   for (int i = 0; i < ns; ++i) key.push_back(sg[i]);
   for (int j = 0; j < nd; ++j) key.push_back(dg[j]);
+  key.push_back((float)vol.nx);
+  key.push_back((float)vol.ny);
+  key.push_back((float)vol.nz);
   if (key == ws->lut_key && ws->lut) return SFW_OK;
+  ws->lut_key.clear();
+  ws->fft_ready = false;
   std::vector<size_t> off;
   std::vector<int> rad;
   size_t total = 0;
@@ -248,6 +253,50 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
   SFW_HIP(hipStreamSynchronize(ws->stream));
   ws->lut_off = off;
   ws->lut_r = rad;
+  // spectra of the table kernels, two per complex array
+  int rmax = 0;
+  for (int r : rad) rmax = std::max(rmax, r);
+  FftPlan pl;
+  if (fft_plan_cert(vol, rmax, pl)) {
+    const size_t N = (size_t)pl.nx * pl.ny * pl.nz;
+    const int npairs = (ns * nd + 1) / 2;
+    if (N > ws->fft_cap || npairs > ws->fft_npairs_cap) {
+      if (ws->fft_qhat) SFW_HIP(hipFree(ws->fft_qhat));
+      if (ws->fft_work) SFW_HIP(hipFree(ws->fft_work));
+      if (ws->fft_pairs) SFW_HIP(hipFree(ws->fft_pairs));
+      ws->fft_qhat = ws->fft_work = ws->fft_pairs = nullptr;
+      ws->fft_cap = 0;
+      ws->fft_npairs_cap = 0;
+      SFW_HIP(hipMalloc(&ws->fft_qhat, N * sizeof(float2)));
+      SFW_HIP(hipMalloc(&ws->fft_work, N * sizeof(float2)));
+      SFW_HIP(hipMalloc(&ws->fft_pairs, (size_t)npairs * N * sizeof(float2)));
+      ws->fft_cap = N;
+      ws->fft_npairs_cap = npairs;
+    }
+    if (!ws->fft_tw) SFW_HIP(hipMalloc(&ws->fft_tw, 3 * kFftMaxLen * sizeof(float2)));
+    std::vector<float2> tw, all;
+    for (int a = 0; a < 3; ++a) {
+      fft_twiddles(pl.ax[a].n, tw);
+      all.insert(all.end(), tw.begin(), tw.end());
+    }
+    SFW_HIP(hipMemcpy(ws->fft_tw, all.data(), all.size() * sizeof(float2), hipMemcpyHostToDevice));
+    pl.ax[0].tw = ws->fft_tw;
+    pl.ax[1].tw = ws->fft_tw + pl.ax[0].n;
+    pl.ax[2].tw = ws->fft_tw + pl.ax[0].n + pl.ax[1].n;
+    for (int pi = 0; pi < npairs; ++pi) {
+      const int sa = 2 * pi, sb = 2 * pi + 1;
+      auto kz_of = [&](int s) { return plan_conv(vol, 2 * rad[s] + 1, 2 * rad[s] + 1, 2 * rad[s] + 1).kzp; };
+      float2* dst = ws->fft_pairs + (size_t)pi * ws->fft_cap;  // stride of the allocation
+      SFW_HIP(fft_scatter_pair(pl, ws->lut + off[sa], rad[sa], kz_of(sa),
+                               sb < ns * nd ? ws->lut + off[sb] : nullptr,
+                               sb < ns * nd ? rad[sb] : 0, sb < ns * nd ? kz_of(sb) : 0, dst,
+                               ws->stream));
+      SFW_HIP(fft_forward_c2c(pl, dst, ws->stream));
+    }
+    SFW_HIP(hipStreamSynchronize(ws->stream));
+    ws->fft = pl;
+    ws->fft_ready = true;
+  }
   ws->lut_key = key;
   return SFW_OK;
 }
@@ -257,6 +306,29 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
   int rc = lut_prepare(ws, sg, ns, dg, nd, T, vol);
   if (rc) return rc;
   const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
+  const char* env = std::getenv("SFW_CERT");
+  const bool direct = (env && std::strcmp(env, "direct") == 0) || !ws->fft_ready;
+  if (!direct) {
+    const FftPlan& pl = ws->fft;
+    const int nblk = fft_argmax_blocks(pl, vol);
+    if ((size_t)nblk * ns * nd > ws->apart_cap)
+      return fail(SFW_EINVAL, "certificate partial buffer too small");
+    {
+      ProfScope ps(ws, kProfCertFft);
+      SFW_HIP(fft_forward_volume(pl, q, vol, ws->fft_qhat, ws->stream));
+    }
+    const int npairs = (ns * nd + 1) / 2;
+    for (int pi = 0; pi < npairs; ++pi) {
+      const int sa = 2 * pi, sb = 2 * pi + 1 < ns * nd ? 2 * pi + 1 : -1;
+      ProfScope ps(ws, kProfCertFft);
+      SFW_HIP(fft_inverse_pair(pl, ws->fft_qhat, ws->fft_pairs + (size_t)pi * ws->fft_cap,
+                               ws->fft_work, vol, 1.0f / lambda, sa, sb, eta_out, ws->apart,
+                               nblk, ws->stream));
+    }
+    ProfScope ps(ws, kProfCertArgmax);
+    SFW_HIP(launch_argmax_final(ws->apart, nblk * ns * nd, vol, nd, ws->best, ws->stream));
+    return SFW_OK;
+  }
   int nb = 0;
   for (int i = 0; i < ns; ++i)
     for (int j = 0; j < nd; ++j) {
@@ -442,6 +514,10 @@ void sfw_workspace_destroy(sfw_workspace* ws) {
   if (ws->apart) (void)hipFree(ws->apart);
   if (ws->best) (void)hipFree(ws->best);
   if (ws->hashbuf) (void)hipFree(ws->hashbuf);
+  if (ws->fft_tw) (void)hipFree(ws->fft_tw);
+  if (ws->fft_qhat) (void)hipFree(ws->fft_qhat);
+  if (ws->fft_work) (void)hipFree(ws->fft_work);
+  if (ws->fft_pairs) (void)hipFree(ws->fft_pairs);
   if (ws->hpin) (void)hipHostFree(ws->hpin);
   for (hipEvent_t e : ws->prof_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ws->prof_stop) (void)hipEventDestroy(e);
@@ -559,7 +635,7 @@ int sfw_profile_end(sfw_workspace* ws, sfw_prof_entry* out, int* n_out) {
   static const char* names[kProfCount] = {
       "prep", "render", "conv_residual", "conv_adjoint", "conv_forward", "grad",
       "grad_finalize", "cert_conv", "cert_argmax", "lasso_render", "lasso_conv", "lasso_dots",
-      "hash", "eta_grad"};
+      "hash", "eta_grad", "cert_fft"};
   ws->prof_on = false;
   SFW_HIP(hipStreamSynchronize(ws->stream));
   double ms[kProfCount] = {0};

@@ -1,0 +1,453 @@
+// Grid certificate through the Fourier domain (the paper computes its convolutions there,
+// section 2): eta_ij = correlation of q = Phi^T r with the tabulated unit atom of
+// (sigma_i, d_j), for all 12 (or ns * nd) table kernels at once.
+//
+// q is zero-padded to an Nx x Ny x Nz grid with N_a >= max(n_a + R_max, 2 R_max + 1) on every
+// axis, so the circular correlation equals the linear one on the volume. The table kernels are real and
+// symmetric, so their spectra are real and two of them ride in one complex spectrum
+// P = (K_a + i K_b)^ / N; one inverse transform of Qhat * P then yields eta_a + i eta_b.
+// Transforms are separable passes of batched 1D mixed-radix (2, 3, 4, 5) Stockham FFTs in
+// LDS; passes skip the rows that are known zero on input or not needed on output, and the
+// last pass keeps the running maximum of eta (ties to the lowest flat index).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "sfw_internal.h"
+
+namespace sfw {
+
+namespace {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// multiply by -i
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+
+// Forward DFT of size R in place (Y_k = sum_n x_n exp(-2 pi i n k / R)).
+template <int R>
+__device__ __forceinline__ void dft(float2* v);
+
+template <>
+__device__ __forceinline__ void dft<2>(float2* v) {
+  const float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <>
+__device__ __forceinline__ void dft<3>(float2* v) {
+  const float s = 0.86602540378443865f;  // sin(2 pi / 3)
+  const float2 t1 = cadd(v[1], v[2]);
+  const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+  const float2 d = csub(v[1], v[2]);
+  const float2 t3 = make_float2(s * d.y, -s * d.x);  // -i s (x1 - x2)
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, t3);
+  v[2] = csub(t2, t3);
+}
+
+template <>
+__device__ __forceinline__ void dft<4>(float2* v) {
+  const float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  const float2 c = cadd(v[1], v[3]), d = mul_mi(csub(v[1], v[3]));
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+
+template <>
+__device__ __forceinline__ void dft<5>(float2* v) {
+  const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+  const float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;
+  const float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+  const float2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+  const float2 x0 = v[0];
+  const float2 p1 = make_float2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+  const float2 p2 = make_float2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+  // q1 = -i (s1 b1 + s2 b2), q2 = -i (s2 b1 - s1 b2)
+  const float2 q1 = mul_mi(make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+  const float2 q2 = mul_mi(make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+  v[0] = make_float2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+  v[1] = cadd(p1, q1);
+  v[4] = csub(p1, q1);
+  v[2] = cadd(p2, q2);
+  v[3] = csub(p2, q2);
+}
+
+// One Stockham stage of radix R over `lines` lines of length L held in LDS (src -> dst).
+// Ns = product of the radices of the previous stages; tw[m] = exp(-2 pi i m / L).
+template <int R>
+__device__ __forceinline__ void stage(const float2* __restrict__ src, float2* __restrict__ dst,
+                                      int L, int lines, int Ns, const float2* __restrict__ tw) {
+  const int per = L / R;
+  const int tasks = lines * per;
+  const int tstep = L / (Ns * R);
+  for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+    const int line = t / per;
+    const int j = t - line * per;
+    const int k = j % Ns;
+    const float2* in = src + line * L;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[r] = in[j + r * per];
+      if (r > 0) v[r] = cmul(v[r], tw[r * k * tstep]);  // r k tstep < L
+    }
+    dft<R>(v);
+    float2* out = dst + line * L + (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r * Ns] = v[r];
+  }
+}
+
+// Runs every stage of the plan; returns the LDS buffer holding the result.
+__device__ float2* run_plan(float2* a, float2* b, int L, int lines, const FftAxis& ax) {
+  int Ns = 1;
+  for (int s = 0; s < ax.nstage; ++s) {
+    const int R = ax.radix[s];
+    __syncthreads();
+    switch (R) {
+      case 2: stage<2>(a, b, L, lines, Ns, ax.tw); break;
+      case 3: stage<3>(a, b, L, lines, Ns, ax.tw); break;
+      case 4: stage<4>(a, b, L, lines, Ns, ax.tw); break;
+      default: stage<5>(a, b, L, lines, Ns, ax.tw); break;
+    }
+    Ns *= R;
+    float2* t = a;
+    a = b;
+    b = t;
+  }
+  __syncthreads();
+  return a;
+}
+
+__device__ __forceinline__ bool arg_better(float v, long long i, float bv, long long bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+// ---------------------------------------------------------------- x passes (contiguous lines)
+
+// Forward x pass of the real volume q: line (y, z) for y < ny, z < nz, zero beyond nx.
+// out[(z * Ny + y) * Nx + i], i < Nx.
+__global__ __launch_bounds__(256) void k_fft_x_real(const float* __restrict__ q, int nx, int ny,
+                                                    int nz, FftAxis ax, int Ny, int B,
+                                                    float2* __restrict__ out) {
+  extern __shared__ float2 sm[];
+  const int L = ax.n;
+  float2* a = sm;
+  float2* b = sm + B * L;
+  const int y0 = blockIdx.x * B, z = blockIdx.y;
+  const int lines = min(B, ny - y0);
+  for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
+    const int l = e / L, i = e - l * L;
+    float v = 0.f;
+    if (l < lines && i < nx) v = q[((size_t)z * ny + y0 + l) * nx + i];
+    a[e] = make_float2(v, 0.f);
+  }
+  float2* r = run_plan(a, b, L, B, ax);
+  for (int e = threadIdx.x; e < lines * L; e += blockDim.x) {
+    const int l = e / L, i = e - l * L;
+    out[((size_t)z * Ny + y0 + l) * L + i] = r[e];
+  }
+}
+
+// Forward x pass of a complex array, every line of an Ny x Nz grid.
+__global__ __launch_bounds__(256) void k_fft_x_c2c(float2* __restrict__ data, FftAxis ax, int Ny,
+                                                   int B) {
+  extern __shared__ float2 sm[];
+  const int L = ax.n;
+  float2* a = sm;
+  float2* b = sm + B * L;
+  const int y0 = blockIdx.x * B, z = blockIdx.y;
+  const int lines = min(B, Ny - y0);
+  float2* base = data + ((size_t)z * Ny + y0) * L;
+  for (int e = threadIdx.x; e < B * L; e += blockDim.x)
+    a[e] = e < lines * L ? base[e] : make_float2(0.f, 0.f);
+  float2* r = run_plan(a, b, L, B, ax);
+  for (int e = threadIdx.x; e < lines * L; e += blockDim.x) base[e] = r[e];
+}
+
+// Last inverse pass: line (y < ny, z < nz) of work, forward FFT, conjugated output; real part
+// is eta_a, imaginary part eta_b (times scale). Writes eta (optional) and the block maxima.
+__global__ __launch_bounds__(256) void k_fft_x_argmax(
+    const float2* __restrict__ work, int nx, int ny, int nz, FftAxis ax, int Ny, int B,
+    float scale, int slice_a, int slice_b, float* __restrict__ eta_out, ArgPart* __restrict__ apart,
+    int nblk) {
+  extern __shared__ float2 sm[];
+  __shared__ float rv[2][4];
+  __shared__ long long ri[2][4];
+  const int L = ax.n;
+  float2* a = sm;
+  float2* b = sm + B * L;
+  const int y0 = blockIdx.x * B, z = blockIdx.y;
+  const int lines = min(B, ny - y0);
+  const float2* base = work + ((size_t)z * Ny + y0) * L;
+  for (int e = threadIdx.x; e < B * L; e += blockDim.x)
+    a[e] = e < lines * L ? base[e] : make_float2(0.f, 0.f);
+  float2* r = run_plan(a, b, L, B, ax);
+  const long long V = (long long)nx * ny * nz;
+  float bv[2] = {-INFINITY, -INFINITY};
+  long long bi[2] = {0x7fffffffffffffffLL, 0x7fffffffffffffffLL};
+  for (int e = threadIdx.x; e < lines * L; e += blockDim.x) {
+    const int l = e / L, i = e - l * L;
+    if (i >= nx) continue;
+    const long long v = ((long long)z * ny + y0 + l) * nx + i;
+    const float ea = r[e].x * scale;
+    const float eb = -r[e].y * scale;
+    if (eta_out) {
+      eta_out[(size_t)slice_a * V + v] = ea;
+      if (slice_b >= 0) eta_out[(size_t)slice_b * V + v] = eb;
+    }
+    const long long ga = (long long)slice_a * V + v;
+    if (arg_better(ea, ga, bv[0], bi[0])) {
+      bv[0] = ea;
+      bi[0] = ga;
+    }
+    if (slice_b >= 0) {
+      const long long gb = (long long)slice_b * V + v;
+      if (arg_better(eb, gb, bv[1], bi[1])) {
+        bv[1] = eb;
+        bi[1] = gb;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    for (int o = 32; o > 0; o >>= 1) {
+      const float ov = __shfl_xor(bv[s], o, 64);
+      const long long oi = __shfl_xor(bi[s], o, 64);
+      if (arg_better(ov, oi, bv[s], bi[s])) {
+        bv[s] = ov;
+        bi[s] = oi;
+      }
+    }
+    if ((threadIdx.x & 63) == 0) {
+      rv[s][threadIdx.x >> 6] = bv[s];
+      ri[s][threadIdx.x >> 6] = bi[s];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    for (int s = 0; s < 2; ++s) {
+      if (s == 1 && slice_b < 0) break;
+      float v = rv[s][0];
+      long long id = ri[s][0];
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+        if (arg_better(rv[s][w], ri[s][w], v, id)) {
+          v = rv[s][w];
+          id = ri[s][w];
+        }
+      ArgPart ap;
+      ap.val = v;
+      ap.pad = 0;
+      ap.idx = id;
+      apart[(size_t)(s == 0 ? slice_a : slice_b) * nblk + blk] = ap;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- strided passes (y or z)
+
+// Lines along one axis with element stride `istride`; a block owns B adjacent x columns at
+// one outer coordinate o (address o * ostride + i * istride + x). Reads i < n_in (zero beyond),
+// writes i < n_out. mode 0: plain; mode 1: input = conj(data * mulp) (first inverse pass).
+__global__ __launch_bounds__(256) void k_fft_strided(const float2* __restrict__ src,
+                                                     const float2* __restrict__ mulp,
+                                                     float2* __restrict__ dst, FftAxis ax,
+                                                     int ncols, size_t istride, size_t ostride,
+                                                     int n_in, int n_out, int B, int mode) {
+  extern __shared__ float2 sm[];
+  const int L = ax.n;
+  float2* a = sm;
+  float2* b = sm + B * L;
+  const int x0 = blockIdx.x * B;
+  const size_t obase = (size_t)blockIdx.y * ostride;
+  const int cols = min(B, ncols - x0);
+  for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
+    const int i = e / B, c = e - i * B;  // consecutive threads: consecutive columns
+    float2 v = make_float2(0.f, 0.f);
+    if (c < cols && i < n_in) {
+      const size_t g = obase + (size_t)i * istride + x0 + c;
+      v = src[g];
+      if (mode == 1) {
+        v = cmul(v, mulp[g]);
+        v.y = -v.y;
+      }
+    }
+    a[c * L + i] = v;
+  }
+  float2* r = run_plan(a, b, L, B, ax);
+  for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
+    const int i = e / B, c = e - i * B;
+    if (c < cols && i < n_out) dst[obase + (size_t)i * istride + x0 + c] = r[c * L + i];
+  }
+}
+
+// Kernel pair (a, b) of the table, wrapped around the origin of the Nx x Ny x Nz grid:
+// out = (K_a + i K_b) / N. Tables are [ky][kx][kzp] with radius R (2R + 1 taps per axis).
+__global__ __launch_bounds__(256) void k_fft_scatter_pair(
+    const float* __restrict__ ka, int ra, int kzpa, const float* __restrict__ kb, int rb,
+    int kzpb, int Nx, int Ny, int Nz, float inv_n, float2* __restrict__ out) {
+  const size_t N = (size_t)Nx * Ny * Nz;
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int x = (int)(i % Nx);
+  const int y = (int)((i / Nx) % Ny);
+  const int z = (int)(i / ((size_t)Nx * Ny));
+  // signed offsets t in (-N/2, N/2]
+  const int tx = x <= Nx / 2 ? x : x - Nx;
+  const int ty = y <= Ny / 2 ? y : y - Ny;
+  const int tz = z <= Nz / 2 ? z : z - Nz;
+  float va = 0.f, vb = 0.f;
+  if (abs(tx) <= ra && abs(ty) <= ra && abs(tz) <= ra) {
+    const int P = 2 * ra + 1;
+    va = ka[((size_t)(ty + ra) * P + (tx + ra)) * kzpa + (tz + ra)];
+  }
+  if (kb && abs(tx) <= rb && abs(ty) <= rb && abs(tz) <= rb) {
+    const int P = 2 * rb + 1;
+    vb = kb[((size_t)(ty + rb) * P + (tx + rb)) * kzpb + (tz + rb)];
+  }
+  out[i] = make_float2(va * inv_n, vb * inv_n);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+static int good_size(int n) {
+  for (int m = n;; ++m) {
+    int t = m;
+    for (int p : {2, 3, 5})
+      while (t % p == 0) t /= p;
+    if (t == 1) return m;
+  }
+}
+
+static bool make_axis_plan(int n, FftAxis& ax) {
+  ax.n = n;
+  ax.nstage = 0;
+  int t = n;
+  while (t % 4 == 0 && ax.nstage < kFftMaxStages) {
+    ax.radix[ax.nstage++] = 4;
+    t /= 4;
+  }
+  for (int p : {2, 3, 5})
+    while (t % p == 0 && ax.nstage < kFftMaxStages) {
+      ax.radix[ax.nstage++] = p;
+      t /= p;
+    }
+  return t == 1;
+}
+
+int fft_lines_per_block(int L, bool strided) {
+  int B = strided ? 16 : 8;
+  while (B > 1 && (size_t)2 * B * L * sizeof(float2) > 48 * 1024) B /= 2;
+  return B;
+}
+
+// Grid sizes: N >= n + R keeps wrapped reads of q off the volume, N >= 2R + 1 keeps the
+// wrapped table kernel from overlapping itself; both make the circular correlation equal the
+// linear one on the volume.
+bool fft_plan_cert(sfw_dims vol, int rmax, FftPlan& pl) {
+  pl.nx = good_size(std::max(vol.nx + rmax, 2 * rmax + 1));
+  pl.ny = good_size(std::max(vol.ny + rmax, 2 * rmax + 1));
+  pl.nz = good_size(std::max(vol.nz + rmax, 2 * rmax + 1));
+  if (pl.nx > kFftMaxLen || pl.ny > kFftMaxLen || pl.nz > kFftMaxLen) return false;
+  return make_axis_plan(pl.nx, pl.ax[0]) && make_axis_plan(pl.ny, pl.ax[1]) &&
+         make_axis_plan(pl.nz, pl.ax[2]);
+}
+
+void fft_twiddles(int n, std::vector<float2>& tw) {
+  tw.resize(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = -2.0 * 3.14159265358979323846 * (double)m / (double)n;
+    tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+}
+
+// Forward 3D transform of a complex array on the full grid (used for the table spectra).
+hipError_t fft_forward_c2c(const FftPlan& pl, float2* data, hipStream_t st) {
+  const int Bx = fft_lines_per_block(pl.nx, false);
+  hipLaunchKernelGGL(k_fft_x_c2c, dim3((pl.ny + Bx - 1) / Bx, pl.nz), dim3(256),
+                     2 * Bx * pl.nx * sizeof(float2), st, data, pl.ax[0], pl.ny, Bx);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int By = fft_lines_per_block(pl.ny, true);
+  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + By - 1) / By, pl.nz), dim3(256),
+                     2 * By * pl.ny * sizeof(float2), st, data, nullptr, data, pl.ax[1], pl.nx,
+                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, pl.ny, pl.ny, By, 0);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int Bz = fft_lines_per_block(pl.nz, true);
+  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(256),
+                     2 * Bz * pl.nz * sizeof(float2), st, data, nullptr, data, pl.ax[2], pl.nx,
+                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, pl.nz, pl.nz, Bz, 0);
+  return hipGetLastError();
+}
+
+hipError_t fft_scatter_pair(const FftPlan& pl, const float* ka, int ra, int kzpa, const float* kb,
+                            int rb, int kzpb, float2* out, hipStream_t st) {
+  const size_t N = (size_t)pl.nx * pl.ny * pl.nz;
+  hipLaunchKernelGGL(k_fft_scatter_pair, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, ka,
+                     ra, kzpa, kb, rb, kzpb, pl.nx, pl.ny, pl.nz, (float)(1.0 / (double)N), out);
+  return hipGetLastError();
+}
+
+// Qhat = FFT(q) with q zero-padded from the volume to the grid.
+hipError_t fft_forward_volume(const FftPlan& pl, const float* q, sfw_dims vol, float2* qhat,
+                              hipStream_t st) {
+  const int Bx = fft_lines_per_block(pl.nx, false);
+  hipLaunchKernelGGL(k_fft_x_real, dim3((vol.ny + Bx - 1) / Bx, vol.nz), dim3(256),
+                     2 * Bx * pl.nx * sizeof(float2), st, q, vol.nx, vol.ny, vol.nz, pl.ax[0],
+                     pl.ny, Bx, qhat);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int By = fft_lines_per_block(pl.ny, true);
+  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + By - 1) / By, vol.nz), dim3(256),
+                     2 * By * pl.ny * sizeof(float2), st, qhat, nullptr, qhat, pl.ax[1], pl.nx,
+                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, vol.ny, pl.ny, By, 0);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int Bz = fft_lines_per_block(pl.nz, true);
+  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(256),
+                     2 * Bz * pl.nz * sizeof(float2), st, qhat, nullptr, qhat, pl.ax[2], pl.nx,
+                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, vol.nz, pl.nz, Bz, 0);
+  return hipGetLastError();
+}
+
+int fft_argmax_blocks(const FftPlan& pl, sfw_dims vol) {
+  const int Bx = fft_lines_per_block(pl.nx, false);
+  return ((vol.ny + Bx - 1) / Bx) * vol.nz;
+}
+
+// eta_a + i eta_b = IFFT(Qhat * P) on the volume, with the block maxima of both slices.
+hipError_t fft_inverse_pair(const FftPlan& pl, const float2* qhat, const float2* pair,
+                            float2* work, sfw_dims vol, float scale, int slice_a, int slice_b,
+                            float* eta_out, ArgPart* apart, int nblk, hipStream_t st) {
+  const int Bz = fft_lines_per_block(pl.nz, true);
+  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(256),
+                     2 * Bz * pl.nz * sizeof(float2), st, qhat, pair, work, pl.ax[2], pl.nx,
+                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, pl.nz, vol.nz, Bz, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int By = fft_lines_per_block(pl.ny, true);
+  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + By - 1) / By, vol.nz), dim3(256),
+                     2 * By * pl.ny * sizeof(float2), st, work, nullptr, work, pl.ax[1], pl.nx,
+                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, pl.ny, vol.ny, By, 0);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int Bx = fft_lines_per_block(pl.nx, false);
+  hipLaunchKernelGGL(k_fft_x_argmax, dim3((vol.ny + Bx - 1) / Bx, vol.nz), dim3(256),
+                     2 * Bx * pl.nx * sizeof(float2), st, work, vol.nx, vol.ny, vol.nz, pl.ax[0],
+                     pl.ny, Bx, scale, slice_a, slice_b, eta_out, apart, nblk);
+  return hipGetLastError();
+}
+
+}  // namespace sfw

@@ -53,6 +53,20 @@ constexpr int conv_tile_lzp(int kz) {
   return (l / 4) % 2 == 1 ? l : l + 4;
 }
 
+// One axis of a separable FFT: length n = prod(radix), twiddles tw[m] = exp(-2 pi i m / n).
+constexpr int kFftMaxStages = 16;
+constexpr int kFftMaxLen = 1024;
+struct FftAxis {
+  int n = 1;
+  int nstage = 0;
+  int radix[kFftMaxStages] = {0};
+  const float2* tw = nullptr;
+};
+struct FftPlan {
+  int nx = 0, ny = 0, nz = 0;
+  FftAxis ax[3];
+};
+
 struct ConvPlan {
   int px = 1, py = 1, pz = 1;  // kernel taps per axis
   int kz = 4;                  // z taps per LDS pass (template parameter)
@@ -66,7 +80,7 @@ struct ConvPlan {
 enum ProfKind {
   kProfPrep = 0, kProfRender, kProfConvResidual, kProfConvAdjoint, kProfConvForward, kProfGrad,
   kProfGradFinalize, kProfCertConv, kProfCertArgmax, kProfLassoRender, kProfLassoConv,
-  kProfLassoDots, kProfHash, kProfEtaGrad, kProfCount
+  kProfLassoDots, kProfHash, kProfEtaGrad, kProfCertFft, kProfCount
 };
 constexpr int kProfPool = 16384;
 
@@ -110,7 +124,17 @@ struct sfw_workspace {
   size_t lut_cap = 0;
   std::vector<size_t> lut_off;
   std::vector<int> lut_r;
-  std::vector<float> lut_key;  // (T, ns, nd, sigmas..., ds...) of the cached table
+  std::vector<float> lut_key;  // (T, ns, nd, sigmas..., ds..., volume) of the cached table
+  // Fourier-domain certificate: plan, twiddles, spectrum of q, work array and the table
+  // spectra paired two per complex array
+  sfw::FftPlan fft;
+  bool fft_ready = false;
+  float2* fft_tw = nullptr;      // [nx + ny + nz]
+  float2* fft_qhat = nullptr;    // [N]
+  float2* fft_work = nullptr;    // [N]
+  float2* fft_pairs = nullptr;   // [npairs][N]
+  size_t fft_cap = 0;            // complex elements per array
+  int fft_npairs_cap = 0;
 
   // atoms
   sfw_atom* atoms_dev = nullptr;  // [max_atoms + 1] staging for host-provided atoms
@@ -235,5 +259,18 @@ hipError_t launch_dots(const float* a, const float* cols, int k, size_t colstrid
                        const float* y, size_t nvox, double* dpart, int nblocks, double* out,
                        hipStream_t st);
 hipError_t launch_any_nonfinite(const float* v, size_t n, int* flag, hipStream_t st);
+
+// ---- Fourier-domain grid certificate (sfw_fft.hip)
+bool fft_plan_cert(sfw_dims vol, int rmax, FftPlan& pl);
+void fft_twiddles(int n, std::vector<float2>& tw);
+hipError_t fft_scatter_pair(const FftPlan& pl, const float* ka, int ra, int kzpa, const float* kb,
+                            int rb, int kzpb, float2* out, hipStream_t st);
+hipError_t fft_forward_c2c(const FftPlan& pl, float2* data, hipStream_t st);
+hipError_t fft_forward_volume(const FftPlan& pl, const float* q, sfw_dims vol, float2* qhat,
+                              hipStream_t st);
+int fft_argmax_blocks(const FftPlan& pl, sfw_dims vol);
+hipError_t fft_inverse_pair(const FftPlan& pl, const float2* qhat, const float2* pair,
+                            float2* work, sfw_dims vol, float scale, int slice_a, int slice_b,
+                            float* eta_out, ArgPart* apart, int nblk, hipStream_t st);
 
 }  // namespace sfw

@@ -182,13 +182,23 @@ def test_adjoint_identity_on_gpu(L, ws_big, conv_path):
     assert abs(lhs - rhs) <= 1e-5 * (np.linalg.norm(f) * np.linalg.norm(r) * np.abs(psf).sum())
 
 
+@pytest.fixture(params=["fft", "direct"])
+def cert_path(request, monkeypatch):
+    """Run a test on the Fourier-domain certificate (default) and on the direct one."""
+    if request.param == "direct":
+        monkeypatch.setenv("SFW_CERT", "direct")
+    else:
+        monkeypatch.delenv("SFW_CERT", raising=False)
+    return request.param
+
+
 @pytest.mark.parametrize("name", ["c1", "c2"])
-def test_certificate_parity(L, ws_big, name):
+def test_certificate_parity(L, ws_big, name, cert_path):
     prob, atoms, psf, y = _problem(name)
     lam = 0.9
     sg, dg = prob.config.sigma_grid, prob.config.d_grid
     sgf = [float(np.float32(v)) for v in sg]
-    say("sfw_certificate", name, prob.shape)
+    say("sfw_certificate", name, prob.shape, cert_path)
     eta, best = L.sfw_certificate(ws_big, dev(psf), dev(y), lam, sgf, dg, want_eta=True)
     torch.cuda.synchronize()
     q = oracle.adjoint(y, psf)
@@ -205,7 +215,29 @@ def test_certificate_parity(L, ws_big, name):
     assert best["eta"] == e[idx]
 
 
-def test_certificate_argmax_only_matches_grid(L, ws_big):
+@pytest.mark.parametrize("shape,sg,dg", [
+    ((6, 7, 8), (0.6, 0.9), (1.8, 2.6)),        # tiny volume, tiny kernels
+    ((5, 9, 4), (2.0, 3.0), (1.5,)),             # kernels wider than the volume
+    ((37, 23, 41), (1.2, 2.2, 3.1), (1.3, 2.0)), # ragged, odd grid count (one unpaired kernel)
+])
+def test_certificate_edge_shapes(L, ws_big, cert_path, shape, sg, dg):
+    rng = np.random.default_rng(sum(shape))
+    r = f32(rng.standard_normal(shape))
+    psf = f32(np.abs(rng.standard_normal((5, 3, 3))) + 0.1)
+    lam = 0.7
+    say("sfw_certificate edge", shape, sg, dg, cert_path)
+    eta, best = L.sfw_certificate(ws_big, dev(psf), dev(r), lam, list(sg), list(dg), want_eta=True)
+    torch.cuda.synchronize()
+    eta_o = oracle.grid_certificate(oracle.adjoint(r, psf), lam, sg, dg)
+    assert rel_l2(eta.cpu().numpy(), eta_o) <= 1e-5
+    v_o, idx_o = oracle.grid_argmax(eta_o)
+    assert rel_err(best["eta"], v_o) <= 1e-5
+    idx = (best["i_sigma"], best["i_d"], best["z"], best["y"], best["x"])
+    if idx != idx_o:
+        assert rel_err(eta_o[idx], v_o) <= 1e-5
+
+
+def test_certificate_argmax_only_matches_grid(L, ws_big, cert_path):
     prob, atoms, psf, y = _problem("c1")
     say("sfw_certificate argmax only")
     _, b1 = L.sfw_certificate(ws_big, dev(psf), dev(y), 0.5, [1.0, 1.5], [2.0], want_eta=False)
