@@ -135,12 +135,16 @@ def main():
         s[-1, 1:4] += rng.uniform(-1.0, 1.0, size=3).astype(np.float32)
         supports.append(dev(s))
 
+    loss_buf = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad_buf = torch.empty((N, 6), dtype=torch.float32, device="cuda")
+    w_buf = torch.empty(N, dtype=torch.float64, device="cuda")
+
     def step(k):
-        L.sfw_residual_grad(ws, H, Y, lam, A, r_out=R)                       # a1-a5
+        L.sfw_residual_grad(ws, H, Y, lam, A, r_out=R, loss_out=loss_buf, grad_out=grad_buf)  # a1-a5
         _, best = L.sfw_certificate(ws, H, None, lam, sg, dg, vol_shape=shape)  # a6-a7
         th = [[best["x"], best["y"], best["z"], sg[best["i_sigma"]], dg[best["i_d"]]]]
         L.sfw_eta_points(ws, shape, None, lam, th)                           # a8
-        L.sfw_lasso_weights(ws, H, Y, lam, supports[k])                      # a9
+        L.sfw_lasso_weights(ws, H, Y, lam, supports[k], w_out=w_buf)          # a9
 
     for k in range(args.warmup):
         step(k)

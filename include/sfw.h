@@ -148,7 +148,8 @@ int sfw_adjoint(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
  * r: device [V], or NULL to use the q = Phi^T r left by the last sfw_residual_grad /
  * sfw_certificate on this workspace; sigma_grid, d_grid: HOST float [ns], [nd]
  * (ns, nd <= SFW_MAX_GRID);
- * eta_out: device [ns][nd][nz][ny][nx] or NULL; best_out: device [1] or NULL. */
+ * eta_out: device [ns][nd][nz][ny][nx] or NULL; best_out: device or HOST [1], or NULL
+ * (a host best_out makes the call synchronise before returning). */
 int sfw_certificate(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
                     const float* r, float lambda, const float* sigma_grid, int ns,
                     const float* d_grid, int nd, float trunc_T, float* eta_out,
@@ -166,8 +167,11 @@ int sfw_eta_points(sfw_workspace* ws, sfw_dims vol, const float* q, float lambda
 /* Weights-only LASSO (section 1.3 step 3): w = argmin_{w >= 0} 1/2 ||y - sum w_n a_n||^2
  * + lambda sum w_n, a_n = H * g(theta_n) (unit weight). The Gram matrix and A^T y are
  * accumulated in float64 on the GPU; the non-negative quadratic program is solved in
- * float64 on the host by an active-set method. The atoms' w fields are ignored.
- * atoms: device [n]; w_out: device double [n]. Synchronises the stream. */
+ * float64 on the host by an active-set method. The atoms' w fields are ignored. Columns and
+ * Gram rows of the longest unchanged prefix of the atom list are reused from the previous
+ * call on the same y (pointer and contents) and H, as BSFW needs (its atoms do not move).
+ * atoms: device [n]; w_out: device double [n], written in stream order. Synchronises the
+ * stream to read the atoms and the Gram rows. */
 int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
                       const float* y, float lambda, const sfw_atom* atoms, int n,
                       double* w_out);

@@ -213,14 +213,16 @@ def sfw_forward(ws: Workspace, H, atoms, vol_shape, phi_mu=None):
     return phi_mu
 
 
-def sfw_residual_grad(ws: Workspace, H, y, lam, atoms, r_out=None, want_r=True):
-    """Returns (r, loss[1] float64 tensor, grad[n, 6] tensor)."""
+def sfw_residual_grad(ws: Workspace, H, y, lam, atoms, r_out=None, want_r=True, loss_out=None,
+                      grad_out=None):
+    """Returns (r, loss[1] float64 tensor, grad[n, 6] tensor). Output tensors may be passed in."""
     import torch
     n = 0 if atoms is None else int(atoms.shape[0])
     if want_r and r_out is None:
         r_out = torch.empty_like(y)
-    loss = torch.empty(1, dtype=torch.float64, device="cuda")
-    grad = torch.empty((max(n, 1), 6), dtype=torch.float32, device="cuda")
+    loss = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = grad_out if grad_out is not None else torch.empty((max(n, 1), 6), dtype=torch.float32,
+                                                             device="cuda")
     check(lib.sfw_residual_grad(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape),
                                 dims(y.shape), _dev_ptr(y, "float32", "y"), float(lam),
                                 _dev_ptr(atoms, "float32", "atoms") if n else None, n,
@@ -246,22 +248,19 @@ def sfw_certificate(ws: Workspace, H, r, lam, sigma_grid, d_grid, trunc_T=12.0, 
     import torch
     sg = (ctypes.c_float * len(sigma_grid))(*[float(v) for v in sigma_grid])
     dg = (ctypes.c_float * len(d_grid))(*[float(v) for v in d_grid])
+    vol = tuple(r.shape) if r is not None else tuple(vol_shape)
     eta = None
     if want_eta:
-        eta = torch.empty((len(sigma_grid), len(d_grid)) + (tuple(r.shape) if r is not None
-                                                             else tuple(vol_shape)),
-                          dtype=torch.float32, device="cuda")
-    best = torch.zeros(6, dtype=torch.int32, device="cuda")  # sfw_argmax is 24 bytes
-    vol = tuple(r.shape) if r is not None else tuple(vol_shape)
-    check(lib.sfw_certificate(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape),
-                              dims(vol), _dev_ptr(r, "float32", "r"), float(lam),
+        eta = torch.empty((len(sigma_grid), len(d_grid)) + vol, dtype=torch.float32, device="cuda")
+    best = SfwArgmax()  # host: the library synchronises and fills it
+    check(lib.sfw_certificate(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape), dims(vol),
+                              _dev_ptr(r, "float32", "r"), float(lam),
                               ctypes.cast(sg, ctypes.c_void_p), len(sigma_grid),
                               ctypes.cast(dg, ctypes.c_void_p), len(d_grid), float(trunc_T),
                               _dev_ptr(eta, "float32", "eta") if want_eta else None,
-                              _dev_ptr(best, "int32", "best")))
-    b = best.cpu().numpy()
-    return eta, {"eta": float(b[:1].view(np.float32)[0]), "i_sigma": int(b[1]), "i_d": int(b[2]),
-                 "x": int(b[3]), "y": int(b[4]), "z": int(b[5])}
+                              ctypes.byref(best)))
+    return eta, {"eta": float(best.eta), "i_sigma": int(best.i_sigma), "i_d": int(best.i_d),
+                 "x": int(best.x), "y": int(best.y), "z": int(best.z)}
 
 
 def sfw_eta_points(ws: Workspace, vol_shape, q, lam, thetas):
@@ -278,10 +277,10 @@ def sfw_eta_points(ws: Workspace, vol_shape, q, lam, thetas):
     return eta, grad
 
 
-def sfw_lasso_weights(ws: Workspace, H, y, lam, atoms):
+def sfw_lasso_weights(ws: Workspace, H, y, lam, atoms, w_out=None):
     import torch
     n = int(atoms.shape[0])
-    w = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
+    w = w_out if w_out is not None else torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
     check(lib.sfw_lasso_weights(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape),
                                 dims(y.shape), _dev_ptr(y, "float32", "y"), float(lam),
                                 _dev_ptr(atoms, "float32", "atoms"), n, _dev_ptr(w, "float64", "w")))

@@ -158,7 +158,7 @@ int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
 int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double lambda,
                   const double* thetas, int n, double* eta_out, double* grad_out) {
   // unit-weight atom constants computed on the host in float64, staged through pinned memory
-  AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin);
+  AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin + ws->hp_stage);
   for (int i = 0; i < n; ++i) {
     const double* t = thetas + 5 * i;
     hk[i] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
@@ -171,7 +171,7 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
     SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, nullptr, 0, nullptr, 0.f, ws->dres,
                                  nullptr, nullptr, ws->stream));
   }
-  double* hs = ws->hpin + 8 * (size_t)ws->max_atoms + 16;
+  double* hs = ws->hpin + ws->hp_sums;
   SFW_HIP(hipMemcpyAsync(hs, ws->dres, sizeof(double) * 6 * n, hipMemcpyDeviceToHost,
                          ws->stream));
   SFW_HIP(hipStreamSynchronize(ws->stream));
@@ -375,46 +375,70 @@ int op_gram_row(sfw_workspace* ws, const sfw_dims& vol, const float* y, int i, d
   return SFW_OK;
 }
 
-// Weights-only LASSO for unit-weight atoms thetas [n][5] (host, float32 values as the device
-// sees them); the PSF operands for the forward convolution must already be prepared. Columns
-// and Gram rows of the longest prefix of atoms identical to the workspace's cached list (same
-// y, H, shapes and convolution kind) are reused; the rest are computed on the GPU.
-int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
-             const float* H, double lambda, const float* thetas, int n, std::vector<double>& w) {
-  w.assign(n, 0.0);
-  if (n == 0) return SFW_OK;
+// Enqueue the fingerprints of y and H into ws->hashbuf.
+static int enqueue_fingerprints(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
+                                const float* y, const float* H) {
+  ProfScope ps(ws, kProfHash);
   const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
-  const int M = ws->max_atoms;
-  {
-    ProfScope ps(ws, kProfHash);
-    SFW_HIP(hipMemsetAsync(ws->hashbuf, 0, 2 * sizeof(unsigned long long), ws->stream));
-    SFW_HIP(launch_hash(y, V, ws->hashbuf, ws->stream));
-    SFW_HIP(launch_hash(H, (size_t)p.psf.nx * p.psf.ny * p.psf.nz, ws->hashbuf + 1, ws->stream));
-  }
-  unsigned long long* hh = reinterpret_cast<unsigned long long*>(ws->hpin);
-  SFW_HIP(hipMemcpyAsync(hh, ws->hashbuf, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                         ws->stream));
-  SFW_HIP(hipStreamSynchronize(ws->stream));
-  const unsigned long long yh = hh[0], hhv = hh[1];
-  int pre = 0;
-  const bool same = ws->lasso_y == y && ws->lasso_yhash == yh && ws->lasso_hhash == hhv &&
+  SFW_HIP(hipMemsetAsync(ws->hashbuf, 0, 2 * sizeof(unsigned long long), ws->stream));
+  SFW_HIP(launch_hash(y, V, ws->hashbuf, ws->stream));
+  SFW_HIP(launch_hash(H, (size_t)p.psf.nx * p.psf.ny * p.psf.nz, ws->hashbuf + 1, ws->stream));
+  return SFW_OK;
+}
+
+// Drop the cached LASSO columns unless they were computed for this y pointer, shapes,
+// convolution kind and the given fingerprints of y and H.
+static void lasso_validate(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
+                           const float* y, unsigned long long yh, unsigned long long hh) {
+  const bool same = ws->lasso_y == y && ws->lasso_yhash == yh && ws->lasso_hhash == hh &&
                     ws->lasso_mfma == p.mfma && ws->lasso_vol.nx == vol.nx &&
                     ws->lasso_vol.ny == vol.ny && ws->lasso_vol.nz == vol.nz &&
                     ws->lasso_psf.nx == p.psf.nx && ws->lasso_psf.ny == p.psf.ny &&
                     ws->lasso_psf.nz == p.psf.nz;
-  if (same) {
-    const int kmax = std::min(ws->lasso_k, n);
-    while (pre < kmax &&
-           std::memcmp(&ws->lasso_thetas[5 * (size_t)pre], thetas + 5 * (size_t)pre,
-                       5 * sizeof(float)) == 0)
-      ++pre;
-  }
+  if (!same) ws->lasso_k = 0;
+  ws->lasso_y = y;
+  ws->lasso_yhash = yh;
+  ws->lasso_hhash = hh;
+  ws->lasso_mfma = p.mfma;
+  ws->lasso_vol = vol;
+  ws->lasso_psf = p.psf;
+}
+
+// Fingerprint y and H and validate the cache (one synchronisation).
+int lasso_check_inputs(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
+                       const float* H) {
+  int rc = enqueue_fingerprints(ws, p, vol, y, H);
+  if (rc) return rc;
+  unsigned long long* hh = reinterpret_cast<unsigned long long*>(ws->hpin + ws->hp_hash);
+  SFW_HIP(hipMemcpyAsync(hh, ws->hashbuf, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         ws->stream));
+  SFW_HIP(hipStreamSynchronize(ws->stream));
+  lasso_validate(ws, p, vol, y, hh[0], hh[1]);
+  return SFW_OK;
+}
+
+// Weights-only LASSO for unit-weight atoms thetas [n][5] (host, float32 values as the device
+// sees them); the PSF operands for the forward convolution must be prepared and the cache
+// validated for (y, H) (lasso_check_inputs). Columns and Gram rows of the longest prefix of
+// atoms identical to the cached list are reused; the rest are computed on the GPU (one
+// synchronisation for the Gram readback).
+int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
+             double lambda, const float* thetas, int n, std::vector<double>& w) {
+  w.assign(n, 0.0);
+  if (n == 0) return SFW_OK;
+  const int M = ws->max_atoms;
   if ((int)ws->lasso_G.size() != M * M) {
     ws->lasso_G.assign((size_t)M * M, 0.0);
     ws->lasso_b.assign(M, 0.0);
+    ws->lasso_k = 0;
   }
+  int pre = 0;
+  const int kmax = std::min(ws->lasso_k, n);
+  while (pre < kmax && std::memcmp(&ws->lasso_thetas[5 * (size_t)pre], thetas + 5 * (size_t)pre,
+                                   5 * sizeof(float)) == 0)
+    ++pre;
   if (pre < n) {
-    AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin);
+    AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin + ws->hp_stage);
     for (int i = pre; i < n; ++i) {
       const float* t = thetas + 5 * (size_t)i;
       hk[i - pre] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
@@ -429,26 +453,19 @@ int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
     }
     const size_t o0 = (size_t)pre * (pre + 1) / 2 + pre;
     const size_t o1 = (size_t)n * (n + 1) / 2 + n;
-    // the staged atom constants share the pinned buffer: wait for that copy first
-    SFW_HIP(hipStreamSynchronize(ws->stream));
-    SFW_HIP(hipMemcpyAsync(ws->hpin + o0, ws->dres + o0, (o1 - o0) * 8, hipMemcpyDeviceToHost,
+    double* rows = ws->hpin + ws->hp_rows;
+    SFW_HIP(hipMemcpyAsync(rows + o0, ws->dres + o0, (o1 - o0) * 8, hipMemcpyDeviceToHost,
                            ws->stream));
     SFW_HIP(hipStreamSynchronize(ws->stream));
     for (int i = pre; i < n; ++i) {
-      const double* row = ws->hpin + (size_t)i * (i + 1) / 2 + i;
+      const double* row = rows + (size_t)i * (i + 1) / 2 + i;
       for (int j = 0; j <= i; ++j)
         ws->lasso_G[(size_t)i * M + j] = ws->lasso_G[(size_t)j * M + i] = row[j];
       ws->lasso_b[i] = row[i + 1];
     }
-    ws->lasso_thetas.assign(thetas, thetas + 5 * (size_t)n);
-    ws->lasso_k = n;
-    ws->lasso_y = y;
-    ws->lasso_yhash = yh;
-    ws->lasso_hhash = hhv;
-    ws->lasso_vol = vol;
-    ws->lasso_psf = p.psf;
-    ws->lasso_mfma = p.mfma;
   }
+  ws->lasso_thetas.assign(thetas, thetas + 5 * (size_t)n);
+  ws->lasso_k = n;
   std::vector<double> Gk((size_t)n * n), c(n);
   for (int i = 0; i < n; ++i) {
     for (int j = 0; j < n; ++j) Gk[(size_t)i * n + j] = ws->lasso_G[(size_t)i * M + j];
@@ -598,7 +615,13 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ALLOC(ws->hashbuf, 2 * sizeof(unsigned long long), "fingerprints");
     ALLOC(ws->cols, (size_t)max_atoms * V * 4, "LASSO columns");
 #undef ALLOC
-    ws->hpin_cap = dres_n + 8 * (size_t)(na + 2) + 64;
+    ws->hp_hash = 0;
+    ws->hp_atoms = 2;
+    ws->hp_stage = ws->hp_atoms + 3 * (size_t)na;
+    ws->hp_sums = ws->hp_stage + 4 * (size_t)na;
+    ws->hp_w = ws->hp_sums + 6 * (size_t)na + 8;
+    ws->hp_rows = ws->hp_w + (size_t)na;
+    ws->hpin_cap = ws->hp_rows + (size_t)(na + 2) * (na + 2) + 64;
     if (hipHostMalloc(reinterpret_cast<void**>(&ws->hpin), ws->hpin_cap * 8, 0) != hipSuccess) {
       (void)hipGetLastError();
       sfw_workspace_destroy(ws);
@@ -746,9 +769,22 @@ int sfw_certificate(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vo
     }
     rc = op_certificate(ws, vol, ws->q, lambda, sigma_grid, ns, d_grid, nd, T, eta_out);
     if (rc) return rc;
-    if (best_out)
-      SFW_HIP(hipMemcpyAsync(best_out, ws->best, sizeof(sfw_argmax), hipMemcpyDeviceToDevice,
-                             ws->stream));
+    if (best_out) {
+      hipPointerAttribute_t attr;
+      const bool on_device = hipPointerGetAttributes(&attr, best_out) == hipSuccess &&
+                             attr.type == hipMemoryTypeDevice;
+      if (!on_device) (void)hipGetLastError();
+      if (on_device) {
+        SFW_HIP(hipMemcpyAsync(best_out, ws->best, sizeof(sfw_argmax), hipMemcpyDeviceToDevice,
+                               ws->stream));
+      } else {
+        sfw_argmax* hb = reinterpret_cast<sfw_argmax*>(ws->hpin + ws->hp_sums);
+        SFW_HIP(hipMemcpyAsync(hb, ws->best, sizeof(sfw_argmax), hipMemcpyDeviceToHost,
+                               ws->stream));
+        SFW_HIP(hipStreamSynchronize(ws->stream));
+        *best_out = *hb;
+      }
+    }
     return SFW_OK;
   } catch (...) {
     return fail(SFW_EINVAL, "unexpected exception in sfw_certificate");
@@ -790,9 +826,16 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
     PsfPlan p = plan_psf(vol, psf);
     rc = prep_psf(ws, H, p, true, false);
     if (rc) return rc;
-    sfw_atom* ha = reinterpret_cast<sfw_atom*>(ws->hpin);
+    // one synchronisation brings back the atoms and the fingerprints of y and H
+    rc = enqueue_fingerprints(ws, p, vol, y, H);
+    if (rc) return rc;
+    sfw_atom* ha = reinterpret_cast<sfw_atom*>(ws->hpin + ws->hp_atoms);
+    unsigned long long* hh = reinterpret_cast<unsigned long long*>(ws->hpin + ws->hp_hash);
     SFW_HIP(hipMemcpyAsync(ha, atoms, sizeof(sfw_atom) * n, hipMemcpyDeviceToHost, ws->stream));
+    SFW_HIP(hipMemcpyAsync(hh, ws->hashbuf, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           ws->stream));
     SFW_HIP(hipStreamSynchronize(ws->stream));
+    lasso_validate(ws, p, vol, y, hh[0], hh[1]);
     std::vector<float> th(5 * (size_t)n);
     for (int i = 0; i < n; ++i) {
       th[5 * i + 0] = ha[i].mx;
@@ -804,10 +847,12 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
         return fail(SFW_EINVAL, "atoms: sigma and d must be > 0");
     }
     std::vector<double> w;
-    rc = op_lasso(ws, p, vol, y, H, lambda, th.data(), n, w);
+    rc = op_lasso(ws, p, vol, y, lambda, th.data(), n, w);
     if (rc) return rc;
-    SFW_HIP(hipMemcpyAsync(w_out, w.data(), 8 * (size_t)n, hipMemcpyHostToDevice, ws->stream));
-    SFW_HIP(hipStreamSynchronize(ws->stream));
+    // stream-ordered upload from a pinned region no other call writes before synchronising
+    double* hw = ws->hpin + ws->hp_w;
+    std::memcpy(hw, w.data(), 8 * (size_t)n);
+    SFW_HIP(hipMemcpyAsync(w_out, hw, 8 * (size_t)n, hipMemcpyHostToDevice, ws->stream));
     return SFW_OK;
   } catch (...) {
     return fail(SFW_EINVAL, "unexpected exception in sfw_lasso_weights");

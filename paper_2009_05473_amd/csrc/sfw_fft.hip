@@ -80,19 +80,24 @@ __device__ __forceinline__ void dft<5>(float2* v) {
   v[3] = csub(p2, q2);
 }
 
-// One Stockham stage of radix R over `lines` lines of length L held in LDS (src -> dst).
-// Ns = product of the radices of the previous stages; tw[m] = exp(-2 pi i m / L).
+// One Stockham stage of radix R over 2^lgB lines of length L held in LDS (src -> dst, line
+// pitch LS). Ns = product of the radices of the previous stages; tw[m] = exp(-2 pi i m / L).
+// Tasks are mapped line-fastest so that line and butterfly index come from shifts; j / Ns is
+// a multiply-high by ceil(2^32 / Ns), exact for j, Ns < 2^16.
 template <int R>
 __device__ __forceinline__ void stage(const float2* __restrict__ src, float2* __restrict__ dst,
-                                      int L, int lines, int Ns, const float2* __restrict__ tw) {
+                                      int L, int LS, int lgB, int Ns, const float2* __restrict__ tw) {
   const int per = L / R;
-  const int tasks = lines * per;
+  const int tasks = per << lgB;
   const int tstep = L / (Ns * R);
+  const unsigned mNs = Ns > 1 ? 0xffffffffu / (unsigned)Ns + 1u : 0u;
+  const int B1 = (1 << lgB) - 1;
   for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
-    const int line = t / per;
-    const int j = t - line * per;
-    const int k = j % Ns;
-    const float2* in = src + line * L;
+    const int line = t & B1;
+    const int j = t >> lgB;
+    const int q = Ns > 1 ? (int)__umulhi((unsigned)j, mNs) : j;
+    const int k = j - q * Ns;
+    const float2* in = src + line * LS;
     float2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -100,23 +105,25 @@ __device__ __forceinline__ void stage(const float2* __restrict__ src, float2* __
       if (r > 0) v[r] = cmul(v[r], tw[r * k * tstep]);  // r k tstep < L
     }
     dft<R>(v);
-    float2* out = dst + line * L + (j / Ns) * Ns * R + k;
+    float2* out = dst + line * LS + q * Ns * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) out[r * Ns] = v[r];
   }
 }
 
 // Runs every stage of the plan; returns the LDS buffer holding the result.
-__device__ float2* run_plan(float2* a, float2* b, int L, int lines, const FftAxis& ax) {
+__device__ float2* run_plan(float2* a, float2* b, int LS, int lgB, const FftAxis& ax,
+                            const float2* tw) {
+  const int L = ax.n;
   int Ns = 1;
   for (int s = 0; s < ax.nstage; ++s) {
     const int R = ax.radix[s];
     __syncthreads();
     switch (R) {
-      case 2: stage<2>(a, b, L, lines, Ns, ax.tw); break;
-      case 3: stage<3>(a, b, L, lines, Ns, ax.tw); break;
-      case 4: stage<4>(a, b, L, lines, Ns, ax.tw); break;
-      default: stage<5>(a, b, L, lines, Ns, ax.tw); break;
+      case 2: stage<2>(a, b, L, LS, lgB, Ns, tw); break;
+      case 3: stage<3>(a, b, L, LS, lgB, Ns, tw); break;
+      case 4: stage<4>(a, b, L, LS, lgB, Ns, tw); break;
+      default: stage<5>(a, b, L, LS, lgB, Ns, tw); break;
     }
     Ns *= R;
     float2* t = a;
@@ -127,6 +134,19 @@ __device__ float2* run_plan(float2* a, float2* b, int L, int lines, const FftAxi
   return a;
 }
 
+// LDS carve-up shared by the pass kernels: two line buffers of 2^lgB lines at pitch LS (odd,
+// so 64-bit accesses of consecutive lines fall in distinct banks) and the twiddle table.
+__device__ __forceinline__ int line_pitch(int L) { return L | 1; }
+
+__device__ __forceinline__ float2* load_twiddles(float2* sm, int lgB, int LS, const FftAxis& ax) {
+  float2* tw = sm + (2 << lgB) * LS;
+  for (int i = threadIdx.x; i < ax.n; i += blockDim.x) tw[i] = ax.tw[i];
+  return tw;
+}
+
+// e / L for e < 2^16 by multiply-high with ceil(2^32 / L).
+__device__ __forceinline__ int div_by(int e, unsigned m) { return (int)__umulhi((unsigned)e, m); }
+
 __device__ __forceinline__ bool arg_better(float v, long long i, float bv, long long bi) {
   return v > bv || (v == bv && i < bi);
 }
@@ -136,70 +156,83 @@ __device__ __forceinline__ bool arg_better(float v, long long i, float bv, long 
 // Forward x pass of the real volume q: line (y, z) for y < ny, z < nz, zero beyond nx.
 // out[(z * Ny + y) * Nx + i], i < Nx.
 __global__ __launch_bounds__(256) void k_fft_x_real(const float* __restrict__ q, int nx, int ny,
-                                                    int nz, FftAxis ax, int Ny, int B,
+                                                    int nz, FftAxis ax, int Ny, int lgB,
                                                     float2* __restrict__ out) {
   extern __shared__ float2 sm[];
-  const int L = ax.n;
+  const int L = ax.n, LS = line_pitch(L), B = 1 << lgB;
+  const unsigned mL = 0xffffffffu / (unsigned)L + 1u;
   float2* a = sm;
-  float2* b = sm + B * L;
+  float2* b = sm + B * LS;
+  const float2* tw = load_twiddles(sm, lgB, LS, ax);
   const int y0 = blockIdx.x * B, z = blockIdx.y;
   const int lines = min(B, ny - y0);
   for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
-    const int l = e / L, i = e - l * L;
+    const int l = div_by(e, mL), i = e - l * L;
     float v = 0.f;
     if (l < lines && i < nx) v = q[((size_t)z * ny + y0 + l) * nx + i];
-    a[e] = make_float2(v, 0.f);
+    a[l * LS + i] = make_float2(v, 0.f);
   }
-  float2* r = run_plan(a, b, L, B, ax);
+  float2* r = run_plan(a, b, LS, lgB, ax, tw);
   for (int e = threadIdx.x; e < lines * L; e += blockDim.x) {
-    const int l = e / L, i = e - l * L;
-    out[((size_t)z * Ny + y0 + l) * L + i] = r[e];
+    const int l = div_by(e, mL), i = e - l * L;
+    out[((size_t)z * Ny + y0 + l) * L + i] = r[l * LS + i];
   }
 }
 
 // Forward x pass of a complex array, every line of an Ny x Nz grid.
 __global__ __launch_bounds__(256) void k_fft_x_c2c(float2* __restrict__ data, FftAxis ax, int Ny,
-                                                   int B) {
+                                                   int lgB) {
   extern __shared__ float2 sm[];
-  const int L = ax.n;
+  const int L = ax.n, LS = line_pitch(L), B = 1 << lgB;
+  const unsigned mL = 0xffffffffu / (unsigned)L + 1u;
   float2* a = sm;
-  float2* b = sm + B * L;
+  float2* b = sm + B * LS;
+  const float2* tw = load_twiddles(sm, lgB, LS, ax);
   const int y0 = blockIdx.x * B, z = blockIdx.y;
   const int lines = min(B, Ny - y0);
   float2* base = data + ((size_t)z * Ny + y0) * L;
-  for (int e = threadIdx.x; e < B * L; e += blockDim.x)
-    a[e] = e < lines * L ? base[e] : make_float2(0.f, 0.f);
-  float2* r = run_plan(a, b, L, B, ax);
-  for (int e = threadIdx.x; e < lines * L; e += blockDim.x) base[e] = r[e];
+  for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
+    const int l = div_by(e, mL), i = e - l * L;
+    a[l * LS + i] = e < lines * L ? base[e] : make_float2(0.f, 0.f);
+  }
+  float2* r = run_plan(a, b, LS, lgB, ax, tw);
+  for (int e = threadIdx.x; e < lines * L; e += blockDim.x) {
+    const int l = div_by(e, mL), i = e - l * L;
+    base[e] = r[l * LS + i];
+  }
 }
 
 // Last inverse pass: line (y < ny, z < nz) of work, forward FFT, conjugated output; real part
 // is eta_a, imaginary part eta_b (times scale). Writes eta (optional) and the block maxima.
 __global__ __launch_bounds__(256) void k_fft_x_argmax(
-    const float2* __restrict__ work, int nx, int ny, int nz, FftAxis ax, int Ny, int B,
+    const float2* __restrict__ work, int nx, int ny, int nz, FftAxis ax, int Ny, int lgB,
     float scale, int slice_a, int slice_b, float* __restrict__ eta_out, ArgPart* __restrict__ apart,
     int nblk) {
   extern __shared__ float2 sm[];
   __shared__ float rv[2][4];
   __shared__ long long ri[2][4];
-  const int L = ax.n;
+  const int L = ax.n, LS = line_pitch(L), B = 1 << lgB;
+  const unsigned mL = 0xffffffffu / (unsigned)L + 1u;
   float2* a = sm;
-  float2* b = sm + B * L;
+  float2* b = sm + B * LS;
+  const float2* tw = load_twiddles(sm, lgB, LS, ax);
   const int y0 = blockIdx.x * B, z = blockIdx.y;
   const int lines = min(B, ny - y0);
   const float2* base = work + ((size_t)z * Ny + y0) * L;
-  for (int e = threadIdx.x; e < B * L; e += blockDim.x)
-    a[e] = e < lines * L ? base[e] : make_float2(0.f, 0.f);
-  float2* r = run_plan(a, b, L, B, ax);
+  for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
+    const int l = div_by(e, mL), i = e - l * L;
+    a[l * LS + i] = e < lines * L ? base[e] : make_float2(0.f, 0.f);
+  }
+  float2* r = run_plan(a, b, LS, lgB, ax, tw);
   const long long V = (long long)nx * ny * nz;
   float bv[2] = {-INFINITY, -INFINITY};
   long long bi[2] = {0x7fffffffffffffffLL, 0x7fffffffffffffffLL};
   for (int e = threadIdx.x; e < lines * L; e += blockDim.x) {
-    const int l = e / L, i = e - l * L;
+    const int l = div_by(e, mL), i = e - l * L;
     if (i >= nx) continue;
     const long long v = ((long long)z * ny + y0 + l) * nx + i;
-    const float ea = r[e].x * scale;
-    const float eb = -r[e].y * scale;
+    const float ea = r[l * LS + i].x * scale;
+    const float eb = -r[l * LS + i].y * scale;
     if (eta_out) {
       eta_out[(size_t)slice_a * V + v] = ea;
       if (slice_b >= 0) eta_out[(size_t)slice_b * V + v] = eb;
@@ -262,16 +295,17 @@ __global__ __launch_bounds__(256) void k_fft_strided(const float2* __restrict__ 
                                                      const float2* __restrict__ mulp,
                                                      float2* __restrict__ dst, FftAxis ax,
                                                      int ncols, size_t istride, size_t ostride,
-                                                     int n_in, int n_out, int B, int mode) {
+                                                     int n_in, int n_out, int lgB, int mode) {
   extern __shared__ float2 sm[];
-  const int L = ax.n;
+  const int L = ax.n, LS = line_pitch(L), B = 1 << lgB;
   float2* a = sm;
-  float2* b = sm + B * L;
+  float2* b = sm + B * LS;
+  const float2* tw = load_twiddles(sm, lgB, LS, ax);
   const int x0 = blockIdx.x * B;
   const size_t obase = (size_t)blockIdx.y * ostride;
   const int cols = min(B, ncols - x0);
   for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
-    const int i = e / B, c = e - i * B;  // consecutive threads: consecutive columns
+    const int i = e >> lgB, c = e & (B - 1);  // consecutive threads: consecutive columns
     float2 v = make_float2(0.f, 0.f);
     if (c < cols && i < n_in) {
       const size_t g = obase + (size_t)i * istride + x0 + c;
@@ -281,12 +315,12 @@ __global__ __launch_bounds__(256) void k_fft_strided(const float2* __restrict__ 
         v.y = -v.y;
       }
     }
-    a[c * L + i] = v;
+    a[c * LS + i] = v;
   }
-  float2* r = run_plan(a, b, L, B, ax);
+  float2* r = run_plan(a, b, LS, lgB, ax, tw);
   for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
-    const int i = e / B, c = e - i * B;
-    if (c < cols && i < n_out) dst[obase + (size_t)i * istride + x0 + c] = r[c * L + i];
+    const int i = e >> lgB, c = e & (B - 1);
+    if (c < cols && i < n_out) dst[obase + (size_t)i * istride + x0 + c] = r[c * LS + i];
   }
 }
 
@@ -346,11 +380,14 @@ static bool make_axis_plan(int n, FftAxis& ax) {
   return t == 1;
 }
 
-int fft_lines_per_block(int L, bool strided) {
-  int B = strided ? 16 : 8;
-  while (B > 1 && (size_t)2 * B * L * sizeof(float2) > 48 * 1024) B /= 2;
-  return B;
+// log2 of the lines per block and the dynamic LDS bytes of a pass over lines of length L.
+static int fft_lg_lines(int L, bool strided) {
+  int lg = strided ? 4 : 3;
+  while (lg > 0 && ((size_t)2 * ((size_t)1 << lg) * (L | 1) + L) * sizeof(float2) > 48 * 1024)
+    --lg;
+  return lg;
 }
+static size_t fft_lds(int L, int lg) { return ((size_t)2 * ((size_t)1 << lg) * (L | 1) + L) * sizeof(float2); }
 
 // Grid sizes: N >= n + R keeps wrapped reads of q off the volume, N >= 2R + 1 keeps the
 // wrapped table kernel from overlapping itself; both make the circular correlation equal the
@@ -374,21 +411,21 @@ void fft_twiddles(int n, std::vector<float2>& tw) {
 
 // Forward 3D transform of a complex array on the full grid (used for the table spectra).
 hipError_t fft_forward_c2c(const FftPlan& pl, float2* data, hipStream_t st) {
-  const int Bx = fft_lines_per_block(pl.nx, false);
+  const int gx = fft_lg_lines(pl.nx, false), Bx = 1 << gx;
   hipLaunchKernelGGL(k_fft_x_c2c, dim3((pl.ny + Bx - 1) / Bx, pl.nz), dim3(256),
-                     2 * Bx * pl.nx * sizeof(float2), st, data, pl.ax[0], pl.ny, Bx);
+                     fft_lds(pl.nx, gx), st, data, pl.ax[0], pl.ny, gx);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int By = fft_lines_per_block(pl.ny, true);
+  const int gy = fft_lg_lines(pl.ny, true), By = 1 << gy;
   hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + By - 1) / By, pl.nz), dim3(256),
-                     2 * By * pl.ny * sizeof(float2), st, data, nullptr, data, pl.ax[1], pl.nx,
-                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, pl.ny, pl.ny, By, 0);
+                     fft_lds(pl.ny, gy), st, data, nullptr, data, pl.ax[1], pl.nx,
+                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, pl.ny, pl.ny, gy, 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int Bz = fft_lines_per_block(pl.nz, true);
+  const int gz = fft_lg_lines(pl.nz, true), Bz = 1 << gz;
   hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(256),
-                     2 * Bz * pl.nz * sizeof(float2), st, data, nullptr, data, pl.ax[2], pl.nx,
-                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, pl.nz, pl.nz, Bz, 0);
+                     fft_lds(pl.nz, gz), st, data, nullptr, data, pl.ax[2], pl.nx,
+                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, pl.nz, pl.nz, gz, 0);
   return hipGetLastError();
 }
 
@@ -403,27 +440,27 @@ hipError_t fft_scatter_pair(const FftPlan& pl, const float* ka, int ra, int kzpa
 // Qhat = FFT(q) with q zero-padded from the volume to the grid.
 hipError_t fft_forward_volume(const FftPlan& pl, const float* q, sfw_dims vol, float2* qhat,
                               hipStream_t st) {
-  const int Bx = fft_lines_per_block(pl.nx, false);
+  const int gx = fft_lg_lines(pl.nx, false), Bx = 1 << gx;
   hipLaunchKernelGGL(k_fft_x_real, dim3((vol.ny + Bx - 1) / Bx, vol.nz), dim3(256),
-                     2 * Bx * pl.nx * sizeof(float2), st, q, vol.nx, vol.ny, vol.nz, pl.ax[0],
-                     pl.ny, Bx, qhat);
+                     fft_lds(pl.nx, gx), st, q, vol.nx, vol.ny, vol.nz, pl.ax[0], pl.ny, gx,
+                     qhat);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int By = fft_lines_per_block(pl.ny, true);
+  const int gy = fft_lg_lines(pl.ny, true), By = 1 << gy;
   hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + By - 1) / By, vol.nz), dim3(256),
-                     2 * By * pl.ny * sizeof(float2), st, qhat, nullptr, qhat, pl.ax[1], pl.nx,
-                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, vol.ny, pl.ny, By, 0);
+                     fft_lds(pl.ny, gy), st, qhat, nullptr, qhat, pl.ax[1], pl.nx,
+                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, vol.ny, pl.ny, gy, 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int Bz = fft_lines_per_block(pl.nz, true);
+  const int gz = fft_lg_lines(pl.nz, true), Bz = 1 << gz;
   hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(256),
-                     2 * Bz * pl.nz * sizeof(float2), st, qhat, nullptr, qhat, pl.ax[2], pl.nx,
-                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, vol.nz, pl.nz, Bz, 0);
+                     fft_lds(pl.nz, gz), st, qhat, nullptr, qhat, pl.ax[2], pl.nx,
+                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, vol.nz, pl.nz, gz, 0);
   return hipGetLastError();
 }
 
 int fft_argmax_blocks(const FftPlan& pl, sfw_dims vol) {
-  const int Bx = fft_lines_per_block(pl.nx, false);
+  const int Bx = 1 << fft_lg_lines(pl.nx, false);
   return ((vol.ny + Bx - 1) / Bx) * vol.nz;
 }
 
@@ -431,22 +468,22 @@ int fft_argmax_blocks(const FftPlan& pl, sfw_dims vol) {
 hipError_t fft_inverse_pair(const FftPlan& pl, const float2* qhat, const float2* pair,
                             float2* work, sfw_dims vol, float scale, int slice_a, int slice_b,
                             float* eta_out, ArgPart* apart, int nblk, hipStream_t st) {
-  const int Bz = fft_lines_per_block(pl.nz, true);
+  const int gz = fft_lg_lines(pl.nz, true), Bz = 1 << gz;
   hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(256),
-                     2 * Bz * pl.nz * sizeof(float2), st, qhat, pair, work, pl.ax[2], pl.nx,
-                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, pl.nz, vol.nz, Bz, 1);
+                     fft_lds(pl.nz, gz), st, qhat, pair, work, pl.ax[2], pl.nx,
+                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, pl.nz, vol.nz, gz, 1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int By = fft_lines_per_block(pl.ny, true);
+  const int gy = fft_lg_lines(pl.ny, true), By = 1 << gy;
   hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + By - 1) / By, vol.nz), dim3(256),
-                     2 * By * pl.ny * sizeof(float2), st, work, nullptr, work, pl.ax[1], pl.nx,
-                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, pl.ny, vol.ny, By, 0);
+                     fft_lds(pl.ny, gy), st, work, nullptr, work, pl.ax[1], pl.nx,
+                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, pl.ny, vol.ny, gy, 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int Bx = fft_lines_per_block(pl.nx, false);
+  const int gx = fft_lg_lines(pl.nx, false), Bx = 1 << gx;
   hipLaunchKernelGGL(k_fft_x_argmax, dim3((vol.ny + Bx - 1) / Bx, vol.nz), dim3(256),
-                     2 * Bx * pl.nx * sizeof(float2), st, work, vol.nx, vol.ny, vol.nz, pl.ax[0],
-                     pl.ny, Bx, scale, slice_a, slice_b, eta_out, apart, nblk);
+                     fft_lds(pl.nx, gx), st, work, vol.nx, vol.ny, vol.nz, pl.ax[0], pl.ny, gx,
+                     scale, slice_a, slice_b, eta_out, apart, nblk);
   return hipGetLastError();
 }
 

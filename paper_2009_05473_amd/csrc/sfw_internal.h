@@ -162,9 +162,13 @@ struct sfw_workspace {
   std::vector<double> lasso_G, lasso_b;  // [max_atoms][max_atoms], [max_atoms]
   unsigned long long* hashbuf = nullptr;  // [2] device
 
-  // pinned host staging
+  // pinned host staging (doubles), carved into regions that never overlap:
+  //   [hp_hash, +2) fingerprints | [hp_atoms, +3 na) atom readback / upload (sfw_atom)
+  //   [hp_stage, +4 na) atom constants (AtomK) | [hp_sums, +6 na + 8) reduction sums
+  //   [hp_w, +na) LASSO weights on their way to the device | [hp_rows, ...) Gram rows
   double* hpin = nullptr;
-  size_t hpin_cap = 0;  // doubles
+  size_t hpin_cap = 0;
+  size_t hp_hash = 0, hp_atoms = 0, hp_stage = 0, hp_sums = 0, hp_w = 0, hp_rows = 0;
 
   // optional per-kernel-class event timing (sfw_profile_begin / end)
   bool prof_on = false;

@@ -347,124 +347,124 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // out[z][y][x] = sum_{kz,ky,kx} W[kz][ky][kx] in[z + cz - kz][y + cy - ky][x + cx - kx] on the
 // matrix cores (pz <= 16, px * py <= 4 * STEPS; amat holds STEPS steps, zero past the taps).
-// A block owns 16 consecutive x of 4 rows y (one wave per row) and streams the input planes
-// zi = 0 .. nz-1. For each plane the in-plane taps form the K dimension of a chain of
+// A block owns 16 consecutive x of 4 rows y and streams the input planes zi = 0 .. nz-1.
+// For each plane the in-plane taps form the K dimension of a chain of
 // v_mfma_f32_16x16x4_f32 with A = W[kz][tap] (registers), B[tap][n] =
 // in[zi][y + cy - ky][x0 + n + cx - kx] and accumulator rows indexed by kz: row j holds the
-// partial sum of output plane zi - cz + j. After a plane row 0 is complete and is stored,
-// and the rows roll up by one. The block stages each plane's (16 + px - 1) x (4 + py - 1)
-// input patch (zero outside the volume) in a ring of LDS buffers, with the global loads
-// issued three planes ahead.
+// partial sum of output plane zi - cz + j. After a plane row 0 is complete, and the rows
+// roll up by one. Each row is served by two waves (8 waves per block, two per SIMD) that
+// split the taps, so one wave's per-plane latencies overlap the other's MFMAs; the second
+// wave hands its row 0 to the first through LDS, which stores the sum one plane later. The
+// block stages each plane's (16 + px - 1) x (4 + py - 1) input patch (zero outside the
+// volume) in a ring of LDS buffers, with the global loads issued three planes ahead.
 // Accumulator layout (16x16x4 f32): lane l holds rows 4 (l / 16) + 0..3 of column l % 16.
 template <int STEPS, int EPI>
-__global__ __launch_bounds__(256) void k_conv_mfma(
+__global__ __launch_bounds__(512) void k_conv_mfma(
     const float* __restrict__ in, const float* __restrict__ amat, int px, int py, int pz,
     int nx, int ny, int nz, float* __restrict__ out, const float* __restrict__ yobs,
     double* __restrict__ dpart) {
   constexpr int NBUF = 4;
   constexpr int PLANE = kMfmaPatchMax;
+  constexpr int SH = (STEPS + 1) / 2;  // taps of the first half (the second gets the rest)
   __shared__ float patch[NBUF][PLANE];
+  __shared__ float xch[2][4][16];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int rowi = wave & 3, half = wave >> 2;
   const int n = lane & 15, g = lane >> 4;
   const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4;
-  const int y = y0 + wave, x = x0 + n;
+  const int y = y0 + rowi, x = x0 + n;
   const int cx = (px - 1) / 2, cy = (py - 1) / 2, cz = (pz - 1) / 2;
   const size_t nxy = (size_t)nx * ny;
   const int PW = 16 + px - 1, PH = 4 + py - 1, PN = PW * PH;
 
-  // staging: thread owns patch elements tid and tid + 256 (in-plane offset, -1 = zero)
-  int goff[2];
-  bool lown[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int e = tid + 256 * j;
-    lown[j] = e < PN;
-    goff[j] = -1;
-    if (lown[j]) {
-      const int row = e / PW, col = e - (e / PW) * PW;
-      const int iy = y0 + cy - (py - 1) + row, ix = x0 + cx - (px - 1) + col;
-      if (iy >= 0 && iy < ny && ix >= 0 && ix < nx) goff[j] = iy * nx + ix;
-    }
+  // staging: thread owns patch element tid (in-plane offset, -1 = zero)
+  const bool lown = tid < PN;
+  int goff = -1;
+  if (lown) {
+    const int row = tid / PW, col = tid - (tid / PW) * PW;
+    const int iy = y0 + cy - (py - 1) + row, ix = x0 + cx - (px - 1) + col;
+    if (iy >= 0 && iy < ny && ix >= 0 && ix < nx) goff = iy * nx + ix;
   }
-  auto fetch = [&](int plane, int j) -> float {
-    const bool ok = plane < nz && goff[j] >= 0;
-    const float t = in[(size_t)min(plane, nz - 1) * nxy + max(goff[j], 0)];
+  auto fetch = [&](int plane) -> float {
+    const bool ok = plane < nz && goff >= 0;
+    const float t = in[(size_t)min(plane, nz - 1) * nxy + max(goff, 0)];
     return ok ? t : 0.f;
   };
-  // B operand addresses inside a plane buffer
-  float a[STEPS];
-  int boff[STEPS];
+  // this wave's taps: steps [s0, s0 + SH) of the plan (past STEPS: zero weights)
+  const int s0 = half * SH;
+  float a[SH];
+  int boff[SH];
 #pragma unroll
-  for (int s = 0; s < STEPS; ++s) {
-    a[s] = amat[s * 64 + lane];
-    const int k = 4 * s + g;
+  for (int s = 0; s < SH; ++s) {
+    const int st = s0 + s;
+    a[s] = st < STEPS ? amat[st * 64 + lane] : 0.f;
+    const int k = 4 * st + g;
     int o = 0;
-    if (k < px * py) {
+    if (st < STEPS && k < px * py) {
       const int ky = k / px, kx = k - ky * px;
-      o = (wave + py - 1 - ky) * PW + n + px - 1 - kx;
+      o = (rowi + py - 1 - ky) * PW + n + px - 1 - kx;
     }
     boff[s] = o;
   }
   // prologue: planes 0 and 1 in LDS, plane 2 in flight
-#pragma unroll
-  for (int j = 0; j < 2; ++j)
-    if (lown[j]) {
-      patch[0][tid + 256 * j] = fetch(0, j);
-      patch[1][tid + 256 * j] = fetch(1, j);
-    }
-  float st1[2] = {fetch(2, 0), fetch(2, 1)};
-  const bool out_lane = g == 0 && x < nx && y < ny;
+  if (lown) {
+    patch[0][tid] = fetch(0);
+    patch[1][tid] = fetch(1);
+  }
+  float st1 = fetch(2);
+  const bool out_lane = half == 0 && g == 0 && x < nx && y < ny;
   const size_t col = (size_t)min(y, ny - 1) * nx + min(x, nx - 1);
   float ynext = 0.f;
-  if (EPI == kEpiResidual) ynext = yobs[col];  // plane 0, used when zo = 0
+  if (EPI == kEpiResidual) ynext = yobs[col];  // plane 0
   __syncthreads();
 
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  float ssf = 0.f;
-  for (int zi = 0; zi < nz + cz; ++zi) {
-    const float st0[2] = {fetch(zi + 3, 0), fetch(zi + 3, 1)};
-    const int zo = zi - cz;
-    float ycur = 0.f;
-    if (EPI == kEpiResidual && zo >= 0) {
-      ycur = ynext;
-      ynext = yobs[(size_t)min(zo + 1, nz - 1) * nxy + col];
+  float ssf = 0.f, prev = 0.f;
+  for (int zi = 0; zi <= nz + cz; ++zi) {
+    const float st0 = fetch(zi + 3);
+    // the first half stores output plane zi - 1 - cz: its own row 0 of the previous plane
+    // plus the second half's, exchanged through LDS before the last barrier
+    const int zo = zi - 1 - cz;
+    if (half == 0 && zo >= 0) {
+      const float row = prev + xch[(zi - 1) & 1][rowi][n];
+      if (out_lane) {
+        const size_t v = (size_t)zo * nxy + col;
+        if (EPI == kEpiPlain) {
+          out[v] = row;
+        } else {
+          const float rv = ynext - row;
+          out[v] = rv;
+          ssf = fmaf(rv, rv, ssf);
+        }
+      }
+      if (EPI == kEpiResidual) ynext = yobs[(size_t)min(zo + 1, nz - 1) * nxy + col];
     }
     if (zi < nz) {
       const float* buf = patch[zi & (NBUF - 1)];
-      float b[STEPS];
+      float b[SH];
 #pragma unroll
-      for (int s = 0; s < STEPS; ++s) b[s] = buf[boff[s]];
+      for (int s = 0; s < SH; ++s) b[s] = buf[boff[s]];
 #pragma unroll
-      for (int s = 0; s < STEPS; ++s)
+      for (int s = 0; s < SH; ++s)
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
     }
-    if (zo >= 0 && out_lane) {
-      const size_t v = (size_t)zo * nxy + col;
-      if (EPI == kEpiPlain) {
-        out[v] = acc[0];
-      } else {
-        const float rv = ycur - acc[0];
-        out[v] = rv;
-        ssf = fmaf(rv, rv, ssf);
-      }
-    }
+    const float r0 = acc[0];
+    if (half == 1 && g == 0) xch[zi & 1][rowi][n] = r0;
+    prev = r0;
     const float up = __shfl_down(acc[0], 16, 64);
     acc[0] = acc[1];
     acc[1] = acc[2];
     acc[2] = acc[3];
     acc[3] = g < 3 ? up : 0.f;
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (lown[j]) patch[(zi + 2) & (NBUF - 1)][tid + 256 * j] = st1[j];
-    st1[0] = st0[0];
-    st1[1] = st0[1];
+    if (lown) patch[(zi + 2) & (NBUF - 1)][tid] = st1;
+    st1 = st0;
     __syncthreads();
   }
-  if (EPI == kEpiResidual) {
+  if (EPI == kEpiResidual && half == 0) {
     double ss = shfl_sum_d((double)ssf);
-    if (lane == 0) dpart[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + wave] = ss;
+    if (lane == 0) dpart[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + rowi] = ss;
   }
 }
 
@@ -611,18 +611,30 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
 
 // ------------------------------------------------------------------ certificate maximum
 
-__global__ __launch_bounds__(256) void k_argmax_final(const ArgPart* __restrict__ apart,
-                                                      int nparts, int nx, int ny, int nz, int nd,
-                                                      sfw_argmax* __restrict__ best) {
+__global__ __launch_bounds__(1024) void k_argmax_final(const ArgPart* __restrict__ apart,
+                                                       int nparts, int nx, int ny, int nz, int nd,
+                                                       sfw_argmax* __restrict__ best) {
   const int tid = threadIdx.x;
   float bv = -INFINITY;
   long long bi = 0x7fffffffffffffffLL;
-  for (int i = tid; i < nparts; i += 256) {
-    const ArgPart ap = apart[i];
-    if (arg_better(ap.val, ap.idx, bv, bi)) {
-      bv = ap.val;
-      bi = ap.idx;
+  for (int i0 = tid; i0 < nparts; i0 += 4 * 1024) {
+    ArgPart ap[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * 1024;
+      if (i < nparts) {
+        ap[u] = apart[i];
+      } else {
+        ap[u].val = -INFINITY;
+        ap[u].idx = 0x7fffffffffffffffLL;
+      }
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (arg_better(ap[u].val, ap[u].idx, bv, bi)) {
+        bv = ap[u].val;
+        bi = ap[u].idx;
+      }
   }
   for (int o = 32; o > 0; o >>= 1) {
     const float ov = __shfl_xor(bv, o, 64);
@@ -632,15 +644,15 @@ __global__ __launch_bounds__(256) void k_argmax_final(const ArgPart* __restrict_
       bi = oi;
     }
   }
-  __shared__ float rv[4];
-  __shared__ long long ri[4];
+  __shared__ float rv[16];
+  __shared__ long long ri[16];
   if ((tid & 63) == 0) {
     rv[tid / 64] = bv;
     ri[tid / 64] = bi;
   }
   __syncthreads();
   if (tid == 0) {
-    for (int i = 1; i < 4; ++i)
+    for (int i = 1; i < 16; ++i)
       if (arg_better(rv[i], ri[i], bv, bi)) {
         bv = rv[i];
         bi = ri[i];
@@ -663,34 +675,77 @@ __global__ __launch_bounds__(256) void k_argmax_final(const ArgPart* __restrict_
 // ------------------------------------------------------------------ LASSO dot products
 
 // dpart[block][c] = partial sum over the block's voxels of a * cols[c] (c < k), a * y (c = k):
-// each thread owns 4 consecutive voxels per grid stride (128-bit loads), float32 products,
-// float64 accumulation, fixed-order block reduction.
+// each thread owns 4 consecutive voxels per grid stride (128-bit loads; its part of a stays
+// in registers across the columns when it owns at most kDotsHold groups), float32 products,
+// float64 accumulation, fixed-order block reduction; columns go four at a time so that four
+// independent loads are in flight per thread.
+constexpr int kDotsHold = 4;
+constexpr int kDotsCols = 4;
+
+__device__ __forceinline__ double dot4(const float4& a, const float4& b) {
+  return (double)(a.x * b.x) + (double)(a.y * b.y) + (double)(a.z * b.z) + (double)(a.w * b.w);
+}
+
 __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
                                               const float* __restrict__ cols, int k,
                                               size_t colstride, const float* __restrict__ y,
                                               size_t nvox, double* __restrict__ dpart) {
-  __shared__ double red[4];
+  __shared__ double red[kDotsCols][4];
   const int tid = threadIdx.x;
   const size_t stride = (size_t)gridDim.x * 256 * 4;
   const size_t v0 = ((size_t)blockIdx.x * 256 + tid) * 4;
-  for (int c = 0; c <= k; ++c) {
-    const float* b = c < k ? cols + (size_t)c * colstride : y;
-    const bool vec = nvox % 4 == 0 && (((uintptr_t)a | (uintptr_t)b) & 15) == 0;
-    double s = 0.0;
-    for (size_t v = v0; v < nvox; v += stride) {
-      if (vec) {
-        const float4 av = *reinterpret_cast<const float4*>(a + v);
-        const float4 bv = *reinterpret_cast<const float4*>(b + v);
-        s += (double)(av.x * bv.x) + (double)(av.y * bv.y) + (double)(av.z * bv.z) +
-             (double)(av.w * bv.w);
-      } else {
-        for (size_t u = v; u < v + 4 && u < nvox; ++u) s += (double)(a[u] * b[u]);
-      }
+  const bool avec = nvox % 4 == 0 && ((uintptr_t)a & 15) == 0;
+  const bool hold = avec && nvox <= stride * kDotsHold;
+  float4 ah[kDotsHold];
+#pragma unroll
+  for (int h = 0; h < kDotsHold; ++h) {
+    const size_t v = v0 + (size_t)h * stride;
+    ah[h] = (hold && v < nvox) ? *reinterpret_cast<const float4*>(a + v) : make_float4(0, 0, 0, 0);
+  }
+  for (int c0 = 0; c0 <= k; c0 += kDotsCols) {
+    const int nc = min(kDotsCols, k + 1 - c0);
+    const float* b[kDotsCols];
+    bool vec = avec;
+#pragma unroll
+    for (int u = 0; u < kDotsCols; ++u) {
+      const int c = min(c0 + u, k);
+      b[u] = c < k ? cols + (size_t)c * colstride : y;
+      vec = vec && (((uintptr_t)b[u]) & 15) == 0;
     }
-    s = shfl_sum_d(s);
-    if ((tid & 63) == 0) red[tid / 64] = s;
+    double s[kDotsCols] = {0.0, 0.0, 0.0, 0.0};
+    if (hold && vec) {
+#pragma unroll
+      for (int h = 0; h < kDotsHold; ++h) {
+        const size_t v = v0 + (size_t)h * stride;
+        if (v < nvox) {
+          float4 bv[kDotsCols];
+#pragma unroll
+          for (int u = 0; u < kDotsCols; ++u) bv[u] = *reinterpret_cast<const float4*>(b[u] + v);
+#pragma unroll
+          for (int u = 0; u < kDotsCols; ++u) s[u] += dot4(ah[h], bv[u]);
+        }
+      }
+    } else {
+      for (size_t v = v0; v < nvox; v += stride)
+#pragma unroll
+        for (int u = 0; u < kDotsCols; ++u) {
+          if (vec) {
+            s[u] += dot4(*reinterpret_cast<const float4*>(a + v),
+                         *reinterpret_cast<const float4*>(b[u] + v));
+          } else {
+            for (size_t w = v; w < v + 4 && w < nvox; ++w) s[u] += (double)(a[w] * b[u][w]);
+          }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kDotsCols; ++u) {
+      const double t = shfl_sum_d(s[u]);
+      if ((tid & 63) == 0) red[u][tid / 64] = t;
+    }
     __syncthreads();
-    if (tid == 0) dpart[(size_t)blockIdx.x * (k + 1) + c] = red[0] + red[1] + red[2] + red[3];
+    if (tid < nc)
+      dpart[(size_t)blockIdx.x * (k + 1) + c0 + tid] =
+          red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
     __syncthreads();
   }
 }
@@ -851,7 +906,7 @@ template <int STEPS, int EPI>
 static hipError_t mfma_t(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
                          float* out, const float* yobs, double* dpart, hipStream_t st) {
   dim3 grid((vol.nx + 15) / 16, (vol.ny + 3) / 4);
-  hipLaunchKernelGGL((k_conv_mfma<STEPS, EPI>), grid, dim3(256), 0, st, in, amat, psf.nx, psf.ny,
+  hipLaunchKernelGGL((k_conv_mfma<STEPS, EPI>), grid, dim3(512), 0, st, in, amat, psf.nx, psf.ny,
                      psf.nz, vol.nx, vol.ny, vol.nz, out, yobs, dpart);
   return hipGetLastError();
 }
@@ -907,7 +962,7 @@ hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const dou
 
 hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
                                sfw_argmax* best, hipStream_t st) {
-  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(256), 0, st, apart, nparts, vol.nx, vol.ny,
+  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, st, apart, nparts, vol.nx, vol.ny,
                      vol.nz, nd, best);
   return hipGetLastError();
 }

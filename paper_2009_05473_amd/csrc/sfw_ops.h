@@ -29,9 +29,12 @@ int prep_all(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool
 int prep_psf(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool adj);
 // Atom constants (see AtomK) from float64 parameters.
 AtomK make_atomk(double w, double mx, double my, double mz, double sigma, double d);
-// Weights-only LASSO with the workspace's column cache (see sfw_api.cpp).
+// Weights-only LASSO with the workspace's column cache (see sfw_api.cpp); the cache must have
+// been validated for (y, H) by lasso_check_inputs (once per y).
+int lasso_check_inputs(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
+                       const float* H);
 int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
-             const float* H, double lambda, const float* thetas, int n, std::vector<double>& w);
+             double lambda, const float* thetas, int n, std::vector<double>& w);
 // out = H * in (adjoint = false) or correlation with H (adjoint = true); epilogue as launch_conv.
 int conv_psf(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjoint,
              const float* in, float* out, int epi, const float* yobs, int prof_kind);

@@ -327,7 +327,7 @@ struct Solver {
   int upload_atoms(const std::vector<double>& a, bool unit_weight) {
     const int n = (int)(a.size() / 6);
     if (n == 0) return SFW_OK;
-    sfw_atom* h = reinterpret_cast<sfw_atom*>(ws->hpin);
+    sfw_atom* h = reinterpret_cast<sfw_atom*>(ws->hpin + ws->hp_atoms);
     for (int i = 0; i < n; ++i) {
       h[i].w = (float)a[6 * i + 0];
       h[i].mx = (float)a[6 * i + 1];
@@ -352,7 +352,7 @@ struct Solver {
     if (rc) return rc;
     rc = op_cgrad(ws, plan, vol, y, (float)lam, ws->atoms_dev, n, nullptr, nullptr, nullptr);
     if (rc) return rc;
-    double* hs = ws->hpin + 8 * (size_t)ws->max_atoms + 16;
+    double* hs = ws->hpin + ws->hp_sums;
     SFW_HIP(hipMemcpyAsync(hs, ws->dres, sizeof(double) * (6 * n + 2), hipMemcpyDeviceToHost,
                            ws->stream));
     SFW_HIP(hipStreamSynchronize(ws->stream));
@@ -434,7 +434,7 @@ struct Solver {
     for (int i = 0; i < n; ++i)
       for (int c = 0; c < 5; ++c) th[5 * i + c] = (float)atoms[6 * i + 1 + c];
     std::vector<double> w;
-    int rc = op_lasso(ws, plan, vol, y, H, lam, th.data(), n, w);
+    int rc = op_lasso(ws, plan, vol, y, lam, th.data(), n, w);
     if (rc) return rc;
     for (int i = 0; i < n; ++i) atoms[6 * i] = w[i];
     return SFW_OK;
@@ -531,6 +531,9 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
       if (hflag) return fail(SFW_EINVAL, "y or H holds NaN or Inf");
     }
     rc = prep_psf(ws, H, S.plan, true, true);
+    if (rc) return rc;
+    // y is fixed for the whole solve: validate the LASSO column cache against it once
+    rc = lasso_check_inputs(ws, S.plan, vol, y, H);
     if (rc) return rc;
 
     const float T = o.trunc_T > 0 ? o.trunc_T : 12.0f;
