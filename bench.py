@@ -35,10 +35,40 @@ if ROOT not in sys.path:
 PEAK_FP32_TFLOPS = 157.3   # vector and matrix FP32, dense
 PEAK_HBM_GBS = 8000.0
 
+# The dominant kernel: the plain-epilogue MFMA convolution (adjoint Phi^T r and the LASSO
+# columns; one launch of it per step is timed, in the conv_adjoint class).
+ROOF_CLASS = "conv_adjoint"
+ROOF_KERNEL = "k_conv_mfma (plain epilogue)"
+
 # Algorithmic ALU work per voxel-atom pair in FMA-slot units (one VALU instruction = 1 slot,
 # one v_exp/v_log/v_rcp = 4 slots: quarter rate, measured), reported as 2 FLOP per slot.
 RENDER_SLOTS_PER_PAIR = 4 + 3 * 4   # 4 VALU + log2, exp2, exp2
 GRAD_SLOTS_PER_PAIR = 12 + 3 * 4    # 12 VALU + log2, exp2, exp2
+
+
+# HBM traffic of one launch of the roofline kernel at this workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+#   bench.py --steps 2 --warmup 1 --profile-steps 0 --no-cpu-baseline --copy-probe-mib 256
+# each scaled by the same counter's reading for the known 256 MiB device copy at the end.
+# The record holds for the kernel source it was taken on (sha256 of KERNEL_SOURCE).
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_05473_amd", "csrc", "sfw_kernels.hip")
+CONV_TRAFFIC = None
+
+
+def conv_traffic():
+    """Counter-measured HBM bytes per launch of the roofline kernel, or None when the record
+    is missing or the kernel source changed since it was taken."""
+    import hashlib
+    t = CONV_TRAFFIC
+    if t is None:
+        return None
+    with open(KERNEL_SOURCE, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != t["source_sha256"]:
+            return None
+    copy_bytes = float(t["copy_mib"]) * (1 << 20)
+    fetch = t["fetch_kib"] * 1024.0 * copy_bytes / (t["copy_fetch_kib"] * 1024.0)
+    write = t["write_kib"] * 1024.0 * copy_bytes / (t["copy_write_kib"] * 1024.0)
+    return fetch + write
 
 
 def parse():
@@ -46,7 +76,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--profile-steps", type=int, default=5,
+                    help="untimed steps with every kernel class timed, for the breakdown")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB on the device (the "
+                         "known-size copy that scales the HBM counters of a --pmc run)")
     return ap.parse_args()
 
 
@@ -130,7 +165,7 @@ def main():
     # one support per step: the 49 first atoms fixed, the last one new each step
     rng = np.random.default_rng(prob.seed + 900)
     supports = []
-    for _ in range(args.warmup + args.steps):
+    for _ in range(args.warmup + args.profile_steps + args.steps):
         s = atoms_eval.copy()
         s[-1, 1:4] += rng.uniform(-1.0, 1.0, size=3).astype(np.float32)
         supports.append(dev(s))
@@ -149,13 +184,23 @@ def main():
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
-    L.sfw_profile_begin(ws)
+    # untimed: every kernel class behind an event pair, for the per-class breakdown
+    prof = {}
+    if args.profile_steps > 0:
+        L.sfw_profile_begin(ws)
+        for k in range(args.profile_steps):
+            step(args.warmup + k)
+        prof = L.sfw_profile_end(ws)
+    # timed: only the roofline kernel's launches carry events (one pair per step)
+    k0 = args.warmup + args.profile_steps
+    torch.cuda.synchronize()
+    L.sfw_profile_begin(ws, [ROOF_CLASS])
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(args.warmup + k)
+        step(k0 + k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = L.sfw_profile_end(ws)
+    roof_prof = L.sfw_profile_end(ws)
     dt = t1 - t0
     ms_per_step = dt / args.steps * 1e3
     value = V * N * args.steps / dt / 1e9
@@ -163,40 +208,38 @@ def main():
     # algorithmic work per launch of each kernel class
     px, py, pz = psf.shape[2], psf.shape[1], psf.shape[0]
     taps = px * py * pz
-    cert_taps = lut_taps(sg, dg)
+    conv_flops = 2.0 * V * taps
     work = {
-        "render": ("alu", 2.0 * V * N * RENDER_SLOTS_PER_PAIR, "TFLOP/s"),
-        "grad": ("alu", 2.0 * V * N * GRAD_SLOTS_PER_PAIR, "TFLOP/s"),
-        "conv_residual": ("mfma", 2.0 * V * taps, "TFLOP/s"),
-        "conv_adjoint": ("mfma", 2.0 * V * taps, "TFLOP/s"),
-        "lasso_conv": ("mfma", 2.0 * V * taps, "TFLOP/s"),
-        "cert_conv": ("alu", 2.0 * V * cert_taps / (len(sg) * len(dg)), "TFLOP/s"),
+        "render": ("alu", 2.0 * V * N * RENDER_SLOTS_PER_PAIR, PEAK_FP32_TFLOPS),
+        "grad": ("alu", 2.0 * V * N * GRAD_SLOTS_PER_PAIR, PEAK_FP32_TFLOPS),
+        "conv_residual": ("mfma", conv_flops, PEAK_FP32_TFLOPS),
+        "conv_adjoint": ("mfma", conv_flops, PEAK_FP32_TFLOPS),
+        "lasso_conv": ("mfma", conv_flops, PEAK_FP32_TFLOPS),
     }
+    ps = max(args.profile_steps, 1)
     breakdown = {}
     for name, (launches, ms) in prof.items():
-        e = {"launches": launches, "ms_per_step": ms / args.steps,
+        e = {"launches_per_step": launches / ps, "ms_per_step": ms / ps,
              "us_per_launch": ms / launches * 1e3}
         if name in work:
-            bound, flops, unit = work[name]
+            bound, flops, peak = work[name]
             achieved = flops / (ms / launches * 1e-3) / 1e12
-            e.update({"bound": bound, "achieved_tflops": achieved,
-                      "frac": achieved / PEAK_FP32_TFLOPS})
+            e.update({"bound": bound, "achieved_tflops": achieved, "frac": achieved / peak})
         breakdown[name] = e
-    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
-    if dom in work:
-        bound, flops, unit = work[dom]
-        avg_s = prof[dom][1] / prof[dom][0] * 1e-3
-        achieved = flops / avg_s / 1e12
-        roofline = {"kernel": dom, "bound": bound, "achieved": achieved,
-                    "peak": PEAK_FP32_TFLOPS, "unit": unit, "frac": achieved / PEAK_FP32_TFLOPS,
-                    "traffic": None}
-    else:
-        roofline = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None,
-                    "frac": None, "traffic": None}
-    fwd_grad_ms = sum(prof.get(k, (0, 0.0))[1] for k in
-                      ("prep", "render", "conv_residual", "conv_adjoint", "grad",
-                       "grad_finalize")) / args.steps
-    breakdown["fwd_grad_GVoxel_atom_per_s"] = V * N / (fwd_grad_ms * 1e-3) / 1e9
+    if prof:
+        fwd_grad_ms = sum(prof.get(k, (0, 0.0))[1] for k in
+                          ("prep", "render", "conv_residual", "conv_adjoint", "grad",
+                           "grad_finalize")) / ps
+        breakdown["fwd_grad_GVoxel_atom_per_s"] = V * N / (fwd_grad_ms * 1e-3) / 1e9
+
+    # roofline of the dominant kernel, timed live over the timed region
+    launches, ms = roof_prof[ROOF_CLASS]
+    avg_s = ms / launches * 1e-3
+    achieved = conv_flops / avg_s / 1e12
+    roofline = {"kernel": ROOF_KERNEL, "bound": "mfma", "achieved": achieved,
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                "traffic": conv_traffic(), "us_per_launch": avg_s * 1e6,
+                "flops_per_launch": conv_flops}
 
     out = {
         "metric": "fwd+grad GVoxel*atom/s (one step = every hot-path row once)",
@@ -222,6 +265,13 @@ def main():
         out["cpu_baseline"] = cpu_baseline(prob, atoms_eval.astype(np.float64),
                                            psf.astype(np.float64))
     print(json.dumps(out), flush=True)
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
     ws.close()
 
 

@@ -181,12 +181,16 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
 /* Per-kernel-class device time recorded with HIP events on the workspace stream between
  * sfw_profile_begin and sfw_profile_end. Classes: "prep", "render", "conv_residual",
  * "conv_adjoint", "conv_forward", "grad", "grad_finalize", "cert_conv", "cert_argmax",
- * "lasso_render", "lasso_conv", "lasso_dots", "hash", "eta_grad". */
+ * "lasso_render", "lasso_conv", "lasso_dots", "hash", "eta_grad", "cert_fft". Each timed
+ * launch group costs an event pair on the stream (a few microseconds of device idle), so
+ * time only the classes of interest when the surrounding throughput matters. */
 #define SFW_PROF_KINDS 16
 typedef struct { char name[24]; int32_t launches; double ms; } sfw_prof_entry;
 
-/* Start recording (creates the event pool on first use; host call, no device sync). */
-int sfw_profile_begin(sfw_workspace* ws);
+/* Start recording the classes named in `classes` (HOST, comma-separated, e.g.
+ * "conv_adjoint,cert_fft"; NULL or "" = every class). Creates the event pool on first use;
+ * host call, no device sync. SFW_EINVAL for an unknown class name. */
+int sfw_profile_begin(sfw_workspace* ws, const char* classes);
 /* Stop, synchronise the stream and write one entry per class with launches > 0 into
  * out (HOST [SFW_PROF_KINDS]); *n_out = entries written. */
 int sfw_profile_end(sfw_workspace* ws, sfw_prof_entry* out, int* n_out);

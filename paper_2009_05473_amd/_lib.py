@@ -102,7 +102,7 @@ def _load():
         "sfw_lasso_weights": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp]),
         "sfw_solve": (i32, [vp, vp, D, vp, D, f32, ctypes.POINTER(SfwOptions), vp, i32,
                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SfwStats)]),
-        "sfw_profile_begin": (i32, [vp]),
+        "sfw_profile_begin": (i32, [vp, ctypes.c_char_p]),
         "sfw_profile_end": (i32, [vp, ctypes.POINTER(SfwProfEntry), ctypes.POINTER(ctypes.c_int)]),
     }
     for name, (res, args) in sig.items():
@@ -304,8 +304,12 @@ def sfw_solve(ws: Workspace, y, H, lam, opts: SfwOptions | None = None, cap: int
     return arr.reshape(-1, 6), stats.as_dict(), code
 
 
-def sfw_profile_begin(ws: Workspace):
-    check(lib.sfw_profile_begin(ws.handle))
+def sfw_profile_begin(ws: Workspace, classes=None):
+    """Time the named kernel classes (an iterable of names or a comma-separated string; None
+    = every class) until sfw_profile_end."""
+    if classes is not None and not isinstance(classes, str):
+        classes = ",".join(classes)
+    check(lib.sfw_profile_begin(ws.handle, classes.encode() if classes else None))
 
 
 def sfw_profile_end(ws: Workspace):

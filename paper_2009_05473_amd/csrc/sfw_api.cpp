@@ -19,6 +19,11 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+const char* const kProfNames[kProfCount] = {
+    "prep", "render", "conv_residual", "conv_adjoint", "conv_forward", "grad",
+    "grad_finalize", "cert_conv", "cert_argmax", "lasso_render", "lasso_conv", "lasso_dots",
+    "hash", "eta_grad", "cert_fft"};
+
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
@@ -258,7 +263,7 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
   for (int r : rad) rmax = std::max(rmax, r);
   FftPlan pl;
   if (fft_plan_cert(vol, rmax, pl)) {
-    const size_t N = (size_t)pl.nx * pl.ny * pl.nz;
+    const size_t N = (size_t)pl.px * pl.ny * pl.nz;
     const int npairs = (ns * nd + 1) / 2;
     if (N > ws->fft_cap || npairs > ws->fft_npairs_cap) {
       if (ws->fft_qhat) SFW_HIP(hipFree(ws->fft_qhat));
@@ -268,7 +273,7 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
       ws->fft_cap = 0;
       ws->fft_npairs_cap = 0;
       SFW_HIP(hipMalloc(&ws->fft_qhat, N * sizeof(float2)));
-      SFW_HIP(hipMalloc(&ws->fft_work, N * sizeof(float2)));
+      SFW_HIP(hipMalloc(&ws->fft_work, (size_t)npairs * N * sizeof(float2)));
       SFW_HIP(hipMalloc(&ws->fft_pairs, (size_t)npairs * N * sizeof(float2)));
       ws->fft_cap = N;
       ws->fft_npairs_cap = npairs;
@@ -317,13 +322,11 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
       ProfScope ps(ws, kProfCertFft);
       SFW_HIP(fft_forward_volume(pl, q, vol, ws->fft_qhat, ws->stream));
     }
-    const int npairs = (ns * nd + 1) / 2;
-    for (int pi = 0; pi < npairs; ++pi) {
-      const int sa = 2 * pi, sb = 2 * pi + 1 < ns * nd ? 2 * pi + 1 : -1;
+    {
       ProfScope ps(ws, kProfCertFft);
-      SFW_HIP(fft_inverse_pair(pl, ws->fft_qhat, ws->fft_pairs + (size_t)pi * ws->fft_cap,
-                               ws->fft_work, vol, 1.0f / lambda, sa, sb, eta_out, ws->apart,
-                               nblk, ws->stream));
+      SFW_HIP(fft_inverse_pairs(pl, ws->fft_qhat, ws->fft_pairs, ws->fft_work, ws->fft_cap,
+                                ns * nd, vol, 1.0f / lambda, eta_out, ws->apart, nblk,
+                                ws->stream));
     }
     ProfScope ps(ws, kProfCertArgmax);
     SFW_HIP(launch_argmax_final(ws->apart, nblk * ns * nd, vol, nd, ws->best, ws->stream));
@@ -375,15 +378,30 @@ int op_gram_row(sfw_workspace* ws, const sfw_dims& vol, const float* y, int i, d
   return SFW_OK;
 }
 
-// Enqueue the fingerprints of y and H into ws->hashbuf.
+// Enqueue the fingerprints of y and H (and a copy of the n device atoms, if any) and their
+// readback into the pinned region at hp_hash (atoms at hp_atoms); read them with
+// read_fingerprints once the stream has been synchronised.
 static int enqueue_fingerprints(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
-                                const float* y, const float* H) {
+                                const float* y, const float* H, const sfw_atom* atoms, int n,
+                                int* by, int* bh) {
   ProfScope ps(ws, kProfHash);
   const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
-  SFW_HIP(hipMemsetAsync(ws->hashbuf, 0, 2 * sizeof(unsigned long long), ws->stream));
-  SFW_HIP(launch_hash(y, V, ws->hashbuf, ws->stream));
-  SFW_HIP(launch_hash(H, (size_t)p.psf.nx * p.psf.ny * p.psf.nz, ws->hashbuf + 1, ws->stream));
+  SFW_HIP(launch_fingerprints(y, V, H, (size_t)p.psf.nx * p.psf.ny * p.psf.nz, atoms, n,
+                              ws->hashbuf, by, bh, ws->stream));
+  const size_t words = 2 * (size_t)kFpParts + (atoms ? 3 * (size_t)n : 0);
+  SFW_HIP(hipMemcpyAsync(ws->hpin + ws->hp_hash, ws->hashbuf, words * 8, hipMemcpyDeviceToHost,
+                         ws->stream));
   return SFW_OK;
+}
+
+static void read_fingerprints(const sfw_workspace* ws, int by, int bh, unsigned long long* yh,
+                              unsigned long long* hh) {
+  const unsigned long long* part = reinterpret_cast<const unsigned long long*>(ws->hpin + ws->hp_hash);
+  unsigned long long a = 0, b = 0;
+  for (int i = 0; i < by; ++i) a += part[i];
+  for (int i = 0; i < bh; ++i) b += part[kFpParts + i];
+  *yh = a;
+  *hh = b;
 }
 
 // Drop the cached LASSO columns unless they were computed for this y pointer, shapes,
@@ -407,13 +425,13 @@ static void lasso_validate(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& 
 // Fingerprint y and H and validate the cache (one synchronisation).
 int lasso_check_inputs(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
                        const float* H) {
-  int rc = enqueue_fingerprints(ws, p, vol, y, H);
+  int by = 0, bh = 0;
+  int rc = enqueue_fingerprints(ws, p, vol, y, H, nullptr, 0, &by, &bh);
   if (rc) return rc;
-  unsigned long long* hh = reinterpret_cast<unsigned long long*>(ws->hpin + ws->hp_hash);
-  SFW_HIP(hipMemcpyAsync(hh, ws->hashbuf, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                         ws->stream));
   SFW_HIP(hipStreamSynchronize(ws->stream));
-  lasso_validate(ws, p, vol, y, hh[0], hh[1]);
+  unsigned long long yh = 0, hh = 0;
+  read_fingerprints(ws, by, bh, &yh, &hh);
+  lasso_validate(ws, p, vol, y, yh, hh);
   return SFW_OK;
 }
 
@@ -612,11 +630,11 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ws->apart_cap = cblocks * SFW_MAX_GRID * SFW_MAX_GRID;
     ALLOC(ws->apart, ws->apart_cap * sizeof(ArgPart), "argmax partials");
     ALLOC(ws->best, sizeof(sfw_argmax) * 2, "argmax");
-    ALLOC(ws->hashbuf, 2 * sizeof(unsigned long long), "fingerprints");
+    ALLOC(ws->hashbuf, (2 * (size_t)kFpParts + 3 * (size_t)na) * 8, "fingerprints");
     ALLOC(ws->cols, (size_t)max_atoms * V * 4, "LASSO columns");
 #undef ALLOC
     ws->hp_hash = 0;
-    ws->hp_atoms = 2;
+    ws->hp_atoms = 2 * (size_t)kFpParts;  // right behind the partials: one readback
     ws->hp_stage = ws->hp_atoms + 3 * (size_t)na;
     ws->hp_sums = ws->hp_stage + 4 * (size_t)na;
     ws->hp_w = ws->hp_sums + 6 * (size_t)na + 8;
@@ -636,8 +654,25 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
   }
 }
 
-int sfw_profile_begin(sfw_workspace* ws) {
+int sfw_profile_begin(sfw_workspace* ws, const char* classes) {
   if (!ws) return fail(SFW_EINVAL, "workspace is NULL");
+  unsigned mask = 0;
+  if (!classes || !*classes) {
+    mask = (1u << kProfCount) - 1u;
+  } else {
+    std::string list(classes);
+    size_t a = 0;
+    while (a <= list.size()) {
+      size_t b = list.find(',', a);
+      if (b == std::string::npos) b = list.size();
+      const std::string name = list.substr(a, b - a);
+      int k = 0;
+      while (k < kProfCount && name != kProfNames[k]) ++k;
+      if (k == kProfCount) return fail(SFW_EINVAL, "unknown profile class '" + name + "'");
+      mask |= 1u << k;
+      a = b + 1;
+    }
+  }
   if (ws->prof_start.empty()) {
     ws->prof_start.resize(kProfPool);
     ws->prof_stop.resize(kProfPool);
@@ -649,16 +684,13 @@ int sfw_profile_begin(sfw_workspace* ws) {
   }
   ws->prof_used = 0;
   ws->prof_overflow = false;
+  ws->prof_mask = mask;
   ws->prof_on = true;
   return SFW_OK;
 }
 
 int sfw_profile_end(sfw_workspace* ws, sfw_prof_entry* out, int* n_out) {
   if (!ws || !out || !n_out) return fail(SFW_EINVAL, "ws, out or n_out is NULL");
-  static const char* names[kProfCount] = {
-      "prep", "render", "conv_residual", "conv_adjoint", "conv_forward", "grad",
-      "grad_finalize", "cert_conv", "cert_argmax", "lasso_render", "lasso_conv", "lasso_dots",
-      "hash", "eta_grad", "cert_fft"};
   ws->prof_on = false;
   SFW_HIP(hipStreamSynchronize(ws->stream));
   double ms[kProfCount] = {0};
@@ -673,7 +705,7 @@ int sfw_profile_end(sfw_workspace* ws, sfw_prof_entry* out, int* n_out) {
   for (int i = 0; i < kProfCount && k < SFW_PROF_KINDS; ++i) {
     if (!cnt[i]) continue;
     std::memset(&out[k], 0, sizeof(out[k]));
-    std::strncpy(out[k].name, names[i], sizeof(out[k].name) - 1);
+    std::strncpy(out[k].name, kProfNames[i], sizeof(out[k].name) - 1);
     out[k].launches = cnt[i];
     out[k].ms = ms[i];
     ++k;
@@ -827,15 +859,14 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
     rc = prep_psf(ws, H, p, true, false);
     if (rc) return rc;
     // one synchronisation brings back the atoms and the fingerprints of y and H
-    rc = enqueue_fingerprints(ws, p, vol, y, H);
+    int by = 0, bh = 0;
+    rc = enqueue_fingerprints(ws, p, vol, y, H, atoms, n, &by, &bh);
     if (rc) return rc;
-    sfw_atom* ha = reinterpret_cast<sfw_atom*>(ws->hpin + ws->hp_atoms);
-    unsigned long long* hh = reinterpret_cast<unsigned long long*>(ws->hpin + ws->hp_hash);
-    SFW_HIP(hipMemcpyAsync(ha, atoms, sizeof(sfw_atom) * n, hipMemcpyDeviceToHost, ws->stream));
-    SFW_HIP(hipMemcpyAsync(hh, ws->hashbuf, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                           ws->stream));
     SFW_HIP(hipStreamSynchronize(ws->stream));
-    lasso_validate(ws, p, vol, y, hh[0], hh[1]);
+    unsigned long long yh = 0, hh = 0;
+    read_fingerprints(ws, by, bh, &yh, &hh);
+    lasso_validate(ws, p, vol, y, yh, hh);
+    const sfw_atom* ha = reinterpret_cast<const sfw_atom*>(ws->hpin + ws->hp_atoms);
     std::vector<float> th(5 * (size_t)n);
     for (int i = 0; i < n; ++i) {
       th[5 * i + 0] = ha[i].mx;

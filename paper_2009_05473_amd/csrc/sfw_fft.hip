@@ -80,10 +80,15 @@ __device__ __forceinline__ void dft<5>(float2* v) {
   v[3] = csub(p2, q2);
 }
 
+constexpr int kFftThreads = 256;
+constexpr int kFftBatch = 8;  // global loads in flight per thread while filling LDS
+
 // One Stockham stage of radix R over 2^lgB lines of length L held in LDS (src -> dst, line
 // pitch LS). Ns = product of the radices of the previous stages; tw[m] = exp(-2 pi i m / L).
 // Tasks are mapped line-fastest so that line and butterfly index come from shifts; j / Ns is
-// a multiply-high by ceil(2^32 / Ns), exact for j, Ns < 2^16.
+// a multiply-high by ceil(2^32 / Ns), exact for j, Ns < 2^16. Each thread takes two tasks per
+// round (the second clamped to the last task and not stored when out of range) so that both
+// sets of LDS reads are in flight together.
 template <int R>
 __device__ __forceinline__ void stage(const float2* __restrict__ src, float2* __restrict__ dst,
                                       int L, int LS, int lgB, int Ns, const float2* __restrict__ tw) {
@@ -92,22 +97,32 @@ __device__ __forceinline__ void stage(const float2* __restrict__ src, float2* __
   const int tstep = L / (Ns * R);
   const unsigned mNs = Ns > 1 ? 0xffffffffu / (unsigned)Ns + 1u : 0u;
   const int B1 = (1 << lgB) - 1;
-  for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
-    const int line = t & B1;
-    const int j = t >> lgB;
-    const int q = Ns > 1 ? (int)__umulhi((unsigned)j, mNs) : j;
-    const int k = j - q * Ns;
-    const float2* in = src + line * LS;
-    float2 v[R];
+  for (int t0 = threadIdx.x; t0 < tasks; t0 += 2 * kFftThreads) {
+    float2 v[2][R];
+    int o[2];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      v[r] = in[j + r * per];
-      if (r > 0) v[r] = cmul(v[r], tw[r * k * tstep]);  // r k tstep < L
+    for (int h = 0; h < 2; ++h) {
+      const int t = min(t0 + h * kFftThreads, tasks - 1);
+      const int line = t & B1;
+      const int j = t >> lgB;
+      const int q = Ns > 1 ? (int)__umulhi((unsigned)j, mNs) : j;
+      const int k = j - q * Ns;
+      const float2* in = src + line * LS + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        v[h][r] = in[r * per];
+        if (r > 0) v[h][r] = cmul(v[h][r], tw[r * k * tstep]);  // r k tstep < L
+      }
+      o[h] = line * LS + q * Ns * R + k;
     }
-    dft<R>(v);
-    float2* out = dst + line * LS + q * Ns * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[r * Ns] = v[r];
+    for (int h = 0; h < 2; ++h) {
+      dft<R>(v[h]);
+      if (t0 + h * kFftThreads < tasks) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[o[h] + r * Ns] = v[h][r];
+      }
+    }
   }
 }
 
@@ -140,7 +155,7 @@ __device__ __forceinline__ int line_pitch(int L) { return L | 1; }
 
 __device__ __forceinline__ float2* load_twiddles(float2* sm, int lgB, int LS, const FftAxis& ax) {
   float2* tw = sm + (2 << lgB) * LS;
-  for (int i = threadIdx.x; i < ax.n; i += blockDim.x) tw[i] = ax.tw[i];
+  for (int i = threadIdx.x; i < ax.n; i += kFftThreads) tw[i] = ax.tw[i];
   return tw;
 }
 
@@ -151,13 +166,31 @@ __device__ __forceinline__ bool arg_better(float v, long long i, float bv, long 
   return v > bv || (v == bv && i < bi);
 }
 
+// Fills LDS with `total` elements: get(e, ok) returns element e, loading from a clamped (always
+// valid) address and returning zero when !ok; put(e, v) stores it. The loads of a batch are
+// issued before any of them is waited on.
+template <class Get, class Put>
+__device__ __forceinline__ void fill_lds(int total, Get get, Put put) {
+  for (int e0 = threadIdx.x; e0 < total; e0 += kFftBatch * kFftThreads) {
+    float2 v[kFftBatch];
+#pragma unroll
+    for (int u = 0; u < kFftBatch; ++u) v[u] = get(e0 + u * kFftThreads);
+#pragma unroll
+    for (int u = 0; u < kFftBatch; ++u)
+      if (e0 + u * kFftThreads < total) put(e0 + u * kFftThreads, v[u]);
+  }
+}
+
 // ---------------------------------------------------------------- x passes (contiguous lines)
+// Spectrum arrays are [z][y][x] with x pitch px (a multiple of 16 elements, so that the
+// 16-column runs of the strided passes are whole 128-byte lines).
 
 // Forward x pass of the real volume q: line (y, z) for y < ny, z < nz, zero beyond nx.
-// out[(z * Ny + y) * Nx + i], i < Nx.
-__global__ __launch_bounds__(256) void k_fft_x_real(const float* __restrict__ q, int nx, int ny,
-                                                    int nz, FftAxis ax, int Ny, int lgB,
-                                                    float2* __restrict__ out) {
+// out[(z * Ny + y) * px + i], i < Nx.
+__global__ __launch_bounds__(kFftThreads) void k_fft_x_real(const float* __restrict__ q, int nx,
+                                                            int ny, int nz, FftAxis ax, int Ny,
+                                                            int px, int lgB,
+                                                            float2* __restrict__ out) {
   extern __shared__ float2 sm[];
   const int L = ax.n, LS = line_pitch(L), B = 1 << lgB;
   const unsigned mL = 0xffffffffu / (unsigned)L + 1u;
@@ -166,22 +199,30 @@ __global__ __launch_bounds__(256) void k_fft_x_real(const float* __restrict__ q,
   const float2* tw = load_twiddles(sm, lgB, LS, ax);
   const int y0 = blockIdx.x * B, z = blockIdx.y;
   const int lines = min(B, ny - y0);
-  for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
-    const int l = div_by(e, mL), i = e - l * L;
-    float v = 0.f;
-    if (l < lines && i < nx) v = q[((size_t)z * ny + y0 + l) * nx + i];
-    a[l * LS + i] = make_float2(v, 0.f);
-  }
+  const float* base = q + ((size_t)z * ny + y0) * nx;
+  fill_lds(
+      B * L,
+      [&](int e) {
+        const int l = div_by(e, mL), i = e - l * L;
+        const bool ok = l < lines && i < nx;
+        const float v = base[ok ? l * nx + i : 0];
+        return make_float2(ok ? v : 0.f, 0.f);
+      },
+      [&](int e, float2 v) {
+        const int l = div_by(e, mL), i = e - l * L;
+        a[l * LS + i] = v;
+      });
   float2* r = run_plan(a, b, LS, lgB, ax, tw);
-  for (int e = threadIdx.x; e < lines * L; e += blockDim.x) {
+  float2* obase = out + ((size_t)z * Ny + y0) * px;
+  for (int e = threadIdx.x; e < lines * L; e += kFftThreads) {
     const int l = div_by(e, mL), i = e - l * L;
-    out[((size_t)z * Ny + y0 + l) * L + i] = r[l * LS + i];
+    obase[l * px + i] = r[l * LS + i];
   }
 }
 
 // Forward x pass of a complex array, every line of an Ny x Nz grid.
-__global__ __launch_bounds__(256) void k_fft_x_c2c(float2* __restrict__ data, FftAxis ax, int Ny,
-                                                   int lgB) {
+__global__ __launch_bounds__(kFftThreads) void k_fft_x_c2c(float2* __restrict__ data, FftAxis ax,
+                                                           int Ny, int px, int lgB) {
   extern __shared__ float2 sm[];
   const int L = ax.n, LS = line_pitch(L), B = 1 << lgB;
   const unsigned mL = 0xffffffffu / (unsigned)L + 1u;
@@ -190,27 +231,39 @@ __global__ __launch_bounds__(256) void k_fft_x_c2c(float2* __restrict__ data, Ff
   const float2* tw = load_twiddles(sm, lgB, LS, ax);
   const int y0 = blockIdx.x * B, z = blockIdx.y;
   const int lines = min(B, Ny - y0);
-  float2* base = data + ((size_t)z * Ny + y0) * L;
-  for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
-    const int l = div_by(e, mL), i = e - l * L;
-    a[l * LS + i] = e < lines * L ? base[e] : make_float2(0.f, 0.f);
-  }
+  float2* base = data + ((size_t)z * Ny + y0) * px;
+  fill_lds(
+      B * L,
+      [&](int e) {
+        const int l = div_by(e, mL), i = e - l * L;
+        const bool ok = l < lines;
+        const float2 v = base[ok ? l * px + i : 0];
+        return ok ? v : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) {
+        const int l = div_by(e, mL), i = e - l * L;
+        a[l * LS + i] = v;
+      });
   float2* r = run_plan(a, b, LS, lgB, ax, tw);
-  for (int e = threadIdx.x; e < lines * L; e += blockDim.x) {
+  for (int e = threadIdx.x; e < lines * L; e += kFftThreads) {
     const int l = div_by(e, mL), i = e - l * L;
-    base[e] = r[l * LS + i];
+    base[l * px + i] = r[l * LS + i];
   }
 }
 
-// Last inverse pass: line (y < ny, z < nz) of work, forward FFT, conjugated output; real part
-// is eta_a, imaginary part eta_b (times scale). Writes eta (optional) and the block maxima.
-__global__ __launch_bounds__(256) void k_fft_x_argmax(
-    const float2* __restrict__ work, int nx, int ny, int nz, FftAxis ax, int Ny, int lgB,
-    float scale, int slice_a, int slice_b, float* __restrict__ eta_out, ArgPart* __restrict__ apart,
-    int nblk) {
+// Last inverse pass: line (y < ny, z < nz) of the work array of pair p = blockIdx.z, forward
+// FFT, conjugated output; real part is eta of table kernel 2p, imaginary part eta of kernel
+// 2p + 1 (if < nslices), times scale. Writes eta (optional) and the block maxima.
+__global__ __launch_bounds__(kFftThreads) void k_fft_x_argmax(
+    const float2* __restrict__ work, size_t work_bstride, int nx, int ny, int nz, FftAxis ax,
+    int Ny, int px, int lgB, float scale, int nslices, float* __restrict__ eta_out,
+    ArgPart* __restrict__ apart, int nblk) {
+  const int slice_a = 2 * (int)blockIdx.z;
+  const int slice_b = slice_a + 1 < nslices ? slice_a + 1 : -1;
+  work += blockIdx.z * work_bstride;
   extern __shared__ float2 sm[];
-  __shared__ float rv[2][4];
-  __shared__ long long ri[2][4];
+  __shared__ float rv[2][kFftThreads / 64];
+  __shared__ long long ri[2][kFftThreads / 64];
   const int L = ax.n, LS = line_pitch(L), B = 1 << lgB;
   const unsigned mL = 0xffffffffu / (unsigned)L + 1u;
   float2* a = sm;
@@ -218,21 +271,31 @@ __global__ __launch_bounds__(256) void k_fft_x_argmax(
   const float2* tw = load_twiddles(sm, lgB, LS, ax);
   const int y0 = blockIdx.x * B, z = blockIdx.y;
   const int lines = min(B, ny - y0);
-  const float2* base = work + ((size_t)z * Ny + y0) * L;
-  for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
-    const int l = div_by(e, mL), i = e - l * L;
-    a[l * LS + i] = e < lines * L ? base[e] : make_float2(0.f, 0.f);
-  }
+  const float2* base = work + ((size_t)z * Ny + y0) * px;
+  fill_lds(
+      B * L,
+      [&](int e) {
+        const int l = div_by(e, mL), i = e - l * L;
+        const bool ok = l < lines;
+        const float2 v = base[ok ? l * px + i : 0];
+        return ok ? v : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) {
+        const int l = div_by(e, mL), i = e - l * L;
+        a[l * LS + i] = v;
+      });
   float2* r = run_plan(a, b, LS, lgB, ax, tw);
   const long long V = (long long)nx * ny * nz;
   float bv[2] = {-INFINITY, -INFINITY};
   long long bi[2] = {0x7fffffffffffffffLL, 0x7fffffffffffffffLL};
-  for (int e = threadIdx.x; e < lines * L; e += blockDim.x) {
-    const int l = div_by(e, mL), i = e - l * L;
-    if (i >= nx) continue;
+  const int nxl = lines * nx;
+  const unsigned mX = 0xffffffffu / (unsigned)nx + 1u;
+  for (int e = threadIdx.x; e < nxl; e += kFftThreads) {
+    const int l = div_by(e, mX), i = e - l * nx;
     const long long v = ((long long)z * ny + y0 + l) * nx + i;
-    const float ea = r[l * LS + i].x * scale;
-    const float eb = -r[l * LS + i].y * scale;
+    const float2 c = r[l * LS + i];
+    const float ea = c.x * scale;
+    const float eb = -c.y * scale;
     if (eta_out) {
       eta_out[(size_t)slice_a * V + v] = ea;
       if (slice_b >= 0) eta_out[(size_t)slice_b * V + v] = eb;
@@ -267,12 +330,12 @@ __global__ __launch_bounds__(256) void k_fft_x_argmax(
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;  // < nblk
     for (int s = 0; s < 2; ++s) {
       if (s == 1 && slice_b < 0) break;
       float v = rv[s][0];
       long long id = ri[s][0];
-      for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      for (int w = 1; w < kFftThreads / 64; ++w)
         if (arg_better(rv[s][w], ri[s][w], v, id)) {
           v = rv[s][w];
           id = ri[s][w];
@@ -289,62 +352,71 @@ __global__ __launch_bounds__(256) void k_fft_x_argmax(
 // ---------------------------------------------------------------- strided passes (y or z)
 
 // Lines along one axis with element stride `istride`; a block owns B adjacent x columns at
-// one outer coordinate o (address o * ostride + i * istride + x). Reads i < n_in (zero beyond),
-// writes i < n_out. mode 0: plain; mode 1: input = conj(data * mulp) (first inverse pass).
-__global__ __launch_bounds__(256) void k_fft_strided(const float2* __restrict__ src,
-                                                     const float2* __restrict__ mulp,
-                                                     float2* __restrict__ dst, FftAxis ax,
-                                                     int ncols, size_t istride, size_t ostride,
-                                                     int n_in, int n_out, int lgB, int mode) {
+// one outer coordinate o (address o * ostride + i * istride + x) of batch entry blockIdx.z
+// (arrays offset by blockIdx.z times their batch stride). Reads i < n_in (zero beyond), writes
+// i < n_out. MUL: input = conj(data * mulp) (first inverse pass).
+template <bool MUL>
+__global__ __launch_bounds__(kFftThreads) void k_fft_strided(
+    const float2* __restrict__ src, size_t src_bstride, const float2* __restrict__ mulp,
+    size_t mul_bstride, float2* __restrict__ dst, size_t dst_bstride, FftAxis ax, int ncols,
+    size_t istride, size_t ostride, int n_in, int n_out, int lgB) {
   extern __shared__ float2 sm[];
+  src += blockIdx.z * src_bstride;
+  if (MUL) mulp += blockIdx.z * mul_bstride;
+  dst += blockIdx.z * dst_bstride;
   const int L = ax.n, LS = line_pitch(L), B = 1 << lgB;
   float2* a = sm;
   float2* b = sm + B * LS;
   const float2* tw = load_twiddles(sm, lgB, LS, ax);
   const int x0 = blockIdx.x * B;
-  const size_t obase = (size_t)blockIdx.y * ostride;
+  const size_t obase = (size_t)blockIdx.y * ostride + x0;
   const int cols = min(B, ncols - x0);
-  for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
-    const int i = e >> lgB, c = e & (B - 1);  // consecutive threads: consecutive columns
-    float2 v = make_float2(0.f, 0.f);
-    if (c < cols && i < n_in) {
-      const size_t g = obase + (size_t)i * istride + x0 + c;
-      v = src[g];
-      if (mode == 1) {
-        v = cmul(v, mulp[g]);
-        v.y = -v.y;
-      }
-    }
-    a[c * LS + i] = v;
-  }
+  fill_lds(
+      B * L,
+      [&](int e) {
+        const int i = e >> lgB, c = e & (B - 1);  // consecutive threads: consecutive columns
+        const bool ok = c < cols && i < n_in;
+        const size_t g = obase + (ok ? (size_t)i * istride + c : 0);
+        float2 v = src[g];
+        if (MUL) {
+          v = cmul(v, mulp[g]);
+          v.y = -v.y;
+        }
+        return ok ? v : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) {
+        const int i = e >> lgB, c = e & (B - 1);
+        a[c * LS + i] = v;
+      });
   float2* r = run_plan(a, b, LS, lgB, ax, tw);
-  for (int e = threadIdx.x; e < B * L; e += blockDim.x) {
+  for (int e = threadIdx.x; e < B * n_out; e += kFftThreads) {
     const int i = e >> lgB, c = e & (B - 1);
-    if (c < cols && i < n_out) dst[obase + (size_t)i * istride + x0 + c] = r[c * LS + i];
+    if (c < cols) dst[obase + (size_t)i * istride + c] = r[c * LS + i];
   }
 }
 
-// Kernel pair (a, b) of the table, wrapped around the origin of the Nx x Ny x Nz grid:
-// out = (K_a + i K_b) / N. Tables are [ky][kx][kzp] with radius R (2R + 1 taps per axis).
+// Kernel pair (a, b) of the table, wrapped around the origin of the Nx x Ny x Nz grid (x pitch
+// px, padding columns zero): out = (K_a + i K_b) / N. Tables are [ky][kx][kzp] with radius R
+// (2R + 1 taps per axis).
 __global__ __launch_bounds__(256) void k_fft_scatter_pair(
     const float* __restrict__ ka, int ra, int kzpa, const float* __restrict__ kb, int rb,
-    int kzpb, int Nx, int Ny, int Nz, float inv_n, float2* __restrict__ out) {
-  const size_t N = (size_t)Nx * Ny * Nz;
+    int kzpb, int Nx, int Ny, int Nz, int px, float inv_n, float2* __restrict__ out) {
+  const size_t N = (size_t)px * Ny * Nz;
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
-  const int x = (int)(i % Nx);
-  const int y = (int)((i / Nx) % Ny);
-  const int z = (int)(i / ((size_t)Nx * Ny));
+  const int x = (int)(i % px);
+  const int y = (int)((i / px) % Ny);
+  const int z = (int)(i / ((size_t)px * Ny));
   // signed offsets t in (-N/2, N/2]
   const int tx = x <= Nx / 2 ? x : x - Nx;
   const int ty = y <= Ny / 2 ? y : y - Ny;
   const int tz = z <= Nz / 2 ? z : z - Nz;
   float va = 0.f, vb = 0.f;
-  if (abs(tx) <= ra && abs(ty) <= ra && abs(tz) <= ra) {
+  if (x < Nx && abs(tx) <= ra && abs(ty) <= ra && abs(tz) <= ra) {
     const int P = 2 * ra + 1;
     va = ka[((size_t)(ty + ra) * P + (tx + ra)) * kzpa + (tz + ra)];
   }
-  if (kb && abs(tx) <= rb && abs(ty) <= rb && abs(tz) <= rb) {
+  if (kb && x < Nx && abs(tx) <= rb && abs(ty) <= rb && abs(tz) <= rb) {
     const int P = 2 * rb + 1;
     vb = kb[((size_t)(ty + rb) * P + (tx + rb)) * kzpb + (tz + rb)];
   }
@@ -396,6 +468,7 @@ bool fft_plan_cert(sfw_dims vol, int rmax, FftPlan& pl) {
   pl.nx = good_size(std::max(vol.nx + rmax, 2 * rmax + 1));
   pl.ny = good_size(std::max(vol.ny + rmax, 2 * rmax + 1));
   pl.nz = good_size(std::max(vol.nz + rmax, 2 * rmax + 1));
+  pl.px = (pl.nx + 15) & ~15;
   if (pl.nx > kFftMaxLen || pl.ny > kFftMaxLen || pl.nz > kFftMaxLen) return false;
   return make_axis_plan(pl.nx, pl.ax[0]) && make_axis_plan(pl.ny, pl.ax[1]) &&
          make_axis_plan(pl.nz, pl.ax[2]);
@@ -412,28 +485,30 @@ void fft_twiddles(int n, std::vector<float2>& tw) {
 // Forward 3D transform of a complex array on the full grid (used for the table spectra).
 hipError_t fft_forward_c2c(const FftPlan& pl, float2* data, hipStream_t st) {
   const int gx = fft_lg_lines(pl.nx, false), Bx = 1 << gx;
-  hipLaunchKernelGGL(k_fft_x_c2c, dim3((pl.ny + Bx - 1) / Bx, pl.nz), dim3(256),
-                     fft_lds(pl.nx, gx), st, data, pl.ax[0], pl.ny, gx);
+  hipLaunchKernelGGL(k_fft_x_c2c, dim3((pl.ny + Bx - 1) / Bx, pl.nz), dim3(kFftThreads),
+                     fft_lds(pl.nx, gx), st, data, pl.ax[0], pl.ny, pl.px, gx);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int gy = fft_lg_lines(pl.ny, true), By = 1 << gy;
-  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + By - 1) / By, pl.nz), dim3(256),
-                     fft_lds(pl.ny, gy), st, data, nullptr, data, pl.ax[1], pl.nx,
-                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, pl.ny, pl.ny, gy, 0);
+  hipLaunchKernelGGL(k_fft_strided<false>, dim3((pl.nx + By - 1) / By, pl.nz), dim3(kFftThreads),
+                     fft_lds(pl.ny, gy), st, data, (size_t)0, nullptr, (size_t)0, data, (size_t)0, pl.ax[1], pl.nx,
+                     (size_t)pl.px, (size_t)pl.px * pl.ny, pl.ny, pl.ny, gy);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int gz = fft_lg_lines(pl.nz, true), Bz = 1 << gz;
-  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(256),
-                     fft_lds(pl.nz, gz), st, data, nullptr, data, pl.ax[2], pl.nx,
-                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, pl.nz, pl.nz, gz, 0);
+  hipLaunchKernelGGL(k_fft_strided<false>, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(kFftThreads),
+                     fft_lds(pl.nz, gz), st, data, (size_t)0, nullptr, (size_t)0, data, (size_t)0, pl.ax[2], pl.nx,
+                     (size_t)pl.px * pl.ny, (size_t)pl.px, pl.nz, pl.nz, gz);
   return hipGetLastError();
 }
 
 hipError_t fft_scatter_pair(const FftPlan& pl, const float* ka, int ra, int kzpa, const float* kb,
                             int rb, int kzpb, float2* out, hipStream_t st) {
   const size_t N = (size_t)pl.nx * pl.ny * pl.nz;
-  hipLaunchKernelGGL(k_fft_scatter_pair, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, ka,
-                     ra, kzpa, kb, rb, kzpb, pl.nx, pl.ny, pl.nz, (float)(1.0 / (double)N), out);
+  const size_t Np = (size_t)pl.px * pl.ny * pl.nz;
+  hipLaunchKernelGGL(k_fft_scatter_pair, dim3((unsigned)((Np + 255) / 256)), dim3(256), 0, st, ka,
+                     ra, kzpa, kb, rb, kzpb, pl.nx, pl.ny, pl.nz, pl.px,
+                     (float)(1.0 / (double)N), out);
   return hipGetLastError();
 }
 
@@ -441,21 +516,21 @@ hipError_t fft_scatter_pair(const FftPlan& pl, const float* ka, int ra, int kzpa
 hipError_t fft_forward_volume(const FftPlan& pl, const float* q, sfw_dims vol, float2* qhat,
                               hipStream_t st) {
   const int gx = fft_lg_lines(pl.nx, false), Bx = 1 << gx;
-  hipLaunchKernelGGL(k_fft_x_real, dim3((vol.ny + Bx - 1) / Bx, vol.nz), dim3(256),
-                     fft_lds(pl.nx, gx), st, q, vol.nx, vol.ny, vol.nz, pl.ax[0], pl.ny, gx,
-                     qhat);
+  hipLaunchKernelGGL(k_fft_x_real, dim3((vol.ny + Bx - 1) / Bx, vol.nz), dim3(kFftThreads),
+                     fft_lds(pl.nx, gx), st, q, vol.nx, vol.ny, vol.nz, pl.ax[0], pl.ny, pl.px,
+                     gx, qhat);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int gy = fft_lg_lines(pl.ny, true), By = 1 << gy;
-  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + By - 1) / By, vol.nz), dim3(256),
-                     fft_lds(pl.ny, gy), st, qhat, nullptr, qhat, pl.ax[1], pl.nx,
-                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, vol.ny, pl.ny, gy, 0);
+  hipLaunchKernelGGL(k_fft_strided<false>, dim3((pl.nx + By - 1) / By, vol.nz), dim3(kFftThreads),
+                     fft_lds(pl.ny, gy), st, qhat, (size_t)0, nullptr, (size_t)0, qhat, (size_t)0, pl.ax[1], pl.nx,
+                     (size_t)pl.px, (size_t)pl.px * pl.ny, vol.ny, pl.ny, gy);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int gz = fft_lg_lines(pl.nz, true), Bz = 1 << gz;
-  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(256),
-                     fft_lds(pl.nz, gz), st, qhat, nullptr, qhat, pl.ax[2], pl.nx,
-                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, vol.nz, pl.nz, gz, 0);
+  hipLaunchKernelGGL(k_fft_strided<false>, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(kFftThreads),
+                     fft_lds(pl.nz, gz), st, qhat, (size_t)0, nullptr, (size_t)0, qhat, (size_t)0, pl.ax[2], pl.nx,
+                     (size_t)pl.px * pl.ny, (size_t)pl.px, vol.nz, pl.nz, gz);
   return hipGetLastError();
 }
 
@@ -464,26 +539,32 @@ int fft_argmax_blocks(const FftPlan& pl, sfw_dims vol) {
   return ((vol.ny + Bx - 1) / Bx) * vol.nz;
 }
 
-// eta_a + i eta_b = IFFT(Qhat * P) on the volume, with the block maxima of both slices.
-hipError_t fft_inverse_pair(const FftPlan& pl, const float2* qhat, const float2* pair,
-                            float2* work, sfw_dims vol, float scale, int slice_a, int slice_b,
-                            float* eta_out, ArgPart* apart, int nblk, hipStream_t st) {
+// eta_{2p} + i eta_{2p+1} = IFFT(Qhat * P_p) on the volume for every pair p < npairs at once
+// (pair spectra and work arrays at a stride of `bstride` elements), with the block maxima of
+// every slice.
+hipError_t fft_inverse_pairs(const FftPlan& pl, const float2* qhat, const float2* pairs,
+                             float2* work, size_t bstride, int nslices, sfw_dims vol,
+                             float scale, float* eta_out, ArgPart* apart, int nblk,
+                             hipStream_t st) {
+  const unsigned np = (unsigned)((nslices + 1) / 2);
   const int gz = fft_lg_lines(pl.nz, true), Bz = 1 << gz;
-  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(256),
-                     fft_lds(pl.nz, gz), st, qhat, pair, work, pl.ax[2], pl.nx,
-                     (size_t)pl.nx * pl.ny, (size_t)pl.nx, pl.nz, vol.nz, gz, 1);
+  hipLaunchKernelGGL(k_fft_strided<true>, dim3((pl.nx + Bz - 1) / Bz, pl.ny, np),
+                     dim3(kFftThreads), fft_lds(pl.nz, gz), st, qhat, (size_t)0, pairs, bstride,
+                     work, bstride, pl.ax[2], pl.nx, (size_t)pl.px * pl.ny, (size_t)pl.px, pl.nz,
+                     vol.nz, gz);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int gy = fft_lg_lines(pl.ny, true), By = 1 << gy;
-  hipLaunchKernelGGL(k_fft_strided, dim3((pl.nx + By - 1) / By, vol.nz), dim3(256),
-                     fft_lds(pl.ny, gy), st, work, nullptr, work, pl.ax[1], pl.nx,
-                     (size_t)pl.nx, (size_t)pl.nx * pl.ny, pl.ny, vol.ny, gy, 0);
+  hipLaunchKernelGGL(k_fft_strided<false>, dim3((pl.nx + By - 1) / By, vol.nz, np),
+                     dim3(kFftThreads), fft_lds(pl.ny, gy), st, work, bstride, nullptr, (size_t)0,
+                     work, bstride, pl.ax[1], pl.nx, (size_t)pl.px, (size_t)pl.px * pl.ny, pl.ny,
+                     vol.ny, gy);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int gx = fft_lg_lines(pl.nx, false), Bx = 1 << gx;
-  hipLaunchKernelGGL(k_fft_x_argmax, dim3((vol.ny + Bx - 1) / Bx, vol.nz), dim3(256),
-                     fft_lds(pl.nx, gx), st, work, vol.nx, vol.ny, vol.nz, pl.ax[0], pl.ny, gx,
-                     scale, slice_a, slice_b, eta_out, apart, nblk);
+  hipLaunchKernelGGL(k_fft_x_argmax, dim3((vol.ny + Bx - 1) / Bx, vol.nz, np), dim3(kFftThreads),
+                     fft_lds(pl.nx, gx), st, work, bstride, vol.nx, vol.ny, vol.nz, pl.ax[0],
+                     pl.ny, pl.px, gx, scale, nslices, eta_out, apart, nblk);
   return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ constexpr int conv_tile_lzp(int kz) {
 }
 
 // One axis of a separable FFT: length n = prod(radix), twiddles tw[m] = exp(-2 pi i m / n).
+constexpr int kFpParts = 256;  // fingerprint partials per array
 constexpr int kFftMaxStages = 16;
 constexpr int kFftMaxLen = 1024;
 struct FftAxis {
@@ -64,6 +65,7 @@ struct FftAxis {
 };
 struct FftPlan {
   int nx = 0, ny = 0, nz = 0;
+  int px = 0;  // x pitch of the spectrum arrays (nx rounded up to 16)
   FftAxis ax[3];
 };
 
@@ -131,7 +133,7 @@ struct sfw_workspace {
   bool fft_ready = false;
   float2* fft_tw = nullptr;      // [nx + ny + nz]
   float2* fft_qhat = nullptr;    // [N]
-  float2* fft_work = nullptr;    // [N]
+  float2* fft_work = nullptr;    // [npairs][N]
   float2* fft_pairs = nullptr;   // [npairs][N]
   size_t fft_cap = 0;            // complex elements per array
   int fft_npairs_cap = 0;
@@ -160,10 +162,13 @@ struct sfw_workspace {
   bool lasso_mfma = false;
   std::vector<float> lasso_thetas;  // [lasso_k][5]
   std::vector<double> lasso_G, lasso_b;  // [max_atoms][max_atoms], [max_atoms]
-  unsigned long long* hashbuf = nullptr;  // [2] device
+  // device [2 kFpParts + 3 max_atoms]: per-block fingerprint partials of y and H, then a copy
+  // of the atoms (one readback)
+  unsigned long long* hashbuf = nullptr;
 
   // pinned host staging (doubles), carved into regions that never overlap:
-  //   [hp_hash, +2) fingerprints | [hp_atoms, +3 na) atom readback / upload (sfw_atom)
+  //   [hp_hash, +2 kFpParts) fingerprint partials, directly followed by
+  //   [hp_atoms, +3 na) atom readback / upload (sfw_atom)
   //   [hp_stage, +4 na) atom constants (AtomK) | [hp_sums, +6 na + 8) reduction sums
   //   [hp_w, +na) LASSO weights on their way to the device | [hp_rows, ...) Gram rows
   double* hpin = nullptr;
@@ -172,6 +177,7 @@ struct sfw_workspace {
 
   // optional per-kernel-class event timing (sfw_profile_begin / end)
   bool prof_on = false;
+  unsigned prof_mask = 0;  // bit k: class k is timed
   int prof_used = 0;
   bool prof_overflow = false;
   std::vector<hipEvent_t> prof_start, prof_stop;
@@ -184,7 +190,7 @@ struct ProfScope {
   sfw_workspace* ws;
   int slot = -1;
   ProfScope(sfw_workspace* w, int kind) : ws(w) {
-    if (!ws->prof_on) return;
+    if (!ws->prof_on || !((ws->prof_mask >> kind) & 1u)) return;
     if (ws->prof_used >= (int)ws->prof_start.size()) {
       ws->prof_overflow = true;
       return;
@@ -222,7 +228,9 @@ hipError_t launch_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* ak
                        sfw_dims psf, bool mfma, int kzp, bool fwd, bool adj, float* out_fwd,
                        float* out_adj, hipStream_t st);
 // atomicAdd of the fingerprint of v[0..n) into *out (zero it first).
-hipError_t launch_hash(const float* v, size_t n, unsigned long long* out, hipStream_t st);
+hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t nh,
+                               const sfw_atom* atoms, int n, unsigned long long* fp, int* by_out,
+                               int* bh_out, hipStream_t st);
 hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st);
 
 enum ConvEpilogue { kEpiPlain = 0, kEpiResidual = 1, kEpiArgmax = 2 };
@@ -273,8 +281,9 @@ hipError_t fft_forward_c2c(const FftPlan& pl, float2* data, hipStream_t st);
 hipError_t fft_forward_volume(const FftPlan& pl, const float* q, sfw_dims vol, float2* qhat,
                               hipStream_t st);
 int fft_argmax_blocks(const FftPlan& pl, sfw_dims vol);
-hipError_t fft_inverse_pair(const FftPlan& pl, const float2* qhat, const float2* pair,
-                            float2* work, sfw_dims vol, float scale, int slice_a, int slice_b,
-                            float* eta_out, ArgPart* apart, int nblk, hipStream_t st);
+hipError_t fft_inverse_pairs(const FftPlan& pl, const float2* qhat, const float2* pairs,
+                             float2* work, size_t bstride, int nslices, sfw_dims vol,
+                             float scale, float* eta_out, ArgPart* apart, int nblk,
+                             hipStream_t st);
 
 }  // namespace sfw

@@ -116,17 +116,31 @@ __global__ void k_prep(const sfw_atom* __restrict__ atoms, int n, int unit_weigh
 
 // Order-independent 64-bit fingerprint of a float array: sum over i of bits(v[i]) * (2 i + 1)
 // (mod 2^64). Used to recognise inputs already seen by cached LASSO columns.
-__global__ __launch_bounds__(256) void k_hash(const float* __restrict__ v, size_t n,
-                                              unsigned long long* __restrict__ out) {
+// Fingerprint sum_i bits(v_i) * (2 i + 1) (mod 2^64) of y (blocks [0, by)) and H (blocks
+// [by, by + bh)), one partial per block: fp[b] for y, fp[kFpParts + b - by] for H; the host
+// adds the partials. Block 0 also copies the n atoms behind the partials (fp[2 kFpParts...])
+// so that one device-to-host copy returns everything.
+__global__ __launch_bounds__(256) void k_fingerprints(const float* __restrict__ y, size_t ny,
+                                                      int by, const float* __restrict__ H,
+                                                      size_t nh, const float* __restrict__ atoms,
+                                                      int n, unsigned long long* __restrict__ fp) {
   __shared__ unsigned long long red[4];
-  const size_t stride = (size_t)gridDim.x * 256;
+  const bool is_y = (int)blockIdx.x < by;
+  const int b = is_y ? (int)blockIdx.x : (int)blockIdx.x - by;
+  const float* v = is_y ? y : H;
+  const size_t len = is_y ? ny : nh;
+  const size_t stride = (size_t)(is_y ? by : (int)gridDim.x - by) * 256;
   unsigned long long h = 0ull;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+  for (size_t i = (size_t)b * 256 + threadIdx.x; i < len; i += stride)
     h += (unsigned long long)__float_as_uint(v[i]) * (2ull * i + 1ull);
   for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = h;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(out, red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) fp[(is_y ? 0 : kFpParts) + b] = red[0] + red[1] + red[2] + red[3];
+  if (blockIdx.x == 0) {
+    float* dst = reinterpret_cast<float*>(fp + 2 * kFpParts);
+    for (int i = threadIdx.x; i < 6 * n; i += 256) dst[i] = atoms[i];
+  }
 }
 
 // ------------------------------------------------------------------ render
@@ -835,11 +849,19 @@ hipError_t launch_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* ak
   return hipGetLastError();
 }
 
-hipError_t launch_hash(const float* v, size_t n, unsigned long long* out, hipStream_t st) {
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 256) blocks = 256;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_hash, dim3((unsigned)blocks), dim3(256), 0, st, v, n, out);
+static int fp_blocks(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)std::max<size_t>(1, std::min<size_t>(b, kFpParts));
+}
+
+hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t nh,
+                               const sfw_atom* atoms, int n, unsigned long long* fp, int* by_out,
+                               int* bh_out, hipStream_t st) {
+  const int by = fp_blocks(ny), bh = fp_blocks(nh);
+  hipLaunchKernelGGL(k_fingerprints, dim3((unsigned)(by + bh)), dim3(256), 0, st, y, ny, by, H,
+                     nh, reinterpret_cast<const float*>(atoms), atoms ? n : 0, fp);
+  *by_out = by;
+  *bh_out = bh;
   return hipGetLastError();
 }
 

@@ -92,11 +92,27 @@ int nnqp(const std::vector<double>& G, const std::vector<double>& c, int k,
          std::vector<double>& w) {
   w.assign(k, 0.0);
   if (k == 0) return SFW_OK;
+  std::vector<double> z;
+  {
+    // Supports usually keep every weight positive (zero-weight atoms are pruned), so try the
+    // solution of the full system first: if it is strictly positive, the gradient vanishes on
+    // every coordinate, the KKT conditions of the non-negative problem hold and, the
+    // objective being strictly convex, it is the minimiser.
+    std::vector<int> all(k);
+    for (int i = 0; i < k; ++i) all[i] = i;
+    solve_passive(G, c, k, all, z);
+    bool positive = true;
+    for (int i = 0; i < k; ++i)
+      if (!(z[i] > 0.0)) positive = false;
+    if (positive) {
+      w = z;
+      return SFW_OK;
+    }
+  }
   std::vector<char> passive(k, 0);
   double scale = 0.0;
   for (int i = 0; i < k; ++i) scale = std::max(scale, std::fabs(c[i]));
   const double tol = 1e-13 * std::max(scale, 1e-300);
-  std::vector<double> z;
   for (int outer = 0; outer < 4 * k + 20; ++outer) {
     // gradient of 1/2 w'Gw - c'w
     int jbest = -1;
