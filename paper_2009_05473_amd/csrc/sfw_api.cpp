@@ -168,7 +168,10 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
     const double* t = thetas + 5 * i;
     hk[i] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
   }
-  SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
+  if (n <= kAtomArgs)  // small batches travel as kernel arguments (no copy command)
+    SFW_HIP(launch_store_atoms(hk, n, ws->ak, ws->stream));
+  else
+    SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
   GradPlan gp = plan_grad(vol, n);
   {
     ProfScope ps(ws, kProfEtaGrad);
@@ -291,12 +294,14 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
     for (int pi = 0; pi < npairs; ++pi) {
       const int sa = 2 * pi, sb = 2 * pi + 1;
       auto kz_of = [&](int s) { return plan_conv(vol, 2 * rad[s] + 1, 2 * rad[s] + 1, 2 * rad[s] + 1).kzp; };
-      float2* dst = ws->fft_pairs + (size_t)pi * ws->fft_cap;  // stride of the allocation
+      // full spectrum in the work array, then its octant into the dense pair table
+      float2* full = ws->fft_work;
       SFW_HIP(fft_scatter_pair(pl, ws->lut + off[sa], rad[sa], kz_of(sa),
                                sb < ns * nd ? ws->lut + off[sb] : nullptr,
-                               sb < ns * nd ? rad[sb] : 0, sb < ns * nd ? kz_of(sb) : 0, dst,
+                               sb < ns * nd ? rad[sb] : 0, sb < ns * nd ? kz_of(sb) : 0, full,
                                ws->stream));
-      SFW_HIP(fft_forward_c2c(pl, dst, ws->stream));
+      SFW_HIP(fft_forward_c2c(pl, full, ws->stream));
+      SFW_HIP(fft_pack_octant(pl, full, ws->fft_pairs + (size_t)pi * pl.oct, ws->stream));
     }
     SFW_HIP(hipStreamSynchronize(ws->stream));
     ws->fft = pl;
@@ -437,11 +442,12 @@ int lasso_check_inputs(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
 
 // Weights-only LASSO for unit-weight atoms thetas [n][5] (host, float32 values as the device
 // sees them); the PSF operands for the forward convolution must be prepared and the cache
-// validated for (y, H) (lasso_check_inputs). Columns and Gram rows of the longest prefix of
+// validated for (y, H) (lasso_check_inputs). ak_ready: the unit-weight atom constants of all
+// n atoms are already in ws->ak (else they are uploaded for the atoms past the cached prefix). Columns and Gram rows of the longest prefix of
 // atoms identical to the cached list are reused; the rest are computed on the GPU (one
 // synchronisation for the Gram readback).
 int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
-             double lambda, const float* thetas, int n, std::vector<double>& w) {
+             double lambda, const float* thetas, int n, std::vector<double>& w, bool ak_ready) {
   w.assign(n, 0.0);
   if (n == 0) return SFW_OK;
   const int M = ws->max_atoms;
@@ -456,13 +462,15 @@ int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
                                    5 * sizeof(float)) == 0)
     ++pre;
   if (pre < n) {
-    AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin + ws->hp_stage);
-    for (int i = pre; i < n; ++i) {
-      const float* t = thetas + 5 * (size_t)i;
-      hk[i - pre] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
+    if (!ak_ready) {
+      AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin + ws->hp_stage);
+      for (int i = pre; i < n; ++i) {
+        const float* t = thetas + 5 * (size_t)i;
+        hk[i - pre] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
+      }
+      SFW_HIP(hipMemcpyAsync(ws->ak + pre, hk, sizeof(AtomK) * (n - pre), hipMemcpyHostToDevice,
+                             ws->stream));
     }
-    SFW_HIP(hipMemcpyAsync(ws->ak + pre, hk, sizeof(AtomK) * (n - pre), hipMemcpyHostToDevice,
-                           ws->stream));
     int rc = op_columns(ws, p, vol, pre, n);
     if (rc) return rc;
     for (int i = pre; i < n; ++i) {
@@ -627,7 +635,10 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ALLOC(ws->dpart, ws->dpart_cap * 8, "float64 partials");
     const size_t dres_n = (size_t)(na + 2) * (na + 2) + 8 * (size_t)(na + 2) + 64;
     ALLOC(ws->dres, dres_n * 8, "float64 results");
-    ws->apart_cap = cblocks * SFW_MAX_GRID * SFW_MAX_GRID;
+    // argmax partials: per table kernel, the blocks of a direct certificate convolution or of
+    // the last Fourier pass (at least 8 lines of one plane per block)
+    const size_t fblocks = (size_t)((vol_max.ny + 7) / 8) * vol_max.nz;
+    ws->apart_cap = std::max(cblocks, fblocks) * SFW_MAX_GRID * SFW_MAX_GRID;
     ALLOC(ws->apart, ws->apart_cap * sizeof(ArgPart), "argmax partials");
     ALLOC(ws->best, sizeof(sfw_argmax) * 2, "argmax");
     ALLOC(ws->hashbuf, (2 * (size_t)kFpParts + 3 * (size_t)na) * 8, "fingerprints");
@@ -856,7 +867,8 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
     if (n == 0) return SFW_OK;
     if (!atoms || !w_out) return fail(SFW_EINVAL, "atoms or w_out is NULL");
     PsfPlan p = plan_psf(vol, psf);
-    rc = prep_psf(ws, H, p, true, false);
+    // PSF operands and the unit-weight constants of every atom, from the device atoms
+    rc = prep_all(ws, H, p, true, false, atoms, n, true);
     if (rc) return rc;
     // one synchronisation brings back the atoms and the fingerprints of y and H
     int by = 0, bh = 0;
@@ -878,7 +890,7 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
         return fail(SFW_EINVAL, "atoms: sigma and d must be > 0");
     }
     std::vector<double> w;
-    rc = op_lasso(ws, p, vol, y, lambda, th.data(), n, w);
+    rc = op_lasso(ws, p, vol, y, lambda, th.data(), n, w, true);
     if (rc) return rc;
     // stream-ordered upload from a pinned region no other call writes before synchronising
     double* hw = ws->hpin + ws->hp_w;

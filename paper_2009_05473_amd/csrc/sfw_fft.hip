@@ -354,15 +354,17 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_argmax(
 // Lines along one axis with element stride `istride`; a block owns B adjacent x columns at
 // one outer coordinate o (address o * ostride + i * istride + x) of batch entry blockIdx.z
 // (arrays offset by blockIdx.z times their batch stride). Reads i < n_in (zero beyond), writes
-// i < n_out. MUL: input = conj(data * mulp) (first inverse pass).
-template <bool MUL>
+// i < n_out. OCT (first inverse pass, lines along z, o = y): the input is conj(src * P) with P
+// the pair spectrum of batch entry p = blockIdx.z read from its octant (hx x hy x hz,
+// mulp + p * mul_bstride).
+template <bool OCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_strided(
     const float2* __restrict__ src, size_t src_bstride, const float2* __restrict__ mulp,
     size_t mul_bstride, float2* __restrict__ dst, size_t dst_bstride, FftAxis ax, int ncols,
-    size_t istride, size_t ostride, int n_in, int n_out, int lgB) {
+    size_t istride, size_t ostride, int n_in, int n_out, int lgB, int hx, int hy, int Ny) {
   extern __shared__ float2 sm[];
   src += blockIdx.z * src_bstride;
-  if (MUL) mulp += blockIdx.z * mul_bstride;
+  if (OCT) mulp += blockIdx.z * mul_bstride;
   dst += blockIdx.z * dst_bstride;
   const int L = ax.n, LS = line_pitch(L), B = 1 << lgB;
   float2* a = sm;
@@ -371,15 +373,19 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_strided(
   const int x0 = blockIdx.x * B;
   const size_t obase = (size_t)blockIdx.y * ostride + x0;
   const int cols = min(B, ncols - x0);
+  const int my = OCT ? (2 * (int)blockIdx.y <= Ny ? (int)blockIdx.y : Ny - (int)blockIdx.y) : 0;
   fill_lds(
       B * L,
       [&](int e) {
         const int i = e >> lgB, c = e & (B - 1);  // consecutive threads: consecutive columns
         const bool ok = c < cols && i < n_in;
-        const size_t g = obase + (ok ? (size_t)i * istride + c : 0);
-        float2 v = src[g];
-        if (MUL) {
-          v = cmul(v, mulp[g]);
+        float2 v = src[obase + (ok ? (size_t)i * istride + c : 0)];
+        if (OCT) {
+          const int x = x0 + (ok ? c : 0);
+          const int mx = 2 * x <= ncols ? x : ncols - x;
+          const int iz = ok ? i : 0;
+          const int mz = 2 * iz <= L ? iz : L - iz;
+          v = cmul(v, mulp[((size_t)mz * hy + my) * hx + mx]);
           v.y = -v.y;
         }
         return ok ? v : make_float2(0.f, 0.f);
@@ -393,6 +399,19 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_strided(
     const int i = e >> lgB, c = e & (B - 1);
     if (c < cols) dst[obase + (size_t)i * istride + c] = r[c * LS + i];
   }
+}
+
+// Packs the k <= N / 2 octant of a full pair spectrum (x pitch px) densely, x fastest.
+__global__ __launch_bounds__(256) void k_fft_pack_octant(const float2* __restrict__ full, int px,
+                                                         int Ny, int hx, int hy, int hz,
+                                                         float2* __restrict__ oct) {
+  const size_t n = (size_t)hx * hy * hz;
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int x = (int)(e % hx);
+  const int y = (int)((e / hx) % hy);
+  const int z = (int)(e / ((size_t)hx * hy));
+  oct[e] = full[((size_t)z * Ny + y) * px + x];
 }
 
 // Kernel pair (a, b) of the table, wrapped around the origin of the Nx x Ny x Nz grid (x pitch
@@ -449,10 +468,23 @@ static bool make_axis_plan(int n, FftAxis& ax) {
       ax.radix[ax.nstage++] = p;
       t /= p;
     }
+  if (!fft_fixed_plan(n, &ax.r1, &ax.r2)) ax.r1 = ax.r2 = 0;
   return t == 1;
 }
 
-// log2 of the lines per block and the dynamic LDS bytes of a pass over lines of length L.
+// Smallest transform length >= nmin: a fixed-length (two-stage) size when it is at most a
+// quarter longer than the smallest 2-3-5-smooth size, whose generic passes cost about twice
+// as much per element; else the smooth size.
+static int choose_length(int nmin) {
+  const int g = good_size(nmin);
+  int r1 = 0, r2 = 0;
+  for (int L = nmin; L <= g + g / 4; ++L)
+    if (fft_fixed_plan(L, &r1, &r2)) return L;
+  return g;
+}
+
+// log2 of the lines per block and the dynamic LDS bytes of a generic pass over lines of
+// length L.
 static int fft_lg_lines(int L, bool strided) {
   int lg = strided ? 4 : 3;
   while (lg > 0 && ((size_t)2 * ((size_t)1 << lg) * (L | 1) + L) * sizeof(float2) > 48 * 1024)
@@ -465,10 +497,14 @@ static size_t fft_lds(int L, int lg) { return ((size_t)2 * ((size_t)1 << lg) * (
 // wrapped table kernel from overlapping itself; both make the circular correlation equal the
 // linear one on the volume.
 bool fft_plan_cert(sfw_dims vol, int rmax, FftPlan& pl) {
-  pl.nx = good_size(std::max(vol.nx + rmax, 2 * rmax + 1));
-  pl.ny = good_size(std::max(vol.ny + rmax, 2 * rmax + 1));
-  pl.nz = good_size(std::max(vol.nz + rmax, 2 * rmax + 1));
+  pl.nx = choose_length(std::max(vol.nx + rmax, 2 * rmax + 1));
+  pl.ny = choose_length(std::max(vol.ny + rmax, 2 * rmax + 1));
+  pl.nz = choose_length(std::max(vol.nz + rmax, 2 * rmax + 1));
   pl.px = (pl.nx + 15) & ~15;
+  pl.hx = pl.nx / 2 + 1;
+  pl.hy = pl.ny / 2 + 1;
+  pl.hz = pl.nz / 2 + 1;
+  pl.oct = (size_t)pl.hx * pl.hy * pl.hz;
   if (pl.nx > kFftMaxLen || pl.ny > kFftMaxLen || pl.nz > kFftMaxLen) return false;
   return make_axis_plan(pl.nx, pl.ax[0]) && make_axis_plan(pl.ny, pl.ax[1]) &&
          make_axis_plan(pl.nz, pl.ax[2]);
@@ -482,6 +518,20 @@ void fft_twiddles(int n, std::vector<float2>& tw) {
   }
 }
 
+// One strided pass (lines along y or z): fixed-length kernel when the axis has one.
+static hipError_t strided_pass(const FftAxis& ax, unsigned outer, unsigned batch, hipStream_t st,
+                               const float2* src, size_t src_b, float2* dst, size_t dst_b,
+                               int ncols, size_t istride, size_t ostride, int n_in, int n_out) {
+  if (ax.r1 > 0)
+    return fx_strided(ax.n, dim3((ncols + kFxLines - 1) / kFxLines, outer, batch), st, src, src_b,
+                      dst, dst_b, ax.tw, ncols, istride, ostride, n_in, n_out);
+  const int g = fft_lg_lines(ax.n, true), B = 1 << g;
+  hipLaunchKernelGGL(k_fft_strided<false>, dim3((ncols + B - 1) / B, outer, batch),
+                     dim3(kFftThreads), fft_lds(ax.n, g), st, src, src_b, nullptr, (size_t)0, dst,
+                     dst_b, ax, ncols, istride, ostride, n_in, n_out, g, 0, 0, 0);
+  return hipGetLastError();
+}
+
 // Forward 3D transform of a complex array on the full grid (used for the table spectra).
 hipError_t fft_forward_c2c(const FftPlan& pl, float2* data, hipStream_t st) {
   const int gx = fft_lg_lines(pl.nx, false), Bx = 1 << gx;
@@ -489,17 +539,11 @@ hipError_t fft_forward_c2c(const FftPlan& pl, float2* data, hipStream_t st) {
                      fft_lds(pl.nx, gx), st, data, pl.ax[0], pl.ny, pl.px, gx);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int gy = fft_lg_lines(pl.ny, true), By = 1 << gy;
-  hipLaunchKernelGGL(k_fft_strided<false>, dim3((pl.nx + By - 1) / By, pl.nz), dim3(kFftThreads),
-                     fft_lds(pl.ny, gy), st, data, (size_t)0, nullptr, (size_t)0, data, (size_t)0, pl.ax[1], pl.nx,
-                     (size_t)pl.px, (size_t)pl.px * pl.ny, pl.ny, pl.ny, gy);
-  e = hipGetLastError();
+  e = strided_pass(pl.ax[1], pl.nz, 1, st, data, 0, data, 0, pl.nx, (size_t)pl.px,
+                   (size_t)pl.px * pl.ny, pl.ny, pl.ny);
   if (e != hipSuccess) return e;
-  const int gz = fft_lg_lines(pl.nz, true), Bz = 1 << gz;
-  hipLaunchKernelGGL(k_fft_strided<false>, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(kFftThreads),
-                     fft_lds(pl.nz, gz), st, data, (size_t)0, nullptr, (size_t)0, data, (size_t)0, pl.ax[2], pl.nx,
-                     (size_t)pl.px * pl.ny, (size_t)pl.px, pl.nz, pl.nz, gz);
-  return hipGetLastError();
+  return strided_pass(pl.ax[2], pl.ny, 1, st, data, 0, data, 0, pl.nx, (size_t)pl.px * pl.ny,
+                      (size_t)pl.px, pl.nz, pl.nz);
 }
 
 hipError_t fft_scatter_pair(const FftPlan& pl, const float* ka, int ra, int kzpa, const float* kb,
@@ -515,52 +559,65 @@ hipError_t fft_scatter_pair(const FftPlan& pl, const float* ka, int ra, int kzpa
 // Qhat = FFT(q) with q zero-padded from the volume to the grid.
 hipError_t fft_forward_volume(const FftPlan& pl, const float* q, sfw_dims vol, float2* qhat,
                               hipStream_t st) {
-  const int gx = fft_lg_lines(pl.nx, false), Bx = 1 << gx;
-  hipLaunchKernelGGL(k_fft_x_real, dim3((vol.ny + Bx - 1) / Bx, vol.nz), dim3(kFftThreads),
-                     fft_lds(pl.nx, gx), st, q, vol.nx, vol.ny, vol.nz, pl.ax[0], pl.ny, pl.px,
-                     gx, qhat);
-  hipError_t e = hipGetLastError();
+  hipError_t e;
+  if (pl.ax[0].r1 > 0) {
+    e = fx_x_real(pl.nx, dim3((vol.ny + kFxLines - 1) / kFxLines, vol.nz), st, q, vol.nx, vol.ny,
+                  pl.ax[0].tw, pl.ny, pl.px, qhat);
+  } else {
+    const int gx = fft_lg_lines(pl.nx, false), Bx = 1 << gx;
+    hipLaunchKernelGGL(k_fft_x_real, dim3((vol.ny + Bx - 1) / Bx, vol.nz), dim3(kFftThreads),
+                       fft_lds(pl.nx, gx), st, q, vol.nx, vol.ny, vol.nz, pl.ax[0], pl.ny, pl.px,
+                       gx, qhat);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) return e;
-  const int gy = fft_lg_lines(pl.ny, true), By = 1 << gy;
-  hipLaunchKernelGGL(k_fft_strided<false>, dim3((pl.nx + By - 1) / By, vol.nz), dim3(kFftThreads),
-                     fft_lds(pl.ny, gy), st, qhat, (size_t)0, nullptr, (size_t)0, qhat, (size_t)0, pl.ax[1], pl.nx,
-                     (size_t)pl.px, (size_t)pl.px * pl.ny, vol.ny, pl.ny, gy);
-  e = hipGetLastError();
+  e = strided_pass(pl.ax[1], vol.nz, 1, st, qhat, 0, qhat, 0, pl.nx, (size_t)pl.px,
+                   (size_t)pl.px * pl.ny, vol.ny, pl.ny);
   if (e != hipSuccess) return e;
-  const int gz = fft_lg_lines(pl.nz, true), Bz = 1 << gz;
-  hipLaunchKernelGGL(k_fft_strided<false>, dim3((pl.nx + Bz - 1) / Bz, pl.ny), dim3(kFftThreads),
-                     fft_lds(pl.nz, gz), st, qhat, (size_t)0, nullptr, (size_t)0, qhat, (size_t)0, pl.ax[2], pl.nx,
-                     (size_t)pl.px * pl.ny, (size_t)pl.px, vol.nz, pl.nz, gz);
-  return hipGetLastError();
+  return strided_pass(pl.ax[2], pl.ny, 1, st, qhat, 0, qhat, 0, pl.nx, (size_t)pl.px * pl.ny,
+                      (size_t)pl.px, vol.nz, pl.nz);
 }
 
 int fft_argmax_blocks(const FftPlan& pl, sfw_dims vol) {
-  const int Bx = 1 << fft_lg_lines(pl.nx, false);
+  const int Bx = pl.ax[0].r1 > 0 ? kFxLines : 1 << fft_lg_lines(pl.nx, false);
   return ((vol.ny + Bx - 1) / Bx) * vol.nz;
 }
 
+hipError_t fft_pack_octant(const FftPlan& pl, const float2* full, float2* oct, hipStream_t st) {
+  hipLaunchKernelGGL(k_fft_pack_octant, dim3((unsigned)((pl.oct + 255) / 256)), dim3(256), 0, st,
+                     full, pl.px, pl.ny, pl.hx, pl.hy, pl.hz, oct);
+  return hipGetLastError();
+}
+
 // eta_{2p} + i eta_{2p+1} = IFFT(Qhat * P_p) on the volume for every pair p < npairs at once
-// (pair spectra and work arrays at a stride of `bstride` elements), with the block maxima of
-// every slice.
+// (pair spectra as octants at a stride of pl.oct, work arrays at a stride of `bstride`
+// elements), with the block maxima of every slice.
 hipError_t fft_inverse_pairs(const FftPlan& pl, const float2* qhat, const float2* pairs,
                              float2* work, size_t bstride, int nslices, sfw_dims vol,
                              float scale, float* eta_out, ArgPart* apart, int nblk,
                              hipStream_t st) {
   const unsigned np = (unsigned)((nslices + 1) / 2);
-  const int gz = fft_lg_lines(pl.nz, true), Bz = 1 << gz;
-  hipLaunchKernelGGL(k_fft_strided<true>, dim3((pl.nx + Bz - 1) / Bz, pl.ny, np),
-                     dim3(kFftThreads), fft_lds(pl.nz, gz), st, qhat, (size_t)0, pairs, bstride,
-                     work, bstride, pl.ax[2], pl.nx, (size_t)pl.px * pl.ny, (size_t)pl.px, pl.nz,
-                     vol.nz, gz);
-  hipError_t e = hipGetLastError();
+  hipError_t e;
+  if (pl.ax[2].r1 > 0) {
+    e = fx_z_inverse(pl.nz, dim3((pl.nx + kFxLines - 1) / kFxLines, pl.ny), st, qhat, pairs,
+                     pl.oct, pl.hx, pl.hy, work, bstride, pl.ax[2].tw, pl.nx, pl.ny, pl.px, vol.nz,
+                     (int)np);
+  } else {
+    const int g = fft_lg_lines(pl.nz, true), B = 1 << g;
+    hipLaunchKernelGGL(k_fft_strided<true>, dim3((pl.nx + B - 1) / B, pl.ny, np),
+                       dim3(kFftThreads), fft_lds(pl.nz, g), st, qhat, (size_t)0, pairs, pl.oct,
+                       work, bstride, pl.ax[2], pl.nx, (size_t)pl.px * pl.ny, (size_t)pl.px,
+                       pl.nz, vol.nz, g, pl.hx, pl.hy, pl.ny);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) return e;
-  const int gy = fft_lg_lines(pl.ny, true), By = 1 << gy;
-  hipLaunchKernelGGL(k_fft_strided<false>, dim3((pl.nx + By - 1) / By, vol.nz, np),
-                     dim3(kFftThreads), fft_lds(pl.ny, gy), st, work, bstride, nullptr, (size_t)0,
-                     work, bstride, pl.ax[1], pl.nx, (size_t)pl.px, (size_t)pl.px * pl.ny, pl.ny,
-                     vol.ny, gy);
-  e = hipGetLastError();
+  e = strided_pass(pl.ax[1], vol.nz, np, st, work, bstride, work, bstride, pl.nx, (size_t)pl.px,
+                   (size_t)pl.px * pl.ny, pl.ny, vol.ny);
   if (e != hipSuccess) return e;
+  if (pl.ax[0].r1 > 0)
+    return fx_x_argmax(pl.nx, dim3((vol.ny + kFxLines - 1) / kFxLines, vol.nz, np), st, work,
+                       bstride, vol.nx, vol.ny, vol.nz, pl.ax[0].tw, pl.ny, pl.px, scale,
+                       nslices, eta_out, apart, nblk);
   const int gx = fft_lg_lines(pl.nx, false), Bx = 1 << gx;
   hipLaunchKernelGGL(k_fft_x_argmax, dim3((vol.ny + Bx - 1) / Bx, vol.nz, np), dim3(kFftThreads),
                      fft_lds(pl.nx, gx), st, work, bstride, vol.nx, vol.ny, vol.nz, pl.ax[0],

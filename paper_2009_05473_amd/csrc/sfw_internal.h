@@ -55,17 +55,24 @@ constexpr int conv_tile_lzp(int kz) {
 
 // One axis of a separable FFT: length n = prod(radix), twiddles tw[m] = exp(-2 pi i m / n).
 constexpr int kFpParts = 256;  // fingerprint partials per array
+constexpr int kAtomArgs = 8;   // atom constants passed by value in one launch
 constexpr int kFftMaxStages = 16;
 constexpr int kFftMaxLen = 1024;
+constexpr int kFxLines = 16;  // lines (or columns) per block of the fixed-length passes
 struct FftAxis {
   int n = 1;
   int nstage = 0;
   int radix[kFftMaxStages] = {0};
+  int r1 = 0, r2 = 0;  // two-stage fixed-length plan (n = r1 * r2), 0 if none
   const float2* tw = nullptr;
 };
 struct FftPlan {
   int nx = 0, ny = 0, nz = 0;
   int px = 0;  // x pitch of the spectrum arrays (nx rounded up to 16)
+  // The table kernels are real and even in every axis, so are their spectra: one octant
+  // (k <= N / 2 on each axis, hx x hy x hz, x fastest) holds each pair spectrum.
+  int hx = 0, hy = 0, hz = 0;
+  size_t oct = 0;
   FftAxis ax[3];
 };
 
@@ -134,7 +141,7 @@ struct sfw_workspace {
   float2* fft_tw = nullptr;      // [nx + ny + nz]
   float2* fft_qhat = nullptr;    // [N]
   float2* fft_work = nullptr;    // [npairs][N]
-  float2* fft_pairs = nullptr;   // [npairs][N]
+  float2* fft_pairs = nullptr;   // [npairs][oct] pair spectra (octants, dense)
   size_t fft_cap = 0;            // complex elements per array
   int fft_npairs_cap = 0;
 
@@ -228,6 +235,7 @@ hipError_t launch_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* ak
                        sfw_dims psf, bool mfma, int kzp, bool fwd, bool adj, float* out_fwd,
                        float* out_adj, hipStream_t st);
 // atomicAdd of the fingerprint of v[0..n) into *out (zero it first).
+hipError_t launch_store_atoms(const AtomK* host, int n, AtomK* dst, hipStream_t st);
 hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t nh,
                                const sfw_atom* atoms, int n, unsigned long long* fp, int* by_out,
                                int* bh_out, hipStream_t st);
@@ -281,6 +289,20 @@ hipError_t fft_forward_c2c(const FftPlan& pl, float2* data, hipStream_t st);
 hipError_t fft_forward_volume(const FftPlan& pl, const float* q, sfw_dims vol, float2* qhat,
                               hipStream_t st);
 int fft_argmax_blocks(const FftPlan& pl, sfw_dims vol);
+// fixed-length passes (sfw_fft_fixed.hip)
+bool fft_fixed_plan(int L, int* r1, int* r2);
+hipError_t fx_strided(int L, dim3 grid, hipStream_t st, const float2* src, size_t src_b,
+                      float2* dst, size_t dst_b, const float2* tw, int ncols, size_t istride,
+                      size_t ostride, int n_in, int n_out);
+hipError_t fx_z_inverse(int L, dim3 grid, hipStream_t st, const float2* qhat, const float2* oct,
+                        size_t oct_b, int hx, int hy, float2* work, size_t work_b,
+                        const float2* tw, int Nx, int Ny, int px, int n_out, int npairs);
+hipError_t fx_x_real(int L, dim3 grid, hipStream_t st, const float* q, int nx, int ny,
+                     const float2* tw, int Ny, int px, float2* out);
+hipError_t fx_x_argmax(int L, dim3 grid, hipStream_t st, const float2* work, size_t work_b,
+                       int nx, int ny, int nz, const float2* tw, int Ny, int px, float scale,
+                       int nslices, float* eta_out, ArgPart* apart, int nblk);
+hipError_t fft_pack_octant(const FftPlan& pl, const float2* full, float2* oct, hipStream_t st);
 hipError_t fft_inverse_pairs(const FftPlan& pl, const float2* qhat, const float2* pairs,
                              float2* work, size_t bstride, int nslices, sfw_dims vol,
                              float scale, float* eta_out, ArgPart* apart, int nblk,

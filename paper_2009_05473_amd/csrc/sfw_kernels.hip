@@ -7,6 +7,8 @@
 // for the convolutions, and wavefront DPP reductions for the per-atom gradient sums.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include <cfloat>
 #include <cmath>
 
@@ -141,6 +143,15 @@ __global__ __launch_bounds__(256) void k_fingerprints(const float* __restrict__ 
     float* dst = reinterpret_cast<float*>(fp + 2 * kFpParts);
     for (int i = threadIdx.x; i < 6 * n; i += 256) dst[i] = atoms[i];
   }
+}
+
+// Stores up to kAtomArgs atom constants carried in the kernel arguments.
+struct AtomArgs {
+  AtomK a[kAtomArgs];
+};
+__global__ void k_store_atoms(AtomArgs args, int n, AtomK* __restrict__ dst) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = args.a[i];
 }
 
 // ------------------------------------------------------------------ render
@@ -846,6 +857,16 @@ hipError_t launch_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* ak
   hipLaunchKernelGGL(k_prep, grid, dim3(256), 0, st, atoms, n, unit_weight ? 1 : 0, ak, H, psf.nx,
                      psf.ny, psf.nz, mfma ? 1 : 0, steps, kzp, (fwd && npsf) ? 1 : 0,
                      (adj && npsf) ? 1 : 0, out_fwd, out_adj);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_atoms(const AtomK* host, int n, AtomK* dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (n > kAtomArgs) return hipErrorInvalidValue;
+  AtomArgs args;
+  std::memset(&args, 0, sizeof(args));
+  std::memcpy(args.a, host, sizeof(AtomK) * n);
+  hipLaunchKernelGGL(k_store_atoms, dim3(1), dim3(64), 0, st, args, n, dst);
   return hipGetLastError();
 }
 

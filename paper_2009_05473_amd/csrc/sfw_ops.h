@@ -34,7 +34,8 @@ AtomK make_atomk(double w, double mx, double my, double mz, double sigma, double
 int lasso_check_inputs(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
                        const float* H);
 int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
-             double lambda, const float* thetas, int n, std::vector<double>& w);
+             double lambda, const float* thetas, int n, std::vector<double>& w,
+             bool ak_ready = false);
 // out = H * in (adjoint = false) or correlation with H (adjoint = true); epilogue as launch_conv.
 int conv_psf(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjoint,
              const float* in, float* out, int epi, const float* yobs, int prof_kind);

@@ -30,142 +30,7 @@ double secs(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double>(b - a).count();
 }
 
-// Cholesky of the s x s matrix A (row-major, lower factor in place). False if not SPD.
-bool cholesky(std::vector<double>& A, int s) {
-  for (int j = 0; j < s; ++j) {
-    double d = A[(size_t)j * s + j];
-    for (int k = 0; k < j; ++k) d -= A[(size_t)j * s + k] * A[(size_t)j * s + k];
-    if (!(d > 0.0)) return false;
-    d = std::sqrt(d);
-    A[(size_t)j * s + j] = d;
-    for (int i = j + 1; i < s; ++i) {
-      double v = A[(size_t)i * s + j];
-      for (int k = 0; k < j; ++k) v -= A[(size_t)i * s + k] * A[(size_t)j * s + k];
-      A[(size_t)i * s + j] = v / d;
-    }
-  }
-  return true;
-}
-
-void chol_solve(const std::vector<double>& L, int s, std::vector<double>& b) {
-  for (int i = 0; i < s; ++i) {
-    double v = b[i];
-    for (int k = 0; k < i; ++k) v -= L[(size_t)i * s + k] * b[k];
-    b[i] = v / L[(size_t)i * s + i];
-  }
-  for (int i = s - 1; i >= 0; --i) {
-    double v = b[i];
-    for (int k = i + 1; k < s; ++k) v -= L[(size_t)k * s + i] * b[k];
-    b[i] = v / L[(size_t)i * s + i];
-  }
-}
-
-// z_P = G_PP^{-1} c_P (ridge added if G_PP is singular, as duplicate atoms make it).
-void solve_passive(const std::vector<double>& G, const std::vector<double>& c, int k,
-                   const std::vector<int>& P, std::vector<double>& z) {
-  const int s = (int)P.size();
-  std::vector<double> A((size_t)s * s), b(s);
-  double tr = 0.0;
-  for (int i = 0; i < s; ++i) {
-    for (int j = 0; j < s; ++j) A[(size_t)i * s + j] = G[(size_t)P[i] * k + P[j]];
-    b[i] = c[P[i]];
-    tr += A[(size_t)i * s + i];
-  }
-  std::vector<double> L = A;
-  if (!cholesky(L, s)) {
-    L = A;
-    const double ridge = 1e-12 * tr / std::max(s, 1);
-    for (int i = 0; i < s; ++i) L[(size_t)i * s + i] += ridge;
-    if (!cholesky(L, s)) {
-      for (int i = 0; i < s; ++i) L[(size_t)i * s + i] += 1e-6 * tr / std::max(s, 1);
-      cholesky(L, s);
-    }
-  }
-  chol_solve(L, s, b);
-  z.assign(k, 0.0);
-  for (int i = 0; i < s; ++i) z[P[i]] = b[i];
-}
-
 }  // namespace
-
-int nnqp(const std::vector<double>& G, const std::vector<double>& c, int k,
-         std::vector<double>& w) {
-  w.assign(k, 0.0);
-  if (k == 0) return SFW_OK;
-  std::vector<double> z;
-  {
-    // Supports usually keep every weight positive (zero-weight atoms are pruned), so try the
-    // solution of the full system first: if it is strictly positive, the gradient vanishes on
-    // every coordinate, the KKT conditions of the non-negative problem hold and, the
-    // objective being strictly convex, it is the minimiser.
-    std::vector<int> all(k);
-    for (int i = 0; i < k; ++i) all[i] = i;
-    solve_passive(G, c, k, all, z);
-    bool positive = true;
-    for (int i = 0; i < k; ++i)
-      if (!(z[i] > 0.0)) positive = false;
-    if (positive) {
-      w = z;
-      return SFW_OK;
-    }
-  }
-  std::vector<char> passive(k, 0);
-  double scale = 0.0;
-  for (int i = 0; i < k; ++i) scale = std::max(scale, std::fabs(c[i]));
-  const double tol = 1e-13 * std::max(scale, 1e-300);
-  for (int outer = 0; outer < 4 * k + 20; ++outer) {
-    // gradient of 1/2 w'Gw - c'w
-    int jbest = -1;
-    double gbest = -tol;
-    for (int i = 0; i < k; ++i) {
-      if (passive[i]) continue;
-      double g = -c[i];
-      for (int j = 0; j < k; ++j) g += G[(size_t)i * k + j] * w[j];
-      if (g < gbest) {
-        gbest = g;
-        jbest = i;
-      }
-    }
-    if (jbest < 0) return SFW_OK;
-    passive[jbest] = 1;
-    for (int inner = 0; inner < 4 * k + 20; ++inner) {
-      std::vector<int> P;
-      for (int i = 0; i < k; ++i)
-        if (passive[i]) P.push_back(i);
-      solve_passive(G, c, k, P, z);
-      bool feasible = true;
-      for (int i : P)
-        if (!(z[i] > 0.0)) feasible = false;
-      if (feasible) {
-        w = z;
-        break;
-      }
-      double alpha = 1.0;
-      for (int i : P)
-        if (!(z[i] > 0.0)) {
-          const double den = w[i] - z[i];
-          const double a = den > 0.0 ? w[i] / den : 0.0;
-          alpha = std::min(alpha, a);
-        }
-      for (int i = 0; i < k; ++i) w[i] += alpha * (z[i] - w[i]);
-      bool moved = false;
-      for (int i : P)
-        if (w[i] <= 1e-15 * std::max(1.0, std::fabs(z[i]))) {
-          passive[i] = 0;
-          w[i] = 0.0;
-          moved = true;
-        }
-      if (!moved) {  // numerically stuck: drop the most negative member
-        int worst = P[0];
-        for (int i : P)
-          if (z[i] < z[worst]) worst = i;
-        passive[worst] = 0;
-        w[worst] = 0.0;
-      }
-    }
-  }
-  return SFW_OK;
-}
 
 namespace {
 
