@@ -52,7 +52,11 @@ GRAD_SLOTS_PER_PAIR = 12 + 3 * 4    # 12 VALU + log2, exp2, exp2
 # each scaled by the same counter's reading for the known 256 MiB device copy at the end.
 # The record holds for the kernel source it was taken on (sha256 of KERNEL_SOURCE).
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_05473_amd", "csrc", "sfw_kernels.hip")
-CONV_TRAFFIC = None
+CONV_TRAFFIC = {
+    "fetch_kib": 7253.0, "write_kib": 4096.0,            # k_conv_mfma<21, 0>, per dispatch
+    "copy_mib": 256, "copy_fetch_kib": 131086.7, "copy_write_kib": 262144.0,
+    "source_sha256": "cd061364d4c9fd41ea3a966c9333b88ed97c234e481c1ff617de65843932d3e5",
+}
 
 
 def conv_traffic():

@@ -212,6 +212,8 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
   key.push_back((float)vol.nx);
   key.push_back((float)vol.ny);
   key.push_back((float)vol.nz);
+  const char* fenv = std::getenv("SFW_FFT");  // transform-length policy (a test switch)
+  key.push_back(fenv && std::strcmp(fenv, "generic") == 0 ? 1.f : 0.f);
   if (key == ws->lut_key && ws->lut) return SFW_OK;
   ws->lut_key.clear();
   ws->fft_ready = false;

@@ -13,6 +13,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 
 #include "sfw_internal.h"
 
@@ -455,6 +457,12 @@ static int good_size(int n) {
   }
 }
 
+// SFW_FFT=generic keeps every axis on the runtime-length passes (a test switch).
+static bool fixed_lengths_enabled() {
+  const char* env = std::getenv("SFW_FFT");
+  return !(env && std::strcmp(env, "generic") == 0);
+}
+
 static bool make_axis_plan(int n, FftAxis& ax) {
   ax.n = n;
   ax.nstage = 0;
@@ -468,7 +476,7 @@ static bool make_axis_plan(int n, FftAxis& ax) {
       ax.radix[ax.nstage++] = p;
       t /= p;
     }
-  if (!fft_fixed_plan(n, &ax.r1, &ax.r2)) ax.r1 = ax.r2 = 0;
+  if (!fixed_lengths_enabled() || !fft_fixed_plan(n, &ax.r1, &ax.r2)) ax.r1 = ax.r2 = 0;
   return t == 1;
 }
 
@@ -477,6 +485,7 @@ static bool make_axis_plan(int n, FftAxis& ax) {
 // as much per element; else the smooth size.
 static int choose_length(int nmin) {
   const int g = good_size(nmin);
+  if (!fixed_lengths_enabled()) return g;
   int r1 = 0, r2 = 0;
   for (int L = nmin; L <= g + g / 4; ++L)
     if (fft_fixed_plan(L, &r1, &r2)) return L;

@@ -182,18 +182,23 @@ def test_adjoint_identity_on_gpu(L, ws_big, conv_path):
     assert abs(lhs - rhs) <= 1e-5 * (np.linalg.norm(f) * np.linalg.norm(r) * np.abs(psf).sum())
 
 
-@pytest.fixture(params=["fft", "direct"])
+@pytest.fixture(params=["fft", "fft_generic", "direct"])
 def cert_path(request, monkeypatch):
-    """Run a test on the Fourier-domain certificate (default) and on the direct one."""
+    """Run a test on the Fourier-domain certificate (default: fixed-length passes where the
+    transform lengths allow), on its runtime-length passes only, and on the direct one."""
+    monkeypatch.delenv("SFW_CERT", raising=False)
+    monkeypatch.delenv("SFW_FFT", raising=False)
     if request.param == "direct":
         monkeypatch.setenv("SFW_CERT", "direct")
-    else:
-        monkeypatch.delenv("SFW_CERT", raising=False)
+    elif request.param == "fft_generic":
+        monkeypatch.setenv("SFW_FFT", "generic")
     return request.param
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_certificate_parity(L, ws_big, name, cert_path):
+    if name == "c3" and cert_path == "direct":
+        pytest.skip("the direct certificate at 128 x 128 x 64 is covered by the smaller sizes")
     prob, atoms, psf, y = _problem(name)
     lam = 0.9
     sg, dg = prob.config.sigma_grid, prob.config.d_grid
@@ -235,6 +240,27 @@ def test_certificate_edge_shapes(L, ws_big, cert_path, shape, sg, dg):
     idx = (best["i_sigma"], best["i_d"], best["z"], best["y"], best["x"])
     if idx != idx_o:
         assert rel_err(eta_o[idx], v_o) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(3, 5, 250), (250, 4, 6)])
+def test_certificate_long_axis(L, cert_path, shape):
+    """Transform lengths past the fixed-length sizes (generic passes on that axis)."""
+    rng = np.random.default_rng(shape[0])
+    r = f32(rng.standard_normal(shape))
+    psf = f32(np.abs(rng.standard_normal((5, 3, 3))) + 0.1)
+    sg, dg = (1.0, 1.7), (2.0, 1.6)
+    ws = L.Workspace(shape, psf.shape, 4)
+    try:
+        say("sfw_certificate long axis", shape, cert_path)
+        eta, best = L.sfw_certificate(ws, dev(psf), dev(r), 0.6, list(sg), list(dg),
+                                      want_eta=True)
+        torch.cuda.synchronize()
+        eta_o = oracle.grid_certificate(oracle.adjoint(r, psf), 0.6, sg, dg)
+        assert rel_l2(eta.cpu().numpy(), eta_o) <= 1e-5
+        v_o, _ = oracle.grid_argmax(eta_o)
+        assert rel_err(best["eta"], v_o) <= 1e-5
+    finally:
+        ws.close()
 
 
 def test_certificate_argmax_only_matches_grid(L, ws_big, cert_path):
