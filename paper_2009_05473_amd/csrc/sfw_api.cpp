@@ -374,12 +374,51 @@ int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int i0,
   return SFW_OK;
 }
 
+// Box holding every nonzero of the column a = H * g of a unit atom theta = (m, sigma, d): the
+// rendered atom exp2(-u log2 e) is exactly zero in float32 once u = (r / sigma)^d / 2 >= 110
+// (2^-158 rounds to zero even with denormals), so g vanishes outside the ball of radius
+// sigma (220)^(1/d) and a outside that ball grown by the PSF half-widths. x bounds are widened
+// to multiples of 4 for vector loads. False when the box is the whole volume anyway.
+static bool column_box(const float* theta, const sfw_dims& psf, const sfw_dims& vol, int box[6]) {
+  const double sig = theta[3], d = theta[4];
+  const double R = sig * std::pow(220.0, 1.0 / d) + 1.0;
+  const double c[3] = {(psf.nx - 1) / 2.0, (psf.ny - 1) / 2.0, (psf.nz - 1) / 2.0};
+  const int n[3] = {vol.nx, vol.ny, vol.nz};
+  bool whole = true;
+  for (int a = 0; a < 3; ++a) {
+    const double lo = std::floor(theta[a] - R - c[a]), hi = std::ceil(theta[a] + R + c[a]) + 1.0;
+    int l = (int)std::max(0.0, std::min((double)n[a], lo));
+    int h = (int)std::max(0.0, std::min((double)n[a], hi));
+    if (a == 0) {
+      l &= ~3;
+      h = std::min(n[a], (h + 3) & ~3);
+    }
+    if (h <= l) {  // the column vanishes on the volume: keep a one-vector box
+      l = 0;
+      h = a == 0 ? 4 : 1;
+    }
+    box[2 * a] = l;
+    box[2 * a + 1] = h;
+    whole = whole && l == 0 && h == n[a];
+  }
+  return !whole;
+}
+
 // G[i][0..i] and b[i] for the column i into out (float64, device), k = i + 1 entries + b.
-int op_gram_row(sfw_workspace* ws, const sfw_dims& vol, const float* y, int i, double* out) {
+// theta: the unit atom of column i (host), used to restrict the sums to its support.
+int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int i,
+                const float* theta, double* out) {
   const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
+  ProfScope ps(ws, kProfLassoDots);
+  int box[6];
+  if (vol.nx % 4 == 0 && ws->vcap % 4 == 0 && column_box(theta, p.psf, vol, box)) {
+    SFW_HIP(launch_dots_box(ws->cols + (size_t)i * ws->vcap, ws->cols, i + 1, ws->vcap, y, vol,
+                            box, ws->dpart, (int)std::min<size_t>(ws->dpart_cap, 1u << 30),
+                            out, ws->stream));
+    return SFW_OK;
+  }
   int nb = (int)std::min<size_t>(1024, (V + 1023) / 1024);
   if ((size_t)nb * (i + 2) > ws->dpart_cap) return fail(SFW_EINVAL, "dot partial buffer too small");
-  ProfScope ps(ws, kProfLassoDots);
   SFW_HIP(launch_dots(ws->cols + (size_t)i * ws->vcap, ws->cols, i + 1, ws->vcap, y, V, ws->dpart,
                       nb, out, ws->stream));
   return SFW_OK;
@@ -476,7 +515,8 @@ int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
     int rc = op_columns(ws, p, vol, pre, n);
     if (rc) return rc;
     for (int i = pre; i < n; ++i) {
-      rc = op_gram_row(ws, vol, y, i, ws->dres + (size_t)i * (i + 1) / 2 + i);
+      rc = op_gram_row(ws, p, vol, y, i, thetas + 5 * (size_t)i,
+                       ws->dres + (size_t)i * (i + 1) / 2 + i);
       if (rc) return rc;
     }
     const size_t o0 = (size_t)pre * (pre + 1) / 2 + pre;
@@ -594,7 +634,8 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ws->vol_max = vol_max;
     ws->psf_max = psf_max;
     ws->max_atoms = max_atoms;
-    ws->vcap = (size_t)vol_max.nx * vol_max.ny * vol_max.nz;
+    // volume capacity in elements, a multiple of 64 (aligned columns for vector loads)
+    ws->vcap = ((size_t)vol_max.nx * vol_max.ny * vol_max.nz + 63) / 64 * 64;
     const size_t V = ws->vcap;
     const int na = max_atoms + 1;
     auto dmalloc = [&](void** p, size_t bytes, const char* what) -> int {

@@ -278,6 +278,11 @@ hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, i
 hipError_t launch_dots(const float* a, const float* cols, int k, size_t colstride,
                        const float* y, size_t nvox, double* dpart, int nblocks, double* out,
                        hipStream_t st);
+// Gram row over box = {x0, x1, y0, y1, z0, z1} (half-open; x0, x1, nx and colstride multiples
+// of 4) that holds every nonzero of a.
+hipError_t launch_dots_box(const float* a, const float* cols, int k, size_t colstride,
+                           const float* y, sfw_dims vol, const int box[6], double* dpart,
+                           int dpart_cap, double* out, hipStream_t st);
 hipError_t launch_any_nonfinite(const float* v, size_t n, int* flag, hipStream_t st);
 
 // ---- Fourier-domain grid certificate (sfw_fft.hip)

@@ -775,6 +775,67 @@ __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
   }
 }
 
+// Gram row of column a over a box that holds every nonzero of a: out partials
+// dpart[blockIdx.x][c] = sum over the box of a * col_c (c < k: cached columns, c = k: y) for
+// the columns of chunk blockIdx.y (cpb per chunk). The box is rows (y, z) of bw4 float4 starting
+// at x0 (x0, nx and the column stride multiples of 4); a thread keeps its kDotsHold float4 of a
+// in registers across the columns.
+__global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
+                                                  const float* __restrict__ cols, int k,
+                                                  size_t colstride, const float* __restrict__ y,
+                                                  int nx, int ny, int x0, int bw4, int y0,
+                                                  int bh, int z0, int nrows, int cpb,
+                                                  double* __restrict__ dpart) {
+  __shared__ double red[kDotsCols][4];
+  const int tid = threadIdx.x;
+  const int E = nrows * bw4;
+  const int stride = gridDim.x * 256;
+  const int e0 = blockIdx.x * 256 + tid;
+  float4 ah[kDotsHold];
+  size_t vh[kDotsHold];
+#pragma unroll
+  for (int h = 0; h < kDotsHold; ++h) {
+    const int e = e0 + h * stride;
+    const bool ok = e < E;
+    const int row = ok ? e / bw4 : 0;
+    const int q = ok ? e - row * bw4 : 0;
+    const int yy = y0 + row % bh, zz = z0 + row / bh;
+    vh[h] = ((size_t)zz * ny + yy) * nx + x0 + 4 * q;
+    ah[h] = ok ? *reinterpret_cast<const float4*>(a + vh[h]) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  const int cb = blockIdx.y * cpb, ce = min(k + 1, cb + cpb);
+  for (int c0 = cb; c0 < ce; c0 += kDotsCols) {
+    const int nc = min(kDotsCols, ce - c0);
+    const float* b[kDotsCols];
+#pragma unroll
+    for (int u = 0; u < kDotsCols; ++u) {
+      const int c = min(c0 + u, ce - 1);
+      b[u] = c < k ? cols + (size_t)c * colstride : y;
+    }
+    double s[kDotsCols] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < kDotsHold; ++h) {
+      if (e0 + h * stride < E) {
+        float4 bv[kDotsCols];
+#pragma unroll
+        for (int u = 0; u < kDotsCols; ++u) bv[u] = *reinterpret_cast<const float4*>(b[u] + vh[h]);
+#pragma unroll
+        for (int u = 0; u < kDotsCols; ++u) s[u] += dot4(ah[h], bv[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kDotsCols; ++u) {
+      const double t = shfl_sum_d(s[u]);
+      if ((tid & 63) == 0) red[u][tid / 64] = t;
+    }
+    __syncthreads();
+    if (tid < nc)
+      dpart[(size_t)blockIdx.x * (k + 1) + c0 + tid] =
+          red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ dpart, int nblocks,
                                                     int k1, double* __restrict__ out) {
   __shared__ double red[4];
@@ -1018,6 +1079,27 @@ hipError_t launch_dots(const float* a, const float* cols, int k, size_t colstrid
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dots_final, dim3(k + 1), dim3(256), 0, st, dpart, nblocks, k + 1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots_box(const float* a, const float* cols, int k, size_t colstride,
+                           const float* y, sfw_dims vol, const int box[6], double* dpart,
+                           int dpart_cap, double* out, hipStream_t st) {
+  const int bw4 = (box[1] - box[0]) / 4, bh = box[3] - box[2], nrows = bh * (box[5] - box[4]);
+  const int E = nrows * bw4;
+  if (E <= 0) return hipErrorInvalidValue;
+  const int nbx = std::max(1, (E + 256 * kDotsHold - 1) / (256 * kDotsHold));
+  // column chunks: enough blocks to fill the chip, chunks of whole column groups
+  int chunks = std::max(1, std::min((k + 1 + kDotsCols - 1) / kDotsCols, (1024 + nbx - 1) / nbx));
+  const int groups = (k + 1 + kDotsCols - 1) / kDotsCols;
+  const int cpb = (groups + chunks - 1) / chunks * kDotsCols;
+  chunks = (k + 1 + cpb - 1) / cpb;
+  if ((size_t)nbx * (k + 1) > (size_t)dpart_cap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dots_box, dim3(nbx, chunks), dim3(256), 0, st, a, cols, k, colstride, y,
+                     vol.nx, vol.ny, box[0], bw4, box[2], bh, box[4], nrows, cpb, dpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dots_final, dim3(k + 1), dim3(256), 0, st, dpart, nbx, k + 1, out);
   return hipGetLastError();
 }
 

@@ -55,7 +55,8 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
 // LASSO columns for unit-weight atoms i in [i0, i1) already staged in ws->ak.
 int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int i0, int i1);
 // out[0..i] = <a_i, a_j> (j <= i), out[i + 1] = <a_i, y>, float64 on the device.
-int op_gram_row(sfw_workspace* ws, const sfw_dims& vol, const float* y, int i, double* out);
+int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int i,
+                const float* theta, double* out);
 // min_{w >= 0} 1/2 w^T G w - c^T w.
 int nnqp(const std::vector<double>& G, const std::vector<double>& c, int k, std::vector<double>& w);
 

@@ -307,6 +307,26 @@ def test_lasso_parity(L, ws_big):
     assert np.all(grad[w == 0] >= -1e-4 * np.abs(b).max())
 
 
+def test_lasso_incremental_full_size(L, ws_big):
+    """BSFW's weight step at 128 x 128 x 64 with 50 atoms: the 49-atom support first, then the
+    same support plus one atom (cached columns, one new Gram row summed over the new column's
+    support box) against the oracle's LASSO on the 50 atoms."""
+    prob, _, psf, y = _problem("c3")
+    thetas = f32(prob.atoms_true[:, 1:6])
+    atoms = np.hstack([np.zeros((len(thetas), 1)), thetas])
+    lam = 0.05 * oracle.max_grid_certificate(y, psf, prob.config.sigma_grid, prob.config.d_grid)
+    lam = float(np.float32(lam))
+    Hd, Yd = dev(psf), dev(y)
+    say("sfw_lasso_weights c3 49 then 50 atoms")
+    L.sfw_lasso_weights(ws_big, Hd, Yd, lam, dev(atoms[:-1]))
+    w = L.sfw_lasso_weights(ws_big, Hd, Yd, lam, dev(atoms)).cpu().numpy()
+    w_o, G, b = oracle.lasso_weights(y, thetas, psf, lam)
+    assert rel_l2(w, w_o) <= 1e-4
+    grad = G @ w - b + lam
+    assert np.all(np.abs(grad[w > 0]) <= 1e-4 * np.abs(b).max())
+    assert np.all(grad[w == 0] >= -1e-4 * np.abs(b).max())
+
+
 def test_lasso_zero_weight_case(L, ws_big):
     """A far-off atom with no signal gets weight 0 (KKT lower bound active)."""
     prob, _, psf, y = _problem("c1")
