@@ -50,25 +50,38 @@ GRAD_SLOTS_PER_PAIR = 12 + 3 * 4    # 12 VALU + log2, exp2, exp2
 # runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
 #   bench.py --steps 2 --warmup 1 --profile-steps 0 --no-cpu-baseline --copy-probe-mib 256
 # each scaled by the same counter's reading for the known 256 MiB device copy at the end.
-# The record holds for the kernel source it was taken on (sha256 of KERNEL_SOURCE).
+# The record holds for the kernel source it was taken on: sha256 of the kernel's definition in
+# KERNEL_SOURCE (from its template line to the next section rule).
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_05473_amd", "csrc", "sfw_kernels.hip")
+KERNEL_START = "template <int STEPS, int EPI>\n__global__ __launch_bounds__(512) void k_conv_mfma("
+SECTION_RULE = "\n// ------------------------------------------------------------------"
 CONV_TRAFFIC = {
-    "fetch_kib": 7253.0, "write_kib": 4096.0,            # k_conv_mfma<21, 0>, per dispatch
-    "copy_mib": 256, "copy_fetch_kib": 131086.7, "copy_write_kib": 262144.0,
-    "source_sha256": "cd061364d4c9fd41ea3a966c9333b88ed97c234e481c1ff617de65843932d3e5",
+    "fetch_kib": 7266.6, "write_kib": 4096.0,            # k_conv_mfma<21, 0>, per dispatch
+    "copy_mib": 256, "copy_fetch_kib": 131087.25, "copy_write_kib": 262144.0,
+    "source_sha256": "6cce3b9915745470318b76e62eb957db0db791295a91267716354c8194d8f38b",
 }
+
+
+def kernel_sha256():
+    """sha256 of the roofline kernel's definition text (None if it cannot be located)."""
+    import hashlib
+    with open(KERNEL_SOURCE) as fh:
+        src = fh.read()
+    i = src.find(KERNEL_START)
+    if i < 0:
+        return None
+    j = src.find(SECTION_RULE, i)
+    return hashlib.sha256(src[i:j if j > 0 else len(src)].encode()).hexdigest()
 
 
 def conv_traffic():
     """Counter-measured HBM bytes per launch of the roofline kernel, or None when the record
     is missing or the kernel source changed since it was taken."""
-    import hashlib
     t = CONV_TRAFFIC
     if t is None:
         return None
-    with open(KERNEL_SOURCE, "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != t["source_sha256"]:
-            return None
+    if kernel_sha256() != t["source_sha256"]:
+        return None
     copy_bytes = float(t["copy_mib"]) * (1 << 20)
     fetch = t["fetch_kib"] * 1024.0 * copy_bytes / (t["copy_fetch_kib"] * 1024.0)
     write = t["write_kib"] * 1024.0 * copy_bytes / (t["copy_write_kib"] * 1024.0)

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <type_traits>
 
 #include <cfloat>
 #include <cmath>
@@ -375,24 +376,30 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // A block owns 16 consecutive x of 4 rows y and streams the input planes zi = 0 .. nz-1.
 // For each plane the in-plane taps form the K dimension of a chain of
 // v_mfma_f32_16x16x4_f32 with A = W[kz][tap] (registers), B[tap][n] =
-// in[zi][y + cy - ky][x0 + n + cx - kx] and accumulator rows indexed by kz: row j holds the
-// partial sum of output plane zi - cz + j. After a plane row 0 is complete, and the rows
-// roll up by one. Each row is served by two waves (8 waves per block, two per SIMD) that
-// split the taps, so one wave's per-plane latencies overlap the other's MFMAs; the second
-// wave hands its row 0 to the first through LDS, which stores the sum one plane later. The
-// block stages each plane's (16 + px - 1) x (4 + py - 1) input patch (zero outside the
-// volume) in a ring of LDS buffers, with the global loads issued three planes ahead.
+// in[zi][y + cy - ky][x0 + n + cx - kx] and accumulator rows indexed by kz: row j holds a
+// partial sum of output plane zi - cz + j.
+//
+// Two accumulators take the even (E) and the odd (O) input planes, so every wave runs two
+// independent MFMA chains per iteration of two planes. After its plane, an accumulator's rows
+// 0 and 1 hold its final share of two output planes; they are read out and the rows roll up by
+// two (one 16-lane shuffle per two rows). Output plane 2t - cz is E's row 0 of iteration t plus
+// O's row 1 of iteration t - 1; plane 2t - cz + 1 is E's row 1 plus O's row 0 of iteration t.
+// Each row is served by two waves (8 waves per block, two per SIMD) that split the taps; the
+// second hands its shares to the first through LDS. The block stages each plane's
+// (16 + px - 1) x (4 + py - 1) input patch (zero outside the volume) in a ring of 8 LDS
+// buffers: planes 2t + 4 and 2t + 5 are stored at iteration t from registers loaded one
+// iteration earlier, with one barrier per iteration.
 // Accumulator layout (16x16x4 f32): lane l holds rows 4 (l / 16) + 0..3 of column l % 16.
 template <int STEPS, int EPI>
 __global__ __launch_bounds__(512) void k_conv_mfma(
     const float* __restrict__ in, const float* __restrict__ amat, int px, int py, int pz,
     int nx, int ny, int nz, float* __restrict__ out, const float* __restrict__ yobs,
     double* __restrict__ dpart) {
-  constexpr int NBUF = 4;
+  constexpr int NBUF = 8;
   constexpr int PLANE = kMfmaPatchMax;
   constexpr int SH = (STEPS + 1) / 2;  // taps of the first half (the second gets the rest)
   __shared__ float patch[NBUF][PLANE];
-  __shared__ float xch[2][4][16];
+  __shared__ float xch[2][4][4][16];  // [t & 1][row][E0, E1, O0, O1][x]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -433,60 +440,123 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
     }
     boff[s] = o;
   }
-  // prologue: planes 0 and 1 in LDS, plane 2 in flight
+  // prologue: planes 0-3 in LDS, planes 4 and 5 in registers
   if (lown) {
-    patch[0][tid] = fetch(0);
-    patch[1][tid] = fetch(1);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) patch[p][tid] = fetch(p);
   }
-  float st1 = fetch(2);
+  float sa = fetch(4), sb = fetch(5);
   const bool out_lane = half == 0 && g == 0 && x < nx && y < ny;
   const size_t col = (size_t)min(y, ny - 1) * nx + min(x, nx - 1);
-  float ynext = 0.f;
-  if (EPI == kEpiResidual) ynext = yobs[col];  // plane 0
+  // observed y at this iteration's two output planes (residual epilogue), one iteration ahead
+  auto yat = [&](int o) -> float { return yobs[(size_t)min(max(o, 0), nz - 1) * nxy + col]; };
+  float y1 = 0.f, y2 = 0.f;
+  if (EPI == kEpiResidual) {
+    y1 = yat(-cz);
+    y2 = yat(1 - cz);
+  }
   __syncthreads();
 
-  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  float ssf = 0.f, prev = 0.f;
-  for (int zi = 0; zi <= nz + cz; ++zi) {
-    const float st0 = fetch(zi + 3);
-    // the first half stores output plane zi - 1 - cz: its own row 0 of the previous plane
-    // plus the second half's, exchanged through LDS before the last barrier
-    const int zo = zi - 1 - cz;
-    if (half == 0 && zo >= 0) {
-      const float row = prev + xch[(zi - 1) & 1][rowi][n];
-      if (out_lane) {
-        const size_t v = (size_t)zo * nxy + col;
-        if (EPI == kEpiPlain) {
-          out[v] = row;
-        } else {
-          const float rv = ynext - row;
-          out[v] = rv;
-          ssf = fmaf(rv, rv, ssf);
-        }
-      }
-      if (EPI == kEpiResidual) ynext = yobs[(size_t)min(zo + 1, nz - 1) * nxy + col];
-    }
-    if (zi < nz) {
-      const float* buf = patch[zi & (NBUF - 1)];
-      float b[SH];
+  floatx4 accE = {0.f, 0.f, 0.f, 0.f}, accO = {0.f, 0.f, 0.f, 0.f};
+  float ssf = 0.f, ob_prev = 0.f;
+  const int T = (nz - 1 + cz) / 2 + 1;  // the last iteration completes output plane nz - 1
+  auto roll2 = [&](floatx4& acc) {
+    const float u0 = __shfl_down(acc[0], 16, 64);
+    const float u1 = __shfl_down(acc[1], 16, 64);
+    acc[0] = acc[2];
+    acc[1] = acc[3];
+    acc[2] = g < 3 ? u0 : 0.f;
+    acc[3] = g < 3 ? u1 : 0.f;
+  };
+  // one iteration: planes 2t (E) and 2t + 1 (O); FULL: both planes inside the volume
+  auto iteration = [&](int t, auto full) {
+    constexpr bool FULL = decltype(full)::value;
+    const int ze = 2 * t, zo = 2 * t + 1;
+    const float na = fetch(ze + 6), nb = fetch(ze + 7);
+    const float* bufE = patch[ze & (NBUF - 1)];
+    const float* bufO = patch[zo & (NBUF - 1)];
+    if (FULL) {
+      float bE[SH], bO[SH];
 #pragma unroll
-      for (int s = 0; s < SH; ++s) b[s] = buf[boff[s]];
+      for (int s = 0; s < SH; ++s) {
+        bE[s] = bufE[boff[s]];
+        bO[s] = bufO[boff[s]];
+      }
+#pragma unroll
+      for (int s = 0; s < SH; ++s) {
+        accE = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bE[s], accE, 0, 0, 0);
+        accO = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bO[s], accO, 0, 0, 0);
+      }
+    } else if (ze < nz) {
+      float bE[SH];
+#pragma unroll
+      for (int s = 0; s < SH; ++s) bE[s] = bufE[boff[s]];
 #pragma unroll
       for (int s = 0; s < SH; ++s)
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
+        accE = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bE[s], accE, 0, 0, 0);
     }
-    const float r0 = acc[0];
-    if (half == 1 && g == 0) xch[zi & 1][rowi][n] = r0;
-    prev = r0;
-    const float up = __shfl_down(acc[0], 16, 64);
-    acc[0] = acc[1];
-    acc[1] = acc[2];
-    acc[2] = acc[3];
-    acc[3] = g < 3 ? up : 0.f;
-    if (lown) patch[(zi + 2) & (NBUF - 1)][tid] = st1;
-    st1 = st0;
+    const float e0 = accE[0], e1 = accE[1], o0 = accO[0], o1 = accO[1];
+    roll2(accE);
+    roll2(accO);
+    if (half == 1 && g == 0) {
+      float(*xc)[16] = xch[t & 1][rowi];
+      xc[0][n] = e0;
+      xc[1][n] = e1;
+      xc[2][n] = o0;
+      xc[3][n] = o1;
+    }
+    if (lown) {
+      patch[(ze + 4) & (NBUF - 1)][tid] = sa;
+      patch[(ze + 5) & (NBUF - 1)][tid] = sb;
+    }
+    sa = na;
+    sb = nb;
     __syncthreads();
-  }
+    if (half == 0) {
+      // output planes 2t - cz and 2t - cz + 1
+      const float(*xc)[16] = xch[t & 1][rowi];
+      const float E0 = e0 + xc[0][n], E1 = e1 + xc[1][n];
+      const float O0 = o0 + xc[2][n], O1 = o1 + xc[3][n];
+      const float v1 = E0 + ob_prev, v2 = E1 + O0;
+      ob_prev = O1;
+      const int p1 = 2 * t - cz, p2 = p1 + 1;
+      float yn1 = 0.f, yn2 = 0.f;
+      if (EPI == kEpiResidual) {
+        yn1 = yat(p1 + 2);
+        yn2 = yat(p2 + 2);
+      }
+      if (out_lane) {
+        if (p1 >= 0 && p1 < nz) {
+          const size_t v = (size_t)p1 * nxy + col;
+          if (EPI == kEpiPlain) {
+            out[v] = v1;
+          } else {
+            const float rv = y1 - v1;
+            out[v] = rv;
+            ssf = fmaf(rv, rv, ssf);
+          }
+        }
+        if (p2 >= 0 && p2 < nz) {
+          const size_t v = (size_t)p2 * nxy + col;
+          if (EPI == kEpiPlain) {
+            out[v] = v2;
+          } else {
+            const float rv = y2 - v2;
+            out[v] = rv;
+            ssf = fmaf(rv, rv, ssf);
+          }
+        }
+      }
+      if (EPI == kEpiResidual) {
+        y1 = yn1;
+        y2 = yn2;
+      }
+    }
+  };
+  const int TF = min(T, nz / 2);  // iterations whose two planes are both inside the volume
+  int t = 0;
+  for (; t < TF; ++t) iteration(t, std::true_type{});
+  for (; t < T; ++t) iteration(t, std::false_type{});
   if (EPI == kEpiResidual && half == 0) {
     double ss = shfl_sum_d((double)ssf);
     if (lane == 0) dpart[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + rowi] = ss;
