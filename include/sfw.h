@@ -168,8 +168,9 @@ int sfw_eta_points(sfw_workspace* ws, sfw_dims vol, const float* q, float lambda
  * + lambda sum w_n, a_n = H * g(theta_n) (unit weight). The Gram matrix and A^T y are
  * accumulated in float64 on the GPU; the non-negative quadratic program is solved in
  * float64 on the host by an active-set method. The atoms' w fields are ignored. Columns and
- * Gram rows of the longest unchanged prefix of the atom list are reused from the previous
- * call on the same y (pointer and contents) and H, as BSFW needs (its atoms do not move).
+ * Gram entries are cached in the workspace by atom parameters (exact float match) for the
+ * same y (pointer and contents) and H: an atom seen in an earlier call reuses its column, as
+ * BSFW needs (its atoms do not move between iterations; pruned atoms just drop out).
  * atoms: device [n]; w_out: device double [n], written in stream order. Synchronises the
  * stream to read the atoms and the Gram rows. */
 int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,

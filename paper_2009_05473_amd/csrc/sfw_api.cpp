@@ -361,17 +361,14 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
 
 // Columns a_i = H * g(theta_i) (unit weight) for i in [i0, i1) into ws->cols; atoms staged in
 // ws->ak with unit weights.
-int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int i0, int i1) {
-  for (int i = i0; i < i1; ++i) {
-    {
-      ProfScope ps(ws, kProfLassoRender);
-      SFW_HIP(launch_render(ws->ak + i, 1, vol, ws->f, ws->stream));
-    }
-    int rc = conv_psf(ws, p, vol, false, ws->f, ws->cols + (size_t)i * ws->vcap, kEpiPlain,
-                      nullptr, kProfLassoConv);
-    if (rc) return rc;
+// Column of the unit atom whose constants are ws->ak[atom] into LASSO slot `slot`.
+int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int atom, int slot) {
+  {
+    ProfScope ps(ws, kProfLassoRender);
+    SFW_HIP(launch_render(ws->ak + atom, 1, vol, ws->f, ws->stream));
   }
-  return SFW_OK;
+  return conv_psf(ws, p, vol, false, ws->f, ws->cols + (size_t)slot * ws->vcap, kEpiPlain,
+                  nullptr, kProfLassoConv);
 }
 
 // Box holding every nonzero of the column a = H * g of a unit atom theta = (m, sigma, d): the
@@ -404,23 +401,24 @@ static bool column_box(const float* theta, const sfw_dims& psf, const sfw_dims& 
   return !whole;
 }
 
-// G[i][0..i] and b[i] for the column i into out (float64, device), k = i + 1 entries + b.
-// theta: the unit atom of column i (host), used to restrict the sums to its support.
-int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int i,
-                const float* theta, double* out) {
+// Gram row of slot `slot` against the nd slots listed in ws->lasso_slots, then <a, y>: out
+// (float64, device) [nd + 1]. theta: the unit atom of the slot (host), used to restrict the sums
+// to its support.
+int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int slot,
+                const float* theta, int nd, double* out) {
   const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
+  const float* a = ws->cols + (size_t)slot * ws->vcap;
   ProfScope ps(ws, kProfLassoDots);
   int box[6];
   if (vol.nx % 4 == 0 && ws->vcap % 4 == 0 && column_box(theta, p.psf, vol, box)) {
-    SFW_HIP(launch_dots_box(ws->cols + (size_t)i * ws->vcap, ws->cols, i + 1, ws->vcap, y, vol,
-                            box, ws->dpart, (int)std::min<size_t>(ws->dpart_cap, 1u << 30),
-                            out, ws->stream));
+    SFW_HIP(launch_dots_box(a, ws->cols, ws->lasso_slots, nd, ws->vcap, y, vol, box, ws->dpart,
+                            (int)std::min<size_t>(ws->dpart_cap, 1u << 30), out, ws->stream));
     return SFW_OK;
   }
   int nb = (int)std::min<size_t>(1024, (V + 1023) / 1024);
-  if ((size_t)nb * (i + 2) > ws->dpart_cap) return fail(SFW_EINVAL, "dot partial buffer too small");
-  SFW_HIP(launch_dots(ws->cols + (size_t)i * ws->vcap, ws->cols, i + 1, ws->vcap, y, V, ws->dpart,
-                      nb, out, ws->stream));
+  if ((size_t)nb * (nd + 1) > ws->dpart_cap) return fail(SFW_EINVAL, "dot partial buffer too small");
+  SFW_HIP(launch_dots(a, ws->cols, ws->lasso_slots, nd, ws->vcap, y, V, ws->dpart, nb, out,
+                      ws->stream));
   return SFW_OK;
 }
 
@@ -459,7 +457,10 @@ static void lasso_validate(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& 
                     ws->lasso_vol.ny == vol.ny && ws->lasso_vol.nz == vol.nz &&
                     ws->lasso_psf.nx == p.psf.nx && ws->lasso_psf.ny == p.psf.ny &&
                     ws->lasso_psf.nz == p.psf.nz;
-  if (!same) ws->lasso_k = 0;
+  if (!same) {
+    std::fill(ws->slot_ok.begin(), ws->slot_ok.end(), 0);
+    std::fill(ws->gram_ok.begin(), ws->gram_ok.end(), 0);
+  }
   ws->lasso_y = y;
   ws->lasso_yhash = yh;
   ws->lasso_hhash = hh;
@@ -483,61 +484,119 @@ int lasso_check_inputs(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
 
 // Weights-only LASSO for unit-weight atoms thetas [n][5] (host, float32 values as the device
 // sees them); the PSF operands for the forward convolution must be prepared and the cache
-// validated for (y, H) (lasso_check_inputs). ak_ready: the unit-weight atom constants of all
-// n atoms are already in ws->ak (else they are uploaded for the atoms past the cached prefix). Columns and Gram rows of the longest prefix of
-// atoms identical to the cached list are reused; the rest are computed on the GPU (one
-// synchronisation for the Gram readback).
+// validated for (y, H) (lasso_check_inputs). ak_ready: the unit-weight atom constants of all n
+// atoms are in ws->ak (else they are uploaded). Columns are cached in slots keyed by the atom
+// parameters, and Gram entries by slot pair: only atoms without a cached column get one
+// (render + blur), and only slots with a missing entry against the support get a Gram row
+// (one synchronisation for the readback).
 int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
              double lambda, const float* thetas, int n, std::vector<double>& w, bool ak_ready) {
   w.assign(n, 0.0);
   if (n == 0) return SFW_OK;
   const int M = ws->max_atoms;
-  if ((int)ws->lasso_G.size() != M * M) {
-    ws->lasso_G.assign((size_t)M * M, 0.0);
-    ws->lasso_b.assign(M, 0.0);
-    ws->lasso_k = 0;
+  if (n > M) return fail(SFW_EINVAL, "LASSO support exceeds max_atoms");
+  // slot of every atom: a cached column with the same parameters, else a slot no atom of this
+  // support maps to (free ones first)
+  std::vector<int> map(n, -1);
+  std::vector<char> in_use(M, 0);
+  for (int i = 0; i < n; ++i)
+    for (int s2 = 0; s2 < M; ++s2)
+      if (ws->slot_ok[s2] &&
+          std::memcmp(&ws->slot_theta[5 * (size_t)s2], thetas + 5 * (size_t)i, 5 * sizeof(float)) == 0) {
+        map[i] = s2;
+        in_use[s2] = 1;
+        break;
+      }
+  std::vector<std::pair<int, int>> fresh;  // (atom, slot)
+  for (int i = 0; i < n; ++i) {
+    if (map[i] >= 0) continue;
+    for (int j = 0; j < i; ++j)  // a duplicate of an atom placed earlier in this call
+      if (std::memcmp(thetas + 5 * (size_t)j, thetas + 5 * (size_t)i, 5 * sizeof(float)) == 0) {
+        map[i] = map[j];
+        break;
+      }
+    if (map[i] >= 0) continue;
+    int slot = -1;
+    for (int s2 = 0; s2 < M && slot < 0; ++s2)
+      if (!ws->slot_ok[s2] && !in_use[s2]) slot = s2;
+    for (int s2 = 0; s2 < M && slot < 0; ++s2)
+      if (!in_use[s2]) slot = s2;
+    map[i] = slot;  // n <= M guarantees a slot
+    in_use[slot] = 1;
+    ws->slot_ok[slot] = 0;
+    for (int t = 0; t < M; ++t) ws->gram_ok[(size_t)slot * M + t] = ws->gram_ok[(size_t)t * M + slot] = 0;
+    std::memcpy(&ws->slot_theta[5 * (size_t)slot], thetas + 5 * (size_t)i, 5 * sizeof(float));
+    fresh.emplace_back(i, slot);
   }
-  int pre = 0;
-  const int kmax = std::min(ws->lasso_k, n);
-  while (pre < kmax && std::memcmp(&ws->lasso_thetas[5 * (size_t)pre], thetas + 5 * (size_t)pre,
-                                   5 * sizeof(float)) == 0)
-    ++pre;
-  if (pre < n) {
+  // the distinct slots of the support, in atom order
+  std::vector<int> D;
+  for (int i = 0; i < n; ++i)
+    if (std::find(D.begin(), D.end(), map[i]) == D.end()) D.push_back(map[i]);
+  const int nd = (int)D.size();
+  if (!fresh.empty()) {
     if (!ak_ready) {
       AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin + ws->hp_stage);
-      for (int i = pre; i < n; ++i) {
+      for (int i = 0; i < n; ++i) {
         const float* t = thetas + 5 * (size_t)i;
-        hk[i - pre] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
+        hk[i] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
       }
-      SFW_HIP(hipMemcpyAsync(ws->ak + pre, hk, sizeof(AtomK) * (n - pre), hipMemcpyHostToDevice,
-                             ws->stream));
+      SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
     }
-    int rc = op_columns(ws, p, vol, pre, n);
-    if (rc) return rc;
-    for (int i = pre; i < n; ++i) {
-      rc = op_gram_row(ws, p, vol, y, i, thetas + 5 * (size_t)i,
-                       ws->dres + (size_t)i * (i + 1) / 2 + i);
+    for (const auto& f : fresh) {
+      int rc = op_columns(ws, p, vol, f.first, f.second);
       if (rc) return rc;
-    }
-    const size_t o0 = (size_t)pre * (pre + 1) / 2 + pre;
-    const size_t o1 = (size_t)n * (n + 1) / 2 + n;
-    double* rows = ws->hpin + ws->hp_rows;
-    SFW_HIP(hipMemcpyAsync(rows + o0, ws->dres + o0, (o1 - o0) * 8, hipMemcpyDeviceToHost,
-                           ws->stream));
-    SFW_HIP(hipStreamSynchronize(ws->stream));
-    for (int i = pre; i < n; ++i) {
-      const double* row = rows + (size_t)i * (i + 1) / 2 + i;
-      for (int j = 0; j <= i; ++j)
-        ws->lasso_G[(size_t)i * M + j] = ws->lasso_G[(size_t)j * M + i] = row[j];
-      ws->lasso_b[i] = row[i + 1];
+      ws->slot_ok[f.second] = 1;
     }
   }
-  ws->lasso_thetas.assign(thetas, thetas + 5 * (size_t)n);
-  ws->lasso_k = n;
+  // Gram rows for the entries missing between support slots: fresh slots first, each row
+  // covering its slot's whole row and column, then any slot still missing an entry
+  std::vector<int> rows;
+  {
+    std::vector<char> ok((size_t)nd * nd);
+    for (int a = 0; a < nd; ++a)
+      for (int b = 0; b < nd; ++b) ok[(size_t)a * nd + b] = ws->gram_ok[(size_t)D[a] * M + D[b]];
+    std::vector<int> order;
+    for (const auto& f : fresh) order.push_back((int)(std::find(D.begin(), D.end(), f.second) - D.begin()));
+    for (int a = 0; a < nd; ++a)
+      if (std::find(order.begin(), order.end(), a) == order.end()) order.push_back(a);
+    for (int a : order) {
+      bool full = true;
+      for (int b = 0; b < nd && full; ++b) full = ok[(size_t)a * nd + b] != 0;
+      if (full) continue;
+      rows.push_back(D[a]);
+      for (int b = 0; b < nd; ++b) ok[(size_t)a * nd + b] = ok[(size_t)b * nd + a] = 1;
+    }
+  }
+  if (!rows.empty()) {
+    int* hs = reinterpret_cast<int*>(ws->hpin + ws->hp_slots);
+    std::copy(D.begin(), D.end(), hs);
+    SFW_HIP(hipMemcpyAsync(ws->lasso_slots, hs, sizeof(int) * nd, hipMemcpyHostToDevice,
+                           ws->stream));
+    const size_t stride = (size_t)nd + 1;
+    for (size_t r = 0; r < rows.size(); ++r) {
+      int rc = op_gram_row(ws, p, vol, y, rows[r], &ws->slot_theta[5 * (size_t)rows[r]], nd,
+                           ws->dres + r * stride);
+      if (rc) return rc;
+    }
+    double* hr = ws->hpin + ws->hp_rows;
+    SFW_HIP(hipMemcpyAsync(hr, ws->dres, rows.size() * stride * 8, hipMemcpyDeviceToHost,
+                           ws->stream));
+    SFW_HIP(hipStreamSynchronize(ws->stream));
+    for (size_t r = 0; r < rows.size(); ++r) {
+      const int sa = rows[r];
+      const double* row = hr + r * stride;
+      for (int b = 0; b < nd; ++b) {
+        const int sb = D[b];
+        ws->lasso_G[(size_t)sa * M + sb] = ws->lasso_G[(size_t)sb * M + sa] = row[b];
+        ws->gram_ok[(size_t)sa * M + sb] = ws->gram_ok[(size_t)sb * M + sa] = 1;
+      }
+      ws->lasso_b[sa] = row[nd];
+    }
+  }
   std::vector<double> Gk((size_t)n * n), c(n);
   for (int i = 0; i < n; ++i) {
-    for (int j = 0; j < n; ++j) Gk[(size_t)i * n + j] = ws->lasso_G[(size_t)i * M + j];
-    c[i] = ws->lasso_b[i] - lambda;
+    for (int j = 0; j < n; ++j) Gk[(size_t)i * n + j] = ws->lasso_G[(size_t)map[i] * M + map[j]];
+    c[i] = ws->lasso_b[map[i]] - lambda;
   }
   return nnqp(Gk, c, n, w);
 }
@@ -599,6 +658,7 @@ void sfw_workspace_destroy(sfw_workspace* ws) {
   if (ws->apart) (void)hipFree(ws->apart);
   if (ws->best) (void)hipFree(ws->best);
   if (ws->hashbuf) (void)hipFree(ws->hashbuf);
+  if (ws->lasso_slots) (void)hipFree(ws->lasso_slots);
   if (ws->fft_tw) (void)hipFree(ws->fft_tw);
   if (ws->fft_qhat) (void)hipFree(ws->fft_qhat);
   if (ws->fft_work) (void)hipFree(ws->fft_work);
@@ -686,6 +746,12 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ALLOC(ws->best, sizeof(sfw_argmax) * 2, "argmax");
     ALLOC(ws->hashbuf, (2 * (size_t)kFpParts + 3 * (size_t)na) * 8, "fingerprints");
     ALLOC(ws->cols, (size_t)max_atoms * V * 4, "LASSO columns");
+    ALLOC(ws->lasso_slots, (size_t)max_atoms * sizeof(int), "LASSO slot list");
+    ws->slot_theta.assign(5 * (size_t)max_atoms, 0.f);
+    ws->slot_ok.assign((size_t)max_atoms, 0);
+    ws->gram_ok.assign((size_t)max_atoms * max_atoms, 0);
+    ws->lasso_G.assign((size_t)max_atoms * max_atoms, 0.0);
+    ws->lasso_b.assign((size_t)max_atoms, 0.0);
 #undef ALLOC
     ws->hp_hash = 0;
     ws->hp_atoms = 2 * (size_t)kFpParts;  // right behind the partials: one readback
@@ -693,7 +759,8 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ws->hp_sums = ws->hp_stage + 4 * (size_t)na;
     ws->hp_w = ws->hp_sums + 6 * (size_t)na + 8;
     ws->hp_rows = ws->hp_w + (size_t)na;
-    ws->hpin_cap = ws->hp_rows + (size_t)(na + 2) * (na + 2) + 64;
+    ws->hp_slots = ws->hp_rows + (size_t)(na + 2) * (na + 2) + 64;
+    ws->hpin_cap = ws->hp_slots + (size_t)na / 2 + 8;
     if (hipHostMalloc(reinterpret_cast<void**>(&ws->hpin), ws->hpin_cap * 8, 0) != hipSuccess) {
       (void)hipGetLastError();
       sfw_workspace_destroy(ws);

@@ -159,15 +159,18 @@ struct sfw_workspace {
   size_t apart_cap = 0;
   sfw_argmax* best = nullptr;  // [1]
 
-  // LASSO columns a_n = H * g_n, [max_atoms][vcap], valid for the first lasso_k atoms of the
-  // cached theta list, for the y / H fingerprints, shapes and convolution kind below
+  // LASSO columns a = H * g of unit atoms, cached by atom parameters: slot s of cols
+  // [max_atoms][vcap] holds the column of slot_theta[s] when slot_ok[s]; gram_ok[s][t] marks
+  // the valid entries of lasso_G (indexed by slot) and lasso_b[s] = <a_s, y>. All of it holds
+  // for the y / H fingerprints, shapes and convolution kind below.
   float* cols = nullptr;
-  int lasso_k = 0;
+  int* lasso_slots = nullptr;  // device [max_atoms]: slot list of the Gram rows being computed
   const float* lasso_y = nullptr;
   unsigned long long lasso_yhash = 0, lasso_hhash = 0;
   sfw_dims lasso_vol{0, 0, 0}, lasso_psf{0, 0, 0};
   bool lasso_mfma = false;
-  std::vector<float> lasso_thetas;  // [lasso_k][5]
+  std::vector<float> slot_theta;         // [max_atoms][5]
+  std::vector<char> slot_ok, gram_ok;    // [max_atoms], [max_atoms][max_atoms]
   std::vector<double> lasso_G, lasso_b;  // [max_atoms][max_atoms], [max_atoms]
   // device [2 kFpParts + 3 max_atoms]: per-block fingerprint partials of y and H, then a copy
   // of the atoms (one readback)
@@ -181,6 +184,7 @@ struct sfw_workspace {
   double* hpin = nullptr;
   size_t hpin_cap = 0;
   size_t hp_hash = 0, hp_atoms = 0, hp_stage = 0, hp_sums = 0, hp_w = 0, hp_rows = 0;
+  size_t hp_slots = 0;  // [max_atoms] int32 slot list on its way to lasso_slots
 
   // optional per-kernel-class event timing (sfw_profile_begin / end)
   bool prof_on = false;
@@ -275,14 +279,15 @@ hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const dou
 hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
                                sfw_argmax* best, hipStream_t st);
 // out[c] = sum_v a[v] * cols[c][v] for c < k, out[k] = sum_v a[v] * y[v] (float64).
-hipError_t launch_dots(const float* a, const float* cols, int k, size_t colstride,
-                       const float* y, size_t nvox, double* dpart, int nblocks, double* out,
-                       hipStream_t st);
+// dots of column a with the k columns cols + slots[c] * colstride and with y (out[k])
+hipError_t launch_dots(const float* a, const float* cols, const int* slots, int k,
+                       size_t colstride, const float* y, size_t nvox, double* dpart,
+                       int nblocks, double* out, hipStream_t st);
 // Gram row over box = {x0, x1, y0, y1, z0, z1} (half-open; x0, x1, nx and colstride multiples
 // of 4) that holds every nonzero of a.
-hipError_t launch_dots_box(const float* a, const float* cols, int k, size_t colstride,
-                           const float* y, sfw_dims vol, const int box[6], double* dpart,
-                           int dpart_cap, double* out, hipStream_t st);
+hipError_t launch_dots_box(const float* a, const float* cols, const int* slots, int k,
+                           size_t colstride, const float* y, sfw_dims vol, const int box[6],
+                           double* dpart, int dpart_cap, double* out, hipStream_t st);
 hipError_t launch_any_nonfinite(const float* v, size_t n, int* flag, hipStream_t st);
 
 // ---- Fourier-domain grid certificate (sfw_fft.hip)

@@ -782,7 +782,8 @@ __device__ __forceinline__ double dot4(const float4& a, const float4& b) {
 }
 
 __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
-                                              const float* __restrict__ cols, int k,
+                                              const float* __restrict__ cols,
+                                              const int* __restrict__ slots, int k,
                                               size_t colstride, const float* __restrict__ y,
                                               size_t nvox, double* __restrict__ dpart) {
   __shared__ double red[kDotsCols][4];
@@ -804,7 +805,7 @@ __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
 #pragma unroll
     for (int u = 0; u < kDotsCols; ++u) {
       const int c = min(c0 + u, k);
-      b[u] = c < k ? cols + (size_t)c * colstride : y;
+      b[u] = c < k ? cols + (size_t)slots[c] * colstride : y;
       vec = vec && (((uintptr_t)b[u]) & 15) == 0;
     }
     double s[kDotsCols] = {0.0, 0.0, 0.0, 0.0};
@@ -846,12 +847,14 @@ __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
 }
 
 // Gram row of column a over a box that holds every nonzero of a: out partials
-// dpart[blockIdx.x][c] = sum over the box of a * col_c (c < k: cached columns, c = k: y) for
+// dpart[blockIdx.x][c] = sum over the box of a * col_c (c < k: cached column slots[c], c = k:
+// y) for
 // the columns of chunk blockIdx.y (cpb per chunk). The box is rows (y, z) of bw4 float4 starting
 // at x0 (x0, nx and the column stride multiples of 4); a thread keeps its kDotsHold float4 of a
 // in registers across the columns.
 __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
-                                                  const float* __restrict__ cols, int k,
+                                                  const float* __restrict__ cols,
+                                                  const int* __restrict__ slots, int k,
                                                   size_t colstride, const float* __restrict__ y,
                                                   int nx, int ny, int x0, int bw4, int y0,
                                                   int bh, int z0, int nrows, int cpb,
@@ -880,7 +883,7 @@ __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
 #pragma unroll
     for (int u = 0; u < kDotsCols; ++u) {
       const int c = min(c0 + u, ce - 1);
-      b[u] = c < k ? cols + (size_t)c * colstride : y;
+      b[u] = c < k ? cols + (size_t)slots[c] * colstride : y;
     }
     double s[kDotsCols] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1141,20 +1144,20 @@ hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, i
   return hipGetLastError();
 }
 
-hipError_t launch_dots(const float* a, const float* cols, int k, size_t colstride,
-                       const float* y, size_t nvox, double* dpart, int nblocks, double* out,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_dots, dim3(nblocks), dim3(256), 0, st, a, cols, k, colstride, y, nvox,
-                     dpart);
+hipError_t launch_dots(const float* a, const float* cols, const int* slots, int k,
+                       size_t colstride, const float* y, size_t nvox, double* dpart,
+                       int nblocks, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dots, dim3(nblocks), dim3(256), 0, st, a, cols, slots, k, colstride, y,
+                     nvox, dpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dots_final, dim3(k + 1), dim3(256), 0, st, dpart, nblocks, k + 1, out);
   return hipGetLastError();
 }
 
-hipError_t launch_dots_box(const float* a, const float* cols, int k, size_t colstride,
-                           const float* y, sfw_dims vol, const int box[6], double* dpart,
-                           int dpart_cap, double* out, hipStream_t st) {
+hipError_t launch_dots_box(const float* a, const float* cols, const int* slots, int k,
+                           size_t colstride, const float* y, sfw_dims vol, const int box[6],
+                           double* dpart, int dpart_cap, double* out, hipStream_t st) {
   const int bw4 = (box[1] - box[0]) / 4, bh = box[3] - box[2], nrows = bh * (box[5] - box[4]);
   const int E = nrows * bw4;
   if (E <= 0) return hipErrorInvalidValue;
@@ -1165,8 +1168,9 @@ hipError_t launch_dots_box(const float* a, const float* cols, int k, size_t cols
   const int cpb = (groups + chunks - 1) / chunks * kDotsCols;
   chunks = (k + 1 + cpb - 1) / cpb;
   if ((size_t)nbx * (k + 1) > (size_t)dpart_cap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dots_box, dim3(nbx, chunks), dim3(256), 0, st, a, cols, k, colstride, y,
-                     vol.nx, vol.ny, box[0], bw4, box[2], bh, box[4], nrows, cpb, dpart);
+  hipLaunchKernelGGL(k_dots_box, dim3(nbx, chunks), dim3(256), 0, st, a, cols, slots, k,
+                     colstride, y, vol.nx, vol.ny, box[0], bw4, box[2], bh, box[4], nrows, cpb,
+                     dpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dots_final, dim3(k + 1), dim3(256), 0, st, dpart, nbx, k + 1, out);

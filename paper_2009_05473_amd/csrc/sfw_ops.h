@@ -53,10 +53,10 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
 int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float lambda,
                    const float* sg, int ns, const float* dg, int nd, float T, float* eta_out);
 // LASSO columns for unit-weight atoms i in [i0, i1) already staged in ws->ak.
-int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int i0, int i1);
+int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int atom, int slot);
 // out[0..i] = <a_i, a_j> (j <= i), out[i + 1] = <a_i, y>, float64 on the device.
-int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int i,
-                const float* theta, double* out);
+int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int slot,
+                const float* theta, int nd, double* out);
 // min_{w >= 0} 1/2 w^T G w - c^T w.
 int nnqp(const std::vector<double>& G, const std::vector<double>& c, int k, std::vector<double>& w);
 

@@ -6,6 +6,8 @@ the descents reach beyond that is parity unpinned (the paper leaves the descent 
 open).
 """
 import ctypes
+import json
+import os
 
 import numpy as np
 import pytest
@@ -113,3 +115,30 @@ def test_solve_capacity_and_iteration_cap(L, ws):
     atoms, stats, code = L.sfw_solve(ws, dev(y), dev(psf), lam, opts1)
     assert code == L.SFW_ENOCONV
     assert atoms.shape[0] == 1 and stats["converged"] == 0
+
+
+def test_solve_matches_oracle_golden_c2(L):
+    """BSFW on the 64 x 64 x 32, 10-atom workload (15 x 15 x 31 PSF: the VALU convolution and
+    a larger certificate grid) against the oracle's solution stored by
+    tests/golden/make_solve_golden.py: same atom count, every centre within 0.05 voxel of the
+    oracle's, criterion within 1e-4 (relative)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "solve_c2_bsfw.json")
+    with open(path) as fh:
+        golden = json.load(fh)
+    prob = synth.draw_problem("c2")
+    psf = f32(prob.psf)
+    clean = oracle.blur(oracle.render(prob.shape, prob.atoms_true), psf)
+    y = f32(synth.make_observation(clean, prob.noise_unit, prob.config.noise_rel))
+    ws = L.Workspace(prob.shape, psf.shape, 64)
+    try:
+        opts = L.default_options(mode="BSFW", sigma_grid=golden["sigma_grid"],
+                                 d_grid=golden["d_grid"])
+        say("sfw_solve c2 BSFW vs stored oracle solution")
+        atoms, stats, code = L.sfw_solve(ws, dev(y), dev(psf), golden["lambda"], opts)
+    finally:
+        ws.close()
+    assert code == L.SFW_OK
+    ref = np.asarray(golden["atoms"])
+    assert atoms.shape[0] == ref.shape[0]
+    assert match(atoms, ref, 0.05)
+    assert abs(stats["criterion"] - golden["criterion"]) <= 1e-4 * golden["criterion"]
