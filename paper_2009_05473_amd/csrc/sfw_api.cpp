@@ -112,7 +112,7 @@ AtomK make_atomk(double w, double mx, double my, double mz, double sigma, double
   k.hd = (float)(0.5 * d);
   k.hdm1 = k.hd - 1.f;
   k.c = (float)(-d * std::log2(sigma) - 1.0 + 0.52876637294489772);
-  k.pad = 0.f;
+  k.rcut2 = atom_rcut2(sigma, d);
   return k;
 }
 
@@ -150,6 +150,8 @@ int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
   if (rc) return rc;
   ws->q_valid = true;
   GradPlan gp = plan_grad(vol, n);
+  if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
+    return fail(SFW_EINVAL, "gradient partial buffer too small");
   {
     ProfScope ps(ws, kProfGrad);
     SFW_HIP(launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream));
@@ -173,6 +175,8 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
   else
     SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
   GradPlan gp = plan_grad(vol, n);
+  if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
+    return fail(SFW_EINVAL, "gradient partial buffer too small");
   {
     ProfScope ps(ws, kProfEtaGrad);
     SFW_HIP(launch_grad(gp, ws->ak, n, q, vol, ws->gpart, ws->stream));
@@ -727,7 +731,9 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ALLOC(ws->atoms_dev, sizeof(sfw_atom) * na, "atoms");
     ALLOC(ws->ak, sizeof(AtomK) * na, "atom constants");
     const size_t nxy = (size_t)vol_max.nx * vol_max.ny;
-    const size_t gtiles = ((nxy + kGradThreads - 1) / kGradThreads) * ((vol_max.nz + 15) / 16);
+    // gradient tiles: 16 x 16 (y, x) patches times z chunks of at least 16 planes
+    const size_t gtiles = (size_t)((vol_max.nx + 15) / 16) * ((vol_max.ny + 15) / 16) *
+                          ((vol_max.nz + 15) / 16);
     ws->gpart_cap = gtiles * na * 6;
     ALLOC(ws->gpart, ws->gpart_cap * 4, "gradient partials");
     const size_t cblocks = (size_t)((vol_max.nx + kConvTX - 1) / kConvTX) *

@@ -17,9 +17,21 @@ namespace sfw {
 //   u * log2(e) = exp2(hd * l + c)        (u = ||s - m||^d / (2 sigma^d))
 //   u * log2(e) / r^2 = exp2(hdm1 * l + c)
 // where hd = d / 2, hdm1 = hd - 1 and c = -d log2(sigma) - 1 + log2(log2(e)).
+// Per-atom constants of the render / gradient kernels: weight, centre, d/2, d/2 - 1,
+// c = -d log2(sigma) - 1 + log2(log2 e) (so u log2 e = exp2(d/2 log2 r^2 + c)), and rcut2, the
+// squared radius beyond which the atom is exactly zero in float32 (see kAtomCutU).
 struct AtomK {
-  float w, mx, my, mz, hd, c, hdm1, pad;
+  float w, mx, my, mz, hd, c, hdm1, rcut2;
 };
+
+// u = (r / sigma)^d / 2 at which an atom's value exp(-u) = exp2(-u log2 e) is exactly zero in
+// float32: 2^-158 is below the smallest denormal, with room for the approximate log2 / exp2.
+constexpr double kAtomCutU = 110.0;
+// Squared cut radius sigma (2 kAtomCutU)^(1/d), widened by a relative 1e-4 and 1e-3 voxel.
+__host__ __device__ inline float atom_rcut2(double sigma, double d) {
+  const double r = sigma * pow(2.0 * kAtomCutU, 1.0 / d) * 1.0001 + 1e-3;
+  return (float)(r * r);
+}
 
 // One candidate of the grid-certificate maximum.
 struct ArgPart {

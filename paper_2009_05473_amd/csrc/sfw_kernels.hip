@@ -80,7 +80,7 @@ __global__ void k_prep(const sfw_atom* __restrict__ atoms, int n, int unit_weigh
     k.hd = 0.5f * a.d;
     k.hdm1 = k.hd - 1.0f;
     k.c = (float)(-(double)a.d * log2((double)a.sigma) - 1.0 + kLog2Log2e);
-    k.pad = 0.f;
+    k.rcut2 = atom_rcut2((double)a.sigma, (double)a.d);
     ak[i] = k;
     return;
   }
@@ -155,24 +155,70 @@ __global__ void k_store_atoms(AtomArgs args, int n, AtomK* __restrict__ dst) {
   if (i < n) dst[i] = args.a[i];
 }
 
+// Voxel tiles of the render and gradient kernels: a block of 256 threads owns a 16 x 16 patch
+// of (y, x) columns (thread t: x = 16 bx + t % 16, y = 16 by + t / 16), so a wave owns a
+// 16 x 4 patch; tiles are numbered bx + tiles_x * by.
+constexpr int kTile = 16;
+struct TileXY {
+  int x, y;     // this thread's column
+  bool in;      // inside the plane
+  int x0, y0w;  // wave patch origin (wave-uniform)
+};
+__device__ __forceinline__ TileXY tile_xy(int tile, int nx, int ny) {
+  const int tiles_x = (nx + kTile - 1) / kTile;
+  const int by = tile / tiles_x, bx = tile - by * tiles_x;
+  TileXY t;
+  t.x0 = bx * kTile;
+  t.x = t.x0 + (int)(threadIdx.x & (kTile - 1));
+  t.y = by * kTile + (int)(threadIdx.x / kTile);
+  t.y0w = __builtin_amdgcn_readfirstlane(by * kTile + (int)((threadIdx.x & ~63u) / kTile));
+  t.in = t.x < nx && t.y < ny;
+  return t;
+}
+
+// Bounding box of the voxels of the calling wave (its 16 x 4 patch over planes zlo..zhi,
+// clipped to the volume). misses(k) tells that atom k is exactly zero on all of them: its cut
+// ball does not reach the box. Wave-uniform.
+struct WaveBox {
+  float xlo, xhi, ylo, yhi, zlo, zhi;
+  __device__ bool misses(const AtomK& k) const {
+    const float dx = fmaxf(0.f, fmaxf(xlo - k.mx, k.mx - xhi));
+    const float dy = fmaxf(0.f, fmaxf(ylo - k.my, k.my - yhi));
+    const float dz = fmaxf(0.f, fmaxf(zlo - k.mz, k.mz - zhi));
+    return fmaf(dx, dx, fmaf(dy, dy, dz * dz)) > k.rcut2;
+  }
+};
+__device__ __forceinline__ WaveBox wave_box(const TileXY& t, int nx, int ny, int zlo, int zhi) {
+  WaveBox b;
+  b.xlo = (float)t.x0;
+  b.xhi = (float)min(t.x0 + kTile - 1, nx - 1);
+  b.ylo = (float)min(t.y0w, ny - 1);
+  b.yhi = (float)min(t.y0w + 64 / kTile - 1, ny - 1);
+  b.zlo = (float)zlo;
+  b.zhi = (float)max(zhi, zlo);
+  return b;
+}
+
 // ------------------------------------------------------------------ render
 
-// f(s) = sum_n w_n exp(-u_n(s)) for every voxel; thread = one (y, x) column, kRenderVPT z.
+// f(s) = sum_n w_n exp(-u_n(s)) for every voxel; thread = one (y, x) column of a 16 x 16 tile
+// (blockIdx.x), kRenderVPT planes (blockIdx.y). Atoms whose cut ball misses the wave's voxels
+// are skipped: they add exact zeros there.
 __global__ __launch_bounds__(256) void k_render(const AtomK* __restrict__ ak, int n, int nx,
                                                 int ny, int nz, float* __restrict__ f) {
   constexpr int VPT = kRenderVPT;
-  const int p = blockIdx.x * 256 + threadIdx.x;
+  const TileXY t = tile_xy(blockIdx.x, nx, ny);
   const int nxy = nx * ny;
-  if (p >= nxy) return;
-  const int y = p / nx;
-  const int x = p - y * nx;
+  const int x = min(t.x, nx - 1), y = min(t.y, ny - 1);
   const int z0 = blockIdx.y * VPT;
   const float fx = (float)x, fy = (float)y, fz0 = (float)z0;
+  const WaveBox wb = wave_box(t, nx, ny, z0, min(z0 + VPT, nz) - 1);
   float acc[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) acc[j] = 0.f;
   for (int a = 0; a < n; ++a) {
     const AtomK k = ak[a];
+    if (wb.misses(k)) continue;  // exactly zero on every voxel of this wave
     const float dx = fx - k.mx;
     const float dy = fy - k.my;
     const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
@@ -187,7 +233,8 @@ __global__ __launch_bounds__(256) void k_render(const AtomK* __restrict__ ak, in
       acc[j] = fmaf(k.w, g, acc[j]);
     }
   }
-  float* col = f + (size_t)z0 * nxy + p;
+  if (!t.in) return;
+  float* col = f + (size_t)z0 * nxy + (size_t)y * nx + x;
 #pragma unroll
   for (int j = 0; j < VPT; ++j)
     if (z0 + j < nz) col[(size_t)j * nxy] = acc[j];
@@ -580,11 +627,10 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
   const int txy = tile % ntile_xy;
   const int tz = tile / ntile_xy;
   const int nxy = nx * ny;
-  const int p = txy * kGradThreads + tid;
-  const bool pin = p < nxy;
-  const int pp = pin ? p : 0;
-  const int y = pp / nx;
-  const int x = pp - y * nx;
+  const TileXY t = tile_xy(txy, nx, ny);
+  const bool pin = t.in;
+  const int x = min(t.x, nx - 1), y = min(t.y, ny - 1);
+  const int p = y * nx + x;
   const int z0 = tz * VPT;
   float qv[VPT];
 #pragma unroll
@@ -594,8 +640,17 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
   const int a0 = blockIdx.y * apg;
   const int a1 = min(n, a0 + apg);
   const int wave = tid / 64;
+  const WaveBox wb = wave_box(t, nx, ny, z0, min(z0 + VPT, nz) - 1);
   for (int a = a0; a < a1; ++a) {
     const AtomK k = ak[a];
+    if (wb.misses(k)) {  // every term of this wave is exactly zero
+      if ((tid & 63) == 0) {
+        float* rr = red[wave][a - a0];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) rr[c] = 0.f;
+      }
+      continue;
+    }
     const float dx = fx - k.mx;
     const float dy = fy - k.my;
     const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
@@ -963,8 +1018,7 @@ ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz) {
 GradPlan plan_grad(sfw_dims vol, int n_atoms) {
   GradPlan p;
   p.vpt = vol.nz >= 64 ? 64 : (vol.nz >= 32 ? 32 : 16);
-  const int nxy = vol.nx * vol.ny;
-  p.ntile_xy = (nxy + kGradThreads - 1) / kGradThreads;
+  p.ntile_xy = ((vol.nx + kTile - 1) / kTile) * ((vol.ny + kTile - 1) / kTile);
   p.ntile_z = (vol.nz + p.vpt - 1) / p.vpt;
   p.ntiles = p.ntile_xy * p.ntile_z;
   const int target_blocks = 512;
@@ -1021,8 +1075,8 @@ hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t
 }
 
 hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st) {
-  const int nxy = vol.nx * vol.ny;
-  dim3 grid((nxy + 255) / 256, (vol.nz + kRenderVPT - 1) / kRenderVPT);
+  const int tiles = ((vol.nx + kTile - 1) / kTile) * ((vol.ny + kTile - 1) / kTile);
+  dim3 grid(tiles, (vol.nz + kRenderVPT - 1) / kRenderVPT);
   hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
   return hipGetLastError();
 }
