@@ -365,14 +365,39 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
 
 // Columns a_i = H * g(theta_i) (unit weight) for i in [i0, i1) into ws->cols; atoms staged in
 // ws->ak with unit weights.
-// Column of the unit atom whose constants are ws->ak[atom] into LASSO slot `slot`.
-int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int atom, int slot) {
+static bool column_box(const float* theta, const sfw_dims& psf, const sfw_dims& vol, int box[6]);
+
+// Column of the unit atom whose constants are ws->ak[atom] (parameters theta, host) into LASSO
+// slot `slot`. On the matrix-core path only the column's support box is convolved, in
+// z-chunks spread over the chip; the rest of the slot is cleared (the column is exactly zero
+// there, and later Gram rows read it).
+int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int atom, int slot,
+               const float* theta) {
+  float* col = ws->cols + (size_t)slot * ws->vcap;
   {
     ProfScope ps(ws, kProfLassoRender);
     SFW_HIP(launch_render(ws->ak + atom, 1, vol, ws->f, ws->stream));
   }
-  return conv_psf(ws, p, vol, false, ws->f, ws->cols + (size_t)slot * ws->vcap, kEpiPlain,
-                  nullptr, kProfLassoConv);
+  int box[6];
+  if (!p.mfma || !column_box(theta, p.psf, vol, box))
+    return conv_psf(ws, p, vol, false, ws->f, col, kEpiPlain, nullptr, kProfLassoConv);
+  ProfScope ps(ws, kProfLassoConv);
+  const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
+  SFW_HIP(hipMemsetAsync(col, 0, V * sizeof(float), ws->stream));
+  ConvRegion rg;
+  rg.tx0 = box[0] / 16;
+  rg.tx1 = (box[1] + 15) / 16;
+  rg.ty0 = box[2] / 4;
+  rg.ty1 = (box[3] + 3) / 4;
+  rg.z0 = box[4];
+  rg.z1 = box[5];
+  // z-chunks: about two blocks per CU, at least 4 output planes each
+  const int tiles = (rg.tx1 - rg.tx0) * (rg.ty1 - rg.ty0);
+  const int depth = rg.z1 - rg.z0;
+  const int chunks = std::max(1, std::min((512 + tiles - 1) / tiles, (depth + 3) / 4));
+  rg.zchunk = (depth + chunks - 1) / chunks;
+  SFW_HIP(launch_conv_mfma_region(ws->f, ws->am_fwd, p.psf, vol, rg, col, ws->stream));
+  return SFW_OK;
 }
 
 // Box holding every nonzero of the column a = H * g of a unit atom theta = (m, sigma, d): the
@@ -547,7 +572,7 @@ int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
       SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
     }
     for (const auto& f : fresh) {
-      int rc = op_columns(ws, p, vol, f.first, f.second);
+      int rc = op_columns(ws, p, vol, f.first, f.second, thetas + 5 * (size_t)f.first);
       if (rc) return rc;
       ws->slot_ok[f.second] = 1;
     }

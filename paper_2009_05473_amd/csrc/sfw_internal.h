@@ -275,6 +275,15 @@ int mfma_conv_blocks(sfw_dims vol);
 hipError_t launch_conv_mfma(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
                             int epi, float* out, const float* yobs, double* dpart,
                             hipStream_t st);
+// Output region of the matrix-core convolution: 16-wide x tiles [tx0, tx1), 4-high y tiles
+// [ty0, ty1) and output planes [z0, z1) in chunks of zchunk planes (one per blockIdx.z).
+struct ConvRegion {
+  int tx0, tx1, ty0, ty1, z0, z1, zchunk;
+};
+ConvRegion conv_region_full(sfw_dims vol);
+// Plain convolution restricted to a region (outputs elsewhere are not written).
+hipError_t launch_conv_mfma_region(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
+                                   const ConvRegion& rg, float* out, hipStream_t st);
 
 hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q, sfw_dims vol,
                        float* gpart, hipStream_t st);

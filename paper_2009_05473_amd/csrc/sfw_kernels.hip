@@ -437,11 +437,16 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // buffers: planes 2t + 4 and 2t + 5 are stored at iteration t from registers loaded one
 // iteration earlier, with one barrier per iteration.
 // Accumulator layout (16x16x4 f32): lane l holds rows 4 (l / 16) + 0..3 of column l % 16.
+//
+// Output region: tiles (tx0 + blockIdx.x, ty0 + blockIdx.y) and output planes
+// [zlo + blockIdx.z * zchunk, min(zhi, that + zchunk)); a block streams the input planes from
+// cz below its first output plane (rounded down to an even plane, never below 0). The whole
+// volume is tx0 = ty0 = 0, zlo = 0, zhi = zchunk = nz.
 template <int STEPS, int EPI>
 __global__ __launch_bounds__(512) void k_conv_mfma(
     const float* __restrict__ in, const float* __restrict__ amat, int px, int py, int pz,
-    int nx, int ny, int nz, float* __restrict__ out, const float* __restrict__ yobs,
-    double* __restrict__ dpart) {
+    int nx, int ny, int nz, int tx0, int ty0, int zlo, int zhi, int zchunk,
+    float* __restrict__ out, const float* __restrict__ yobs, double* __restrict__ dpart) {
   constexpr int NBUF = 8;
   constexpr int PLANE = kMfmaPatchMax;
   constexpr int SH = (STEPS + 1) / 2;  // taps of the first half (the second gets the rest)
@@ -452,11 +457,15 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
   const int wave = tid >> 6;
   const int rowi = wave & 3, half = wave >> 2;
   const int n = lane & 15, g = lane >> 4;
-  const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4;
+  const int x0 = (tx0 + (int)blockIdx.x) * 16, y0 = (ty0 + (int)blockIdx.y) * 4;
   const int y = y0 + rowi, x = x0 + n;
   const int cx = (px - 1) / 2, cy = (py - 1) / 2, cz = (pz - 1) / 2;
   const size_t nxy = (size_t)nx * ny;
   const int PW = 16 + px - 1, PH = 4 + py - 1, PN = PW * PH;
+  const int oc0 = zlo + (int)blockIdx.z * zchunk, oc1 = min(zhi, oc0 + zchunk);
+  // first input plane streamed: even, so every output plane sees the same even / odd split and
+  // summation order as in a whole-volume launch (bit-identical results)
+  const int zb = max(0, oc0 - cz) & ~1;
 
   // staging: thread owns patch element tid (in-plane offset, -1 = zero)
   const bool lown = tid < PN;
@@ -466,7 +475,8 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
     const int iy = y0 + cy - (py - 1) + row, ix = x0 + cx - (px - 1) + col;
     if (iy >= 0 && iy < ny && ix >= 0 && ix < nx) goff = iy * nx + ix;
   }
-  auto fetch = [&](int plane) -> float {
+  auto fetch = [&](int l) -> float {  // input plane zb + l
+    const int plane = zb + l;
     const bool ok = plane < nz && goff >= 0;
     const float t = in[(size_t)min(plane, nz - 1) * nxy + max(goff, 0)];
     return ok ? t : 0.f;
@@ -499,14 +509,15 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
   auto yat = [&](int o) -> float { return yobs[(size_t)min(max(o, 0), nz - 1) * nxy + col]; };
   float y1 = 0.f, y2 = 0.f;
   if (EPI == kEpiResidual) {
-    y1 = yat(-cz);
-    y2 = yat(1 - cz);
+    y1 = yat(zb - cz);
+    y2 = yat(zb + 1 - cz);
   }
   __syncthreads();
 
   floatx4 accE = {0.f, 0.f, 0.f, 0.f}, accO = {0.f, 0.f, 0.f, 0.f};
   float ssf = 0.f, ob_prev = 0.f;
-  const int T = (nz - 1 + cz) / 2 + 1;  // the last iteration completes output plane nz - 1
+  // iteration t completes output planes zb - cz + 2t and the next; the last one reaches oc1 - 1
+  const int T = oc1 > oc0 ? (oc1 - 1 - (zb - cz)) / 2 + 1 : 0;
   auto roll2 = [&](floatx4& acc) {
     const float u0 = __shfl_down(acc[0], 16, 64);
     const float u1 = __shfl_down(acc[1], 16, 64);
@@ -518,7 +529,7 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
   // one iteration: planes 2t (E) and 2t + 1 (O); FULL: both planes inside the volume
   auto iteration = [&](int t, auto full) {
     constexpr bool FULL = decltype(full)::value;
-    const int ze = 2 * t, zo = 2 * t + 1;
+    const int ze = 2 * t, zo = 2 * t + 1;  // local input planes (absolute: zb + local)
     const float na = fetch(ze + 6), nb = fetch(ze + 7);
     const float* bufE = patch[ze & (NBUF - 1)];
     const float* bufO = patch[zo & (NBUF - 1)];
@@ -534,7 +545,7 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
         accE = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bE[s], accE, 0, 0, 0);
         accO = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bO[s], accO, 0, 0, 0);
       }
-    } else if (ze < nz) {
+    } else if (zb + ze < nz) {
       float bE[SH];
 #pragma unroll
       for (int s = 0; s < SH; ++s) bE[s] = bufE[boff[s]];
@@ -566,14 +577,14 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
       const float O0 = o0 + xc[2][n], O1 = o1 + xc[3][n];
       const float v1 = E0 + ob_prev, v2 = E1 + O0;
       ob_prev = O1;
-      const int p1 = 2 * t - cz, p2 = p1 + 1;
+      const int p1 = zb - cz + 2 * t, p2 = p1 + 1;
       float yn1 = 0.f, yn2 = 0.f;
       if (EPI == kEpiResidual) {
         yn1 = yat(p1 + 2);
         yn2 = yat(p2 + 2);
       }
       if (out_lane) {
-        if (p1 >= 0 && p1 < nz) {
+        if (p1 >= oc0 && p1 < oc1) {
           const size_t v = (size_t)p1 * nxy + col;
           if (EPI == kEpiPlain) {
             out[v] = v1;
@@ -583,7 +594,7 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
             ssf = fmaf(rv, rv, ssf);
           }
         }
-        if (p2 >= 0 && p2 < nz) {
+        if (p2 >= oc0 && p2 < oc1) {
           const size_t v = (size_t)p2 * nxy + col;
           if (EPI == kEpiPlain) {
             out[v] = v2;
@@ -600,13 +611,15 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
       }
     }
   };
-  const int TF = min(T, nz / 2);  // iterations whose two planes are both inside the volume
+  const int TF = min(T, max(0, (nz - zb) / 2));  // iterations with both planes in the volume
   int t = 0;
   for (; t < TF; ++t) iteration(t, std::true_type{});
   for (; t < T; ++t) iteration(t, std::false_type{});
   if (EPI == kEpiResidual && half == 0) {
     double ss = shfl_sum_d((double)ssf);
-    if (lane == 0) dpart[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + rowi] = ss;
+    if (lane == 0)
+      dpart[(((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 4 + rowi] =
+          ss;
   }
 }
 
@@ -1135,31 +1148,56 @@ int mfma_conv_blocks(sfw_dims vol) { return ((vol.nx + 15) / 16) * ((vol.ny + 3)
 
 template <int STEPS, int EPI>
 static hipError_t mfma_t(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
-                         float* out, const float* yobs, double* dpart, hipStream_t st) {
-  dim3 grid((vol.nx + 15) / 16, (vol.ny + 3) / 4);
+                         const ConvRegion& rg, float* out, const float* yobs, double* dpart,
+                         hipStream_t st) {
+  const int chunks = (rg.z1 - rg.z0 + rg.zchunk - 1) / rg.zchunk;
+  dim3 grid(rg.tx1 - rg.tx0, rg.ty1 - rg.ty0, chunks);
   hipLaunchKernelGGL((k_conv_mfma<STEPS, EPI>), grid, dim3(512), 0, st, in, amat, psf.nx, psf.ny,
-                     psf.nz, vol.nx, vol.ny, vol.nz, out, yobs, dpart);
+                     psf.nz, vol.nx, vol.ny, vol.nz, rg.tx0, rg.ty0, rg.z0, rg.z1, rg.zchunk, out,
+                     yobs, dpart);
   return hipGetLastError();
 }
 
 template <int EPI>
 static hipError_t mfma_e(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
-                         float* out, const float* yobs, double* dpart, hipStream_t st) {
+                         const ConvRegion& rg, float* out, const float* yobs, double* dpart,
+                         hipStream_t st) {
   switch (mfma_steps(psf.nx, psf.ny)) {
-    case 1: return mfma_t<1, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
-    case 3: return mfma_t<3, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
-    case 7: return mfma_t<7, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
-    case 13: return mfma_t<13, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
-    case 21: return mfma_t<21, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
-    default: return mfma_t<32, EPI>(in, amat, psf, vol, out, yobs, dpart, st);
+    case 1: return mfma_t<1, EPI>(in, amat, psf, vol, rg, out, yobs, dpart, st);
+    case 3: return mfma_t<3, EPI>(in, amat, psf, vol, rg, out, yobs, dpart, st);
+    case 7: return mfma_t<7, EPI>(in, amat, psf, vol, rg, out, yobs, dpart, st);
+    case 13: return mfma_t<13, EPI>(in, amat, psf, vol, rg, out, yobs, dpart, st);
+    case 21: return mfma_t<21, EPI>(in, amat, psf, vol, rg, out, yobs, dpart, st);
+    default: return mfma_t<32, EPI>(in, amat, psf, vol, rg, out, yobs, dpart, st);
   }
+}
+
+ConvRegion conv_region_full(sfw_dims vol) {
+  ConvRegion rg;
+  rg.tx0 = 0;
+  rg.tx1 = (vol.nx + 15) / 16;
+  rg.ty0 = 0;
+  rg.ty1 = (vol.ny + 3) / 4;
+  rg.z0 = 0;
+  rg.z1 = vol.nz;
+  rg.zchunk = std::max(vol.nz, 1);
+  return rg;
 }
 
 hipError_t launch_conv_mfma(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
                             int epi, float* out, const float* yobs, double* dpart,
                             hipStream_t st) {
-  if (epi == kEpiResidual) return mfma_e<kEpiResidual>(in, amat, psf, vol, out, yobs, dpart, st);
-  return mfma_e<kEpiPlain>(in, amat, psf, vol, out, yobs, dpart, st);
+  const ConvRegion rg = conv_region_full(vol);
+  if (epi == kEpiResidual)
+    return mfma_e<kEpiResidual>(in, amat, psf, vol, rg, out, yobs, dpart, st);
+  return mfma_e<kEpiPlain>(in, amat, psf, vol, rg, out, yobs, dpart, st);
+}
+
+hipError_t launch_conv_mfma_region(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
+                                   const ConvRegion& rg, float* out, hipStream_t st) {
+  if (rg.tx1 <= rg.tx0 || rg.ty1 <= rg.ty0 || rg.z1 <= rg.z0 || rg.zchunk < 1)
+    return hipSuccess;
+  return mfma_e<kEpiPlain>(in, amat, psf, vol, rg, out, nullptr, nullptr, st);
 }
 
 hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q, sfw_dims vol,

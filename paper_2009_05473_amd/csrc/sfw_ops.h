@@ -53,7 +53,8 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
 int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float lambda,
                    const float* sg, int ns, const float* dg, int nd, float T, float* eta_out);
 // LASSO columns for unit-weight atoms i in [i0, i1) already staged in ws->ak.
-int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int atom, int slot);
+int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int atom, int slot,
+               const float* theta);
 // out[0..i] = <a_i, a_j> (j <= i), out[i + 1] = <a_i, y>, float64 on the device.
 int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int slot,
                 const float* theta, int nd, double* out);
