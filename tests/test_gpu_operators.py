@@ -153,6 +153,39 @@ def test_residual_grad_edge(L, ws_big, conv_path):
     assert rel_err(loss0.cpu().numpy()[0], 0.5 * np.sum(y * y)) <= 1e-6
 
 
+def test_residual_grad_cut_atoms(L, ws_big):
+    """Atoms skipped where they are exactly zero: many narrow atoms (most tiles skip most of
+    them), centres outside the volume, and wide long-tailed atoms (cut radius past the whole
+    volume, never skipped), against the oracle's dense sums."""
+    shape = (40, 96, 80)
+    rng = np.random.default_rng(2024)
+    psf = f32(synth.gaussian_psf(1.0, 2.0, (15, 9, 9)))
+    atoms = np.zeros((30, 6))
+    atoms[:, 0] = rng.uniform(0.5, 2.0, 30)
+    atoms[:, 1] = rng.uniform(-6, 86, 30)     # x, some outside [0, 79]
+    atoms[:, 2] = rng.uniform(-6, 102, 30)    # y
+    atoms[:, 3] = rng.uniform(-4, 44, 30)     # z
+    atoms[:, 4] = rng.uniform(0.5, 1.2, 30)   # narrow
+    atoms[:, 5] = rng.uniform(1.8, 3.0, 30)
+    atoms[:3, 4] = (3.5, 4.0, 3.8)            # wide and long-tailed
+    atoms[:3, 5] = (1.2, 1.25, 1.3)
+    atoms = f32(atoms)
+    truth = f32(synth.random_atoms(rng, 6, shape, margin=4))
+    y = f32(oracle.blur(oracle.render(shape, truth), psf) + 0.01 * rng.standard_normal(shape))
+    lam = 0.3
+    say("sfw_residual_grad cut atoms", shape, len(atoms))
+    phi = L.sfw_forward(ws_big, dev(psf), dev(atoms), shape)
+    r, loss, grad = L.sfw_residual_grad(ws_big, dev(psf), dev(y), lam, dev(atoms))
+    torch.cuda.synchronize()
+    C, g, r_o, _ = oracle.criterion_and_grad(y, atoms, psf, lam)
+    assert rel_l2(phi.cpu().numpy(), oracle.blur(oracle.render(shape, atoms), psf)) <= 1e-5
+    assert rel_l2(r.cpu().numpy(), r_o) <= 1e-5
+    assert rel_err(loss.cpu().numpy()[0], C) <= 1e-5
+    gg = grad.cpu().numpy()
+    assert np.all(np.isfinite(gg))
+    assert rel_l2(gg, g) <= 1e-4
+
+
 def test_adjoint_parity(L, ws_big, conv_path):
     rng = np.random.default_rng(5)
     shape = (31, 45, 50)
