@@ -35,10 +35,10 @@ if ROOT not in sys.path:
 PEAK_FP32_TFLOPS = 157.3   # vector and matrix FP32, dense
 PEAK_HBM_GBS = 8000.0
 
-# The dominant kernel: the plain-epilogue MFMA convolution (adjoint Phi^T r and the LASSO
-# columns; one launch of it per step is timed, in the conv_adjoint class).
-ROOF_CLASS = "conv_adjoint"
-ROOF_KERNEL = "k_conv_mfma (plain epilogue)"
+# The dominant kernel: the MFMA convolution with the residual epilogue (r = y - H*f and the
+# float64 loss partials), one launch per step, timed in the conv_residual class.
+ROOF_CLASS = "conv_residual"
+ROOF_KERNEL = "k_conv_mfma (residual epilogue)"
 
 # Algorithmic ALU work per voxel-atom pair in FMA-slot units (one VALU instruction = 1 slot,
 # one v_exp/v_log/v_rcp = 4 slots: quarter rate, measured), reported as 2 FLOP per slot.
@@ -56,9 +56,9 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_05473_amd", "csrc", "sfw_kernels.
 KERNEL_START = "template <int STEPS, int EPI>\n__global__ __launch_bounds__(512) void k_conv_mfma("
 SECTION_RULE = "\n// ------------------------------------------------------------------"
 CONV_TRAFFIC = {
-    "fetch_kib": 7266.6, "write_kib": 4096.0,            # k_conv_mfma<21, 0>, per dispatch
-    "copy_mib": 256, "copy_fetch_kib": 131087.25, "copy_write_kib": 262144.0,
-    "source_sha256": "6cce3b9915745470318b76e62eb957db0db791295a91267716354c8194d8f38b",
+    "fetch_kib": 11371.0, "write_kib": 4104.0,           # k_conv_mfma<21, 1>, per dispatch
+    "copy_mib": 256, "copy_fetch_kib": 131087.94, "copy_write_kib": 262144.0,
+    "source_sha256": "8df5ca4424e70c3806d6945788b39c23abcd899c519bb00c6b6c45899c6b60f7",
 }
 
 
@@ -255,7 +255,6 @@ def main():
         "grad": ("alu", 2.0 * V * N * GRAD_SLOTS_PER_PAIR, PEAK_FP32_TFLOPS),
         "conv_residual": ("mfma", conv_flops, PEAK_FP32_TFLOPS),
         "conv_adjoint": ("mfma", conv_flops, PEAK_FP32_TFLOPS),
-        "lasso_conv": ("mfma", conv_flops, PEAK_FP32_TFLOPS),
     }
     ps = max(args.profile_steps, 1)
     breakdown = {}

@@ -257,9 +257,10 @@ hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t
                                int* bh_out, hipStream_t st);
 hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st);
 
-enum ConvEpilogue { kEpiPlain = 0, kEpiResidual = 1, kEpiArgmax = 2 };
+enum ConvEpilogue { kEpiPlain = 0, kEpiResidual = 1, kEpiArgmax = 2, kEpiColumn = 3 };
 // out = conv(in, W) with W in [ky][kx][kzp] layout (already flipped for a correlation).
-//  kEpiPlain:    out[v] = conv
+//  kEpiPlain:    out[v] = conv (kEpiColumn: the same, for region launches of the matrix-core
+//                kernel)
 //  kEpiResidual: out[v] = yobs[v] - conv; dpart[block] = sum over the block of out^2
 //  kEpiArgmax:   eta = conv * scale; out[v] = eta if out != nullptr;
 //                apart[block] = max of eta over the block, flat index idx_base + v

@@ -586,7 +586,7 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
       if (out_lane) {
         if (p1 >= oc0 && p1 < oc1) {
           const size_t v = (size_t)p1 * nxy + col;
-          if (EPI == kEpiPlain) {
+          if (EPI != kEpiResidual) {
             out[v] = v1;
           } else {
             const float rv = y1 - v1;
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
         }
         if (p2 >= oc0 && p2 < oc1) {
           const size_t v = (size_t)p2 * nxy + col;
-          if (EPI == kEpiPlain) {
+          if (EPI != kEpiResidual) {
             out[v] = v2;
           } else {
             const float rv = y2 - v2;
@@ -1197,7 +1197,8 @@ hipError_t launch_conv_mfma_region(const float* in, const float* amat, sfw_dims 
                                    const ConvRegion& rg, float* out, hipStream_t st) {
   if (rg.tx1 <= rg.tx0 || rg.ty1 <= rg.ty0 || rg.z1 <= rg.z0 || rg.zchunk < 1)
     return hipSuccess;
-  return mfma_e<kEpiPlain>(in, amat, psf, vol, rg, out, nullptr, nullptr, st);
+  // its own instantiation (same plain epilogue), so profiles tell it from whole-volume launches
+  return mfma_e<kEpiColumn>(in, amat, psf, vol, rg, out, nullptr, nullptr, st);
 }
 
 hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q, sfw_dims vol,
