@@ -75,7 +75,7 @@ typedef struct {
   float trunc_T;                     /* grid kernels keep g >= exp(-T) cube, default 12 */
   double eta_tol;                    /* continue while eta* > 1 + eta_tol, default 1e-3 */
   double prune_rel;                  /* drop w <= prune_rel * max w, default 1e-6 */
-  double merge_tol;                  /* fuse masses closer than this per coordinate, 2e-2 */
+  double merge_tol;                  /* fuse masses closer than this per coordinate, 5e-2 */
   int32_t max_iter;                  /* outer iterations, default 200 */
   int32_t ascent_max_iter;           /* default 200 */
   int32_t slide_max_iter;            /* default 1000 */

@@ -35,7 +35,7 @@ PRUNE_REL = 1e-6  # "remove zero-weighted masses": w <= PRUNE_REL * max(w)
 # eta = 1 exactly (its KKT condition), so in floating point the test needs a margin.
 ETA_TOL = 1e-3
 # Two masses closer than this in every coordinate of (m, sigma, d) are one mass.
-MERGE_TOL = 2e-2
+MERGE_TOL = 5e-2
 
 __all__ = [
     "T_TRUNC", "PRUNE_REL", "ETA_TOL", "MERGE_TOL", "merge_coincident", "coords", "atom_profile", "render", "blur", "adjoint",

@@ -174,7 +174,25 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
     SFW_HIP(launch_store_atoms(hk, n, ws->ak, ws->stream));
   else
     SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
-  GradPlan gp = plan_grad(vol, n);
+  // only the tiles where some point's atom is nonzero (its cut ball) carry terms
+  int box[6] = {vol.nx, 0, vol.ny, 0, vol.nz, 0};
+  const int nv[3] = {vol.nx, vol.ny, vol.nz};
+  for (int i = 0; i < n; ++i) {
+    const double R = std::sqrt((double)hk[i].rcut2);
+    const double m[3] = {hk[i].mx, hk[i].my, hk[i].mz};
+    for (int a = 0; a < 3; ++a) {
+      const int lo = (int)std::max(0.0, std::floor(m[a] - R));
+      const int hi = (int)std::min((double)nv[a], std::ceil(m[a] + R) + 1.0);
+      box[2 * a] = std::min(box[2 * a], lo);
+      box[2 * a + 1] = std::max(box[2 * a + 1], hi);
+    }
+  }
+  for (int a = 0; a < 3; ++a)
+    if (box[2 * a + 1] <= box[2 * a]) {  // nothing inside the volume: one tile of zeros
+      box[2 * a] = 0;
+      box[2 * a + 1] = 1;
+    }
+  GradPlan gp = plan_grad_box(vol, n, box);
   if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
     return fail(SFW_EINVAL, "gradient partial buffer too small");
   {
@@ -657,7 +675,7 @@ int sfw_default_options(sfw_options* o) {
   o->trunc_T = 12.0f;
   o->eta_tol = 1e-3;
   o->prune_rel = 1e-6;
-  o->merge_tol = 2e-2;
+  o->merge_tol = 5e-2;
   o->max_iter = 200;
   o->ascent_max_iter = 200;
   o->slide_max_iter = 1000;

@@ -107,11 +107,14 @@ constexpr int kProfPool = 16384;
 
 struct GradPlan {
   int vpt = 16;       // z voxels per thread (template parameter)
-  int ntile_xy = 0;   // blocks over the flattened (y, x) plane
+  int ntile_xy = 0;   // 16 x 16 (y, x) tiles covered
   int ntile_z = 0;
   int ntiles = 0;     // ntile_xy * ntile_z
   int groups = 1;     // atom groups (second grid dimension)
   int apg = 0;        // atoms per group
+  // covered region: x tiles [rx0, rx0 + rtx), y tiles from ry0, z tiles from rz0 (the whole
+  // volume unless restricted to where the atoms are nonzero)
+  int rx0 = 0, ry0 = 0, rtx = 1, rz0 = 0;
 };
 
 }  // namespace sfw
@@ -244,6 +247,8 @@ int hip_fail(hipError_t e, const char* what);
 // ---- launchers (sfw_kernels.hip); each returns a hipError_t from the launch
 ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz);
 GradPlan plan_grad(sfw_dims vol, int n_atoms);
+// Plan over the tiles that meet box {x0, x1, y0, y1, z0, z1} (voxels, half-open).
+GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6]);
 
 // One launch: atom constants (atoms may be null when n == 0) and the forward / adjoint PSF
 // operands for the matrix-core (mfma) or VALU (kzp) convolution (H may be null).

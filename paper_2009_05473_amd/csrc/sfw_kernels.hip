@@ -164,9 +164,10 @@ struct TileXY {
   bool in;      // inside the plane
   int x0, y0w;  // wave patch origin (wave-uniform)
 };
-__device__ __forceinline__ TileXY tile_xy(int tile, int nx, int ny) {
-  const int tiles_x = (nx + kTile - 1) / kTile;
-  const int by = tile / tiles_x, bx = tile - by * tiles_x;
+__device__ __forceinline__ TileXY tile_xy(int tile, int nx, int ny, int rx0 = 0, int ry0 = 0,
+                                          int rtx = -1) {
+  const int tiles_x = rtx > 0 ? rtx : (nx + kTile - 1) / kTile;
+  const int by = ry0 + tile / tiles_x, bx = rx0 + tile % tiles_x;
   TileXY t;
   t.x0 = bx * kTile;
   t.x = t.x0 + (int)(threadIdx.x & (kTile - 1));
@@ -632,15 +633,16 @@ template <int VPT>
 __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__ ak, int n,
                                                        int apg, const float* __restrict__ q,
                                                        int nx, int ny, int nz, int ntile_xy,
+                                                       int rx0, int ry0, int rtx, int rz0,
                                                        float* __restrict__ gpart) {
   constexpr int NW = kGradThreads / 64;
   __shared__ float red[NW][kGradMaxAtomsPerGroup][6];
   const int tid = threadIdx.x;
   const int tile = blockIdx.x;
   const int txy = tile % ntile_xy;
-  const int tz = tile / ntile_xy;
+  const int tz = rz0 + tile / ntile_xy;
   const int nxy = nx * ny;
-  const TileXY t = tile_xy(txy, nx, ny);
+  const TileXY t = tile_xy(txy, nx, ny, rx0, ry0, rtx);
   const bool pin = t.in;
   const int x = min(t.x, nx - 1), y = min(t.y, ny - 1);
   const int p = y * nx + x;
@@ -1031,7 +1033,8 @@ ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz) {
 GradPlan plan_grad(sfw_dims vol, int n_atoms) {
   GradPlan p;
   p.vpt = vol.nz >= 64 ? 64 : (vol.nz >= 32 ? 32 : 16);
-  p.ntile_xy = ((vol.nx + kTile - 1) / kTile) * ((vol.ny + kTile - 1) / kTile);
+  p.rtx = (vol.nx + kTile - 1) / kTile;
+  p.ntile_xy = p.rtx * ((vol.ny + kTile - 1) / kTile);
   p.ntile_z = (vol.nz + p.vpt - 1) / p.vpt;
   p.ntiles = p.ntile_xy * p.ntile_z;
   const int target_blocks = 512;
@@ -1044,6 +1047,24 @@ GradPlan plan_grad(sfw_dims vol, int n_atoms) {
   p.apg = apg;
   p.groups = (n_atoms + apg - 1) / apg;
   if (p.groups < 1) p.groups = 1;
+  return p;
+}
+
+GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6]) {
+  GradPlan p = plan_grad(vol, n_atoms);
+  p.rx0 = box[0] / kTile;
+  p.rtx = std::max(1, (box[1] + kTile - 1) / kTile - p.rx0);
+  p.ry0 = box[2] / kTile;
+  const int rty = std::max(1, (box[3] + kTile - 1) / kTile - p.ry0);
+  p.ntile_xy = p.rtx * rty;
+  p.rz0 = box[4] / p.vpt;
+  p.ntile_z = std::max(1, (box[5] + p.vpt - 1) / p.vpt - p.rz0);
+  p.ntiles = p.ntile_xy * p.ntile_z;
+  // atom groups for the smaller grid (same rule as plan_grad)
+  int groups = (512 + p.ntiles - 1) / p.ntiles;
+  groups = std::max(1, std::min(groups, n_atoms));
+  p.apg = std::max(1, std::min(kGradMaxAtomsPerGroup, (n_atoms + groups - 1) / groups));
+  p.groups = std::max(1, (n_atoms + p.apg - 1) / p.apg);
   return p;
 }
 
@@ -1208,15 +1229,15 @@ hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q
   switch (p.vpt) {
     case 64:
       hipLaunchKernelGGL(k_grad<64>, grid, dim3(kGradThreads), 0, st, ak, n, p.apg, q, vol.nx,
-                         vol.ny, vol.nz, p.ntile_xy, gpart);
+                         vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart);
       break;
     case 32:
       hipLaunchKernelGGL(k_grad<32>, grid, dim3(kGradThreads), 0, st, ak, n, p.apg, q, vol.nx,
-                         vol.ny, vol.nz, p.ntile_xy, gpart);
+                         vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart);
       break;
     default:
       hipLaunchKernelGGL(k_grad<16>, grid, dim3(kGradThreads), 0, st, ak, n, p.apg, q, vol.nx,
-                         vol.ny, vol.nz, p.ntile_xy, gpart);
+                         vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart);
       break;
   }
   return hipGetLastError();
