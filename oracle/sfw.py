@@ -39,7 +39,7 @@ MERGE_TOL = 5e-2
 
 __all__ = [
     "T_TRUNC", "PRUNE_REL", "ETA_TOL", "MERGE_TOL", "merge_coincident", "coords", "atom_profile", "render", "blur", "adjoint",
-    "criterion", "criterion_and_grad", "eta_point", "lut_radius", "lut_kernel",
+    "criterion", "criterion_and_grad", "forward_vjp", "eta_point", "lut_radius", "lut_kernel",
     "grid_certificate", "grid_argmax", "lasso_columns", "lasso_weights", "ascent",
     "slide", "prune", "solve", "SolveResult", "max_grid_certificate",
 ]
@@ -163,6 +163,36 @@ def criterion_and_grad(y, atoms, psf, lam):
         grad[n, 4] = -w * (d / s) * qgu.sum()
         grad[n, 5] = w * np.sum(qgu * log_rs)
     return C, grad, r, q
+
+
+def forward_vjp(g, atoms, psf):
+    """Vector-Jacobian product of the forward model: d<g, Phi mu>/d(w, mx, my, mz, sigma, d).
+
+    Section 1.1 observation model, differentiated as in section 2 (analytic derivatives).
+    <g, H * f> = <Phi^T g, f>, so with q = Phi^T g and f = sum_n w_n exp(-u_n):
+      d/dw     = sum q g
+      d/dm     = w d sum q g u (s - m) / ||s - m||^2
+      d/dsigma = w (d / sigma) sum q g u
+      d/dd     = -w sum q g u ln(||s - m|| / sigma)
+    with the centre voxel contributing 0 to the m, sigma and d terms (limits).
+    """
+    atoms = np.asarray(atoms, dtype=np.float64).reshape(-1, 6)
+    g = np.asarray(g, dtype=np.float64)
+    q = adjoint(g, psf)
+    out = np.zeros_like(atoms)
+    for n, (w, mx, my, mz, s, d) in enumerate(atoms):
+        dx, dy, dz, r2, u, gn, nz = _atom_terms(g.shape, mx, my, mz, s, d)
+        qg = q * gn
+        qgu = qg * u
+        inv_r2 = np.where(nz, 1.0 / np.where(nz, r2, 1.0), 0.0)
+        log_rs = np.where(nz, 0.5 * np.log(np.where(nz, r2, 1.0)) - math.log(s), 0.0)
+        out[n, 0] = qg.sum()
+        out[n, 1] = w * d * np.sum(qgu * dx * inv_r2)
+        out[n, 2] = w * d * np.sum(qgu * dy * inv_r2)
+        out[n, 3] = w * d * np.sum(qgu * dz * inv_r2)
+        out[n, 4] = w * (d / s) * qgu.sum()
+        out[n, 5] = -w * np.sum(qgu * log_rs)
+    return out
 
 
 def eta_point(q, lam, theta):

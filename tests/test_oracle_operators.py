@@ -212,6 +212,34 @@ def test_gradient_matches_central_differences():
     np.testing.assert_allclose(grad, fd, rtol=2e-6, atol=1e-7 * np.abs(fd).max())
 
 
+def test_forward_vjp_matches_central_differences():
+    """d<g, Phi mu>/dtheta against central differences of the FP64 forward model."""
+    y, psf, atoms = _small_problem(seed=11)
+    g = np.random.default_rng(12).standard_normal(y.shape)
+    vjp = oracle.forward_vjp(g, atoms, psf)
+    h = 1e-5
+    fd = np.zeros_like(atoms)
+    for n in range(atoms.shape[0]):
+        for p in range(6):
+            a = atoms.copy(); a[n, p] += h
+            lp = np.sum(g * oracle.blur(oracle.render(y.shape, a), psf))
+            a[n, p] -= 2 * h
+            lm = np.sum(g * oracle.blur(oracle.render(y.shape, a), psf))
+            fd[n, p] = (lp - lm) / (2 * h)
+    np.testing.assert_allclose(vjp, fd, rtol=2e-6, atol=1e-7 * np.abs(fd).max())
+
+
+def test_forward_vjp_of_residual_is_data_gradient():
+    """With g = r = y - Phi mu, the product is minus the data-fit part of dC/dtheta."""
+    y, psf, atoms = _small_problem(seed=13)
+    lam = 0.25
+    _, grad, r, _ = oracle.criterion_and_grad(y, atoms, psf, lam)
+    vjp = oracle.forward_vjp(r, atoms, psf)
+    data = grad.copy()
+    data[:, 0] -= lam
+    np.testing.assert_allclose(vjp, -data, rtol=1e-10, atol=1e-12 * np.abs(data).max())
+
+
 def test_gradient_atom_on_voxel_centre_is_finite():
     y, psf, atoms = _small_problem()
     atoms[0, 1:4] = np.round(atoms[0, 1:4])  # centre exactly on a voxel
