@@ -140,6 +140,15 @@ int sfw_residual_grad(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
 int sfw_adjoint(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
                 const float* r, float* q_out);
 
+/* Vector-Jacobian product of the forward model (section 1.1 observation model; the analytic
+ * derivatives of section 2): for a volume g, grad[n] = d<g, Phi mu>/d(w, mx, my, mz, sigma, d)
+ * = sum_s (Phi^T g)(s) d(w_n g_n)(s)/dtheta_n, untruncated. It is what reverse-mode
+ * differentiation of sfw_forward needs; with g = r it is minus the data-fit part of the
+ * gradient of sfw_residual_grad. The workspace's q becomes Phi^T g.
+ * g: device [V]; atoms: device [n]; grad_out: device [n] (not NULL when n > 0). */
+int sfw_forward_vjp(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
+                    const float* g, const sfw_atom* atoms, int n, sfw_atom* grad_out);
+
 /* Grid certificate and its maximum (section 1.3 step 1, lookup table of section 2):
  * eta_ij(m) = (1/lambda) sum_{||t||_inf <= R_ij} g(t; 0, sigma_i, d_j) q(m + t),
  * q = Phi^T r, R_ij = ceil(sigma_i (2T)^(1/d_j)), T = trunc_T (<= 0 selects 12),

@@ -22,8 +22,8 @@ SFW_MAX_GRID = 16
 EXPORTED = (
     "sfw_default_options", "sfw_workspace_create", "sfw_workspace_destroy",
     "sfw_workspace_set_stream", "sfw_last_error", "sfw_forward", "sfw_residual_grad",
-    "sfw_adjoint", "sfw_certificate", "sfw_eta_points", "sfw_lasso_weights", "sfw_solve",
-    "sfw_profile_begin", "sfw_profile_end",
+    "sfw_adjoint", "sfw_forward_vjp", "sfw_certificate", "sfw_eta_points", "sfw_lasso_weights",
+    "sfw_solve", "sfw_profile_begin", "sfw_profile_end",
 )
 SFW_PROF_KINDS = 16
 
@@ -97,6 +97,7 @@ def _load():
         "sfw_forward": (i32, [vp, vp, D, D, vp, i32, vp]),
         "sfw_residual_grad": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp, vp, vp]),
         "sfw_adjoint": (i32, [vp, vp, D, D, vp, vp]),
+        "sfw_forward_vjp": (i32, [vp, vp, D, D, vp, vp, i32, vp]),
         "sfw_certificate": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp, i32, f32, vp, vp]),
         "sfw_eta_points": (i32, [vp, D, vp, f32, vp, i32, vp, vp]),
         "sfw_lasso_weights": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp]),
@@ -239,6 +240,19 @@ def sfw_adjoint(ws: Workspace, H, r, q_out=None):
     check(lib.sfw_adjoint(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape), dims(r.shape),
                           _dev_ptr(r, "float32", "r"), _dev_ptr(q_out, "float32", "q_out")))
     return q_out
+
+
+def sfw_forward_vjp(ws: Workspace, H, g, atoms, grad_out=None):
+    """Returns grad[n, 6] = d<g, Phi mu>/d(w, mx, my, mz, sigma, d) per atom."""
+    import torch
+    n = 0 if atoms is None else int(atoms.shape[0])
+    grad = grad_out if grad_out is not None else torch.empty((max(n, 1), 6), dtype=torch.float32,
+                                                             device="cuda")
+    check(lib.sfw_forward_vjp(ws.handle, _dev_ptr(H, "float32", "H"), dims(H.shape),
+                              dims(g.shape), _dev_ptr(g, "float32", "g"),
+                              _dev_ptr(atoms, "float32", "atoms") if n else None, n,
+                              _dev_ptr(grad, "float32", "grad") if n else None))
+    return grad[:n]
 
 
 def sfw_certificate(ws: Workspace, H, r, lam, sigma_grid, d_grid, trunc_T=12.0, want_eta=False,

@@ -162,6 +162,25 @@ int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
   return SFW_OK;
 }
 
+int op_vjp(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* gvol,
+           const sfw_atom* atoms_dev, int n, sfw_atom* grad_out) {
+  int rc = conv_psf(ws, p, vol, true, gvol, ws->q, kEpiPlain, nullptr, kProfConvAdjoint);
+  if (rc) return rc;
+  ws->q_valid = true;
+  if (n == 0) return SFW_OK;
+  GradPlan gp = plan_grad(vol, n);
+  if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
+    return fail(SFW_EINVAL, "gradient partial buffer too small");
+  {
+    ProfScope ps(ws, kProfGrad);
+    SFW_HIP(launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream));
+  }
+  ProfScope ps(ws, kProfGradFinalize);
+  SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, nullptr, 0, atoms_dev, 0.f, ws->dres,
+                               grad_out, nullptr, ws->stream, true));
+  return SFW_OK;
+}
+
 int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double lambda,
                   const double* thetas, int n, double* eta_out, double* grad_out) {
   // unit-weight atom constants computed on the host in float64, staged through pinned memory
@@ -938,6 +957,22 @@ int sfw_adjoint(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol, c
     return conv_psf(ws, p, vol, true, r, q_out, kEpiPlain, nullptr, kProfConvAdjoint);
   } catch (...) {
     return fail(SFW_EINVAL, "unexpected exception in sfw_adjoint");
+  }
+}
+
+int sfw_forward_vjp(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
+                    const float* g, const sfw_atom* atoms, int n, sfw_atom* grad_out) {
+  try {
+    int rc = check_ws_fit(ws, vol, &psf, n);
+    if (rc) return rc;
+    if (!H || !g) return fail(SFW_EINVAL, "H or g is NULL");
+    if (n > 0 && (!atoms || !grad_out)) return fail(SFW_EINVAL, "atoms or grad_out is NULL");
+    PsfPlan p = plan_psf(vol, psf);
+    rc = prep_all(ws, H, p, false, true, atoms, n, false);
+    if (rc) return rc;
+    return op_vjp(ws, p, vol, g, atoms, n, grad_out);
+  } catch (...) {
+    return fail(SFW_EINVAL, "unexpected exception in sfw_forward_vjp");
   }
 }
 

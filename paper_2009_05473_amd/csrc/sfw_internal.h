@@ -298,11 +298,12 @@ hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q
 // with S_g = sum q g, S_u = sum q g u', S_l = sum q g u' log2 r^2,
 // S_m = sum q g u' (s - m) / r^2 and u' = u log2(e). If loss_part != nullptr,
 // sums[6 n] = 1/2 sum of the nloss loss partials. If grad_out != nullptr, also writes the
-// gradient of C (float) using atoms and lambda.
+// gradient of C (float) using atoms and lambda, or with vjp the vector-Jacobian product
+// sum_s q df/d(w, m, sigma, d) of the forward model (lambda unused).
 hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const double* loss_part,
                                 int nloss, const sfw_atom* atoms, float lambda,
                                 double* sums, sfw_atom* grad_out, double* loss_out,
-                                hipStream_t st);
+                                hipStream_t st, bool vjp = false);
 hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
                                sfw_argmax* best, hipStream_t st);
 // out[c] = sum_v a[v] * cols[c][v] for c < k, out[k] = sum_v a[v] * y[v] (float64).

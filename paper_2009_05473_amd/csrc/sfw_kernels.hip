@@ -719,7 +719,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
 __global__ __launch_bounds__(256) void k_grad_finalize(
     const float* __restrict__ gpart, int ntiles, int n, const double* __restrict__ loss_part,
     int nloss, const sfw_atom* __restrict__ atoms, float lambda, double* __restrict__ sums,
-    sfw_atom* __restrict__ grad_out, double* __restrict__ loss_out) {
+    sfw_atom* __restrict__ grad_out, double* __restrict__ loss_out, int vjp) {
   __shared__ double red[6][4];
   const int tid = threadIdx.x;
   const int a = blockIdx.x;
@@ -743,14 +743,18 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
       if (grad_out) {
         const sfw_atom at = atoms[a];
         const double w = at.w, d = at.d, sg = at.sigma;
+        // dC/dtheta = lambda [theta = w] - sum_s q df/dtheta; the vector-Jacobian product of
+        // the forward model is sum_s q df/dtheta itself (lambda = 0, opposite sign)
+        const double sgn = vjp ? -1.0 : 1.0;
+        const double lam = vjp ? 0.0 : (double)lambda;
         sfw_atom g;
-        g.w = (float)((double)lambda - S[0]);
-        const double fm = -w * d * kLn2;
+        g.w = (float)(sgn * (lam - S[0]));
+        const double fm = -sgn * w * d * kLn2;
         g.mx = (float)(fm * S[3]);
         g.my = (float)(fm * S[4]);
         g.mz = (float)(fm * S[5]);
-        g.sigma = (float)(-w * (d / sg) * kLn2 * S[1]);
-        g.d = (float)(w * (0.5 * kLn2 * kLn2 * S[2] - log(sg) * kLn2 * S[1]));
+        g.sigma = (float)(-sgn * w * (d / sg) * kLn2 * S[1]);
+        g.d = (float)(sgn * w * (0.5 * kLn2 * kLn2 * S[2] - log(sg) * kLn2 * S[1]));
         grad_out[a] = g;
       }
     }
@@ -1245,9 +1249,10 @@ hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q
 
 hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const double* loss_part,
                                 int nloss, const sfw_atom* atoms, float lambda, double* sums,
-                                sfw_atom* grad_out, double* loss_out, hipStream_t st) {
+                                sfw_atom* grad_out, double* loss_out, hipStream_t st,
+                                bool vjp) {
   hipLaunchKernelGGL(k_grad_finalize, dim3(n + 1), dim3(256), 0, st, gpart, ntiles, n, loss_part,
-                     nloss, atoms, lambda, sums, grad_out, loss_out);
+                     nloss, atoms, lambda, sums, grad_out, loss_out, vjp ? 1 : 0);
   return hipGetLastError();
 }
 

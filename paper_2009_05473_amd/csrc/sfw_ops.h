@@ -46,6 +46,10 @@ int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, 
 int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
              float lambda, const sfw_atom* atoms_dev, int n, float* r_out, double* loss_out,
              sfw_atom* grad_out);
+// q = Phi^T g (ws->q) and grad[n] = sum_s q df/d(w, m, sigma, d): the vector-Jacobian
+// product of the forward model; ws->ak must hold the n atoms' constants.
+int op_vjp(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* gvol,
+           const sfw_atom* atoms_dev, int n, sfw_atom* grad_out);
 // eta and its gradient at n points theta = (mx, my, mz, sigma, d) (host, float64); syncs.
 int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double lambda,
                   const double* thetas, int n, double* eta_out, double* grad_out);
