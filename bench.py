@@ -35,10 +35,17 @@ if ROOT not in sys.path:
 PEAK_FP32_TFLOPS = 157.3   # vector and matrix FP32, dense
 PEAK_HBM_GBS = 8000.0
 
-# The dominant kernel: the MFMA convolution with the residual epilogue (r = y - H*f and the
-# float64 loss partials), one launch per step, timed in the conv_residual class.
-ROOF_CLASS = "conv_residual"
-ROOF_KERNEL = "k_conv_mfma (residual epilogue)"
+# The dominant kernel: the certificate's inverse z pass, which multiplies the spectrum of q by
+# every pair of table-kernel spectra and transforms along z (one launch per step, timed alone
+# in the cert_zinv class). It is bound by HBM.
+ROOF_CLASS = "cert_zinv"
+ROOF_KERNEL = "k_fx_z_inverse (certificate: inverse z pass of every table-kernel pair)"
+
+# Transform lengths of the library's fixed-length (two-stage) passes; the certificate grid
+# takes the smallest of them >= max(n + R, 2R + 1) per axis when it is at most a quarter
+# above the smallest 2-3-5-smooth length.
+FIXED_LENGTHS = (16, 18, 20, 24, 25, 27, 30, 32, 36, 40, 45, 48, 50, 54, 60, 64, 72, 75, 80, 81,
+                 90, 96, 100, 108, 120, 128, 135, 144, 150, 160, 180, 192, 225, 240, 256)
 
 # Algorithmic ALU work per voxel-atom pair in FMA-slot units (one VALU instruction = 1 slot,
 # one v_exp/v_log/v_rcp = 4 slots: quarter rate, measured), reported as 2 FLOP per slot.
@@ -48,17 +55,19 @@ GRAD_SLOTS_PER_PAIR = 12 + 3 * 4    # 12 VALU + log2, exp2, exp2
 
 # HBM traffic of one launch of the roofline kernel at this workload, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
-#   bench.py --steps 2 --warmup 1 --profile-steps 0 --no-cpu-baseline --copy-probe-mib 256
+#   bench.py --steps 2 --warmup 1 --profile-steps 0 --no-cpu-baseline --no-solve
+#            --copy-probe-mib 256
 # each scaled by the same counter's reading for the known 256 MiB device copy at the end.
 # The record holds for the kernel source it was taken on: sha256 of the kernel's definition in
-# KERNEL_SOURCE (from its template line to the next section rule).
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_05473_amd", "csrc", "sfw_kernels.hip")
-KERNEL_START = "template <int STEPS, int EPI>\n__global__ __launch_bounds__(512) void k_conv_mfma("
-SECTION_RULE = "\n// ------------------------------------------------------------------"
-CONV_TRAFFIC = {
-    "fetch_kib": 11371.0, "write_kib": 4104.0,           # k_conv_mfma<21, 1>, per dispatch
-    "copy_mib": 256, "copy_fetch_kib": 131087.94, "copy_write_kib": 262144.0,
-    "source_sha256": "8df5ca4424e70c3806d6945788b39c23abcd899c519bb00c6b6c45899c6b60f7",
+# KERNEL_SOURCE (from its template line to the next section rule). None until measured.
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_05473_amd", "csrc", "sfw_fft_fixed.hip")
+KERNEL_START = ("template <int R1, int R2>\n__global__ __launch_bounds__(fx_threads(R1, R2)) "
+                "void k_fx_z_inverse(")
+SECTION_RULE = "\n// ----"
+ROOF_TRAFFIC = {
+    "fetch_kib": 13912.9, "write_kib": 68400.0,          # k_fx_z_inverse<9, 9>, per dispatch
+    "copy_mib": 256, "copy_fetch_kib": 131087.8, "copy_write_kib": 262144.0,
+    "source_sha256": "f704e2e1e3aed9bcc307d2448205cd2e4cda3ac669b12996c99839e0aee76965",
 }
 
 
@@ -74,10 +83,10 @@ def kernel_sha256():
     return hashlib.sha256(src[i:j if j > 0 else len(src)].encode()).hexdigest()
 
 
-def conv_traffic():
+def roof_traffic():
     """Counter-measured HBM bytes per launch of the roofline kernel, or None when the record
     is missing or the kernel source changed since it was taken."""
-    t = CONV_TRAFFIC
+    t = ROOF_TRAFFIC
     if t is None:
         return None
     if kernel_sha256() != t["source_sha256"]:
@@ -102,6 +111,43 @@ def parse():
                     help="after the run, copy a buffer of this many MiB on the device (the "
                          "known-size copy that scales the HBM counters of a --pmc run)")
     return ap.parse_args()
+
+
+def cert_grid(shape, sigmas, ds, T=12.0):
+    """Certificate transform lengths (x, y, z) and the largest table-kernel radius."""
+    R = max(int(np.ceil(float(np.float32(s)) * (2 * T) ** (1 / float(d))))
+            for s in sigmas for d in ds)
+
+    def good(n):
+        m = n
+        while True:
+            t = m
+            for p in (2, 3, 5):
+                while t % p == 0:
+                    t //= p
+            if t == 1:
+                return m
+            m += 1
+
+    def length(nmin):
+        g = good(nmin)
+        for L in FIXED_LENGTHS:
+            if nmin <= L <= g + g // 4:
+                return L
+        return g
+
+    nz, ny, nx = shape
+    return tuple(length(max(n + R, 2 * R + 1)) for n in (nx, ny, nz)), R
+
+
+def zinv_bytes(shape, grid, npairs):
+    """Algorithmic HBM bytes of one launch of the certificate's inverse z pass: the spectrum
+    of q (Nx Ny Nz complex), the pair spectra (one octant each), and the z < nz planes of
+    every pair's work array."""
+    Nx, Ny, Nz = grid
+    hx, hy, hz = Nx // 2 + 1, Ny // 2 + 1, Nz // 2 + 1
+    nz = shape[0]
+    return 8 * (Nx * Ny * Nz + npairs * hx * hy * hz + npairs * nz * Ny * Nx)
 
 
 def lut_taps(sigmas, ds, T=12.0):
@@ -250,21 +296,27 @@ def main():
     px, py, pz = psf.shape[2], psf.shape[1], psf.shape[0]
     taps = px * py * pz
     conv_flops = 2.0 * V * taps
-    work = {
+    grid, rmax = cert_grid(shape, sg, dg)
+    npairs = (len(sg) * len(dg) + 1) // 2
+    zbytes = zinv_bytes(shape, grid, npairs)
+    work = {  # (bound, algorithmic amount per launch, peak): FLOP vs TFLOP/s, bytes vs GB/s
         "render": ("alu", 2.0 * V * N * RENDER_SLOTS_PER_PAIR, PEAK_FP32_TFLOPS),
         "grad": ("alu", 2.0 * V * N * GRAD_SLOTS_PER_PAIR, PEAK_FP32_TFLOPS),
-        "conv_residual": ("mfma", conv_flops, PEAK_FP32_TFLOPS),
-        "conv_adjoint": ("mfma", conv_flops, PEAK_FP32_TFLOPS),
+        "cert_zinv": ("hbm", float(zbytes), PEAK_HBM_GBS),
     }
     ps = max(args.profile_steps, 1)
     breakdown = {}
     for name, (launches, ms) in prof.items():
         e = {"launches_per_step": launches / ps, "ms_per_step": ms / ps,
              "us_per_launch": ms / launches * 1e3}
+        t = ms / launches * 1e-3
         if name in work:
-            bound, flops, peak = work[name]
-            achieved = flops / (ms / launches * 1e-3) / 1e12
-            e.update({"bound": bound, "achieved_tflops": achieved, "frac": achieved / peak})
+            bound, amount, peak = work[name]
+            achieved = amount / t / (1e9 if bound == "hbm" else 1e12)
+            e.update({"bound": bound, "achieved": achieved, "frac": achieved / peak})
+        if name in ("conv_residual", "conv_adjoint"):
+            # spectral blur: the direct convolution's FLOP rate it stands in for
+            e["direct_equivalent_tflops"] = conv_flops / t / 1e12
         breakdown[name] = e
     if prof:
         fwd_grad_ms = sum(prof.get(k, (0, 0.0))[1] for k in
@@ -275,11 +327,11 @@ def main():
     # roofline of the dominant kernel, timed live over the timed region
     launches, ms = roof_prof[ROOF_CLASS]
     avg_s = ms / launches * 1e-3
-    achieved = conv_flops / avg_s / 1e12
-    roofline = {"kernel": ROOF_KERNEL, "bound": "mfma", "achieved": achieved,
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": conv_traffic(), "us_per_launch": avg_s * 1e6,
-                "flops_per_launch": conv_flops}
+    achieved = zbytes / avg_s / 1e9
+    roofline = {"kernel": ROOF_KERNEL, "bound": "hbm", "achieved": achieved,
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                "traffic": roof_traffic(), "us_per_launch": avg_s * 1e6,
+                "bytes_per_launch": zbytes, "grid": list(grid), "pairs": npairs}
 
     out = {
         "metric": "fwd+grad GVoxel*atom/s (one step = every hot-path row once)",

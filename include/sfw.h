@@ -191,7 +191,8 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
 /* Per-kernel-class device time recorded with HIP events on the workspace stream between
  * sfw_profile_begin and sfw_profile_end. Classes: "prep", "render", "conv_residual",
  * "conv_adjoint", "conv_forward", "grad", "grad_finalize", "cert_conv", "cert_argmax",
- * "lasso_render", "lasso_conv", "lasso_dots", "hash", "eta_grad", "cert_fft". Each timed
+ * "lasso_render", "lasso_conv", "lasso_dots", "hash", "eta_grad", "cert_fft" (the
+ * certificate's transforms except the inverse z pass), "cert_zinv" (that pass). Each timed
  * launch group costs an event pair on the stream (a few microseconds of device idle), so
  * time only the classes of interest when the surrounding throughput matters. */
 #define SFW_PROF_KINDS 16

@@ -22,7 +22,7 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 const char* const kProfNames[kProfCount] = {
     "prep", "render", "conv_residual", "conv_adjoint", "conv_forward", "grad",
     "grad_finalize", "cert_conv", "cert_argmax", "lasso_render", "lasso_conv", "lasso_dots",
-    "hash", "eta_grad", "cert_fft"};
+    "hash", "eta_grad", "cert_fft", "cert_zinv"};
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -78,15 +78,36 @@ int check_lambda(float lambda) {
 
 // ------------------------------------------------------------------ internal operators
 
-PsfPlan plan_psf(const sfw_dims& vol, const sfw_dims& psf) {
+PsfPlan plan_psf(const sfw_workspace* ws, const sfw_dims& vol, const sfw_dims& psf) {
   PsfPlan p;
   p.psf = psf;
   p.valu = plan_conv(vol, psf.nx, psf.ny, psf.nz);
   const char* env = std::getenv("SFW_CONV");
   const bool force_valu = env && std::strcmp(env, "valu") == 0;
+  const bool force_mfma = env && std::strcmp(env, "mfma") == 0;
+  const bool force_fft = env && std::strcmp(env, "fft") == 0;
   p.mfma = !force_valu && mfma_conv_ok(psf.nx, psf.ny, psf.nz);
-  p.nres = p.mfma ? 4 * mfma_conv_blocks(vol) : p.valu.nblocks;
+  const long long taps = (long long)psf.nx * psf.ny * psf.nz;
+  if (!force_valu && !force_mfma && (force_fft || taps >= 343) && blur_plan(vol, psf, p.blur)) {
+    const size_t rowp = (size_t)p.blur.px * p.blur.N[1];
+    p.fft = rowp * vol.nz <= ws->blur_spec_cap && rowp * p.blur.N[2] <= ws->blur_hhat_cap;
+  }
+  p.nres = p.fft ? blur_residual_parts(p.blur, vol)
+                 : (p.mfma ? 4 * mfma_conv_blocks(vol) : p.valu.nblocks);
   return p;
+}
+
+int prep_spectrum(sfw_workspace* ws, const float* H, const PsfPlan& p) {
+  if (!p.fft) return SFW_OK;
+  ProfScope ps(ws, kProfPrep);
+  if (ws->blur_tw_key[0] != p.blur.N[0] || ws->blur_tw_key[1] != p.blur.N[1] ||
+      ws->blur_tw_key[2] != p.blur.N[2]) {
+    SFW_HIP(launch_blur_twiddles(p.blur, ws->blur_tw, ws->stream));
+    for (int a = 0; a < 3; ++a) ws->blur_tw_key[a] = p.blur.N[a];
+  }
+  SFW_HIP(launch_psf_spectrum(p.blur, H, p.psf, ws->blur_hhat, ws->blur_hcache,
+                              ws->blur_changed, ws->stream));
+  return SFW_OK;
 }
 
 int prep_all(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool adj,
@@ -118,6 +139,18 @@ AtomK make_atomk(double w, double mx, double my, double mz, double sigma, double
 
 int conv_psf(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjoint,
              const float* in, float* out, int epi, const float* yobs, int kind) {
+  if (!p.fft) return conv_direct(ws, p, vol, adjoint, in, out, epi, yobs, kind);
+  if (epi != kEpiPlain && epi != kEpiResidual)
+    return fail(SFW_EINVAL, "spectral blur: unsupported epilogue");
+  if ((size_t)p.nres > ws->dpart_cap) return fail(SFW_EINVAL, "loss partial buffer too small");
+  ProfScope ps(ws, kind);
+  SFW_HIP(launch_blur(p.blur, in, vol, ws->blur_hhat, adjoint, epi, out, yobs, ws->dpart,
+                      ws->blur_spec, ws->blur_tw, ws->stream));
+  return SFW_OK;
+}
+
+int conv_direct(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjoint,
+                const float* in, float* out, int epi, const float* yobs, int kind) {
   ProfScope ps(ws, kind);
   if (p.mfma)
     SFW_HIP(launch_conv_mfma(in, adjoint ? ws->am_adj : ws->am_fwd, p.psf, vol, epi, out, yobs,
@@ -144,10 +177,23 @@ int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
     ProfScope ps(ws, kProfRender);
     SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream));
   }
-  int rc = conv_psf(ws, p, vol, false, ws->f, r, kEpiResidual, y, kProfConvResidual);
-  if (rc) return rc;
-  rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr, kProfConvAdjoint);
-  if (rc) return rc;
+  if (p.fft && p.blur.chain) {
+    // residual and adjoint share the plane pass between them (see launch_blur_residual_chain)
+    if ((size_t)p.nres > ws->dpart_cap) return fail(SFW_EINVAL, "loss partial buffer too small");
+    {
+      ProfScope ps(ws, kProfConvResidual);
+      SFW_HIP(launch_blur_residual_chain(p.blur, ws->f, vol, ws->blur_hhat, y, r, ws->dpart,
+                                         ws->blur_spec, ws->blur_tw, ws->stream));
+    }
+    ProfScope ps(ws, kProfConvAdjoint);
+    SFW_HIP(launch_blur_adjoint_chain(p.blur, vol, ws->blur_hhat, ws->q, ws->blur_spec,
+                                      ws->blur_tw, ws->stream));
+  } else {
+    int rc = conv_psf(ws, p, vol, false, ws->f, r, kEpiResidual, y, kProfConvResidual);
+    if (rc) return rc;
+    rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr, kProfConvAdjoint);
+    if (rc) return rc;
+  }
   ws->q_valid = true;
   GradPlan gp = plan_grad(vol, n);
   if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
@@ -371,10 +417,14 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
       SFW_HIP(fft_forward_volume(pl, q, vol, ws->fft_qhat, ws->stream));
     }
     {
+      ProfScope ps(ws, kProfCertZinv);
+      SFW_HIP(fft_inverse_pairs_z(pl, ws->fft_qhat, ws->fft_pairs, ws->fft_work, ws->fft_cap,
+                                  ns * nd, vol, ws->stream));
+    }
+    {
       ProfScope ps(ws, kProfCertFft);
-      SFW_HIP(fft_inverse_pairs(pl, ws->fft_qhat, ws->fft_pairs, ws->fft_work, ws->fft_cap,
-                                ns * nd, vol, 1.0f / lambda, eta_out, ws->apart, nblk,
-                                ws->stream));
+      SFW_HIP(fft_inverse_pairs_yx(pl, ws->fft_work, ws->fft_cap, ns * nd, vol, 1.0f / lambda,
+                                   eta_out, ws->apart, nblk, ws->stream));
     }
     ProfScope ps(ws, kProfCertArgmax);
     SFW_HIP(launch_argmax_final(ws->apart, nblk * ns * nd, vol, nd, ws->best, ws->stream));
@@ -405,21 +455,29 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
 static bool column_box(const float* theta, const sfw_dims& psf, const sfw_dims& vol, int box[6]);
 
 // Column of the unit atom whose constants are ws->ak[atom] (parameters theta, host) into LASSO
-// slot `slot`. On the matrix-core path only the column's support box is convolved, in
-// z-chunks spread over the chip; the rest of the slot is cleared (the column is exactly zero
-// there, and later Gram rows read it).
-int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int atom, int slot,
-               const float* theta) {
+// slot `slot`. Only the column's support box is computed: by the box kernel, which evaluates
+// the atom itself, or after a render by the matrix-core kernel in z-chunks. The rest of the
+// slot is cleared, since later Gram rows read it.
+int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* H, int atom,
+               int slot, const float* theta) {
   float* col = ws->cols + (size_t)slot * ws->vcap;
+  int box[6];
+  const bool boxed = column_box(theta, p.psf, vol, box);
+  const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
+  if (boxed && column_box_ok(p.psf)) {
+    // the atom is computed inside the convolution kernel: no rendered volume
+    ProfScope ps(ws, kProfLassoConv);
+    SFW_HIP(hipMemsetAsync(col, 0, V * sizeof(float), ws->stream));
+    SFW_HIP(launch_column_box(ws->ak + atom, H, p.psf, vol, box, col, ws->stream));
+    return SFW_OK;
+  }
   {
     ProfScope ps(ws, kProfLassoRender);
     SFW_HIP(launch_render(ws->ak + atom, 1, vol, ws->f, ws->stream));
   }
-  int box[6];
-  if (!p.mfma || !column_box(theta, p.psf, vol, box))
-    return conv_psf(ws, p, vol, false, ws->f, col, kEpiPlain, nullptr, kProfLassoConv);
+  if (!boxed || !p.mfma)
+    return conv_direct(ws, p, vol, false, ws->f, col, kEpiPlain, nullptr, kProfLassoConv);
   ProfScope ps(ws, kProfLassoConv);
-  const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
   SFW_HIP(hipMemsetAsync(col, 0, V * sizeof(float), ws->stream));
   ConvRegion rg;
   rg.tx0 = box[0] / 16;
@@ -437,14 +495,14 @@ int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int ato
   return SFW_OK;
 }
 
-// Box holding every nonzero of the column a = H * g of a unit atom theta = (m, sigma, d): the
-// rendered atom exp2(-u log2 e) is exactly zero in float32 once u = (r / sigma)^d / 2 >= 110
-// (2^-158 rounds to zero even with denormals), so g vanishes outside the ball of radius
-// sigma (220)^(1/d) and a outside that ball grown by the PSF half-widths. x bounds are widened
-// to multiples of 4 for vector loads. False when the box is the whole volume anyway.
+// Support box of the column a = H * g of a unit atom theta = (m, sigma, d): the ball where
+// u = (r / sigma)^d / 2 < kColumnCutU, of radius sigma (2 kColumnCutU)^(1/d), grown by one
+// voxel and the PSF half-widths. Outside it every tap of a meets g < exp(-kColumnCutU), and the
+// column is stored as zero there. x bounds are widened to multiples of 4 for vector loads.
+// False when the box is the whole volume anyway.
 static bool column_box(const float* theta, const sfw_dims& psf, const sfw_dims& vol, int box[6]) {
   const double sig = theta[3], d = theta[4];
-  const double R = sig * std::pow(220.0, 1.0 / d) + 1.0;
+  const double R = sig * std::pow(2.0 * kColumnCutU, 1.0 / d) + 1.0;
   const double c[3] = {(psf.nx - 1) / 2.0, (psf.ny - 1) / 2.0, (psf.nz - 1) / 2.0};
   const int n[3] = {vol.nx, vol.ny, vol.nz};
   bool whole = true;
@@ -556,7 +614,8 @@ int lasso_check_inputs(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
 // (render + blur), and only slots with a missing entry against the support get a Gram row
 // (one synchronisation for the readback).
 int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
-             double lambda, const float* thetas, int n, std::vector<double>& w, bool ak_ready) {
+             const float* H, double lambda, const float* thetas, int n, std::vector<double>& w,
+             bool ak_ready) {
   w.assign(n, 0.0);
   if (n == 0) return SFW_OK;
   const int M = ws->max_atoms;
@@ -609,7 +668,7 @@ int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
       SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
     }
     for (const auto& f : fresh) {
-      int rc = op_columns(ws, p, vol, f.first, f.second, thetas + 5 * (size_t)f.first);
+      int rc = op_columns(ws, p, vol, H, f.first, f.second, thetas + 5 * (size_t)f.first);
       if (rc) return rc;
       ws->slot_ok[f.second] = 1;
     }
@@ -729,6 +788,11 @@ void sfw_workspace_destroy(sfw_workspace* ws) {
   if (ws->fft_qhat) (void)hipFree(ws->fft_qhat);
   if (ws->fft_work) (void)hipFree(ws->fft_work);
   if (ws->fft_pairs) (void)hipFree(ws->fft_pairs);
+  if (ws->blur_spec) (void)hipFree(ws->blur_spec);
+  if (ws->blur_hhat) (void)hipFree(ws->blur_hhat);
+  if (ws->blur_tw) (void)hipFree(ws->blur_tw);
+  if (ws->blur_hcache) (void)hipFree(ws->blur_hcache);
+  if (ws->blur_changed) (void)hipFree(ws->blur_changed);
   if (ws->hpin) (void)hipHostFree(ws->hpin);
   for (hipEvent_t e : ws->prof_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ws->prof_stop) (void)hipEventDestroy(e);
@@ -802,7 +866,8 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
                            ((vol_max.ny + kConvTY - 1) / kConvTY) *
                            ((vol_max.nz + kConvRZ - 1) / kConvRZ);
     const size_t mparts = 4 * (size_t)mfma_conv_blocks(vol_max);
-    ws->dpart_cap = std::max(std::max(cblocks, mparts), (size_t)1024 * (na + 2));
+    const size_t bparts = (size_t)((vol_max.ny + 15) / 16) * vol_max.nz;  // spectral residual
+    ws->dpart_cap = std::max(std::max(std::max(cblocks, mparts), bparts), (size_t)1024 * (na + 2));
     ALLOC(ws->dpart, ws->dpart_cap * 8, "float64 partials");
     const size_t dres_n = (size_t)(na + 2) * (na + 2) + 8 * (size_t)(na + 2) + 64;
     ALLOC(ws->dres, dres_n * 8, "float64 results");
@@ -814,6 +879,35 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ALLOC(ws->best, sizeof(sfw_argmax) * 2, "argmax");
     ALLOC(ws->hashbuf, (2 * (size_t)kFpParts + 3 * (size_t)na) * 8, "fingerprints");
     ALLOC(ws->cols, (size_t)max_atoms * V * 4, "LASSO columns");
+    {
+      // spectral blur arrays for the largest plan (lengths grow with the volume and the PSF;
+      // axes past kFftMaxBlur use the direct kernels)
+      const int nmax[3] = {vol_max.nx, vol_max.ny, vol_max.nz};
+      const int cmax[3] = {(psf_max.nx - 1) / 2, (psf_max.ny - 1) / 2, (psf_max.nz - 1) / 2};
+      int L[3];
+      for (int a = 0; a < 3; ++a) {
+        L[a] = kFftMaxBlur;
+        int r1 = 0, r2 = 0;
+        for (int m = std::max(nmax[a] + cmax[a], 16); m <= kFftMaxBlur; ++m)
+          if (fft_fixed_plan(m, &r1, &r2)) {
+            L[a] = m;
+            break;
+          }
+      }
+      const size_t px = (size_t)((L[0] / 2 + 1 + 3) & ~3);
+      ws->blur_spec_cap = px * L[1] * vol_max.nz;
+      ws->blur_hhat_cap = px * L[1] * L[2];
+      ALLOC(ws->blur_spec, ws->blur_spec_cap * sizeof(float2), "blur spectrum");
+      ALLOC(ws->blur_hhat, ws->blur_hhat_cap * sizeof(float2), "PSF spectrum");
+      ALLOC(ws->blur_tw, 3 * (size_t)kFftMaxBlur * sizeof(float2), "blur twiddles");
+      ALLOC(ws->blur_hcache, (size_t)kHcacheFloats * sizeof(float), "PSF spectrum key");
+      ALLOC(ws->blur_changed, sizeof(int), "PSF spectrum flag");
+      if (hipMemset(ws->blur_hcache, 0, (size_t)kHcacheFloats * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        sfw_workspace_destroy(ws);
+        return fail(SFW_EHIP, "clearing the PSF spectrum key failed");
+      }
+    }
     ALLOC(ws->lasso_slots, (size_t)max_atoms * sizeof(int), "LASSO slot list");
     ws->slot_theta.assign(5 * (size_t)max_atoms, 0.f);
     ws->slot_ok.assign((size_t)max_atoms, 0);
@@ -917,8 +1011,10 @@ int sfw_forward(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol,
     if (rc) return rc;
     if (!H) return fail(SFW_EINVAL, "H is NULL");
     if (n > 0 && !atoms) return fail(SFW_EINVAL, "atoms is NULL");
-    PsfPlan p = plan_psf(vol, psf);
-    rc = prep_all(ws, H, p, true, false, atoms, n, false);
+    PsfPlan p = plan_psf(ws, vol, psf);
+    rc = prep_all(ws, H, p, !p.fft, false, atoms, n, false);
+    if (rc) return rc;
+    rc = prep_spectrum(ws, H, p);
     if (rc) return rc;
     return op_forward(ws, p, vol, n, phi_mu ? phi_mu : ws->phi);
   } catch (...) {
@@ -936,8 +1032,10 @@ int sfw_residual_grad(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
     if (n > 0 && !atoms) return fail(SFW_EINVAL, "atoms is NULL");
     rc = check_lambda(lambda);
     if (rc) return rc;
-    PsfPlan p = plan_psf(vol, psf);
-    rc = prep_all(ws, H, p, true, true, atoms, n, false);
+    PsfPlan p = plan_psf(ws, vol, psf);
+    rc = prep_all(ws, H, p, !p.fft, !p.fft, atoms, n, false);
+    if (rc) return rc;
+    rc = prep_spectrum(ws, H, p);
     if (rc) return rc;
     return op_cgrad(ws, p, vol, y, lambda, atoms, n, r_out, loss_out, n > 0 ? grad_out : nullptr);
   } catch (...) {
@@ -951,8 +1049,10 @@ int sfw_adjoint(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vol, c
     int rc = check_ws_fit(ws, vol, &psf, 0);
     if (rc) return rc;
     if (!H || !r || !q_out) return fail(SFW_EINVAL, "H, r or q_out is NULL");
-    PsfPlan p = plan_psf(vol, psf);
-    rc = prep_psf(ws, H, p, false, true);
+    PsfPlan p = plan_psf(ws, vol, psf);
+    rc = prep_psf(ws, H, p, false, !p.fft);
+    if (rc) return rc;
+    rc = prep_spectrum(ws, H, p);
     if (rc) return rc;
     return conv_psf(ws, p, vol, true, r, q_out, kEpiPlain, nullptr, kProfConvAdjoint);
   } catch (...) {
@@ -967,8 +1067,10 @@ int sfw_forward_vjp(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vo
     if (rc) return rc;
     if (!H || !g) return fail(SFW_EINVAL, "H or g is NULL");
     if (n > 0 && (!atoms || !grad_out)) return fail(SFW_EINVAL, "atoms or grad_out is NULL");
-    PsfPlan p = plan_psf(vol, psf);
-    rc = prep_all(ws, H, p, false, true, atoms, n, false);
+    PsfPlan p = plan_psf(ws, vol, psf);
+    rc = prep_all(ws, H, p, false, !p.fft, atoms, n, false);
+    if (rc) return rc;
+    rc = prep_spectrum(ws, H, p);
     if (rc) return rc;
     return op_vjp(ws, p, vol, g, atoms, n, grad_out);
   } catch (...) {
@@ -997,8 +1099,10 @@ int sfw_certificate(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vo
         return fail(SFW_EINVAL, "d_grid values must be finite and > 0");
     const float T = trunc_T > 0.f ? trunc_T : 12.0f;
     if (r) {
-      PsfPlan p = plan_psf(vol, psf);
-      rc = prep_psf(ws, H, p, false, true);
+      PsfPlan p = plan_psf(ws, vol, psf);
+      rc = prep_psf(ws, H, p, false, !p.fft);
+      if (rc) return rc;
+      rc = prep_spectrum(ws, H, p);
       if (rc) return rc;
       rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr, kProfConvAdjoint);
       if (rc) return rc;
@@ -1060,8 +1164,9 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
     if (rc) return rc;
     if (n == 0) return SFW_OK;
     if (!atoms || !w_out) return fail(SFW_EINVAL, "atoms or w_out is NULL");
-    PsfPlan p = plan_psf(vol, psf);
-    // PSF operands and the unit-weight constants of every atom, from the device atoms
+    PsfPlan p = plan_psf(ws, vol, psf);
+    // PSF operands (the columns use the direct kernels) and the unit-weight constants of every
+    // atom, from the device atoms
     rc = prep_all(ws, H, p, true, false, atoms, n, true);
     if (rc) return rc;
     // one synchronisation brings back the atoms and the fingerprints of y and H
@@ -1084,7 +1189,7 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
         return fail(SFW_EINVAL, "atoms: sigma and d must be > 0");
     }
     std::vector<double> w;
-    rc = op_lasso(ws, p, vol, y, lambda, th.data(), n, w, true);
+    rc = op_lasso(ws, p, vol, y, H, lambda, th.data(), n, w, true);
     if (rc) return rc;
     // stream-ordered upload from a pinned region no other call writes before synchronising
     double* hw = ws->hpin + ws->hp_w;

@@ -1,0 +1,1028 @@
+// PSF blur and its adjoint through the Fourier domain, as the paper evaluates its
+// convolutions (section 2): H * f = IDFT(DFT(f) . Hhat) on a grid N >= n + (P - 1) / 2 per
+// axis, where the wrapped-around part of the circular convolution only meets the zero
+// padding, so the volume receives exactly the zero-padded linear ("same") convolution of the
+// observation model (section 1.1). The correlation Phi^T r uses conj(Hhat).
+//
+// f and the results are real, so only the half spectrum kx <= Nx / 2 is kept. Five passes
+// over the volume, each a batch of fixed-length two-stage transforms (register DFTs, one
+// LDS exchange):
+//   x  real -> half spectrum: two real rows ride in one complex line and are separated
+//      through the conjugate symmetry of real-input spectra;
+//   y  forward, rows y < ny in, all Ny out (the strided pass of the certificate);
+//   z  forward, times Hhat, inverse, planes z < nz in and out, all in one kernel;
+//   y  inverse, rows y < ny out;
+//   x  half spectrum -> real rows, two rows per complex line, with the epilogue (plain
+//      store, or residual y - H * f with float64 partial sums of its squares).
+// Inverse transforms are forward transforms of the conjugate (IDFT(X) = conj(DFT(conj X))/N);
+// the conjugations and the 1 / (Nx Ny Nz) scale are folded into the z and last x passes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+
+#include "sfw_fft_radix.h"
+#include "sfw_internal.h"
+
+namespace sfw {
+
+namespace {
+
+using fftr::cmul;
+using fftr::Dft;
+
+constexpr int kBxPairs = 8;  // complex lines (pairs of real rows) per block of the x passes
+
+constexpr int bx_threads(int R1, int R2) {
+  const int t = kBxPairs * (R1 > R2 ? R1 : R2);
+  return (t + 63) / 64 * 64;
+}
+constexpr int bz_threads(int R1, int R2) {
+  const int t = kFxLines * (R1 > R2 ? R1 : R2);
+  return (t + 63) / 64 * 64;
+}
+
+// ---------------------------------------------------------------- x, real -> half spectrum
+
+// Rows a = y0 + l and b = y0 + kBxPairs + l (l < kBxPairs) of plane z = blockIdx.y, with
+// y0 = 2 kBxPairs blockIdx.x, form the complex line a + i b (zero beyond nx and ny). After its
+// DFT Z, A[k] = (Z[k] + conj Z[L - k]) / 2 and B[k] = (Z[k] - conj Z[L - k]) / (2i) are the
+// spectra of the two rows; k < hx = L / 2 + 1 is stored at spec[(z Ny + row) px + k].
+template <int R1, int R2>
+__global__ __launch_bounds__(bx_threads(R1, R2)) void k_bx_r2c(
+    const float* __restrict__ in, int nx, int ny, float2* __restrict__ spec, int Ny, int px,
+    int hx, const float2* __restrict__ twg) {
+  constexpr int L = R1 * R2, LS = L | 1, B = kBxPairs, NT = bx_threads(R1, R2);
+  __shared__ float2 buf[B * LS];
+  __shared__ float2 tw[L];
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = twg[i];
+  const int y0 = blockIdx.x * 2 * B, z = blockIdx.y;
+  const float* plane = in + (size_t)z * ny * nx;
+  const int t = threadIdx.x;
+  if (t < B * R2) {
+    const int j = t % R2, l = t / R2;
+    const int ya = y0 + l, yb = y0 + B + l;
+    const bool oka = ya < ny, okb = yb < ny;
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int i = j + r * R2;
+      const bool ia = oka && i < nx, ib = okb && i < nx;
+      const float a = plane[ia ? (size_t)ya * nx + i : 0];
+      const float b = plane[ib ? (size_t)yb * nx + i : 0];
+      v[r] = make_float2(ia ? a : 0.f, ib ? b : 0.f);
+    }
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) buf[l * LS + j * R1 + r] = v[r];
+  }
+  __syncthreads();
+  float2 v[R2];
+  const int j2 = t % R1, l2 = t / R1;
+  if (t < B * R1) {
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = buf[l2 * LS + j2 + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j2]);
+    }
+    Dft<R2>::run(v);
+  }
+  __syncthreads();
+  if (t < B * R1) {
+#pragma unroll
+    for (int r = 0; r < R2; ++r) buf[l2 * LS + j2 + r * R1] = v[r];
+  }
+  __syncthreads();
+  for (int e = t; e < B * hx; e += NT) {
+    const int l = e / hx, k = e - l * hx;
+    const float2 zk = buf[l * LS + k];
+    const float2 zm = buf[l * LS + (k == 0 ? 0 : L - k)];
+    const int ya = y0 + l, yb = y0 + B + l;
+    if (ya < ny)
+      spec[((size_t)z * Ny + ya) * px + k] =
+          make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    if (yb < ny)
+      spec[((size_t)z * Ny + yb) * px + k] =
+          make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+  }
+}
+
+// ---------------------------------------------------------------- z: forward, filter, inverse
+
+// Columns (x0 + c, y = blockIdx.y), c < kFxLines, x < ncols, along z (stride Ny px): planes
+// z < nz in (zero beyond), DFT, times Hhat (conj(Hhat) when conj_h), conjugate, DFT again,
+// planes z < nz written back in place. What is stored is DFT_z(conj(X Hhat)), the z part of
+// the conjugated inverse.
+template <int R1, int R2>
+__global__ __launch_bounds__(bz_threads(R1, R2)) void k_bz_filter(
+    float2* __restrict__ spec, const float2* __restrict__ hhat, int conj_h, int ncols, int Ny,
+    int px, int nz, const float2* __restrict__ twg) {
+  constexpr int L = R1 * R2, LS = L | 1, C = kFxLines, NT = bz_threads(R1, R2);
+  __shared__ float2 bufa[C * LS];
+  __shared__ float2 bufb[C * LS];
+  __shared__ float2 tw[L];
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = twg[i];
+  const int x0 = blockIdx.x * C, y = blockIdx.y;
+  const size_t zstride = (size_t)Ny * px;
+  const size_t base = (size_t)y * px + x0;
+  const int cols = min(C, ncols - x0);
+  const int t = threadIdx.x;
+  // second-stage role: task (c, j), j < R1, owns frequencies kz = j + r R1
+  const int c2 = t % C, j2 = t / C;
+  const bool s2 = t < C * R1;
+  float2 h[R2];
+#pragma unroll
+  for (int r = 0; r < R2; ++r) {
+    const bool ok = s2 && c2 < cols;
+    const float2 g = hhat[ok ? base + (size_t)(j2 + r * R1) * zstride + c2 : 0];
+    h[r] = ok ? make_float2(g.x, conj_h ? -g.y : g.y) : make_float2(0.f, 0.f);
+  }
+  const int c1 = t % C, j1 = t / C;
+  const bool s1 = t < C * R2;
+  if (s1) {
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int i = j1 + r * R2;
+      const bool ok = c1 < cols && i < nz;
+      const float2 a = spec[ok ? base + (size_t)i * zstride + c1 : 0];
+      v[r] = ok ? a : make_float2(0.f, 0.f);
+    }
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) bufa[c1 * LS + j1 * R1 + r] = v[r];
+  }
+  __syncthreads();
+  if (s2) {
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = bufa[c2 * LS + j2 + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j2]);
+    }
+    Dft<R2>::run(v);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const float2 u = cmul(v[r], h[r]);
+      bufb[c2 * LS + j2 + r * R1] = make_float2(u.x, -u.y);
+    }
+  }
+  __syncthreads();
+  if (s1) {
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) v[r] = bufb[c1 * LS + j1 + r * R2];
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) bufa[c1 * LS + j1 * R1 + r] = v[r];
+  }
+  __syncthreads();
+  if (s2) {
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = bufa[c2 * LS + j2 + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j2]);
+    }
+    Dft<R2>::run(v);
+    if (c2 < cols) {
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int i = j2 + r * R1;
+        if (i < nz) spec[base + (size_t)i * zstride + c2] = v[r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- x, half spectrum -> real
+
+// Rows a = y0 + l and b = y0 + kBxPairs + l of plane z = blockIdx.y hold D = DFT_y DFT_z
+// conj(U) for the half spectrum U of the result. The conjugated full x spectrum of the line
+// u_a + i u_b is D_a[k] - i D_b[k] for k <= L / 2 and conj(D_a[L - k]) - i conj(D_b[L - k])
+// above; its DFT W gives u_a = Re W scale and u_b = -Im W scale (scale = 1 / (Nx Ny Nz)).
+// EPI == kEpiResidual: out = yobs - u and dpart[block] = sum of out^2 (float64).
+template <int R1, int R2, int EPI>
+__global__ __launch_bounds__(bx_threads(R1, R2)) void k_bx_c2r(
+    const float2* __restrict__ spec, int nx, int ny, int Ny, int px, float scale,
+    const float2* __restrict__ twg, float* __restrict__ out, const float* __restrict__ yobs,
+    double* __restrict__ dpart) {
+  constexpr int L = R1 * R2, LS = L | 1, B = kBxPairs, NT = bx_threads(R1, R2);
+  __shared__ float2 buf[B * LS];
+  __shared__ float2 tw[L];
+  __shared__ double red[NT / 64];
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = twg[i];
+  const int y0 = blockIdx.x * 2 * B, z = blockIdx.y;
+  const int t = threadIdx.x;
+  if (t < B * R2) {
+    const int j = t % R2, l = t / R2;
+    const int ya = y0 + l, yb = y0 + B + l;
+    const bool oka = ya < ny, okb = yb < ny;
+    const float2* ra = spec + ((size_t)z * Ny + (oka ? ya : 0)) * px;
+    const float2* rb = spec + ((size_t)z * Ny + (okb ? yb : 0)) * px;
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int i = j + r * R2;
+      const bool lo = 2 * i <= L;
+      const int m = lo ? i : L - i;
+      const float2 da0 = ra[m], db0 = rb[m];
+      const float2 da = oka ? da0 : make_float2(0.f, 0.f);
+      const float2 db = okb ? db0 : make_float2(0.f, 0.f);
+      v[r] = lo ? make_float2(da.x + db.y, da.y - db.x) : make_float2(da.x - db.y, -da.y - db.x);
+    }
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) buf[l * LS + j * R1 + r] = v[r];
+  }
+  __syncthreads();
+  double acc = 0.0;
+  if (t < B * R1) {
+    const int j = t % R1, l = t / R1;
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = buf[l * LS + j + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j]);
+    }
+    Dft<R2>::run(v);
+    const int ya = y0 + l, yb = y0 + B + l;
+    const size_t oa = ((size_t)z * ny + ya) * nx, ob = ((size_t)z * ny + yb) * nx;
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int x = j + r * R1;
+      if (x < nx) {
+        const float ua = v[r].x * scale, ub = -v[r].y * scale;
+        if (EPI == kEpiResidual) {
+          if (ya < ny) {
+            const float d = yobs[oa + x] - ua;
+            out[oa + x] = d;
+            acc += (double)d * d;
+          }
+          if (yb < ny) {
+            const float d = yobs[ob + x] - ub;
+            out[ob + x] = d;
+            acc += (double)d * d;
+          }
+        } else {
+          if (ya < ny) out[oa + x] = ua;
+          if (yb < ny) out[ob + x] = ub;
+        }
+      }
+    }
+  }
+  if (EPI == kEpiResidual) {
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((t & 63) == 0) red[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += red[w];
+      dpart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- fused plane passes
+
+// When a plane's half spectrum and one exchange buffer fit in LDS (and Nx = Ny = L), one
+// block per plane z = blockIdx.x does the x and y transforms of the plane together, so the
+// volume is read and written once per side instead of twice. Rows a = l and b = l + np
+// (np = ceil(ny / 2)) share complex line l. Dynamic LDS: plane [ny][hx], then the exchange
+// buffer [max(np, hx)][L | 1].
+constexpr int kPlaneThreads = 1024;
+// dynamic LDS of the fused passes: 160 KiB per block less the static twiddles and partials
+constexpr size_t kPlaneLdsMax = 160 * 1024 - 4096;
+
+// Forward: real plane -> x half spectrum (LDS) -> y DFT, all L rows to spec[(z L + i) px + k].
+template <int R1, int R2>
+__global__ __launch_bounds__(kPlaneThreads) void k_bxy_fwd(
+    const float* __restrict__ in, int nx, int ny, float2* __restrict__ spec, int px, int hx,
+    const float2* __restrict__ twg) {
+  constexpr int L = R1 * R2, LS = L | 1, NT = kPlaneThreads;
+  extern __shared__ float2 lds[];
+  __shared__ float2 tw[L];
+  float2* plane = lds;
+  float2* xb = lds + (size_t)ny * hx;
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = twg[i];
+  const int z = blockIdx.x, np = (ny + 1) / 2;
+  const float* src = in + (size_t)z * ny * nx;
+  const int t = threadIdx.x;
+  // x, stage 1: task (l, j), j < R2
+  for (int task = t; task < np * R2; task += NT) {
+    const int j = task % R2, l = task / R2;
+    const int ya = l, yb = l + np;
+    const bool okb = yb < ny;
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int i = j + r * R2;
+      const bool ia = i < nx, ib = okb && i < nx;
+      const float a = src[ia ? (size_t)ya * nx + i : 0];
+      const float b = src[ib ? (size_t)yb * nx + i : 0];
+      v[r] = make_float2(ia ? a : 0.f, ib ? b : 0.f);
+    }
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) xb[l * LS + j * R1 + r] = v[r];
+  }
+  __syncthreads();
+  // x, stage 2: task (l, j), j < R1 reads and writes positions j + r R1 of line l
+  for (int task = t; task < np * R1; task += NT) {
+    const int j = task % R1, l = task / R1;
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = xb[l * LS + j + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j]);
+    }
+    Dft<R2>::run(v);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) xb[l * LS + j + r * R1] = v[r];
+  }
+  __syncthreads();
+  // separate the two rows of every line into the plane's half spectrum
+  for (int e = t; e < np * hx; e += NT) {
+    const int l = e / hx, k = e - l * hx;
+    const float2 zk = xb[l * LS + k];
+    const float2 zm = xb[l * LS + (k == 0 ? 0 : L - k)];
+    plane[l * hx + k] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    if (l + np < ny)
+      plane[(l + np) * hx + k] = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+  }
+  __syncthreads();
+  // y, stage 1: column c < hx, task j < R2 (rows beyond ny are zero)
+  for (int task = t; task < hx * R2; task += NT) {
+    const int c = task % hx, j = task / hx;
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int i = j + r * R2;
+      v[r] = i < ny ? plane[i * hx + c] : make_float2(0.f, 0.f);
+    }
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) xb[c * LS + j * R1 + r] = v[r];
+  }
+  __syncthreads();
+  float2* dst = spec + (size_t)z * L * px;
+  for (int task = t; task < hx * R1; task += NT) {
+    const int c = task % hx, j = task / hx;
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = xb[c * LS + j + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j]);
+    }
+    Dft<R2>::run(v);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) dst[(size_t)(j + r * R1) * px + c] = v[r];
+  }
+}
+
+// Inverse: y DFT of all L rows of plane z (rows < ny kept in LDS), then the x pass of k_bx_c2r
+// with its epilogue; the residual partial of plane z goes to dpart[z].
+template <int R1, int R2, int EPI>
+__global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv(
+    const float2* __restrict__ spec, int nx, int ny, int px, int hx, float scale,
+    const float2* __restrict__ twg, float* __restrict__ out, const float* __restrict__ yobs,
+    double* __restrict__ dpart) {
+  constexpr int L = R1 * R2, LS = L | 1, NT = kPlaneThreads;
+  extern __shared__ float2 lds[];
+  __shared__ float2 tw[L];
+  __shared__ double red[NT / 64];
+  float2* plane = lds;
+  float2* xb = lds + (size_t)ny * hx;
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = twg[i];
+  const int z = blockIdx.x, np = (ny + 1) / 2;
+  const float2* src = spec + (size_t)z * L * px;
+  const int t = threadIdx.x;
+  for (int task = t; task < hx * R2; task += NT) {
+    const int c = task % hx, j = task / hx;
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) v[r] = src[(size_t)(j + r * R2) * px + c];
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) xb[c * LS + j * R1 + r] = v[r];
+  }
+  __syncthreads();
+  for (int task = t; task < hx * R1; task += NT) {
+    const int c = task % hx, j = task / hx;
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = xb[c * LS + j + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j]);
+    }
+    Dft<R2>::run(v);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int i = j + r * R1;
+      if (i < ny) plane[i * hx + c] = v[r];
+    }
+  }
+  __syncthreads();
+  for (int task = t; task < np * R2; task += NT) {
+    const int j = task % R2, l = task / R2;
+    const bool okb = l + np < ny;
+    const float2* ra = plane + l * hx;
+    const float2* rb = plane + (okb ? l + np : l) * hx;
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int i = j + r * R2;
+      const bool lo = 2 * i <= L;
+      const int m = lo ? i : L - i;
+      const float2 da = ra[m];
+      const float2 db = okb ? rb[m] : make_float2(0.f, 0.f);
+      v[r] = lo ? make_float2(da.x + db.y, da.y - db.x) : make_float2(da.x - db.y, -da.y - db.x);
+    }
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) xb[l * LS + j * R1 + r] = v[r];
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int task = t; task < np * R1; task += NT) {
+    const int j = task % R1, l = task / R1;
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = xb[l * LS + j + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j]);
+    }
+    Dft<R2>::run(v);
+    const int ya = l, yb = l + np;
+    const size_t oa = ((size_t)z * ny + ya) * nx, ob = ((size_t)z * ny + yb) * nx;
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int x = j + r * R1;
+      if (x < nx) {
+        const float ua = v[r].x * scale, ub = -v[r].y * scale;
+        if (EPI == kEpiResidual) {
+          const float d = yobs[oa + x] - ua;
+          out[oa + x] = d;
+          acc += (double)d * d;
+          if (yb < ny) {
+            const float e = yobs[ob + x] - ub;
+            out[ob + x] = e;
+            acc += (double)e * e;
+          }
+        } else {
+          out[oa + x] = ua;
+          if (yb < ny) out[ob + x] = ub;
+        }
+      }
+    }
+  }
+  if (EPI == kEpiResidual) {
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((t & 63) == 0) red[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += red[w];
+      dpart[z] = s;
+    }
+  }
+}
+
+// Residual, then the forward transform of the residual for the adjoint, in one block per plane:
+// the y and x inverse passes of k_bxy_inv with the residual epilogue (r = yobs - H * f to r_out,
+// loss partial to dpart[z]), then r of the same two rows per line goes straight back through
+// the forward x DFT and the y DFT of k_bxy_fwd, whose spectrum overwrites plane z of spec.
+// Needs every phase to fit in one task per thread (checked on the host), so that a stage can
+// read all its inputs before any thread overwrites them in place.
+template <int R1, int R2>
+__global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv_fwd(
+    float2* __restrict__ spec, int nx, int ny, int px, int hx, float scale,
+    const float2* __restrict__ twg, float* __restrict__ r_out, const float* __restrict__ yobs,
+    double* __restrict__ dpart) {
+  constexpr int L = R1 * R2, LS = L | 1, NT = kPlaneThreads;
+  extern __shared__ float2 lds[];
+  __shared__ float2 tw[L];
+  __shared__ double red[NT / 64];
+  float2* plane = lds;
+  float2* xb = lds + (size_t)ny * hx;
+  for (int i = threadIdx.x; i < L; i += NT) tw[i] = twg[i];
+  const int z = blockIdx.x, np = (ny + 1) / 2;
+  float2* sp = spec + (size_t)z * L * px;
+  const int t = threadIdx.x;
+  // y inverse: all L rows in, rows < ny to the plane
+  if (t < hx * R2) {
+    const int c = t % hx, j = t / hx;
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) v[r] = sp[(size_t)(j + r * R2) * px + c];
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) xb[c * LS + j * R1 + r] = v[r];
+  }
+  __syncthreads();
+  if (t < hx * R1) {
+    const int c = t % hx, j = t / hx;
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = xb[c * LS + j + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j]);
+    }
+    Dft<R2>::run(v);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int i = j + r * R1;
+      if (i < ny) plane[i * hx + c] = v[r];
+    }
+  }
+  __syncthreads();
+  // x inverse, stage 1
+  if (t < np * R2) {
+    const int j = t % R2, l = t / R2;
+    const bool okb = l + np < ny;
+    const float2* ra = plane + l * hx;
+    const float2* rb = plane + (okb ? l + np : l) * hx;
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int i = j + r * R2;
+      const bool lo = 2 * i <= L;
+      const int m = lo ? i : L - i;
+      const float2 da = ra[m];
+      const float2 db = okb ? rb[m] : make_float2(0.f, 0.f);
+      v[r] = lo ? make_float2(da.x + db.y, da.y - db.x) : make_float2(da.x - db.y, -da.y - db.x);
+    }
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) xb[l * LS + j * R1 + r] = v[r];
+  }
+  __syncthreads();
+  // x inverse, stage 2, residual epilogue; (r_a, r_b) of line l replaces its own slots
+  double acc = 0.0;
+  if (t < np * R1) {
+    const int j = t % R1, l = t / R1;
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = xb[l * LS + j + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j]);
+    }
+    Dft<R2>::run(v);
+    const int ya = l, yb = l + np;
+    const bool okb = yb < ny;
+    const size_t oa = ((size_t)z * ny + ya) * nx, ob = ((size_t)z * ny + yb) * nx;
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int x = j + r * R1;
+      float2 rr = make_float2(0.f, 0.f);
+      if (x < nx) {
+        rr.x = yobs[oa + x] - v[r].x * scale;
+        r_out[oa + x] = rr.x;
+        acc += (double)rr.x * rr.x;
+        if (okb) {
+          rr.y = yobs[ob + x] + v[r].y * scale;
+          r_out[ob + x] = rr.y;
+          acc += (double)rr.y * rr.y;
+        }
+      }
+      xb[l * LS + x] = rr;
+    }
+  }
+  __syncthreads();
+  // forward x, stage 1: read every input first, then write in place
+  {
+    float2 v[R1];
+    const int j = t % R2, l = t / R2;
+    const bool act = t < np * R2;
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < R1; ++r) v[r] = xb[l * LS + j + r * R2];
+      Dft<R1>::run(v);
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < R1; ++r) xb[l * LS + j * R1 + r] = v[r];
+    }
+  }
+  __syncthreads();
+  if (t < np * R1) {
+    const int j = t % R1, l = t / R1;
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = xb[l * LS + j + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j]);
+    }
+    Dft<R2>::run(v);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) xb[l * LS + j + r * R1] = v[r];
+  }
+  __syncthreads();
+  for (int e = t; e < np * hx; e += NT) {
+    const int l = e / hx, k = e - l * hx;
+    const float2 zk = xb[l * LS + k];
+    const float2 zm = xb[l * LS + (k == 0 ? 0 : L - k)];
+    plane[l * hx + k] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    if (l + np < ny)
+      plane[(l + np) * hx + k] = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+  }
+  __syncthreads();
+  if (t < hx * R2) {
+    const int c = t % hx, j = t / hx;
+    float2 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int i = j + r * R2;
+      v[r] = i < ny ? plane[i * hx + c] : make_float2(0.f, 0.f);
+    }
+    Dft<R1>::run(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) xb[c * LS + j * R1 + r] = v[r];
+  }
+  __syncthreads();
+  if (t < hx * R1) {
+    const int c = t % hx, j = t / hx;
+    float2 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      v[r] = xb[c * LS + j + r * R1];
+      if (r > 0) v[r] = cmul(v[r], tw[r * j]);
+    }
+    Dft<R2>::run(v);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) sp[(size_t)(j + r * R1) * px + c] = v[r];
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((t & 63) == 0) red[t >> 6] = acc;
+  __syncthreads();
+  if (t == 0) {
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    dpart[z] = s;
+  }
+}
+
+// ---------------------------------------------------------------- PSF spectrum and twiddles
+
+// Hhat(kx, ky, kz) = sum_t H[c + t] exp(-2 pi i (kx tx / Nx + ky ty / Ny + kz tz / Nz)) over
+// the taps t in [-c, c]^3 (the PSF placed with its centre at the origin of the periodic grid),
+// for kx < hx, every ky and kz; float64 sums, stored at [(kz Ny + ky) px + kx]. Block:
+// 32 columns kx of row ky = blockIdx.y. S(tz, kx) = sum_{ty, tx} H w_y w_x goes through LDS.
+constexpr int kHhatCols = 32;
+constexpr int kHhatMaxPz = 31;
+constexpr int kHhatMaxTaps = 8192;  // PSF staged in LDS
+
+// hcache holds the PSF and grid the stored spectrum was computed for: ints [0, 6) = (P_x, P_y,
+// P_z, N_x, N_y, N_z), taps from kHcacheHead on. One block compares the request with it and
+// sets *changed (updating the copy when it differs); the spectrum kernel then returns at once
+// when nothing changed, so an unchanged PSF costs no recomputation and no host round trip.
+constexpr int kHcacheHead = 16;
+
+__global__ __launch_bounds__(1024) void k_psf_check(const float* __restrict__ H, int pxs, int pys,
+                                                    int pzs, int Nx, int Ny, int Nz,
+                                                    float* __restrict__ hcache,
+                                                    int* __restrict__ changed) {
+  __shared__ int diff;
+  const int t = threadIdx.x;
+  const int ntaps = pxs * pys * pzs;
+  if (t == 0) {
+    const int* h = reinterpret_cast<const int*>(hcache);
+    diff = h[0] != pxs || h[1] != pys || h[2] != pzs || h[3] != Nx || h[4] != Ny || h[5] != Nz;
+  }
+  __syncthreads();
+  int d = 0;
+  for (int i = t; i < ntaps; i += 1024)
+    d |= __float_as_int(H[i]) != __float_as_int(hcache[kHcacheHead + i]);
+  if (d) diff = 1;  // benign race: every writer stores 1
+  __syncthreads();
+  const int ch = diff;
+  if (ch) {
+    for (int i = t; i < ntaps; i += 1024) hcache[kHcacheHead + i] = H[i];
+    if (t == 0) {
+      int* h = reinterpret_cast<int*>(hcache);
+      h[0] = pxs;
+      h[1] = pys;
+      h[2] = pzs;
+      h[3] = Nx;
+      h[4] = Ny;
+      h[5] = Nz;
+    }
+  }
+  if (t == 0) *changed = ch;
+}
+
+__global__ __launch_bounds__(256) void k_psf_spectrum(
+    const float* __restrict__ H, int pxs, int pys, int pzs, int Nx, int Ny, int Nz, int hx,
+    int px, float2* __restrict__ hhat, const int* __restrict__ changed) {
+  if (*changed == 0) return;
+  __shared__ double2 wx[kFftMaxBlur], wy[kFftMaxBlur], wz[kFftMaxBlur];
+  __shared__ double2 S[kHhatMaxPz * kHhatCols];
+  __shared__ float hs[kHhatMaxTaps];
+  const int t = threadIdx.x;
+  const int ntaps = pxs * pys * pzs;
+  for (int i = t; i < ntaps; i += 256) hs[i] = H[i];
+  // exp(-2 pi i m / N) = cospi(-2 m / N) + i sinpi(-2 m / N)
+  for (int m = t; m < Nx; m += 256) {
+    double s, c;
+    sincospi(-2.0 * m / Nx, &s, &c);
+    wx[m] = make_double2(c, s);
+  }
+  for (int m = t; m < Ny; m += 256) {
+    double s, c;
+    sincospi(-2.0 * m / Ny, &s, &c);
+    wy[m] = make_double2(c, s);
+  }
+  for (int m = t; m < Nz; m += 256) {
+    double s, c;
+    sincospi(-2.0 * m / Nz, &s, &c);
+    wz[m] = make_double2(c, s);
+  }
+  __syncthreads();
+  const int ky = blockIdx.y, kx0 = blockIdx.x * kHhatCols;
+  const int cx = (pxs - 1) / 2, cy = (pys - 1) / 2, cz = (pzs - 1) / 2;
+  // index of exp(-2 pi i k t / N) for t = -c: (-k c) mod N; each further tap adds k (mod N)
+  auto first = [](int k, int c, int N) {
+    const int m = (k * c) % N;
+    return m == 0 ? 0 : N - m;
+  };
+  for (int e = t; e < pzs * kHhatCols; e += 256) {
+    const int tz = e / kHhatCols, kx = kx0 + e % kHhatCols;
+    double sr = 0.0, si = 0.0;
+    if (kx < hx) {
+      int my = first(ky, cy, Ny);
+      const int mx0 = first(kx, cx, Nx);
+      for (int ty = 0; ty < pys; ++ty) {
+        const float* row = hs + (tz * pys + ty) * pxs;
+        double xr = 0.0, xi = 0.0;
+        int mx = mx0;
+#pragma unroll 4
+        for (int tx = 0; tx < pxs; ++tx) {
+          const double h = row[tx];
+          const double2 w = wx[mx];
+          xr += h * w.x;
+          xi += h * w.y;
+          mx += kx;
+          if (mx >= Nx) mx -= Nx;
+        }
+        const double2 w = wy[my];
+        sr += xr * w.x - xi * w.y;
+        si += xr * w.y + xi * w.x;
+        my += ky;
+        if (my >= Ny) my -= Ny;
+      }
+    }
+    S[e] = make_double2(sr, si);
+  }
+  __syncthreads();
+  for (int e = t; e < Nz * kHhatCols; e += 256) {
+    const int kz = e / kHhatCols, c = e % kHhatCols, kx = kx0 + c;
+    if (kx >= hx) continue;
+    double gr = 0.0, gi = 0.0;
+    int mz = first(kz, cz, Nz);
+#pragma unroll 4
+    for (int tz = 0; tz < pzs; ++tz) {
+      const double2 sv = S[tz * kHhatCols + c];
+      const double2 w = wz[mz];
+      gr += sv.x * w.x - sv.y * w.y;
+      gi += sv.x * w.y + sv.y * w.x;
+      mz += kz;
+      if (mz >= Nz) mz -= Nz;
+    }
+    hhat[((size_t)kz * Ny + ky) * px + kx] = make_float2((float)gr, (float)gi);
+  }
+}
+
+// tw[a * kFftMaxBlur + m] = exp(-2 pi i m / N_a), m < N_a, for the three axes.
+__global__ __launch_bounds__(256) void k_blur_twiddles(float2* __restrict__ tw, int Nx, int Ny,
+                                                       int Nz) {
+  const int a = blockIdx.y;
+  const int N = a == 0 ? Nx : (a == 1 ? Ny : Nz);
+  for (int m = blockIdx.x * 256 + threadIdx.x; m < N; m += gridDim.x * 256) {
+    double s, c;
+    sincospi(-2.0 * m / N, &s, &c);
+    tw[a * kFftMaxBlur + m] = make_float2((float)c, (float)s);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+bool blur_plan(const sfw_dims& vol, const sfw_dims& psf, BlurPlan& bp) {
+  const int n[3] = {vol.nx, vol.ny, vol.nz};
+  const int c[3] = {(psf.nx - 1) / 2, (psf.ny - 1) / 2, (psf.nz - 1) / 2};
+  if (psf.nz > kHhatMaxPz || psf.nx * psf.ny * psf.nz > kHhatMaxTaps) return false;
+  for (int a = 0; a < 3; ++a) {
+    bp.N[a] = 0;
+    for (int L = std::max(n[a] + c[a], 16); L <= kFftMaxBlur; ++L)
+      if (fft_fixed_plan(L, &bp.r1[a], &bp.r2[a])) {
+        bp.N[a] = L;
+        break;
+      }
+    if (!bp.N[a]) return false;
+  }
+  bp.hx = bp.N[0] / 2 + 1;
+  bp.px = (bp.hx + 3) & ~3;
+  // fused plane passes: square transforms in x and y, plane + exchange buffer in LDS
+  const size_t np = (size_t)(vol.ny + 1) / 2;
+  bp.lds = ((size_t)vol.ny * bp.hx + std::max(np, (size_t)bp.hx) * (size_t)(bp.N[0] | 1)) *
+           sizeof(float2);
+  bp.fused = bp.N[0] == bp.N[1] && bp.lds <= kPlaneLdsMax && std::getenv("SFW_BLUR_PASSES") == nullptr;
+  const int rmax = std::max(bp.r1[0], bp.r2[0]);
+  bp.chain = bp.fused && (int)np * rmax <= kPlaneThreads && bp.hx * rmax <= kPlaneThreads;
+  return true;
+}
+
+hipError_t launch_blur_twiddles(const BlurPlan& bp, float2* tw, hipStream_t st) {
+  hipLaunchKernelGGL(k_blur_twiddles, dim3(1, 3), dim3(256), 0, st, tw, bp.N[0], bp.N[1],
+                     bp.N[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_psf_spectrum(const BlurPlan& bp, const float* H, sfw_dims psf, float2* hhat,
+                               float* hcache, int* changed, hipStream_t st) {
+  hipLaunchKernelGGL(k_psf_check, dim3(1), dim3(1024), 0, st, H, psf.nx, psf.ny, psf.nz, bp.N[0],
+                     bp.N[1], bp.N[2], hcache, changed);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 grid((bp.hx + kHhatCols - 1) / kHhatCols, bp.N[1]);
+  hipLaunchKernelGGL(k_psf_spectrum, grid, dim3(256), 0, st, H, psf.nx, psf.ny, psf.nz, bp.N[0],
+                     bp.N[1], bp.N[2], bp.hx, bp.px, hhat, changed);
+  return hipGetLastError();
+}
+
+int blur_residual_parts(const BlurPlan& bp, const sfw_dims& vol) {
+  if (bp.fused) return vol.nz;
+  return ((vol.ny + 2 * kBxPairs - 1) / (2 * kBxPairs)) * vol.nz;
+}
+
+static hipError_t bxy_fwd(const BlurPlan& bp, const float* in, const sfw_dims& vol, float2* spec,
+                          const float2* tw, hipStream_t st) {
+  switch (bp.N[0]) {
+#define SFW_BXY_CASE(n, a, b)                                                                  \
+  case n: {                                                                                    \
+    static const hipError_t attr = hipFuncSetAttribute(                                        \
+        reinterpret_cast<const void*>(&k_bxy_fwd<a, b>),                                       \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlaneLdsMax);                        \
+    if (attr != hipSuccess) return attr;                                                       \
+    hipLaunchKernelGGL((k_bxy_fwd<a, b>), dim3(vol.nz), dim3(kPlaneThreads), bp.lds, st, in,   \
+                       vol.nx, vol.ny, spec, bp.px, bp.hx, tw);                                \
+    return hipGetLastError();                                                                  \
+  }
+    SFW_FX_LENGTHS(SFW_BXY_CASE)
+#undef SFW_BXY_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int EPI>
+static hipError_t bxy_inv(const BlurPlan& bp, const float2* spec, const sfw_dims& vol,
+                          const float2* tw, float* out, const float* yobs, double* dpart,
+                          hipStream_t st) {
+  const float scale = (float)(1.0 / ((double)bp.N[0] * bp.N[1] * bp.N[2]));
+  switch (bp.N[0]) {
+#define SFW_BXY_CASE(n, a, b)                                                                  \
+  case n: {                                                                                    \
+    static const hipError_t attr = hipFuncSetAttribute(                                        \
+        reinterpret_cast<const void*>(&k_bxy_inv<a, b, EPI>),                                  \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlaneLdsMax);                        \
+    if (attr != hipSuccess) return attr;                                                       \
+    hipLaunchKernelGGL((k_bxy_inv<a, b, EPI>), dim3(vol.nz), dim3(kPlaneThreads), bp.lds, st,  \
+                       spec, vol.nx, vol.ny, bp.px, bp.hx, scale, tw, out, yobs, dpart);      \
+    return hipGetLastError();                                                                  \
+  }
+    SFW_FX_LENGTHS(SFW_BXY_CASE)
+#undef SFW_BXY_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t bx_r2c(const BlurPlan& bp, const float* in, const sfw_dims& vol, float2* spec,
+                         const float2* tw, hipStream_t st) {
+  const dim3 grid((vol.ny + 2 * kBxPairs - 1) / (2 * kBxPairs), vol.nz);
+  switch (bp.N[0]) {
+#define SFW_BX_CASE(n, a, b)                                                                \
+  case n:                                                                                   \
+    hipLaunchKernelGGL((k_bx_r2c<a, b>), grid, dim3(bx_threads(a, b)), 0, st, in, vol.nx,   \
+                       vol.ny, spec, bp.N[1], bp.px, bp.hx, tw);                            \
+    return hipGetLastError();
+    SFW_FX_LENGTHS(SFW_BX_CASE)
+#undef SFW_BX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t bz_filter(const BlurPlan& bp, float2* spec, const float2* hhat, bool conj_h,
+                            int nz, const float2* tw, hipStream_t st) {
+  const dim3 grid((bp.hx + kFxLines - 1) / kFxLines, bp.N[1]);
+  switch (bp.N[2]) {
+#define SFW_BZ_CASE(n, a, b)                                                                 \
+  case n:                                                                                    \
+    hipLaunchKernelGGL((k_bz_filter<a, b>), grid, dim3(bz_threads(a, b)), 0, st, spec, hhat, \
+                       conj_h ? 1 : 0, bp.hx, bp.N[1], bp.px, nz, tw);                       \
+    return hipGetLastError();
+    SFW_FX_LENGTHS(SFW_BZ_CASE)
+#undef SFW_BZ_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int EPI>
+static hipError_t bx_c2r(const BlurPlan& bp, const float2* spec, const sfw_dims& vol,
+                         const float2* tw, float* out, const float* yobs, double* dpart,
+                         hipStream_t st) {
+  const dim3 grid((vol.ny + 2 * kBxPairs - 1) / (2 * kBxPairs), vol.nz);
+  const float scale = (float)(1.0 / ((double)bp.N[0] * bp.N[1] * bp.N[2]));
+  switch (bp.N[0]) {
+#define SFW_BX_CASE(n, a, b)                                                                  \
+  case n:                                                                                     \
+    hipLaunchKernelGGL((k_bx_c2r<a, b, EPI>), grid, dim3(bx_threads(a, b)), 0, st, spec,      \
+                       vol.nx, vol.ny, bp.N[1], bp.px, scale, tw, out, yobs, dpart);          \
+    return hipGetLastError();
+    SFW_FX_LENGTHS(SFW_BX_CASE)
+#undef SFW_BX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t bxy_inv_fwd(const BlurPlan& bp, float2* spec, const sfw_dims& vol,
+                              const float2* tw, float* r_out, const float* yobs, double* dpart,
+                              hipStream_t st) {
+  const float scale = (float)(1.0 / ((double)bp.N[0] * bp.N[1] * bp.N[2]));
+  switch (bp.N[0]) {
+#define SFW_BXY_CASE(n, a, b)                                                                  \
+  case n: {                                                                                    \
+    static const hipError_t attr = hipFuncSetAttribute(                                        \
+        reinterpret_cast<const void*>(&k_bxy_inv_fwd<a, b>),                                   \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlaneLdsMax);                        \
+    if (attr != hipSuccess) return attr;                                                       \
+    hipLaunchKernelGGL((k_bxy_inv_fwd<a, b>), dim3(vol.nz), dim3(kPlaneThreads), bp.lds, st,   \
+                       spec, vol.nx, vol.ny, bp.px, bp.hx, scale, tw, r_out, yobs, dpart);    \
+    return hipGetLastError();                                                                  \
+  }
+    SFW_FX_LENGTHS(SFW_BXY_CASE)
+#undef SFW_BXY_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_blur_residual_chain(const BlurPlan& bp, const float* f, const sfw_dims& vol,
+                                      const float2* hhat, const float* yobs, float* r_out,
+                                      double* dpart, float2* spec, const float2* tw,
+                                      hipStream_t st) {
+  if (!bp.chain) return hipErrorInvalidValue;
+  hipError_t e = bxy_fwd(bp, f, vol, spec, tw, st);
+  if (e != hipSuccess) return e;
+  e = bz_filter(bp, spec, hhat, false, vol.nz, tw + 2 * kFftMaxBlur, st);
+  if (e != hipSuccess) return e;
+  return bxy_inv_fwd(bp, spec, vol, tw, r_out, yobs, dpart, st);
+}
+
+hipError_t launch_blur_adjoint_chain(const BlurPlan& bp, const sfw_dims& vol, const float2* hhat,
+                                     float* q_out, float2* spec, const float2* tw,
+                                     hipStream_t st) {
+  if (!bp.chain) return hipErrorInvalidValue;
+  hipError_t e = bz_filter(bp, spec, hhat, true, vol.nz, tw + 2 * kFftMaxBlur, st);
+  if (e != hipSuccess) return e;
+  return bxy_inv<kEpiPlain>(bp, spec, vol, tw, q_out, nullptr, nullptr, st);
+}
+
+hipError_t launch_blur(const BlurPlan& bp, const float* in, const sfw_dims& vol,
+                       const float2* hhat, bool adjoint, int epi, float* out, const float* yobs,
+                       double* dpart, float2* spec, const float2* tw, hipStream_t st) {
+  const float2* twx = tw;
+  const float2* twy = tw + kFftMaxBlur;
+  const float2* twz = tw + 2 * kFftMaxBlur;
+  if (bp.fused) {
+    hipError_t e = bxy_fwd(bp, in, vol, spec, twx, st);
+    if (e != hipSuccess) return e;
+    e = bz_filter(bp, spec, hhat, adjoint, vol.nz, twz, st);
+    if (e != hipSuccess) return e;
+    if (epi == kEpiResidual) return bxy_inv<kEpiResidual>(bp, spec, vol, twx, out, yobs, dpart, st);
+    if (epi == kEpiPlain) return bxy_inv<kEpiPlain>(bp, spec, vol, twx, out, nullptr, nullptr, st);
+    return hipErrorInvalidValue;
+  }
+  hipError_t e = bx_r2c(bp, in, vol, spec, twx, st);
+  if (e != hipSuccess) return e;
+  const size_t plane = (size_t)bp.N[1] * bp.px;
+  e = fx_strided(bp.N[1], dim3((bp.hx + kFxLines - 1) / kFxLines, vol.nz, 1), st, spec, 0, spec,
+                 0, twy, bp.hx, (size_t)bp.px, plane, vol.ny, bp.N[1]);
+  if (e != hipSuccess) return e;
+  e = bz_filter(bp, spec, hhat, adjoint, vol.nz, twz, st);
+  if (e != hipSuccess) return e;
+  e = fx_strided(bp.N[1], dim3((bp.hx + kFxLines - 1) / kFxLines, vol.nz, 1), st, spec, 0, spec,
+                 0, twy, bp.hx, (size_t)bp.px, plane, bp.N[1], vol.ny);
+  if (e != hipSuccess) return e;
+  if (epi == kEpiResidual) return bx_c2r<kEpiResidual>(bp, spec, vol, twx, out, yobs, dpart, st);
+  if (epi == kEpiPlain) return bx_c2r<kEpiPlain>(bp, spec, vol, twx, out, nullptr, nullptr, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sfw

@@ -600,28 +600,28 @@ hipError_t fft_pack_octant(const FftPlan& pl, const float2* full, float2* oct, h
 
 // eta_{2p} + i eta_{2p+1} = IFFT(Qhat * P_p) on the volume for every pair p < npairs at once
 // (pair spectra as octants at a stride of pl.oct, work arrays at a stride of `bstride`
-// elements), with the block maxima of every slice.
-hipError_t fft_inverse_pairs(const FftPlan& pl, const float2* qhat, const float2* pairs,
-                             float2* work, size_t bstride, int nslices, sfw_dims vol,
-                             float scale, float* eta_out, ArgPart* apart, int nblk,
-                             hipStream_t st) {
+// elements), with the block maxima of every slice: the z pass here, then y and x below.
+hipError_t fft_inverse_pairs_z(const FftPlan& pl, const float2* qhat, const float2* pairs,
+                               float2* work, size_t bstride, int nslices, sfw_dims vol,
+                               hipStream_t st) {
   const unsigned np = (unsigned)((nslices + 1) / 2);
-  hipError_t e;
-  if (pl.ax[2].r1 > 0) {
-    e = fx_z_inverse(pl.nz, dim3((pl.nx + kFxLines - 1) / kFxLines, pl.ny), st, qhat, pairs,
-                     pl.oct, pl.hx, pl.hy, work, bstride, pl.ax[2].tw, pl.nx, pl.ny, pl.px, vol.nz,
-                     (int)np);
-  } else {
-    const int g = fft_lg_lines(pl.nz, true), B = 1 << g;
-    hipLaunchKernelGGL(k_fft_strided<true>, dim3((pl.nx + B - 1) / B, pl.ny, np),
-                       dim3(kFftThreads), fft_lds(pl.nz, g), st, qhat, (size_t)0, pairs, pl.oct,
-                       work, bstride, pl.ax[2], pl.nx, (size_t)pl.px * pl.ny, (size_t)pl.px,
-                       pl.nz, vol.nz, g, pl.hx, pl.hy, pl.ny);
-    e = hipGetLastError();
-  }
-  if (e != hipSuccess) return e;
-  e = strided_pass(pl.ax[1], vol.nz, np, st, work, bstride, work, bstride, pl.nx, (size_t)pl.px,
-                   (size_t)pl.px * pl.ny, pl.ny, vol.ny);
+  if (pl.ax[2].r1 > 0)
+    return fx_z_inverse(pl.nz, st, qhat, pairs, pl.oct, pl.hx, pl.hy, work, bstride,
+                        pl.ax[2].tw, pl.nx, pl.ny, pl.px, vol.nz, (int)np);
+  const int g = fft_lg_lines(pl.nz, true), B = 1 << g;
+  hipLaunchKernelGGL(k_fft_strided<true>, dim3((pl.nx + B - 1) / B, pl.ny, np),
+                     dim3(kFftThreads), fft_lds(pl.nz, g), st, qhat, (size_t)0, pairs, pl.oct,
+                     work, bstride, pl.ax[2], pl.nx, (size_t)pl.px * pl.ny, (size_t)pl.px,
+                     pl.nz, vol.nz, g, pl.hx, pl.hy, pl.ny);
+  return hipGetLastError();
+}
+
+hipError_t fft_inverse_pairs_yx(const FftPlan& pl, float2* work, size_t bstride, int nslices,
+                                sfw_dims vol, float scale, float* eta_out, ArgPart* apart,
+                                int nblk, hipStream_t st) {
+  const unsigned np = (unsigned)((nslices + 1) / 2);
+  hipError_t e = strided_pass(pl.ax[1], vol.nz, np, st, work, bstride, work, bstride, pl.nx,
+                              (size_t)pl.px, (size_t)pl.px * pl.ny, pl.ny, vol.ny);
   if (e != hipSuccess) return e;
   if (pl.ax[0].r1 > 0)
     return fx_x_argmax(pl.nx, dim3((vol.ny + kFxLines - 1) / kFxLines, vol.nz, np), st, work,

@@ -22,44 +22,6 @@ namespace {
 using fftr::cmul;
 using fftr::Dft;
 
-// Every supported length with its two radices (most balanced split, powers of two first).
-#define SFW_FX_LENGTHS(X) \
-  X(16, 4, 4)             \
-  X(18, 6, 3)             \
-  X(20, 5, 4)             \
-  X(24, 6, 4)             \
-  X(25, 5, 5)             \
-  X(27, 9, 3)             \
-  X(30, 6, 5)             \
-  X(32, 8, 4)             \
-  X(36, 6, 6)             \
-  X(40, 8, 5)             \
-  X(45, 9, 5)             \
-  X(48, 8, 6)             \
-  X(50, 10, 5)            \
-  X(54, 9, 6)             \
-  X(60, 10, 6)            \
-  X(64, 8, 8)             \
-  X(72, 9, 8)             \
-  X(75, 15, 5)            \
-  X(80, 10, 8)            \
-  X(81, 9, 9)             \
-  X(90, 10, 9)            \
-  X(96, 12, 8)            \
-  X(100, 10, 10)          \
-  X(108, 12, 9)           \
-  X(120, 12, 10)          \
-  X(128, 16, 8)           \
-  X(135, 15, 9)           \
-  X(144, 12, 12)          \
-  X(150, 15, 10)          \
-  X(160, 16, 10)          \
-  X(180, 15, 12)          \
-  X(192, 16, 12)          \
-  X(225, 15, 15)          \
-  X(240, 16, 15)          \
-  X(256, 16, 16)
-
 // Threads of a block whose C lines need max(C R1, C R2) tasks in one stage, in whole waves.
 constexpr int fx_threads(int R1, int R2) {
   const int t = kFxLines * (R1 > R2 ? R1 : R2);
@@ -132,20 +94,31 @@ __global__ __launch_bounds__(fx_threads(R1, R2)) void k_fx_strided(
 // k <= N / 2 representative of frequency k in [0, N) for spectra even in that axis.
 __device__ __forceinline__ int fold(int k, int N) { return 2 * k <= N ? k : N - k; }
 
-// First inverse pass, along z (L = Nz), for every pair: column (x0 + c, y = blockIdx.y) of
-// Qhat is loaded once, then for each pair p the input conj(Qhat * P_p) (P_p read from its
-// octant) is transformed and rows z < n_out are written to work + p * work_b. The next pair's
-// spectrum values are fetched while the current pair's second stage runs.
+// First inverse pass, along z (L = Nz), for every pair: column (x0 + c, y) of Qhat is loaded
+// once, then for each pair p the input conj(Qhat * P_p) (P_p read from its octant) is
+// transformed and rows z < n_out are written to work + p * work_b. The next pair's spectrum
+// values are fetched while the current pair's second stage runs.
+//
+// Rows y and Ny - y read the same octant rows, as do all x groups of a row. Workgroups go to
+// the 8 XCDs round-robin by linear id and each XCD has its own L2, so the 1D grid is remapped:
+// the x groups of row y = 0, then of rows 1, Ny - 1, 2, Ny - 2, ... form one sequence, cut
+// into 8 contiguous chunks, chunk k running on XCD k. A row and its mirror then share an L2
+// and the octants are fetched from memory about once. Blocks past gx * Ny return at once.
 template <int R1, int R2>
 __global__ __launch_bounds__(fx_threads(R1, R2)) void k_fx_z_inverse(
     const float2* __restrict__ qhat, const float2* __restrict__ oct, size_t oct_b, int hx, int hy,
     float2* __restrict__ work, size_t work_b, const float2* __restrict__ twg, int Nx, int Ny,
-    int px, int n_out, int npairs) {
+    int px, int n_out, int npairs, int gx, int chunk) {
   constexpr int L = R1 * R2, LS = L | 1, C = kFxLines, NT = fx_threads(R1, R2);
   __shared__ float2 buf[C * LS];
   __shared__ float2 tw[L];
+  const int lid = blockIdx.x;
+  const int seq = (lid & 7) * chunk + (lid >> 3);
+  if (seq >= gx * Ny) return;
+  const int rho = seq / gx;
+  const int y = rho == 0 ? 0 : ((rho & 1) ? (rho + 1) >> 1 : Ny - (rho >> 1));
   for (int i = threadIdx.x; i < L; i += NT) tw[i] = twg[i];
-  const int x0 = blockIdx.x * C, y = blockIdx.y;
+  const int x0 = (seq - rho * gx) * C;
   const size_t istride = (size_t)px * Ny;
   const size_t obase = (size_t)y * px + x0;
   const int cols = min(C, Nx - x0);
@@ -404,14 +377,17 @@ hipError_t fx_strided(int L, dim3 grid, hipStream_t st, const float2* src, size_
   }
 }
 
-hipError_t fx_z_inverse(int L, dim3 grid, hipStream_t st, const float2* qhat, const float2* oct,
+hipError_t fx_z_inverse(int L, hipStream_t st, const float2* qhat, const float2* oct,
                         size_t oct_b, int hx, int hy, float2* work, size_t work_b,
                         const float2* tw, int Nx, int Ny, int px, int n_out, int npairs) {
+  const int gx = (Nx + kFxLines - 1) / kFxLines;
+  const int chunk = (gx * Ny + 7) / 8;  // blocks per XCD
+  const dim3 grid(8 * chunk);
   switch (L) {
 #define SFW_FX_CASE(n, a, b)                                                                  \
   case n:                                                                                     \
     hipLaunchKernelGGL((k_fx_z_inverse<a, b>), grid, dim3(fx_threads(a, b)), 0, st, qhat, oct, \
-                       oct_b, hx, hy, work, work_b, tw, Nx, Ny, px, n_out, npairs);           \
+                       oct_b, hx, hy, work, work_b, tw, Nx, Ny, px, n_out, npairs, gx, chunk);\
     return hipGetLastError();
     SFW_FX_LENGTHS(SFW_FX_CASE)
 #undef SFW_FX_CASE

@@ -193,3 +193,44 @@ struct Dft<5> {
 
 }  // namespace fftr
 }  // namespace sfw
+
+// Lengths with a two-stage plan, listed as X(L, R1, R2) with L = R1 * R2: the lengths from 16
+// to 256 that split into two factors with a register DFT above (most balanced split, powers
+// of two first).
+#define SFW_FX_LENGTHS(X) \
+  X(16, 4, 4)             \
+  X(18, 6, 3)             \
+  X(20, 5, 4)             \
+  X(24, 6, 4)             \
+  X(25, 5, 5)             \
+  X(27, 9, 3)             \
+  X(30, 6, 5)             \
+  X(32, 8, 4)             \
+  X(36, 6, 6)             \
+  X(40, 8, 5)             \
+  X(45, 9, 5)             \
+  X(48, 8, 6)             \
+  X(50, 10, 5)            \
+  X(54, 9, 6)             \
+  X(60, 10, 6)            \
+  X(64, 8, 8)             \
+  X(72, 9, 8)             \
+  X(75, 15, 5)            \
+  X(80, 10, 8)            \
+  X(81, 9, 9)             \
+  X(90, 10, 9)            \
+  X(96, 12, 8)            \
+  X(100, 10, 10)          \
+  X(108, 12, 9)           \
+  X(120, 12, 10)          \
+  X(128, 16, 8)           \
+  X(135, 15, 9)           \
+  X(144, 12, 12)          \
+  X(150, 15, 10)          \
+  X(160, 16, 10)          \
+  X(180, 15, 12)          \
+  X(192, 16, 12)          \
+  X(225, 15, 15)          \
+  X(240, 16, 15)          \
+  X(256, 16, 16)
+

@@ -33,6 +33,12 @@ __host__ __device__ inline float atom_rcut2(double sigma, double d) {
   return (float)(r * r);
 }
 
+// u beyond which a LASSO column treats its unit atom as zero: exp(-28) < 7e-13 of the peak.
+// The dropped tail carries less than about 1e-10 of the atom's mass for every d in the
+// domain (the tail of Gamma(3 / d) beyond u), so Gram entries and <a, y> move by far less than
+// the float32 rounding of the column itself, while the support box shrinks several-fold.
+constexpr double kColumnCutU = 28.0;
+
 // One candidate of the grid-certificate maximum.
 struct ArgPart {
   float val;
@@ -71,6 +77,7 @@ constexpr int kAtomArgs = 8;   // atom constants passed by value in one launch
 constexpr int kFftMaxStages = 16;
 constexpr int kFftMaxLen = 1024;
 constexpr int kFxLines = 16;  // lines (or columns) per block of the fixed-length passes
+constexpr int kFftMaxBlur = 256;  // longest transform of the spectral PSF blur
 struct FftAxis {
   int n = 1;
   int nstage = 0;
@@ -88,6 +95,18 @@ struct FftPlan {
   FftAxis ax[3];
 };
 
+// Spectral PSF blur (see sfw_blur.hip): transform lengths N >= n + (P - 1) / 2 per axis, each
+// with a two-stage plan N = r1 r2; half spectrum of hx = N[0] / 2 + 1 columns at a row pitch of
+// px elements; spectra laid out [z][N[1]][px].
+struct BlurPlan {
+  int N[3] = {0, 0, 0};
+  int r1[3] = {0, 0, 0}, r2[3] = {0, 0, 0};
+  int hx = 0, px = 0;
+  bool fused = false;  // x and y of each plane in one block (plane held in LDS)
+  bool chain = false;  // residual and the adjoint's forward transform in one plane pass
+  size_t lds = 0;      // dynamic LDS bytes of the fused passes
+};
+
 struct ConvPlan {
   int px = 1, py = 1, pz = 1;  // kernel taps per axis
   int kz = 4;                  // z taps per LDS pass (template parameter)
@@ -101,7 +120,7 @@ struct ConvPlan {
 enum ProfKind {
   kProfPrep = 0, kProfRender, kProfConvResidual, kProfConvAdjoint, kProfConvForward, kProfGrad,
   kProfGradFinalize, kProfCertConv, kProfCertArgmax, kProfLassoRender, kProfLassoConv,
-  kProfLassoDots, kProfHash, kProfEtaGrad, kProfCertFft, kProfCount
+  kProfLassoDots, kProfHash, kProfEtaGrad, kProfCertFft, kProfCertZinv, kProfCount
 };
 constexpr int kProfPool = 16384;
 
@@ -159,6 +178,16 @@ struct sfw_workspace {
   float2* fft_pairs = nullptr;   // [npairs][oct] pair spectra (octants, dense)
   size_t fft_cap = 0;            // complex elements per array
   int fft_npairs_cap = 0;
+
+  // spectral PSF blur: spectrum work array [nz][N1][px], PSF spectrum [N2][N1][px] and the
+  // twiddles of the three transform lengths in blur_tw_key ([3][kFftMaxBlur])
+  float2* blur_spec = nullptr;
+  float2* blur_hhat = nullptr;
+  float2* blur_tw = nullptr;
+  size_t blur_spec_cap = 0, blur_hhat_cap = 0;  // complex elements
+  int blur_tw_key[3] = {0, 0, 0};
+  float* blur_hcache = nullptr;  // [kHcacheFloats] PSF and grid of the stored spectrum
+  int* blur_changed = nullptr;   // [1]
 
   // atoms
   sfw_atom* atoms_dev = nullptr;  // [max_atoms + 1] staging for host-provided atoms
@@ -290,6 +319,13 @@ ConvRegion conv_region_full(sfw_dims vol);
 // Plain convolution restricted to a region (outputs elsewhere are not written).
 hipError_t launch_conv_mfma_region(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
                                    const ConvRegion& rg, float* out, hipStream_t st);
+// out = H * (w g) of the atom *atom on box = [x0, x1, y0, y1, z0, z1) only (H in its [z][y][x]
+// layout), the atom computed on the fly; the rest of out is left untouched. column_box_ok: the
+// PSF fits the kernel (P_x <= 33, P_z <= 31, LDS tile).
+constexpr int kColumnBoxMaxLds = 160 * 1024;
+bool column_box_ok(sfw_dims psf);
+hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sfw_dims vol,
+                             const int box[6], float* out, hipStream_t st);
 
 hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q, sfw_dims vol,
                        float* gpart, hipStream_t st);
@@ -329,10 +365,36 @@ hipError_t fft_forward_volume(const FftPlan& pl, const float* q, sfw_dims vol, f
 int fft_argmax_blocks(const FftPlan& pl, sfw_dims vol);
 // fixed-length passes (sfw_fft_fixed.hip)
 bool fft_fixed_plan(int L, int* r1, int* r2);
+// Spectral PSF blur (sfw_blur.hip). blur_plan: false when some axis needs a transform longer
+// than kFftMaxBlur or the PSF is deeper than the spectrum kernel supports.
+bool blur_plan(const sfw_dims& vol, const sfw_dims& psf, BlurPlan& bp);
+hipError_t launch_blur_twiddles(const BlurPlan& bp, float2* tw, hipStream_t st);
+// The spectrum is recomputed only when H or the grid differ from the copy in hcache
+// ([kHcacheFloats], zeroed at creation); changed: device int scratch.
+constexpr int kHcacheFloats = 16 + 8192;
+hipError_t launch_psf_spectrum(const BlurPlan& bp, const float* H, sfw_dims psf, float2* hhat,
+                               float* hcache, int* changed, hipStream_t st);
+// Number of float64 loss partials the residual epilogue writes.
+int blur_residual_parts(const BlurPlan& bp, const sfw_dims& vol);
+// out = H * in (adjoint = false) or the correlation with H (adjoint = true) on the volume, with
+// epilogue kEpiPlain or kEpiResidual (out = yobs - H * in, loss partials into dpart).
+// spec: work array; tw: the plan's twiddles; hhat: the PSF spectrum of launch_psf_spectrum.
+hipError_t launch_blur(const BlurPlan& bp, const float* in, const sfw_dims& vol,
+                       const float2* hhat, bool adjoint, int epi, float* out, const float* yobs,
+                       double* dpart, float2* spec, const float2* tw, hipStream_t st);
+// When bp.chain: r = yobs - H * f (loss partials into dpart, one per plane) with the forward
+// x-y spectrum of r left in spec, then q = Phi^T r from that spectrum.
+hipError_t launch_blur_residual_chain(const BlurPlan& bp, const float* f, const sfw_dims& vol,
+                                      const float2* hhat, const float* yobs, float* r_out,
+                                      double* dpart, float2* spec, const float2* tw,
+                                      hipStream_t st);
+hipError_t launch_blur_adjoint_chain(const BlurPlan& bp, const sfw_dims& vol, const float2* hhat,
+                                     float* q_out, float2* spec, const float2* tw,
+                                     hipStream_t st);
 hipError_t fx_strided(int L, dim3 grid, hipStream_t st, const float2* src, size_t src_b,
                       float2* dst, size_t dst_b, const float2* tw, int ncols, size_t istride,
                       size_t ostride, int n_in, int n_out);
-hipError_t fx_z_inverse(int L, dim3 grid, hipStream_t st, const float2* qhat, const float2* oct,
+hipError_t fx_z_inverse(int L, hipStream_t st, const float2* qhat, const float2* oct,
                         size_t oct_b, int hx, int hy, float2* work, size_t work_b,
                         const float2* tw, int Nx, int Ny, int px, int n_out, int npairs);
 hipError_t fx_x_real(int L, dim3 grid, hipStream_t st, const float* q, int nx, int ny,
@@ -341,9 +403,13 @@ hipError_t fx_x_argmax(int L, dim3 grid, hipStream_t st, const float2* work, siz
                        int nx, int ny, int nz, const float2* tw, int Ny, int px, float scale,
                        int nslices, float* eta_out, ArgPart* apart, int nblk);
 hipError_t fft_pack_octant(const FftPlan& pl, const float2* full, float2* oct, hipStream_t st);
-hipError_t fft_inverse_pairs(const FftPlan& pl, const float2* qhat, const float2* pairs,
-                             float2* work, size_t bstride, int nslices, sfw_dims vol,
-                             float scale, float* eta_out, ArgPart* apart, int nblk,
-                             hipStream_t st);
+// The inverse side of the certificate in two launch groups: the z pass of every pair
+// (fft_inverse_pairs_z) and the y and x passes with the block maxima (fft_inverse_pairs_yx).
+hipError_t fft_inverse_pairs_z(const FftPlan& pl, const float2* qhat, const float2* pairs,
+                               float2* work, size_t bstride, int nslices, sfw_dims vol,
+                               hipStream_t st);
+hipError_t fft_inverse_pairs_yx(const FftPlan& pl, float2* work, size_t bstride, int nslices,
+                                sfw_dims vol, float scale, float* eta_out, ArgPart* apart,
+                                int nblk, hipStream_t st);
 
 }  // namespace sfw

@@ -18,10 +18,18 @@ int check_lambda(float lambda);
 struct PsfPlan {
   sfw_dims psf{1, 1, 1};
   ConvPlan valu;
-  bool mfma = false;
+  bool mfma = false;  // direct convolutions on the matrix cores (else the VALU kernel)
+  bool fft = false;   // volume blur and adjoint through the spectrum (blur)
+  BlurPlan blur;
   int nres = 0;  // number of loss partials the residual epilogue writes
 };
-PsfPlan plan_psf(const sfw_dims& vol, const sfw_dims& psf);
+// SFW_CONV selects the volume convolution: "fft", "mfma" or "valu" (direct kernels only);
+// unset, the spectral blur is used for PSFs of at least 343 taps when the workspace holds its
+// arrays.
+PsfPlan plan_psf(const sfw_workspace* ws, const sfw_dims& vol, const sfw_dims& psf);
+// PSF spectrum (and the plan's twiddles when its lengths changed) for a spectral plan; no-op
+// otherwise.
+int prep_spectrum(sfw_workspace* ws, const float* H, const PsfPlan& p);
 // Build the forward (convolution) and / or adjoint (correlation) operands of H and, when atoms
 // is not null, the constants of its n atoms into ws->ak, in one launch.
 int prep_all(sfw_workspace* ws, const float* H, const PsfPlan& p, bool fwd, bool adj,
@@ -34,11 +42,15 @@ AtomK make_atomk(double w, double mx, double my, double mz, double sigma, double
 int lasso_check_inputs(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
                        const float* H);
 int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
-             double lambda, const float* thetas, int n, std::vector<double>& w,
+             const float* H, double lambda, const float* thetas, int n, std::vector<double>& w,
              bool ak_ready = false);
 // out = H * in (adjoint = false) or correlation with H (adjoint = true); epilogue as launch_conv.
+// Spectral when p.fft (epilogues kEpiPlain and kEpiResidual), else direct.
 int conv_psf(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjoint,
              const float* in, float* out, int epi, const float* yobs, int prof_kind);
+// The same on the direct kernels whatever the plan.
+int conv_direct(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool adjoint,
+                const float* in, float* out, int epi, const float* yobs, int prof_kind);
 // ws->ak must hold the n atoms' constants.
 int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, float* phi);
 // r = y - H * f (into r_out or ws->r), q = Phi^T r (ws->q), per-atom sums and loss in ws->dres:
@@ -56,9 +68,9 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
 // Grid certificate of q; the maximum lands in ws->best (device).
 int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float lambda,
                    const float* sg, int ns, const float* dg, int nd, float T, float* eta_out);
-// LASSO columns for unit-weight atoms i in [i0, i1) already staged in ws->ak.
-int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int atom, int slot,
-               const float* theta);
+// LASSO column of the unit-weight atom staged in ws->ak[atom] (parameters theta) into slot.
+int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* H, int atom,
+               int slot, const float* theta);
 // out[0..i] = <a_i, a_j> (j <= i), out[i + 1] = <a_i, y>, float64 on the device.
 int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int slot,
                 const float* theta, int nd, double* out);

@@ -39,14 +39,20 @@ def say(*msg):
 CONFIGS = ["c1", "c2", "c3"]
 
 
-@pytest.fixture(params=["auto", "valu"])
+@pytest.fixture(params=["auto", "fft", "fft5", "mfma", "valu"])
 def conv_path(request, monkeypatch):
-    """Run a test on the default PSF convolution (matrix cores when the PSF fits) and on the
+    """Run a test on each volume convolution: the default choice (the spectral blur for large
+    PSFs, else the matrix cores), the spectral blur forced (with its fused plane passes where
+    they fit, and with the five separate passes), the matrix-core direct kernel and the
     LDS-tiled VALU kernel."""
-    if request.param == "valu":
-        monkeypatch.setenv("SFW_CONV", "valu")
-    else:
+    monkeypatch.delenv("SFW_BLUR_PASSES", raising=False)
+    if request.param == "auto":
         monkeypatch.delenv("SFW_CONV", raising=False)
+    elif request.param == "fft5":
+        monkeypatch.setenv("SFW_CONV", "fft")
+        monkeypatch.setenv("SFW_BLUR_PASSES", "1")
+    else:
+        monkeypatch.setenv("SFW_CONV", request.param)
     return request.param
 
 
