@@ -19,7 +19,7 @@ Conventions shared with the library and the oracle:
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -166,8 +166,24 @@ class Problem:
 
 def draw_problem(config: str, rep: int = 0) -> Problem:
     """Draw one seeded problem; draw order: centres, sigma, d, w, noise."""
-    cfg = CONFIGS[config]
-    seed = seed_for(config, rep)
+    return _draw(CONFIGS[config], seed_for(config, rep))
+
+
+def experiment_config(n: int, n_atoms: int) -> Config:
+    """The paper's SFW / BSFW comparison (section 3): an n^3 volume (60 to 100) holding 4, 6 or 8
+    masses under Gaussian noise. The 32^3 workload's atom distributions, PSF, noise level,
+    lambda rule and grid stand in for the paper's unavailable PSF and data."""
+    return replace(CONFIGS["c1"], name=f"x{n}_{n_atoms}", shape=(n, n, n), n_atoms=n_atoms)
+
+
+def draw_experiment(n: int, n_atoms: int, rep: int) -> Problem:
+    """One seeded problem of the comparison; seed = 10^6 + 10^4 n + 100 n_atoms + rep (rep < 100)."""
+    if not 0 <= rep < 100 or not 0 < n_atoms < 100:
+        raise ValueError("rep must be in [0, 100) and n_atoms in [1, 100)")
+    return _draw(experiment_config(n, n_atoms), 10 ** 6 + 10 ** 4 * n + 100 * n_atoms + rep)
+
+
+def _draw(cfg: Config, seed: int) -> Problem:
     rng = np.random.default_rng(seed)
     atoms = draw_atoms(cfg, rng)
     noise = rng.standard_normal(cfg.shape)
