@@ -235,9 +235,10 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
     const double* t = thetas + 5 * i;
     hk[i] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
   }
-  if (n <= kAtomArgs)  // small batches travel as kernel arguments (no copy command)
-    SFW_HIP(launch_store_atoms(hk, n, ws->ak, ws->stream));
-  else
+  // small batches: one launch, atoms as kernel arguments, sums reduced in the kernel straight
+  // into pinned host memory
+  const bool one_launch = n <= kAtomArgs;
+  if (!one_launch)
     SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
   // only the tiles where some point's atom is nonzero (its cut ball) carry terms
   int box[6] = {vol.nx, 0, vol.ny, 0, vol.nz, 0};
@@ -258,17 +259,26 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
       box[2 * a + 1] = 1;
     }
   GradPlan gp = plan_grad_box(vol, n, box);
+  if (one_launch) {
+    gp.groups = 1;
+    gp.apg = n;
+  }
   if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
     return fail(SFW_EINVAL, "gradient partial buffer too small");
+  double* hs = ws->hpin + ws->hp_sums;
   {
     ProfScope ps(ws, kProfEtaGrad);
-    SFW_HIP(launch_grad(gp, ws->ak, n, q, vol, ws->gpart, ws->stream));
-    SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, nullptr, 0, nullptr, 0.f, ws->dres,
-                                 nullptr, nullptr, ws->stream));
+    if (one_launch) {
+      SFW_HIP(launch_grad_points(gp, hk, n, q, vol, ws->gpart, ws->eta_ticket, hs, ws->stream));
+    } else {
+      SFW_HIP(launch_grad(gp, ws->ak, n, q, vol, ws->gpart, ws->stream));
+      SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, nullptr, 0, nullptr, 0.f, ws->dres,
+                                   nullptr, nullptr, ws->stream));
+    }
   }
-  double* hs = ws->hpin + ws->hp_sums;
-  SFW_HIP(hipMemcpyAsync(hs, ws->dres, sizeof(double) * 6 * n, hipMemcpyDeviceToHost,
-                         ws->stream));
+  if (!one_launch)
+    SFW_HIP(hipMemcpyAsync(hs, ws->dres, sizeof(double) * 6 * n, hipMemcpyDeviceToHost,
+                           ws->stream));
   SFW_HIP(hipStreamSynchronize(ws->stream));
   const double ln2 = 0.69314718055994531;
   for (int i = 0; i < n; ++i) {
@@ -793,6 +803,7 @@ void sfw_workspace_destroy(sfw_workspace* ws) {
   if (ws->blur_tw) (void)hipFree(ws->blur_tw);
   if (ws->blur_hcache) (void)hipFree(ws->blur_hcache);
   if (ws->blur_changed) (void)hipFree(ws->blur_changed);
+  if (ws->eta_ticket) (void)hipFree(ws->eta_ticket);
   if (ws->hpin) (void)hipHostFree(ws->hpin);
   for (hipEvent_t e : ws->prof_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ws->prof_stop) (void)hipEventDestroy(e);
@@ -902,6 +913,12 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
       ALLOC(ws->blur_tw, 3 * (size_t)kFftMaxBlur * sizeof(float2), "blur twiddles");
       ALLOC(ws->blur_hcache, (size_t)kHcacheFloats * sizeof(float), "PSF spectrum key");
       ALLOC(ws->blur_changed, sizeof(int), "PSF spectrum flag");
+      ALLOC(ws->eta_ticket, sizeof(int), "eta block counter");
+      if (hipMemset(ws->eta_ticket, 0, sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        sfw_workspace_destroy(ws);
+        return fail(SFW_EHIP, "clearing the eta block counter failed");
+      }
       if (hipMemset(ws->blur_hcache, 0, (size_t)kHcacheFloats * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         sfw_workspace_destroy(ws);

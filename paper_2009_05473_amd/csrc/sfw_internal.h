@@ -187,6 +187,7 @@ struct sfw_workspace {
   size_t blur_spec_cap = 0, blur_hhat_cap = 0;  // complex elements
   int blur_tw_key[3] = {0, 0, 0};
   float* blur_hcache = nullptr;  // [kHcacheFloats] PSF and grid of the stored spectrum
+  int* eta_ticket = nullptr;     // [1] block counter of the one-launch eta evaluation (0 at rest)
   int* blur_changed = nullptr;   // [1]
 
   // atoms
@@ -327,6 +328,12 @@ bool column_box_ok(sfw_dims psf);
 hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sfw_dims vol,
                              const int box[6], float* out, hipStream_t st);
 
+// The per-atom sums of at most kAtomArgs atoms given by their constants on the host (one atom
+// group: p.groups == 1), reduced to sums_out[6 a + c] (float64; may be host memory) by the last
+// block; ticket: device int that is 0 between launches.
+hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n, const float* q,
+                              sfw_dims vol, float* gpart, int* ticket, double* sums_out,
+                              hipStream_t st);
 hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q, sfw_dims vol,
                        float* gpart, hipStream_t st);
 // Sums partials over tiles in a fixed order (float64). For atom a:

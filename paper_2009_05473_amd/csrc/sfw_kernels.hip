@@ -629,12 +629,19 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
 // Per-atom sums over a tile of voxels (block = 256 (y, x) columns x VPT z); grid.x = tiles,
 // grid.y = atom groups. Writes gpart[tile][atom][0..5] =
 // (S_g, S_u, S_l, S_mx, S_my, S_mz) of the tile (see launch_grad_finalize).
-template <int VPT>
-__global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__ ak, int n,
-                                                       int apg, const float* __restrict__ q,
-                                                       int nx, int ny, int nz, int ntile_xy,
-                                                       int rx0, int ry0, int rtx, int rz0,
-                                                       float* __restrict__ gpart) {
+// With POINTS, the atoms come by value in `args` (at most kAtomArgs, one atom group) and the
+// last block to finish (ticket counter) sums the tile partials over tiles in a fixed order, in
+// float64, into sums_out[6 a + c] (host-visible memory is fine): one launch per evaluation of
+// the certificate at a few points, with nothing left for the host but one synchronisation.
+template <int VPT, bool POINTS>
+__global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__ ak,
+                                                       AtomArgs args, int n, int apg,
+                                                       const float* __restrict__ q, int nx,
+                                                       int ny, int nz, int ntile_xy, int rx0,
+                                                       int ry0, int rtx, int rz0,
+                                                       float* __restrict__ gpart,
+                                                       int* __restrict__ ticket,
+                                                       double* __restrict__ sums_out) {
   constexpr int NW = kGradThreads / 64;
   __shared__ float red[NW][kGradMaxAtomsPerGroup][6];
   const int tid = threadIdx.x;
@@ -657,7 +664,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
   const int wave = tid / 64;
   const WaveBox wb = wave_box(t, nx, ny, z0, min(z0 + VPT, nz) - 1);
   for (int a = a0; a < a1; ++a) {
-    const AtomK k = ak[a];
+    const AtomK k = POINTS ? args.a[a] : ak[a];
     if (wb.misses(k)) {  // every term of this wave is exactly zero
       if ((tid & 63) == 0) {
         float* rr = red[wave][a - a0];
@@ -712,6 +719,35 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
 #pragma unroll
     for (int w = 0; w < NW; ++w) t += red[w][aa][c];
     gpart[((size_t)tile * n + a0 + aa) * 6 + c] = t;
+  }
+  if (POINTS) {
+    constexpr int kSlices = 5;  // tile slices per (atom, component): 6 kAtomArgs * 5 <= 256
+    __shared__ int is_last;
+    __shared__ double part[kAtomArgs * 6][kSlices];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) is_last = atomicAdd(ticket, 1) == (int)(gridDim.x * gridDim.y) - 1;
+    __syncthreads();
+    if (is_last) {
+      __threadfence();
+      const int pairs = n * 6, ntiles = gridDim.x;
+      if (tid < pairs * kSlices) {
+        const int pr = tid / kSlices, sl = tid - pr * kSlices;
+        double acc = 0.0;
+#pragma unroll 4
+        for (int tt = sl; tt < ntiles; tt += kSlices) acc += (double)gpart[(size_t)tt * pairs + pr];
+        part[pr][sl] = acc;
+      }
+      __syncthreads();
+      if (tid < pairs) {
+        double S = 0.0;
+#pragma unroll
+        for (int sl = 0; sl < kSlices; ++sl) S += part[tid][sl];
+        sums_out[tid] = S;
+        __threadfence_system();  // the sums may live in host memory
+      }
+      if (tid == 0) *ticket = 0;  // ready for the next launch
+    }
   }
 }
 
@@ -1384,19 +1420,44 @@ hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q
                        float* gpart, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   dim3 grid(p.ntiles, p.groups);
+  AtomArgs none;
+  std::memset(&none, 0, sizeof(none));
   switch (p.vpt) {
-    case 64:
-      hipLaunchKernelGGL(k_grad<64>, grid, dim3(kGradThreads), 0, st, ak, n, p.apg, q, vol.nx,
-                         vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart);
-      break;
-    case 32:
-      hipLaunchKernelGGL(k_grad<32>, grid, dim3(kGradThreads), 0, st, ak, n, p.apg, q, vol.nx,
-                         vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart);
-      break;
+#define SFW_GRAD_CASE(V)                                                                       \
+  case V:                                                                                      \
+    hipLaunchKernelGGL((k_grad<V, false>), grid, dim3(kGradThreads), 0, st, ak, none, n, p.apg, \
+                       q, vol.nx, vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0,       \
+                       gpart, nullptr, nullptr);                                                \
+    break;
+    SFW_GRAD_CASE(64)
+    SFW_GRAD_CASE(32)
     default:
-      hipLaunchKernelGGL(k_grad<16>, grid, dim3(kGradThreads), 0, st, ak, n, p.apg, q, vol.nx,
-                         vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart);
-      break;
+      SFW_GRAD_CASE(16)
+#undef SFW_GRAD_CASE
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n, const float* q,
+                              sfw_dims vol, float* gpart, int* ticket, double* sums_out,
+                              hipStream_t st) {
+  if (n <= 0 || n > kAtomArgs || p.groups != 1) return hipErrorInvalidValue;
+  AtomArgs args;
+  std::memset(&args, 0, sizeof(args));
+  std::memcpy(args.a, host_atoms, sizeof(AtomK) * n);
+  dim3 grid(p.ntiles, 1);
+  switch (p.vpt) {
+#define SFW_GRAD_CASE(V)                                                                       \
+  case V:                                                                                      \
+    hipLaunchKernelGGL((k_grad<V, true>), grid, dim3(kGradThreads), 0, st, nullptr, args, n, n, \
+                       q, vol.nx, vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0,       \
+                       gpart, ticket, sums_out);                                                \
+    break;
+    SFW_GRAD_CASE(64)
+    SFW_GRAD_CASE(32)
+    default:
+      SFW_GRAD_CASE(16)
+#undef SFW_GRAD_CASE
   }
   return hipGetLastError();
 }
