@@ -192,6 +192,31 @@ def test_residual_grad_cut_atoms(L, ws_big):
     assert rel_l2(gg, g) <= 1e-4
 
 
+def test_psf_spectrum_follows_h(L, ws_big, monkeypatch):
+    """The spectral blur keeps the PSF spectrum between calls: overwriting H in place, and a
+    PSF of another shape, must both be seen."""
+    monkeypatch.setenv("SFW_CONV", "fft")
+    rng = np.random.default_rng(77)
+    shape = (20, 36, 30)
+    atoms = f32(synth.random_atoms(rng, 5, shape))
+    h1 = f32(np.abs(rng.standard_normal((9, 7, 7))) + 0.05)
+    h2 = f32(np.abs(rng.standard_normal((9, 7, 7))) + 0.05)
+    h3 = f32(np.abs(rng.standard_normal((5, 9, 3))) + 0.05)
+    H = dev(h1)
+    A = dev(atoms)
+    say("PSF spectrum cache", shape)
+    p1 = L.sfw_forward(ws_big, H, A, shape).cpu().numpy()
+    H.copy_(dev(h2))  # same buffer, new taps
+    p2 = L.sfw_forward(ws_big, H, A, shape).cpu().numpy()
+    p3 = L.sfw_forward(ws_big, dev(h3), A, shape).cpu().numpy()
+    p1b = L.sfw_forward(ws_big, dev(h1), A, shape).cpu().numpy()
+    f = oracle.render(shape, atoms)
+    assert rel_l2(p1, oracle.blur(f, h1)) <= 1e-5
+    assert rel_l2(p2, oracle.blur(f, h2)) <= 1e-5
+    assert rel_l2(p3, oracle.blur(f, h3)) <= 1e-5
+    assert rel_l2(p1b, oracle.blur(f, h1)) <= 1e-5
+
+
 def test_adjoint_parity(L, ws_big, conv_path):
     rng = np.random.default_rng(5)
     shape = (31, 45, 50)
@@ -311,16 +336,19 @@ def test_certificate_argmax_only_matches_grid(L, ws_big, cert_path):
     assert b1 == b2
 
 
-def test_eta_points_parity(L, ws_big):
+@pytest.mark.parametrize("npts", [1, 6, 8, 11])
+def test_eta_points_parity(L, ws_big, npts):
+    """Up to 8 points take the one-launch path (atoms as kernel arguments, sums reduced by the
+    last block into host memory); more take the staged path."""
     prob, atoms, psf, y = _problem("c1")
     lam = 0.8
     r = f32(y - oracle.blur(oracle.render(prob.shape, atoms[:1]), psf))
     q = f32(oracle.adjoint(r, psf))
-    rng = np.random.default_rng(9)
-    th = np.zeros((6, 5))
-    th[:, 0:3] = rng.uniform(3, 28, size=(6, 3))
-    th[:, 3] = rng.uniform(0.7, 3.0, size=6)
-    th[:, 4] = rng.uniform(1.3, 2.9, size=6)
+    rng = np.random.default_rng(9 + npts)
+    th = np.zeros((npts, 5))
+    th[:, 0:3] = rng.uniform(3, 28, size=(npts, 3))
+    th[:, 3] = rng.uniform(0.7, 3.0, size=npts)
+    th[:, 4] = rng.uniform(1.3, 2.9, size=npts)
     th[0, 0:3] = np.round(th[0, 0:3])  # on a voxel centre
     th = f32(th)
     say("sfw_eta_points", th.shape)
