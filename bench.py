@@ -210,6 +210,7 @@ def solve_run(L, ws, H, Y, lam, prob, sg, dg):
             "proposal": "grid", "seconds": dt, "status": int(code), "atoms_found": len(atoms),
             "atoms_true": int(truth.shape[0]), "max_centre_error_voxels": err,
             "iterations": stats["iterations"], "criterion": stats["criterion"],
+            "eta_evaluations": stats["n_eval_eta"], "cgrad_evaluations": stats["n_eval_cgrad"],
             "seconds_certificate": stats["seconds_certificate"],
             "seconds_ascent": stats["seconds_ascent"], "seconds_lasso": stats["seconds_lasso"],
             "seconds_slide": stats["seconds_slide"]}

@@ -46,9 +46,16 @@ struct MinResult {
 
 using FG = std::function<int(const std::vector<double>&, double&, std::vector<double>&)>;
 
+// Relative resolution of a value the library computes (criterion, certificate): float32
+// voxels summed in float64.
+constexpr double kFloat32Resolution = 1e-7;
+
+// noise_stop: end the line search once the predicted decrease is below the float32
+// resolution of f (used for the local ascent, whose result only seeds a new mass; the
+// sliding descents keep backtracking, which lets nearby masses finish merging).
 MinResult minimize_box(const FG& fg, std::vector<double>& x, const std::vector<double>& lo,
                        const std::vector<double>& hi, int m, double gtol, double ftol,
-                       int maxiter) {
+                       int maxiter, bool noise_stop = false) {
   MinResult res;
   const int n = (int)x.size();
   for (int i = 0; i < n; ++i) x[i] = std::min(std::max(x[i], lo[i]), hi[i]);
@@ -132,6 +139,9 @@ MinResult minimize_box(const FG& fg, std::vector<double>& x, const std::vector<d
         xn[i] = std::min(std::max(x[i] + step * d[i], lo[i]), hi[i]);
         dec += g[i] * (xn[i] - x[i]);
       }
+      // f is evaluated from float32 volumes: once the predicted decrease is below its
+      // resolution, no sufficient-decrease test can be trusted; stop backtracking
+      if (noise_stop && -dec <= kFloat32Resolution * std::max(std::fabs(f), 1.0)) break;
       rc = fg(xn, fnew, gn);
       res.evaluations++;
       if (rc) {
@@ -277,12 +287,10 @@ struct Solver {
       return rc;
     };
     MinResult r = minimize_box(fg, th, lo, hi, o.lbfgs_memory, o.ascent_gtol, o.ftol,
-                               o.ascent_max_iter);
+                               o.ascent_max_iter, true);
     if (r.status) return r.status;
-    std::vector<double> g(5);
-    int rc = op_eta_points(ws, vol, ws->q, lam, th.data(), 1, &eta_star, g.data());
-    st.n_eval_eta++;
-    return rc;
+    eta_star = -r.f;  // the minimiser's last value is eta at the returned point
+    return SFW_OK;
   }
 
   int slide() {
