@@ -171,7 +171,7 @@ int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, 
 
 int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
              float lambda, const sfw_atom* atoms_dev, int n, float* r_out, double* loss_out,
-             sfw_atom* grad_out) {
+             sfw_atom* grad_out, double* sums) {
   float* r = r_out ? r_out : ws->r;
   {
     ProfScope ps(ws, kProfRender);
@@ -204,7 +204,7 @@ int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
   }
   ProfScope ps(ws, kProfGradFinalize);
   SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, ws->dpart, p.nres, atoms_dev, lambda,
-                               ws->dres, grad_out, loss_out, ws->stream));
+                               sums ? sums : ws->dres, grad_out, loss_out, ws->stream));
   return SFW_OK;
 }
 

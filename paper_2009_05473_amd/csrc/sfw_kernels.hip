@@ -776,6 +776,7 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
       double S[6];
       for (int c = 0; c < 6; ++c) S[c] = red[c][0] + red[c][1] + red[c][2] + red[c][3];
       for (int c = 0; c < 6; ++c) sums[(size_t)a * 6 + c] = S[c];
+      __threadfence_system();  // sums may live in host memory
       if (grad_out) {
         const sfw_atom at = atoms[a];
         const double w = at.w, d = at.d, sg = at.sigma;
@@ -809,6 +810,7 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
       const double loss = 0.5 * ss + (double)lambda * wsum;
       sums[(size_t)n * 6] = loss;
       sums[(size_t)n * 6 + 1] = 0.5 * ss;
+      __threadfence_system();
       if (loss_out) *loss_out = loss;
     }
   }

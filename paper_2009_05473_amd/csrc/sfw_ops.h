@@ -53,11 +53,12 @@ int conv_direct(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool a
                 const float* in, float* out, int epi, const float* yobs, int prof_kind);
 // ws->ak must hold the n atoms' constants.
 int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, float* phi);
-// r = y - H * f (into r_out or ws->r), q = Phi^T r (ws->q), per-atom sums and loss in ws->dres:
-// dres[6a + c] (see launch_grad_finalize), dres[6n] = C, dres[6n + 1] = 1/2 ||r||^2.
+// r = y - H * f (into r_out or ws->r), q = Phi^T r (ws->q), per-atom sums and loss in sums
+// (ws->dres when null; host-visible memory is fine): sums[6a + c] (see launch_grad_finalize),
+// sums[6n] = C, sums[6n + 1] = 1/2 ||r||^2.
 int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
              float lambda, const sfw_atom* atoms_dev, int n, float* r_out, double* loss_out,
-             sfw_atom* grad_out);
+             sfw_atom* grad_out, double* sums = nullptr);
 // q = Phi^T g (ws->q) and grad[n] = sum_s q df/d(w, m, sigma, d): the vector-Jacobian
 // product of the forward model; ws->ak must hold the n atoms' constants.
 int op_vjp(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* gvol,

@@ -229,11 +229,9 @@ struct Solver {
     }
     SFW_HIP(hipMemcpyAsync(ws->atoms_dev, h, sizeof(sfw_atom) * n, hipMemcpyHostToDevice,
                            ws->stream));
-    int rc = prep_all(ws, nullptr, plan, false, false, ws->atoms_dev, n, unit_weight);
-    if (rc) return rc;
-    // the pinned staging buffer is reused right away by callers: wait for the copy
-    SFW_HIP(hipStreamSynchronize(ws->stream));
-    return SFW_OK;
+    // No wait here: the staging buffer is only rewritten by the next upload, and every caller
+    // synchronises the stream (its readback) before that, so the copy has finished by then.
+    return prep_all(ws, nullptr, plan, false, false, ws->atoms_dev, n, unit_weight);
   }
 
   // C and dC/d(atoms) at a (float64 host), r and q left in the workspace.
@@ -241,11 +239,10 @@ struct Solver {
     const int n = (int)(a.size() / 6);
     int rc = upload_atoms(a, false);
     if (rc) return rc;
-    rc = op_cgrad(ws, plan, vol, y, (float)lam, ws->atoms_dev, n, nullptr, nullptr, nullptr);
-    if (rc) return rc;
+    // the sums land in pinned host memory straight from the finalize kernel
     double* hs = ws->hpin + ws->hp_sums;
-    SFW_HIP(hipMemcpyAsync(hs, ws->dres, sizeof(double) * (6 * n + 2), hipMemcpyDeviceToHost,
-                           ws->stream));
+    rc = op_cgrad(ws, plan, vol, y, (float)lam, ws->atoms_dev, n, nullptr, nullptr, nullptr, hs);
+    if (rc) return rc;
     SFW_HIP(hipStreamSynchronize(ws->stream));
     st.n_eval_cgrad++;
     double wsum = 0.0;
