@@ -631,8 +631,9 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
 // (S_g, S_u, S_l, S_mx, S_my, S_mz) of the tile (see launch_grad_finalize).
 // With POINTS, the atoms come by value in `args` (at most kAtomArgs, one atom group) and the
 // last block to finish (ticket counter) sums the tile partials over tiles in a fixed order, in
-// float64, into sums_out[6 a + c] (host-visible memory is fine): one launch per evaluation of
-// the certificate at a few points, with nothing left for the host but one synchronisation.
+// float64, into sums_out[6 a + c]: one launch per evaluation of the certificate at a few
+// points, with nothing left for the host but one synchronisation. sums_out may be pinned host
+// memory: the kernel's writes to it are visible once the stream has been synchronised.
 template <int VPT, bool POINTS>
 __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__ ak,
                                                        AtomArgs args, int n, int apg,
@@ -744,7 +745,6 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
 #pragma unroll
         for (int sl = 0; sl < kSlices; ++sl) S += part[tid][sl];
         sums_out[tid] = S;
-        __threadfence_system();  // the sums may live in host memory
       }
       if (tid == 0) *ticket = 0;  // ready for the next launch
     }
@@ -776,7 +776,6 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
       double S[6];
       for (int c = 0; c < 6; ++c) S[c] = red[c][0] + red[c][1] + red[c][2] + red[c][3];
       for (int c = 0; c < 6; ++c) sums[(size_t)a * 6 + c] = S[c];
-      __threadfence_system();  // sums may live in host memory
       if (grad_out) {
         const sfw_atom at = atoms[a];
         const double w = at.w, d = at.d, sg = at.sigma;
@@ -810,7 +809,6 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
       const double loss = 0.5 * ss + (double)lambda * wsum;
       sums[(size_t)n * 6] = loss;
       sums[(size_t)n * 6 + 1] = 0.5 * ss;
-      __threadfence_system();
       if (loss_out) *loss_out = loss;
     }
   }
