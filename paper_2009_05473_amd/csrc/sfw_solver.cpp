@@ -16,6 +16,7 @@
 #include <functional>
 #include <limits>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "sfw_internal.h"
@@ -308,6 +309,9 @@ struct Solver {
     };
     MinResult r = minimize_box(fg, atoms, lo, hi, o.lbfgs_memory, o.slide_gtol, o.ftol,
                                o.slide_max_iter);
+    if (o.verbose)
+      std::fprintf(stderr, "[sfw] slide n=%d it=%d evals=%d converged=%d C=%.12g\n", n,
+                   r.iterations, r.evaluations, (int)r.converged, r.f);
     return r.status;
   }
 
@@ -359,12 +363,80 @@ struct Solver {
         double C1 = 0.0;
         rc = cgrad(atoms, C1, nullptr);
         if (rc) return rc;
+        if (o.verbose)
+          std::fprintf(stderr, "[sfw] sliver w=%.6g of %.6g: C %.12g -> %.12g\n", keep[6 * c],
+                       wmax, C0, C1);
         if (C1 <= C0 + kSliverTol * std::fabs(C0)) {
           dropped = true;
           break;
         }
       }
       if (!dropped) {
+        atoms = keep;
+        return SFW_OK;
+      }
+      prune();
+    }
+  }
+
+  // Two masses of the final support within a fraction of a width of each other can stand
+  // for one: the criterion is linear in the weights, so two copies of one atom equal a
+  // single atom of the summed weight, and the float64 descent drives such a pair together.
+  // In float32 the last part of that path is flatter than the criterion's resolution and
+  // the descent can stop with the pair split. Pairs whose centres are closer than
+  // kMergeDist times the smaller sigma are tried closest first: the pair becomes one mass
+  // with the summed weight at the weight-averaged parameters, the support slides, and the
+  // merge stays when the criterion is no higher than before (relative kSliverTol).
+  // Repeats until no pair merges.
+  int merge_pairs() {
+    constexpr double kMergeDist = 0.5, kSliverTol = 1e-7;
+    for (;;) {
+      const int n = k();
+      if (n <= 1) return SFW_OK;
+      std::vector<std::pair<double, std::pair<int, int>>> cand;
+      for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+          const double* a = &atoms[6 * i];
+          const double* b = &atoms[6 * j];
+          const double dist = std::sqrt((a[1] - b[1]) * (a[1] - b[1]) +
+                                        (a[2] - b[2]) * (a[2] - b[2]) +
+                                        (a[3] - b[3]) * (a[3] - b[3]));
+          if (dist < kMergeDist * std::min(a[4], b[4])) cand.push_back({dist, {i, j}});
+        }
+      if (cand.empty()) return SFW_OK;
+      std::sort(cand.begin(), cand.end());
+      double C0 = 0.0;
+      int rc = cgrad(atoms, C0, nullptr);
+      if (rc) return rc;
+      const std::vector<double> keep = atoms;
+      bool merged = false;
+      for (const auto& c : cand) {
+        const int i = c.second.first, j = c.second.second;
+        const double wi = keep[6 * i], wj = keep[6 * j], wsum = wi + wj;
+        atoms.clear();
+        for (int m = 0; m < n; ++m) {
+          if (m == j) continue;
+          atoms.insert(atoms.end(), &keep[6 * m], &keep[6 * m] + 6);
+          if (m == i && wsum > 0.0) {
+            double* a = &atoms[atoms.size() - 6];
+            a[0] = wsum;
+            for (int p = 1; p < 6; ++p) a[p] = (wi * keep[6 * i + p] + wj * keep[6 * j + p]) / wsum;
+          }
+        }
+        rc = slide();
+        if (rc) return rc;
+        double C1 = 0.0;
+        rc = cgrad(atoms, C1, nullptr);
+        if (rc) return rc;
+        if (o.verbose)
+          std::fprintf(stderr, "[sfw] merge %d,%d at %.4g: C %.12g -> %.12g\n", i, j, c.first,
+                       C0, C1);
+        if (C1 <= C0 + kSliverTol * std::fabs(C0)) {
+          merged = true;
+          break;
+        }
+      }
+      if (!merged) {
         atoms = keep;
         return SFW_OK;
       }
@@ -507,6 +579,8 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
           if (rc) return rc;
           S.prune();
         }
+        rc = S.merge_pairs();
+        if (rc) return rc;
         rc = S.drop_slivers();
         if (rc) return rc;
         S.st.seconds_slide += secs(ts, Clock::now());
