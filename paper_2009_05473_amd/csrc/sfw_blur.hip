@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 
 #include "sfw_fft_radix.h"
@@ -291,6 +292,12 @@ __global__ __launch_bounds__(bx_threads(R1, R2)) void k_bx_c2r(
 // (np = ceil(ny / 2)) share complex line l. Dynamic LDS: plane [ny][hx], then the exchange
 // buffer [max(np, hx)][L | 1].
 constexpr int kPlaneThreads = 1024;
+
+// whole planes move as float4 when rows are a multiple of four floats and the buffers are
+// 16-byte aligned (yobs may be null)
+__device__ inline bool vec_rows(int nx, const float* a, const float* b) {
+  return ((nx & 3) | ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15)) == 0;
+}
 // dynamic LDS of the fused passes: 160 KiB per block less the static twiddles and partials
 constexpr size_t kPlaneLdsMax = 160 * 1024 - 4096;
 
@@ -300,7 +307,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_fwd(
     const float* __restrict__ in, int nx, int ny, float2* __restrict__ spec, int px, int hx,
     const float2* __restrict__ twg) {
   constexpr int L = R1 * R2, LS = L | 1, NT = kPlaneThreads;
-  extern __shared__ float2 lds[];
+  extern __shared__ __align__(16) float2 lds[];
   __shared__ float2 tw[L];
   float2* plane = lds;
   float2* xb = lds + (size_t)ny * hx;
@@ -308,6 +315,18 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_fwd(
   const int z = blockIdx.x, np = (ny + 1) / 2;
   const float* src = in + (size_t)z * ny * nx;
   const int t = threadIdx.x;
+  // the real plane first goes to LDS (in the plane buffer, free until the split) with
+  // coalesced loads, four floats per load where the rows allow
+  float* stage = reinterpret_cast<float*>(plane);
+  const int nv = ny * nx;
+  if (((nx & 3) | (reinterpret_cast<uintptr_t>(in) & 15)) == 0) {
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+    float4* d4 = reinterpret_cast<float4*>(stage);
+    for (int e = t; e < nv / 4; e += NT) d4[e] = s4[e];
+  } else {
+    for (int e = t; e < nv; e += NT) stage[e] = src[e];
+  }
+  __syncthreads();
   // x, stage 1: task (l, j), j < R2
   for (int task = t; task < np * R2; task += NT) {
     const int j = task % R2, l = task / R2;
@@ -318,8 +337,8 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_fwd(
     for (int r = 0; r < R1; ++r) {
       const int i = j + r * R2;
       const bool ia = i < nx, ib = okb && i < nx;
-      const float a = src[ia ? (size_t)ya * nx + i : 0];
-      const float b = src[ib ? (size_t)yb * nx + i : 0];
+      const float a = stage[ia ? ya * nx + i : 0];
+      const float b = stage[ib ? yb * nx + i : 0];
       v[r] = make_float2(ia ? a : 0.f, ib ? b : 0.f);
     }
     Dft<R1>::run(v);
@@ -388,7 +407,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv(
     const float2* __restrict__ twg, float* __restrict__ out, const float* __restrict__ yobs,
     double* __restrict__ dpart) {
   constexpr int L = R1 * R2, LS = L | 1, NT = kPlaneThreads;
-  extern __shared__ float2 lds[];
+  extern __shared__ __align__(16) float2 lds[];
   __shared__ float2 tw[L];
   __shared__ double red[NT / 64];
   float2* plane = lds;
@@ -443,6 +462,8 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv(
     for (int r = 0; r < R1; ++r) xb[l * LS + j * R1 + r] = v[r];
   }
   __syncthreads();
+  // x, stage 2: the real rows go to the plane buffer (free once stage 1 has read it)
+  float* stage = reinterpret_cast<float*>(plane);
   double acc = 0.0;
   for (int task = t; task < np * R1; task += NT) {
     const int j = task % R1, l = task / R1;
@@ -454,25 +475,42 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv(
     }
     Dft<R2>::run(v);
     const int ya = l, yb = l + np;
-    const size_t oa = ((size_t)z * ny + ya) * nx, ob = ((size_t)z * ny + yb) * nx;
 #pragma unroll
     for (int r = 0; r < R2; ++r) {
       const int x = j + r * R1;
       if (x < nx) {
-        const float ua = v[r].x * scale, ub = -v[r].y * scale;
-        if (EPI == kEpiResidual) {
-          const float d = yobs[oa + x] - ua;
-          out[oa + x] = d;
-          acc += (double)d * d;
-          if (yb < ny) {
-            const float e = yobs[ob + x] - ub;
-            out[ob + x] = e;
-            acc += (double)e * e;
-          }
-        } else {
-          out[oa + x] = ua;
-          if (yb < ny) out[ob + x] = ub;
-        }
+        stage[ya * nx + x] = v[r].x * scale;
+        if (yb < ny) stage[yb * nx + x] = -v[r].y * scale;
+      }
+    }
+  }
+  __syncthreads();
+  // the plane's rows leave with coalesced accesses (four floats at a time where rows allow)
+  const size_t base = (size_t)z * ny * nx;
+  const int nv = ny * nx;
+  if (vec_rows(nx, out, yobs)) {
+    const float4* s4 = reinterpret_cast<const float4*>(stage);
+    float4* o4 = reinterpret_cast<float4*>(out + base);
+    const float4* y4 = reinterpret_cast<const float4*>(yobs + (EPI == kEpiResidual ? base : 0));
+    for (int e = t; e < nv / 4; e += NT) {
+      const float4 u = s4[e];
+      if (EPI == kEpiResidual) {
+        const float4 yv = y4[e];
+        const float4 d = make_float4(yv.x - u.x, yv.y - u.y, yv.z - u.z, yv.w - u.w);
+        o4[e] = d;
+        acc += (double)d.x * d.x + (double)d.y * d.y + (double)d.z * d.z + (double)d.w * d.w;
+      } else {
+        o4[e] = u;
+      }
+    }
+  } else {
+    for (int e = t; e < nv; e += NT) {
+      if (EPI == kEpiResidual) {
+        const float d = yobs[base + e] - stage[e];
+        out[base + e] = d;
+        acc += (double)d * d;
+      } else {
+        out[base + e] = stage[e];
       }
     }
   }
@@ -492,15 +530,15 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv(
 // the y and x inverse passes of k_bxy_inv with the residual epilogue (r = yobs - H * f to r_out,
 // loss partial to dpart[z]), then r of the same two rows per line goes straight back through
 // the forward x DFT and the y DFT of k_bxy_fwd, whose spectrum overwrites plane z of spec.
-// Needs every phase to fit in one task per thread (checked on the host), so that a stage can
-// read all its inputs before any thread overwrites them in place.
+// Every phase fits in one task per thread (checked on the host); the residual rows stay in
+// the plane buffer between the two halves.
 template <int R1, int R2>
 __global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv_fwd(
     float2* __restrict__ spec, int nx, int ny, int px, int hx, float scale,
     const float2* __restrict__ twg, float* __restrict__ r_out, const float* __restrict__ yobs,
     double* __restrict__ dpart) {
   constexpr int L = R1 * R2, LS = L | 1, NT = kPlaneThreads;
-  extern __shared__ float2 lds[];
+  extern __shared__ __align__(16) float2 lds[];
   __shared__ float2 tw[L];
   __shared__ double red[NT / 64];
   float2* plane = lds;
@@ -557,8 +595,9 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv_fwd(
     for (int r = 0; r < R1; ++r) xb[l * LS + j * R1 + r] = v[r];
   }
   __syncthreads();
-  // x inverse, stage 2, residual epilogue; (r_a, r_b) of line l replaces its own slots
-  double acc = 0.0;
+  // x inverse, stage 2: the real rows H * f go to the plane buffer (free once stage 1 has
+  // read it)
+  float* stage = reinterpret_cast<float*>(plane);
   if (t < np * R1) {
     const int j = t % R1, l = t / R1;
     float2 v[R2];
@@ -569,41 +608,59 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv_fwd(
     }
     Dft<R2>::run(v);
     const int ya = l, yb = l + np;
-    const bool okb = yb < ny;
-    const size_t oa = ((size_t)z * ny + ya) * nx, ob = ((size_t)z * ny + yb) * nx;
 #pragma unroll
     for (int r = 0; r < R2; ++r) {
       const int x = j + r * R1;
-      float2 rr = make_float2(0.f, 0.f);
       if (x < nx) {
-        rr.x = yobs[oa + x] - v[r].x * scale;
-        r_out[oa + x] = rr.x;
-        acc += (double)rr.x * rr.x;
-        if (okb) {
-          rr.y = yobs[ob + x] + v[r].y * scale;
-          r_out[ob + x] = rr.y;
-          acc += (double)rr.y * rr.y;
-        }
+        stage[ya * nx + x] = v[r].x * scale;
+        if (yb < ny) stage[yb * nx + x] = -v[r].y * scale;
       }
-      xb[l * LS + x] = rr;
     }
   }
   __syncthreads();
-  // forward x, stage 1: read every input first, then write in place
+  // residual epilogue with coalesced accesses; r stays in LDS for the forward transform
+  double acc = 0.0;
   {
-    float2 v[R1];
+    const size_t base = (size_t)z * ny * nx;
+    const int nv = ny * nx;
+    if (vec_rows(nx, r_out, yobs)) {
+      float4* s4 = reinterpret_cast<float4*>(stage);
+      float4* o4 = reinterpret_cast<float4*>(r_out + base);
+      const float4* y4 = reinterpret_cast<const float4*>(yobs + base);
+      for (int e = t; e < nv / 4; e += NT) {
+        const float4 u = s4[e], yv = y4[e];
+        const float4 d = make_float4(yv.x - u.x, yv.y - u.y, yv.z - u.z, yv.w - u.w);
+        o4[e] = d;
+        s4[e] = d;
+        acc += (double)d.x * d.x + (double)d.y * d.y + (double)d.z * d.z + (double)d.w * d.w;
+      }
+    } else {
+      for (int e = t; e < nv; e += NT) {
+        const float d = yobs[base + e] - stage[e];
+        r_out[base + e] = d;
+        stage[e] = d;
+        acc += (double)d * d;
+      }
+    }
+  }
+  __syncthreads();
+  // forward x, stage 1 from the residual rows (zero beyond the volume)
+  if (t < np * R2) {
     const int j = t % R2, l = t / R2;
-    const bool act = t < np * R2;
-    if (act) {
+    const int ya = l, yb = l + np;
+    const bool okb = yb < ny;
+    float2 v[R1];
 #pragma unroll
-      for (int r = 0; r < R1; ++r) v[r] = xb[l * LS + j + r * R2];
-      Dft<R1>::run(v);
+    for (int r = 0; r < R1; ++r) {
+      const int i = j + r * R2;
+      const bool ia = i < nx, ib = okb && i < nx;
+      const float a = stage[ia ? ya * nx + i : 0];
+      const float b = stage[ib ? yb * nx + i : 0];
+      v[r] = make_float2(ia ? a : 0.f, ib ? b : 0.f);
     }
-    __syncthreads();
-    if (act) {
+    Dft<R1>::run(v);
 #pragma unroll
-      for (int r = 0; r < R1; ++r) xb[l * LS + j * R1 + r] = v[r];
-    }
+    for (int r = 0; r < R1; ++r) xb[l * LS + j * R1 + r] = v[r];
   }
   __syncthreads();
   if (t < np * R1) {
