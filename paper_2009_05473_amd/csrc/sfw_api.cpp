@@ -437,7 +437,8 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
                                    eta_out, ws->apart, nblk, ws->stream));
     }
     ProfScope ps(ws, kProfCertArgmax);
-    SFW_HIP(launch_argmax_final(ws->apart, nblk * ns * nd, vol, nd, ws->best, ws->stream));
+    SFW_HIP(launch_argmax_final(ws->apart, nblk * ns * nd, vol, nd, ws->best, pinned_best(ws),
+                                ws->stream));
     return SFW_OK;
   }
   int nb = 0;
@@ -456,7 +457,8 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
                           ws->stream));
     }
   ProfScope ps(ws, kProfCertArgmax);
-  SFW_HIP(launch_argmax_final(ws->apart, nb * ns * nd, vol, nd, ws->best, ws->stream));
+  SFW_HIP(launch_argmax_final(ws->apart, nb * ns * nd, vol, nd, ws->best, pinned_best(ws),
+                              ws->stream));
   return SFW_OK;
 }
 
@@ -535,40 +537,41 @@ static bool column_box(const float* theta, const sfw_dims& psf, const sfw_dims& 
   return !whole;
 }
 
-// Gram row of slot `slot` against the nd slots listed in ws->lasso_slots, then <a, y>: out
-// (float64, device) [nd + 1]. theta: the unit atom of the slot (host), used to restrict the sums
-// to its support.
+// Gram row of slot `slot` against the nd slots sa (the first kSlotArgs; all of them in
+// ws->lasso_slots when there are more), then <a, y>: out [nd + 1] (float64; device or pinned
+// host memory). theta: the unit atom of the slot (host), used to restrict the sums to its
+// support.
 int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int slot,
-                const float* theta, int nd, double* out) {
+                const float* theta, const SlotArgs& sa, int nd, double* out) {
   const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
   const float* a = ws->cols + (size_t)slot * ws->vcap;
   ProfScope ps(ws, kProfLassoDots);
   int box[6];
   if (vol.nx % 4 == 0 && ws->vcap % 4 == 0 && column_box(theta, p.psf, vol, box)) {
-    SFW_HIP(launch_dots_box(a, ws->cols, ws->lasso_slots, nd, ws->vcap, y, vol, box, ws->dpart,
-                            (int)std::min<size_t>(ws->dpart_cap, 1u << 30), out, ws->stream));
+    SFW_HIP(launch_dots_box(a, ws->cols, sa, ws->lasso_slots, nd, ws->vcap, y, vol, box,
+                            ws->dpart, (int)std::min<size_t>(ws->dpart_cap, 1u << 30), out,
+                            ws->stream));
     return SFW_OK;
   }
   int nb = (int)std::min<size_t>(1024, (V + 1023) / 1024);
   if ((size_t)nb * (nd + 1) > ws->dpart_cap) return fail(SFW_EINVAL, "dot partial buffer too small");
-  SFW_HIP(launch_dots(a, ws->cols, ws->lasso_slots, nd, ws->vcap, y, V, ws->dpart, nb, out,
+  SFW_HIP(launch_dots(a, ws->cols, sa, ws->lasso_slots, nd, ws->vcap, y, V, ws->dpart, nb, out,
                       ws->stream));
   return SFW_OK;
 }
 
-// Enqueue the fingerprints of y and H (and a copy of the n device atoms, if any) and their
-// readback into the pinned region at hp_hash (atoms at hp_atoms); read them with
-// read_fingerprints once the stream has been synchronised.
+// Enqueue the fingerprints of y and H (and a copy of the n device atoms, if any) into the
+// pinned region at hp_hash (atoms at hp_atoms); read them with read_fingerprints once the
+// stream has been synchronised.
 static int enqueue_fingerprints(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
                                 const float* y, const float* H, const sfw_atom* atoms, int n,
                                 int* by, int* bh) {
   ProfScope ps(ws, kProfHash);
   const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
+  // the kernel writes the partials and the atoms straight into the pinned region
   SFW_HIP(launch_fingerprints(y, V, H, (size_t)p.psf.nx * p.psf.ny * p.psf.nz, atoms, n,
-                              ws->hashbuf, by, bh, ws->stream));
-  const size_t words = 2 * (size_t)kFpParts + (atoms ? 3 * (size_t)n : 0);
-  SFW_HIP(hipMemcpyAsync(ws->hpin + ws->hp_hash, ws->hashbuf, words * 8, hipMemcpyDeviceToHost,
-                         ws->stream));
+                              reinterpret_cast<unsigned long long*>(ws->hpin + ws->hp_hash), by,
+                              bh, ws->stream));
   return SFW_OK;
 }
 
@@ -703,19 +706,24 @@ int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
     }
   }
   if (!rows.empty()) {
-    int* hs = reinterpret_cast<int*>(ws->hpin + ws->hp_slots);
-    std::copy(D.begin(), D.end(), hs);
-    SFW_HIP(hipMemcpyAsync(ws->lasso_slots, hs, sizeof(int) * nd, hipMemcpyHostToDevice,
-                           ws->stream));
+    // the slot list rides in the kernel arguments; a longer one also goes to the device
+    SlotArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    std::copy(D.begin(), D.begin() + std::min(nd, kSlotArgs), sa.s);
+    if (nd > kSlotArgs) {
+      int* hs = reinterpret_cast<int*>(ws->hpin + ws->hp_slots);
+      std::copy(D.begin(), D.end(), hs);
+      SFW_HIP(hipMemcpyAsync(ws->lasso_slots, hs, sizeof(int) * nd, hipMemcpyHostToDevice,
+                             ws->stream));
+    }
+    // the rows' final sums go straight to pinned host memory
     const size_t stride = (size_t)nd + 1;
+    double* hr = ws->hpin + ws->hp_rows;
     for (size_t r = 0; r < rows.size(); ++r) {
-      int rc = op_gram_row(ws, p, vol, y, rows[r], &ws->slot_theta[5 * (size_t)rows[r]], nd,
-                           ws->dres + r * stride);
+      int rc = op_gram_row(ws, p, vol, y, rows[r], &ws->slot_theta[5 * (size_t)rows[r]], sa, nd,
+                           hr + r * stride);
       if (rc) return rc;
     }
-    double* hr = ws->hpin + ws->hp_rows;
-    SFW_HIP(hipMemcpyAsync(hr, ws->dres, rows.size() * stride * 8, hipMemcpyDeviceToHost,
-                           ws->stream));
     SFW_HIP(hipStreamSynchronize(ws->stream));
     for (size_t r = 0; r < rows.size(); ++r) {
       const int sa = rows[r];
@@ -792,7 +800,6 @@ void sfw_workspace_destroy(sfw_workspace* ws) {
   if (ws->dres) (void)hipFree(ws->dres);
   if (ws->apart) (void)hipFree(ws->apart);
   if (ws->best) (void)hipFree(ws->best);
-  if (ws->hashbuf) (void)hipFree(ws->hashbuf);
   if (ws->lasso_slots) (void)hipFree(ws->lasso_slots);
   if (ws->fft_tw) (void)hipFree(ws->fft_tw);
   if (ws->fft_qhat) (void)hipFree(ws->fft_qhat);
@@ -888,7 +895,6 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ws->apart_cap = std::max(cblocks, fblocks) * SFW_MAX_GRID * SFW_MAX_GRID;
     ALLOC(ws->apart, ws->apart_cap * sizeof(ArgPart), "argmax partials");
     ALLOC(ws->best, sizeof(sfw_argmax) * 2, "argmax");
-    ALLOC(ws->hashbuf, (2 * (size_t)kFpParts + 3 * (size_t)na) * 8, "fingerprints");
     ALLOC(ws->cols, (size_t)max_atoms * V * 4, "LASSO columns");
     {
       // spectral blur arrays for the largest plan (lengths grow with the volume and the PSF;
@@ -936,10 +942,10 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ws->hp_atoms = 2 * (size_t)kFpParts;  // right behind the partials: one readback
     ws->hp_stage = ws->hp_atoms + 3 * (size_t)na;
     ws->hp_sums = ws->hp_stage + 4 * (size_t)na;
-    ws->hp_w = ws->hp_sums + 6 * (size_t)na + 8;
-    ws->hp_rows = ws->hp_w + (size_t)na;
+    ws->hp_rows = ws->hp_sums + 6 * (size_t)na + 8;
     ws->hp_slots = ws->hp_rows + (size_t)(na + 2) * (na + 2) + 64;
-    ws->hpin_cap = ws->hp_slots + (size_t)na / 2 + 8;
+    ws->hp_best = ws->hp_slots + (size_t)na / 2 + 8;
+    ws->hpin_cap = ws->hp_best + 4;
     if (hipHostMalloc(reinterpret_cast<void**>(&ws->hpin), ws->hpin_cap * 8, 0) != hipSuccess) {
       (void)hipGetLastError();
       sfw_workspace_destroy(ws);
@@ -1136,11 +1142,9 @@ int sfw_certificate(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vo
         SFW_HIP(hipMemcpyAsync(best_out, ws->best, sizeof(sfw_argmax), hipMemcpyDeviceToDevice,
                                ws->stream));
       } else {
-        sfw_argmax* hb = reinterpret_cast<sfw_argmax*>(ws->hpin + ws->hp_sums);
-        SFW_HIP(hipMemcpyAsync(hb, ws->best, sizeof(sfw_argmax), hipMemcpyDeviceToHost,
-                               ws->stream));
+        // the final kernel also wrote the maximum to pinned host memory
         SFW_HIP(hipStreamSynchronize(ws->stream));
-        *best_out = *hb;
+        *best_out = *pinned_best(ws);
       }
     }
     return SFW_OK;
@@ -1208,10 +1212,8 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
     std::vector<double> w;
     rc = op_lasso(ws, p, vol, y, H, lambda, th.data(), n, w, true);
     if (rc) return rc;
-    // stream-ordered upload from a pinned region no other call writes before synchronising
-    double* hw = ws->hpin + ws->hp_w;
-    std::memcpy(hw, w.data(), 8 * (size_t)n);
-    SFW_HIP(hipMemcpyAsync(w_out, hw, 8 * (size_t)n, hipMemcpyHostToDevice, ws->stream));
+    // stream-ordered store; the values travel in the kernel arguments
+    SFW_HIP(launch_store_doubles(w.data(), n, w_out, ws->stream));
     return SFW_OK;
   } catch (...) {
     return fail(SFW_EINVAL, "unexpected exception in sfw_lasso_weights");

@@ -74,6 +74,11 @@ constexpr int conv_tile_lzp(int kz) {
 // One axis of a separable FFT: length n = prod(radix), twiddles tw[m] = exp(-2 pi i m / n).
 constexpr int kFpParts = 256;  // fingerprint partials per array
 constexpr int kAtomArgs = 8;   // atom constants passed by value in one launch
+constexpr int kSlotArgs = 128;    // LASSO slot indices passed by value to the Gram-row kernels
+constexpr int kDoubleArgs = 128;  // float64 values passed by value to k_store_doubles
+struct SlotArgs {
+  int s[kSlotArgs];
+};
 constexpr int kFftMaxStages = 16;
 constexpr int kFftMaxLen = 1024;
 constexpr int kFxLines = 16;  // lines (or columns) per block of the fixed-length passes
@@ -217,19 +222,18 @@ struct sfw_workspace {
   std::vector<float> slot_theta;         // [max_atoms][5]
   std::vector<char> slot_ok, gram_ok;    // [max_atoms], [max_atoms][max_atoms]
   std::vector<double> lasso_G, lasso_b;  // [max_atoms][max_atoms], [max_atoms]
-  // device [2 kFpParts + 3 max_atoms]: per-block fingerprint partials of y and H, then a copy
-  // of the atoms (one readback)
-  unsigned long long* hashbuf = nullptr;
 
   // pinned host staging (doubles), carved into regions that never overlap:
   //   [hp_hash, +2 kFpParts) fingerprint partials, directly followed by
   //   [hp_atoms, +3 na) atom readback / upload (sfw_atom)
   //   [hp_stage, +4 na) atom constants (AtomK) | [hp_sums, +6 na + 8) reduction sums
-  //   [hp_w, +na) LASSO weights on their way to the device | [hp_rows, ...) Gram rows
+  //   [hp_rows, ...) Gram rows | [hp_slots, ...) slot list
+  //   [hp_best, +4) certificate maximum
   double* hpin = nullptr;
   size_t hpin_cap = 0;
-  size_t hp_hash = 0, hp_atoms = 0, hp_stage = 0, hp_sums = 0, hp_w = 0, hp_rows = 0;
+  size_t hp_hash = 0, hp_atoms = 0, hp_stage = 0, hp_sums = 0, hp_rows = 0;
   size_t hp_slots = 0;  // [max_atoms] int32 slot list on its way to lasso_slots
+  size_t hp_best = 0;   // sfw_argmax written by the certificate's final kernel
 
   // optional per-kernel-class event timing (sfw_profile_begin / end)
   bool prof_on = false;
@@ -239,6 +243,12 @@ struct sfw_workspace {
   std::vector<hipEvent_t> prof_start, prof_stop;
   std::vector<int> prof_kind;
 };
+
+// the certificate maximum as the final kernel left it in pinned host memory (valid once the
+// stream has been synchronised)
+inline sfw_argmax* pinned_best(sfw_workspace* ws) {
+  return reinterpret_cast<sfw_argmax*>(ws->hpin + ws->hp_best);
+}
 
 namespace sfw {
 // Records a start event on construction and a stop event on destruction when profiling is on.
@@ -287,6 +297,8 @@ hipError_t launch_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* ak
                        float* out_adj, hipStream_t st);
 // atomicAdd of the fingerprint of v[0..n) into *out (zero it first).
 hipError_t launch_store_atoms(const AtomK* host, int n, AtomK* dst, hipStream_t st);
+// dst[0..n) = host[0..n) through kernel arguments (launches of kDoubleArgs values)
+hipError_t launch_store_doubles(const double* host, int n, double* dst, hipStream_t st);
 hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t nh,
                                const sfw_atom* atoms, int n, unsigned long long* fp, int* by_out,
                                int* bh_out, hipStream_t st);
@@ -347,18 +359,21 @@ hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const dou
                                 int nloss, const sfw_atom* atoms, float lambda,
                                 double* sums, sfw_atom* grad_out, double* loss_out,
                                 hipStream_t st, bool vjp = false);
+// The maximum goes to best (device) and, when best_host is not null, to pinned host memory.
 hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
-                               sfw_argmax* best, hipStream_t st);
+                               sfw_argmax* best, sfw_argmax* best_host, hipStream_t st);
 // out[c] = sum_v a[v] * cols[c][v] for c < k, out[k] = sum_v a[v] * y[v] (float64).
-// dots of column a with the k columns cols + slots[c] * colstride and with y (out[k])
-hipError_t launch_dots(const float* a, const float* cols, const int* slots, int k,
-                       size_t colstride, const float* y, size_t nvox, double* dpart,
+// dots of column a with the k columns cols + slot(c) * colstride and with y (out[k]); slot(c)
+// is sa.s[c] for c < kSlotArgs, else slots[c] (device). out may be pinned host memory.
+hipError_t launch_dots(const float* a, const float* cols, const SlotArgs& sa, const int* slots,
+                       int k, size_t colstride, const float* y, size_t nvox, double* dpart,
                        int nblocks, double* out, hipStream_t st);
 // Gram row over box = {x0, x1, y0, y1, z0, z1} (half-open; x0, x1, nx and colstride multiples
 // of 4) that holds every nonzero of a.
-hipError_t launch_dots_box(const float* a, const float* cols, const int* slots, int k,
-                           size_t colstride, const float* y, sfw_dims vol, const int box[6],
-                           double* dpart, int dpart_cap, double* out, hipStream_t st);
+hipError_t launch_dots_box(const float* a, const float* cols, const SlotArgs& sa,
+                           const int* slots, int k, size_t colstride, const float* y,
+                           sfw_dims vol, const int box[6], double* dpart, int dpart_cap,
+                           double* out, hipStream_t st);
 hipError_t launch_any_nonfinite(const float* v, size_t n, int* flag, hipStream_t st);
 
 // ---- Fourier-domain grid certificate (sfw_fft.hip)

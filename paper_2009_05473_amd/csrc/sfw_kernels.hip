@@ -155,6 +155,15 @@ __global__ void k_store_atoms(AtomArgs args, int n, AtomK* __restrict__ dst) {
   if (i < n) dst[i] = args.a[i];
 }
 
+// Stores up to kDoubleArgs float64 values carried in the kernel arguments.
+struct DoubleArgs {
+  double v[kDoubleArgs];
+};
+__global__ void k_store_doubles(DoubleArgs args, int n, double* __restrict__ dst) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = args.v[i];
+}
+
 // Voxel tiles of the render and gradient kernels: a block of 256 threads owns a 16 x 16 patch
 // of (y, x) columns (thread t: x = 16 bx + t % 16, y = 16 by + t / 16), so a wave owns a
 // 16 x 4 patch; tiles are numbered bx + tiles_x * by.
@@ -818,7 +827,8 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
 
 __global__ __launch_bounds__(1024) void k_argmax_final(const ArgPart* __restrict__ apart,
                                                        int nparts, int nx, int ny, int nz, int nd,
-                                                       sfw_argmax* __restrict__ best) {
+                                                       sfw_argmax* __restrict__ best,
+                                                       sfw_argmax* __restrict__ best_host) {
   const int tid = threadIdx.x;
   float bv = -INFINITY;
   long long bi = 0x7fffffffffffffffLL;
@@ -874,6 +884,7 @@ __global__ __launch_bounds__(1024) void k_argmax_final(const ArgPart* __restrict
     b.y = (int)(v / nx);
     b.x = (int)(v - (long long)b.y * nx);
     *best = b;
+    if (best_host) *best_host = b;  // pinned host memory: read after the stream synchronises
   }
 }
 
@@ -887,13 +898,19 @@ __global__ __launch_bounds__(1024) void k_argmax_final(const ArgPart* __restrict
 constexpr int kDotsHold = 4;
 constexpr int kDotsCols = 4;
 
+// slot of column c: the first kSlotArgs come in the kernel arguments, the rest from device
+// memory (only read when the support is longer)
+__device__ __forceinline__ int slot_of(const SlotArgs& sa, const int* slots, int c) {
+  return c < kSlotArgs ? sa.s[c] : slots[c];
+}
+
 __device__ __forceinline__ double dot4(const float4& a, const float4& b) {
   return (double)(a.x * b.x) + (double)(a.y * b.y) + (double)(a.z * b.z) + (double)(a.w * b.w);
 }
 
 __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
                                               const float* __restrict__ cols,
-                                              const int* __restrict__ slots, int k,
+                                              SlotArgs sa, const int* __restrict__ slots, int k,
                                               size_t colstride, const float* __restrict__ y,
                                               size_t nvox, double* __restrict__ dpart) {
   __shared__ double red[kDotsCols][4];
@@ -915,7 +932,7 @@ __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
 #pragma unroll
     for (int u = 0; u < kDotsCols; ++u) {
       const int c = min(c0 + u, k);
-      b[u] = c < k ? cols + (size_t)slots[c] * colstride : y;
+      b[u] = c < k ? cols + (size_t)slot_of(sa, slots, c) * colstride : y;
       vec = vec && (((uintptr_t)b[u]) & 15) == 0;
     }
     double s[kDotsCols] = {0.0, 0.0, 0.0, 0.0};
@@ -964,8 +981,9 @@ __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
 // in registers across the columns.
 __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
                                                   const float* __restrict__ cols,
-                                                  const int* __restrict__ slots, int k,
-                                                  size_t colstride, const float* __restrict__ y,
+                                                  SlotArgs sa, const int* __restrict__ slots,
+                                                  int k, size_t colstride,
+                                                  const float* __restrict__ y,
                                                   int nx, int ny, int x0, int bw4, int y0,
                                                   int bh, int z0, int nrows, int cpb,
                                                   double* __restrict__ dpart) {
@@ -993,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
 #pragma unroll
     for (int u = 0; u < kDotsCols; ++u) {
       const int c = min(c0 + u, ce - 1);
-      b[u] = c < k ? cols + (size_t)slots[c] * colstride : y;
+      b[u] = c < k ? cols + (size_t)slot_of(sa, slots, c) * colstride : y;
     }
     double s[kDotsCols] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1130,6 +1148,19 @@ hipError_t launch_store_atoms(const AtomK* host, int n, AtomK* dst, hipStream_t 
   std::memcpy(args.a, host, sizeof(AtomK) * n);
   hipLaunchKernelGGL(k_store_atoms, dim3(1), dim3(64), 0, st, args, n, dst);
   return hipGetLastError();
+}
+
+hipError_t launch_store_doubles(const double* host, int n, double* dst, hipStream_t st) {
+  for (int i0 = 0; i0 < n; i0 += kDoubleArgs) {
+    const int m = std::min(kDoubleArgs, n - i0);
+    DoubleArgs args;
+    std::memset(&args, 0, sizeof(args));
+    std::memcpy(args.v, host + i0, sizeof(double) * m);
+    hipLaunchKernelGGL(k_store_doubles, dim3(1), dim3(kDoubleArgs), 0, st, args, m, dst + i0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 static int fp_blocks(size_t n) {
@@ -1472,16 +1503,16 @@ hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const dou
 }
 
 hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
-                               sfw_argmax* best, hipStream_t st) {
+                               sfw_argmax* best, sfw_argmax* best_host, hipStream_t st) {
   hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, st, apart, nparts, vol.nx, vol.ny,
-                     vol.nz, nd, best);
+                     vol.nz, nd, best, best_host);
   return hipGetLastError();
 }
 
-hipError_t launch_dots(const float* a, const float* cols, const int* slots, int k,
-                       size_t colstride, const float* y, size_t nvox, double* dpart,
+hipError_t launch_dots(const float* a, const float* cols, const SlotArgs& sa, const int* slots,
+                       int k, size_t colstride, const float* y, size_t nvox, double* dpart,
                        int nblocks, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_dots, dim3(nblocks), dim3(256), 0, st, a, cols, slots, k, colstride, y,
+  hipLaunchKernelGGL(k_dots, dim3(nblocks), dim3(256), 0, st, a, cols, sa, slots, k, colstride, y,
                      nvox, dpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1489,9 +1520,10 @@ hipError_t launch_dots(const float* a, const float* cols, const int* slots, int 
   return hipGetLastError();
 }
 
-hipError_t launch_dots_box(const float* a, const float* cols, const int* slots, int k,
-                           size_t colstride, const float* y, sfw_dims vol, const int box[6],
-                           double* dpart, int dpart_cap, double* out, hipStream_t st) {
+hipError_t launch_dots_box(const float* a, const float* cols, const SlotArgs& sa,
+                           const int* slots, int k, size_t colstride, const float* y,
+                           sfw_dims vol, const int box[6], double* dpart, int dpart_cap,
+                           double* out, hipStream_t st) {
   const int bw4 = (box[1] - box[0]) / 4, bh = box[3] - box[2], nrows = bh * (box[5] - box[4]);
   const int E = nrows * bw4;
   if (E <= 0) return hipErrorInvalidValue;
@@ -1502,7 +1534,7 @@ hipError_t launch_dots_box(const float* a, const float* cols, const int* slots, 
   const int cpb = (groups + chunks - 1) / chunks * kDotsCols;
   chunks = (k + 1 + cpb - 1) / cpb;
   if ((size_t)nbx * (k + 1) > (size_t)dpart_cap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dots_box, dim3(nbx, chunks), dim3(256), 0, st, a, cols, slots, k,
+  hipLaunchKernelGGL(k_dots_box, dim3(nbx, chunks), dim3(256), 0, st, a, cols, sa, slots, k,
                      colstride, y, vol.nx, vol.ny, box[0], bw4, box[2], bh, box[4], nrows, cpb,
                      dpart);
   hipError_t e = hipGetLastError();

@@ -72,9 +72,11 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
 // LASSO column of the unit-weight atom staged in ws->ak[atom] (parameters theta) into slot.
 int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* H, int atom,
                int slot, const float* theta);
-// out[0..i] = <a_i, a_j> (j <= i), out[i + 1] = <a_i, y>, float64 on the device.
+// out[j] = <a_slot, a_(slot of j)> for j < nd, out[nd] = <a_slot, y>, float64 (device or
+// pinned host memory); the slots come in sa (all of them in ws->lasso_slots when nd exceeds
+// kSlotArgs).
 int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int slot,
-                const float* theta, int nd, double* out);
+                const float* theta, const SlotArgs& sa, int nd, double* out);
 // min_{w >= 0} 1/2 w^T G w - c^T w.
 int nnqp(const std::vector<double>& G, const std::vector<double>& c, int k, std::vector<double>& w);
 

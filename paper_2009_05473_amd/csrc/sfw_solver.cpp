@@ -556,9 +556,8 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
       rc = op_certificate(ws, vol, ws->q, lambda, o.sigma_grid, o.n_sigma, o.d_grid, o.n_d, T,
                           nullptr);
       if (rc) return rc;
-      sfw_argmax best;
-      SFW_HIP(hipMemcpyAsync(&best, ws->best, sizeof(best), hipMemcpyDeviceToHost, ws->stream));
       SFW_HIP(hipStreamSynchronize(ws->stream));
+      const sfw_argmax best = *pinned_best(ws);
       S.st.n_certificates++;
       auto ta = Clock::now();
       S.st.seconds_certificate += secs(tc, ta);

@@ -407,6 +407,33 @@ def test_lasso_zero_weight_case(L, ws_big):
     assert rel_l2(w, w_o) <= 1e-4
 
 
+def test_lasso_support_longer_than_inline_slot_list(L):
+    """130 atoms: the Gram-row kernels take the first 128 slots from their arguments and the
+    rest from the device slot list. Lattice centres 5 voxels apart keep G well conditioned."""
+    shape, psf_shape = (40, 40, 40), (5, 3, 3)
+    rng = np.random.default_rng(7130)
+    psf = np.abs(rng.standard_normal(psf_shape)) + 0.1
+    psf = f32(psf / psf.sum())
+    sites = np.array([(x, y, z) for z in range(4, 36, 5) for y in range(4, 36, 5)
+                      for x in range(4, 36, 5)], dtype=np.float64)
+    pick = sites[rng.choice(len(sites), 130, replace=False)]
+    thetas = f32(np.hstack([pick + rng.uniform(-0.4, 0.4, pick.shape),
+                            rng.uniform(1.0, 1.4, (130, 1)), np.full((130, 1), 2.0)]))
+    truth = np.hstack([rng.uniform(0.5, 2.0, (130, 1)), thetas])
+    y = f32(oracle.blur(oracle.render(shape, truth), psf)
+            + 0.01 * rng.standard_normal(shape))
+    lam = 0.05
+    atoms = np.hstack([np.zeros((130, 1)), thetas])
+    w_o, G, b = oracle.lasso_weights(y, thetas, psf, lam)
+    assert np.count_nonzero(w_o) > 120
+    say("sfw_lasso_weights 130 atoms", shape, psf_shape)
+    with L.Workspace(shape, psf_shape, 160) as w:
+        got = L.sfw_lasso_weights(w, dev(psf), dev(y), lam, dev(atoms)).cpu().numpy()
+    assert rel_l2(got, w_o) <= 1e-4
+    grad = G @ got - b + lam
+    assert np.all(np.abs(grad[got > 0]) <= 1e-4 * np.abs(b).max())
+
+
 def test_reductions_are_deterministic(L, ws_big):
     prob, atoms, psf, y = _problem("c3")
     say("determinism c3")
