@@ -35,6 +35,32 @@ int hip_fail(hipError_t e, const char* what) {
   return SFW_EHIP;
 }
 
+// ------------------------------------------------------------------ completion signal
+
+SigArgs sig_arm(sfw_workspace* ws) {
+  if (++ws->sig_seq <= 0) ws->sig_seq = 1;  // the flag starts at 0
+  return SigArgs{ws->sig_flag, ws->sig_ticket, ws->sig_seq};
+}
+
+int sig_wait(sfw_workspace* ws, const SigArgs& s) {
+  if (!s.flag) {
+    SFW_HIP(hipStreamSynchronize(ws->stream));
+    return SFW_OK;
+  }
+  for (unsigned long spins = 1;; ++spins) {
+    if (__atomic_load_n(s.flag, __ATOMIC_ACQUIRE) == s.seq) return SFW_OK;
+    if ((spins & 0x3fff) == 0) {  // now and then: has the stream finished without the signal?
+      const hipError_t e = hipStreamQuery(ws->stream);
+      if (e == hipSuccess) {
+        if (__atomic_load_n(s.flag, __ATOMIC_ACQUIRE) == s.seq) return SFW_OK;
+        return fail(SFW_EHIP, "the stream finished without its completion signal");
+      }
+      if (e != hipErrorNotReady) return hip_fail(e, "waiting for a completion signal");
+    }
+    __builtin_ia32_pause();
+  }
+}
+
 // ------------------------------------------------------------------ validation
 
 int check_dims(const sfw_dims& d, const char* what) {
@@ -203,8 +229,11 @@ int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
     SFW_HIP(launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream));
   }
   ProfScope ps(ws, kProfGradFinalize);
+  // sums for the host: the finalize kernel signals them (ws->sums_sig)
+  ws->sums_sig = sums ? sig_arm(ws) : kNoSig;
   SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, ws->dpart, p.nres, atoms_dev, lambda,
-                               sums ? sums : ws->dres, grad_out, loss_out, ws->stream));
+                               sums ? sums : ws->dres, grad_out, loss_out, ws->stream, false,
+                               ws->sums_sig));
   return SFW_OK;
 }
 
@@ -266,10 +295,13 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
   if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
     return fail(SFW_EINVAL, "gradient partial buffer too small");
   double* hs = ws->hpin + ws->hp_sums;
+  SigArgs sig = kNoSig;
   {
     ProfScope ps(ws, kProfEtaGrad);
     if (one_launch) {
-      SFW_HIP(launch_grad_points(gp, hk, n, q, vol, ws->gpart, ws->eta_ticket, hs, ws->stream));
+      sig = sig_arm(ws);
+      SFW_HIP(launch_grad_points(gp, hk, n, q, vol, ws->gpart, ws->eta_ticket, hs, sig,
+                                 ws->stream));
     } else {
       SFW_HIP(launch_grad(gp, ws->ak, n, q, vol, ws->gpart, ws->stream));
       SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, nullptr, 0, nullptr, 0.f, ws->dres,
@@ -279,7 +311,8 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
   if (!one_launch)
     SFW_HIP(hipMemcpyAsync(hs, ws->dres, sizeof(double) * 6 * n, hipMemcpyDeviceToHost,
                            ws->stream));
-  SFW_HIP(hipStreamSynchronize(ws->stream));
+  int rcw = sig_wait(ws, sig);  // kNoSig (the copy): synchronises the stream
+  if (rcw) return rcw;
   const double ln2 = 0.69314718055994531;
   for (int i = 0; i < n; ++i) {
     const double* S = hs + 6 * i;
@@ -437,8 +470,9 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
                                    eta_out, ws->apart, nblk, ws->stream));
     }
     ProfScope ps(ws, kProfCertArgmax);
+    ws->cert_sig = sig_arm(ws);
     SFW_HIP(launch_argmax_final(ws->apart, nblk * ns * nd, vol, nd, ws->best, pinned_best(ws),
-                                ws->stream));
+                                ws->cert_sig, ws->stream));
     return SFW_OK;
   }
   int nb = 0;
@@ -457,8 +491,9 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
                           ws->stream));
     }
   ProfScope ps(ws, kProfCertArgmax);
+  ws->cert_sig = sig_arm(ws);
   SFW_HIP(launch_argmax_final(ws->apart, nb * ns * nd, vol, nd, ws->best, pinned_best(ws),
-                              ws->stream));
+                              ws->cert_sig, ws->stream));
   return SFW_OK;
 }
 
@@ -542,47 +577,48 @@ static bool column_box(const float* theta, const sfw_dims& psf, const sfw_dims& 
 // host memory). theta: the unit atom of the slot (host), used to restrict the sums to its
 // support.
 int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int slot,
-                const float* theta, const SlotArgs& sa, int nd, double* out) {
+                const float* theta, const SlotArgs& sa, int nd, double* out, const SigArgs& sig) {
   const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
   const float* a = ws->cols + (size_t)slot * ws->vcap;
   ProfScope ps(ws, kProfLassoDots);
   int box[6];
   if (vol.nx % 4 == 0 && ws->vcap % 4 == 0 && column_box(theta, p.psf, vol, box)) {
     SFW_HIP(launch_dots_box(a, ws->cols, sa, ws->lasso_slots, nd, ws->vcap, y, vol, box,
-                            ws->dpart, (int)std::min<size_t>(ws->dpart_cap, 1u << 30), out,
+                            ws->dpart, (int)std::min<size_t>(ws->dpart_cap, 1u << 30), out, sig,
                             ws->stream));
     return SFW_OK;
   }
   int nb = (int)std::min<size_t>(1024, (V + 1023) / 1024);
   if ((size_t)nb * (nd + 1) > ws->dpart_cap) return fail(SFW_EINVAL, "dot partial buffer too small");
   SFW_HIP(launch_dots(a, ws->cols, sa, ws->lasso_slots, nd, ws->vcap, y, V, ws->dpart, nb, out,
-                      ws->stream));
+                      sig, ws->stream));
   return SFW_OK;
 }
 
 // Enqueue the fingerprints of y and H (and a copy of the n device atoms, if any) into the
-// pinned region at hp_hash (atoms at hp_atoms); read them with read_fingerprints once the
-// stream has been synchronised.
+// pinned region at hp_hash (atoms at hp_atoms); read them with read_fingerprints once *sig
+// has been waited for.
 static int enqueue_fingerprints(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
                                 const float* y, const float* H, const sfw_atom* atoms, int n,
-                                int* by, int* bh) {
+                                SigArgs* sig) {
   ProfScope ps(ws, kProfHash);
   const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
-  // the kernel writes the partials and the atoms straight into the pinned region
+  // the final kernel writes the fingerprints and the atoms straight into the pinned region,
+  // then signals *sig
+  *sig = sig_arm(ws);
   SFW_HIP(launch_fingerprints(y, V, H, (size_t)p.psf.nx * p.psf.ny * p.psf.nz, atoms, n,
-                              reinterpret_cast<unsigned long long*>(ws->hpin + ws->hp_hash), by,
-                              bh, ws->stream));
+                              ws->fp_part,
+                              reinterpret_cast<unsigned long long*>(ws->hpin + ws->hp_hash),
+                              reinterpret_cast<float*>(ws->hpin + ws->hp_atoms), *sig,
+                              ws->stream));
   return SFW_OK;
 }
 
-static void read_fingerprints(const sfw_workspace* ws, int by, int bh, unsigned long long* yh,
+static void read_fingerprints(const sfw_workspace* ws, unsigned long long* yh,
                               unsigned long long* hh) {
-  const unsigned long long* part = reinterpret_cast<const unsigned long long*>(ws->hpin + ws->hp_hash);
-  unsigned long long a = 0, b = 0;
-  for (int i = 0; i < by; ++i) a += part[i];
-  for (int i = 0; i < bh; ++i) b += part[kFpParts + i];
-  *yh = a;
-  *hh = b;
+  const unsigned long long* fp = reinterpret_cast<const unsigned long long*>(ws->hpin + ws->hp_hash);
+  *yh = fp[0];
+  *hh = fp[1];
 }
 
 // Drop the cached LASSO columns unless they were computed for this y pointer, shapes,
@@ -609,12 +645,13 @@ static void lasso_validate(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& 
 // Fingerprint y and H and validate the cache (one synchronisation).
 int lasso_check_inputs(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
                        const float* H) {
-  int by = 0, bh = 0;
-  int rc = enqueue_fingerprints(ws, p, vol, y, H, nullptr, 0, &by, &bh);
+  SigArgs sig = kNoSig;
+  int rc = enqueue_fingerprints(ws, p, vol, y, H, nullptr, 0, &sig);
   if (rc) return rc;
-  SFW_HIP(hipStreamSynchronize(ws->stream));
+  rc = sig_wait(ws, sig);
+  if (rc) return rc;
   unsigned long long yh = 0, hh = 0;
-  read_fingerprints(ws, by, bh, &yh, &hh);
+  read_fingerprints(ws, &yh, &hh);
   lasso_validate(ws, p, vol, y, yh, hh);
   return SFW_OK;
 }
@@ -719,12 +756,15 @@ int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
     // the rows' final sums go straight to pinned host memory
     const size_t stride = (size_t)nd + 1;
     double* hr = ws->hpin + ws->hp_rows;
+    SigArgs sig = kNoSig;
     for (size_t r = 0; r < rows.size(); ++r) {
+      if (r + 1 == rows.size()) sig = sig_arm(ws);  // the last row's kernel signals
       int rc = op_gram_row(ws, p, vol, y, rows[r], &ws->slot_theta[5 * (size_t)rows[r]], sa, nd,
-                           hr + r * stride);
+                           hr + r * stride, sig);
       if (rc) return rc;
     }
-    SFW_HIP(hipStreamSynchronize(ws->stream));
+    int rcw = sig_wait(ws, sig);
+    if (rcw) return rcw;
     for (size_t r = 0; r < rows.size(); ++r) {
       const int sa = rows[r];
       const double* row = hr + r * stride;
@@ -812,6 +852,9 @@ void sfw_workspace_destroy(sfw_workspace* ws) {
   if (ws->blur_changed) (void)hipFree(ws->blur_changed);
   if (ws->eta_ticket) (void)hipFree(ws->eta_ticket);
   if (ws->hpin) (void)hipHostFree(ws->hpin);
+  if (ws->sig_flag) (void)hipHostFree(ws->sig_flag);
+  if (ws->sig_ticket) (void)hipFree(ws->sig_ticket);
+  if (ws->fp_part) (void)hipFree(ws->fp_part);
   for (hipEvent_t e : ws->prof_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ws->prof_stop) (void)hipEventDestroy(e);
   (void)hipSetDevice(cur);
@@ -932,6 +975,13 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
       }
     }
     ALLOC(ws->lasso_slots, (size_t)max_atoms * sizeof(int), "LASSO slot list");
+    ALLOC(ws->sig_ticket, sizeof(unsigned), "completion signal counter");
+    ALLOC(ws->fp_part, 2 * (size_t)kFpParts * sizeof(unsigned long long), "fingerprint partials");
+    if (hipMemset(ws->sig_ticket, 0, sizeof(unsigned)) != hipSuccess) {
+      (void)hipGetLastError();
+      sfw_workspace_destroy(ws);
+      return fail(SFW_EHIP, "clearing the completion signal counter failed");
+    }
     ws->slot_theta.assign(5 * (size_t)max_atoms, 0.f);
     ws->slot_ok.assign((size_t)max_atoms, 0);
     ws->gram_ok.assign((size_t)max_atoms * max_atoms, 0);
@@ -939,7 +989,7 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ws->lasso_b.assign((size_t)max_atoms, 0.0);
 #undef ALLOC
     ws->hp_hash = 0;
-    ws->hp_atoms = 2 * (size_t)kFpParts;  // right behind the partials: one readback
+    ws->hp_atoms = ws->hp_hash + 2;  // right behind the two fingerprints
     ws->hp_stage = ws->hp_atoms + 3 * (size_t)na;
     ws->hp_sums = ws->hp_stage + 4 * (size_t)na;
     ws->hp_rows = ws->hp_sums + 6 * (size_t)na + 8;
@@ -951,6 +1001,14 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
       sfw_workspace_destroy(ws);
       return fail(SFW_ENOMEM, "pinned host allocation failed");
     }
+    // the completion flag: coherent, so that the kernels' stores reach host memory directly
+    if (hipHostMalloc(reinterpret_cast<void**>(&ws->sig_flag), 64, hipHostMallocCoherent) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      sfw_workspace_destroy(ws);
+      return fail(SFW_ENOMEM, "pinned host allocation of the completion flag failed");
+    }
+    *ws->sig_flag = 0;
     *out = ws;
     return SFW_OK;
   } catch (const std::exception& e) {
@@ -1142,8 +1200,9 @@ int sfw_certificate(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vo
         SFW_HIP(hipMemcpyAsync(best_out, ws->best, sizeof(sfw_argmax), hipMemcpyDeviceToDevice,
                                ws->stream));
       } else {
-        // the final kernel also wrote the maximum to pinned host memory
-        SFW_HIP(hipStreamSynchronize(ws->stream));
+        // the final kernel also wrote the maximum to pinned host memory, then signalled
+        rc = sig_wait(ws, ws->cert_sig);
+        if (rc) return rc;
         *best_out = *pinned_best(ws);
       }
     }
@@ -1191,12 +1250,13 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
     rc = prep_all(ws, H, p, true, false, atoms, n, true);
     if (rc) return rc;
     // one synchronisation brings back the atoms and the fingerprints of y and H
-    int by = 0, bh = 0;
-    rc = enqueue_fingerprints(ws, p, vol, y, H, atoms, n, &by, &bh);
+    SigArgs sig = kNoSig;
+    rc = enqueue_fingerprints(ws, p, vol, y, H, atoms, n, &sig);
     if (rc) return rc;
-    SFW_HIP(hipStreamSynchronize(ws->stream));
+    rc = sig_wait(ws, sig);
+    if (rc) return rc;
     unsigned long long yh = 0, hh = 0;
-    read_fingerprints(ws, by, bh, &yh, &hh);
+    read_fingerprints(ws, &yh, &hh);
     lasso_validate(ws, p, vol, y, yh, hh);
     const sfw_atom* ha = reinterpret_cast<const sfw_atom*>(ws->hpin + ws->hp_atoms);
     std::vector<float> th(5 * (size_t)n);

@@ -79,6 +79,17 @@ constexpr int kDoubleArgs = 128;  // float64 values passed by value to k_store_d
 struct SlotArgs {
   int s[kSlotArgs];
 };
+// Completion signal of a kernel whose results the host reads from pinned memory: once every
+// block's results are visible at system scope, the last block to finish (counted on ticket, a
+// device counter that is 0 between launches) stores seq into *flag (coherent pinned memory),
+// so that the host can spin on the flag instead of synchronising the stream. flag == nullptr:
+// no signal.
+struct SigArgs {
+  int* flag;
+  unsigned* ticket;
+  int seq;
+};
+constexpr SigArgs kNoSig{nullptr, nullptr, 0};
 constexpr int kFftMaxStages = 16;
 constexpr int kFftMaxLen = 1024;
 constexpr int kFxLines = 16;  // lines (or columns) per block of the fixed-length passes
@@ -193,6 +204,12 @@ struct sfw_workspace {
   int blur_tw_key[3] = {0, 0, 0};
   float* blur_hcache = nullptr;  // [kHcacheFloats] PSF and grid of the stored spectrum
   int* eta_ticket = nullptr;     // [1] block counter of the one-launch eta evaluation (0 at rest)
+  unsigned* sig_ticket = nullptr;  // [1] block counter of the completion signal (0 at rest)
+  int* sig_flag = nullptr;         // coherent pinned host word the signalling kernels write
+  int sig_seq = 0;                 // sequence number of the last armed signal
+  unsigned long long* fp_part = nullptr;  // [2 kFpParts] fingerprint partials (device)
+  sfw::SigArgs cert_sig = sfw::kNoSig;  // signal of the last certificate maximum (pinned_best)
+  sfw::SigArgs sums_sig = sfw::kNoSig;  // signal of the last (C, grad C) sums in host memory
   int* blur_changed = nullptr;   // [1]
 
   // atoms
@@ -224,7 +241,7 @@ struct sfw_workspace {
   std::vector<double> lasso_G, lasso_b;  // [max_atoms][max_atoms], [max_atoms]
 
   // pinned host staging (doubles), carved into regions that never overlap:
-  //   [hp_hash, +2 kFpParts) fingerprint partials, directly followed by
+  //   [hp_hash, +2) fingerprints of y and H, directly followed by
   //   [hp_atoms, +3 na) atom readback / upload (sfw_atom)
   //   [hp_stage, +4 na) atom constants (AtomK) | [hp_sums, +6 na + 8) reduction sums
   //   [hp_rows, ...) Gram rows | [hp_slots, ...) slot list
@@ -277,6 +294,13 @@ namespace sfw {
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
+// A new completion signal of the workspace (next sequence number) for one launch of a kernel
+// that writes results for the host.
+SigArgs sig_arm(sfw_workspace* ws);
+// Waits until the kernel launched with s has written its results (a host spin on the coherent
+// flag; a stream that finishes without the signal is an error); kNoSig: synchronises the
+// stream instead.
+int sig_wait(sfw_workspace* ws, const SigArgs& s);
 
 #define SFW_HIP(call)                                  \
   do {                                                 \
@@ -295,13 +319,17 @@ GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6]);
 hipError_t launch_prep(const sfw_atom* atoms, int n, bool unit_weight, AtomK* ak, const float* H,
                        sfw_dims psf, bool mfma, int kzp, bool fwd, bool adj, float* out_fwd,
                        float* out_adj, hipStream_t st);
-// atomicAdd of the fingerprint of v[0..n) into *out (zero it first).
+// dst[0..n) = host[0..n) (at most kAtomArgs atom constants) through kernel arguments.
 hipError_t launch_store_atoms(const AtomK* host, int n, AtomK* dst, hipStream_t st);
 // dst[0..n) = host[0..n) through kernel arguments (launches of kDoubleArgs values)
 hipError_t launch_store_doubles(const double* host, int n, double* dst, hipStream_t st);
+// Fingerprints of y and H (partials in part, device [2 kFpParts]) into out[0], out[1], and a
+// copy of the n atoms into atoms_out; out and atoms_out may be pinned host memory, signalled
+// by sig.
 hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t nh,
-                               const sfw_atom* atoms, int n, unsigned long long* fp, int* by_out,
-                               int* bh_out, hipStream_t st);
+                               const sfw_atom* atoms, int n, unsigned long long* part,
+                               unsigned long long* out, float* atoms_out, const SigArgs& sig,
+                               hipStream_t st);
 hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st);
 
 enum ConvEpilogue { kEpiPlain = 0, kEpiResidual = 1, kEpiArgmax = 2, kEpiColumn = 3 };
@@ -345,7 +373,7 @@ hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sf
 // block; ticket: device int that is 0 between launches.
 hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n, const float* q,
                               sfw_dims vol, float* gpart, int* ticket, double* sums_out,
-                              hipStream_t st);
+                              const SigArgs& sig, hipStream_t st);
 hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q, sfw_dims vol,
                        float* gpart, hipStream_t st);
 // Sums partials over tiles in a fixed order (float64). For atom a:
@@ -358,22 +386,24 @@ hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q
 hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const double* loss_part,
                                 int nloss, const sfw_atom* atoms, float lambda,
                                 double* sums, sfw_atom* grad_out, double* loss_out,
-                                hipStream_t st, bool vjp = false);
+                                hipStream_t st, bool vjp = false,
+                                const SigArgs& sig = kNoSig);
 // The maximum goes to best (device) and, when best_host is not null, to pinned host memory.
 hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
-                               sfw_argmax* best, sfw_argmax* best_host, hipStream_t st);
+                               sfw_argmax* best, sfw_argmax* best_host, const SigArgs& sig,
+                               hipStream_t st);
 // out[c] = sum_v a[v] * cols[c][v] for c < k, out[k] = sum_v a[v] * y[v] (float64).
 // dots of column a with the k columns cols + slot(c) * colstride and with y (out[k]); slot(c)
 // is sa.s[c] for c < kSlotArgs, else slots[c] (device). out may be pinned host memory.
 hipError_t launch_dots(const float* a, const float* cols, const SlotArgs& sa, const int* slots,
                        int k, size_t colstride, const float* y, size_t nvox, double* dpart,
-                       int nblocks, double* out, hipStream_t st);
+                       int nblocks, double* out, const SigArgs& sig, hipStream_t st);
 // Gram row over box = {x0, x1, y0, y1, z0, z1} (half-open; x0, x1, nx and colstride multiples
 // of 4) that holds every nonzero of a.
 hipError_t launch_dots_box(const float* a, const float* cols, const SlotArgs& sa,
                            const int* slots, int k, size_t colstride, const float* y,
                            sfw_dims vol, const int box[6], double* dpart, int dpart_cap,
-                           double* out, hipStream_t st);
+                           double* out, const SigArgs& sig, hipStream_t st);
 hipError_t launch_any_nonfinite(const float* v, size_t n, int* flag, hipStream_t st);
 
 // ---- Fourier-domain grid certificate (sfw_fft.hip)

@@ -117,33 +117,85 @@ __global__ void k_prep(const sfw_atom* __restrict__ atoms, int n, int unit_weigh
   }
 }
 
+// Completion signal (SigArgs), called by every thread of every block of a signalling kernel
+// after its last write of results for the host. Only the block's first wave may write such
+// results: its writes are made visible at system scope (one fence, which writes back the L2,
+// per block) before the block is counted, and the block that completes the count resets the
+// ticket and stores the sequence number into the host flag (a vector store).
+__device__ __forceinline__ void signal_host(const SigArgs& s, unsigned nblocks) {
+  if (!s.flag) return;
+  if (threadIdx.x < 64) __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned done = nblocks > 1 ? atomicAdd(s.ticket, 1u) + 1u : 1u;
+    if (done == nblocks) {
+      if (nblocks > 1) *s.ticket = 0u;  // every block has been counted
+      __threadfence_system();
+      *reinterpret_cast<volatile int*>(s.flag) = s.seq;
+    }
+  }
+}
+
 // Order-independent 64-bit fingerprint of a float array: sum over i of bits(v[i]) * (2 i + 1)
-// (mod 2^64). Used to recognise inputs already seen by cached LASSO columns.
-// Fingerprint sum_i bits(v_i) * (2 i + 1) (mod 2^64) of y (blocks [0, by)) and H (blocks
-// [by, by + bh)), one partial per block: fp[b] for y, fp[kFpParts + b - by] for H; the host
-// adds the partials. Block 0 also copies the n atoms behind the partials (fp[2 kFpParts...])
-// so that one device-to-host copy returns everything.
+// (mod 2^64). Used to recognise inputs already seen by cached LASSO columns. Blocks [0, by)
+// take y and blocks [by, gridDim.x) take H; each leaves one partial, in part[b] (y) or
+// part[kFpParts + b] (H). Threads read four consecutive values at a time where the array is
+// 16-byte aligned.
+__device__ __forceinline__ unsigned long long fp_term(float v, size_t i) {
+  return (unsigned long long)__float_as_uint(v) * (2ull * i + 1ull);
+}
 __global__ __launch_bounds__(256) void k_fingerprints(const float* __restrict__ y, size_t ny,
                                                       int by, const float* __restrict__ H,
-                                                      size_t nh, const float* __restrict__ atoms,
-                                                      int n, unsigned long long* __restrict__ fp) {
+                                                      size_t nh,
+                                                      unsigned long long* __restrict__ part) {
   __shared__ unsigned long long red[4];
   const bool is_y = (int)blockIdx.x < by;
   const int b = is_y ? (int)blockIdx.x : (int)blockIdx.x - by;
   const float* v = is_y ? y : H;
   const size_t len = is_y ? ny : nh;
   const size_t stride = (size_t)(is_y ? by : (int)gridDim.x - by) * 256;
+  const size_t t0 = (size_t)b * 256 + threadIdx.x;
   unsigned long long h = 0ull;
-  for (size_t i = (size_t)b * 256 + threadIdx.x; i < len; i += stride)
-    h += (unsigned long long)__float_as_uint(v[i]) * (2ull * i + 1ull);
+  size_t done = 0;
+  if ((reinterpret_cast<uintptr_t>(v) & 15) == 0) {
+    const float4* v4 = reinterpret_cast<const float4*>(v);
+    const size_t n4 = len / 4;
+#pragma unroll 4
+    for (size_t i = t0; i < n4; i += stride) {
+      const float4 q = v4[i];
+      const size_t e = 4 * i;
+      h += fp_term(q.x, e) + fp_term(q.y, e + 1) + fp_term(q.z, e + 2) + fp_term(q.w, e + 3);
+    }
+    done = 4 * n4;
+  }
+  for (size_t i = done + t0; i < len; i += stride) h += fp_term(v[i], i);
   for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = h;
   __syncthreads();
-  if (threadIdx.x == 0) fp[(is_y ? 0 : kFpParts) + b] = red[0] + red[1] + red[2] + red[3];
-  if (blockIdx.x == 0) {
-    float* dst = reinterpret_cast<float*>(fp + 2 * kFpParts);
-    for (int i = threadIdx.x; i < 6 * n; i += 256) dst[i] = atoms[i];
+  if (threadIdx.x == 0) part[(is_y ? 0 : kFpParts) + b] = red[0] + red[1] + red[2] + red[3];
+}
+
+// One wave: out[0] = fingerprint of y (the sum of its by partials), out[1] = that of H, and a
+// copy of the n atoms (6 floats each) in atoms_out; out and atoms_out may be pinned host memory
+// (signalled).
+__global__ __launch_bounds__(64) void k_fingerprints_final(
+    const unsigned long long* __restrict__ part, int by, int bh,
+    const float* __restrict__ atoms, int n, unsigned long long* __restrict__ out,
+    float* __restrict__ atoms_out, SigArgs sig) {
+  const int lane = threadIdx.x;
+  unsigned long long a = 0ull, c = 0ull;
+  for (int i = lane; i < by; i += 64) a += part[i];
+  for (int i = lane; i < bh; i += 64) c += part[kFpParts + i];
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    c += __shfl_xor(c, o, 64);
   }
+  if (lane == 0) {
+    out[0] = a;
+    out[1] = c;
+  }
+  for (int i = lane; i < 6 * n; i += 64) atoms_out[i] = atoms[i];
+  signal_host(sig, 1);
 }
 
 // Stores up to kAtomArgs atom constants carried in the kernel arguments.
@@ -651,7 +703,8 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
                                                        int ry0, int rtx, int rz0,
                                                        float* __restrict__ gpart,
                                                        int* __restrict__ ticket,
-                                                       double* __restrict__ sums_out) {
+                                                       double* __restrict__ sums_out,
+                                                       SigArgs sig) {
   constexpr int NW = kGradThreads / 64;
   __shared__ float red[NW][kGradMaxAtomsPerGroup][6];
   const int tid = threadIdx.x;
@@ -734,6 +787,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
     constexpr int kSlices = 5;  // tile slices per (atom, component): 6 kAtomArgs * 5 <= 256
     __shared__ int is_last;
     __shared__ double part[kAtomArgs * 6][kSlices];
+    static_assert(kAtomArgs * 6 <= 64, "the sums must be written by the first wave");
     __threadfence();
     __syncthreads();
     if (tid == 0) is_last = atomicAdd(ticket, 1) == (int)(gridDim.x * gridDim.y) - 1;
@@ -756,6 +810,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
         sums_out[tid] = S;
       }
       if (tid == 0) *ticket = 0;  // ready for the next launch
+      signal_host(sig, 1);
     }
   }
 }
@@ -764,7 +819,8 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
 __global__ __launch_bounds__(256) void k_grad_finalize(
     const float* __restrict__ gpart, int ntiles, int n, const double* __restrict__ loss_part,
     int nloss, const sfw_atom* __restrict__ atoms, float lambda, double* __restrict__ sums,
-    sfw_atom* __restrict__ grad_out, double* __restrict__ loss_out, int vjp) {
+    sfw_atom* __restrict__ grad_out, double* __restrict__ loss_out, int vjp,
+    SigArgs sig) {
   __shared__ double red[6][4];
   const int tid = threadIdx.x;
   const int a = blockIdx.x;
@@ -821,6 +877,7 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
       if (loss_out) *loss_out = loss;
     }
   }
+  signal_host(sig, gridDim.x);
 }
 
 // ------------------------------------------------------------------ certificate maximum
@@ -828,7 +885,8 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
 __global__ __launch_bounds__(1024) void k_argmax_final(const ArgPart* __restrict__ apart,
                                                        int nparts, int nx, int ny, int nz, int nd,
                                                        sfw_argmax* __restrict__ best,
-                                                       sfw_argmax* __restrict__ best_host) {
+                                                       sfw_argmax* __restrict__ best_host,
+                                                       SigArgs sig) {
   const int tid = threadIdx.x;
   float bv = -INFINITY;
   long long bi = 0x7fffffffffffffffLL;
@@ -884,8 +942,9 @@ __global__ __launch_bounds__(1024) void k_argmax_final(const ArgPart* __restrict
     b.y = (int)(v / nx);
     b.x = (int)(v - (long long)b.y * nx);
     *best = b;
-    if (best_host) *best_host = b;  // pinned host memory: read after the stream synchronises
+    if (best_host) *best_host = b;  // pinned host memory
   }
+  signal_host(sig, 1);
 }
 
 // ------------------------------------------------------------------ LASSO dot products
@@ -1037,17 +1096,28 @@ __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
   }
 }
 
+// out[c] for c < k1: the sum over the nblocks partials dpart[b][c], in float64, in partial
+// order. One block, a thread per column (coalesced across columns, several partials in
+// flight); the first wave stores the sums (host memory is fine: see signal_host).
 __global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ dpart, int nblocks,
-                                                    int k1, double* __restrict__ out) {
-  __shared__ double red[4];
+                                                    int k1, double* __restrict__ out,
+                                                    SigArgs sig) {
+  __shared__ double res[256];
   const int tid = threadIdx.x;
-  const int c = blockIdx.x;
-  double s = 0.0;
-  for (int b = tid; b < nblocks; b += 256) s += dpart[(size_t)b * k1 + c];
-  s = shfl_sum_d(s);
-  if ((tid & 63) == 0) red[tid / 64] = s;
-  __syncthreads();
-  if (tid == 0) out[c] = red[0] + red[1] + red[2] + red[3];
+  for (int c0 = 0; c0 < k1; c0 += 256) {
+    const int cn = min(256, k1 - c0);
+    if (tid < cn) {
+      double s = 0.0;
+#pragma unroll 8
+      for (int b = 0; b < nblocks; ++b) s += dpart[(size_t)b * k1 + c0 + tid];
+      res[tid] = s;
+    }
+    __syncthreads();
+    if (tid < 64)
+      for (int cc = tid; cc < cn; cc += 64) out[c0 + cc] = res[cc];
+    __syncthreads();
+  }
+  signal_host(sig, 1);
 }
 
 __global__ __launch_bounds__(256) void k_any_nonfinite(const float* __restrict__ v, size_t n,
@@ -1169,13 +1239,16 @@ static int fp_blocks(size_t n) {
 }
 
 hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t nh,
-                               const sfw_atom* atoms, int n, unsigned long long* fp, int* by_out,
-                               int* bh_out, hipStream_t st) {
+                               const sfw_atom* atoms, int n, unsigned long long* part,
+                               unsigned long long* out, float* atoms_out, const SigArgs& sig,
+                               hipStream_t st) {
   const int by = fp_blocks(ny), bh = fp_blocks(nh);
   hipLaunchKernelGGL(k_fingerprints, dim3((unsigned)(by + bh)), dim3(256), 0, st, y, ny, by, H,
-                     nh, reinterpret_cast<const float*>(atoms), atoms ? n : 0, fp);
-  *by_out = by;
-  *bh_out = bh;
+                     nh, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fingerprints_final, dim3(1), dim3(64), 0, st, part, by, bh,
+                     reinterpret_cast<const float*>(atoms), atoms ? n : 0, out, atoms_out, sig);
   return hipGetLastError();
 }
 
@@ -1458,7 +1531,7 @@ hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q
   case V:                                                                                      \
     hipLaunchKernelGGL((k_grad<V, false>), grid, dim3(kGradThreads), 0, st, ak, none, n, p.apg, \
                        q, vol.nx, vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0,       \
-                       gpart, nullptr, nullptr);                                                \
+                       gpart, nullptr, nullptr, kNoSig);                                                \
     break;
     SFW_GRAD_CASE(64)
     SFW_GRAD_CASE(32)
@@ -1471,7 +1544,7 @@ hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q
 
 hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n, const float* q,
                               sfw_dims vol, float* gpart, int* ticket, double* sums_out,
-                              hipStream_t st) {
+                              const SigArgs& sig, hipStream_t st) {
   if (n <= 0 || n > kAtomArgs || p.groups != 1) return hipErrorInvalidValue;
   AtomArgs args;
   std::memset(&args, 0, sizeof(args));
@@ -1482,7 +1555,7 @@ hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n,
   case V:                                                                                      \
     hipLaunchKernelGGL((k_grad<V, true>), grid, dim3(kGradThreads), 0, st, nullptr, args, n, n, \
                        q, vol.nx, vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0,       \
-                       gpart, ticket, sums_out);                                                \
+                       gpart, ticket, sums_out, sig);                                                \
     break;
     SFW_GRAD_CASE(64)
     SFW_GRAD_CASE(32)
@@ -1496,34 +1569,35 @@ hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n,
 hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const double* loss_part,
                                 int nloss, const sfw_atom* atoms, float lambda, double* sums,
                                 sfw_atom* grad_out, double* loss_out, hipStream_t st,
-                                bool vjp) {
+                                bool vjp, const SigArgs& sig) {
   hipLaunchKernelGGL(k_grad_finalize, dim3(n + 1), dim3(256), 0, st, gpart, ntiles, n, loss_part,
-                     nloss, atoms, lambda, sums, grad_out, loss_out, vjp ? 1 : 0);
+                     nloss, atoms, lambda, sums, grad_out, loss_out, vjp ? 1 : 0, sig);
   return hipGetLastError();
 }
 
 hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
-                               sfw_argmax* best, sfw_argmax* best_host, hipStream_t st) {
+                               sfw_argmax* best, sfw_argmax* best_host, const SigArgs& sig,
+                               hipStream_t st) {
   hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, st, apart, nparts, vol.nx, vol.ny,
-                     vol.nz, nd, best, best_host);
+                     vol.nz, nd, best, best_host, sig);
   return hipGetLastError();
 }
 
 hipError_t launch_dots(const float* a, const float* cols, const SlotArgs& sa, const int* slots,
                        int k, size_t colstride, const float* y, size_t nvox, double* dpart,
-                       int nblocks, double* out, hipStream_t st) {
+                       int nblocks, double* out, const SigArgs& sig, hipStream_t st) {
   hipLaunchKernelGGL(k_dots, dim3(nblocks), dim3(256), 0, st, a, cols, sa, slots, k, colstride, y,
                      nvox, dpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dots_final, dim3(k + 1), dim3(256), 0, st, dpart, nblocks, k + 1, out);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, st, dpart, nblocks, k + 1, out, sig);
   return hipGetLastError();
 }
 
 hipError_t launch_dots_box(const float* a, const float* cols, const SlotArgs& sa,
                            const int* slots, int k, size_t colstride, const float* y,
                            sfw_dims vol, const int box[6], double* dpart, int dpart_cap,
-                           double* out, hipStream_t st) {
+                           double* out, const SigArgs& sig, hipStream_t st) {
   const int bw4 = (box[1] - box[0]) / 4, bh = box[3] - box[2], nrows = bh * (box[5] - box[4]);
   const int E = nrows * bw4;
   if (E <= 0) return hipErrorInvalidValue;
@@ -1539,7 +1613,7 @@ hipError_t launch_dots_box(const float* a, const float* cols, const SlotArgs& sa
                      dpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dots_final, dim3(k + 1), dim3(256), 0, st, dpart, nbx, k + 1, out);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, st, dpart, nbx, k + 1, out, sig);
   return hipGetLastError();
 }
 

@@ -54,8 +54,8 @@ int conv_direct(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool a
 // ws->ak must hold the n atoms' constants.
 int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, float* phi);
 // r = y - H * f (into r_out or ws->r), q = Phi^T r (ws->q), per-atom sums and loss in sums
-// (ws->dres when null; host-visible memory is fine): sums[6a + c] (see launch_grad_finalize),
-// sums[6n] = C, sums[6n + 1] = 1/2 ||r||^2.
+// (ws->dres when null; else pinned host memory, readable once ws->sums_sig has been waited
+// for): sums[6a + c] (see launch_grad_finalize), sums[6n] = C, sums[6n + 1] = 1/2 ||r||^2.
 int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
              float lambda, const sfw_atom* atoms_dev, int n, float* r_out, double* loss_out,
              sfw_atom* grad_out, double* sums = nullptr);
@@ -76,7 +76,8 @@ int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const f
 // pinned host memory); the slots come in sa (all of them in ws->lasso_slots when nd exceeds
 // kSlotArgs).
 int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y, int slot,
-                const float* theta, const SlotArgs& sa, int nd, double* out);
+                const float* theta, const SlotArgs& sa, int nd, double* out,
+                const SigArgs& sig = kNoSig);
 // min_{w >= 0} 1/2 w^T G w - c^T w.
 int nnqp(const std::vector<double>& G, const std::vector<double>& c, int k, std::vector<double>& w);
 

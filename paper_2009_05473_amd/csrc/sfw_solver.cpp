@@ -244,7 +244,8 @@ struct Solver {
     double* hs = ws->hpin + ws->hp_sums;
     rc = op_cgrad(ws, plan, vol, y, (float)lam, ws->atoms_dev, n, nullptr, nullptr, nullptr, hs);
     if (rc) return rc;
-    SFW_HIP(hipStreamSynchronize(ws->stream));
+    rc = sig_wait(ws, ws->sums_sig);
+    if (rc) return rc;
     st.n_eval_cgrad++;
     double wsum = 0.0;
     for (int i = 0; i < n; ++i) wsum += a[6 * i];
@@ -556,7 +557,8 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
       rc = op_certificate(ws, vol, ws->q, lambda, o.sigma_grid, o.n_sigma, o.d_grid, o.n_d, T,
                           nullptr);
       if (rc) return rc;
-      SFW_HIP(hipStreamSynchronize(ws->stream));
+      rc = sig_wait(ws, ws->cert_sig);
+      if (rc) return rc;
       const sfw_argmax best = *pinned_best(ws);
       S.st.n_certificates++;
       auto ta = Clock::now();

@@ -407,6 +407,28 @@ def test_lasso_zero_weight_case(L, ws_big):
     assert rel_l2(w, w_o) <= 1e-4
 
 
+def test_lasso_cache_follows_y_and_h_in_place(L, ws_big):
+    """Cached LASSO columns and Gram rows are keyed by fingerprints of y and H: overwriting
+    either in place (same pointers) gives the weights of the new data."""
+    prob, _, psf, y = _problem("c1")
+    thetas = f32(prob.atoms_true[:, 1:6])
+    atoms = dev(np.hstack([np.zeros((len(thetas), 1)), thetas]))
+    lam = 0.5
+    Hd, Yd = dev(psf), dev(y)
+    say("sfw_lasso_weights cache: y and H overwritten in place")
+    w0 = L.sfw_lasso_weights(ws_big, Hd, Yd, lam, atoms).cpu().numpy()
+    assert rel_l2(w0, oracle.lasso_weights(y, thetas, psf, lam)[0]) <= 1e-4
+    y2 = f32(1.7 * y)
+    Yd.copy_(dev(y2))
+    w1 = L.sfw_lasso_weights(ws_big, Hd, Yd, lam, atoms).cpu().numpy()
+    assert rel_l2(w1, oracle.lasso_weights(y2, thetas, psf, lam)[0]) <= 1e-4
+    psf2 = f32(0.8 * psf)
+    Hd.copy_(dev(psf2))
+    w2 = L.sfw_lasso_weights(ws_big, Hd, Yd, lam, atoms).cpu().numpy()
+    assert rel_l2(w2, oracle.lasso_weights(y2, thetas, psf2, lam)[0]) <= 1e-4
+    assert rel_l2(w1, w0) > 0.1 and rel_l2(w2, w1) > 0.1
+
+
 def test_lasso_support_longer_than_inline_slot_list(L):
     """130 atoms: the Gram-row kernels take the first 128 slots from their arguments and the
     rest from the device slot list. Lattice centres 5 voxels apart keep G well conditioned."""
