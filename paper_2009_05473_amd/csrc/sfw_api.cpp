@@ -503,29 +503,33 @@ static bool column_box(const float* theta, const sfw_dims& psf, const sfw_dims& 
 
 // Column of the unit atom whose constants are ws->ak[atom] (parameters theta, host) into LASSO
 // slot `slot`. Only the column's support box is computed: by the box kernel, which evaluates
-// the atom itself, or after a render by the matrix-core kernel in z-chunks. The rest of the
-// slot is cleared, since later Gram rows read it.
+// the atom itself, or after a render by the matrix-core kernel in z-chunks. The slot's box
+// (ws->slot_box) records where it is valid; outside it the slot keeps whatever it held, and
+// the Gram rows count the column as zero there.
 int op_columns(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* H, int atom,
                int slot, const float* theta) {
   float* col = ws->cols + (size_t)slot * ws->vcap;
+  int* sbox = ws->slot_box + 6 * (size_t)slot;
   int box[6];
   const bool boxed = column_box(theta, p.psf, vol, box);
-  const size_t V = (size_t)vol.nx * vol.ny * vol.nz;
   if (boxed && column_box_ok(p.psf)) {
-    // the atom is computed inside the convolution kernel: no rendered volume
+    // the atom is computed inside the convolution kernel (no rendered volume), which also
+    // records the box
     ProfScope ps(ws, kProfLassoConv);
-    SFW_HIP(hipMemsetAsync(col, 0, V * sizeof(float), ws->stream));
-    SFW_HIP(launch_column_box(ws->ak + atom, H, p.psf, vol, box, col, ws->stream));
+    SFW_HIP(launch_column_box(ws->ak + atom, H, p.psf, vol, box, col, sbox, ws->stream));
     return SFW_OK;
   }
   {
     ProfScope ps(ws, kProfLassoRender);
     SFW_HIP(launch_render(ws->ak + atom, 1, vol, ws->f, ws->stream));
   }
-  if (!boxed || !p.mfma)
+  if (!boxed || !p.mfma) {
+    const int whole[6] = {0, vol.nx, 0, vol.ny, 0, vol.nz};
+    SFW_HIP(launch_store_box(whole, sbox, ws->stream));
     return conv_direct(ws, p, vol, false, ws->f, col, kEpiPlain, nullptr, kProfLassoConv);
+  }
   ProfScope ps(ws, kProfLassoConv);
-  SFW_HIP(hipMemsetAsync(col, 0, V * sizeof(float), ws->stream));
+  SFW_HIP(launch_store_box(box, sbox, ws->stream));
   ConvRegion rg;
   rg.tx0 = box[0] / 16;
   rg.tx1 = (box[1] + 15) / 16;
@@ -563,7 +567,7 @@ static bool column_box(const float* theta, const sfw_dims& psf, const sfw_dims& 
     }
     if (h <= l) {  // the column vanishes on the volume: keep a one-vector box
       l = 0;
-      h = a == 0 ? 4 : 1;
+      h = a == 0 ? std::min(4, n[a]) : 1;
     }
     box[2 * a] = l;
     box[2 * a + 1] = h;
@@ -582,16 +586,25 @@ int op_gram_row(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const 
   const float* a = ws->cols + (size_t)slot * ws->vcap;
   ProfScope ps(ws, kProfLassoDots);
   int box[6];
-  if (vol.nx % 4 == 0 && ws->vcap % 4 == 0 && column_box(theta, p.psf, vol, box)) {
-    SFW_HIP(launch_dots_box(a, ws->cols, sa, ws->lasso_slots, nd, ws->vcap, y, vol, box,
-                            ws->dpart, (int)std::min<size_t>(ws->dpart_cap, 1u << 30), out, sig,
-                            ws->stream));
+  const bool boxed = column_box(theta, p.psf, vol, box);
+  if (vol.nx % 4 == 0 && ws->vcap % 4 == 0 && boxed) {
+    SFW_HIP(launch_dots_box(a, ws->cols, sa, ws->lasso_slots, ws->slot_box, nd, ws->vcap, y, vol,
+                            box, ws->dpart, (int)std::min<size_t>(ws->dpart_cap, 1u << 30), out,
+                            sig, ws->stream));
     return SFW_OK;
+  }
+  if (!boxed) {  // the column was computed on the whole volume
+    box[0] = 0;
+    box[1] = vol.nx;
+    box[2] = 0;
+    box[3] = vol.ny;
+    box[4] = 0;
+    box[5] = vol.nz;
   }
   int nb = (int)std::min<size_t>(1024, (V + 1023) / 1024);
   if ((size_t)nb * (nd + 1) > ws->dpart_cap) return fail(SFW_EINVAL, "dot partial buffer too small");
-  SFW_HIP(launch_dots(a, ws->cols, sa, ws->lasso_slots, nd, ws->vcap, y, V, ws->dpart, nb, out,
-                      sig, ws->stream));
+  SFW_HIP(launch_dots(a, box, ws->cols, sa, ws->lasso_slots, ws->slot_box, nd, ws->vcap, y, vol,
+                      ws->dpart, nb, out, sig, ws->stream));
   return SFW_OK;
 }
 
@@ -855,6 +868,7 @@ void sfw_workspace_destroy(sfw_workspace* ws) {
   if (ws->sig_flag) (void)hipHostFree(ws->sig_flag);
   if (ws->sig_ticket) (void)hipFree(ws->sig_ticket);
   if (ws->fp_part) (void)hipFree(ws->fp_part);
+  if (ws->slot_box) (void)hipFree(ws->slot_box);
   for (hipEvent_t e : ws->prof_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ws->prof_stop) (void)hipEventDestroy(e);
   (void)hipSetDevice(cur);
@@ -977,6 +991,7 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
     ALLOC(ws->lasso_slots, (size_t)max_atoms * sizeof(int), "LASSO slot list");
     ALLOC(ws->sig_ticket, sizeof(unsigned), "completion signal counter");
     ALLOC(ws->fp_part, 2 * (size_t)kFpParts * sizeof(unsigned long long), "fingerprint partials");
+    ALLOC(ws->slot_box, 6 * (size_t)max_atoms * sizeof(int), "LASSO column boxes");
     if (hipMemset(ws->sig_ticket, 0, sizeof(unsigned)) != hipSuccess) {
       (void)hipGetLastError();
       sfw_workspace_destroy(ws);

@@ -208,6 +208,9 @@ struct sfw_workspace {
   int* sig_flag = nullptr;         // coherent pinned host word the signalling kernels write
   int sig_seq = 0;                 // sequence number of the last armed signal
   unsigned long long* fp_part = nullptr;  // [2 kFpParts] fingerprint partials (device)
+  // [max_atoms][6] (device): the box each LASSO column slot is valid on; the slot holds
+  // stale values outside it, which the Gram-row kernels never read
+  int* slot_box = nullptr;
   sfw::SigArgs cert_sig = sfw::kNoSig;  // signal of the last certificate maximum (pinned_best)
   sfw::SigArgs sums_sig = sfw::kNoSig;  // signal of the last (C, grad C) sums in host memory
   int* blur_changed = nullptr;   // [1]
@@ -365,8 +368,9 @@ hipError_t launch_conv_mfma_region(const float* in, const float* amat, sfw_dims 
 // PSF fits the kernel (P_x <= 33, P_z <= 31, LDS tile).
 constexpr int kColumnBoxMaxLds = 160 * 1024;
 bool column_box_ok(sfw_dims psf);
+// box_out (device int[6], may be null) receives the box.
 hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sfw_dims vol,
-                             const int box[6], float* out, hipStream_t st);
+                             const int box[6], float* out, int* box_out, hipStream_t st);
 
 // The per-atom sums of at most kAtomArgs atoms given by their constants on the host (one atom
 // group: p.groups == 1), reduced to sums_out[6 a + c] (float64; may be host memory) by the last
@@ -393,17 +397,22 @@ hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, i
                                sfw_argmax* best, sfw_argmax* best_host, const SigArgs& sig,
                                hipStream_t st);
 // out[c] = sum_v a[v] * cols[c][v] for c < k, out[k] = sum_v a[v] * y[v] (float64).
-// dots of column a with the k columns cols + slot(c) * colstride and with y (out[k]); slot(c)
-// is sa.s[c] for c < kSlotArgs, else slots[c] (device). out may be pinned host memory.
-hipError_t launch_dots(const float* a, const float* cols, const SlotArgs& sa, const int* slots,
-                       int k, size_t colstride, const float* y, size_t nvox, double* dpart,
-                       int nblocks, double* out, const SigArgs& sig, hipStream_t st);
+// dots of column a (valid on abox) with the k columns cols + slot(c) * colstride (each valid
+// on its box slot_box[6 slot(c)...], device) and with y (out[k]), a product counting only
+// where both factors are valid; slot(c) is sa.s[c] for c < kSlotArgs, else slots[c] (device).
+// out may be pinned host memory.
+hipError_t launch_dots(const float* a, const int abox[6], const float* cols, const SlotArgs& sa,
+                       const int* slots, const int* slot_box, int k, size_t colstride,
+                       const float* y, sfw_dims vol, double* dpart, int nblocks, double* out,
+                       const SigArgs& sig, hipStream_t st);
 // Gram row over box = {x0, x1, y0, y1, z0, z1} (half-open; x0, x1, nx and colstride multiples
 // of 4) that holds every nonzero of a.
 hipError_t launch_dots_box(const float* a, const float* cols, const SlotArgs& sa,
-                           const int* slots, int k, size_t colstride, const float* y,
-                           sfw_dims vol, const int box[6], double* dpart, int dpart_cap,
-                           double* out, const SigArgs& sig, hipStream_t st);
+                           const int* slots, const int* slot_box, int k, size_t colstride,
+                           const float* y, sfw_dims vol, const int box[6], double* dpart,
+                           int dpart_cap, double* out, const SigArgs& sig, hipStream_t st);
+// dst[0..6) = box (device)
+hipError_t launch_store_box(const int box[6], int* dst, hipStream_t st);
 hipError_t launch_any_nonfinite(const float* v, size_t n, int* flag, hipStream_t st);
 
 // ---- Fourier-domain grid certificate (sfw_fft.hip)

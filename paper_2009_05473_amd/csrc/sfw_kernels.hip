@@ -949,13 +949,19 @@ __global__ __launch_bounds__(1024) void k_argmax_final(const ArgPart* __restrict
 
 // ------------------------------------------------------------------ LASSO dot products
 
-// dpart[block][c] = partial sum over the block's voxels of a * cols[c] (c < k), a * y (c = k):
-// each thread owns 4 consecutive voxels per grid stride (128-bit loads; its part of a stays
-// in registers across the columns when it owns at most kDotsHold groups), float32 products,
-// float64 accumulation, fixed-order block reduction; columns go four at a time so that four
-// independent loads are in flight per thread.
-constexpr int kDotsHold = 4;
-constexpr int kDotsCols = 4;
+// A LASSO column is valid on its box {x0, x1, y0, y1, z0, z1} (half-open, from slot_box) and
+// stands for zero elsewhere: the slot may hold stale values there.
+struct Box6 {
+  int x0, x1, y0, y1, z0, z1;
+};
+__device__ __forceinline__ Box6 slot_box_of(const int* __restrict__ slot_box, int slot) {
+  const int* b = slot_box + 6 * slot;
+  return Box6{b[0], b[1], b[2], b[3], b[4], b[5]};
+}
+__device__ __forceinline__ bool in_box(const Box6& b, int x, int y, int z) {
+  return x >= b.x0 && x < b.x1 && y >= b.y0 && y < b.y1 && z >= b.z0 && z < b.z1;
+}
+constexpr Box6 kBoxAll{0, 0x7fffffff, 0, 0x7fffffff, 0, 0x7fffffff};
 
 // slot of column c: the first kSlotArgs come in the kernel arguments, the rest from device
 // memory (only read when the support is longer)
@@ -963,61 +969,49 @@ __device__ __forceinline__ int slot_of(const SlotArgs& sa, const int* slots, int
   return c < kSlotArgs ? sa.s[c] : slots[c];
 }
 
+// dpart[block][c] = partial sum over the block's voxels of a * cols[c] (c < k), a * y (c = k),
+// in flat voxel order over the whole volume: a is valid on abox and column c on its own box
+// (slot_box), and a product counts only where both are valid. Float32 products, float64
+// accumulation, fixed-order block reduction. Used where the Gram-row box kernel does not
+// apply (a column without a box, or rows that are not a multiple of four floats).
+constexpr int kDotsHold = 4;
+constexpr int kDotsCols = 4;
+
 __device__ __forceinline__ double dot4(const float4& a, const float4& b) {
   return (double)(a.x * b.x) + (double)(a.y * b.y) + (double)(a.z * b.z) + (double)(a.w * b.w);
 }
 
-__global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
+__global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a, Box6 abox,
                                               const float* __restrict__ cols,
-                                              SlotArgs sa, const int* __restrict__ slots, int k,
+                                              SlotArgs sa, const int* __restrict__ slots,
+                                              const int* __restrict__ slot_box, int k,
                                               size_t colstride, const float* __restrict__ y,
-                                              size_t nvox, double* __restrict__ dpart) {
+                                              int nx, int ny, size_t nvox,
+                                              double* __restrict__ dpart) {
   __shared__ double red[kDotsCols][4];
   const int tid = threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * 256 * 4;
-  const size_t v0 = ((size_t)blockIdx.x * 256 + tid) * 4;
-  const bool avec = nvox % 4 == 0 && ((uintptr_t)a & 15) == 0;
-  const bool hold = avec && nvox <= stride * kDotsHold;
-  float4 ah[kDotsHold];
-#pragma unroll
-  for (int h = 0; h < kDotsHold; ++h) {
-    const size_t v = v0 + (size_t)h * stride;
-    ah[h] = (hold && v < nvox) ? *reinterpret_cast<const float4*>(a + v) : make_float4(0, 0, 0, 0);
-  }
+  const size_t stride = (size_t)gridDim.x * 256;
   for (int c0 = 0; c0 <= k; c0 += kDotsCols) {
     const int nc = min(kDotsCols, k + 1 - c0);
     const float* b[kDotsCols];
-    bool vec = avec;
+    Box6 bb[kDotsCols];
 #pragma unroll
     for (int u = 0; u < kDotsCols; ++u) {
       const int c = min(c0 + u, k);
-      b[u] = c < k ? cols + (size_t)slot_of(sa, slots, c) * colstride : y;
-      vec = vec && (((uintptr_t)b[u]) & 15) == 0;
+      const int sl = c < k ? slot_of(sa, slots, c) : 0;
+      b[u] = c < k ? cols + (size_t)sl * colstride : y;
+      bb[u] = c < k ? slot_box_of(slot_box, sl) : kBoxAll;
     }
     double s[kDotsCols] = {0.0, 0.0, 0.0, 0.0};
-    if (hold && vec) {
+    for (size_t v = (size_t)blockIdx.x * 256 + tid; v < nvox; v += stride) {
+      const size_t row = v / (size_t)nx;
+      const int x = (int)(v - row * (size_t)nx);
+      const int yy = (int)(row % (size_t)ny), zz = (int)(row / (size_t)ny);
+      if (!in_box(abox, x, yy, zz)) continue;
+      const float av = a[v];
 #pragma unroll
-      for (int h = 0; h < kDotsHold; ++h) {
-        const size_t v = v0 + (size_t)h * stride;
-        if (v < nvox) {
-          float4 bv[kDotsCols];
-#pragma unroll
-          for (int u = 0; u < kDotsCols; ++u) bv[u] = *reinterpret_cast<const float4*>(b[u] + v);
-#pragma unroll
-          for (int u = 0; u < kDotsCols; ++u) s[u] += dot4(ah[h], bv[u]);
-        }
-      }
-    } else {
-      for (size_t v = v0; v < nvox; v += stride)
-#pragma unroll
-        for (int u = 0; u < kDotsCols; ++u) {
-          if (vec) {
-            s[u] += dot4(*reinterpret_cast<const float4*>(a + v),
-                         *reinterpret_cast<const float4*>(b[u] + v));
-          } else {
-            for (size_t w = v; w < v + 4 && w < nvox; ++w) s[u] += (double)(a[w] * b[u][w]);
-          }
-        }
+      for (int u = 0; u < kDotsCols; ++u)
+        if (in_box(bb[u], x, yy, zz)) s[u] += (double)(av * b[u][v]);
     }
 #pragma unroll
     for (int u = 0; u < kDotsCols; ++u) {
@@ -1032,15 +1026,16 @@ __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a,
   }
 }
 
-// Gram row of column a over a box that holds every nonzero of a: out partials
-// dpart[blockIdx.x][c] = sum over the box of a * col_c (c < k: cached column slots[c], c = k:
-// y) for
-// the columns of chunk blockIdx.y (cpb per chunk). The box is rows (y, z) of bw4 float4 starting
-// at x0 (x0, nx and the column stride multiples of 4); a thread keeps its kDotsHold float4 of a
-// in registers across the columns.
+// Gram row of column a over its box (a is valid there and stands for zero elsewhere): out
+// partials dpart[blockIdx.x][c] = sum over the box of a * col_c (c < k: cached column
+// slot(c), counted only inside its own box; c = k: y) for the columns of chunk blockIdx.y (cpb
+// per chunk). The box is rows (y, z) of bw4 float4 starting at x0 (x0, nx, the column stride
+// and every column box's x bounds multiples of 4, so a float4 lies wholly inside or outside a
+// box); a thread keeps its kDotsHold float4 of a in registers across the columns.
 __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
                                                   const float* __restrict__ cols,
                                                   SlotArgs sa, const int* __restrict__ slots,
+                                                  const int* __restrict__ slot_box,
                                                   int k, size_t colstride,
                                                   const float* __restrict__ y,
                                                   int nx, int ny, int x0, int bw4, int y0,
@@ -1053,6 +1048,7 @@ __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
   const int e0 = blockIdx.x * 256 + tid;
   float4 ah[kDotsHold];
   size_t vh[kDotsHold];
+  int xh[kDotsHold], yh[kDotsHold], zh[kDotsHold];
 #pragma unroll
   for (int h = 0; h < kDotsHold; ++h) {
     const int e = e0 + h * stride;
@@ -1060,6 +1056,9 @@ __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
     const int row = ok ? e / bw4 : 0;
     const int q = ok ? e - row * bw4 : 0;
     const int yy = y0 + row % bh, zz = z0 + row / bh;
+    xh[h] = x0 + 4 * q;
+    yh[h] = yy;
+    zh[h] = zz;
     vh[h] = ((size_t)zz * ny + yy) * nx + x0 + 4 * q;
     ah[h] = ok ? *reinterpret_cast<const float4*>(a + vh[h]) : make_float4(0.f, 0.f, 0.f, 0.f);
   }
@@ -1067,10 +1066,13 @@ __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
   for (int c0 = cb; c0 < ce; c0 += kDotsCols) {
     const int nc = min(kDotsCols, ce - c0);
     const float* b[kDotsCols];
+    Box6 bb[kDotsCols];
 #pragma unroll
     for (int u = 0; u < kDotsCols; ++u) {
       const int c = min(c0 + u, ce - 1);
-      b[u] = c < k ? cols + (size_t)slot_of(sa, slots, c) * colstride : y;
+      const int sl = c < k ? slot_of(sa, slots, c) : 0;
+      b[u] = c < k ? cols + (size_t)sl * colstride : y;
+      bb[u] = c < k ? slot_box_of(slot_box, sl) : kBoxAll;
     }
     double s[kDotsCols] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1078,7 +1080,10 @@ __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
       if (e0 + h * stride < E) {
         float4 bv[kDotsCols];
 #pragma unroll
-        for (int u = 0; u < kDotsCols; ++u) bv[u] = *reinterpret_cast<const float4*>(b[u] + vh[h]);
+        for (int u = 0; u < kDotsCols; ++u)
+          bv[u] = in_box(bb[u], xh[h], yh[h], zh[h])
+                      ? *reinterpret_cast<const float4*>(b[u] + vh[h])
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int u = 0; u < kDotsCols; ++u) s[u] += dot4(ah[h], bv[u]);
       }
@@ -1217,6 +1222,23 @@ hipError_t launch_store_atoms(const AtomK* host, int n, AtomK* dst, hipStream_t 
   std::memset(&args, 0, sizeof(args));
   std::memcpy(args.a, host, sizeof(AtomK) * n);
   hipLaunchKernelGGL(k_store_atoms, dim3(1), dim3(64), 0, st, args, n, dst);
+  return hipGetLastError();
+}
+
+__global__ void k_store_box(Box6 b, int* __restrict__ dst) {
+  if (threadIdx.x == 0) {
+    dst[0] = b.x0;
+    dst[1] = b.x1;
+    dst[2] = b.y0;
+    dst[3] = b.y1;
+    dst[4] = b.z0;
+    dst[5] = b.z1;
+  }
+}
+
+hipError_t launch_store_box(const int box[6], int* dst, hipStream_t st) {
+  const Box6 b{box[0], box[1], box[2], box[3], box[4], box[5]};
+  hipLaunchKernelGGL(k_store_box, dim3(1), dim3(64), 0, st, b, dst);
   return hipGetLastError();
 }
 
@@ -1375,7 +1397,16 @@ constexpr int kBoxThreads = kBoxTX * kBoxTY * kBoxSplit;
 template <int PZ>
 __global__ __launch_bounds__(kBoxThreads) void k_column_box(
     const AtomK* __restrict__ atom, const float* __restrict__ H, int pxs, int pys, int nx, int ny,
-    int nz, int bx0, int by0, int bz0, int bx1, int by1, int bz1, float* __restrict__ out) {
+    int nz, int bx0, int by0, int bz0, int bx1, int by1, int bz1, float* __restrict__ out,
+    int* __restrict__ box_out) {
+  if (box_out && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
+    box_out[0] = bx0;  // the box this column is valid on (read by the Gram-row kernels)
+    box_out[1] = bx1;
+    box_out[2] = by0;
+    box_out[3] = by1;
+    box_out[4] = bz0;
+    box_out[5] = bz1;
+  }
   // tile [yy][xx][w] with the z window w innermost (WZP floats per column, 16-byte aligned),
   // taps [ky][kx][kz] (PZP per row): both read as float4
   constexpr int WZ = kBoxZ + PZ - 1, WZP = (WZ + 3) & ~3, PZP = (PZ + 3) & ~3;
@@ -1484,7 +1515,7 @@ bool column_box_ok(sfw_dims psf) {
 }
 
 hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sfw_dims vol,
-                             const int box[6], float* out, hipStream_t st) {
+                             const int box[6], float* out, int* box_out, hipStream_t st) {
   if (!column_box_ok(psf)) return hipErrorInvalidValue;
   const int bw = box[1] - box[0], bh = box[3] - box[2], bd = box[5] - box[4];
   if (bw <= 0 || bh <= 0 || bd <= 0) return hipSuccess;
@@ -1499,7 +1530,7 @@ hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sf
     if (attr != hipSuccess) return attr;                                                       \
     hipLaunchKernelGGL(k_column_box<P>, grid, dim3(kBoxThreads), lds, st, atom, H, psf.nx,     \
                        psf.ny, vol.nx, vol.ny, vol.nz, box[0], box[2], box[4], box[1], box[3], \
-                       box[5], out);                                                           \
+                       box[5], out, box_out);                                                  \
     return hipGetLastError();                                                                  \
   }
     SFW_BOX_CASE(1) SFW_BOX_CASE(3) SFW_BOX_CASE(5) SFW_BOX_CASE(7) SFW_BOX_CASE(9)
@@ -1583,11 +1614,14 @@ hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, i
   return hipGetLastError();
 }
 
-hipError_t launch_dots(const float* a, const float* cols, const SlotArgs& sa, const int* slots,
-                       int k, size_t colstride, const float* y, size_t nvox, double* dpart,
-                       int nblocks, double* out, const SigArgs& sig, hipStream_t st) {
-  hipLaunchKernelGGL(k_dots, dim3(nblocks), dim3(256), 0, st, a, cols, sa, slots, k, colstride, y,
-                     nvox, dpart);
+hipError_t launch_dots(const float* a, const int abox[6], const float* cols, const SlotArgs& sa,
+                       const int* slots, const int* slot_box, int k, size_t colstride,
+                       const float* y, sfw_dims vol, double* dpart, int nblocks, double* out,
+                       const SigArgs& sig, hipStream_t st) {
+  const Box6 ab{abox[0], abox[1], abox[2], abox[3], abox[4], abox[5]};
+  const size_t nvox = (size_t)vol.nx * vol.ny * vol.nz;
+  hipLaunchKernelGGL(k_dots, dim3(nblocks), dim3(256), 0, st, a, ab, cols, sa, slots, slot_box, k,
+                     colstride, y, vol.nx, vol.ny, nvox, dpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, st, dpart, nblocks, k + 1, out, sig);
@@ -1595,9 +1629,9 @@ hipError_t launch_dots(const float* a, const float* cols, const SlotArgs& sa, co
 }
 
 hipError_t launch_dots_box(const float* a, const float* cols, const SlotArgs& sa,
-                           const int* slots, int k, size_t colstride, const float* y,
-                           sfw_dims vol, const int box[6], double* dpart, int dpart_cap,
-                           double* out, const SigArgs& sig, hipStream_t st) {
+                           const int* slots, const int* slot_box, int k, size_t colstride,
+                           const float* y, sfw_dims vol, const int box[6], double* dpart,
+                           int dpart_cap, double* out, const SigArgs& sig, hipStream_t st) {
   const int bw4 = (box[1] - box[0]) / 4, bh = box[3] - box[2], nrows = bh * (box[5] - box[4]);
   const int E = nrows * bw4;
   if (E <= 0) return hipErrorInvalidValue;
@@ -1608,8 +1642,8 @@ hipError_t launch_dots_box(const float* a, const float* cols, const SlotArgs& sa
   const int cpb = (groups + chunks - 1) / chunks * kDotsCols;
   chunks = (k + 1 + cpb - 1) / cpb;
   if ((size_t)nbx * (k + 1) > (size_t)dpart_cap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dots_box, dim3(nbx, chunks), dim3(256), 0, st, a, cols, sa, slots, k,
-                     colstride, y, vol.nx, vol.ny, box[0], bw4, box[2], bh, box[4], nrows, cpb,
+  hipLaunchKernelGGL(k_dots_box, dim3(nbx, chunks), dim3(256), 0, st, a, cols, sa, slots,
+                     slot_box, k, colstride, y, vol.nx, vol.ny, box[0], bw4, box[2], bh, box[4], nrows, cpb,
                      dpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -429,6 +429,31 @@ def test_lasso_cache_follows_y_and_h_in_place(L, ws_big):
     assert rel_l2(w1, w0) > 0.1 and rel_l2(w2, w1) > 0.1
 
 
+def test_lasso_reused_slots_ignore_stale_values(L):
+    """Four column slots for supports that keep replacing atoms: a reused slot keeps the old
+    column's values outside the new column's box, which the Gram rows must not read (boxed
+    columns at 64 x 64 x 32)."""
+    shape, psf_shape = (32, 64, 64), (9, 5, 5)
+    rng = np.random.default_rng(4404)
+    psf = np.abs(rng.standard_normal(psf_shape)) + 0.1
+    psf = f32(psf / psf.sum())
+    cen = np.array([[14, 14, 10], [48, 20, 16], [20, 50, 20], [50, 50, 12], [32, 32, 16],
+                    [10, 40, 22], [40, 8, 9]], dtype=np.float64)
+    thetas = f32(np.hstack([cen + rng.uniform(-0.4, 0.4, cen.shape),
+                            rng.uniform(1.0, 1.5, (len(cen), 1)), np.full((len(cen), 1), 2.0)]))
+    truth = np.hstack([rng.uniform(0.5, 2.0, (len(cen), 1)), thetas])
+    y = f32(oracle.blur(oracle.render(shape, truth), psf) + 0.01 * rng.standard_normal(shape))
+    lam = 0.05
+    Hd, Yd = dev(psf), dev(y)
+    with L.Workspace(shape, psf_shape, 4) as w:
+        for sup in ([0, 1, 2], [0, 3, 4], [5, 3, 1, 6], [2, 4, 0], [6, 5]):
+            say("sfw_lasso_weights reused slots", sup)
+            th = thetas[sup]
+            atoms = dev(np.hstack([np.zeros((len(sup), 1)), th]))
+            got = L.sfw_lasso_weights(w, Hd, Yd, lam, atoms).cpu().numpy()
+            assert rel_l2(got, oracle.lasso_weights(y, th, psf, lam)[0]) <= 1e-4, sup
+
+
 def test_lasso_support_longer_than_inline_slot_list(L):
     """130 atoms: the Gram-row kernels take the first 128 slots from their arguments and the
     rest from the device slot list. Lattice centres 5 voxels apart keep G well conditioned."""
