@@ -1385,17 +1385,18 @@ hipError_t launch_conv_mfma(const float* in, const float* amat, sfw_dims psf, sf
 // The LASSO column a = H * (w g) of one atom (unit weight in the LASSO) on the box
 // [bx0, bx1) x [by0, by1) x [bz0, bz1) only, without a rendered volume: each block computes
 // the atom on its input tile (its kBoxTX x kBoxTY x kBoxZ outputs grown by the PSF
-// half-widths, zero outside the volume) straight into LDS with the render's arithmetic, stages
-// the taps there as [ky][kx][kz] rows, and convolves. A column box is small, so to occupy the
-// chip each output column is shared by kBoxSplit threads, thread s taking the tap rows
-// ky = s mod kBoxSplit; for each tap (ky, kx) it keeps the kBoxZ + PZ - 1 tile values of its
-// column in registers and applies the PZ taps along z to its kBoxZ outputs. The partial sums
-// meet in LDS.
-constexpr int kBoxTX = 32, kBoxTY = 2, kBoxZ = 4, kBoxSplit = 4;
-constexpr int kBoxThreads = kBoxTX * kBoxTY * kBoxSplit;
+// half-widths, zero outside the volume) straight into LDS with the render's arithmetic, and
+// convolves. Every wave covers the block's kBoxTX x kBoxTY output columns, one per lane, for
+// the tap rows ky = wave, wave + nwaves, ... (nwaves = min(P_y, kBoxMaxWaves) waves per
+// block, so that a small box still gives the chip enough waves). For each tap (ky, kx) a lane
+// keeps the kBoxZ + PZ - 1 tile values of its column in registers and applies the PZ taps
+// along z, the same for the whole wave (scalar loads of H), to its kBoxZ outputs. The
+// partial sums of the waves meet in LDS and are added in wave order.
+constexpr int kBoxTX = 16, kBoxTY = 4, kBoxZ = 4, kBoxMaxWaves = 16;
+static_assert(kBoxTX * kBoxTY == 64, "one output column per lane");
 
 template <int PZ>
-__global__ __launch_bounds__(kBoxThreads) void k_column_box(
+__global__ __launch_bounds__(64 * kBoxMaxWaves) void k_column_box(
     const AtomK* __restrict__ atom, const float* __restrict__ H, int pxs, int pys, int nx, int ny,
     int nz, int bx0, int by0, int bz0, int bx1, int by1, int bz1, float* __restrict__ out,
     int* __restrict__ box_out) {
@@ -1408,54 +1409,50 @@ __global__ __launch_bounds__(kBoxThreads) void k_column_box(
     box_out[5] = bz1;
   }
   // tile [yy][xx][w] with the z window w innermost (WZP floats per column, 16-byte aligned),
-  // taps [ky][kx][kz] (PZP per row): both read as float4
-  constexpr int WZ = kBoxZ + PZ - 1, WZP = (WZ + 3) & ~3, PZP = (PZ + 3) & ~3;
-  constexpr int NT = kBoxThreads;
+  // read as float4
+  constexpr int WZ = kBoxZ + PZ - 1, WZP = (WZ + 3) & ~3;
   extern __shared__ float4 lds4[];
   float* tile = reinterpret_cast<float*>(lds4);
   const int LX = kBoxTX + pxs - 1, LY = kBoxTY + pys - 1;
-  const int ntile = LY * LX * WZP;
-  float* hs = tile + ntile;
   const int X0 = bx0 + blockIdx.x * kBoxTX, Y0 = by0 + blockIdx.y * kBoxTY;
   const int Z0 = bz0 + blockIdx.z * kBoxZ;
   const int cx = (pxs - 1) / 2, cy = (pys - 1) / 2, cz = (PZ - 1) / 2;
   const int t = threadIdx.x;
+  const int nwaves = (int)(blockDim.x >> 6);
   const AtomK k = *atom;
-  // tile rows (zz, yy) go to waves in turn, x to lanes
+  // the tile, element e = (zz LY + yy) LX + xx, spread over all threads (several elements in
+  // flight per thread)
   const int wave = t >> 6, lane = t & 63;
-  const int x = X0 - cx + lane;
-  const float dx = (float)x - k.mx;
-  for (int row = wave; row < WZ * LY; row += NT / 64) {
-    const int zz = row / LY, yy = row - zz * LY;
-    const int y = Y0 - cy + yy, z = Z0 - cz + zz;
-    if (lane < LX) {
-      float g = 0.f;
-      if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) {
-        const float dy = (float)y - k.my, dz = (float)z - k.mz;
-        const float r2 = fmaf(dz, dz, fmaf(dx, dx, fmaf(dy, dy, kTinyR2)));
-        const float up = fast_exp2(fmaf(k.hd, fast_log2(r2), k.c));  // u * log2(e)
-        g = k.w * fast_exp2(-up);
-      }
-      tile[(yy * LX + lane) * WZP + zz] = g;
+  const int ntile = WZ * LY * LX, NT = (int)blockDim.x;
+#pragma unroll 4
+  for (int e = t; e < ntile; e += NT) {
+    const int xx = e % LX, r = e / LX;
+    const int yy = r % LY, zz = r / LY;
+    const int x = X0 - cx + xx, y = Y0 - cy + yy, z = Z0 - cz + zz;
+    float g = 0.f;
+    if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) {
+      const float dx = (float)x - k.mx, dy = (float)y - k.my, dz = (float)z - k.mz;
+      const float r2 = fmaf(dz, dz, fmaf(dx, dx, fmaf(dy, dy, kTinyR2)));
+      const float up = fast_exp2(fmaf(k.hd, fast_log2(r2), k.c));  // u * log2(e)
+      g = k.w * fast_exp2(-up);
     }
-  }
-  for (int e = t; e < pys * pxs * PZP; e += NT) {
-    const int kz = e % PZP, r = e / PZP;  // r = ky * pxs + kx
-    hs[e] = kz < PZ ? H[(size_t)kz * pys * pxs + r] : 0.f;
+    tile[(yy * LX + xx) * WZP + zz] = g;
   }
   __syncthreads();
-  const int xl = t % kBoxTX, grp = t / kBoxTX;
-  const int yl = grp % kBoxTY, part = grp / kBoxTY;
+  const int xl = lane % kBoxTX, yl = lane / kBoxTX;
+  const int part = __builtin_amdgcn_readfirstlane(wave);
+  const int hstride = pys * pxs;  // H is [kz][ky][kx]
   float acc[kBoxZ];
 #pragma unroll
   for (int o = 0; o < kBoxZ; ++o) acc[o] = 0.f;
-  for (int ky = part; ky < pys; ky += kBoxSplit) {
+  for (int ky = part; ky < pys; ky += nwaves) {
     const int yy = yl + pys - 1 - ky;
+#pragma unroll 3
     for (int kx = 0; kx < pxs; ++kx) {
       const int xx = xl + pxs - 1 - kx;
       const float4* tv = reinterpret_cast<const float4*>(tile + (yy * LX + xx) * WZP);
-      const float4* hv = reinterpret_cast<const float4*>(hs + (ky * pxs + kx) * PZP);
-      float v[WZP], h[PZP];
+      const float* hp = H + ky * pxs + kx;
+      float v[WZP], h[PZ];
 #pragma unroll
       for (int q = 0; q < WZP / 4; ++q) {
         const float4 f = tv[q];
@@ -1465,13 +1462,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_column_box(
         v[4 * q + 3] = f.w;
       }
 #pragma unroll
-      for (int q = 0; q < PZP / 4; ++q) {
-        const float4 f = hv[q];
-        h[4 * q] = f.x;
-        h[4 * q + 1] = f.y;
-        h[4 * q + 2] = f.z;
-        h[4 * q + 3] = f.w;
-      }
+      for (int kz = 0; kz < PZ; ++kz) h[kz] = hp[kz * hstride];
 #pragma unroll
       for (int kz = 0; kz < PZ; ++kz) {
 #pragma unroll
@@ -1479,11 +1470,10 @@ __global__ __launch_bounds__(kBoxThreads) void k_column_box(
       }
     }
   }
-  // partial sums of the kBoxSplit tap groups, through the (no longer needed) tile
+  // partial sums of the waves, through the (no longer needed) tile: [part][o][lane]
   __syncthreads();
-  const int cell = yl * kBoxTX + xl;  // < kBoxTX * kBoxTY
 #pragma unroll
-  for (int o = 0; o < kBoxZ; ++o) tile[(part * kBoxZ + o) * (kBoxTX * kBoxTY) + cell] = acc[o];
+  for (int o = 0; o < kBoxZ; ++o) tile[(part * kBoxZ + o) * 64 + lane] = acc[o];
   __syncthreads();
   if (part == 0) {
     const int ox = X0 + xl, oy = Y0 + yl;
@@ -1491,8 +1481,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_column_box(
 #pragma unroll
       for (int o = 0; o < kBoxZ; ++o) {
         float sum = 0.f;
-#pragma unroll
-        for (int q = 0; q < kBoxSplit; ++q) sum += tile[(q * kBoxZ + o) * (kBoxTX * kBoxTY) + cell];
+        for (int q = 0; q < nwaves; ++q) sum += tile[(q * kBoxZ + o) * 64 + lane];
         const int oz = Z0 + o;
         if (oz < bz1) out[((size_t)oz * ny + oy) * nx + ox] = sum;
       }
@@ -1500,12 +1489,13 @@ __global__ __launch_bounds__(kBoxThreads) void k_column_box(
   }
 }
 
+static int column_box_waves(sfw_dims psf) { return std::min(psf.ny, kBoxMaxWaves); }
+
 static size_t column_box_lds(sfw_dims psf) {
-  const size_t taps = (size_t)psf.ny * psf.nx * ((psf.nz + 3) & ~3);
   const size_t wzp = (size_t)((kBoxZ + psf.nz - 1 + 3) & ~3);
   const size_t tile = std::max(wzp * (kBoxTY + psf.ny - 1) * (kBoxTX + psf.nx - 1),
-                               (size_t)kBoxSplit * kBoxZ * kBoxTX * kBoxTY);
-  return (tile + taps) * sizeof(float);
+                               (size_t)column_box_waves(psf) * kBoxZ * 64);
+  return tile * sizeof(float);
 }
 
 bool column_box_ok(sfw_dims psf) {
@@ -1528,7 +1518,8 @@ hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sf
         reinterpret_cast<const void*>(&k_column_box<P>),                                       \
         hipFuncAttributeMaxDynamicSharedMemorySize, kColumnBoxMaxLds);                         \
     if (attr != hipSuccess) return attr;                                                       \
-    hipLaunchKernelGGL(k_column_box<P>, grid, dim3(kBoxThreads), lds, st, atom, H, psf.nx,     \
+    hipLaunchKernelGGL(k_column_box<P>, grid, dim3(64 * column_box_waves(psf)), lds, st, atom, \
+                       H, psf.nx,                                                              \
                        psf.ny, vol.nx, vol.ny, vol.nz, box[0], box[2], box[4], box[1], box[3], \
                        box[5], out, box_out);                                                  \
     return hipGetLastError();                                                                  \
