@@ -107,6 +107,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the BSFW time-to-solution run after the timed steps")
+    ap.add_argument("--batch", type=int, default=0, metavar="K",
+                    help="also time sfw_solve_batch on the batched-solve workload, on one "
+                         "workspace and on K workspaces (0: skip)")
+    ap.add_argument("--batch-volumes", type=int, default=64)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB on the device (the "
                          "known-size copy that scales the HBM counters of a --pmc run)")
@@ -214,6 +218,62 @@ def solve_run(L, ws, H, Y, lam, prob, sg, dg):
             "seconds_certificate": stats["seconds_certificate"],
             "seconds_ascent": stats["seconds_ascent"], "seconds_lasso": stats["seconds_lasso"],
             "seconds_slide": stats["seconds_slide"]}
+
+
+def batch_run(L, synth, n_volumes, n_workspaces):
+    """Throughput of sfw_solve_batch (BSFW, grid proposal) on the batched-solve workload
+    (synth.draw_batch: volumes of 48..96 x 48..96 x 48 voxels holding 5..40 masses, each with
+    its own PSF): the whole batch on one workspace (solves one after another), then on
+    n_workspaces workspaces, each with its own stream (solves overlapping on the GPU). Both
+    runs must return the same atoms."""
+    import torch
+    probs = synth.draw_batch(n_volumes)
+    psf_max = tuple(max(p.config.psf_shape[a] for p in probs) for a in range(3))
+    vol_max = tuple(max(p.config.shape[a] for p in probs) for a in range(3))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    data = []
+    # inputs built on torch's current stream (the builder workspace's), which the tensor
+    # arithmetic uses too
+    with L.Workspace(vol_max, psf_max, 128) as builder:
+        for p in probs:
+            cfg = p.config
+            H = dev(p.psf)
+            clean = L.sfw_forward(builder, H, dev(p.atoms_true), p.shape)
+            y = (clean + cfg.noise_rel * clean.max() * dev(p.noise_unit)).contiguous()
+            _, best = L.sfw_certificate(builder, H, y, 1.0, list(np.float32(cfg.sigma_grid)),
+                                        list(cfg.d_grid))
+            data.append((y, H, float(np.float32(cfg.lambda_rel * best["eta"]))))
+    streams = [torch.cuda.Stream() for _ in range(n_workspaces)]
+    wss = [L.Workspace(vol_max, psf_max, 128, stream=st) for st in streams]
+    cfg0 = probs[0].config
+    opts = L.default_options(mode="BSFW", sigma_grid=[float(np.float32(v)) for v in cfg0.sigma_grid],
+                             d_grid=cfg0.d_grid)
+    torch.cuda.synchronize()
+    print(f"[batch] {n_volumes} volumes built", file=sys.stderr, flush=True)
+    L.sfw_solve_batch(wss, data[:n_workspaces], opts)  # untimed: first use of every workspace
+    t0 = time.perf_counter()
+    one = L.sfw_solve_batch(wss[:1], data, opts)
+    t1 = time.perf_counter()
+    print(f"[batch] one workspace: {t1 - t0:.3f} s", file=sys.stderr, flush=True)
+    many = L.sfw_solve_batch(wss, data, opts)
+    t2 = time.perf_counter()
+    print(f"[batch] {n_workspaces} workspaces: {t2 - t1:.3f} s", file=sys.stderr, flush=True)
+    for w in wss:
+        w.close()
+    same = all(np.array_equal(a[0], b[0]) for a, b in zip(one, many))
+    found = sum(len(r[0]) for r in many)
+    true = sum(p.config.n_atoms for p in probs)
+    return {"workload": f"{n_volumes} volumes of 48..96 x 48..96 x 48 voxels, 5..40 masses, "
+                        "own Gaussian PSF each (up to 15x15x29), from mu = 0",
+            "mode": "BSFW", "workspaces": n_workspaces,
+            "voxels": int(sum(np.prod(p.config.shape) for p in probs)),
+            "seconds_one_workspace": t1 - t0, "seconds": t2 - t1,
+            "volumes_per_s": n_volumes / (t2 - t1), "speedup": (t1 - t0) / (t2 - t1),
+            "same_atoms": bool(same), "status_ok": int(sum(r[2] == L.SFW_OK for r in many)),
+            "not_ok": {str(i): {"status": int(r[2]), "iterations": r[1]["iterations"],
+                                "atoms": len(r[0]), "atoms_true": probs[i].config.n_atoms}
+                       for i, r in enumerate(many) if r[2] != L.SFW_OK},
+            "atoms_found": int(found), "atoms_true": int(true)}
 
 
 def main():
@@ -356,6 +416,8 @@ def main():
     }
     if not args.no_solve:
         out["solve"] = solve_run(L, ws, H, Y, lam, prob, sg, dg)
+    if args.batch > 0:
+        out["batch"] = batch_run(L, synth, args.batch_volumes, args.batch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, atoms_eval.astype(np.float64),
                                            psf.astype(np.float64))

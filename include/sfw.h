@@ -217,6 +217,33 @@ int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const float* H,
               sfw_dims psf, float lambda, const sfw_options* opts, sfw_atom* atoms_out,
               int cap, int* n_out, sfw_stats* stats);
 
+/* One independent problem of a batch: the arguments and outputs of one sfw_solve call.
+ * y, H: device; atoms_out: HOST [cap]; n_out: HOST; stats: HOST or NULL; status: written
+ * with that solve's return code. */
+typedef struct {
+  const float* y;
+  sfw_dims vol;
+  const float* H;
+  sfw_dims psf;
+  float lambda;
+  sfw_atom* atoms_out;
+  int32_t cap;
+  int32_t* n_out;
+  sfw_stats* stats;
+  int32_t status;
+} sfw_batch_item;
+
+/* Solves n independent problems (many small volumes, each too small to fill the GPU on its
+ * own) on n_ws workspaces: one host thread per workspace takes the next unsolved item and
+ * runs sfw_solve on it, each workspace on its own stream, so the solves overlap on the GPU.
+ * Every workspace must fit every item (vol_max, psf_max, max_atoms); the results of an item
+ * do not depend on which workspace solved it. ws: HOST [n_ws]; items: HOST [n]; opts: HOST or
+ * NULL (shared by all items). Returns SFW_OK when every item returned SFW_OK, else the code of
+ * the first item (in item order) that did not, with sfw_last_error naming it; every item's
+ * status is written either way. Synchronous. */
+int sfw_solve_batch(sfw_workspace* const* ws, int n_ws, sfw_batch_item* items, int n,
+                    const sfw_options* opts);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,7 @@ EXPORTED = (
     "sfw_default_options", "sfw_workspace_create", "sfw_workspace_destroy",
     "sfw_workspace_set_stream", "sfw_last_error", "sfw_forward", "sfw_residual_grad",
     "sfw_adjoint", "sfw_forward_vjp", "sfw_certificate", "sfw_eta_points", "sfw_lasso_weights",
-    "sfw_solve", "sfw_profile_begin", "sfw_profile_end",
+    "sfw_solve", "sfw_solve_batch", "sfw_profile_begin", "sfw_profile_end",
 )
 SFW_PROF_KINDS = 16
 
@@ -71,6 +71,14 @@ class SfwStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class SfwBatchItem(ctypes.Structure):
+    _fields_ = [
+        ("y", ctypes.c_void_p), ("vol", SfwDims), ("H", ctypes.c_void_p), ("psf", SfwDims),
+        ("lam", ctypes.c_float), ("atoms_out", ctypes.c_void_p), ("cap", ctypes.c_int32),
+        ("n_out", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("status", ctypes.c_int32),
+    ]
+
+
 class SfwProfEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int32), ("ms", ctypes.c_double)]
 
@@ -103,6 +111,8 @@ def _load():
         "sfw_lasso_weights": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp]),
         "sfw_solve": (i32, [vp, vp, D, vp, D, f32, ctypes.POINTER(SfwOptions), vp, i32,
                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SfwStats)]),
+        "sfw_solve_batch": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(SfwBatchItem), i32,
+                                  ctypes.POINTER(SfwOptions)]),
         "sfw_profile_begin": (i32, [vp, ctypes.c_char_p]),
         "sfw_profile_end": (i32, [vp, ctypes.POINTER(SfwProfEntry), ctypes.POINTER(ctypes.c_int)]),
     }
@@ -173,7 +183,10 @@ def default_options(**overrides) -> SfwOptions:
 
 
 class Workspace:
-    """Owns an sfw_workspace bound to the current device and torch's current stream."""
+    """Owns an sfw_workspace bound to the current device and to a stream: torch's current
+    stream, or `stream` (a torch.cuda.Stream). Calls enqueue on that stream and return before
+    their kernels finish; with a stream of its own, order it against the tensors' stream
+    (torch.cuda.synchronize, events) before reading results or handing it new inputs."""
 
     def __init__(self, vol_max, psf_max, max_atoms, stream=None):
         self.handle = ctypes.c_void_p()
@@ -316,6 +329,49 @@ def sfw_solve(ws: Workspace, y, H, lam, opts: SfwOptions | None = None, cap: int
     n = n_out.value
     arr = np.array([[a.w, a.mx, a.my, a.mz, a.sigma, a.d] for a in out[:n]], dtype=np.float64)
     return arr.reshape(-1, 6), stats.as_dict(), code
+
+
+def sfw_solve_batch(workspaces, problems, opts: SfwOptions | None = None, cap: int | None = None):
+    """Independent solves: problems is a sequence of (y, H, lam) (device tensors, float);
+    workspaces a sequence of Workspace, one host thread each. Returns one (atoms [n, 6] float64
+    numpy, stats dict, status code) per problem, in order; raises on the first item (in
+    order) whose status is neither SFW_OK nor SFW_ENOCONV."""
+    wss = list(workspaces)
+    cap = min(w.max_atoms for w in wss) if cap is None else int(cap)
+    n = len(problems)
+    items = (SfwBatchItem * max(n, 1))()
+    outs, counts, stats = [], [], []
+    for i, (y, H, lam) in enumerate(problems):
+        out = (SfwAtom * max(cap, 1))()
+        cnt = ctypes.c_int32(0)
+        st = SfwStats()
+        outs.append(out)
+        counts.append(cnt)
+        stats.append(st)
+        it = items[i]
+        it.y = _dev_ptr(y, "float32", "y")
+        it.vol = dims(y.shape)
+        it.H = _dev_ptr(H, "float32", "H")
+        it.psf = dims(H.shape)
+        it.lam = float(lam)
+        it.atoms_out = ctypes.cast(out, ctypes.c_void_p)
+        it.cap = cap
+        it.n_out = ctypes.cast(ctypes.byref(cnt), ctypes.c_void_p)
+        it.stats = ctypes.cast(ctypes.byref(st), ctypes.c_void_p)
+        it.status = 0
+    handles = (ctypes.c_void_p * len(wss))(*[w.handle.value for w in wss])
+    lib.sfw_solve_batch(handles, len(wss), items, n, ctypes.byref(opts) if opts is not None else None)
+    msg = last_error()
+    res = []
+    for i in range(n):
+        code = items[i].status
+        if code not in (SFW_OK, SFW_ENOCONV):
+            raise SfwError(code, msg)
+        k = counts[i].value
+        arr = np.array([[a.w, a.mx, a.my, a.mz, a.sigma, a.d] for a in outs[i][:k]],
+                       dtype=np.float64)
+        res.append((arr.reshape(-1, 6), stats[i].as_dict(), code))
+    return res
 
 
 def sfw_profile_begin(ws: Workspace, classes=None):

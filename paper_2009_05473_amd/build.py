@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsfw.so")
 SOURCES = ["sfw_kernels.hip", "sfw_fft.hip", "sfw_fft_fixed.hip", "sfw_blur.hip", "sfw_api.cpp", "sfw_solver.cpp",
-           "sfw_nnqp.cpp"]
+           "sfw_nnqp.cpp", "sfw_batch.cpp"]
 ARCH = "gfx950"
 
 
@@ -28,7 +28,7 @@ def command(out: str = LIB) -> list:
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
             # no packed-FP32 VALU instructions anywhere in the device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-x", "hip", *srcs, "-I", INCLUDE, "-I", CSRC, "-o", out]
+            "-x", "hip", *srcs, "-I", INCLUDE, "-I", CSRC, "-pthread", "-o", out]
 
 
 def build(verbose: bool = False) -> str:

@@ -183,6 +183,39 @@ def draw_experiment(n: int, n_atoms: int, rep: int) -> Problem:
     return _draw(experiment_config(n, n_atoms), 10 ** 6 + 10 ** 4 * n + 100 * n_atoms + rep)
 
 
+BATCH_SHAPES_XY = tuple(range(48, 97, 8))  # n_x, n_y of a batch volume; n_z = 48
+
+
+def batch_config(rng: np.random.Generator, index: int) -> Config:
+    """One volume of the batched-solve workload (many uneven small volumes), drawn in the order
+    n_x, n_y, N, PSF sigma_xy, PSF sigma_z: n_x, n_y in {48, 56, ..., 96}, n_z = 48,
+    N ~ U{5..40}, the 64x64x32 workload's atom distributions, noise and grid, and an
+    anisotropic Gaussian PSF with sigma_xy ~ U[1, 2], sigma_z ~ U[2, 4] cut at
+    ceil(3.5 sigma) per axis (P_z <= 29)."""
+    nx = int(rng.choice(BATCH_SHAPES_XY))
+    ny = int(rng.choice(BATCH_SHAPES_XY))
+    n_atoms = int(rng.integers(5, 41))
+    sxy = float(rng.uniform(1.0, 2.0))
+    sz = float(rng.uniform(2.0, 4.0))
+    hxy, hz = int(np.ceil(3.5 * sxy)), int(np.ceil(3.5 * sz))
+    return replace(CONFIGS["c2"], name=f"b{index}", shape=(48, ny, nx), n_atoms=n_atoms,
+                   psf_sigma_xy=sxy, psf_sigma_z=sz, psf_shape=(2 * hz + 1, 2 * hxy + 1, 2 * hxy + 1))
+
+
+def draw_batch(n_volumes: int = 64, rep: int = 0) -> list:
+    """The batched-solve workload: n_volumes seeded problems. Volume i draws its shape, N and PSF
+    from seed s = 4000 + 100 rep + i (batch_config), then its atoms and noise from seed
+    s + 100000 in draw_problem's order."""
+    if not 0 <= n_volumes <= 100:
+        raise ValueError("n_volumes must be in [0, 100]")
+    out = []
+    for i in range(n_volumes):
+        seed = 4000 + 100 * rep + i
+        cfg = batch_config(np.random.default_rng(seed), i)
+        out.append(_draw(cfg, seed + 10 ** 5))
+    return out
+
+
 def _draw(cfg: Config, seed: int) -> Problem:
     rng = np.random.default_rng(seed)
     atoms = draw_atoms(cfg, rng)

@@ -79,6 +79,22 @@ def test_operators_reject_null_workspace_and_bad_lambda():
     assert L.sfw_workspace_set_stream(None, None) == _lib.SFW_EINVAL
 
 
+def test_solve_batch_validates_before_touching_the_gpu():
+    from paper_2009_05473_amd import _lib
+    L = _lib.lib
+    item = (_lib.SfwBatchItem * 1)()
+    assert L.sfw_solve_batch(None, 0, None, 0, None) == _lib.SFW_OK  # nothing to solve
+    assert L.sfw_solve_batch(None, 0, item, 1, None) == _lib.SFW_EINVAL
+    assert "workspace" in _lib.last_error()
+    assert L.sfw_solve_batch(None, 1, item, -1, None) == _lib.SFW_EINVAL
+    nulls = (ctypes.c_void_p * 2)(None, None)
+    assert L.sfw_solve_batch(nulls, 2, item, 1, None) == _lib.SFW_EINVAL
+    assert "NULL" in _lib.last_error()
+    fake = (ctypes.c_void_p * 2)(0x1000, 0x1000)  # never dereferenced: rejected as a repeat
+    assert L.sfw_solve_batch(fake, 2, item, 1, None) == _lib.SFW_EINVAL
+    assert "twice" in _lib.last_error()
+
+
 def test_last_error_is_thread_local():
     import threading
     from paper_2009_05473_amd import _lib
