@@ -244,6 +244,47 @@ typedef struct {
 int sfw_solve_batch(sfw_workspace* const* ws, int n_ws, sfw_batch_item* items, int n,
                     const sfw_options* opts);
 
+/* ---------------------------------------------------------------- proposal network
+ *
+ * A learned proposal for step 1 of Algorithms 1 and 2 (which take the maximum of the grid
+ * certificate): four 3x3x3 convolutions with 32 channels, the first of stride 2, ReLU between,
+ * reading x = scale * Phi^T r (scale = 1 / lambda gives the certificate's units) and producing
+ * on the half-resolution grid ((n + 1) / 2 per axis; voxel o at full-resolution position 2 o)
+ * a centre heatmap logit and sigma and d maps. bf16 weights and activations, float32
+ * accumulation, on the matrix cores; trained by sfw_net_train_step on these kernels.
+ * Parameters (HOST float32, sfw_net_num_params() values): per layer the weights
+ * [co][ci][tz][ty][tx] then the biases [co], layers (co, ci) = (32, 1), (32, 32), (32, 32),
+ * (3, 32). The solver uses a network through sfw_options.proposal. */
+typedef struct sfw_net sfw_net;
+
+int sfw_net_num_params(void);
+/* Network buffers for volumes up to vol_max voxels, on the current device; every call
+ * enqueues on `stream` (0 = the null stream). Parameters start at zero. */
+int sfw_net_create(sfw_net** net, sfw_dims vol_max, hipStream_t stream);
+void sfw_net_destroy(sfw_net* net);
+/* Copy the parameters in (and reset the optimizer state) or out; count must equal
+ * sfw_net_num_params(). Synchronous. */
+int sfw_net_set_params(sfw_net* net, const float* params, int count);
+int sfw_net_get_params(sfw_net* net, float* params, int count);
+/* out (device f32 [(nz+1)/2][(ny+1)/2][(nx+1)/2][4]): heatmap logit, sigma, d, unused per
+ * half-resolution voxel, for the device volume x [nz][ny][nx] times scale. Asynchronous. */
+int sfw_net_forward(sfw_net* net, const float* x, sfw_dims vol, float scale, float* out);
+/* Loss and gradients against the k (<= 96) atoms still to be found (HOST rows w, mx, my, mz,
+ * sigma, d): L = mean over half-resolution voxels of (h - T)^2 + M ((sigma_hat - S)^2 +
+ * (d_hat - D)^2), T the maximum of unit Gaussian blobs at the half-resolution centres, M = 1
+ * within one voxel of the nearest centre, whose sigma and d are S and D. loss (HOST, nullable),
+ * grads (HOST [num_params], nullable). Synchronous. */
+int sfw_net_gradients(sfw_net* net, const float* x, sfw_dims vol, float scale, const float* atoms,
+                      int k, double* loss, float* grads);
+/* One Adam step (beta 0.9, 0.999) of the same loss with learning rate lr; loss (HOST,
+ * nullable: the call then returns without synchronising). */
+int sfw_net_train_step(sfw_net* net, const float* x, sfw_dims vol, float scale,
+                       const float* atoms, int k, float lr, double* loss);
+/* The proposal: theta (HOST [5]) = (mx, my, mz, sigma, d) at the heatmap maximum (ties to the
+ * lowest voxel), score (HOST) = the logit there. Synchronous. */
+int sfw_net_propose(sfw_net* net, const float* x, sfw_dims vol, float scale, double* theta,
+                    double* score);
+
 #ifdef __cplusplus
 }
 #endif

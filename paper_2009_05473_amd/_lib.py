@@ -24,6 +24,9 @@ EXPORTED = (
     "sfw_workspace_set_stream", "sfw_last_error", "sfw_forward", "sfw_residual_grad",
     "sfw_adjoint", "sfw_forward_vjp", "sfw_certificate", "sfw_eta_points", "sfw_lasso_weights",
     "sfw_solve", "sfw_solve_batch", "sfw_profile_begin", "sfw_profile_end",
+    "sfw_net_num_params", "sfw_net_create", "sfw_net_destroy", "sfw_net_set_params",
+    "sfw_net_get_params", "sfw_net_forward", "sfw_net_gradients", "sfw_net_train_step",
+    "sfw_net_propose",
 )
 SFW_PROF_KINDS = 16
 
@@ -114,6 +117,15 @@ def _load():
         "sfw_solve_batch": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(SfwBatchItem), i32,
                                   ctypes.POINTER(SfwOptions)]),
         "sfw_profile_begin": (i32, [vp, ctypes.c_char_p]),
+        "sfw_net_num_params": (i32, []),
+        "sfw_net_create": (i32, [ctypes.POINTER(vp), D, vp]),
+        "sfw_net_destroy": (None, [vp]),
+        "sfw_net_set_params": (i32, [vp, vp, i32]),
+        "sfw_net_get_params": (i32, [vp, vp, i32]),
+        "sfw_net_forward": (i32, [vp, vp, D, f32, vp]),
+        "sfw_net_gradients": (i32, [vp, vp, D, f32, vp, i32, vp, vp]),
+        "sfw_net_train_step": (i32, [vp, vp, D, f32, vp, i32, f32, vp]),
+        "sfw_net_propose": (i32, [vp, vp, D, f32, vp, vp]),
         "sfw_profile_end": (i32, [vp, ctypes.POINTER(SfwProfEntry), ctypes.POINTER(ctypes.c_int)]),
     }
     for name, (res, args) in sig.items():
@@ -372,6 +384,84 @@ def sfw_solve_batch(workspaces, problems, opts: SfwOptions | None = None, cap: i
                        dtype=np.float64)
         res.append((arr.reshape(-1, 6), stats[i].as_dict(), code))
     return res
+
+
+class Net:
+    """The proposal network (sfw_net_*): parameters as one float32 vector in the library's
+    master layout (per layer weights [co][ci][tz][ty][tx], then biases)."""
+
+    def __init__(self, vol_max, stream=None):
+        self.handle = ctypes.c_void_p()
+        self.vol_max = tuple(vol_max)
+        check(lib.sfw_net_create(ctypes.byref(self.handle), dims(vol_max), _stream_handle(stream)))
+        self.num_params = int(lib.sfw_net_num_params())
+
+    def close(self):
+        if self.handle:
+            lib.sfw_net_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        check(lib.sfw_net_set_params(self.handle, p.ctypes.data_as(ctypes.c_void_p), p.size))
+
+    def get_params(self):
+        p = np.zeros(self.num_params, dtype=np.float32)
+        check(lib.sfw_net_get_params(self.handle, p.ctypes.data_as(ctypes.c_void_p), p.size))
+        return p
+
+    def forward(self, x, scale):
+        """[(nz+1)/2, (ny+1)/2, (nx+1)/2, 4] float32 tensor (heatmap logit, sigma, d, unused)."""
+        import torch
+        half = tuple((n + 1) // 2 for n in x.shape)
+        out = torch.empty(half + (4,), dtype=torch.float32, device="cuda")
+        check(lib.sfw_net_forward(self.handle, _dev_ptr(x, "float32", "x"), dims(x.shape),
+                                  float(scale), _dev_ptr(out, "float32", "out")))
+        return out
+
+    @staticmethod
+    def _atoms(atoms):
+        a = np.ascontiguousarray(np.asarray(atoms, dtype=np.float32).reshape(-1, 6))
+        return a, a.shape[0]
+
+    def gradients(self, x, scale, atoms):
+        """(loss, grads float32 [num_params]) against the atoms still to be found."""
+        a, k = self._atoms(atoms)
+        loss = ctypes.c_double(0.0)
+        g = np.zeros(self.num_params, dtype=np.float32)
+        check(lib.sfw_net_gradients(self.handle, _dev_ptr(x, "float32", "x"), dims(x.shape),
+                                    float(scale), a.ctypes.data_as(ctypes.c_void_p), k,
+                                    ctypes.byref(loss), g.ctypes.data_as(ctypes.c_void_p)))
+        return loss.value, g
+
+    def train_step(self, x, scale, atoms, lr, want_loss=False):
+        a, k = self._atoms(atoms)
+        loss = ctypes.c_double(0.0)
+        check(lib.sfw_net_train_step(self.handle, _dev_ptr(x, "float32", "x"), dims(x.shape),
+                                     float(scale), a.ctypes.data_as(ctypes.c_void_p), k,
+                                     float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def propose(self, x, scale):
+        """(theta [5] = mx, my, mz, sigma, d, score)."""
+        th = np.zeros(5, dtype=np.float64)
+        sc = ctypes.c_double(0.0)
+        check(lib.sfw_net_propose(self.handle, _dev_ptr(x, "float32", "x"), dims(x.shape),
+                                  float(scale), th.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(sc)))
+        return th, sc.value
 
 
 def sfw_profile_begin(ws: Workspace, classes=None):

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsfw.so")
 SOURCES = ["sfw_kernels.hip", "sfw_fft.hip", "sfw_fft_fixed.hip", "sfw_blur.hip", "sfw_api.cpp", "sfw_solver.cpp",
-           "sfw_nnqp.cpp", "sfw_batch.cpp"]
+           "sfw_nnqp.cpp", "sfw_batch.cpp", "sfw_cnn.hip"]
 ARCH = "gfx950"
 
 
