@@ -62,6 +62,7 @@ typedef struct { float w, mx, my, mz, sigma, d; } sfw_atom;
 typedef struct { float eta; int32_t i_sigma, i_d, x, y, z; } sfw_argmax;
 
 typedef struct sfw_workspace sfw_workspace;
+typedef struct sfw_net sfw_net; /* the proposal network (see the end of this header) */
 
 /* Solver options (host memory). sfw_default_options fills the defaults. */
 typedef struct {
@@ -84,6 +85,11 @@ typedef struct {
   int32_t lbfgs_memory;              /* curvature pairs kept, default 10 */
   int32_t check_finite;              /* reject NaN/Inf in y and H, default 1 */
   int32_t verbose;                   /* print one line per iteration to stderr */
+  sfw_net* proposal;                 /* NULL (default): step 1 seeds the local ascent at the
+                                        grid maximum of eta. Else a trained proposal network
+                                        (on the workspace's stream) seeds it; when the ascent
+                                        from that seed ends at eta* <= 1 + eta_tol, the grid
+                                        maximum seeds a second ascent, which decides */
 } sfw_options;
 
 /* Per-solve statistics (host memory). */
@@ -98,6 +104,8 @@ typedef struct {
   double criterion;          /* C of the returned measure */
   double last_eta;           /* eta* of the last iteration */
   double seconds_total, seconds_certificate, seconds_ascent, seconds_lasso, seconds_slide;
+  int32_t n_proposals;       /* seeds from the proposal network */
+  int32_t n_fallbacks;       /* of which the grid maximum had to replace */
 } sfw_stats;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -255,8 +263,6 @@ int sfw_solve_batch(sfw_workspace* const* ws, int n_ws, sfw_batch_item* items, i
  * Parameters (HOST float32, sfw_net_num_params() values): per layer the weights
  * [co][ci][tz][ty][tx] then the biases [co], layers (co, ci) = (32, 1), (32, 32), (32, 32),
  * (3, 32). The solver uses a network through sfw_options.proposal. */
-typedef struct sfw_net sfw_net;
-
 int sfw_net_num_params(void);
 /* Network buffers for volumes up to vol_max voxels, on the current device; every call
  * enqueues on `stream` (0 = the null stream). Parameters start at zero. */

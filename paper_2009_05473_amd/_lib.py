@@ -55,7 +55,7 @@ class SfwOptions(ctypes.Structure):
         ("slide_max_iter", ctypes.c_int32), ("ascent_gtol", ctypes.c_double),
         ("slide_gtol", ctypes.c_double), ("ftol", ctypes.c_double),
         ("lbfgs_memory", ctypes.c_int32), ("check_finite", ctypes.c_int32),
-        ("verbose", ctypes.c_int32),
+        ("verbose", ctypes.c_int32), ("proposal", ctypes.c_void_p),
     ]
 
 
@@ -67,7 +67,8 @@ class SfwStats(ctypes.Structure):
         ("criterion", ctypes.c_double), ("last_eta", ctypes.c_double),
         ("seconds_total", ctypes.c_double), ("seconds_certificate", ctypes.c_double),
         ("seconds_ascent", ctypes.c_double), ("seconds_lasso", ctypes.c_double),
-        ("seconds_slide", ctypes.c_double),
+        ("seconds_slide", ctypes.c_double), ("n_proposals", ctypes.c_int32),
+        ("n_fallbacks", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -656,6 +656,8 @@ int net_propose(sfw_net* n, const float* x, const sfw_dims& vol, float scale, do
 
 }  // namespace sfw
 
+hipStream_t net_stream(const sfw_net* n) { return n->stream; }
+
 using namespace sfw;
 
 extern "C" {

@@ -264,6 +264,9 @@ struct sfw_workspace {
   std::vector<int> prof_kind;
 };
 
+// the stream a proposal network enqueues on (sfw_cnn.hip)
+hipStream_t net_stream(const sfw_net* n);
+
 // the certificate maximum as the final kernel left it in pinned host memory (valid once the
 // stream has been synchronised)
 inline sfw_argmax* pinned_best(sfw_workspace* ws) {

@@ -521,6 +521,8 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
     for (int j = 0; j < o.n_d; ++j)
       if (!(o.d_grid[j] > 0)) return fail(SFW_EINVAL, "opts.d_grid must be > 0");
     if (o.max_iter < 1) return fail(SFW_EINVAL, "opts.max_iter must be >= 1");
+    if (o.proposal && net_stream(o.proposal) != ws->stream)
+      return fail(SFW_EINVAL, "opts.proposal must enqueue on the workspace's stream");
     S.V = (size_t)vol.nx * vol.ny * vol.nz;
     S.plan = plan_psf(ws, vol, psf);
     const auto t0 = Clock::now();
@@ -552,27 +554,48 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
       // residual of the current measure, q = Phi^T r, criterion
       rc = S.cgrad(S.atoms, C, nullptr);
       if (rc) return rc;
-      // step 1: grid maximum of eta, then local ascent
-      auto tc = Clock::now();
-      rc = op_certificate(ws, vol, ws->q, lambda, o.sigma_grid, o.n_sigma, o.d_grid, o.n_d, T,
-                          nullptr);
-      if (rc) return rc;
-      rc = sig_wait(ws, ws->cert_sig);
-      if (rc) return rc;
-      const sfw_argmax best = *pinned_best(ws);
-      S.st.n_certificates++;
-      auto ta = Clock::now();
-      S.st.seconds_certificate += secs(tc, ta);
-      std::vector<double> th = {(double)best.x, (double)best.y, (double)best.z,
-                                (double)o.sigma_grid[best.i_sigma], (double)o.d_grid[best.i_d]};
+      // step 1: a seed (the proposal network's, else the grid maximum of eta), then local
+      // ascent; a proposal whose ascent ends at eta* <= 1 + eta_tol falls back to the grid,
+      // whose ascent decides
+      std::vector<double> th(5);
       double eta_star = 0.0;
-      rc = S.ascent(th, eta_star);
-      if (rc) return rc;
-      S.st.seconds_ascent += secs(ta, Clock::now());
+      bool seeded = false;
+      if (o.proposal) {
+        auto tp = Clock::now();
+        double seed[5], score = 0.0;
+        rc = sfw_net_propose(o.proposal, ws->q, vol, (float)(1.0 / lambda), seed, &score);
+        if (rc) return rc;
+        S.st.n_proposals++;
+        auto ta = Clock::now();
+        S.st.seconds_certificate += secs(tp, ta);
+        th.assign(seed, seed + 5);
+        rc = S.ascent(th, eta_star);
+        if (rc) return rc;
+        S.st.seconds_ascent += secs(ta, Clock::now());
+        seeded = eta_star > 1.0 + o.eta_tol;
+        if (!seeded) S.st.n_fallbacks++;
+      }
+      if (!seeded) {
+        auto tc = Clock::now();
+        rc = op_certificate(ws, vol, ws->q, lambda, o.sigma_grid, o.n_sigma, o.d_grid, o.n_d, T,
+                            nullptr);
+        if (rc) return rc;
+        rc = sig_wait(ws, ws->cert_sig);
+        if (rc) return rc;
+        const sfw_argmax best = *pinned_best(ws);
+        S.st.n_certificates++;
+        auto ta = Clock::now();
+        S.st.seconds_certificate += secs(tc, ta);
+        th = {(double)best.x, (double)best.y, (double)best.z, (double)o.sigma_grid[best.i_sigma],
+              (double)o.d_grid[best.i_d]};
+        rc = S.ascent(th, eta_star);
+        if (rc) return rc;
+        S.st.seconds_ascent += secs(ta, Clock::now());
+      }
       S.st.last_eta = eta_star;
       if (o.verbose)
-        std::fprintf(stderr, "[sfw] k=%d C=%.9g grid=%.6g eta*=%.9g atoms=%d\n", it, C, best.eta,
-                     eta_star, S.k());
+        std::fprintf(stderr, "[sfw] k=%d C=%.9g seed=%s eta*=%.9g atoms=%d\n", it, C,
+                     seeded ? "proposal" : "grid", eta_star, S.k());
       if (eta_star <= 1.0 + o.eta_tol) {
         auto ts = Clock::now();
         if (o.mode == SFW_MODE_BSFW) {  // 2b: final slide, 3b: prune
