@@ -287,7 +287,9 @@ int sfw_net_gradients(sfw_net* net, const float* x, sfw_dims vol, float scale, c
 int sfw_net_train_step(sfw_net* net, const float* x, sfw_dims vol, float scale,
                        const float* atoms, int k, float lr, double* loss);
 /* The proposal: theta (HOST [5]) = (mx, my, mz, sigma, d) at the heatmap maximum (ties to the
- * lowest voxel), score (HOST) = the logit there. Synchronous. */
+ * lowest voxel); the centre is refined along each axis by the peak of the parabola through
+ * log max(h, 1e-3) at the maximum and its two neighbours (at most half a voxel), since the
+ * heatmap is fitted to unit Gaussian blobs. score (HOST) = the heatmap there. Synchronous. */
 int sfw_net_propose(sfw_net* net, const float* x, sfw_dims vol, float scale, double* theta,
                     double* score);
 

@@ -58,46 +58,57 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // Stride-1 convolution of a channels-last bf16 input with CIN channels into NT * 16 output
 // channels, on the grid (Z, Y, X). w: [27][NT*16][CIN] bf16. EPI 0: + bias, ReLU, bf16 out
 // [v][NT*16]; EPI 1: + bias, f32 out [v][4] (channels < cout); EPI 2: times (mask[v][c] > 0)
-// (the ReLU of the layer below), bf16 out [v][NT*16]. A block is four waves, each one segment
-// of 16 voxels along x.
+// (the ReLU of the layer below), bf16 out [v][NT*16]. A block covers 16 x 4 output voxels of
+// one z plane (wave w: row y0 + w): it first stages its input tile, 18 x 6 x 3 voxels with
+// zeros outside the grid, in LDS with coalesced loads (channel rows padded by 4 against bank
+// conflicts), then every wave runs the 27 taps, activations from LDS and weights (a few tens
+// of KB, shared by every block) from the caches.
+constexpr int kConvTX = 16, kConvTY = 4;
 template <int CIN, int NT, int EPI>
 __global__ __launch_bounds__(256) void k_net_conv(const uint16_t* __restrict__ in, int Z, int Y,
                                                   int X, const uint16_t* __restrict__ w,
                                                   const float* __restrict__ bias, int cout,
                                                   void* __restrict__ out,
                                                   const uint16_t* __restrict__ mask) {
-  constexpr int CO = NT * 16;
-  __shared__ uint16_t ws[27 * CO * CIN];
-  for (int e = threadIdx.x; e < 27 * CO * CIN / 4; e += 256)
-    reinterpret_cast<uint2*>(ws)[e] = reinterpret_cast<const uint2*>(w)[e];
+  constexpr int CO = NT * 16, CP = CIN + 4;
+  constexpr int TX = kConvTX + 2, TY = kConvTY + 2, NTILE = 3 * TY * TX;
+  __shared__ uint16_t tile[NTILE * CP];
+  const int nbx = (X + kConvTX - 1) / kConvTX, nby = (Y + kConvTY - 1) / kConvTY;
+  const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, z = blockIdx.x / (nbx * nby);
+  const int x0 = bx * kConvTX, y0 = by * kConvTY;
+  // stage: element (voxel, channel quad) of the tile, 8 bytes each
+  constexpr int QUADS = CIN / 4;
+  for (int e = threadIdx.x; e < NTILE * QUADS; e += 256) {
+    const int cq = e % QUADS, vox = e / QUADS;
+    const int lx = vox % TX, ly = (vox / TX) % TY, lz = vox / (TX * TY);
+    const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z + lz - 1;
+    uint2 val = make_uint2(0u, 0u);
+    if (xx >= 0 && xx < X && yy >= 0 && yy < Y && zz >= 0 && zz < Z)
+      val = *reinterpret_cast<const uint2*>(in + (((size_t)zz * Y + yy) * X + xx) * CIN + 4 * cq);
+    *reinterpret_cast<uint2*>(tile + vox * CP + 4 * cq) = val;
+  }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m = lane & 15, q = lane >> 4;
-  const int nxs = (X + 15) / 16;
-  const long long seg = (long long)blockIdx.x * 4 + wave;
-  const int xs = (int)(seg % nxs);
-  const long long r = seg / nxs;
-  const int y = (int)(r % Y), z = (int)(r / Y);
-  if (z >= Z) return;  // past the grid (no barrier follows)
-  const int x0 = xs * 16;
+  const int y = y0 + wave;
   v4f acc[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
   for (int t = 0; t < 27; ++t) {
-    const int zz = z + t / 9 - 1, yy = y + (t / 3) % 3 - 1, xx = x0 + m + t % 3 - 1;
-    const bool ok = zz >= 0 && zz < Z && yy >= 0 && yy < Y && xx >= 0 && xx < X;
-    const uint16_t* src = in + (((size_t)(ok ? zz : 0) * Y + (ok ? yy : 0)) * X + (ok ? xx : 0)) * CIN;
+    const int lz = t / 9, ly = wave + (t / 3) % 3, lx = m + t % 3;
+    const uint16_t* src = tile + ((lz * TY + ly) * TX + lx) * CP;
 #pragma unroll
     for (int c0 = 0; c0 < CIN; c0 += 16) {
-      v4s a = v4s{0, 0, 0, 0};
-      if (ok) a = *reinterpret_cast<const v4s*>(src + c0 + 4 * q);
+      const v4s a = *reinterpret_cast<const v4s*>(src + c0 + 4 * q);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const v4s b = *reinterpret_cast<const v4s*>(ws + ((t * CO + nt * 16 + m) * CIN + c0 + 4 * q));
+        const v4s b = *reinterpret_cast<const v4s*>(w + ((t * CO + nt * 16 + m) * CIN + c0 + 4 * q));
         acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
       }
     }
   }
+  if (y >= Y) return;
   // lane holds D[4 q + i][m]: voxel x0 + 4 q + i, channel nt * 16 + m
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
@@ -429,10 +440,23 @@ __global__ __launch_bounds__(256) void k_net_argmax(const float* __restrict__ ou
   }
 }
 
+// The heatmap is fitted to unit Gaussian blobs, so log h is quadratic near a centre: the peak
+// of the parabola through the maximum and its two neighbours along each axis (h clamped to
+// 1e-3, offset clamped to half a voxel) refines the centre below the grid step. res[4..6] =
+// the offsets along x, y, z (half-resolution voxels).
+__device__ __forceinline__ double peak_offset(float hm, float h0, float hp) {
+  const double a = log(fmax((double)hm, 1e-3)), b = log(fmax((double)h0, 1e-3)),
+               c = log(fmax((double)hp, 1e-3));
+  const double den = a - 2.0 * b + c;
+  if (!(den < 0.0)) return 0.0;
+  return fmin(0.5, fmax(-0.5, 0.5 * (a - c) / den));
+}
+
 __global__ __launch_bounds__(64) void k_net_argmax_final(const float* __restrict__ pv,
                                                          const long long* __restrict__ pi, int n,
-                                                         const float* __restrict__ out,
-                                                         double* __restrict__ res, SigArgs sig) {
+                                                         const float* __restrict__ out, int Z,
+                                                         int Y, int X, double* __restrict__ res,
+                                                         SigArgs sig) {
   const int lane = threadIdx.x;
   float bv = -INFINITY;
   long long bi = 0x7fffffffffffffffLL;
@@ -455,6 +479,15 @@ __global__ __launch_bounds__(64) void k_net_argmax_final(const float* __restrict
     const bool ok = bi >= 0 && bi != 0x7fffffffffffffffLL && bv > -INFINITY;
     res[2] = ok ? out[bi * 4 + 1] : 0.0;
     res[3] = ok ? out[bi * 4 + 2] : 0.0;
+    res[4] = res[5] = res[6] = 0.0;
+    if (ok) {
+      const int x = (int)(bi % X), y = (int)((bi / X) % Y), z = (int)(bi / ((long long)X * Y));
+      const float h0 = out[bi * 4];
+      const long long sx = 1, sy = X, sz = (long long)X * Y;
+      if (x > 0 && x + 1 < X) res[4] = peak_offset(out[(bi - sx) * 4], h0, out[(bi + sx) * 4]);
+      if (y > 0 && y + 1 < Y) res[5] = peak_offset(out[(bi - sy) * 4], h0, out[(bi + sy) * 4]);
+      if (z > 0 && z + 1 < Z) res[6] = peak_offset(out[(bi - sz) * 4], h0, out[(bi + sz) * 4]);
+    }
   }
   if (lane < 64) __threadfence_system();
   if (lane == 0 && sig.flag) *reinterpret_cast<volatile int*>(sig.flag) = sig.seq;
@@ -508,9 +541,14 @@ NetDims net_dims(const sfw_dims& vol) {
   return d;
 }
 
-unsigned conv_blocks(const NetDims& d) {
+unsigned conv_blocks(const NetDims& d) {  // k_net_conv1: four 16-voxel segments per block
   const long long seg = (long long)((d.X + 15) / 16) * d.Y * d.Z;
   return (unsigned)((seg + 3) / 4);
+}
+
+unsigned tile_blocks(const NetDims& d) {  // k_net_conv: 16 x 4 voxels of one plane per block
+  return (unsigned)((long long)((d.X + kConvTX - 1) / kConvTX) * ((d.Y + kConvTY - 1) / kConvTY) *
+                    d.Z);
 }
 
 int net_check(const sfw_net* net, const float* x, const sfw_dims& vol) {
@@ -538,14 +576,14 @@ hipError_t net_pack(sfw_net* n) {
 }
 
 int net_forward(sfw_net* n, const float* x, const NetDims& d, float scale) {
-  const unsigned nb = conv_blocks(d);
+  const unsigned nb = conv_blocks(d), tb = tile_blocks(d);
   hipLaunchKernelGGL(k_net_conv1, dim3(nb), dim3(256), 0, n->stream, x, d.Zi, d.Yi, d.Xi, scale,
                      d.Z, d.Y, d.X, n->wf1, n->params + kOff1 + kW1, n->a1);
-  hipLaunchKernelGGL((k_net_conv<32, 2, 0>), dim3(nb), dim3(256), 0, n->stream, n->a1, d.Z, d.Y,
+  hipLaunchKernelGGL((k_net_conv<32, 2, 0>), dim3(tb), dim3(256), 0, n->stream, n->a1, d.Z, d.Y,
                      d.X, n->wf2, n->params + kOff2 + kW2, 32, (void*)n->a2, nullptr);
-  hipLaunchKernelGGL((k_net_conv<32, 2, 0>), dim3(nb), dim3(256), 0, n->stream, n->a2, d.Z, d.Y,
+  hipLaunchKernelGGL((k_net_conv<32, 2, 0>), dim3(tb), dim3(256), 0, n->stream, n->a2, d.Z, d.Y,
                      d.X, n->wf3, n->params + kOff3 + kW2, 32, (void*)n->a3, nullptr);
-  hipLaunchKernelGGL((k_net_conv<32, 1, 1>), dim3(nb), dim3(256), 0, n->stream, n->a3, d.Z, d.Y,
+  hipLaunchKernelGGL((k_net_conv<32, 1, 1>), dim3(tb), dim3(256), 0, n->stream, n->a3, d.Z, d.Y,
                      d.X, n->wf4, n->params + kOff4 + kW4, kNetOut, (void*)n->out, nullptr);
   SFW_HIP(hipGetLastError());
   return SFW_OK;
@@ -584,22 +622,22 @@ int net_backprop(sfw_net* n, const float* x, const NetDims& d, float scale, cons
   hipLaunchKernelGGL(k_net_loss_sum, dim3(1), dim3(256), 0, n->stream, n->lpart, (int)lb, V,
                      n->loss);
   SFW_HIP(hipGetLastError());
-  const unsigned nb = conv_blocks(d);
+  const unsigned tb = tile_blocks(d);
   // layer 4
   rc = net_wgrad<32, kNetOutPad>(n, n->a3, n->dout, d, kNetOut, n->grads + kOff4,
                                   n->grads + kOff4 + kW4);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_net_conv<kNetOutPad, 2, 2>), dim3(nb), dim3(256), 0, n->stream, n->dout,
+  hipLaunchKernelGGL((k_net_conv<kNetOutPad, 2, 2>), dim3(tb), dim3(256), 0, n->stream, n->dout,
                      d.Z, d.Y, d.X, n->wb4, nullptr, 32, (void*)n->g3, n->a3);
   // layer 3
   rc = net_wgrad<32, 32>(n, n->a2, n->g3, d, 32, n->grads + kOff3, n->grads + kOff3 + kW2);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_net_conv<32, 2, 2>), dim3(nb), dim3(256), 0, n->stream, n->g3, d.Z, d.Y,
+  hipLaunchKernelGGL((k_net_conv<32, 2, 2>), dim3(tb), dim3(256), 0, n->stream, n->g3, d.Z, d.Y,
                      d.X, n->wb3, nullptr, 32, (void*)n->g2, n->a2);
   // layer 2
   rc = net_wgrad<32, 32>(n, n->a1, n->g2, d, 32, n->grads + kOff2, n->grads + kOff2 + kW2);
   if (rc) return rc;
-  hipLaunchKernelGGL((k_net_conv<32, 2, 2>), dim3(nb), dim3(256), 0, n->stream, n->g2, d.Z, d.Y,
+  hipLaunchKernelGGL((k_net_conv<32, 2, 2>), dim3(tb), dim3(256), 0, n->stream, n->g2, d.Z, d.Y,
                      d.X, n->wb2, nullptr, 32, (void*)n->g1, n->a1);
   // layer 1 (stride 2 from the full-resolution input)
   const int ng = (int)std::max<long long>(1, std::min<long long>(64, (V + 1023) / 1024));
@@ -629,7 +667,7 @@ int net_propose(sfw_net* n, const float* x, const sfw_dims& vol, float scale, do
   if (++n->sig_seq <= 0) n->sig_seq = 1;
   const SigArgs sig{n->sig_flag, nullptr, n->sig_seq};
   hipLaunchKernelGGL(k_net_argmax_final, dim3(1), dim3(64), 0, n->stream, n->apv, n->api, nb,
-                     n->out, n->hres, sig);
+                     n->out, d.Z, d.Y, d.X, n->hres, sig);
   SFW_HIP(hipGetLastError());
   for (unsigned long spins = 1;; ++spins) {
     if (__atomic_load_n(n->sig_flag, __ATOMIC_ACQUIRE) == sig.seq) break;
@@ -645,9 +683,9 @@ int net_propose(sfw_net* n, const float* x, const sfw_dims& vol, float scale, do
   }
   const long long v = (long long)n->hres[1];
   const int ox = (int)(v % d.X), oy = (int)((v / d.X) % d.Y), oz = (int)(v / ((long long)d.X * d.Y));
-  theta[0] = 2.0 * ox;
-  theta[1] = 2.0 * oy;
-  theta[2] = 2.0 * oz;
+  theta[0] = 2.0 * (ox + n->hres[4]);
+  theta[1] = 2.0 * (oy + n->hres[5]);
+  theta[2] = 2.0 * (oz + n->hres[6]);
   theta[3] = n->hres[2];
   theta[4] = n->hres[3];
   *score = n->hres[0];

@@ -123,5 +123,17 @@ def test_training_lowers_the_loss_and_propose_reads_the_maximum(L):
     h = out[..., 0]
     o = np.unravel_index(np.argmax(h), h.shape)  # first maximum in C order
     assert score == pytest.approx(float(h[o]))
-    assert np.array_equal(theta[:3], 2.0 * np.array([o[2], o[1], o[0]]))
+
+    def offset(axis):  # parabola through log max(h, 1e-3) at the maximum and its neighbours
+        if o[axis] == 0 or o[axis] + 1 == h.shape[axis]:
+            return 0.0
+        lo, hi = list(o), list(o)
+        lo[axis] -= 1
+        hi[axis] += 1
+        a, b, c = (np.log(max(float(h[tuple(i)]), 1e-3)) for i in (lo, o, hi))
+        den = a - 2 * b + c
+        return 0.0 if not den < 0 else float(np.clip(0.5 * (a - c) / den, -0.5, 0.5))
+
+    want = [2.0 * (o[2] + offset(2)), 2.0 * (o[1] + offset(1)), 2.0 * (o[0] + offset(0))]
+    assert np.allclose(theta[:3], want, atol=1e-5)
     assert theta[3] == pytest.approx(float(out[o][1])) and theta[4] == pytest.approx(float(out[o][2]))
