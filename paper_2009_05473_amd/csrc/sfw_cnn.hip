@@ -191,11 +191,13 @@ __global__ __launch_bounds__(256) void k_net_conv1(const float* __restrict__ xin
 
 // part[g][t][co][ci] = sum over voxels v of group g of dy[v][co] * x[v + t - 1][ci] (stride 1,
 // zero outside): x bf16 [v][CIN], dy bf16 [v][COP]; block (t, g), 256 threads = COP x CIN/4
-// (co, four ci) pairs at most; voxels staged 64 at a time in LDS.
+// (co, four ci) pairs at most; voxels staged 64 at a time in LDS. The centre tap's blocks also
+// leave the bias partial bpart[g][co] = sum over the group of dy[v][co].
 template <int CIN, int COP>
 __global__ __launch_bounds__(256) void k_net_wgrad(const uint16_t* __restrict__ x,
                                                    const uint16_t* __restrict__ dy, int Z, int Y,
-                                                   int X, int vpg, float* __restrict__ part) {
+                                                   int X, int vpg, float* __restrict__ part,
+                                                   float* __restrict__ bpart) {
   static_assert(COP * CIN / 4 <= 256, "one (co, ci quad) per thread");
   __shared__ float sdy[64][COP];
   __shared__ float sx[64][CIN];
@@ -207,6 +209,8 @@ __global__ __launch_bounds__(256) void k_net_wgrad(const uint16_t* __restrict__ 
   const int co = tid / (CIN / 4), cq = (tid % (CIN / 4)) * 4;
   const bool act = co < COP;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+  const bool centre = t == 13 && cq == 0;
   for (long long vb = v0; vb < v1; vb += 64) {
     __syncthreads();
     for (int e = tid; e < 64 * COP; e += 256) {
@@ -229,44 +233,56 @@ __global__ __launch_bounds__(256) void k_net_wgrad(const uint16_t* __restrict__ 
     if (act) {
       for (int j = 0; j < 64; ++j) {
         const float d = sdy[j][co];
+        bsum += d;
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i] = fmaf(d, sx[j][cq + i], acc[i]);
       }
     }
   }
-  if (act)
+  if (act) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) part[(((size_t)g * 27 + t) * COP + co) * CIN + cq + i] = acc[i];
+    if (centre) bpart[(size_t)g * COP + co] = bsum;
+  }
 }
 
 // The first layer's weight gradient: part[g][t][co] = sum over voxels v of group g of
 // dy[v][co] * scale x[2 v + t - 1] (full-resolution input, zero outside). Block (t, g): 32 co
-// x 8 voxel lanes.
+// x 8 voxel lanes. The centre tap's blocks also leave bpart[g][co] = sum of dy[v][co].
 __global__ __launch_bounds__(256) void k_net_wgrad1(const float* __restrict__ xin, int Zi, int Yi,
                                                     int Xi, float scale,
                                                     const uint16_t* __restrict__ dy, int Z, int Y,
-                                                    int X, int vpg, float* __restrict__ part) {
+                                                    int X, int vpg, float* __restrict__ part,
+                                                    float* __restrict__ bpart) {
   __shared__ float red[8][32];
+  __shared__ float bred[8][32];
   const int t = blockIdx.x, g = blockIdx.y;
   const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
   const long long V = (long long)Z * Y * X;
   const long long v0 = (long long)g * vpg, v1 = std::min(V, v0 + vpg);
   const int co = threadIdx.x & 31, lv = threadIdx.x >> 5;
-  float acc = 0.f;
+  float acc = 0.f, bsum = 0.f;
   for (long long v = v0 + lv; v < v1; v += 8) {
     const int x = (int)(v % X);
     const long long rr = v / X;
     const int y = (int)(rr % Y), z = (int)(rr / Y);
     const int xx = 2 * x + dx, yy = 2 * y + dyy, zz = 2 * z + dz;
+    const float d = bf2f(dy[v * 32 + co]);
+    bsum += d;
     if (xx >= 0 && xx < Xi && yy >= 0 && yy < Yi && zz >= 0 && zz < Zi)
-      acc = fmaf(bf2f(dy[v * 32 + co]), xin[((size_t)zz * Yi + yy) * Xi + xx] * scale, acc);
+      acc = fmaf(d, xin[((size_t)zz * Yi + yy) * Xi + xx] * scale, acc);
   }
   red[lv][co] = acc;
+  bred[lv][co] = bsum;
   __syncthreads();
   if (lv == 0) {
-    float s = 0.f;
-    for (int i = 0; i < 8; ++i) s += red[i][co];
+    float s = 0.f, b = 0.f;
+    for (int i = 0; i < 8; ++i) {
+      s += red[i][co];
+      b += bred[i][co];
+    }
     part[((size_t)g * 27 + t) * 32 + co] = s;
+    if (t == 13) bpart[(size_t)g * 32 + co] = b;
   }
 }
 
@@ -284,19 +300,14 @@ __global__ __launch_bounds__(256) void k_net_wgrad_sum(const float* __restrict__
   grad[e] = s;
 }
 
-__global__ __launch_bounds__(256) void k_net_bgrad(const uint16_t* __restrict__ dy, long long V,
-                                                   int cop, float* __restrict__ bgrad) {
-  __shared__ float red[256];
-  const int co = blockIdx.x;
+// bgrad[co] = sum over the ng groups (in order) of bpart[g][co], co < cout.
+__global__ __launch_bounds__(64) void k_net_bgrad(const float* __restrict__ bpart, int ng, int cop,
+                                                  int cout, float* __restrict__ bgrad) {
+  const int co = threadIdx.x;
+  if (co >= cout) return;
   float s = 0.f;
-  for (long long v = threadIdx.x; v < V; v += 256) s += bf2f(dy[v * cop + co]);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) bgrad[co] = red[0];
+  for (int g = 0; g < ng; ++g) s += bpart[(size_t)g * cop + co];
+  bgrad[co] = s;
 }
 
 // ---------------------------------------------------------------- loss, packing, update
@@ -510,6 +521,7 @@ struct sfw_net {
   uint16_t *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
   float* out = nullptr;
   float* part = nullptr;
+  float* bpart = nullptr;  // [64 groups][32] bias partials
   size_t part_cap = 0;  // floats
   double *lpart = nullptr, *loss = nullptr;
   float* apv = nullptr;
@@ -598,11 +610,11 @@ int net_wgrad(sfw_net* n, const uint16_t* xin, const uint16_t* dy, const NetDims
   const int vpg = (int)((V + ng - 1) / ng);
   if ((size_t)ng * 27 * COP * CIN > n->part_cap) return fail(SFW_EINVAL, "gradient partials too small");
   hipLaunchKernelGGL((k_net_wgrad<CIN, COP>), dim3(27, ng), dim3(256), 0, n->stream, xin, dy, d.Z,
-                     d.Y, d.X, vpg, n->part);
+                     d.Y, d.X, vpg, n->part, n->bpart);
   const int e = cout * CIN * 27;
   hipLaunchKernelGGL(k_net_wgrad_sum, dim3((e + 255) / 256), dim3(256), 0, n->stream, n->part, ng,
                      COP, CIN, cout, CIN, gw);
-  hipLaunchKernelGGL(k_net_bgrad, dim3(cout), dim3(256), 0, n->stream, dy, V, COP, gb);
+  hipLaunchKernelGGL(k_net_bgrad, dim3(1), dim3(64), 0, n->stream, n->bpart, ng, COP, cout, gb);
   SFW_HIP(hipGetLastError());
   return SFW_OK;
 }
@@ -643,10 +655,10 @@ int net_backprop(sfw_net* n, const float* x, const NetDims& d, float scale, cons
   const int ng = (int)std::max<long long>(1, std::min<long long>(64, (V + 1023) / 1024));
   const int vpg = (int)((V + ng - 1) / ng);
   hipLaunchKernelGGL(k_net_wgrad1, dim3(27, ng), dim3(256), 0, n->stream, x, d.Zi, d.Yi, d.Xi,
-                     scale, n->g1, d.Z, d.Y, d.X, vpg, n->part);
+                     scale, n->g1, d.Z, d.Y, d.X, vpg, n->part, n->bpart);
   hipLaunchKernelGGL(k_net_wgrad_sum, dim3((32 * 27 + 255) / 256), dim3(256), 0, n->stream,
                      n->part, ng, 32, 1, 32, 1, n->grads + kOff1);
-  hipLaunchKernelGGL(k_net_bgrad, dim3(32), dim3(256), 0, n->stream, n->g1, V, 32,
+  hipLaunchKernelGGL(k_net_bgrad, dim3(1), dim3(64), 0, n->stream, n->bpart, ng, 32, 32,
                      n->grads + kOff1 + kW1);
   SFW_HIP(hipGetLastError());
   return SFW_OK;
@@ -710,7 +722,7 @@ void sfw_net_destroy(sfw_net* n) {
   if (n->stream) (void)hipStreamSynchronize(n->stream);
   void* dev[] = {n->params, n->grads, n->m1, n->m2, n->wf1, n->wf2, n->wf3, n->wf4, n->wb2,
                  n->wb3, n->wb4, n->a1, n->a2, n->a3, n->dout, n->g1, n->g2, n->g3, n->out,
-                 n->part, n->lpart, n->loss, n->apv, n->api};
+                 n->part, n->bpart, n->lpart, n->loss, n->apv, n->api};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (n->hres) (void)hipHostFree(n->hres);
@@ -759,6 +771,7 @@ int sfw_net_create(sfw_net** out, sfw_dims vol_max, hipStream_t stream) {
   NET_ALLOC(n->dout, vh * kNetOutPad * 2);
   NET_ALLOC(n->out, vh * 4 * sizeof(float));
   NET_ALLOC(n->part, n->part_cap * sizeof(float));
+  NET_ALLOC(n->bpart, 64 * 32 * sizeof(float));
   NET_ALLOC(n->lpart, ((vh + 255) / 256) * sizeof(double));
   NET_ALLOC(n->loss, sizeof(double));
   NET_ALLOC(n->apv, kNetArgBlocks * sizeof(float));
