@@ -110,3 +110,20 @@ def test_last_error_is_thread_local():
     t.join()
     assert seen["msg"] == ""
     assert "workspace" in _lib.last_error()
+
+
+def test_net_entry_points_validate_before_touching_the_gpu():
+    from paper_2009_05473_amd import _lib
+    L = _lib.lib
+    D = _lib.SfwDims
+    # per layer weights [co][ci][3][3][3] then biases: (32, 1), (32, 32), (32, 32), (3, 32)
+    assert L.sfw_net_num_params() == (32 * 27 + 32) + 2 * (32 * 32 * 27 + 32) + (3 * 32 * 27 + 3)
+    assert L.sfw_net_create(None, D(8, 8, 8), None) == _lib.SFW_EINVAL
+    assert L.sfw_net_set_params(None, None, 0) == _lib.SFW_EINVAL
+    assert L.sfw_net_get_params(None, None, 0) == _lib.SFW_EINVAL
+    assert L.sfw_net_forward(None, None, D(8, 8, 8), 1.0, None) == _lib.SFW_EINVAL
+    assert "net" in _lib.last_error()
+    assert L.sfw_net_gradients(None, None, D(8, 8, 8), 1.0, None, 0, None, None) == _lib.SFW_EINVAL
+    assert L.sfw_net_train_step(None, None, D(8, 8, 8), 1.0, None, 0, 1e-3, None) == _lib.SFW_EINVAL
+    assert L.sfw_net_propose(None, None, D(8, 8, 8), 1.0, None, None) == _lib.SFW_EINVAL
+    L.sfw_net_destroy(None)  # no-op

@@ -137,3 +137,24 @@ def test_training_lowers_the_loss_and_propose_reads_the_maximum(L):
     want = [2.0 * (o[2] + offset(2)), 2.0 * (o[1] + offset(1)), 2.0 * (o[0] + offset(0))]
     assert np.allclose(theta[:3], want, atol=1e-5)
     assert theta[3] == pytest.approx(float(out[o][1])) and theta[4] == pytest.approx(float(out[o][2]))
+
+
+def test_net_rejects_bad_inputs(L):
+    say("sfw_net argument checks")
+    with L.Net((8, 8, 8)) as net:
+        with pytest.raises(L.SfwError):
+            net.forward(dev(np.zeros((10, 8, 8))), 1.0)  # beyond vol_max
+        x = dev(np.zeros((8, 8, 8)))
+        with pytest.raises(L.SfwError):
+            net.gradients(x, 1.0, np.zeros((97, 6)))  # more than 96 atoms
+        with pytest.raises(L.SfwError):
+            net.set_params(np.zeros(5))
+        # the solver takes a proposal network only on its workspace's stream
+        other = torch.cuda.Stream()
+        with L.Workspace((8, 8, 8), (3, 3, 3), 8, stream=other) as ws:
+            H = dev(np.full((3, 3, 3), 1.0 / 27))
+            opts = L.default_options()
+            opts.proposal = net.handle.value
+            with pytest.raises(L.SfwError) as e:
+                L.sfw_solve(ws, x, H, 1.0, opts)
+            assert e.value.code == L.SFW_EINVAL and "stream" in str(e.value)
