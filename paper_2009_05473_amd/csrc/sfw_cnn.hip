@@ -12,11 +12,12 @@
 // [27][Ci][Co] with the taps flipped (the data gradient of a stride-1 layer is the
 // convolution of the output gradient with the flipped, transposed kernel).
 //
-// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16bf16_1k: a wave owns 16 consecutive
-// output voxels along x (M) and 16 or 32 output channels (N, one or two tiles); K runs over the
-// taps and 16 input channels at a time (lane l loads the 4 channels 4 (l / 16) .. of voxel
-// l % 16). Weights are staged in LDS per block. Weight gradients are float32 VALU sums over
-// voxel chunks staged in LDS, then a fixed-order sum over chunks.
+// Convolutions are implicit GEMMs on the matrix cores: a wave owns 32 consecutive output voxels
+// along x (M, two tiles) and 16 or 32 output channels (N, one or two tiles); K runs over the
+// taps and the input channels, 32 at a time on gfx950's 16x16x32 bf16 MFMA (16 where the input
+// has 16 channels). Activations are staged in LDS per block, weights read through the caches.
+// Weight gradients are float32 VALU sums over voxel chunks staged in LDS, then a fixed-order
+// sum over chunks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,70 +56,122 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 // ---------------------------------------------------------------- convolutions
 
+// One MFMA step of K = 16 (v_mfma_f32_16x16x16bf16_1k, 4 bf16 per lane) or K = 32 (gfx950's
+// v_mfma_f32_16x16x32_bf16, 8 per lane). Lane l supplies row l % 16 of A and column l % 16 of
+// B with the K slice (l / 16) * K / 4 ..; both share the 16x16 f32 output layout (lane l holds
+// rows 4 (l / 16) .. + 3 of column l % 16).
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8b __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ v4f mma(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mma(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8b, a),
+                                                  __builtin_bit_cast(v8b, b), c, 0, 0, 0);
+}
+template <int CIN> struct FragOf { typedef v8s T; static constexpr int K = 32; };
+template <> struct FragOf<16> { typedef v4s T; static constexpr int K = 16; };
+
 // Stride-1 convolution of a channels-last bf16 input with CIN channels into NT * 16 output
 // channels, on the grid (Z, Y, X). w: [27][NT*16][CIN] bf16. EPI 0: + bias, ReLU, bf16 out
 // [v][NT*16]; EPI 1: + bias, f32 out [v][4] (channels < cout); EPI 2: times (mask[v][c] > 0)
-// (the ReLU of the layer below), bf16 out [v][NT*16]. A block covers 16 x 4 output voxels of
-// one z plane (wave w: row y0 + w): it first stages its input tile, 18 x 6 x 3 voxels with
-// zeros outside the grid, in LDS with coalesced loads (channel rows padded by 4 against bank
-// conflicts), then every wave runs the 27 taps, activations from LDS and weights (a few tens
-// of KB, shared by every block) from the caches.
-constexpr int kConvTX = 16, kConvTY = 4;
+// (the ReLU of the layer below), bf16 out [v][NT*16]. A block covers 32 x 4 output voxels of
+// one z plane (wave w: row y0 + w, two 16-voxel M-tiles that share every weight fragment).
+// It first stages its input tile, 34 x 6 x 3 voxels with zeros outside the grid, in LDS (all
+// of a thread's loads issued before its first store; channel rows padded by one fragment
+// against bank conflicts); then every wave runs the 27 taps, activations from LDS and
+// weights (a few tens of KB, shared by every block) from the caches, each tap's weight
+// fragments loaded two taps ahead so that the cache latency hides behind the MFMAs.
+constexpr int kConvTX = 32, kConvTY = 4;
 template <int CIN, int NT, int EPI>
 __global__ __launch_bounds__(256) void k_net_conv(const uint16_t* __restrict__ in, int Z, int Y,
                                                   int X, const uint16_t* __restrict__ w,
                                                   const float* __restrict__ bias, int cout,
                                                   void* __restrict__ out,
                                                   const uint16_t* __restrict__ mask) {
-  constexpr int CO = NT * 16, CP = CIN + 4;
+  using Frag = typename FragOf<CIN>::T;
+  constexpr int KC = FragOf<CIN>::K, FL = KC / 4;  // K per MFMA; bf16 per lane and fragment
+  constexpr int CO = NT * 16, CP = CIN + FL, KT = CIN / KC;
   constexpr int TX = kConvTX + 2, TY = kConvTY + 2, NTILE = 3 * TY * TX;
-  __shared__ uint16_t tile[NTILE * CP];
+  __shared__ __align__(16) uint16_t tile[NTILE * CP];
   const int nbx = (X + kConvTX - 1) / kConvTX, nby = (Y + kConvTY - 1) / kConvTY;
   const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, z = blockIdx.x / (nbx * nby);
   const int x0 = bx * kConvTX, y0 = by * kConvTY;
-  // stage: element (voxel, channel quad) of the tile, 8 bytes each
-  constexpr int QUADS = CIN / 4;
-  for (int e = threadIdx.x; e < NTILE * QUADS; e += 256) {
-    const int cq = e % QUADS, vox = e / QUADS;
-    const int lx = vox % TX, ly = (vox / TX) % TY, lz = vox / (TX * TY);
-    const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z + lz - 1;
-    uint2 val = make_uint2(0u, 0u);
-    if (xx >= 0 && xx < X && yy >= 0 && yy < Y && zz >= 0 && zz < Z)
-      val = *reinterpret_cast<const uint2*>(in + (((size_t)zz * Y + yy) * X + xx) * CIN + 4 * cq);
-    *reinterpret_cast<uint2*>(tile + vox * CP + 4 * cq) = val;
+  {  // stage: element (voxel, fragment-sized channel group) of the tile
+    constexpr int GR = CIN / FL, NE = NTILE * GR, PER = (NE + 255) / 256;
+    Frag buf[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      buf[i] = Frag{};
+      const int cg = e % GR, vox = e / GR;
+      const int lx = vox % TX, ly = (vox / TX) % TY, lz = vox / (TX * TY);
+      const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z + lz - 1;
+      if (e < NE && xx >= 0 && xx < X && yy >= 0 && yy < Y && zz >= 0 && zz < Z)
+        buf[i] = *reinterpret_cast<const Frag*>(in + (((size_t)zz * Y + yy) * X + xx) * CIN +
+                                                FL * cg);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < NE) *reinterpret_cast<Frag*>(tile + (e / GR) * CP + FL * (e % GR)) = buf[i];
+    }
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m = lane & 15, q = lane >> 4;
   const int y = y0 + wave;
-  v4f acc[NT];
+  v4f acc[2][NT];
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 3
-  for (int t = 0; t < 27; ++t) {
-    const int lz = t / 9, ly = wave + (t / 3) % 3, lx = m + t % 3;
-    const uint16_t* src = tile + ((lz * TY + ly) * TX + lx) * CP;
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int c0 = 0; c0 < CIN; c0 += 16) {
-      const v4s a = *reinterpret_cast<const v4s*>(src + c0 + 4 * q);
+    for (int nt = 0; nt < NT; ++nt) acc[h][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+  // lane (m, q) supplies row m of A (voxel) and column m of B (output channel) with the input
+  // channels kt KC + FL q .. kt KC + FL q + FL - 1
+  const uint16_t* wl = w + m * CIN + FL * q;
+  const uint16_t* al = tile + (wave * TX + m) * CP + FL * q;
+  constexpr int D = 2;  // prefetch distance in taps
+  Frag bq[D + 1][KT][NT];
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const v4s b = *reinterpret_cast<const v4s*>(w + ((t * CO + nt * 16 + m) * CIN + c0 + 4 * q));
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+  for (int s = 0; s < 27 + D; ++s) {
+    if (s < 27) {
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          bq[s % (D + 1)][kt][nt] =
+              *reinterpret_cast<const Frag*>(wl + (s * CO + nt * 16) * CIN + kt * KC);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this tap's MFMAs
+    if (s >= D) {
+      const int t = s - D;
+      const int off = (((t / 9) * TY + (t / 3) % 3) * TX + t % 3) * CP;
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        Frag a[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          a[h] = *reinterpret_cast<const Frag*>(al + off + 16 * h * CP + kt * KC);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) acc[h][nt] = mma(a[h], bq[t % (D + 1)][kt][nt], acc[h][nt]);
       }
     }
   }
   if (y >= Y) return;
-  // lane holds D[4 q + i][m]: voxel x0 + 4 q + i, channel nt * 16 + m
+  // lane holds D[4 q + i][m] of M-tile h: voxel x0 + 16 h + 4 q + i, channel nt * 16 + m
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int c = nt * 16 + m;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int x = x0 + 4 * q + i;
+      const int x = x0 + 16 * h + 4 * q + i;
       if (x >= X) continue;
       const size_t v = ((size_t)z * Y + y) * X + x;
-      float val = acc[nt][i];
+      float val = acc[h][nt][i];
       if (EPI == 0) {
         val = fmaxf(val + bias[c], 0.f);
         reinterpret_cast<uint16_t*>(out)[v * CO + c] = f2bf(val);
@@ -558,7 +611,7 @@ unsigned conv_blocks(const NetDims& d) {  // k_net_conv1: four 16-voxel segments
   return (unsigned)((seg + 3) / 4);
 }
 
-unsigned tile_blocks(const NetDims& d) {  // k_net_conv: 16 x 4 voxels of one plane per block
+unsigned tile_blocks(const NetDims& d) {  // k_net_conv: 32 x 4 voxels of one plane per block
   return (unsigned)((long long)((d.X + kConvTX - 1) / kConvTX) * ((d.Y + kConvTY - 1) / kConvTY) *
                     d.Z);
 }

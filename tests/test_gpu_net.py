@@ -5,7 +5,7 @@ oracle is fed the same bf16-rounded weights and input, so what remains is the ro
 three hidden activations and of the backward gradients to bf16 (half an ulp = 2^-9 relative,
 about 0.2 % RMS per rounding): relative L2 <= 2e-2 for the output and <= 5e-2 for the weight
 gradients, which pass through up to three more roundings. Volumes have ragged x segments (18
-half-resolution voxels for 16-wide waves) and odd sizes.
+half-resolution voxels against 32-voxel tiles) and odd sizes.
 """
 import numpy as np
 import pytest
