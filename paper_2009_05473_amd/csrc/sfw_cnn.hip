@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -53,6 +54,11 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even (f
   return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// four bf16 (two packed words, lower half first) as float32
+__device__ __forceinline__ float4 bf4(uint32_t lo, uint32_t hi) {
+  return make_float4(__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u),
+                     __uint_as_float(hi << 16), __uint_as_float(hi & 0xffff0000u));
+}
 
 // ---------------------------------------------------------------- convolutions
 
@@ -243,65 +249,95 @@ __global__ __launch_bounds__(256) void k_net_conv1(const float* __restrict__ xin
 // ---------------------------------------------------------------- weight gradients
 
 // part[g][t][co][ci] = sum over voxels v of group g of dy[v][co] * x[v + t - 1][ci] (stride 1,
-// zero outside): x bf16 [v][CIN], dy bf16 [v][COP]; block (t, g), 256 threads = COP x CIN/4
-// (co, four ci) pairs at most; voxels staged 64 at a time in LDS. The centre tap's blocks also
-// leave the bias partial bpart[g][co] = sum over the group of dy[v][co].
+// zero outside): x bf16 [v][CIN], dy bf16 [v][COP]; block (t, g). Voxels are staged 64 at a
+// time in LDS as float32 (16-byte loads, coordinates once per voxel); thread (s, co quad, ci
+// quad) accumulates a 4 x 4 tile over the staged voxels j = s, s + S, ..., so each voxel costs
+// it two 16-byte LDS reads for 16 FMAs; the S voxel subsets are summed in order at the end.
+// The centre tap's blocks also leave the bias partial bpart[g][co] = sum over the group of
+// dy[v][co]. Voxel indices fit in int (checked by the launcher).
 template <int CIN, int COP>
 __global__ __launch_bounds__(256) void k_net_wgrad(const uint16_t* __restrict__ x,
                                                    const uint16_t* __restrict__ dy, int Z, int Y,
                                                    int X, int vpg, float* __restrict__ part,
                                                    float* __restrict__ bpart) {
-  static_assert(COP * CIN / 4 <= 256, "one (co, ci quad) per thread");
-  __shared__ float sdy[64][COP];
-  __shared__ float sx[64][CIN];
+  constexpr int TC = COP / 4, TI = CIN / 4, NTILE = TC * TI, S = 256 / NTILE;
+  static_assert(256 % NTILE == 0 && S >= 1, "whole 4 x 4 tiles per block");
+  __shared__ __align__(16) float sdy[64][COP];
+  __shared__ __align__(16) float sx[64][CIN];
+  __shared__ float red[S][NTILE * 16];
+  __shared__ float bred[S][COP];
   const int t = blockIdx.x, g = blockIdx.y;
   const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-  const long long V = (long long)Z * Y * X;
-  const long long v0 = (long long)g * vpg, v1 = std::min(V, v0 + vpg);
+  const int V = Z * Y * X;
+  const int v0 = g * vpg, v1 = min(V, v0 + vpg);
   const int tid = threadIdx.x;
-  const int co = tid / (CIN / 4), cq = (tid % (CIN / 4)) * 4;
-  const bool act = co < COP;
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  float bsum = 0.f;
-  const bool centre = t == 13 && cq == 0;
-  for (long long vb = v0; vb < v1; vb += 64) {
+  const int s = tid / NTILE, ct = (tid % NTILE) / TI, it = tid % TI;
+  float acc[4][4] = {};
+  float bsum[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int vb = v0; vb < v1; vb += 64) {
     __syncthreads();
-    for (int e = tid; e < 64 * COP; e += 256) {
-      const long long v = vb + e / COP;
-      sdy[e / COP][e % COP] = v < v1 ? bf2f(dy[v * COP + e % COP]) : 0.f;
+    for (int e = tid; e < 64 * COP / 8; e += 256) {
+      const int j = e / (COP / 8), c8 = (e % (COP / 8)) * 8, v = vb + j;
+      uint4 raw = make_uint4(0u, 0u, 0u, 0u);
+      if (v < v1) raw = *reinterpret_cast<const uint4*>(dy + (size_t)v * COP + c8);
+      *reinterpret_cast<float4*>(&sdy[j][c8]) = bf4(raw.x, raw.y);
+      *reinterpret_cast<float4*>(&sdy[j][c8 + 4]) = bf4(raw.z, raw.w);
     }
-    for (int e = tid; e < 64 * CIN; e += 256) {
-      const long long v = vb + e / CIN;
-      float val = 0.f;
+    for (int e = tid; e < 64 * CIN / 8; e += 256) {
+      const int j = e / (CIN / 8), c8 = (e % (CIN / 8)) * 8, v = vb + j;
+      uint4 raw = make_uint4(0u, 0u, 0u, 0u);
       if (v < v1) {
-        const int xx = (int)(v % X) + dx;
-        const long long rr = v / X;
-        const int yy = (int)(rr % Y) + dyy, zz = (int)(rr / Y) + dz;
+        const int xx = v % X + dx, r = v / X;
+        const int yy = r % Y + dyy, zz = r / Y + dz;
         if (xx >= 0 && xx < X && yy >= 0 && yy < Y && zz >= 0 && zz < Z)
-          val = bf2f(x[(((size_t)zz * Y + yy) * X + xx) * CIN + e % CIN]);
+          raw = *reinterpret_cast<const uint4*>(x + (((size_t)zz * Y + yy) * X + xx) * CIN + c8);
       }
-      sx[e / CIN][e % CIN] = val;
+      *reinterpret_cast<float4*>(&sx[j][c8]) = bf4(raw.x, raw.y);
+      *reinterpret_cast<float4*>(&sx[j][c8 + 4]) = bf4(raw.z, raw.w);
     }
     __syncthreads();
-    if (act) {
-      for (int j = 0; j < 64; ++j) {
-        const float d = sdy[j][co];
-        bsum += d;
+    for (int j = s; j < 64; j += S) {
+      const float4 d = *reinterpret_cast<const float4*>(&sdy[j][4 * ct]);
+      const float4 xv = *reinterpret_cast<const float4*>(&sx[j][4 * it]);
+      const float dd[4] = {d.x, d.y, d.z, d.w}, xa[4] = {xv.x, xv.y, xv.z, xv.w};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = fmaf(d, sx[j][cq + i], acc[i]);
+      for (int a = 0; a < 4; ++a) {
+        bsum[a] += dd[a];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(dd[a], xa[b], acc[a][b]);
       }
     }
   }
-  if (act) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) part[(((size_t)g * 27 + t) * COP + co) * CIN + cq + i] = acc[i];
-    if (centre) bpart[(size_t)g * COP + co] = bsum;
-  }
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) red[s][(tid % NTILE) * 16 + a * 4 + b] = acc[a][b];
+  if (it == 0)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) bred[s][4 * ct + a] = bsum[a];
+  __syncthreads();
+  if (s != 0) return;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      float sum = 0.f;
+      for (int k = 0; k < S; ++k) sum += red[k][tid * 16 + a * 4 + b];
+      part[(((size_t)g * 27 + t) * COP + 4 * ct + a) * CIN + 4 * it + b] = sum;
+    }
+  if (t == 13 && it == 0)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      float sum = 0.f;
+      for (int k = 0; k < S; ++k) sum += bred[k][4 * ct + a];
+      bpart[(size_t)g * COP + 4 * ct + a] = sum;
+    }
 }
 
 // The first layer's weight gradient: part[g][t][co] = sum over voxels v of group g of
 // dy[v][co] * scale x[2 v + t - 1] (full-resolution input, zero outside). Block (t, g): 32 co
-// x 8 voxel lanes. The centre tap's blocks also leave bpart[g][co] = sum of dy[v][co].
+// x 8 voxel lanes. The centre tap's blocks also leave bpart[g][co] = sum of dy[v][co]. Voxel
+// indices fit in int (checked by the launcher).
 __global__ __launch_bounds__(256) void k_net_wgrad1(const float* __restrict__ xin, int Zi, int Yi,
                                                     int Xi, float scale,
                                                     const uint16_t* __restrict__ dy, int Z, int Y,
@@ -311,16 +347,16 @@ __global__ __launch_bounds__(256) void k_net_wgrad1(const float* __restrict__ xi
   __shared__ float bred[8][32];
   const int t = blockIdx.x, g = blockIdx.y;
   const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-  const long long V = (long long)Z * Y * X;
-  const long long v0 = (long long)g * vpg, v1 = std::min(V, v0 + vpg);
+  const int V = Z * Y * X;
+  const int v0 = g * vpg, v1 = min(V, v0 + vpg);
   const int co = threadIdx.x & 31, lv = threadIdx.x >> 5;
   float acc = 0.f, bsum = 0.f;
-  for (long long v = v0 + lv; v < v1; v += 8) {
-    const int x = (int)(v % X);
-    const long long rr = v / X;
-    const int y = (int)(rr % Y), z = (int)(rr / Y);
+#pragma unroll 4
+  for (int v = v0 + lv; v < v1; v += 8) {
+    const int x = v % X, rr = v / X;
+    const int y = rr % Y, z = rr / Y;
     const int xx = 2 * x + dx, yy = 2 * y + dyy, zz = 2 * z + dz;
-    const float d = bf2f(dy[v * 32 + co]);
+    const float d = bf2f(dy[(size_t)v * 32 + co]);
     bsum += d;
     if (xx >= 0 && xx < Xi && yy >= 0 && yy < Yi && zz >= 0 && zz < Zi)
       acc = fmaf(d, xin[((size_t)zz * Yi + yy) * Xi + xx] * scale, acc);
@@ -662,6 +698,7 @@ int net_wgrad(sfw_net* n, const uint16_t* xin, const uint16_t* dy, const NetDims
   const int ng = (int)std::max<long long>(1, std::min<long long>(64, (V + 1023) / 1024));
   const int vpg = (int)((V + ng - 1) / ng);
   if ((size_t)ng * 27 * COP * CIN > n->part_cap) return fail(SFW_EINVAL, "gradient partials too small");
+  if (V > INT_MAX - 64) return fail(SFW_EINVAL, "half-resolution volume too large");
   hipLaunchKernelGGL((k_net_wgrad<CIN, COP>), dim3(27, ng), dim3(256), 0, n->stream, xin, dy, d.Z,
                      d.Y, d.X, vpg, n->part, n->bpart);
   const int e = cout * CIN * 27;
@@ -705,6 +742,7 @@ int net_backprop(sfw_net* n, const float* x, const NetDims& d, float scale, cons
   hipLaunchKernelGGL((k_net_conv<32, 2, 2>), dim3(tb), dim3(256), 0, n->stream, n->g2, d.Z, d.Y,
                      d.X, n->wb2, nullptr, 32, (void*)n->g1, n->a1);
   // layer 1 (stride 2 from the full-resolution input)
+  if (V > INT_MAX - 64) return fail(SFW_EINVAL, "half-resolution volume too large");
   const int ng = (int)std::max<long long>(1, std::min<long long>(64, (V + 1023) / 1024));
   const int vpg = (int)((V + ng - 1) / ng);
   hipLaunchKernelGGL(k_net_wgrad1, dim3(27, ng), dim3(256), 0, n->stream, x, d.Zi, d.Yi, d.Xi,
