@@ -351,15 +351,20 @@ __global__ __launch_bounds__(256) void k_net_wgrad1(const float* __restrict__ xi
   const int v0 = g * vpg, v1 = min(V, v0 + vpg);
   const int co = threadIdx.x & 31, lv = threadIdx.x >> 5;
   float acc = 0.f, bsum = 0.f;
+  // the voxel's coordinates, divided out once and then stepped by 8 voxels
+  int x = (v0 + lv) % X, y = ((v0 + lv) / X) % Y, z = (v0 + lv) / (X * Y);
 #pragma unroll 4
   for (int v = v0 + lv; v < v1; v += 8) {
-    const int x = v % X, rr = v / X;
-    const int y = rr % Y, z = rr / Y;
     const int xx = 2 * x + dx, yy = 2 * y + dyy, zz = 2 * z + dz;
     const float d = bf2f(dy[(size_t)v * 32 + co]);
     bsum += d;
     if (xx >= 0 && xx < Xi && yy >= 0 && yy < Yi && zz >= 0 && zz < Zi)
       acc = fmaf(d, xin[((size_t)zz * Yi + yy) * Xi + xx] * scale, acc);
+    for (x += 8; x >= X; x -= X)
+      if (++y == Y) {
+        y = 0;
+        ++z;
+      }
   }
   red[lv][co] = acc;
   bred[lv][co] = bsum;
@@ -385,6 +390,7 @@ __global__ __launch_bounds__(256) void k_net_wgrad_sum(const float* __restrict__
   if (e >= cout * cin * 27) return;
   const int t = e % 27, ci = (e / 27) % cin, co = e / (27 * cin);
   float s = 0.f;
+#pragma unroll 8
   for (int g = 0; g < ng; ++g) s += part[(((size_t)g * 27 + t) * cop + co) * cinp + ci];
   grad[e] = s;
 }
@@ -395,6 +401,7 @@ __global__ __launch_bounds__(64) void k_net_bgrad(const float* __restrict__ bpar
   const int co = threadIdx.x;
   if (co >= cout) return;
   float s = 0.f;
+#pragma unroll 8
   for (int g = 0; g < ng; ++g) s += bpart[(size_t)g * cop + co];
   bgrad[co] = s;
 }
