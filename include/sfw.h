@@ -89,7 +89,8 @@ typedef struct {
                                         grid maximum of eta. Else a trained proposal network
                                         (on the workspace's stream) seeds it; when the ascent
                                         from that seed ends at eta* <= 1 + eta_tol, the grid
-                                        maximum seeds a second ascent, which decides */
+                                        maximum seeds a second ascent, which decides, and
+                                        the grid seeds the rest of that solve */
 } sfw_options;
 
 /* Per-solve statistics (host memory). */
@@ -105,7 +106,7 @@ typedef struct {
   double last_eta;           /* eta* of the last iteration */
   double seconds_total, seconds_certificate, seconds_ascent, seconds_lasso, seconds_slide;
   int32_t n_proposals;       /* seeds from the proposal network */
-  int32_t n_fallbacks;       /* of which the grid maximum had to replace */
+  int32_t n_fallbacks;       /* of which the grid maximum had to replace (0 or 1) */
 } sfw_stats;
 
 /* ---------------------------------------------------------------- lifecycle */

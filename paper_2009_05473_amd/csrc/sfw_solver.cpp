@@ -548,6 +548,7 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
 
     const float T = o.trunc_T > 0 ? o.trunc_T : 12.0f;
     bool converged = false;
+    bool use_net = o.proposal != nullptr;
     int it = 0;
     double C = 0.0;
     for (it = 1; it <= o.max_iter; ++it) {
@@ -556,13 +557,16 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
       if (rc) return rc;
       // step 1: a seed (the proposal network's, else the grid maximum of eta), then local
       // ascent; a proposal whose ascent ends at eta* <= 1 + eta_tol falls back to the grid,
-      // whose ascent decides
+      // whose ascent decides. After such a rejection the grid seeds the rest of the solve:
+      // the network's later maxima are then almost always atoms already found (eta = 1).
       std::vector<double> th(5);
       double eta_star = 0.0;
       bool seeded = false;
-      if (o.proposal) {
+      double score = 0.0, eta_prop = 0.0;
+      long long evals_prop = 0;
+      if (use_net) {
         auto tp = Clock::now();
-        double seed[5], score = 0.0;
+        double seed[5];
         rc = sfw_net_propose(o.proposal, ws->q, vol, (float)(1.0 / lambda), seed, &score);
         if (rc) return rc;
         S.st.n_proposals++;
@@ -573,7 +577,12 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
         if (rc) return rc;
         S.st.seconds_ascent += secs(ta, Clock::now());
         seeded = eta_star > 1.0 + o.eta_tol;
-        if (!seeded) S.st.n_fallbacks++;
+        if (!seeded) {
+          S.st.n_fallbacks++;
+          use_net = false;
+        }
+        eta_prop = eta_star;
+        evals_prop = S.st.n_eval_eta;
       }
       if (!seeded) {
         auto tc = Clock::now();
@@ -594,8 +603,11 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
       }
       S.st.last_eta = eta_star;
       if (o.verbose)
-        std::fprintf(stderr, "[sfw] k=%d C=%.9g seed=%s eta*=%.9g atoms=%d\n", it, C,
-                     seeded ? "proposal" : "grid", eta_star, S.k());
+        std::fprintf(stderr,
+                     "[sfw] k=%d C=%.9g seed=%s eta*=%.9g atoms=%d evals=%lld score=%.4g "
+                     "proposal_eta*=%.6g proposal_evals=%lld\n",
+                     it, C, seeded ? "proposal" : "grid", eta_star, S.k(),
+                     (long long)S.st.n_eval_eta, score, eta_prop, evals_prop);
       if (eta_star <= 1.0 + o.eta_tol) {
         auto ts = Clock::now();
         if (o.mode == SFW_MODE_BSFW) {  // 2b: final slide, 3b: prune

@@ -4,9 +4,10 @@ The network is trained on the GPU by sfw_net_train_step (the library's forward a
 kernels) on freshly drawn volumes, then BSFW runs from mu = 0 on held-out 128x128x64 volumes
 of 50 atoms (seeds disjoint from training) with the grid maximum and with the network as step
 1's seed. The grid certificate remains the judge (a proposal whose ascent ends at eta* <= 1
-falls back to it), so the learned solver must recover the same number of atoms at the same
-accuracy; the test prints the times of both, which bench.py --proposal reports at a larger
-scale.
+falls back to it, and the grid seeds the rest of that solve), so the learned solver must
+recover the same number of atoms at the same accuracy while computing far fewer grid
+certificates; the test prints the times of both, which bench.py --proposal reports at a
+larger scale.
 """
 import numpy as np
 import pytest
@@ -41,5 +42,8 @@ def test_trained_proposal_matches_grid_recovery(L):
         assert g["status"] == l_["status"] == L.SFW_OK
         assert l_["atoms"] == g["atoms"]
         assert l_["max_centre_error"] <= g["max_centre_error"] + 0.05
-        assert l_["proposals"] > 0 and l_["fallbacks"] < 0.25 * l_["proposals"]
-        assert l_["certificates"] == l_["fallbacks"]
+        # every iteration's step 1 is a proposal, a rejected proposal and a certificate, or
+        # (after the one rejection) a certificate; the network spares most certificates
+        assert l_["fallbacks"] <= 1
+        assert l_["proposals"] + l_["certificates"] - l_["fallbacks"] == l_["iterations"]
+        assert l_["certificates"] < 0.5 * g["certificates"]
