@@ -6,7 +6,7 @@ of 50 atoms (seeds disjoint from training) with the grid maximum and with the ne
 1's seed. The grid certificate remains the judge (a proposal whose ascent ends at eta* <= 1
 falls back to it, and the grid seeds the rest of that solve), so the learned solver must
 recover the same number of atoms at the same accuracy while computing far fewer grid
-certificates; the test prints the times of both, which bench.py --proposal reports at a
+certificates; the test prints the times of both, which bench.py reports at a
 larger scale.
 """
 import numpy as np
