@@ -84,11 +84,15 @@ template <> struct FragOf<16> { typedef v4s T; static constexpr int K = 16; };
 // (the ReLU of the layer below), bf16 out [v][NT*16]. A block covers 32 x 4 output voxels of
 // one z plane (wave w: row y0 + w, two 16-voxel M-tiles that share every weight fragment).
 // It first stages its input tile, 34 x 6 x 3 voxels with zeros outside the grid, in LDS (all
-// of a thread's loads issued before its first store; channel rows padded by one fragment
-// against bank conflicts); then every wave runs the 27 taps, activations from LDS and
+// of a thread's loads issued before its first store; channel chunks swizzled against bank
+// conflicts); then every wave runs the 27 taps, activations from LDS and
 // weights (a few tens of KB, shared by every block) from the caches, each tap's weight
 // fragments loaded two taps ahead so that the cache latency hides behind the MFMAs.
 constexpr int kConvTX = 32, kConvTY = 4;
+// LDS position of a voxel's fragment-sized channel chunk g (of four): rows are not padded, the
+// chunk index is XORed with bits 2..3 of the voxel index, so any 16 consecutive voxels' chunk
+// g fall in 16 distinct 16-byte bank groups (and the tile fits four blocks per CU).
+__device__ __forceinline__ int swz(int g, int vox) { return g ^ ((vox >> 2) & 3); }
 template <int CIN, int NT, int EPI>
 __global__ __launch_bounds__(256) void k_net_conv(const uint16_t* __restrict__ in, int Z, int Y,
                                                   int X, const uint16_t* __restrict__ w,
@@ -97,14 +101,15 @@ __global__ __launch_bounds__(256) void k_net_conv(const uint16_t* __restrict__ i
                                                   const uint16_t* __restrict__ mask) {
   using Frag = typename FragOf<CIN>::T;
   constexpr int KC = FragOf<CIN>::K, FL = KC / 4;  // K per MFMA; bf16 per lane and fragment
-  constexpr int CO = NT * 16, CP = CIN + FL, KT = CIN / KC;
+  constexpr int CO = NT * 16, CP = CIN, KT = CIN / KC, GR = CIN / FL;
+  static_assert(KT == 1 && GR == 4, "one K step of four fragment-sized chunks per voxel");
   constexpr int TX = kConvTX + 2, TY = kConvTY + 2, NTILE = 3 * TY * TX;
   __shared__ __align__(16) uint16_t tile[NTILE * CP];
   const int nbx = (X + kConvTX - 1) / kConvTX, nby = (Y + kConvTY - 1) / kConvTY;
   const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, z = blockIdx.x / (nbx * nby);
   const int x0 = bx * kConvTX, y0 = by * kConvTY;
   {  // stage: element (voxel, fragment-sized channel group) of the tile
-    constexpr int GR = CIN / FL, NE = NTILE * GR, PER = (NE + 255) / 256;
+    constexpr int NE = NTILE * GR, PER = (NE + 255) / 256;
     Frag buf[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -120,7 +125,10 @@ __global__ __launch_bounds__(256) void k_net_conv(const uint16_t* __restrict__ i
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + 256 * i;
-      if (e < NE) *reinterpret_cast<Frag*>(tile + (e / GR) * CP + FL * (e % GR)) = buf[i];
+      if (e < NE) {
+        const int vox = e / GR;
+        *reinterpret_cast<Frag*>(tile + vox * CP + FL * swz(e % GR, vox)) = buf[i];
+      }
     }
   }
   __syncthreads();
@@ -135,7 +143,7 @@ __global__ __launch_bounds__(256) void k_net_conv(const uint16_t* __restrict__ i
   // lane (m, q) supplies row m of A (voxel) and column m of B (output channel) with the input
   // channels kt KC + FL q .. kt KC + FL q + FL - 1
   const uint16_t* wl = w + m * CIN + FL * q;
-  const uint16_t* al = tile + (wave * TX + m) * CP + FL * q;
+  const int vl = wave * TX + m;  // the lane's voxel in the tile at tap 0, M-tile 0
   constexpr int D = 2;  // prefetch distance in taps
   Frag bq[D + 1][KT][NT];
 #pragma unroll
@@ -151,13 +159,15 @@ __global__ __launch_bounds__(256) void k_net_conv(const uint16_t* __restrict__ i
     __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this tap's MFMAs
     if (s >= D) {
       const int t = s - D;
-      const int off = (((t / 9) * TY + (t / 3) % 3) * TX + t % 3) * CP;
+      const int offv = ((t / 9) * TY + (t / 3) % 3) * TX + t % 3;
 #pragma unroll
       for (int kt = 0; kt < KT; ++kt) {
         Frag a[2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-          a[h] = *reinterpret_cast<const Frag*>(al + off + 16 * h * CP + kt * KC);
+        for (int h = 0; h < 2; ++h) {
+          const int vox = vl + offv + 16 * h;
+          a[h] = *reinterpret_cast<const Frag*>(tile + vox * CP + FL * swz(q, vox));
+        }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
