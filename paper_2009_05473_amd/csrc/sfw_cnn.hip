@@ -12,8 +12,8 @@
 // [27][Ci][Co] with the taps flipped (the data gradient of a stride-1 layer is the
 // convolution of the output gradient with the flipped, transposed kernel).
 //
-// Convolutions are implicit GEMMs on the matrix cores: a wave owns 32 consecutive output voxels
-// along x (M, two tiles) and 16 or 32 output channels (N, one or two tiles); K runs over the
+// Convolutions are implicit GEMMs on the matrix cores: a wave owns 64 consecutive output voxels
+// along x (M, four tiles) and 16 or 32 output channels (N, one or two tiles); K runs over the
 // taps and the input channels, 32 at a time on gfx950's 16x16x32 bf16 MFMA (16 where the input
 // has 16 channels). Activations are staged in LDS per block, weights read through the caches.
 // Weight gradients are float32 VALU sums over voxel chunks staged in LDS, then a fixed-order
@@ -81,17 +81,17 @@ template <> struct FragOf<16> { typedef v4s T; static constexpr int K = 16; };
 // Stride-1 convolution of a channels-last bf16 input with CIN channels into NT * 16 output
 // channels, on the grid (Z, Y, X). w: [27][NT*16][CIN] bf16. EPI 0: + bias, ReLU, bf16 out
 // [v][NT*16]; EPI 1: + bias, f32 out [v][4] (channels < cout); EPI 2: times (mask[v][c] > 0)
-// (the ReLU of the layer below), bf16 out [v][NT*16]. A block covers 32 x 4 output voxels of
-// one z plane (wave w: row y0 + w, two 16-voxel M-tiles that share every weight fragment).
-// It first stages its input tile, 34 x 6 x 3 voxels with zeros outside the grid, in LDS (all
+// (the ReLU of the layer below), bf16 out [v][NT*16]. A block covers 64 x 4 output voxels of
+// one z plane (wave w: row y0 + w, four 16-voxel M-tiles that share every weight fragment).
+// It first stages its input tile, 66 x 6 x 3 voxels with zeros outside the grid, in LDS (all
 // of a thread's loads issued before its first store; channel chunks swizzled against bank
 // conflicts); then every wave runs the 27 taps, activations from LDS and
 // weights (a few tens of KB, shared by every block) from the caches, each tap's weight
 // fragments loaded two taps ahead so that the cache latency hides behind the MFMAs.
-constexpr int kConvTX = 32, kConvTY = 4;
+constexpr int kConvTX = 64, kConvTY = 4, kConvMT = kConvTX / 16;
 // LDS position of a voxel's fragment-sized channel chunk g (of four): rows are not padded, the
 // chunk index is XORed with bits 2..3 of the voxel index, so any 16 consecutive voxels' chunk
-// g fall in 16 distinct 16-byte bank groups (and the tile fits four blocks per CU).
+// g fall in 16 distinct 16-byte bank groups (and two 76 KB tiles fit per CU).
 __device__ __forceinline__ int swz(int g, int vox) { return g ^ ((vox >> 2) & 3); }
 template <int CIN, int NT, int EPI>
 __global__ __launch_bounds__(256) void k_net_conv(const uint16_t* __restrict__ in, int Z, int Y,
@@ -135,9 +135,9 @@ __global__ __launch_bounds__(256) void k_net_conv(const uint16_t* __restrict__ i
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m = lane & 15, q = lane >> 4;
   const int y = y0 + wave;
-  v4f acc[2][NT];
+  v4f acc[kConvMT][NT];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < kConvMT; ++h)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[h][nt] = v4f{0.f, 0.f, 0.f, 0.f};
   // lane (m, q) supplies row m of A (voxel) and column m of B (output channel) with the input
@@ -162,23 +162,24 @@ __global__ __launch_bounds__(256) void k_net_conv(const uint16_t* __restrict__ i
       const int offv = ((t / 9) * TY + (t / 3) % 3) * TX + t % 3;
 #pragma unroll
       for (int kt = 0; kt < KT; ++kt) {
-        Frag a[2];
+        Frag a[kConvMT];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < kConvMT; ++h) {
           const int vox = vl + offv + 16 * h;
           a[h] = *reinterpret_cast<const Frag*>(tile + vox * CP + FL * swz(q, vox));
         }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-          for (int h = 0; h < 2; ++h) acc[h][nt] = mma(a[h], bq[t % (D + 1)][kt][nt], acc[h][nt]);
+          for (int h = 0; h < kConvMT; ++h)
+            acc[h][nt] = mma(a[h], bq[t % (D + 1)][kt][nt], acc[h][nt]);
       }
     }
   }
   if (y >= Y) return;
   // lane holds D[4 q + i][m] of M-tile h: voxel x0 + 16 h + 4 q + i, channel nt * 16 + m
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < kConvMT; ++h)
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int c = nt * 16 + m;
@@ -664,7 +665,7 @@ unsigned conv_blocks(const NetDims& d) {  // k_net_conv1: four 16-voxel segments
   return (unsigned)((seg + 3) / 4);
 }
 
-unsigned tile_blocks(const NetDims& d) {  // k_net_conv: 32 x 4 voxels of one plane per block
+unsigned tile_blocks(const NetDims& d) {  // k_net_conv: 64 x 4 voxels of one plane per block
   return (unsigned)((long long)((d.X + kConvTX - 1) / kConvTX) * ((d.Y + kConvTY - 1) / kConvTY) *
                     d.Z);
 }
