@@ -4,8 +4,9 @@ The library computes with bf16 weights, inputs and activations (float32 accumula
 oracle is fed the same bf16-rounded weights and input, so what remains is the rounding of the
 three hidden activations and of the backward gradients to bf16 (half an ulp = 2^-9 relative,
 about 0.2 % RMS per rounding): relative L2 <= 2e-2 for the output and <= 5e-2 for the weight
-gradients, which pass through up to three more roundings. Volumes have ragged x segments (18
-half-resolution voxels against 32-voxel tiles) and odd sizes.
+gradients, which pass through up to three more roundings. Volumes have ragged tiles (18 and 75
+half-resolution voxels along x against 64-voxel tiles, 6 and 10 along y against 4-row tiles),
+odd sizes and a tiny 3 x 4 x 5 case.
 """
 import numpy as np
 import pytest
@@ -64,7 +65,7 @@ def oracle_params(params):
     return [(bf16(w), np.asarray(b, dtype=np.float32).astype(np.float64)) for w, b in params]
 
 
-@pytest.mark.parametrize("shape", [(12, 20, 36), (7, 9, 33)])
+@pytest.mark.parametrize("shape", [(12, 20, 36), (7, 9, 33), (6, 12, 150), (3, 4, 5)])
 def test_forward_parity(L, shape):
     rng, params, x = params_and_input(11, shape)
     scale = 0.7
@@ -82,12 +83,14 @@ def test_forward_parity(L, shape):
         assert rel_l2(got[c], want[c]) <= 3e-2, c
 
 
-def test_gradients_parity(L):
-    shape = (12, 20, 36)
+@pytest.mark.parametrize("shape", [(12, 20, 36), (6, 12, 150)])
+def test_gradients_parity(L, shape):
     rng, params, x = params_and_input(12, shape)
     scale = 0.5
-    atoms = np.column_stack([rng.uniform(0.5, 2, 5), rng.uniform(2, 33, 5), rng.uniform(2, 18, 5),
-                             rng.uniform(1, 10, 5), rng.uniform(1, 2, 5), rng.uniform(1.5, 2.5, 5)])
+    Z, Y, X = shape
+    atoms = np.column_stack([rng.uniform(0.5, 2, 5), rng.uniform(1, X - 2, 5),
+                             rng.uniform(1, Y - 2, 5), rng.uniform(0.5, Z - 1.5, 5),
+                             rng.uniform(1, 2, 5), rng.uniform(1.5, 2.5, 5)])
     say("sfw_net_gradients", shape)
     with L.Net(shape) as net:
         net.set_params(flat(params))
