@@ -304,7 +304,7 @@ def proposal_run(L, shape, steps, volumes):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); it has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -2,7 +2,7 @@
 // between) that read the certificate-scaled adjoint x = Phi^T r / lambda and predict, on the
 // half-resolution grid, a centre heatmap logit and the sigma and d of the next atom (step 1 of
 // Algorithms 1 and 2 takes the grid maximum instead; the network is a proposal that the
-// certificate then judges). Training and inference run on these kernels only.
+// certificate then accepts or rejects). Training and inference run on these kernels only.
 //
 // Layouts: activations bf16 channels-last [z][y][x][C] (C = 32; the gradient of the output
 // layer has 16 channels, 3 used); the output layer f32 [z][y][x][4] (heatmap logit, sigma, d,

@@ -3,7 +3,7 @@
 Step 1 of Algorithms 1 and 2 seeds the local ascent at the grid maximum of the certificate.
 The proposal network predicts that seed instead from x = Phi^T r / lambda (see include/sfw.h);
 the solver falls back to the grid whenever the ascent from the network's seed ends at
-eta* <= 1, so the grid stays the judge of the stopping rule.
+eta* <= 1, so the grid certificate still decides the stopping rule.
 
 A training sample imitates what step 1 sees inside a solve: a volume holding N ~ U{n_lo..n_hi}
 atoms drawn like the 128x128x64 workload's (centres at least 3 voxels apart, sigma ~ U[1, 2],

@@ -3,7 +3,7 @@
 The network is trained on the GPU by sfw_net_train_step (the library's forward and backward
 kernels) on freshly drawn volumes, then BSFW runs from mu = 0 on held-out 128x128x64 volumes
 of 50 atoms (seeds disjoint from training) with the grid maximum and with the network as step
-1's seed. The grid certificate remains the judge (a proposal whose ascent ends at eta* <= 1
+1's seed. The grid certificate still decides (a proposal whose ascent ends at eta* <= 1
 falls back to it, and the grid seeds the rest of that solve), so the learned solver must
 recover the same number of atoms at the same accuracy while computing far fewer grid
 certificates; the test prints the times of both, which bench.py reports at a
