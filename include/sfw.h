@@ -91,6 +91,14 @@ typedef struct {
                                         from that seed ends at eta* <= 1 + eta_tol, the grid
                                         maximum seeds a second ascent, which decides, and
                                         the grid seeds the rest of that solve */
+  const sfw_atom* init_atoms;        /* HOST [n_init] or NULL (default, mu = 0): the measure
+                                        the solve starts from (algorithms 1 and 2 start at
+                                        mu = 0; a measure returned by an earlier solve, e.g.
+                                        one stopped by max_iter, resumes it). w >= 0,
+                                        sigma > 0, d > 0, all finite, else SFW_EINVAL;
+                                        centres, sigma and d are clipped into the box and
+                                        zero weights pruned before the first iteration */
+  int32_t n_init;                    /* atoms in init_atoms, 0..max_atoms, default 0 */
 } sfw_options;
 
 /* Per-solve statistics (host memory). */
@@ -107,6 +115,10 @@ typedef struct {
   double seconds_total, seconds_certificate, seconds_ascent, seconds_lasso, seconds_slide;
   int32_t n_proposals;       /* seeds from the proposal network */
   int32_t n_fallbacks;       /* of which the grid maximum had to replace (0 or 1) */
+  int32_t n_atoms_descent;   /* atoms after the final descent and pruning, before the two
+                                float32 safeguards below */
+  int32_t n_merged;          /* pairs fused by the merge safeguard (0 when disabled) */
+  int32_t n_slivers;         /* masses dropped by the sliver safeguard (0 when disabled) */
 } sfw_stats;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -290,7 +302,9 @@ int sfw_net_train_step(sfw_net* net, const float* x, sfw_dims vol, float scale,
 /* The proposal: theta (HOST [5]) = (mx, my, mz, sigma, d) at the heatmap maximum (ties to the
  * lowest voxel); the centre is refined along each axis by the peak of the parabola through
  * log max(h, 1e-3) at the maximum and its two neighbours (at most half a voxel), since the
- * heatmap is fitted to unit Gaussian blobs. score (HOST) = the heatmap there. Synchronous. */
+ * heatmap is fitted to unit Gaussian blobs. score (HOST) = the heatmap there. When no heatmap
+ * value is finite (a diverged network) there is no proposal: score = -INFINITY, theta = NaN,
+ * and the solver seeds that iteration at the grid maximum instead. Synchronous. */
 int sfw_net_propose(sfw_net* net, const float* x, sfw_dims vol, float scale, double* theta,
                     double* score);
 

@@ -403,7 +403,7 @@ class SolveResult:
 
 
 def solve(y, psf, lam, sigma_grid, d_grid, bounds, mode="BSFW", max_iter=200, T=T_TRUNC,
-          eta_tol=ETA_TOL, ascent_opts=None, slide_opts=None):
+          eta_tol=ETA_TOL, ascent_opts=None, slide_opts=None, log=None):
     """SFW (algorithm 1) or BSFW (algorithm 2) from mu = 0.
 
     Each iteration: residual of the current measure, certificate grid maximum,
@@ -411,6 +411,7 @@ def solve(y, psf, lam, sigma_grid, d_grid, bounds, mode="BSFW", max_iter=200, T=
     by the LASSO and zero weights are pruned (SFW also slides all parameters
     before pruning). Otherwise BSFW runs its single final slide and prune and
     both variants stop. Stopping uses eta* <= 1 + eta_tol (the paper's "> 1" continues).
+    ``log``, if given, is called with each iteration's history entry (progress only).
     """
     if mode not in ("BSFW", "SFW"):
         raise ValueError("mode must be 'BSFW' or 'SFW'")
@@ -428,6 +429,8 @@ def solve(y, psf, lam, sigma_grid, d_grid, bounds, mode="BSFW", max_iter=200, T=
         theta, eta_star = ascent(q, lam, theta0, y.shape, bounds, **ascent_opts)
         history.append({"k": k, "C": C, "grid_max": gmax, "eta_star": eta_star,
                         "n_atoms": atoms.shape[0]})
+        if log is not None:
+            log(history[-1])
         if eta_star <= 1.0 + eta_tol:
             if mode == "BSFW":
                 atoms = prune(slide(y, atoms, psf, lam, bounds, **slide_opts))

@@ -56,6 +56,7 @@ class SfwOptions(ctypes.Structure):
         ("slide_gtol", ctypes.c_double), ("ftol", ctypes.c_double),
         ("lbfgs_memory", ctypes.c_int32), ("check_finite", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("proposal", ctypes.c_void_p),
+        ("init_atoms", ctypes.c_void_p), ("n_init", ctypes.c_int32),
     ]
 
 
@@ -68,7 +69,8 @@ class SfwStats(ctypes.Structure):
         ("seconds_total", ctypes.c_double), ("seconds_certificate", ctypes.c_double),
         ("seconds_ascent", ctypes.c_double), ("seconds_lasso", ctypes.c_double),
         ("seconds_slide", ctypes.c_double), ("n_proposals", ctypes.c_int32),
-        ("n_fallbacks", ctypes.c_int32),
+        ("n_fallbacks", ctypes.c_int32), ("n_atoms_descent", ctypes.c_int32),
+        ("n_merged", ctypes.c_int32), ("n_slivers", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -327,9 +329,26 @@ def sfw_lasso_weights(ws: Workspace, H, y, lam, atoms, w_out=None):
     return w[:n]
 
 
-def sfw_solve(ws: Workspace, y, H, lam, opts: SfwOptions | None = None, cap: int | None = None):
-    """Returns (atoms [n, 6] float64 numpy, stats dict, status code)."""
+def atoms_host(atoms):
+    """Host array [n, 6] (w, mx, my, mz, sigma, d) -> ctypes sfw_atom array (keep it alive)."""
+    a = np.asarray(atoms, dtype=np.float64).reshape(-1, 6)
+    arr = (SfwAtom * max(a.shape[0], 1))()
+    for i, row in enumerate(a):
+        arr[i] = SfwAtom(*[float(v) for v in row])
+    return arr, a.shape[0]
+
+
+def sfw_solve(ws: Workspace, y, H, lam, opts: SfwOptions | None = None, cap: int | None = None,
+              init_atoms=None):
+    """Returns (atoms [n, 6] float64 numpy, stats dict, status code). init_atoms: host array
+    [k, 6] the solve starts from (sets opts.init_atoms / n_init for this call)."""
     cap = ws.max_atoms if cap is None else int(cap)
+    init = None
+    if init_atoms is not None:
+        opts = opts if opts is not None else default_options()
+        init, k = atoms_host(init_atoms)
+        opts.init_atoms = ctypes.cast(init, ctypes.c_void_p)
+        opts.n_init = k
     out = (SfwAtom * max(cap, 1))()
     n_out = ctypes.c_int(0)
     stats = SfwStats()

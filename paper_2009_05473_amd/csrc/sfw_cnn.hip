@@ -20,6 +20,8 @@
 // sum over chunks.
 #include <hip/hip_runtime.h>
 
+#include <limits>
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -598,6 +600,7 @@ __global__ __launch_bounds__(64) void k_net_argmax_final(const float* __restrict
     res[2] = ok ? out[bi * 4 + 1] : 0.0;
     res[3] = ok ? out[bi * 4 + 2] : 0.0;
     res[4] = res[5] = res[6] = 0.0;
+    res[7] = ok ? 1.0 : 0.0;  // no finite heatmap value (a diverged network): no proposal
     if (ok) {
       const int x = (int)(bi % X), y = (int)((bi / X) % Y), z = (int)(bi / ((long long)X * Y));
       const float h0 = out[bi * 4];
@@ -801,6 +804,11 @@ int net_propose(sfw_net* n, const float* x, const sfw_dims& vol, float scale, do
       if (e != hipErrorNotReady) return hip_fail(e, "waiting for the proposal");
     }
     __builtin_ia32_pause();
+  }
+  if (n->hres[7] == 0.0) {  // no finite heatmap value: report that there is no proposal
+    for (int c = 0; c < 5; ++c) theta[c] = std::numeric_limits<double>::quiet_NaN();
+    *score = -std::numeric_limits<double>::infinity();
+    return SFW_OK;
   }
   const long long v = (long long)n->hres[1];
   const int ox = (int)(v % d.X), oy = (int)((v / d.X) % d.Y), oz = (int)(v / ((long long)d.X * d.Y));

@@ -369,6 +369,7 @@ struct Solver {
                        wmax, C0, C1);
         if (C1 <= C0 + kSliverTol * std::fabs(C0)) {
           dropped = true;
+          st.n_slivers++;
           break;
         }
       }
@@ -434,6 +435,7 @@ struct Solver {
                        C0, C1);
         if (C1 <= C0 + kSliverTol * std::fabs(C0)) {
           merged = true;
+          st.n_merged++;
           break;
         }
       }
@@ -546,6 +548,26 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
     rc = lasso_check_inputs(ws, S.plan, vol, y, H);
     if (rc) return rc;
 
+    // the starting measure (mu = 0 unless the caller resumes from init_atoms)
+    if (o.n_init < 0 || o.n_init > ws->max_atoms || (o.n_init > 0 && !o.init_atoms))
+      return fail(SFW_EINVAL, "opts.n_init must be in [0, max_atoms] with init_atoms set");
+    {
+      std::vector<double> lo, hi;
+      S.theta_bounds(lo, hi);
+      for (int i = 0; i < o.n_init; ++i) {
+        const sfw_atom& a = o.init_atoms[i];
+        const double v[6] = {a.w, a.mx, a.my, a.mz, a.sigma, a.d};
+        for (double x : v)
+          if (!std::isfinite(x)) return fail(SFW_EINVAL, "opts.init_atoms holds NaN or Inf");
+        if (v[0] < 0 || !(v[4] > 0) || !(v[5] > 0))
+          return fail(SFW_EINVAL, "opts.init_atoms needs w >= 0, sigma > 0 and d > 0");
+        S.atoms.push_back(v[0]);
+        for (int c = 0; c < 5; ++c) S.atoms.push_back(std::min(std::max(v[1 + c], lo[c]), hi[c]));
+      }
+      S.prune();
+      S.st.max_support = S.k();
+    }
+
     const float T = o.trunc_T > 0 ? o.trunc_T : 12.0f;
     bool converged = false;
     bool use_net = o.proposal != nullptr;
@@ -572,11 +594,13 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
         S.st.n_proposals++;
         auto ta = Clock::now();
         S.st.seconds_certificate += secs(tp, ta);
-        th.assign(seed, seed + 5);
-        rc = S.ascent(th, eta_star);
-        if (rc) return rc;
-        S.st.seconds_ascent += secs(ta, Clock::now());
-        seeded = eta_star > 1.0 + o.eta_tol;
+        if (std::isfinite(score)) {
+          th.assign(seed, seed + 5);
+          rc = S.ascent(th, eta_star);
+          if (rc) return rc;
+          S.st.seconds_ascent += secs(ta, Clock::now());
+          seeded = eta_star > 1.0 + o.eta_tol;
+        }  // else no finite heatmap value: no proposal, the grid seeds
         if (!seeded) {
           S.st.n_fallbacks++;
           use_net = false;
@@ -615,6 +639,7 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
           if (rc) return rc;
           S.prune();
         }
+        S.st.n_atoms_descent = S.k();
         rc = S.merge_pairs();
         if (rc) return rc;
         rc = S.drop_slivers();
@@ -648,6 +673,7 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
     S.st.iterations = converged ? it : o.max_iter;
     S.st.converged = converged ? 1 : 0;
     S.st.n_atoms = n;
+    if (!converged) S.st.n_atoms_descent = n;
     S.st.criterion = C;
     S.st.seconds_total = secs(t0, Clock::now());
     if (stats) *stats = S.st;

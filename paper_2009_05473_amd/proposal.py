@@ -113,13 +113,12 @@ def train(L, net, steps, shape=(64, 128, 128), seed=20000, lr=1e-3, log_every=0,
 
 
 def held_out(n_volumes, shape=(64, 128, 128), n_atoms=50, seed=5000):
-    """Held-out problems (seeds seed + i): the 128x128x64 workload's distributions."""
+    """Held-out problems (seeds seed + i, synth.draw_held_out's draws for seed 5000): the
+    128x128x64 workload's distributions."""
     out = []
     for i in range(n_volumes):
-        rng = np.random.default_rng(seed + i)
-        cfg, atoms = _volume(rng, shape, n_atoms)
-        noise = rng.standard_normal(cfg.shape)
-        out.append((cfg, atoms, noise))
+        p = synth.draw_held_out(seed - 5000 + i, shape, n_atoms)
+        out.append((p.config, p.atoms_true, p.noise_unit))
     return out
 
 

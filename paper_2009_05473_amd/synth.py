@@ -183,6 +183,15 @@ def draw_experiment(n: int, n_atoms: int, rep: int) -> Problem:
     return _draw(experiment_config(n, n_atoms), 10 ** 6 + 10 ** 4 * n + 100 * n_atoms + rep)
 
 
+def draw_held_out(index: int, shape: tuple = (64, 128, 128), n_atoms: int = 50) -> Problem:
+    """Held-out problem ``index`` of the learned-proposal comparison: the 128x128x64 workload's
+    distributions (or another shape / atom count), seed 5000 + index, draw_problem's order."""
+    if index < 0:
+        raise ValueError("index must be >= 0")
+    cfg = replace(CONFIGS["c3"], shape=tuple(shape), n_atoms=int(n_atoms))
+    return _draw(cfg, 5000 + index)
+
+
 BATCH_SHAPES_XY = tuple(range(48, 97, 8))  # n_x, n_y of a batch volume; n_z = 48
 
 

@@ -1,12 +1,20 @@
-"""Writes the oracle's BSFW solution on the 64 x 64 x 32, 10-atom workload (noisy) to
-solve_c2_bsfw.json, the reference of the GPU solver's parity test at that size.
+"""Writes the FP64 oracle's BSFW solutions that the GPU solver's parity tests compare against.
 
-Calls only the oracle and the seeded input drawer; takes a few minutes on one core:
-    python tests/golden/make_solve_golden.py
+Calls only the oracle and the seeded input drawer. Problems:
+    c2      64 x 64 x 32, 10 atoms, 15 x 15 x 31 PSF, noise 0.02 max  -> solve_c2_bsfw.json
+            (a few minutes on one core)
+    c3      128 x 128 x 64, 50 atoms, 9 x 9 x 15 PSF, noise 0.01 max -> solve_c3_bsfw.json
+    h<i>    held-out volume i of the learned-proposal comparison (same workload as c3,
+            seed 5000 + i)                                          -> solve_h<i>_bsfw.json
+            (each 128 x 128 x 64 solve takes hours on one core)
+Usage:
+    python tests/golden/make_solve_golden.py c2 [c3 h5 h7 ...]
+Progress (one line per BSFW iteration) goes to stderr.
 """
 import json
 import os
 import sys
+import time
 
 import numpy as np
 
@@ -17,25 +25,59 @@ import oracle  # noqa: E402
 from paper_2009_05473_amd import synth  # noqa: E402
 
 
-def main():
-    prob = synth.draw_problem("c2")
+def problem(name):
+    if name in ("c2", "c3"):
+        return synth.draw_problem(name)
+    if name.startswith("h"):
+        return synth.draw_held_out(int(name[1:]))
+    raise SystemExit(f"unknown problem {name!r}")
+
+
+WORKLOAD = {
+    "c2": "64 x 64 x 32, 10 atoms, 15 x 15 x 31 PSF, noise 0.02 max",
+    "c3": "128 x 128 x 64, 50 atoms, 9 x 9 x 15 PSF, noise 0.01 max",
+}
+
+
+def observation(prob):
+    """y as the device sees it: the FP64 forward model of the truth plus the seeded noise,
+    rounded to float32; lambda by the workloads' rule, also rounded to float32."""
     cfg = prob.config
     psf = prob.psf.astype(np.float32).astype(np.float64)
     clean = oracle.blur(oracle.render(prob.shape, prob.atoms_true), psf)
     y = synth.make_observation(clean, prob.noise_unit, cfg.noise_rel)
-    y = y.astype(np.float32).astype(np.float64)  # the values the device sees
+    y = y.astype(np.float32).astype(np.float64)
     lam = float(np.float32(cfg.lambda_rel * oracle.max_grid_certificate(
         y, psf, cfg.sigma_grid, cfg.d_grid)))
-    sg = [float(np.float32(v)) for v in cfg.sigma_grid]
-    res = oracle.solve(y, psf, lam, sg, cfg.d_grid, prob.bounds, mode="BSFW")
-    out = {"workload": "c2: 64 x 64 x 32, 10 atoms, 15 x 15 x 31 PSF, noise 0.02 max",
-           "mode": "BSFW", "lambda": lam, "sigma_grid": sg, "d_grid": list(cfg.d_grid),
-           "converged": bool(res.converged), "criterion": float(res.criterion),
-           "atoms": [[float(v) for v in a] for a in res.atoms]}
-    with open(os.path.join(HERE, "solve_c2_bsfw.json"), "w") as fh:
-        json.dump(out, fh, indent=1)
-    print("atoms", len(out["atoms"]), "criterion", out["criterion"])
+    return psf, y, lam
+
+
+def main(names):
+    for name in names:
+        prob = problem(name)
+        cfg = prob.config
+        psf, y, lam = observation(prob)
+        sg = [float(np.float32(v)) for v in cfg.sigma_grid]
+        t0 = time.time()
+
+        def log(h):
+            print(f"[{name}] k {h['k']} atoms {h['n_atoms']} C {h['C']:.6f} "
+                  f"eta* {h['eta_star']:.6f} ({time.time() - t0:.0f} s)", file=sys.stderr, flush=True)
+
+        res = oracle.solve(y, psf, lam, sg, cfg.d_grid, prob.bounds, mode="BSFW", log=log)
+        wl = WORKLOAD.get(name, WORKLOAD["c3"] + f", held-out volume {name[1:]} "
+                          f"(seed {prob.seed})")
+        out = {"workload": wl, "seed": int(prob.seed), "mode": "BSFW", "lambda": lam,
+               "sigma_grid": sg, "d_grid": list(cfg.d_grid),
+               "converged": bool(res.converged), "iterations": int(res.iterations),
+               "largest_support": int(max([h["n_atoms"] for h in res.history] + [0])),
+               "criterion": float(res.criterion), "seconds": time.time() - t0,
+               "atoms": [[float(v) for v in a] for a in res.atoms]}
+        with open(os.path.join(HERE, f"solve_{name}_bsfw.json"), "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(name, "atoms", len(out["atoms"]), "criterion", out["criterion"],
+              "seconds", round(out["seconds"]), flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:] or ["c2"])

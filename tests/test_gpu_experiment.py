@@ -36,3 +36,36 @@ def test_bsfw_matches_sfw(ctx, n, N, rep):
     assert s["atoms"] == b["atoms"] == N
     assert b["max_support"] > N
     assert max(s["max_centre_error"], b["max_centre_error"]) < 1.0
+
+
+@pytest.mark.parametrize("name", ["experiment_60_4_0", "experiment_80_6_2"])
+def test_draw_matches_oracle(ctx, name):
+    """Two draws of the comparison anchored to the FP64 oracle's SFW and BSFW solutions
+    (tests/golden/make_experiment_golden.py, same observation and lambda): in both modes the
+    same number of masses as the oracle, every centre within 0.05 voxel of the oracle's, and the
+    criterion within 1e-4 (relative) of the oracle's."""
+    import json
+    import os
+
+    import oracle
+    from paper_2009_05473_amd import synth
+    L, ws = ctx
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name + ".json")
+    with open(path) as fh:
+        g = json.load(fh)
+    prob = synth.draw_experiment(g["n"], g["N"], g["rep"])
+    psf = prob.psf.astype(np.float32).astype(np.float64)
+    clean = oracle.blur(oracle.render(prob.shape, prob.atoms_true), psf)
+    y = synth.make_observation(clean, prob.noise_unit, prob.config.noise_rel)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    Y, H = dev(y), dev(psf)
+    for mode in ("SFW", "BSFW"):
+        print("[case] oracle-anchored draw", name, mode, flush=True)
+        opts = L.default_options(mode=mode, sigma_grid=g["sigma_grid"], d_grid=g["d_grid"])
+        atoms, st, code = L.sfw_solve(ws, Y, H, g["lambda"], opts)
+        ref = np.asarray(g[mode]["atoms"])
+        assert code == L.SFW_OK
+        assert atoms.shape[0] == ref.shape[0] == g["N"]
+        for t in ref:
+            assert np.min(np.linalg.norm(atoms[:, 1:4] - t[1:4], axis=1)) <= 0.05
+        assert abs(st["criterion"] - g[mode]["criterion"]) <= 1e-4 * g[mode]["criterion"]

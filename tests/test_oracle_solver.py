@@ -126,3 +126,55 @@ def test_sfw_and_bsfw_reach_same_criterion_c1():
     assert rb.atoms.shape[0] == rs.atoms.shape[0] == truth.shape[0]
     # SFW needs exactly K steps to add K atoms (plus the stopping iteration)
     assert rs.iterations == truth.shape[0] + 1
+
+
+def test_merge_coincident_pins():
+    """Removing zero-weighted masses and updating the measure (algorithms 1 and 2) fuses masses
+    at one point of the domain: w_i delta_theta + w_j delta_theta is one mass. Pinned by what the
+    measure fixes, not by the merge's own formula: (1) exact duplicates leave Phi mu unchanged
+    (linearity in the weights); (2) for masses 0.03 apart the merge keeps the total weight and the
+    first moment sum w theta exactly, and moves Phi mu only to second order in the separation (a
+    merge that kept either mass's parameters would move it to first order); (3) masses 0.06 apart
+    in any one coordinate, beyond the 0.05 tolerance, stay separate."""
+    shape = (20, 20, 20)
+    psf = synth.gaussian_psf(1.0, 1.5, (9, 7, 7))
+    a = np.array([1.3, 9.2, 10.1, 9.7, 1.4, 2.0])
+    far = np.array([0.8, 4.0, 5.0, 14.0, 1.1, 1.8])
+    phi = lambda atoms: oracle.blur(oracle.render(shape, atoms), psf)
+    # (1) exact duplicate
+    b = a.copy()
+    b[0] = 0.4
+    m = oracle.merge_coincident(np.vstack([a, far, b]))
+    assert m.shape == (2, 6)
+    assert m[0, 0] == pytest.approx(1.7, rel=1e-15)
+    ref = phi(np.vstack([a, far, b]))
+    assert np.linalg.norm(phi(m) - ref) <= 1e-12 * np.linalg.norm(ref)
+    # (2) 0.03 apart in every coordinate of (m, sigma, d)
+    for delta in (0.03, 0.015):
+        c = a + np.array([0.0, delta, -delta, delta, delta, -delta])
+        c[0] = 0.6
+        pair = np.vstack([a, c])
+        m = oracle.merge_coincident(pair)
+        assert m.shape == (1, 6)
+        assert m[0, 0] == pytest.approx(a[0] + c[0], rel=1e-15)
+        np.testing.assert_allclose(m[0, 0] * m[0, 1:], a[0] * a[1:] + c[0] * c[1:], rtol=1e-14)
+        ref = phi(pair)
+        moved = np.linalg.norm(phi(m) - ref) / np.linalg.norm(ref)
+        keep_first = np.array([a[0] + c[0], *a[1:]])
+        first = np.linalg.norm(phi(keep_first[None]) - ref) / np.linalg.norm(ref)
+        if delta == 0.03:
+            moved_03, first_03 = moved, first
+    assert moved < first / 20  # second order against first order
+    assert moved_03 / moved == pytest.approx(4.0, rel=0.1)  # halving delta quarters the change
+    assert first_03 / first == pytest.approx(2.0, rel=0.1)
+    # (3) 0.06 apart in a single coordinate: separate
+    for k in range(1, 6):
+        c = a.copy()
+        c[k] += 0.06
+        assert oracle.merge_coincident(np.vstack([a, c])).shape == (2, 6)
+    # a third mass joins the first kept mass it coincides with
+    c = a + np.array([0, 0.02, 0, 0, 0, 0])
+    e = a + np.array([0, -0.02, 0, 0, 0, 0])
+    m = oracle.merge_coincident(np.vstack([a, far, c, e]))
+    assert m.shape == (2, 6) and m[0, 0] == pytest.approx(3 * a[0])
+    assert m[0, 1] == pytest.approx(a[1], abs=1e-12)
