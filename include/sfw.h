@@ -53,6 +53,12 @@ enum {
 enum { SFW_MODE_BSFW = 0, SFW_MODE_SFW = 1 };
 
 #define SFW_MAX_GRID 16
+/* A workspace reserves the grid certificate (its table kernels and Fourier-domain arrays) at
+ * creation for up to SFW_CERT_MAX_KERNELS grid points (n_sigma * n_d) whose kernels reach
+ * radius R = ceil(sigma (2T)^(1/d)) <= SFW_CERT_MAX_RADIUS (e.g. sigma <= 4.8 at d = 1.5,
+ * T = 12), so that sfw_certificate and sfw_solve allocate nothing; larger grids are rejected. */
+#define SFW_CERT_MAX_KERNELS 16
+#define SFW_CERT_MAX_RADIUS 40
 
 typedef struct { int32_t nx, ny, nz; } sfw_dims;
 
@@ -128,8 +134,9 @@ int sfw_default_options(sfw_options* opts);
 
 /* Create a workspace on the current HIP device for volumes up to vol_max voxels per axis,
  * PSFs up to psf_max taps per axis and up to max_atoms atoms. All scratch (rendered
- * volume, residual, adjoint, reduction partials, lookup tables, LASSO columns) is
- * allocated here once; hot calls allocate nothing. stream: the stream every call of this
+ * volume, residual, adjoint, reduction partials, lookup tables and the certificate's
+ * Fourier-domain arrays for the reserved grid, LASSO columns) is allocated here once; no
+ * other call allocates device memory. stream: the stream every call of this
  * workspace enqueues on (0 = the null stream). */
 int sfw_workspace_create(sfw_workspace** ws, sfw_dims vol_max, sfw_dims psf_max,
                          int max_atoms, hipStream_t stream);
@@ -173,7 +180,10 @@ int sfw_forward_vjp(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims vo
 /* Grid certificate and its maximum (section 1.3 step 1, lookup table of section 2):
  * eta_ij(m) = (1/lambda) sum_{||t||_inf <= R_ij} g(t; 0, sigma_i, d_j) q(m + t),
  * q = Phi^T r, R_ij = ceil(sigma_i (2T)^(1/d_j)), T = trunc_T (<= 0 selects 12),
- * for every voxel centre m. best_out: the maximum of eta (not |eta|) over
+ * for every voxel centre m. trunc_T is the one argument beyond the paper's statement: the
+ * paper leaves the lookup table's extent open; T sets it (kernel values below exp(-T) are
+ * dropped; the default 12 drops values below 6e-6 of the peak). ns * nd <= SFW_CERT_MAX_KERNELS
+ * and R_ij <= SFW_CERT_MAX_RADIUS (else SFW_EINVAL). best_out: the maximum of eta (not |eta|) over
  * (i, j, z, y, x); ties go to the lowest C-order flat index.
  * r: device [V], or NULL to use the q = Phi^T r left by the last sfw_residual_grad /
  * sfw_certificate on this workspace; sigma_grid, d_grid: HOST float [ns], [nd]

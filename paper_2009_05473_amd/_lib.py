@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsfw.so")
 SFW_OK, SFW_EINVAL, SFW_ENOMEM, SFW_EHIP, SFW_ECAP, SFW_ENOCONV = 0, -1, -2, -3, -4, -5
 SFW_MODE_BSFW, SFW_MODE_SFW = 0, 1
 SFW_MAX_GRID = 16
+SFW_CERT_MAX_KERNELS, SFW_CERT_MAX_RADIUS = 16, 40
 
 EXPORTED = (
     "sfw_default_options", "sfw_workspace_create", "sfw_workspace_destroy",

@@ -256,19 +256,7 @@ int op_vjp(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float
   return SFW_OK;
 }
 
-int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double lambda,
-                  const double* thetas, int n, double* eta_out, double* grad_out) {
-  // unit-weight atom constants computed on the host in float64, staged through pinned memory
-  AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin + ws->hp_stage);
-  for (int i = 0; i < n; ++i) {
-    const double* t = thetas + 5 * i;
-    hk[i] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
-  }
-  // small batches: one launch, atoms as kernel arguments, sums reduced in the kernel straight
-  // into pinned host memory
-  const bool one_launch = n <= kAtomArgs;
-  if (!one_launch)
-    SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
+GradPlan plan_points(const AtomK* hk, int n, const sfw_dims& vol, bool one_group) {
   // only the tiles where some point's atom is nonzero (its cut ball) carry terms
   int box[6] = {vol.nx, 0, vol.ny, 0, vol.nz, 0};
   const int nv[3] = {vol.nx, vol.ny, vol.nz};
@@ -288,10 +276,27 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
       box[2 * a + 1] = 1;
     }
   GradPlan gp = plan_grad_box(vol, n, box);
-  if (one_launch) {
+  if (one_group) {
     gp.groups = 1;
     gp.apg = n;
   }
+  return gp;
+}
+
+int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double lambda,
+                  const double* thetas, int n, double* eta_out, double* grad_out) {
+  // unit-weight atom constants computed on the host in float64, staged through pinned memory
+  AtomK* hk = reinterpret_cast<AtomK*>(ws->hpin + ws->hp_stage);
+  for (int i = 0; i < n; ++i) {
+    const double* t = thetas + 5 * i;
+    hk[i] = make_atomk(1.0, t[0], t[1], t[2], t[3], t[4]);
+  }
+  // small batches: one launch, atoms as kernel arguments, sums reduced in the kernel straight
+  // into pinned host memory
+  const bool one_launch = n <= kAtomArgs;
+  if (!one_launch)
+    SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
+  GradPlan gp = plan_points(hk, n, vol, one_launch);
   if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
     return fail(SFW_EINVAL, "gradient partial buffer too small");
   double* hs = ws->hpin + ws->hp_sums;
@@ -345,6 +350,8 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
   const char* fenv = std::getenv("SFW_FFT");  // transform-length policy (a test switch)
   key.push_back(fenv && std::strcmp(fenv, "generic") == 0 ? 1.f : 0.f);
   if (key == ws->lut_key && ws->lut) return SFW_OK;
+  if (ns * nd > SFW_CERT_MAX_KERNELS)
+    return fail(SFW_EINVAL, "n_sigma * n_d above SFW_CERT_MAX_KERNELS");
   ws->lut_key.clear();
   ws->fft_ready = false;
   std::vector<size_t> off;
@@ -354,7 +361,8 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
     for (int j = 0; j < nd; ++j) {
       const double R = std::ceil((double)sg[i] * std::pow(2.0 * (double)T, 1.0 / (double)dg[j]));
       const int r = (int)R;
-      if (r > 128) return fail(SFW_EINVAL, "certificate grid kernel radius above 128");
+      if (r > SFW_CERT_MAX_RADIUS)
+        return fail(SFW_EINVAL, "certificate grid kernel radius above SFW_CERT_MAX_RADIUS");
       const int P = 2 * r + 1;
       ConvPlan p = plan_conv(vol, P, P, P);
       if (p.lds_bytes > (size_t)kConvMaxLds)
@@ -381,13 +389,8 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
             dst[((size_t)ky * P + kx) * p.kzp + kz] = (float)std::exp(-std::pow(rr, d) * inv);
           }
     }
-  if (total > ws->lut_cap) {
-    if (ws->lut) SFW_HIP(hipFree(ws->lut));
-    ws->lut = nullptr;
-    ws->lut_cap = 0;
-    SFW_HIP(hipMalloc(&ws->lut, total * sizeof(float)));
-    ws->lut_cap = total;
-  }
+  if (total > ws->lut_cap)  // the reservation of sfw_workspace_create bounds this (no allocation)
+    return fail(SFW_EINVAL, "certificate grid kernels exceed the workspace's reservation");
   SFW_HIP(hipMemcpyAsync(ws->lut, host.data(), total * sizeof(float), hipMemcpyHostToDevice,
                          ws->stream));
   SFW_HIP(hipStreamSynchronize(ws->stream));
@@ -397,23 +400,11 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
   int rmax = 0;
   for (int r : rad) rmax = std::max(rmax, r);
   FftPlan pl;
-  if (fft_plan_cert(vol, rmax, pl)) {
-    const size_t N = (size_t)pl.px * pl.ny * pl.nz;
-    const int npairs = (ns * nd + 1) / 2;
-    if (N > ws->fft_cap || npairs > ws->fft_npairs_cap) {
-      if (ws->fft_qhat) SFW_HIP(hipFree(ws->fft_qhat));
-      if (ws->fft_work) SFW_HIP(hipFree(ws->fft_work));
-      if (ws->fft_pairs) SFW_HIP(hipFree(ws->fft_pairs));
-      ws->fft_qhat = ws->fft_work = ws->fft_pairs = nullptr;
-      ws->fft_cap = 0;
-      ws->fft_npairs_cap = 0;
-      SFW_HIP(hipMalloc(&ws->fft_qhat, N * sizeof(float2)));
-      SFW_HIP(hipMalloc(&ws->fft_work, (size_t)npairs * N * sizeof(float2)));
-      SFW_HIP(hipMalloc(&ws->fft_pairs, (size_t)npairs * N * sizeof(float2)));
-      ws->fft_cap = N;
-      ws->fft_npairs_cap = npairs;
-    }
-    if (!ws->fft_tw) SFW_HIP(hipMalloc(&ws->fft_tw, 3 * kFftMaxLen * sizeof(float2)));
+  // the Fourier-domain path runs in the arrays reserved at workspace creation; a plan that
+  // does not fit them (not expected within the reservation's grid) uses the direct kernels
+  const int npairs = (ns * nd + 1) / 2;
+  if (fft_plan_cert(vol, rmax, pl) && (size_t)pl.px * pl.ny * pl.nz <= ws->fft_cap &&
+      pl.oct <= ws->fft_oct_cap && npairs <= ws->fft_npairs_cap) {
     std::vector<float2> tw, all;
     for (int a = 0; a < 3; ++a) {
       fft_twiddles(pl.ax[a].n, tw);
@@ -986,6 +977,26 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
         (void)hipGetLastError();
         sfw_workspace_destroy(ws);
         return fail(SFW_EHIP, "clearing the PSF spectrum key failed");
+      }
+    }
+    {
+      // grid certificate: the table kernels of up to SFW_CERT_MAX_KERNELS grid points of radius
+      // up to SFW_CERT_MAX_RADIUS, and the Fourier-domain arrays of their largest plan at
+      // vol_max, so that sfw_certificate allocates nothing
+      const int P = 2 * SFW_CERT_MAX_RADIUS + 1;
+      ws->lut_cap = (size_t)SFW_CERT_MAX_KERNELS * P * P * plan_conv(vol_max, P, P, P).kzp;
+      ALLOC(ws->lut, ws->lut_cap * sizeof(float), "certificate table kernels");
+      FftPlan pl;
+      if (fft_plan_cert(vol_max, SFW_CERT_MAX_RADIUS, pl)) {
+        ws->fft_cap = (size_t)pl.px * pl.ny * pl.nz;
+        ws->fft_oct_cap = pl.oct;
+        ws->fft_npairs_cap = (SFW_CERT_MAX_KERNELS + 1) / 2;
+        ALLOC(ws->fft_qhat, ws->fft_cap * sizeof(float2), "certificate spectrum");
+        ALLOC(ws->fft_work, ws->fft_npairs_cap * ws->fft_cap * sizeof(float2),
+              "certificate work arrays");
+        ALLOC(ws->fft_pairs, ws->fft_npairs_cap * ws->fft_oct_cap * sizeof(float2),
+              "certificate pair spectra");
+        ALLOC(ws->fft_tw, 3 * (size_t)kFftMaxLen * sizeof(float2), "certificate twiddles");
       }
     }
     ALLOC(ws->lasso_slots, (size_t)max_atoms * sizeof(int), "LASSO slot list");

@@ -192,7 +192,8 @@ struct sfw_workspace {
   float2* fft_qhat = nullptr;    // [N]
   float2* fft_work = nullptr;    // [npairs][N]
   float2* fft_pairs = nullptr;   // [npairs][oct] pair spectra (octants, dense)
-  size_t fft_cap = 0;            // complex elements per array
+  size_t fft_cap = 0;            // complex elements per array (reserved at creation)
+  size_t fft_oct_cap = 0;        // complex elements per pair octant (reserved)
   int fft_npairs_cap = 0;
 
   // spectral PSF blur: spectrum work array [nz][N1][px], PSF spectrum [N2][N1][px] and the

@@ -516,6 +516,8 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
       return fail(SFW_EINVAL, "opts.mode must be SFW_MODE_BSFW or SFW_MODE_SFW");
     if (o.n_sigma < 1 || o.n_sigma > SFW_MAX_GRID || o.n_d < 1 || o.n_d > SFW_MAX_GRID)
       return fail(SFW_EINVAL, "opts grid sizes must be in [1, SFW_MAX_GRID]");
+    if (o.n_sigma * o.n_d > SFW_CERT_MAX_KERNELS)
+      return fail(SFW_EINVAL, "opts.n_sigma * opts.n_d must be at most SFW_CERT_MAX_KERNELS");
     if (!(o.sigma_lo > 0) || !(o.sigma_hi >= o.sigma_lo) || !(o.d_lo > 0) || !(o.d_hi >= o.d_lo))
       return fail(SFW_EINVAL, "opts bounds of sigma / d invalid");
     for (int i = 0; i < o.n_sigma; ++i)

@@ -491,3 +491,31 @@ def test_reductions_are_deterministic(L, ws_big):
         torch.cuda.synchronize()
         out.append((loss.cpu().numpy().tobytes(), grad.cpu().numpy().tobytes(), best))
     assert out[0] == out[1]
+
+
+def test_certificate_allocates_nothing(L):
+    """The workspace reserves the certificate's arrays at creation: a later certificate on a
+    larger grid (16 kernels up to radius 40) leaves the device's free memory unchanged, and a
+    grid beyond the reservation is rejected (SFW_EINVAL) instead of allocating."""
+    shape = (48, 40, 56)
+    rng = np.random.default_rng(11)
+    r = dev(rng.standard_normal(shape))
+    psf = dev(np.full((3, 3, 3), 1.0 / 27))
+    with L.Workspace(shape, (3, 3, 3), 8) as ws:
+        say("sfw_certificate warm-up grid")
+        L.sfw_certificate(ws, psf, r, 0.5, [1.0, 2.0], [2.0])
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        say("sfw_certificate 16-kernel grid, radius up to 40")
+        sg = [1.0, 2.0, 3.0, 4.8]
+        dg = [1.5, 2.0, 2.5, 3.0]
+        _, best = L.sfw_certificate(ws, psf, r, 0.5, sg, dg)
+        torch.cuda.synchronize()
+        assert torch.cuda.mem_get_info()[0] == free0
+        assert 0 <= best["i_sigma"] < 4 and 0 <= best["i_d"] < 4
+        with pytest.raises(L.SfwError) as e:  # 17 kernels
+            L.sfw_certificate(ws, psf, r, 0.5, [1.0] * 17, [2.0])
+        assert e.value.code == L.SFW_EINVAL
+        with pytest.raises(L.SfwError) as e:  # radius ceil(4.9 * 24^(1/1.5)) = 41
+            L.sfw_certificate(ws, psf, r, 0.5, [4.9], [1.5])
+        assert e.value.code == L.SFW_EINVAL and "RADIUS" in L.last_error()
