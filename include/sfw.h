@@ -217,6 +217,23 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
                       const float* y, float lambda, const sfw_atom* atoms, int n,
                       double* w_out);
 
+/* Certificate at points and its gradient, as sfw_eta_points, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace, no allocation and no synchronisation. Its scratch (per-tile
+ * partials, sums, a block counter) is one fixed device array of SFW_NOALLOC_SCRATCH_BYTES per
+ * GPU, held until the process ends; every call on a GPU shares it, so calls that overlap on
+ * one GPU race (order them on one stream).
+ * vol: volume size; q: device [V] (= Phi^T r); lambda > 0; thetas: HOST float [n][5] =
+ * (mx, my, mz, sigma, d), finite, sigma > 0, d > 0; n in [1, SFW_NOALLOC_MAX_POINTS];
+ * eta_out: device double [n]; grad_out: device double [n][5] or NULL; stream: where the
+ * kernels are enqueued (results valid once it reaches them). SFW_EINVAL for invalid
+ * arguments or when the tiles the points' atoms cover need more partials than the scratch
+ * holds (about 43,000 tiles of 16 x 16 x 64 voxels at 1 point, 5,400 at 8 points). */
+#define SFW_NOALLOC_SCRATCH_BYTES (1u << 20)
+#define SFW_NOALLOC_MAX_POINTS 8
+int sfw_eta_points_noalloc(sfw_dims vol, const float* q, float lambda, const float* thetas,
+                           int n, double* eta_out, double* grad_out, hipStream_t stream);
+
 /* ---------------------------------------------------------------- profiling */
 
 /* Per-kernel-class device time recorded with HIP events on the workspace stream between

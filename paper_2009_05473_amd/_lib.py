@@ -27,8 +27,9 @@ EXPORTED = (
     "sfw_solve", "sfw_solve_batch", "sfw_profile_begin", "sfw_profile_end",
     "sfw_net_num_params", "sfw_net_create", "sfw_net_destroy", "sfw_net_set_params",
     "sfw_net_get_params", "sfw_net_forward", "sfw_net_gradients", "sfw_net_train_step",
-    "sfw_net_propose",
+    "sfw_net_propose", "sfw_eta_points_noalloc",
 )
+SFW_NOALLOC_SCRATCH_BYTES, SFW_NOALLOC_MAX_POINTS = 1 << 20, 8
 SFW_PROF_KINDS = 16
 
 
@@ -115,6 +116,7 @@ def _load():
         "sfw_forward_vjp": (i32, [vp, vp, D, D, vp, vp, i32, vp]),
         "sfw_certificate": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp, i32, f32, vp, vp]),
         "sfw_eta_points": (i32, [vp, D, vp, f32, vp, i32, vp, vp]),
+        "sfw_eta_points_noalloc": (i32, [D, vp, f32, vp, i32, vp, vp, vp]),
         "sfw_lasso_weights": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp]),
         "sfw_solve": (i32, [vp, vp, D, vp, D, f32, ctypes.POINTER(SfwOptions), vp, i32,
                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SfwStats)]),
@@ -318,6 +320,25 @@ def sfw_eta_points(ws: Workspace, vol_shape, q, lam, thetas):
                              eta.ctypes.data_as(ctypes.c_void_p),
                              grad.ctypes.data_as(ctypes.c_void_p)))
     return eta, grad
+
+
+def sfw_eta_points_noalloc(vol_shape, q, lam, thetas, eta_out=None, grad_out=None, stream=None):
+    """thetas: host array [n, 5]; q: device volume; eta_out / grad_out: device float64 tensors
+    [n] / [n, 5] (allocated here when None; the library call itself allocates nothing).
+    Enqueues on `stream` (torch's current stream by default) and returns (eta, grad)."""
+    import torch
+    th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float32).reshape(-1, 5))
+    n = th.shape[0]
+    if eta_out is None:
+        eta_out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+    if grad_out is None:
+        grad_out = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda")
+    check(lib.sfw_eta_points_noalloc(dims(vol_shape), _dev_ptr(q, "float32", "q"), float(lam),
+                                     th.ctypes.data_as(ctypes.c_void_p), n,
+                                     _dev_ptr(eta_out, "float64", "eta_out"),
+                                     _dev_ptr(grad_out, "float64", "grad_out"),
+                                     _stream_handle(stream)))
+    return eta_out[:n], grad_out[:n]
 
 
 def sfw_lasso_weights(ws: Workspace, H, y, lam, atoms, w_out=None):
