@@ -47,10 +47,40 @@ ROOF_KERNEL = "k_fx_z_inverse (certificate: inverse z pass of every table-kernel
 FIXED_LENGTHS = (16, 18, 20, 24, 25, 27, 30, 32, 36, 40, 45, 48, 50, 54, 60, 64, 72, 75, 80, 81,
                  90, 96, 100, 108, 120, 128, 135, 144, 150, 160, 180, 192, 225, 240, 256)
 
-# Algorithmic ALU work per voxel-atom pair in FMA-slot units (one VALU instruction = 1 slot,
-# one v_exp/v_log/v_rcp = 4 slots: quarter rate, measured), reported as 2 FLOP per slot.
+# Algorithmic ALU work per evaluated voxel-atom pair in FMA-slot units (one VALU instruction =
+# 1 slot, one v_exp/v_log/v_rcp = 4 slots: quarter rate, measured), reported as 2 FLOP per slot.
 RENDER_SLOTS_PER_PAIR = 4 + 3 * 4   # 4 VALU + log2, exp2, exp2
 GRAD_SLOTS_PER_PAIR = 12 + 3 * 4    # 12 VALU + log2, exp2, exp2
+SLOTS_PER_S = PEAK_FP32_TFLOPS * 1e12 / 2.0   # 256 CUs x 128 lanes x 2.4 GHz = 78.6 T slots/s
+
+# Voxel boxes of one wave in the render and gradient kernels (x, y, z): a wave evaluates an atom
+# only where its cut ball (the radius beyond which the atom is exactly zero in float32) meets its
+# box; every other pair is an exact zero that it skips.
+RENDER_WAVE_BOX = (16, 4, 8)
+GRAD_WAVE_BOX = (16, 4, 16)
+ATOM_CUT_U = 110.0
+
+
+def evaluated_pairs(shape, atoms, box):
+    """Voxel-atom pairs the kernels evaluate: for every wave box (x, y, z) tiling the volume,
+    64 lanes x box z voxels (clipped to the volume) per atom whose cut ball meets the box."""
+    nz, ny, nx = shape
+    bx, by, bz = box
+    a = np.asarray(atoms, dtype=np.float64)
+    r = a[:, 4] * (2.0 * ATOM_CUT_U) ** (1.0 / a[:, 5]) * 1.0001 + 1e-3
+    total = 0
+    for z0 in range(0, nz, bz):
+        z1 = min(z0 + bz, nz) - 1
+        dz = np.maximum(0.0, np.maximum(z0 - a[:, 3], a[:, 3] - z1))
+        for y0 in range(0, ny, by):
+            y1 = min(y0 + by, ny) - 1
+            dy = np.maximum(0.0, np.maximum(y0 - a[:, 2], a[:, 2] - y1))
+            x0 = np.arange(0, nx, bx, dtype=np.float64)
+            x1 = np.minimum(x0 + bx, nx) - 1
+            dx = np.maximum(0.0, np.maximum(x0[:, None] - a[None, :, 1], a[None, :, 1] - x1[:, None]))
+            hit = dx * dx + (dy * dy + dz * dz)[None, :] <= (r * r)[None, :]
+            total += int(hit.sum()) * 64 * (z1 - z0 + 1)
+    return total
 
 
 # HBM traffic of one launch of the roofline kernel at this workload, from two rocprofv3 --pmc
@@ -167,38 +197,99 @@ def lut_taps(sigmas, ds, T=12.0):
     return t
 
 
-def cpu_baseline(prob, atoms_eval, psf):
-    """The oracle (single thread) on one step of the same workload, from its own inputs."""
+_ORACLE_SHARED = {}  # inputs of the parallel oracle leg, inherited by forked workers
+
+
+def _render_chunk(atoms):
+    import oracle
+    return oracle.render(_ORACLE_SHARED["shape"], atoms)
+
+
+def _grad_chunk(atoms):
+    # dC/dw = lam (1 - eta(theta)), dC/dtheta = -w lam grad eta(theta): the sums of the analytic
+    # gradient, per atom, on the shared q
+    import oracle
+    q, lam = _ORACLE_SHARED["q"], _ORACLE_SHARED["lam"]
+    out = []
+    for a in atoms:
+        eta, g = oracle.eta_point(q, lam, a[1:6])
+        out.append(np.concatenate([[lam * (1.0 - eta)], -a[0] * lam * g]))
+    return out
+
+
+def _oracle_step(oracle, prob, y, lam, atoms_eval, psf, cols, workers):
+    """One step of the workload in the FP64 oracle: (C, grad C), grid certificate and its
+    maximum, eta at the maximum, one new LASSO column with its Gram row and the NNLS. With
+    workers > 1 the atoms are split into chunks rendered and differentiated by forked worker
+    processes (the paper's parallelisation across atoms) and the Fourier-domain convolutions
+    use `workers` FFT threads."""
+    import multiprocessing as mp
+
+    from scipy import fft as sfft
+    from scipy import linalg, optimize
+    cfg = prob.config
+    with sfft.set_workers(workers):
+        if workers == 1:
+            _, _, _, q = oracle.criterion_and_grad(y, atoms_eval, psf, lam)
+        else:
+            ctx = mp.get_context("fork")
+            chunks = np.array_split(atoms_eval, workers)
+            _ORACLE_SHARED.update(shape=prob.shape)
+            with ctx.Pool(workers) as pool:
+                f = sum(pool.map(_render_chunk, chunks))
+            r = y - oracle.blur(f, psf)
+            0.5 * float(np.sum(r * r)) + lam * float(np.sum(atoms_eval[:, 0]))
+            q = oracle.adjoint(r, psf)
+            _ORACLE_SHARED.update(q=q, lam=lam)
+            with ctx.Pool(workers) as pool:
+                pool.map(_grad_chunk, chunks)
+            _ORACLE_SHARED.clear()
+        eta = oracle.grid_certificate(q, lam, cfg.sigma_grid, cfg.d_grid)
+        _, (i, j, z, yy, x) = oracle.grid_argmax(eta)
+        oracle.eta_point(q, lam, (x, yy, z, cfg.sigma_grid[i], cfg.d_grid[j]))
+        a_new = oracle.lasso_columns(prob.shape, atoms_eval[-1:, 1:6], psf)
+        A = np.vstack([cols, a_new])
+        G = A @ A.T
+        b = A @ y.reshape(-1)
+        Lc = linalg.cholesky(G, lower=True)
+        optimize.nnls(Lc.T, linalg.solve_triangular(Lc, b - lam, lower=True))
+
+
+def cpu_baseline(prob, atoms_eval, psf, reps=3):
+    """The oracle on one step of the same workload, from its own inputs: single thread (the
+    correctness oracle as written) and on every core the process may use (atoms split across
+    threads, multi-threaded FFTs). Median of `reps` steps each."""
     import oracle
     from paper_2009_05473_amd import synth
     from threadpoolctl import threadpool_limits
+    cores = len(os.sched_getaffinity(0))
     with threadpool_limits(1):
         clean = oracle.blur(oracle.render(prob.shape, prob.atoms_true), psf)
         y = synth.make_observation(clean, prob.noise_unit, prob.config.noise_rel)
         lam = prob.config.lambda_rel * oracle.max_grid_certificate(
             y, psf, prob.config.sigma_grid, prob.config.d_grid)
         cols = oracle.lasso_columns(prob.shape, atoms_eval[:-1, 1:6], psf)  # cached in BSFW
-        t0 = time.perf_counter()
-        _, _, _, q = oracle.criterion_and_grad(y, atoms_eval, psf, lam)
-        eta = oracle.grid_certificate(q, lam, prob.config.sigma_grid, prob.config.d_grid)
-        _, (i, j, z, yy, x) = oracle.grid_argmax(eta)
-        oracle.eta_point(q, lam, (x, yy, z, prob.config.sigma_grid[i], prob.config.d_grid[j]))
-        a_new = oracle.lasso_columns(prob.shape, atoms_eval[-1:, 1:6], psf)
-        A = np.vstack([cols, a_new])
-        G = A @ A.T
-        b = A @ y.reshape(-1)
-        from scipy import linalg, optimize
-        L = linalg.cholesky(G, lower=True)
-        optimize.nnls(L.T, linalg.solve_triangular(L, b - lam, lower=True))
-        dt = time.perf_counter() - t0
+    times = {}
+    for threads in (1, cores):
+        with threadpool_limits(threads):
+            dts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                _oracle_step(oracle, prob, y, lam, atoms_eval, psf, cols, threads)
+                dts.append(time.perf_counter() - t0)
+        times[threads] = float(np.median(dts))
     V = int(np.prod(prob.shape))
     n = atoms_eval.shape[0]
-    return {"value": V * n / dt / 1e9, "unit": "GVoxel*atom/s", "cores": 1, "kind": "oracle",
-            "seconds": dt,
-            "sample": "one full step of the same 128x128x64, 50-atom workload (float64 "
-                      "criterion and gradient, grid certificate and maximum, eta at the "
-                      "maximum, one new LASSO column with its Gram row and the NNLS), "
-                      "single thread"}
+    dt = times[cores]
+    return {"value": V * n / dt / 1e9, "unit": "GVoxel*atom/s", "cores": cores, "kind": "oracle",
+            "seconds": dt, "single_thread_value": V * n / times[1] / 1e9,
+            "single_thread_seconds": times[1], "os_cpu_count": os.cpu_count(),
+            "affinity_cores": cores,
+            "sample": f"one full step of the same 128x128x64, 50-atom workload (float64 "
+                      f"criterion and gradient, grid certificate and maximum, eta at the "
+                      f"maximum, one new LASSO column with its Gram row and the NNLS), median "
+                      f"of {reps}; value: {cores} cores (atoms split across forked worker "
+                      f"processes, multi-threaded FFTs); single_thread_value: one thread"}
 
 
 def solve_run(L, ws, H, Y, lam, prob, sg, dg):
@@ -378,37 +469,55 @@ def main():
     ms_per_step = dt / args.steps * 1e3
     value = V * N * args.steps / dt / 1e9
 
-    # algorithmic work per launch of each kernel class
+    # algorithmic work per launch of each kernel class: HBM bytes that the operation must move
+    # (its inputs and outputs, not the implementation's intermediate arrays) and ALU slots of
+    # the voxel-atom pairs the kernels evaluate (host replica of their box test)
     px, py, pz = psf.shape[2], psf.shape[1], psf.shape[0]
     taps = px * py * pz
     conv_flops = 2.0 * V * taps
     grid, rmax = cert_grid(shape, sg, dg)
     npairs = (len(sg) * len(dg) + 1) // 2
     zbytes = zinv_bytes(shape, grid, npairs)
-    work = {  # (bound, algorithmic amount per launch, peak): FLOP vs TFLOP/s, bytes vs GB/s
-        "render": ("alu", 2.0 * V * N * RENDER_SLOTS_PER_PAIR, PEAK_FP32_TFLOPS),
-        "grad": ("alu", 2.0 * V * N * GRAD_SLOTS_PER_PAIR, PEAK_FP32_TFLOPS),
-        "cert_zinv": ("hbm", float(zbytes), PEAK_HBM_GBS),
+    pairs_render = evaluated_pairs(shape, atoms_eval, RENDER_WAVE_BOX)
+    pairs_grad = evaluated_pairs(shape, atoms_eval, GRAD_WAVE_BOX)
+    vb = 4.0 * V  # one float32 volume
+    work = {  # class: (HBM bytes, ALU slots) per launch
+        "render": (vb + 32.0 * N, float(pairs_render * RENDER_SLOTS_PER_PAIR)),
+        "conv_residual": (3 * vb, 0.0),   # f and y in, r out (r stays in LDS for the adjoint)
+        "conv_adjoint": (vb, 0.0),        # q out
+        "grad": (vb, float(pairs_grad * GRAD_SLOTS_PER_PAIR)),  # q in
+        "cert_zinv": (float(zbytes), 0.0),
     }
     ps = max(args.profile_steps, 1)
     breakdown = {}
+    step_ms = sum(ms for _, ms in prof.values()) / ps if prof else 0.0
     for name, (launches, ms) in prof.items():
         e = {"launches_per_step": launches / ps, "ms_per_step": ms / ps,
-             "us_per_launch": ms / launches * 1e3}
+             "us_per_launch": ms / launches * 1e3, "share": (ms / ps) / step_ms}
         t = ms / launches * 1e-3
         if name in work:
-            bound, amount, peak = work[name]
-            achieved = amount / t / (1e9 if bound == "hbm" else 1e12)
-            e.update({"bound": bound, "achieved": achieved, "frac": achieved / peak})
+            nbytes, slots = work[name]
+            t_hbm, t_alu = nbytes / (PEAK_HBM_GBS * 1e9), slots / SLOTS_PER_S
+            bound = "hbm" if t_hbm >= t_alu else "alu"
+            e.update({"bound": bound, "bytes": nbytes, "alu_slots": slots,
+                      "roofline_us": max(t_hbm, t_alu) * 1e6,
+                      "frac": max(t_hbm, t_alu) / t})
         if name in ("conv_residual", "conv_adjoint"):
             # spectral blur: the direct convolution's FLOP rate it stands in for
             e["direct_equivalent_tflops"] = conv_flops / t / 1e12
         breakdown[name] = e
     if prof:
-        fwd_grad_ms = sum(prof.get(k, (0, 0.0))[1] for k in
-                          ("prep", "render", "conv_residual", "conv_adjoint", "grad",
-                           "grad_finalize")) / ps
+        chain = ("prep", "render", "conv_residual", "conv_adjoint", "grad", "grad_finalize")
+        fwd_grad_ms = sum(prof.get(k, (0, 0.0))[1] for k in chain) / ps
+        roof_us = sum(breakdown[k].get("roofline_us", 0.0) for k in chain if k in breakdown)
         breakdown["fwd_grad_GVoxel_atom_per_s"] = V * N / (fwd_grad_ms * 1e-3) / 1e9
+        breakdown["fwd_grad_chain"] = {
+            "us": fwd_grad_ms * 1e3, "roofline_us": roof_us, "frac": roof_us / (fwd_grad_ms * 1e3),
+            "evaluated_pairs_render": pairs_render, "evaluated_pairs_grad": pairs_grad,
+            "nominal_pairs": V * N,
+            "definition": "sum over the chain's kernel classes of max(algorithmic HBM bytes / "
+                          "8 TB/s, ALU slots of evaluated voxel-atom pairs / 78.6 T slots/s), "
+                          "over the measured chain time"}
 
     # roofline of the dominant kernel, timed live over the timed region
     launches, ms = roof_prof[ROOF_CLASS]

@@ -105,6 +105,11 @@ typedef struct {
                                         centres, sigma and d are clipped into the box and
                                         zero weights pruned before the first iteration */
   int32_t n_init;                    /* atoms in init_atoms, 0..max_atoms, default 0 */
+  double slide_slope_tol;            /* sliding descents: a step whose criterion stays within
+                                        slide_slope_tol |C| of the last one (float32 rounding
+                                        of C) is taken on its slope (approximate Wolfe test)
+                                        when it fails the sufficient-decrease test; default
+                                        1e-6, 0 = sufficient decrease only */
 } sfw_options;
 
 /* Per-solve statistics (host memory). */
@@ -121,10 +126,6 @@ typedef struct {
   double seconds_total, seconds_certificate, seconds_ascent, seconds_lasso, seconds_slide;
   int32_t n_proposals;       /* seeds from the proposal network */
   int32_t n_fallbacks;       /* of which the grid maximum had to replace (0 or 1) */
-  int32_t n_atoms_descent;   /* atoms after the final descent and pruning, before the two
-                                float32 safeguards below */
-  int32_t n_merged;          /* pairs fused by the merge safeguard (0 when disabled) */
-  int32_t n_slivers;         /* masses dropped by the sliver safeguard (0 when disabled) */
 } sfw_stats;
 
 /* ---------------------------------------------------------------- lifecycle */

@@ -59,6 +59,7 @@ class SfwOptions(ctypes.Structure):
         ("lbfgs_memory", ctypes.c_int32), ("check_finite", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("proposal", ctypes.c_void_p),
         ("init_atoms", ctypes.c_void_p), ("n_init", ctypes.c_int32),
+        ("slide_slope_tol", ctypes.c_double),
     ]
 
 
@@ -71,8 +72,7 @@ class SfwStats(ctypes.Structure):
         ("seconds_total", ctypes.c_double), ("seconds_certificate", ctypes.c_double),
         ("seconds_ascent", ctypes.c_double), ("seconds_lasso", ctypes.c_double),
         ("seconds_slide", ctypes.c_double), ("n_proposals", ctypes.c_int32),
-        ("n_fallbacks", ctypes.c_int32), ("n_atoms_descent", ctypes.c_int32),
-        ("n_merged", ctypes.c_int32), ("n_slivers", ctypes.c_int32),
+        ("n_fallbacks", ctypes.c_int32),
     ]
 
     def as_dict(self):

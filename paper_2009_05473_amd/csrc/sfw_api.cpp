@@ -275,7 +275,7 @@ GradPlan plan_points(const AtomK* hk, int n, const sfw_dims& vol, bool one_group
       box[2 * a] = 0;
       box[2 * a + 1] = 1;
     }
-  GradPlan gp = plan_grad_box(vol, n, box);
+  GradPlan gp = plan_grad_box(vol, n, box, one_group);
   if (one_group) {
     gp.groups = 1;
     gp.apg = n;
@@ -825,6 +825,7 @@ int sfw_default_options(sfw_options* o) {
   o->lbfgs_memory = 10;
   o->check_finite = 1;
   o->verbose = 0;
+  o->slide_slope_tol = 1e-6;
   return SFW_OK;
 }
 

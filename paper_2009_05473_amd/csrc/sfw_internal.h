@@ -319,7 +319,7 @@ int sig_wait(sfw_workspace* ws, const SigArgs& s);
 ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz);
 GradPlan plan_grad(sfw_dims vol, int n_atoms);
 // Plan over the tiles that meet box {x0, x1, y0, y1, z0, z1} (voxels, half-open).
-GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6]);
+GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6], bool deep = false);
 
 // One launch: atom constants (atoms may be null when n == 0) and the forward / adjoint PSF
 // operands for the matrix-core (mfma) or VALU (kzp) convolution (H may be null).

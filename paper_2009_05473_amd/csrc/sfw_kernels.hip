@@ -224,6 +224,7 @@ struct TileXY {
   int x, y;     // this thread's column
   bool in;      // inside the plane
   int x0, y0w;  // wave patch origin (wave-uniform)
+  int y0b;      // block tile's first row
 };
 __device__ __forceinline__ TileXY tile_xy(int tile, int nx, int ny, int rx0 = 0, int ry0 = 0,
                                           int rtx = -1) {
@@ -234,6 +235,7 @@ __device__ __forceinline__ TileXY tile_xy(int tile, int nx, int ny, int rx0 = 0,
   t.x = t.x0 + (int)(threadIdx.x & (kTile - 1));
   t.y = by * kTile + (int)(threadIdx.x / kTile);
   t.y0w = __builtin_amdgcn_readfirstlane(by * kTile + (int)((threadIdx.x & ~63u) / kTile));
+  t.y0b = by * kTile;
   t.in = t.x < nx && t.y < ny;
   return t;
 }
@@ -261,11 +263,37 @@ __device__ __forceinline__ WaveBox wave_box(const TileXY& t, int nx, int ny, int
   return b;
 }
 
+// Atom lists of one wave: lane l loads the constants of atom a0 + l (a < a1, at most 64 atoms,
+// one coalesced load) and tests it against the wave's box; the returned ballot marks the atoms
+// whose cut ball meets the box, the only ones with a nonzero term there. The wave then walks
+// the set bits in increasing atom order and takes each atom's constants from its lane
+// (lane_atom: eight readlanes into scalar registers), with no memory access per atom.
+__device__ __forceinline__ unsigned long long wave_hits(const AtomK* __restrict__ ak, int a0,
+                                                        int a1, const WaveBox& wb, AtomK& mine) {
+  const int a = a0 + (int)(threadIdx.x & 63);
+  bool hit = false;
+  if (a < a1) {
+    mine = ak[a];
+    hit = !wb.misses(mine);
+  } else {
+    mine = AtomK{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  }
+  return __ballot(hit);
+}
+__device__ __forceinline__ float lane_f(float v, int i) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), i));
+}
+__device__ __forceinline__ AtomK lane_atom(const AtomK& m, int i) {
+  return AtomK{lane_f(m.w, i),  lane_f(m.mx, i), lane_f(m.my, i),   lane_f(m.mz, i),
+               lane_f(m.hd, i), lane_f(m.c, i),  lane_f(m.hdm1, i), lane_f(m.rcut2, i)};
+}
+
 // ------------------------------------------------------------------ render
 
 // f(s) = sum_n w_n exp(-u_n(s)) for every voxel; thread = one (y, x) column of a 16 x 16 tile
-// (blockIdx.x), kRenderVPT planes (blockIdx.y). Atoms whose cut ball misses the wave's voxels
-// are skipped: they add exact zeros there.
+// (blockIdx.x), kRenderVPT planes (blockIdx.y). Each wave evaluates only the atoms whose cut
+// ball meets its voxels (wave_hits); the others add exact zeros there. Atoms are summed in
+// increasing index order.
 __global__ __launch_bounds__(256) void k_render(const AtomK* __restrict__ ak, int n, int nx,
                                                 int ny, int nz, float* __restrict__ f) {
   constexpr int VPT = kRenderVPT;
@@ -278,21 +306,26 @@ __global__ __launch_bounds__(256) void k_render(const AtomK* __restrict__ ak, in
   float acc[VPT];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) acc[j] = 0.f;
-  for (int a = 0; a < n; ++a) {
-    const AtomK k = ak[a];
-    if (wb.misses(k)) continue;  // exactly zero on every voxel of this wave
-    const float dx = fx - k.mx;
-    const float dy = fy - k.my;
-    const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
-    const float dz0 = fz0 - k.mz;
+  for (int a0 = 0; a0 < n; a0 += 64) {
+    AtomK mine;
+    unsigned long long m = wave_hits(ak, a0, min(n, a0 + 64), wb, mine);
+    while (m) {
+      const int i = __builtin_ctzll(m);
+      m &= m - 1;
+      const AtomK k = lane_atom(mine, i);
+      const float dx = fx - k.mx;
+      const float dy = fy - k.my;
+      const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
+      const float dz0 = fz0 - k.mz;
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const float dz = dz0 + (float)j;
-      const float r2 = fmaf(dz, dz, dxy2);
-      const float l = fast_log2(r2);
-      const float up = fast_exp2(fmaf(k.hd, l, k.c));  // u * log2(e)
-      const float g = fast_exp2(-up);
-      acc[j] = fmaf(k.w, g, acc[j]);
+      for (int j = 0; j < VPT; ++j) {
+        const float dz = dz0 + (float)j;
+        const float r2 = fmaf(dz, dz, dxy2);
+        const float l = fast_log2(r2);
+        const float up = fast_exp2(fmaf(k.hd, l, k.c));  // u * log2(e)
+        const float g = fast_exp2(-up);
+        acc[j] = fmaf(k.w, g, acc[j]);
+      }
     }
   }
   if (!t.in) return;
@@ -689,7 +722,9 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
 
 // Per-atom sums over a tile of voxels (block = 256 (y, x) columns x VPT z); grid.x = tiles,
 // grid.y = atom groups. Writes gpart[tile][atom][0..5] =
-// (S_g, S_u, S_l, S_mx, S_my, S_mz) of the tile (see launch_grad_finalize).
+// (S_g, S_u, S_l, S_mx, S_my, S_mz) of the tile (see launch_grad_finalize), zero for atoms whose
+// cut ball misses the tile. Each wave evaluates only the atoms whose cut ball meets its voxels
+// (wave_hits; the other terms are exact zeros).
 // With POINTS, the atoms come by value in `args` (at most kAtomArgs, one atom group) and the
 // last block to finish (ticket counter) sums the tile partials over tiles in a fixed order, in
 // float64, into sums_out[6 a + c]: one launch per evaluation of the certificate at a few
@@ -706,8 +741,9 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
                                                        double* __restrict__ sums_out,
                                                        SigArgs sig) {
   constexpr int NW = kGradThreads / 64;
-  __shared__ float red[NW][kGradMaxAtomsPerGroup][6];
+  __shared__ float red[NW][64][6];
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int tile = blockIdx.x;
   const int txy = tile % ntile_xy;
   const int tz = rz0 + tile / ntile_xy;
@@ -722,71 +758,84 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
   for (int j = 0; j < VPT; ++j)
     qv[j] = (pin && z0 + j < nz) ? q[(size_t)(z0 + j) * nxy + p] : 0.f;
   const float fx = (float)x, fy = (float)y, fz0 = (float)z0;
-  const int a0 = blockIdx.y * apg;
-  const int a1 = min(n, a0 + apg);
+  const int ga0 = blockIdx.y * apg;
+  const int ga1 = min(n, ga0 + apg);
   const int wave = tid / 64;
   const WaveBox wb = wave_box(t, nx, ny, z0, min(z0 + VPT, nz) - 1);
-  for (int a = a0; a < a1; ++a) {
-    const AtomK k = POINTS ? args.a[a] : ak[a];
-    if (wb.misses(k)) {  // every term of this wave is exactly zero
-      if ((tid & 63) == 0) {
-        float* rr = red[wave][a - a0];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) rr[c] = 0.f;
+  for (int a0 = ga0; a0 < ga1; a0 += 64) {
+    const int a1 = min(ga1, a0 + 64);
+    AtomK mine{};
+    unsigned long long m;
+    if (POINTS) {  // a handful of atoms straight from the arguments
+      m = 0;
+      for (int i = 0; i < a1 - a0; ++i) {
+        const AtomK k = args.a[a0 + i];
+        if (lane == i) mine = k;
+        if (!wb.misses(k)) m |= 1ull << i;
       }
-      continue;
+    } else {
+      m = wave_hits(ak, a0, a1, wb, mine);
     }
-    const float dx = fx - k.mx;
-    const float dy = fy - k.my;
-    const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
-    const float dz0 = fz0 - k.mz;
-    float sg = 0.f, su = 0.f, sl = 0.f, sc = 0.f, scz = 0.f;
+    if (lane < a1 - a0 && !((m >> lane) & 1ull)) {  // this wave's terms of that atom are zero
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const float dz = dz0 + (float)j;
-      const float r2 = fmaf(dz, dz, dxy2);
-      const float l = fast_log2(r2);
-      const float vp = fast_exp2(fmaf(k.hdm1, l, k.c));  // u log2(e) / r^2
-      const float up = vp * r2;                           // u log2(e)
-      const float g = fast_exp2(-up);
-      const float qg = qv[j] * g;
-      sg += qg;
-      const float qgu = qg * up;
-      su += qgu;
-      sl = fmaf(qgu, l, sl);
-      const float c2 = qg * vp;
-      sc += c2;
-      scz = fmaf(c2, dz, scz);
+      for (int c = 0; c < 6; ++c) red[wave][lane][c] = 0.f;
     }
-    const float s0 = wave_sum(sg);
-    const float s1 = wave_sum(su);
-    const float s2 = wave_sum(sl);
-    const float s3 = wave_sum(sc * dx);
-    const float s4 = wave_sum(sc * dy);
-    const float s5 = wave_sum(scz);
-    if ((tid & 63) == 0) {
-      float* rr = red[wave][a - a0];
-      rr[0] = s0;
-      rr[1] = s1;
-      rr[2] = s2;
-      rr[3] = s3;
-      rr[4] = s4;
-      rr[5] = s5;
-    }
-  }
-  __syncthreads();
-  const int cnt = (a1 - a0) * 6;
-  for (int i = tid; i < cnt; i += kGradThreads) {
-    const int aa = i / 6, c = i - aa * 6;
-    float t = 0.f;
+    while (m) {
+      const int i = __builtin_ctzll(m);
+      m &= m - 1;
+      const AtomK k = lane_atom(mine, i);
+      const float dx = fx - k.mx;
+      const float dy = fy - k.my;
+      const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
+      const float dz0 = fz0 - k.mz;
+      float sg = 0.f, su = 0.f, sl = 0.f, sc = 0.f, scz = 0.f;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) t += red[w][aa][c];
-    gpart[((size_t)tile * n + a0 + aa) * 6 + c] = t;
+      for (int j = 0; j < VPT; ++j) {
+        const float dz = dz0 + (float)j;
+        const float r2 = fmaf(dz, dz, dxy2);
+        const float l = fast_log2(r2);
+        const float vp = fast_exp2(fmaf(k.hdm1, l, k.c));  // u log2(e) / r^2
+        const float up = vp * r2;                           // u log2(e)
+        const float g = fast_exp2(-up);
+        const float qg = qv[j] * g;
+        sg += qg;
+        const float qgu = qg * up;
+        su += qgu;
+        sl = fmaf(qgu, l, sl);
+        const float c2 = qg * vp;
+        sc += c2;
+        scz = fmaf(c2, dz, scz);
+      }
+      const float s0 = wave_sum(sg);
+      const float s1 = wave_sum(su);
+      const float s2 = wave_sum(sl);
+      const float s3 = wave_sum(sc * dx);
+      const float s4 = wave_sum(sc * dy);
+      const float s5 = wave_sum(scz);
+      if (lane == 0) {
+        float* rr = red[wave][i];
+        rr[0] = s0;
+        rr[1] = s1;
+        rr[2] = s2;
+        rr[3] = s3;
+        rr[4] = s4;
+        rr[5] = s5;
+      }
+    }
+    __syncthreads();
+    const int cnt = (a1 - a0) * 6;
+    for (int i = tid; i < cnt; i += kGradThreads) {
+      const int aa = i / 6, c = i - aa * 6;
+      float v = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v += red[w][aa][c];
+      gpart[((size_t)tile * n + a0 + aa) * 6 + c] = v;
+    }
+    __syncthreads();  // red is rewritten by the next batch
   }
   if (POINTS) {
-    constexpr int kSlices = 5;  // tile slices per (atom, component): 6 kAtomArgs * 5 <= 256
     __shared__ int is_last;
-    __shared__ double part[kAtomArgs * 6][kSlices];
+    __shared__ double part[kGradThreads];
     static_assert(kAtomArgs * 6 <= 64, "the sums must be written by the first wave");
     __threadfence();
     __syncthreads();
@@ -794,19 +843,21 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
     __syncthreads();
     if (is_last) {
       __threadfence();
+      // the whole block sums the tiles: slice sl of (atom, component) pr takes the tiles
+      // tt = sl (mod nsl), then one thread per pr adds its slices in order (fixed order)
       const int pairs = n * 6, ntiles = gridDim.x;
-      if (tid < pairs * kSlices) {
-        const int pr = tid / kSlices, sl = tid - pr * kSlices;
+      const int nsl = kGradThreads / pairs;
+      if (tid < pairs * nsl) {
+        const int pr = tid % pairs, sl = tid / pairs;
         double acc = 0.0;
 #pragma unroll 4
-        for (int tt = sl; tt < ntiles; tt += kSlices) acc += (double)gpart[(size_t)tt * pairs + pr];
-        part[pr][sl] = acc;
+        for (int tt = sl; tt < ntiles; tt += nsl) acc += (double)gpart[(size_t)tt * pairs + pr];
+        part[sl * pairs + pr] = acc;
       }
       __syncthreads();
       if (tid < pairs) {
         double S = 0.0;
-#pragma unroll
-        for (int sl = 0; sl < kSlices; ++sl) S += part[tid][sl];
+        for (int sl = 0; sl < nsl; ++sl) S += part[sl * pairs + tid];
         sums_out[tid] = S;
       }
       if (tid == 0) *ticket = 0;  // ready for the next launch
@@ -1165,7 +1216,7 @@ ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz) {
 
 GradPlan plan_grad(sfw_dims vol, int n_atoms) {
   GradPlan p;
-  p.vpt = vol.nz >= 64 ? 64 : (vol.nz >= 32 ? 32 : 16);
+  p.vpt = 16;  // a wave's box is 16 x 4 x 16 voxels: atoms are culled along z as well
   p.rtx = (vol.nx + kTile - 1) / kTile;
   p.ntile_xy = p.rtx * ((vol.ny + kTile - 1) / kTile);
   p.ntile_z = (vol.nz + p.vpt - 1) / p.vpt;
@@ -1183,8 +1234,12 @@ GradPlan plan_grad(sfw_dims vol, int n_atoms) {
   return p;
 }
 
-GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6]) {
+GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6], bool deep) {
   GradPlan p = plan_grad(vol, n_atoms);
+  // a few points (one launch, last-block sums): deep tiles keep the block count, and with it
+  // the per-block release fences and the last block's sum, small; a point's atom spans most
+  // of the depth anyway
+  if (deep) p.vpt = vol.nz >= 64 ? 64 : (vol.nz >= 32 ? 32 : 16);
   p.rx0 = box[0] / kTile;
   p.rtx = std::max(1, (box[1] + kTile - 1) / kTile - p.rx0);
   p.ry0 = box[2] / kTile;
@@ -1548,19 +1603,10 @@ hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q
   dim3 grid(p.ntiles, p.groups);
   AtomArgs none;
   std::memset(&none, 0, sizeof(none));
-  switch (p.vpt) {
-#define SFW_GRAD_CASE(V)                                                                       \
-  case V:                                                                                      \
-    hipLaunchKernelGGL((k_grad<V, false>), grid, dim3(kGradThreads), 0, st, ak, none, n, p.apg, \
-                       q, vol.nx, vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0,       \
-                       gpart, nullptr, nullptr, kNoSig);                                                \
-    break;
-    SFW_GRAD_CASE(64)
-    SFW_GRAD_CASE(32)
-    default:
-      SFW_GRAD_CASE(16)
-#undef SFW_GRAD_CASE
-  }
+  if (p.vpt != 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_grad<16, false>), grid, dim3(kGradThreads), 0, st, ak, none, n, p.apg, q,
+                     vol.nx, vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart,
+                     nullptr, nullptr, kNoSig);
   return hipGetLastError();
 }
 
@@ -1577,12 +1623,13 @@ hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n,
   case V:                                                                                      \
     hipLaunchKernelGGL((k_grad<V, true>), grid, dim3(kGradThreads), 0, st, nullptr, args, n, n, \
                        q, vol.nx, vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0,       \
-                       gpart, ticket, sums_out, sig);                                                \
+                       gpart, ticket, sums_out, sig);                                           \
     break;
     SFW_GRAD_CASE(64)
     SFW_GRAD_CASE(32)
+    SFW_GRAD_CASE(16)
     default:
-      SFW_GRAD_CASE(16)
+      return hipErrorInvalidValue;
 #undef SFW_GRAD_CASE
   }
   return hipGetLastError();

@@ -22,6 +22,11 @@
 #include "sfw_internal.h"
 #include "sfw_ops.h"
 
+// Slope-only steps without a halving of the projected gradient before a sliding descent stops
+#ifndef SFW_SLOPE_STALL
+#define SFW_SLOPE_STALL 30
+#endif
+
 namespace sfw {
 
 namespace {
@@ -43,6 +48,7 @@ struct MinResult {
   bool converged = false;
   double f = 0.0;
   int status = SFW_OK;
+  const char* stop = "iterations";  // why the descent stopped (verbose output)
 };
 
 using FG = std::function<int(const std::vector<double>&, double&, std::vector<double>&)>;
@@ -54,9 +60,20 @@ constexpr double kFloat32Resolution = 1e-7;
 // noise_stop: end the line search once the predicted decrease is below the float32
 // resolution of f (used for the local ascent, whose result only seeds a new mass; the
 // sliding descents keep backtracking, which lets nearby masses finish merging).
+// slope_tol > 0 (the sliding descents): f comes from float32 volumes, so near a minimum its
+// decrease along a step sinks below f's own rounding (relative ~1e-7 to 1e-6) long before the
+// gradient, a float64 sum over many voxels, stops resolving the minimum. A step that fails the
+// sufficient-decrease test is then still taken when f stays within slope_tol |f| of its old
+// value and the slope along the step has not changed sign beyond the approximate Wolfe bound
+// of Hager and Zhang (2005): phi'(a) <= (2 delta - 1) phi'(0) with delta = 0.1. Once such
+// slope-only steps stop shrinking the projected gradient (no halving in kSlopeStall steps), the
+// descent has reached the working precision of the gradient and stops.
 MinResult minimize_box(const FG& fg, std::vector<double>& x, const std::vector<double>& lo,
                        const std::vector<double>& hi, int m, double gtol, double ftol,
-                       int maxiter, bool noise_stop = false) {
+                       int maxiter, bool noise_stop = false, double slope_tol = 0.0) {
+  constexpr int kSlopeStall = SFW_SLOPE_STALL;
+  double pg_ref = std::numeric_limits<double>::infinity();
+  int stall = 0;
   MinResult res;
   const int n = (int)x.size();
   for (int i = 0; i < n; ++i) x[i] = std::min(std::max(x[i], lo[i]), hi[i]);
@@ -82,7 +99,12 @@ MinResult minimize_box(const FG& fg, std::vector<double>& x, const std::vector<d
     res.iterations = it;
     if (pgmax <= gtol) {
       res.converged = true;
+      res.stop = "gtol";
       break;
+    }
+    if (pgmax < 0.5 * pg_ref) {
+      pg_ref = pgmax;
+      stall = 0;
     }
     // two-loop recursion on the free coordinates
     for (int i = 0; i < n; ++i) d[i] = freev[i] ? -g[i] : 0.0;
@@ -133,7 +155,7 @@ MinResult minimize_box(const FG& fg, std::vector<double>& x, const std::vector<d
       for (int i = 0; i < n; ++i) dmax = std::max(dmax, std::fabs(d[i]));
       step = dmax > 0 ? std::min(1.0, 1.0 / dmax) : 1.0;
     }
-    bool accepted = false;
+    bool accepted = false, by_slope = false;
     for (int ls = 0; ls < 40; ++ls) {
       double dec = 0.0;
       for (int i = 0; i < n; ++i) {
@@ -153,11 +175,21 @@ MinResult minimize_box(const FG& fg, std::vector<double>& x, const std::vector<d
         accepted = true;
         break;
       }
+      if (slope_tol > 0 && std::isfinite(fnew) &&
+          fnew <= f + slope_tol * std::max(std::fabs(f), 1.0)) {
+        double dnew = 0.0;  // slope at the new point along the step taken
+        for (int i = 0; i < n; ++i) dnew += gn[i] * (xn[i] - x[i]);
+        if (dnew <= -0.8 * dec) {
+          accepted = by_slope = true;
+          break;
+        }
+      }
       step *= (ls < 2 ? 0.5 : 0.25);
     }
     if (!accepted) {
       if (S.empty()) {  // even a steepest-descent step fails: stationary to working precision
         res.converged = true;
+        res.stop = "no descent step";
         break;
       }
       S.clear();
@@ -188,9 +220,16 @@ MinResult minimize_box(const FG& fg, std::vector<double>& x, const std::vector<d
         RHO.pop_front();
       }
     }
-    if (small_dec) {
+    if (by_slope && ++stall >= kSlopeStall) {  // the gradient's working precision
       res.iterations = it + 1;
       res.converged = true;
+      res.stop = "slope stall";
+      break;
+    }
+    if (small_dec && !by_slope) {
+      res.iterations = it + 1;
+      res.converged = true;
+      res.stop = "small decrease";
       break;
     }
     res.iterations = it + 1;
@@ -216,23 +255,23 @@ struct Solver {
   std::vector<double> atoms;
   int k() const { return (int)(atoms.size() / 6); }
 
+  // The atoms' kernel constants (AtomK, from the float32 parameters the kernels see) into
+  // ws->ak: computed here and copied, with no preparation kernel.
   int upload_atoms(const std::vector<double>& a, bool unit_weight) {
     const int n = (int)(a.size() / 6);
     if (n == 0) return SFW_OK;
-    sfw_atom* h = reinterpret_cast<sfw_atom*>(ws->hpin + ws->hp_atoms);
+    AtomK* h = reinterpret_cast<AtomK*>(ws->hpin + ws->hp_stage);
     for (int i = 0; i < n; ++i) {
-      h[i].w = (float)a[6 * i + 0];
-      h[i].mx = (float)a[6 * i + 1];
-      h[i].my = (float)a[6 * i + 2];
-      h[i].mz = (float)a[6 * i + 3];
-      h[i].sigma = (float)a[6 * i + 4];
-      h[i].d = (float)a[6 * i + 5];
+      const double* p = &a[6 * i];
+      h[i] = make_atomk(unit_weight ? 1.0 : (double)(float)p[0], (double)(float)p[1],
+                        (double)(float)p[2], (double)(float)p[3], (double)(float)p[4],
+                        (double)(float)p[5]);
     }
-    SFW_HIP(hipMemcpyAsync(ws->atoms_dev, h, sizeof(sfw_atom) * n, hipMemcpyHostToDevice,
-                           ws->stream));
-    // No wait here: the staging buffer is only rewritten by the next upload, and every caller
-    // synchronises the stream (its readback) before that, so the copy has finished by then.
-    return prep_all(ws, nullptr, plan, false, false, ws->atoms_dev, n, unit_weight);
+    SFW_HIP(hipMemcpyAsync(ws->ak, h, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
+    // No wait here: the staging buffer is only rewritten by the next upload (or an eta
+    // evaluation), and every caller synchronises the stream (its readback) before that, so the
+    // copy has finished by then.
+    return SFW_OK;
   }
 
   // C and dC/d(atoms) at a (float64 host), r and q left in the workspace.
@@ -242,7 +281,8 @@ struct Solver {
     if (rc) return rc;
     // the sums land in pinned host memory straight from the finalize kernel
     double* hs = ws->hpin + ws->hp_sums;
-    rc = op_cgrad(ws, plan, vol, y, (float)lam, ws->atoms_dev, n, nullptr, nullptr, nullptr, hs);
+    // no device atoms: the host adds lambda * sum w to the data term hs[6 n + 1]
+    rc = op_cgrad(ws, plan, vol, y, (float)lam, nullptr, n, nullptr, nullptr, nullptr, hs);
     if (rc) return rc;
     rc = sig_wait(ws, ws->sums_sig);
     if (rc) return rc;
@@ -309,10 +349,10 @@ struct Solver {
       return cgrad(x, f, &g);
     };
     MinResult r = minimize_box(fg, atoms, lo, hi, o.lbfgs_memory, o.slide_gtol, o.ftol,
-                               o.slide_max_iter);
+                               o.slide_max_iter, false, o.slide_slope_tol);
     if (o.verbose)
-      std::fprintf(stderr, "[sfw] slide n=%d it=%d evals=%d converged=%d C=%.12g\n", n,
-                   r.iterations, r.evaluations, (int)r.converged, r.f);
+      std::fprintf(stderr, "[sfw] slide n=%d it=%d evals=%d converged=%d (%s) C=%.12g\n", n,
+                   r.iterations, r.evaluations, (int)r.converged, r.stop, r.f);
     return r.status;
   }
 
@@ -329,122 +369,6 @@ struct Solver {
     if (rc) return rc;
     for (int i = 0; i < n; ++i) atoms[6 * i] = w[i];
     return SFW_OK;
-  }
-
-  // In float32 the final descent can leave a sliver: a mass of tiny weight beside a
-  // near-duplicate, held at a point where moving weight between the two costs nothing to
-  // first order (the float64 oracle drives such weights to exactly zero). A mass below
-  // kSliverRel of the largest weight is dropped when the weights-only LASSO of the other
-  // masses reaches a criterion no higher than the current one (relative kSliverTol): the
-  // criterion does not need it. Smallest weights are tried first; repeats until none drops.
-  int drop_slivers() {
-    constexpr double kSliverRel = 1e-3, kSliverTol = 1e-7;
-    for (;;) {
-      const int n = k();
-      if (n <= 1) return SFW_OK;
-      double wmax = 0.0;
-      for (int i = 0; i < n; ++i) wmax = std::max(wmax, atoms[6 * i]);
-      std::vector<int> cand;
-      for (int i = 0; i < n; ++i)
-        if (atoms[6 * i] < kSliverRel * wmax) cand.push_back(i);
-      if (cand.empty()) return SFW_OK;
-      std::sort(cand.begin(), cand.end(),
-                [&](int a, int b) { return atoms[6 * a] < atoms[6 * b]; });
-      double C0 = 0.0;
-      int rc = cgrad(atoms, C0, nullptr);
-      if (rc) return rc;
-      bool dropped = false;
-      const std::vector<double> keep = atoms;
-      for (int c : cand) {
-        atoms.clear();
-        for (int i = 0; i < n; ++i)
-          if (i != c) atoms.insert(atoms.end(), &keep[6 * i], &keep[6 * i] + 6);
-        rc = lasso();
-        if (rc) return rc;
-        double C1 = 0.0;
-        rc = cgrad(atoms, C1, nullptr);
-        if (rc) return rc;
-        if (o.verbose)
-          std::fprintf(stderr, "[sfw] sliver w=%.6g of %.6g: C %.12g -> %.12g\n", keep[6 * c],
-                       wmax, C0, C1);
-        if (C1 <= C0 + kSliverTol * std::fabs(C0)) {
-          dropped = true;
-          st.n_slivers++;
-          break;
-        }
-      }
-      if (!dropped) {
-        atoms = keep;
-        return SFW_OK;
-      }
-      prune();
-    }
-  }
-
-  // Two masses of the final support within a fraction of a width of each other can stand
-  // for one: the criterion is linear in the weights, so two copies of one atom equal a
-  // single atom of the summed weight, and the float64 descent drives such a pair together.
-  // In float32 the last part of that path is flatter than the criterion's resolution and
-  // the descent can stop with the pair split. Pairs whose centres are closer than
-  // kMergeDist times the smaller sigma are tried closest first: the pair becomes one mass
-  // with the summed weight at the weight-averaged parameters, the support slides, and the
-  // merge stays when the criterion is no higher than before (relative kSliverTol).
-  // Repeats until no pair merges.
-  int merge_pairs() {
-    constexpr double kMergeDist = 0.5, kSliverTol = 1e-7;
-    for (;;) {
-      const int n = k();
-      if (n <= 1) return SFW_OK;
-      std::vector<std::pair<double, std::pair<int, int>>> cand;
-      for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j) {
-          const double* a = &atoms[6 * i];
-          const double* b = &atoms[6 * j];
-          const double dist = std::sqrt((a[1] - b[1]) * (a[1] - b[1]) +
-                                        (a[2] - b[2]) * (a[2] - b[2]) +
-                                        (a[3] - b[3]) * (a[3] - b[3]));
-          if (dist < kMergeDist * std::min(a[4], b[4])) cand.push_back({dist, {i, j}});
-        }
-      if (cand.empty()) return SFW_OK;
-      std::sort(cand.begin(), cand.end());
-      double C0 = 0.0;
-      int rc = cgrad(atoms, C0, nullptr);
-      if (rc) return rc;
-      const std::vector<double> keep = atoms;
-      bool merged = false;
-      for (const auto& c : cand) {
-        const int i = c.second.first, j = c.second.second;
-        const double wi = keep[6 * i], wj = keep[6 * j], wsum = wi + wj;
-        atoms.clear();
-        for (int m = 0; m < n; ++m) {
-          if (m == j) continue;
-          atoms.insert(atoms.end(), &keep[6 * m], &keep[6 * m] + 6);
-          if (m == i && wsum > 0.0) {
-            double* a = &atoms[atoms.size() - 6];
-            a[0] = wsum;
-            for (int p = 1; p < 6; ++p) a[p] = (wi * keep[6 * i + p] + wj * keep[6 * j + p]) / wsum;
-          }
-        }
-        rc = slide();
-        if (rc) return rc;
-        double C1 = 0.0;
-        rc = cgrad(atoms, C1, nullptr);
-        if (rc) return rc;
-        if (o.verbose)
-          std::fprintf(stderr, "[sfw] merge %d,%d at %.4g: C %.12g -> %.12g\n", i, j, c.first,
-                       C0, C1);
-        if (C1 <= C0 + kSliverTol * std::fabs(C0)) {
-          merged = true;
-          st.n_merged++;
-          break;
-        }
-      }
-      if (!merged) {
-        atoms = keep;
-        return SFW_OK;
-      }
-      prune();
-    }
   }
 
   // Remove zero-weighted masses and merge coincident ones.
@@ -641,11 +565,7 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
           if (rc) return rc;
           S.prune();
         }
-        S.st.n_atoms_descent = S.k();
-        rc = S.merge_pairs();
-        if (rc) return rc;
-        rc = S.drop_slivers();
-        if (rc) return rc;
+
         S.st.seconds_slide += secs(ts, Clock::now());
         converged = true;
         break;
@@ -675,7 +595,6 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
     S.st.iterations = converged ? it : o.max_iter;
     S.st.converged = converged ? 1 : 0;
     S.st.n_atoms = n;
-    if (!converged) S.st.n_atoms_descent = n;
     S.st.criterion = C;
     S.st.seconds_total = secs(t0, Clock::now());
     if (stats) *stats = S.st;

@@ -7,8 +7,15 @@ Calls only the oracle and the seeded input drawer. Problems:
     h<i>    held-out volume i of the learned-proposal comparison (same workload as c3,
             seed 5000 + i)                                          -> solve_h<i>_bsfw.json
             (each 128 x 128 x 64 solve takes hours on one core)
+Each stored solution is the oracle's BSFW result, then polished: one more sliding descent from
+it with tight tolerances (gtol 1e-12, ftol 1e-16, at most 3000 iterations) and the pruning step.
+SciPy's L-BFGS-B stops on its relative-decrease test once an iteration gains less than ftol |C|,
+which on the 128 x 128 x 64 workload left a mass of weight 9e-5 beside one of 0.66 with
+dC/dw = +1.8e-3 (its weight still wants to fall to zero); parity is judged at converged optima,
+so the stored measure is the converged one. The solve's own result is kept as "atoms_solve".
 Usage:
     python tests/golden/make_solve_golden.py c2 [c3 h5 h7 ...]
+    python tests/golden/make_solve_golden.py --polish c3 ...   (polish a stored solve's result)
 Progress (one line per BSFW iteration) goes to stderr.
 """
 import json
@@ -52,7 +59,44 @@ def observation(prob):
     return psf, y, lam
 
 
+POLISH = {"gtol": 1e-12, "ftol": 1e-16, "maxiter": 3000}
+
+
+def polish(name, y, psf, lam, prob, atoms):
+    """The converged optimum near the solve's result: a sliding descent with tight tolerances,
+    then the pruning step (algorithm 2, steps 2b and 3b)."""
+    t0 = time.time()
+    C0, _ = oracle.criterion(y, atoms, psf, lam)
+    out = oracle.prune(oracle.slide(y, atoms, psf, lam, prob.bounds, **POLISH))
+    C1, _ = oracle.criterion(y, out, psf, lam)
+    print(f"[{name}] polish: {atoms.shape[0]} -> {out.shape[0]} atoms, C {C0:.9f} -> {C1:.9f} "
+          f"({time.time() - t0:.0f} s)", file=sys.stderr, flush=True)
+    return out, C1
+
+
+def polish_stored(names):
+    for name in names:
+        path = os.path.join(HERE, f"solve_{name}_bsfw.json")
+        with open(path) as fh:
+            out = json.load(fh)
+        prob = problem(name)
+        psf, y, lam = observation(prob)
+        assert lam == out["lambda"]
+        raw = np.asarray(out.get("atoms_solve", out["atoms"]), dtype=np.float64)
+        atoms, C = polish(name, y, psf, lam, prob, raw)
+        out["atoms_solve"] = [[float(v) for v in a] for a in raw]
+        out["criterion_solve"] = out.get("criterion_solve", out["criterion"])
+        out["atoms"] = [[float(v) for v in a] for a in atoms]
+        out["criterion"] = float(C)
+        out["polish"] = dict(POLISH)
+        with open(path, "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(name, "atoms", len(out["atoms"]), "criterion", out["criterion"], flush=True)
+
+
 def main(names):
+    if names and names[0] == "--polish":
+        return polish_stored(names[1:])
     for name in names:
         prob = problem(name)
         cfg = prob.config
@@ -65,14 +109,18 @@ def main(names):
                   f"eta* {h['eta_star']:.6f} ({time.time() - t0:.0f} s)", file=sys.stderr, flush=True)
 
         res = oracle.solve(y, psf, lam, sg, cfg.d_grid, prob.bounds, mode="BSFW", log=log)
+        seconds = time.time() - t0
+        atoms, C = polish(name, y, psf, lam, prob, res.atoms)
         wl = WORKLOAD.get(name, WORKLOAD["c3"] + f", held-out volume {name[1:]} "
                           f"(seed {prob.seed})")
         out = {"workload": wl, "seed": int(prob.seed), "mode": "BSFW", "lambda": lam,
                "sigma_grid": sg, "d_grid": list(cfg.d_grid),
                "converged": bool(res.converged), "iterations": int(res.iterations),
                "largest_support": int(max([h["n_atoms"] for h in res.history] + [0])),
-               "criterion": float(res.criterion), "seconds": time.time() - t0,
-               "atoms": [[float(v) for v in a] for a in res.atoms]}
+               "criterion": float(C), "seconds": seconds, "polish": dict(POLISH),
+               "criterion_solve": float(res.criterion),
+               "atoms_solve": [[float(v) for v in a] for a in res.atoms],
+               "atoms": [[float(v) for v in a] for a in atoms]}
         with open(os.path.join(HERE, f"solve_{name}_bsfw.json"), "w") as fh:
             json.dump(out, fh, indent=1)
         print(name, "atoms", len(out["atoms"]), "criterion", out["criterion"],

