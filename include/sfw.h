@@ -110,6 +110,14 @@ typedef struct {
                                         of C) is taken on its slope (approximate Wolfe test)
                                         when it fails the sufficient-decrease test; default
                                         1e-6, 0 = sufficient decrease only */
+  int32_t graphs;                    /* 1 (default): the (C, grad C) evaluations of a solve whose
+                                        launch arguments repeat (the sliding descents) replay
+                                        one captured HIP graph; 0 = every kernel launched */
+  int32_t autotune;                  /* 1 (default): the render's z planes per thread and the
+                                        gradient sums' block count are timed once per volume
+                                        shape and power-of-two atom-count bucket on the
+                                        workspace, which keeps the choice (every candidate
+                                        gives the same results bit for bit); 0 = defaults */
 } sfw_options;
 
 /* Per-solve statistics (host memory). */
@@ -126,6 +134,8 @@ typedef struct {
   double seconds_total, seconds_certificate, seconds_ascent, seconds_lasso, seconds_slide;
   int32_t n_proposals;       /* seeds from the proposal network */
   int32_t n_fallbacks;       /* of which the grid maximum had to replace (0 or 1) */
+  int32_t n_graph_replays;   /* (C, grad C) evaluations replayed from a captured graph */
+  int32_t n_tunings;         /* launch shapes timed by the autotuner during this solve */
 } sfw_stats;
 
 /* ---------------------------------------------------------------- lifecycle */

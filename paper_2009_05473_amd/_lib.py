@@ -59,7 +59,8 @@ class SfwOptions(ctypes.Structure):
         ("lbfgs_memory", ctypes.c_int32), ("check_finite", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("proposal", ctypes.c_void_p),
         ("init_atoms", ctypes.c_void_p), ("n_init", ctypes.c_int32),
-        ("slide_slope_tol", ctypes.c_double),
+        ("slide_slope_tol", ctypes.c_double), ("graphs", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
     ]
 
 
@@ -72,7 +73,8 @@ class SfwStats(ctypes.Structure):
         ("seconds_total", ctypes.c_double), ("seconds_certificate", ctypes.c_double),
         ("seconds_ascent", ctypes.c_double), ("seconds_lasso", ctypes.c_double),
         ("seconds_slide", ctypes.c_double), ("n_proposals", ctypes.c_int32),
-        ("n_fallbacks", ctypes.c_int32),
+        ("n_fallbacks", ctypes.c_int32), ("n_graph_replays", ctypes.c_int32),
+        ("n_tunings", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <limits>
 #include <new>
 #include <string>
 
@@ -195,17 +197,16 @@ int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, 
   return conv_psf(ws, p, vol, false, ws->f, phi, kEpiPlain, nullptr, kProfConvForward);
 }
 
-int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
-             float lambda, const sfw_atom* atoms_dev, int n, float* r_out, double* loss_out,
-             sfw_atom* grad_out, double* sums) {
-  float* r = r_out ? r_out : ws->r;
+// The chain of a (C, grad C) evaluation up to the per-tile gradient sums: render, blur with the
+// residual and its loss partials, adjoint, gradient sums (everything but the final reduction).
+static int cgrad_chain(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
+                       int n, float* r, const GradPlan& gp, int render_vpt) {
   {
     ProfScope ps(ws, kProfRender);
-    SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream));
+    SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream, render_vpt));
   }
   if (p.fft && p.blur.chain) {
     // residual and adjoint share the plane pass between them (see launch_blur_residual_chain)
-    if ((size_t)p.nres > ws->dpart_cap) return fail(SFW_EINVAL, "loss partial buffer too small");
     {
       ProfScope ps(ws, kProfConvResidual);
       SFW_HIP(launch_blur_residual_chain(p.blur, ws->f, vol, ws->blur_hhat, y, r, ws->dpart,
@@ -220,14 +221,143 @@ int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
     rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr, kProfConvAdjoint);
     if (rc) return rc;
   }
-  ws->q_valid = true;
-  GradPlan gp = plan_grad(vol, n);
+  ProfScope ps(ws, kProfGrad);
+  SFW_HIP(launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream));
+  return SFW_OK;
+}
+
+// Enqueue the chain, or replay it from a graph (ws->graphs, no profiling): a chain whose launch
+// arguments repeat those of the previous evaluation is captured into a graph, which later
+// evaluations with the same arguments replay in one launch. Nothing in the chain sets memory
+// with a memset; every kernel writes all it reads later.
+static int cgrad_enqueue(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
+                         const float* y, int n, float* r, const GradPlan& gp, int render_vpt) {
+  if (!ws->graphs || ws->prof_on)
+    return cgrad_chain(ws, p, vol, y, n, r, gp, render_vpt);
+  const std::vector<long long> key = {
+      vol.nx, vol.ny, vol.nz, n, p.fft, p.blur.chain, p.mfma, p.psf.nx, p.psf.ny, p.psf.nz,
+      p.blur.N[0], p.blur.N[1], p.blur.N[2], (long long)(uintptr_t)y, (long long)(uintptr_t)r,
+      gp.ntiles, gp.groups, gp.apg, p.nres, render_vpt};
+  if (ws->cg_exec && key == ws->cg_key) {
+    SFW_HIP(hipGraphLaunch(ws->cg_exec, ws->stream));
+    ws->cg_replays++;
+    return SFW_OK;
+  }
+  if (key != ws->cg_seen) {  // first time with these arguments: run it as it is
+    ws->cg_seen = key;
+    return cgrad_chain(ws, p, vol, y, n, r, gp, render_vpt);
+  }
+  if (!ws->cap_stream)
+    SFW_HIP(hipStreamCreateWithFlags(&ws->cap_stream, hipStreamNonBlocking));
+  hipStream_t run = ws->stream;
+  ws->stream = ws->cap_stream;
+  hipError_t e = hipStreamBeginCapture(ws->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    ws->stream = run;
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  const int rc = cgrad_chain(ws, p, vol, y, n, r, gp, render_vpt);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(ws->stream, &g);
+  ws->stream = run;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  if (ws->cg_exec) {
+    (void)hipGraphExecDestroy(ws->cg_exec);
+    ws->cg_exec = nullptr;
+  }
+  e = hipGraphInstantiate(&ws->cg_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    ws->cg_exec = nullptr;
+    ws->cg_key.clear();
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  ws->cg_key = key;
+  ws->cg_captures++;
+  SFW_HIP(hipGraphLaunch(ws->cg_exec, ws->stream));
+  return SFW_OK;
+}
+
+// Launch shapes of the chain for (vol, n): the defaults, or, with ws->tune_on, the fastest of
+// the candidates, timed once per (volume shape, power-of-two bucket of n) on the workspace's own
+// buffers (ws->ak must hold the atoms; the render writes ws->f and the gradient sums read ws->q
+// and write ws->gpart, all rewritten by the evaluation that follows). The candidates give the
+// same results bit for bit, so the choice, which depends on timing, never changes a result.
+static int chain_shape(sfw_workspace* ws, const sfw_dims& vol, int n,
+                       sfw_workspace::TuneChoice& c) {
+  c = sfw_workspace::TuneChoice();
+  if (!ws->tune_on || n <= 0) return SFW_OK;
+  int nb = 1;
+  while (nb < n) nb <<= 1;
+  const std::vector<int> key = {vol.nx, vol.ny, vol.nz, nb};
+  auto it = ws->tune.find(key);
+  if (it != ws->tune.end()) {
+    c = it->second;
+    return SFW_OK;
+  }
+  if (!ws->tune_ev[0]) {
+    SFW_HIP(hipEventCreate(&ws->tune_ev[0]));
+    SFW_HIP(hipEventCreate(&ws->tune_ev[1]));
+  }
+  auto timed = [&](const std::function<hipError_t()>& launch, float& best) -> int {
+    best = std::numeric_limits<float>::infinity();
+    for (int rep = 0; rep < 3; ++rep) {
+      SFW_HIP(hipEventRecord(ws->tune_ev[0], ws->stream));
+      SFW_HIP(launch());
+      SFW_HIP(hipEventRecord(ws->tune_ev[1], ws->stream));
+      SFW_HIP(hipEventSynchronize(ws->tune_ev[1]));
+      float ms = 0.f;
+      SFW_HIP(hipEventElapsedTime(&ms, ws->tune_ev[0], ws->tune_ev[1]));
+      best = std::min(best, ms);
+    }
+    return SFW_OK;
+  };
+  float best_r = std::numeric_limits<float>::infinity();
+  for (int vpt : {4, 8, 16}) {
+    float t = 0.f;
+    int rc = timed([&] { return launch_render(ws->ak, n, vol, ws->f, ws->stream, vpt); }, t);
+    if (rc) return rc;
+    if (t < best_r) {
+      best_r = t;
+      c.render_vpt = vpt;
+    }
+  }
+  float best_g = std::numeric_limits<float>::infinity();
+  for (int blocks : {256, 512, 1024}) {
+    const GradPlan gp = plan_grad(vol, n, blocks);
+    if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap) continue;
+    float t = 0.f;
+    int rc = timed([&] { return launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream); }, t);
+    if (rc) return rc;
+    if (t < best_g) {
+      best_g = t;
+      c.grad_blocks = blocks;
+    }
+  }
+  ws->tune[key] = c;
+  ws->tune_runs++;
+  return SFW_OK;
+}
+
+int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
+             float lambda, const sfw_atom* atoms_dev, int n, float* r_out, double* loss_out,
+             sfw_atom* grad_out, double* sums) {
+  float* r = r_out ? r_out : ws->r;
+  if (p.fft && p.blur.chain && (size_t)p.nres > ws->dpart_cap)
+    return fail(SFW_EINVAL, "loss partial buffer too small");
+  sfw_workspace::TuneChoice shape;
+  int rc = chain_shape(ws, vol, n, shape);
+  if (rc) return rc;
+  GradPlan gp = plan_grad(vol, n, shape.grad_blocks);
   if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
     return fail(SFW_EINVAL, "gradient partial buffer too small");
-  {
-    ProfScope ps(ws, kProfGrad);
-    SFW_HIP(launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream));
-  }
+  rc = cgrad_enqueue(ws, p, vol, y, n, r, gp, shape.render_vpt);
+  if (rc) return rc;
+  ws->q_valid = true;
   ProfScope ps(ws, kProfGradFinalize);
   // sums for the host: the finalize kernel signals them (ws->sums_sig)
   ws->sums_sig = sums ? sig_arm(ws) : kNoSig;
@@ -826,6 +956,8 @@ int sfw_default_options(sfw_options* o) {
   o->check_finite = 1;
   o->verbose = 0;
   o->slide_slope_tol = 1e-6;
+  o->graphs = 1;
+  o->autotune = 1;
   return SFW_OK;
 }
 
@@ -835,6 +967,10 @@ void sfw_workspace_destroy(sfw_workspace* ws) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(ws->device);
   if (ws->stream) (void)hipStreamSynchronize(ws->stream);
+  if (ws->cg_exec) (void)hipGraphExecDestroy(ws->cg_exec);
+  if (ws->cap_stream) (void)hipStreamDestroy(ws->cap_stream);
+  for (hipEvent_t e : ws->tune_ev)
+    if (e) (void)hipEventDestroy(e);
   float* fbufs[] = {ws->f, ws->phi, ws->r, ws->q, ws->tmpv, ws->wt_fwd, ws->wt_adj, ws->am_fwd,
                     ws->am_adj, ws->lut, ws->gpart, ws->cols};
   for (float* b : fbufs)

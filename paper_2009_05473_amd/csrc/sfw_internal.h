@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -55,7 +56,7 @@ constexpr int kConvMaxLds = 64 * 1024;
 constexpr int kMfmaPatchMax = 512;
 
 // Voxel columns of the render kernel: 256 threads over the flattened (y, x) plane,
-// kRenderVPT consecutive z per thread.
+// kRenderVPT consecutive z per thread by default (4, 8 or 16: the autotuner's candidates).
 constexpr int kRenderVPT = 8;
 // Reduction kernel: 256 threads over the flattened (y, x) plane, VPT z per thread.
 constexpr int kGradThreads = 256;
@@ -257,6 +258,28 @@ struct sfw_workspace {
   size_t hp_best = 0;   // sfw_argmax written by the certificate's final kernel
 
   // optional per-kernel-class event timing (sfw_profile_begin / end)
+  // The solver's (C, grad C) chain (render, blur with residual, adjoint, gradient sums),
+  // captured once its launch arguments repeat and replayed while they stay the same (key).
+  // Captured on cap_stream (work recorded there is never run there); replayed on `stream`.
+  bool graphs = false;  // set by sfw_solve for its duration (sfw_options.graphs)
+
+  // Autotuned launch shapes of the (C, grad C) chain per (volume shape, atom-count bucket):
+  // the render's z planes per thread and the gradient sums' target block count, chosen by
+  // timing every candidate once on the workspace's own buffers (ws->tune_on, set by sfw_solve
+  // from sfw_options.autotune). Every candidate gives the same results bit for bit.
+  struct TuneChoice {
+    int render_vpt = sfw::kRenderVPT;
+    int grad_blocks = 512;
+  };
+  std::map<std::vector<int>, TuneChoice> tune;
+  bool tune_on = false;
+  int tune_runs = 0;
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t cg_exec = nullptr;
+  std::vector<long long> cg_key, cg_seen;
+  int cg_replays = 0, cg_captures = 0;
+
   bool prof_on = false;
   unsigned prof_mask = 0;  // bit k: class k is timed
   int prof_used = 0;
@@ -317,7 +340,10 @@ int sig_wait(sfw_workspace* ws, const SigArgs& s);
 
 // ---- launchers (sfw_kernels.hip); each returns a hipError_t from the launch
 ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz);
-GradPlan plan_grad(sfw_dims vol, int n_atoms);
+// Gradient-sum tiles of 16 x 16 x 16 voxels over the volume, atoms split into groups so that
+// about target_blocks blocks run (the autotuner's candidates: 256, 512, 1024); the grouping does
+// not change any sum (each tile's partial of an atom is computed the same way).
+GradPlan plan_grad(sfw_dims vol, int n_atoms, int target_blocks = 512);
 // Plan over the tiles that meet box {x0, x1, y0, y1, z0, z1} (voxels, half-open).
 GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6], bool deep = false);
 
@@ -337,7 +363,10 @@ hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t
                                const sfw_atom* atoms, int n, unsigned long long* part,
                                unsigned long long* out, float* atoms_out, const SigArgs& sig,
                                hipStream_t st);
-hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st);
+// vpt: z planes per thread, 4, 8 or 16 (the same f bit for bit: every voxel sums its nonzero
+// atoms in index order whatever the tile).
+hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st,
+                         int vpt = kRenderVPT);
 
 enum ConvEpilogue { kEpiPlain = 0, kEpiResidual = 1, kEpiArgmax = 2, kEpiColumn = 3 };
 // out = conv(in, W) with W in [ky][kx][kzp] layout (already flipped for a correlation).
@@ -369,7 +398,7 @@ hipError_t launch_conv_mfma_region(const float* in, const float* amat, sfw_dims 
                                    const ConvRegion& rg, float* out, hipStream_t st);
 // out = H * (w g) of the atom *atom on box = [x0, x1, y0, y1, z0, z1) only (H in its [z][y][x]
 // layout), the atom computed on the fly; the rest of out is left untouched. column_box_ok: the
-// PSF fits the kernel (P_x <= 33, P_z <= 31, LDS tile).
+// PSF fits the kernel (P_x <= 33, P_z <= 33, LDS tile).
 constexpr int kColumnBoxMaxLds = 160 * 1024;
 bool column_box_ok(sfw_dims psf);
 // box_out (device int[6], may be null) receives the box.

@@ -291,12 +291,12 @@ __device__ __forceinline__ AtomK lane_atom(const AtomK& m, int i) {
 // ------------------------------------------------------------------ render
 
 // f(s) = sum_n w_n exp(-u_n(s)) for every voxel; thread = one (y, x) column of a 16 x 16 tile
-// (blockIdx.x), kRenderVPT planes (blockIdx.y). Each wave evaluates only the atoms whose cut
+// (blockIdx.x), VPT planes (blockIdx.y). Each wave evaluates only the atoms whose cut
 // ball meets its voxels (wave_hits); the others add exact zeros there. Atoms are summed in
 // increasing index order.
+template <int VPT>
 __global__ __launch_bounds__(256) void k_render(const AtomK* __restrict__ ak, int n, int nx,
                                                 int ny, int nz, float* __restrict__ f) {
-  constexpr int VPT = kRenderVPT;
   const TileXY t = tile_xy(blockIdx.x, nx, ny);
   const int nxy = nx * ny;
   const int x = min(t.x, nx - 1), y = min(t.y, ny - 1);
@@ -1214,14 +1214,13 @@ ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz) {
   return p;
 }
 
-GradPlan plan_grad(sfw_dims vol, int n_atoms) {
+GradPlan plan_grad(sfw_dims vol, int n_atoms, int target_blocks) {
   GradPlan p;
   p.vpt = 16;  // a wave's box is 16 x 4 x 16 voxels: atoms are culled along z as well
   p.rtx = (vol.nx + kTile - 1) / kTile;
   p.ntile_xy = p.rtx * ((vol.ny + kTile - 1) / kTile);
   p.ntile_z = (vol.nz + p.vpt - 1) / p.vpt;
   p.ntiles = p.ntile_xy * p.ntile_z;
-  const int target_blocks = 512;
   int groups = (target_blocks + p.ntiles - 1) / p.ntiles;
   if (groups > n_atoms) groups = n_atoms;
   if (groups < 1) groups = 1;
@@ -1329,10 +1328,22 @@ hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t
   return hipGetLastError();
 }
 
-hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st) {
+hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st, int vpt) {
   const int tiles = ((vol.nx + kTile - 1) / kTile) * ((vol.ny + kTile - 1) / kTile);
-  dim3 grid(tiles, (vol.nz + kRenderVPT - 1) / kRenderVPT);
-  hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
+  dim3 grid(tiles, (vol.nz + vpt - 1) / vpt);
+  switch (vpt) {
+    case 4:
+      hipLaunchKernelGGL(k_render<4>, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_render<8>, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_render<16>, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1555,7 +1566,7 @@ static size_t column_box_lds(sfw_dims psf) {
 
 bool column_box_ok(sfw_dims psf) {
   // tile rows of at most one wave of x, P_z a supported template, the LDS of one CU
-  return kBoxTX + psf.nx - 1 <= 64 && psf.nz <= 31 &&
+  return kBoxTX + psf.nx - 1 <= 64 && psf.nz <= 33 &&
          column_box_lds(psf) <= (size_t)kColumnBoxMaxLds;
 }
 
@@ -1582,7 +1593,7 @@ hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sf
     SFW_BOX_CASE(1) SFW_BOX_CASE(3) SFW_BOX_CASE(5) SFW_BOX_CASE(7) SFW_BOX_CASE(9)
     SFW_BOX_CASE(11) SFW_BOX_CASE(13) SFW_BOX_CASE(15) SFW_BOX_CASE(17) SFW_BOX_CASE(19)
     SFW_BOX_CASE(21) SFW_BOX_CASE(23) SFW_BOX_CASE(25) SFW_BOX_CASE(27) SFW_BOX_CASE(29)
-    SFW_BOX_CASE(31)
+    SFW_BOX_CASE(31) SFW_BOX_CASE(33)
 #undef SFW_BOX_CASE
     default:
       return hipErrorInvalidValue;

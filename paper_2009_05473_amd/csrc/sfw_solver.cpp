@@ -453,6 +453,21 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
       return fail(SFW_EINVAL, "opts.proposal must enqueue on the workspace's stream");
     S.V = (size_t)vol.nx * vol.ny * vol.nz;
     S.plan = plan_psf(ws, vol, psf);
+    // graph replays of the (C, grad C) chain for this solve only
+    // and autotuned launch shapes (kept in the workspace beyond the solve)
+    struct GraphScope {
+      sfw_workspace* ws;
+      int replays0, tunings0;
+      GraphScope(sfw_workspace* w, bool graphs, bool tune)
+          : ws(w), replays0(w->cg_replays), tunings0(w->tune_runs) {
+        ws->graphs = graphs;
+        ws->tune_on = tune;
+      }
+      ~GraphScope() {
+        ws->graphs = false;
+        ws->tune_on = false;
+      }
+    } graph_scope(ws, o.graphs != 0, o.autotune != 0);
     const auto t0 = Clock::now();
 
     if (o.check_finite) {
@@ -595,6 +610,8 @@ extern "C" int sfw_solve(sfw_workspace* ws, const float* y, sfw_dims vol, const 
     S.st.iterations = converged ? it : o.max_iter;
     S.st.converged = converged ? 1 : 0;
     S.st.n_atoms = n;
+    S.st.n_graph_replays = ws->cg_replays - graph_scope.replays0;
+    S.st.n_tunings = ws->tune_runs - graph_scope.tunings0;
     S.st.criterion = C;
     S.st.seconds_total = secs(t0, Clock::now());
     if (stats) *stats = S.st;

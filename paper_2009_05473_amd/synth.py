@@ -200,13 +200,13 @@ def batch_config(rng: np.random.Generator, index: int) -> Config:
     n_x, n_y, N, PSF sigma_xy, PSF sigma_z: n_x, n_y in {48, 56, ..., 96}, n_z = 48,
     N ~ U{5..40}, the 64x64x32 workload's atom distributions, noise and grid, and an
     anisotropic Gaussian PSF with sigma_xy ~ U[1, 2], sigma_z ~ U[2, 4] cut at
-    ceil(3.5 sigma) per axis (P_z <= 29)."""
+    ceil(4 sigma) per axis (P_xy <= 17, P_z <= 33)."""
     nx = int(rng.choice(BATCH_SHAPES_XY))
     ny = int(rng.choice(BATCH_SHAPES_XY))
     n_atoms = int(rng.integers(5, 41))
     sxy = float(rng.uniform(1.0, 2.0))
     sz = float(rng.uniform(2.0, 4.0))
-    hxy, hz = int(np.ceil(3.5 * sxy)), int(np.ceil(3.5 * sz))
+    hxy, hz = int(np.ceil(4.0 * sxy)), int(np.ceil(4.0 * sz))
     return replace(CONFIGS["c2"], name=f"b{index}", shape=(48, ny, nx), n_atoms=n_atoms,
                    psf_sigma_xy=sxy, psf_sigma_z=sz, psf_shape=(2 * hz + 1, 2 * hxy + 1, 2 * hxy + 1))
 

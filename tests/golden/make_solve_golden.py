@@ -7,6 +7,7 @@ Calls only the oracle and the seeded input drawer. Problems:
     h<i>    held-out volume i of the learned-proposal comparison (same workload as c3,
             seed 5000 + i)                                          -> solve_h<i>_bsfw.json
             (each 128 x 128 x 64 solve takes hours on one core)
+    b<i>    volume i of the batched-solve workload (synth.draw_batch) -> solve_b<i>_bsfw.json
 Each stored solution is the oracle's BSFW result, then polished: one more sliding descent from
 it with tight tolerances (gtol 1e-12, ftol 1e-16, at most 3000 iterations) and the pruning step.
 SciPy's L-BFGS-B stops on its relative-decrease test once an iteration gains less than ftol |C|,
@@ -37,6 +38,9 @@ def problem(name):
         return synth.draw_problem(name)
     if name.startswith("h"):
         return synth.draw_held_out(int(name[1:]))
+    if name.startswith("b"):
+        i = int(name[1:])
+        return synth.draw_batch(i + 1)[i]
     raise SystemExit(f"unknown problem {name!r}")
 
 
@@ -111,8 +115,14 @@ def main(names):
         res = oracle.solve(y, psf, lam, sg, cfg.d_grid, prob.bounds, mode="BSFW", log=log)
         seconds = time.time() - t0
         atoms, C = polish(name, y, psf, lam, prob, res.atoms)
-        wl = WORKLOAD.get(name, WORKLOAD["c3"] + f", held-out volume {name[1:]} "
-                          f"(seed {prob.seed})")
+        if name.startswith("b"):
+            nz, ny, nx = prob.shape
+            pz, py, px = cfg.psf_shape
+            wl = (f"batch volume {name[1:]}: {nx} x {ny} x {nz}, {cfg.n_atoms} atoms, "
+                  f"{px} x {py} x {pz} PSF, noise 0.02 max (seed {prob.seed})")
+        else:
+            wl = WORKLOAD.get(name, WORKLOAD["c3"] + f", held-out volume {name[1:]} "
+                              f"(seed {prob.seed})")
         out = {"workload": wl, "seed": int(prob.seed), "mode": "BSFW", "lambda": lam,
                "sigma_grid": sg, "d_grid": list(cfg.d_grid),
                "converged": bool(res.converged), "iterations": int(res.iterations),

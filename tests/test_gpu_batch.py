@@ -5,6 +5,8 @@ deterministic and the items share nothing), whichever workspace takes it; a fail
 fails alone and is named. Problems: the first volumes of the batched-solve workload
 (synth.draw_batch), y built with the library's forward model.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -27,7 +29,7 @@ def say(*msg):
     print("[case]", *msg, flush=True)
 
 
-VOL_MAX, PSF_MAX, MAX_ATOMS = (48, 96, 96), (29, 15, 15), 96
+VOL_MAX, PSF_MAX, MAX_ATOMS = (48, 96, 96), (33, 17, 17), 96
 
 
 def dev(a):
@@ -121,3 +123,49 @@ def test_batch_repeats_exactly_on_fresh_and_reused_workspaces(L, batch):
     for i in range(len(data)):
         assert np.array_equal(first[i][0], again[i][0]), ("reused", i)
         assert np.array_equal(first[i][0], fresh[i][0]), ("fresh", i)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_batch_items_match_oracle(L):
+    """Two items of the batched-solve workload (volumes 2 and 4 of synth.draw_batch) solved by
+    sfw_solve_batch on two workspaces, on the oracle's observations, against the oracle's
+    converged BSFW solutions stored by tests/golden/make_solve_golden.py: the same number of
+    masses, every centre within 0.05 voxel of the oracle's, criterion within 1e-5 (relative)."""
+    import json
+
+    import oracle
+    names = [n for n in ("b2", "b4") if os.path.exists(os.path.join(GOLDEN, f"solve_{n}_bsfw.json"))]
+    assert names, "no stored batch solutions"
+    goldens, problems = [], []
+    for name in names:
+        with open(os.path.join(GOLDEN, f"solve_{name}_bsfw.json")) as fh:
+            g = json.load(fh)
+        i = int(name[1:])
+        prob = synth.draw_batch(i + 1)[i]
+        psf = prob.psf.astype(np.float32).astype(np.float64)
+        clean = oracle.blur(oracle.render(prob.shape, prob.atoms_true), psf)
+        y = synth.make_observation(clean, prob.noise_unit, prob.config.noise_rel)
+        goldens.append(g)
+        problems.append((dev(y), dev(psf), g["lambda"]))
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    wss = [L.Workspace(VOL_MAX, PSF_MAX, MAX_ATOMS, stream=s) for s in streams]
+    try:
+        torch.cuda.synchronize()
+        say("sfw_solve_batch on stored oracle solutions", names)
+        opts = L.default_options(mode="BSFW", sigma_grid=goldens[0]["sigma_grid"],
+                                 d_grid=goldens[0]["d_grid"])
+        res = L.sfw_solve_batch(wss, problems, opts)
+    finally:
+        for w in wss:
+            w.close()
+    for name, g, (atoms, st, code) in zip(names, goldens, res):
+        ref = np.asarray(g["atoms"])
+        say(name, "atoms", atoms.shape[0], "oracle", ref.shape[0], "criterion", st["criterion"],
+            "oracle", g["criterion"])
+        assert code == L.SFW_OK
+        assert atoms.shape[0] == ref.shape[0]
+        for t in ref:
+            assert np.min(np.linalg.norm(atoms[:, 1:4] - t[1:4], axis=1)) <= 0.05
+        assert abs(st["criterion"] - g["criterion"]) <= 1e-5 * g["criterion"]

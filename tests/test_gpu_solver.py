@@ -186,3 +186,82 @@ def test_solve_rejects_bad_init_atoms(L, ws):
     with pytest.raises(L.SfwError) as e:
         L.sfw_solve(ws, dev(y), dev(psf), lam, init_atoms=bad)
     assert e.value.code == L.SFW_EINVAL
+
+
+@pytest.mark.parametrize("mode", ["BSFW", "SFW"])
+def test_graph_replays_match_eager_launches(L, ws, mode):
+    """The sliding descents replay the (C, grad C) chain from a captured HIP graph
+    (opts.graphs). Every replay feeds the descent, with eager kernels (certificate, eta, LASSO)
+    and host waits between replays, so a solve whose result equals, bit for bit, the solve with
+    every kernel launched eagerly checks every replay against the eager evaluation."""
+    prob, psf, y, lam = c1_problem(True)
+    sg = [float(np.float32(v)) for v in prob.config.sigma_grid]
+    out = {}
+    for graphs in (0, 1, 1):  # the second graph solve starts with the graph already captured
+        say("sfw_solve c1", mode, "graphs", graphs)
+        opts = L.default_options(mode=mode, sigma_grid=sg, d_grid=prob.config.d_grid,
+                                 graphs=graphs, autotune=graphs)
+        atoms, st, code = L.sfw_solve(ws, dev(y), dev(psf), lam, opts)
+        assert code == L.SFW_OK
+        out.setdefault(graphs, []).append((atoms, st))
+    (a0, s0), = out[0]
+    assert s0["n_graph_replays"] == 0
+    for a1, s1 in out[1]:
+        assert s1["n_graph_replays"] > 0
+        np.testing.assert_array_equal(a1, a0)
+        assert s1["criterion"] == s0["criterion"]
+        assert s1["n_eval_cgrad"] == s0["n_eval_cgrad"]
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+LARGE = [n for n in ("c3", "h5", "h7") if os.path.exists(os.path.join(GOLDEN, f"solve_{n}_bsfw.json"))]
+
+
+@pytest.mark.parametrize("name", LARGE)
+def test_solve_matches_oracle_golden_128(L, name):
+    """BSFW at 128 x 128 x 64 with 50 true atoms (the bench workload's seed, and held-out volumes
+    of the learned-proposal comparison) against the oracle's converged solution stored by
+    tests/golden/make_solve_golden.py, on the same observation: the same number of masses, every
+    centre within 0.05 voxel of the oracle's, criterion within 1e-5 (relative)."""
+    with open(os.path.join(GOLDEN, f"solve_{name}_bsfw.json")) as fh:
+        golden = json.load(fh)
+    prob = synth.draw_problem("c3") if name == "c3" else synth.draw_held_out(int(name[1:]))
+    psf = f32(prob.psf)
+    clean = oracle.blur(oracle.render(prob.shape, prob.atoms_true), psf)
+    y = f32(synth.make_observation(clean, prob.noise_unit, prob.config.noise_rel))
+    ws = L.Workspace(prob.shape, psf.shape, 128)
+    try:
+        opts = L.default_options(mode="BSFW", sigma_grid=golden["sigma_grid"],
+                                 d_grid=golden["d_grid"])
+        say("sfw_solve 128x128x64 BSFW vs stored oracle solution", name)
+        atoms, stats, code = L.sfw_solve(ws, dev(y), dev(psf), golden["lambda"], opts)
+    finally:
+        ws.close()
+    assert code == L.SFW_OK
+    ref = np.asarray(golden["atoms"])
+    say(name, "atoms", atoms.shape[0], "oracle", ref.shape[0], "criterion", stats["criterion"],
+        "oracle", golden["criterion"])
+    assert atoms.shape[0] == ref.shape[0]
+    assert match(atoms, ref, 0.05)
+    assert abs(stats["criterion"] - golden["criterion"]) <= 1e-5 * golden["criterion"]
+
+
+def test_autotuned_shapes_are_kept_and_change_nothing(L):
+    """The autotuner times the render's and the gradient sums' launch shapes once per volume shape
+    and atom-count bucket and keeps the choice in the workspace: a second solve on the same
+    workspace times nothing, and both equal, bit for bit, a solve with the default shapes."""
+    prob, psf, y, lam = c1_problem(True)
+    sg = [float(np.float32(v)) for v in prob.config.sigma_grid]
+    with L.Workspace((32, 32, 32), (15, 9, 9), 64) as w:
+        runs = []
+        for tune in (0, 1, 1):
+            say("sfw_solve c1 autotune", tune)
+            opts = L.default_options(sigma_grid=sg, d_grid=prob.config.d_grid, autotune=tune)
+            atoms, st, code = L.sfw_solve(w, dev(y), dev(psf), lam, opts)
+            assert code == L.SFW_OK
+            runs.append((atoms, st))
+    (a0, s0), (a1, s1), (a2, s2) = runs
+    assert s0["n_tunings"] == 0 and s1["n_tunings"] > 0 and s2["n_tunings"] == 0
+    for a, st in ((a1, s1), (a2, s2)):
+        np.testing.assert_array_equal(a, a0)
+        assert st["criterion"] == s0["criterion"]
