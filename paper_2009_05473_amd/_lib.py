@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsfw.so")
+# SFW_LIB_PATH: another build of the same library (the host-sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("SFW_LIB_PATH") or os.path.join(_HERE, "libsfw.so")
 
 SFW_OK, SFW_EINVAL, SFW_ENOMEM, SFW_EHIP, SFW_ECAP, SFW_ENOCONV = 0, -1, -2, -3, -4, -5
 SFW_MODE_BSFW, SFW_MODE_SFW = 0, 1
