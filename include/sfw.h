@@ -88,7 +88,7 @@ typedef struct {
   int32_t slide_max_iter;            /* default 1000 */
   double ascent_gtol, slide_gtol;    /* projected-gradient tolerances, default 1e-9 */
   double ftol;                       /* relative decrease tolerance, default 1e-12 */
-  int32_t lbfgs_memory;              /* curvature pairs kept, default 10 */
+  int32_t lbfgs_memory;              /* curvature pairs kept, default 40 */
   int32_t check_finite;              /* reject NaN/Inf in y and H, default 1 */
   int32_t verbose;                   /* print one line per iteration to stderr */
   sfw_net* proposal;                 /* NULL (default): step 1 seeds the local ascent at the

@@ -952,7 +952,7 @@ int sfw_default_options(sfw_options* o) {
   o->ascent_gtol = 1e-9;
   o->slide_gtol = 1e-9;
   o->ftol = 1e-12;
-  o->lbfgs_memory = 10;
+  o->lbfgs_memory = 40;
   o->check_finite = 1;
   o->verbose = 0;
   o->slide_slope_tol = 1e-6;

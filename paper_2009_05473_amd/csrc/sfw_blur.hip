@@ -727,7 +727,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv_fwd(
 // for kx < hx, every ky and kz; float64 sums, stored at [(kz Ny + ky) px + kx]. Block:
 // 32 columns kx of row ky = blockIdx.y. S(tz, kx) = sum_{ty, tx} H w_y w_x goes through LDS.
 constexpr int kHhatCols = 32;
-constexpr int kHhatMaxPz = 31;
+constexpr int kHhatMaxPz = 33;
 constexpr int kHhatMaxTaps = 8192;  // PSF staged in LDS
 
 // hcache holds the PSF and grid the stored spectrum was computed for: ints [0, 6) = (P_x, P_y,
