@@ -63,7 +63,8 @@ ATOM_CUT_U = 110.0
 
 def evaluated_pairs(shape, atoms, box):
     """Voxel-atom pairs the kernels evaluate: for every wave box (x, y, z) tiling the volume,
-    64 lanes x box z voxels (clipped to the volume) per atom whose cut ball meets the box."""
+    box x * box y lanes (every lane computes, past the volume's edge too) x box z planes
+    (clipped to the volume) per atom whose cut ball meets the box."""
     nz, ny, nx = shape
     bx, by, bz = box
     a = np.asarray(atoms, dtype=np.float64)
@@ -79,7 +80,7 @@ def evaluated_pairs(shape, atoms, box):
             x1 = np.minimum(x0 + bx, nx) - 1
             dx = np.maximum(0.0, np.maximum(x0[:, None] - a[None, :, 1], a[None, :, 1] - x1[:, None]))
             hit = dx * dx + (dy * dy + dz * dz)[None, :] <= (r * r)[None, :]
-            total += int(hit.sum()) * 64 * (z1 - z0 + 1)
+            total += int(hit.sum()) * bx * by * (z1 - z0 + 1)
     return total
 
 

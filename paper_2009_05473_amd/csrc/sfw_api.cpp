@@ -200,10 +200,10 @@ int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, 
 // The chain of a (C, grad C) evaluation up to the per-tile gradient sums: render, blur with the
 // residual and its loss partials, adjoint, gradient sums (everything but the final reduction).
 static int cgrad_chain(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
-                       int n, float* r, const GradPlan& gp, int render_vpt) {
+                       int n, float* r, const sfw_workspace::TuneChoice& shape) {
   {
     ProfScope ps(ws, kProfRender);
-    SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream, render_vpt));
+    SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream, shape.render_vpt));
   }
   if (p.fft && p.blur.chain) {
     // residual and adjoint share the plane pass between them (see launch_blur_residual_chain)
@@ -222,7 +222,8 @@ static int cgrad_chain(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
     if (rc) return rc;
   }
   ProfScope ps(ws, kProfGrad);
-  SFW_HIP(launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream));
+  SFW_HIP(launch_grad_items(ws->ak, n, ws->q, vol, ws->gpart, ws->gitem, shape.grad_blocks,
+                            ws->stream));
   return SFW_OK;
 }
 
@@ -231,13 +232,13 @@ static int cgrad_chain(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
 // evaluations with the same arguments replay in one launch. Nothing in the chain sets memory
 // with a memset; every kernel writes all it reads later.
 static int cgrad_enqueue(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
-                         const float* y, int n, float* r, const GradPlan& gp, int render_vpt) {
-  if (!ws->graphs || ws->prof_on)
-    return cgrad_chain(ws, p, vol, y, n, r, gp, render_vpt);
+                         const float* y, int n, float* r,
+                         const sfw_workspace::TuneChoice& shape) {
+  if (!ws->graphs || ws->prof_on) return cgrad_chain(ws, p, vol, y, n, r, shape);
   const std::vector<long long> key = {
       vol.nx, vol.ny, vol.nz, n, p.fft, p.blur.chain, p.mfma, p.psf.nx, p.psf.ny, p.psf.nz,
       p.blur.N[0], p.blur.N[1], p.blur.N[2], (long long)(uintptr_t)y, (long long)(uintptr_t)r,
-      gp.ntiles, gp.groups, gp.apg, p.nres, render_vpt};
+      p.nres, shape.render_vpt, shape.grad_blocks};
   if (ws->cg_exec && key == ws->cg_key) {
     SFW_HIP(hipGraphLaunch(ws->cg_exec, ws->stream));
     ws->cg_replays++;
@@ -245,18 +246,20 @@ static int cgrad_enqueue(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vo
   }
   if (key != ws->cg_seen) {  // first time with these arguments: run it as it is
     ws->cg_seen = key;
-    return cgrad_chain(ws, p, vol, y, n, r, gp, render_vpt);
+    return cgrad_chain(ws, p, vol, y, n, r, shape);
   }
   if (!ws->cap_stream)
     SFW_HIP(hipStreamCreateWithFlags(&ws->cap_stream, hipStreamNonBlocking));
   hipStream_t run = ws->stream;
   ws->stream = ws->cap_stream;
-  hipError_t e = hipStreamBeginCapture(ws->stream, hipStreamCaptureModeThreadLocal);
+  // relaxed: the sequence holds kernel launches only, and the solves of other workspaces
+  // (sfw_solve_batch's threads) keep synchronising their own streams meanwhile
+  hipError_t e = hipStreamBeginCapture(ws->stream, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) {
     ws->stream = run;
     return hip_fail(e, "hipStreamBeginCapture");
   }
-  const int rc = cgrad_chain(ws, p, vol, y, n, r, gp, render_vpt);
+  const int rc = cgrad_chain(ws, p, vol, y, n, r, shape);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(ws->stream, &g);
   ws->stream = run;
@@ -285,8 +288,10 @@ static int cgrad_enqueue(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vo
 // Launch shapes of the chain for (vol, n): the defaults, or, with ws->tune_on, the fastest of
 // the candidates, timed once per (volume shape, power-of-two bucket of n) on the workspace's own
 // buffers (ws->ak must hold the atoms; the render writes ws->f and the gradient sums read ws->q
-// and write ws->gpart, all rewritten by the evaluation that follows). The candidates give the
-// same results bit for bit, so the choice, which depends on timing, never changes a result.
+// and write ws->gpart and ws->gitem, all rewritten by the evaluation that follows). The
+// candidates give the same results bit for bit (the render's tiles sum every voxel's atoms in
+// the same order; the gradient items are the same whatever the grid size), so the choice, which
+// depends on timing, never changes a result.
 static int chain_shape(sfw_workspace* ws, const sfw_dims& vol, int n,
                        sfw_workspace::TuneChoice& c) {
   c = sfw_workspace::TuneChoice();
@@ -327,11 +332,11 @@ static int chain_shape(sfw_workspace* ws, const sfw_dims& vol, int n,
     }
   }
   float best_g = std::numeric_limits<float>::infinity();
-  for (int blocks : {256, 512, 1024}) {
-    const GradPlan gp = plan_grad(vol, n, blocks);
-    if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap) continue;
+  for (int blocks : {1024, 2048, 4096}) {
     float t = 0.f;
-    int rc = timed([&] { return launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream); }, t);
+    int rc = timed([&] {
+      return launch_grad_items(ws->ak, n, ws->q, vol, ws->gpart, ws->gitem, blocks, ws->stream);
+    }, t);
     if (rc) return rc;
     if (t < best_g) {
       best_g = t;
@@ -349,19 +354,18 @@ int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
   float* r = r_out ? r_out : ws->r;
   if (p.fft && p.blur.chain && (size_t)p.nres > ws->dpart_cap)
     return fail(SFW_EINVAL, "loss partial buffer too small");
+  if ((size_t)grad_item_tiles(vol) * n * 6 > ws->gpart_cap)
+    return fail(SFW_EINVAL, "gradient partial buffer too small");
   sfw_workspace::TuneChoice shape;
   int rc = chain_shape(ws, vol, n, shape);
   if (rc) return rc;
-  GradPlan gp = plan_grad(vol, n, shape.grad_blocks);
-  if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
-    return fail(SFW_EINVAL, "gradient partial buffer too small");
-  rc = cgrad_enqueue(ws, p, vol, y, n, r, gp, shape.render_vpt);
+  rc = cgrad_enqueue(ws, p, vol, y, n, r, shape);
   if (rc) return rc;
   ws->q_valid = true;
   ProfScope ps(ws, kProfGradFinalize);
   // sums for the host: the finalize kernel signals them (ws->sums_sig)
   ws->sums_sig = sums ? sig_arm(ws) : kNoSig;
-  SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, ws->dpart, p.nres, atoms_dev, lambda,
+  SFW_HIP(launch_grad_finalize(ws->gpart, 0, ws->gitem, n, ws->dpart, p.nres, atoms_dev, lambda,
                                sums ? sums : ws->dres, grad_out, loss_out, ws->stream, false,
                                ws->sums_sig));
   return SFW_OK;
@@ -373,20 +377,20 @@ int op_vjp(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float
   if (rc) return rc;
   ws->q_valid = true;
   if (n == 0) return SFW_OK;
-  GradPlan gp = plan_grad(vol, n);
-  if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
+  if ((size_t)grad_item_tiles(vol) * n * 6 > ws->gpart_cap)
     return fail(SFW_EINVAL, "gradient partial buffer too small");
   {
     ProfScope ps(ws, kProfGrad);
-    SFW_HIP(launch_grad(gp, ws->ak, n, ws->q, vol, ws->gpart, ws->stream));
+    SFW_HIP(launch_grad_items(ws->ak, n, ws->q, vol, ws->gpart, ws->gitem,
+                              sfw_workspace::TuneChoice().grad_blocks, ws->stream));
   }
   ProfScope ps(ws, kProfGradFinalize);
-  SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, nullptr, 0, atoms_dev, 0.f, ws->dres,
+  SFW_HIP(launch_grad_finalize(ws->gpart, 0, ws->gitem, n, nullptr, 0, atoms_dev, 0.f, ws->dres,
                                grad_out, nullptr, ws->stream, true));
   return SFW_OK;
 }
 
-GradPlan plan_points(const AtomK* hk, int n, const sfw_dims& vol, bool one_group) {
+GradPlan plan_points(const AtomK* hk, int n, const sfw_dims& vol) {
   // only the tiles where some point's atom is nonzero (its cut ball) carry terms
   int box[6] = {vol.nx, 0, vol.ny, 0, vol.nz, 0};
   const int nv[3] = {vol.nx, vol.ny, vol.nz};
@@ -405,12 +409,7 @@ GradPlan plan_points(const AtomK* hk, int n, const sfw_dims& vol, bool one_group
       box[2 * a] = 0;
       box[2 * a + 1] = 1;
     }
-  GradPlan gp = plan_grad_box(vol, n, box, one_group);
-  if (one_group) {
-    gp.groups = 1;
-    gp.apg = n;
-  }
-  return gp;
+  return plan_grad_box(vol, box);
 }
 
 int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double lambda,
@@ -426,8 +425,9 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
   const bool one_launch = n <= kAtomArgs;
   if (!one_launch)
     SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
-  GradPlan gp = plan_points(hk, n, vol, one_launch);
-  if ((size_t)gp.ntiles * n * 6 > ws->gpart_cap)
+  GradPlan gp;
+  if (one_launch) gp = plan_points(hk, n, vol);
+  if ((size_t)(one_launch ? gp.ntiles : grad_item_tiles(vol)) * n * 6 > ws->gpart_cap)
     return fail(SFW_EINVAL, "gradient partial buffer too small");
   double* hs = ws->hpin + ws->hp_sums;
   SigArgs sig = kNoSig;
@@ -438,9 +438,10 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
       SFW_HIP(launch_grad_points(gp, hk, n, q, vol, ws->gpart, ws->eta_ticket, hs, sig,
                                  ws->stream));
     } else {
-      SFW_HIP(launch_grad(gp, ws->ak, n, q, vol, ws->gpart, ws->stream));
-      SFW_HIP(launch_grad_finalize(ws->gpart, gp.ntiles, n, nullptr, 0, nullptr, 0.f, ws->dres,
-                                   nullptr, nullptr, ws->stream));
+      SFW_HIP(launch_grad_items(ws->ak, n, q, vol, ws->gpart, ws->gitem,
+                                sfw_workspace::TuneChoice().grad_blocks, ws->stream));
+      SFW_HIP(launch_grad_finalize(ws->gpart, 0, ws->gitem, n, nullptr, 0, nullptr, 0.f,
+                                   ws->dres, nullptr, nullptr, ws->stream));
     }
   }
   if (!one_launch)
@@ -540,7 +541,10 @@ static int lut_prepare(sfw_workspace* ws, const float* sg, int ns, const float* 
       fft_twiddles(pl.ax[a].n, tw);
       all.insert(all.end(), tw.begin(), tw.end());
     }
-    SFW_HIP(hipMemcpy(ws->fft_tw, all.data(), all.size() * sizeof(float2), hipMemcpyHostToDevice));
+    // on the workspace's stream (`all` lives until the synchronisation below): nothing here
+    // goes through the null stream, which another thread's solve may be capturing beside
+    SFW_HIP(hipMemcpyAsync(ws->fft_tw, all.data(), all.size() * sizeof(float2),
+                           hipMemcpyHostToDevice, ws->stream));
     pl.ax[0].tw = ws->fft_tw;
     pl.ax[1].tw = ws->fft_tw + pl.ax[0].n;
     pl.ax[2].tw = ws->fft_tw + pl.ax[0].n + pl.ax[1].n;
@@ -992,6 +996,7 @@ void sfw_workspace_destroy(sfw_workspace* ws) {
   if (ws->blur_hcache) (void)hipFree(ws->blur_hcache);
   if (ws->blur_changed) (void)hipFree(ws->blur_changed);
   if (ws->eta_ticket) (void)hipFree(ws->eta_ticket);
+  if (ws->gitem) (void)hipFree(ws->gitem);
   if (ws->hpin) (void)hipHostFree(ws->hpin);
   if (ws->sig_flag) (void)hipHostFree(ws->sig_flag);
   if (ws->sig_ticket) (void)hipFree(ws->sig_ticket);
@@ -1065,6 +1070,7 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
                           ((vol_max.nz + 15) / 16);
     ws->gpart_cap = gtiles * na * 6;
     ALLOC(ws->gpart, ws->gpart_cap * 4, "gradient partials");
+    ALLOC(ws->gitem, sizeof(int) * (na + 1), "gradient item offsets");
     const size_t cblocks = (size_t)((vol_max.nx + kConvTX - 1) / kConvTX) *
                            ((vol_max.ny + kConvTY - 1) / kConvTY) *
                            ((vol_max.nz + kConvRZ - 1) / kConvRZ);

@@ -58,9 +58,8 @@ constexpr int kMfmaPatchMax = 512;
 // Voxel columns of the render kernel: 256 threads over the flattened (y, x) plane,
 // kRenderVPT consecutive z per thread by default (4, 8 or 16: the autotuner's candidates).
 constexpr int kRenderVPT = 8;
-// Reduction kernel: 256 threads over the flattened (y, x) plane, VPT z per thread.
+// Gradient-sum kernels: 256 threads over a 16 x 16 tile of (y, x) columns, VPT z per thread.
 constexpr int kGradThreads = 256;
-constexpr int kGradMaxAtomsPerGroup = 64;
 
 // 2^-100: added to the in-plane squared distance so log2(r^2) stays finite at an atom
 // centre; every derivative term carrying r^2 then vanishes there as in the limit.
@@ -141,15 +140,13 @@ enum ProfKind {
 };
 constexpr int kProfPool = 16384;
 
+// Tiles of the gradient sums at a few points (k_grad_points).
 struct GradPlan {
   int vpt = 16;       // z voxels per thread (template parameter)
   int ntile_xy = 0;   // 16 x 16 (y, x) tiles covered
   int ntile_z = 0;
   int ntiles = 0;     // ntile_xy * ntile_z
-  int groups = 1;     // atom groups (second grid dimension)
-  int apg = 0;        // atoms per group
-  // covered region: x tiles [rx0, rx0 + rtx), y tiles from ry0, z tiles from rz0 (the whole
-  // volume unless restricted to where the atoms are nonzero)
+  // covered region: x tiles [rx0, rx0 + rtx), y tiles from ry0, z tiles from rz0
   int rx0 = 0, ry0 = 0, rtx = 1, rz0 = 0;
 };
 
@@ -222,8 +219,9 @@ struct sfw_workspace {
   sfw::AtomK* ak = nullptr;       // [max_atoms + 1]
 
   // reduction partials
-  float* gpart = nullptr;   // [tiles][atoms][6]
+  float* gpart = nullptr;   // gradient partials: [items][6], or [tiles][atoms][6] (points)
   size_t gpart_cap = 0;     // floats
+  int* gitem = nullptr;     // [max_atoms + 1] first item of each atom (launch_grad_items)
   double* dpart = nullptr;  // loss / dot partials
   size_t dpart_cap = 0;     // doubles
   double* dres = nullptr;   // [8 * (max_atoms + 2) + 64] float64 results
@@ -264,12 +262,12 @@ struct sfw_workspace {
   bool graphs = false;  // set by sfw_solve for its duration (sfw_options.graphs)
 
   // Autotuned launch shapes of the (C, grad C) chain per (volume shape, atom-count bucket):
-  // the render's z planes per thread and the gradient sums' target block count, chosen by
-  // timing every candidate once on the workspace's own buffers (ws->tune_on, set by sfw_solve
-  // from sfw_options.autotune). Every candidate gives the same results bit for bit.
+  // the render's z planes per thread and the gradient sums' grid size, chosen by timing every
+  // candidate once on the workspace's own buffers (ws->tune_on, set by sfw_solve from
+  // sfw_options.autotune). Every candidate gives the same results bit for bit.
   struct TuneChoice {
     int render_vpt = sfw::kRenderVPT;
-    int grad_blocks = 512;
+    int grad_blocks = 2048;
   };
   std::map<std::vector<int>, TuneChoice> tune;
   bool tune_on = false;
@@ -340,12 +338,9 @@ int sig_wait(sfw_workspace* ws, const SigArgs& s);
 
 // ---- launchers (sfw_kernels.hip); each returns a hipError_t from the launch
 ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz);
-// Gradient-sum tiles of 16 x 16 x 16 voxels over the volume, atoms split into groups so that
-// about target_blocks blocks run (the autotuner's candidates: 256, 512, 1024); the grouping does
-// not change any sum (each tile's partial of an atom is computed the same way).
-GradPlan plan_grad(sfw_dims vol, int n_atoms, int target_blocks = 512);
-// Plan over the tiles that meet box {x0, x1, y0, y1, z0, z1} (voxels, half-open).
-GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6], bool deep = false);
+// Points-kernel tiles (16 x 16 columns, 16 to 64 planes deep) that meet box
+// {x0, x1, y0, y1, z0, z1} (voxels, half-open).
+GradPlan plan_grad_box(sfw_dims vol, const int box[6]);
 
 // One launch: atom constants (atoms may be null when n == 0) and the forward / adjoint PSF
 // operands for the matrix-core (mfma) or VALU (kzp) convolution (H may be null).
@@ -363,8 +358,9 @@ hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t
                                const sfw_atom* atoms, int n, unsigned long long* part,
                                unsigned long long* out, float* atoms_out, const SigArgs& sig,
                                hipStream_t st);
-// vpt: z planes per thread, 4, 8 or 16 (the same f bit for bit: every voxel sums its nonzero
-// atoms in index order whatever the tile).
+// vpt: z planes per thread, 4, 8 or 16 (the same f bit for bit: every voxel takes its offsets
+// to the atom centres from its own coordinates and sums its nonzero atoms in index order,
+// whatever the tile).
 hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st,
                          int vpt = kRenderVPT);
 
@@ -405,24 +401,31 @@ bool column_box_ok(sfw_dims psf);
 hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sfw_dims vol,
                              const int box[6], float* out, int* box_out, hipStream_t st);
 
-// The per-atom sums of at most kAtomArgs atoms given by their constants on the host (one atom
-// group: p.groups == 1), reduced to sums_out[6 a + c] (float64; may be host memory) by the last
-// block; ticket: device int that is 0 between launches.
+// The per-atom sums of at most kAtomArgs atoms given by their constants on the host, reduced
+// to sums_out[6 a + c] (float64; may be host memory) by the last block; ticket: device int that
+// is 0 between launches.
 hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n, const float* q,
                               sfw_dims vol, float* gpart, int* ticket, double* sums_out,
                               const SigArgs& sig, hipStream_t st);
-hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q, sfw_dims vol,
-                       float* gpart, hipStream_t st);
-// Sums partials over tiles in a fixed order (float64). For atom a:
+// The gradient sums of the atoms ak[0, n) against q, one partial per item (an atom on one of
+// the 16 x 16 x 16 volume tiles its cut ball may reach) at gpart[6 i + c]; atom a's items are
+// item_start[a] .. item_start[a + 1] - 1 (device, n + 1 ints, written by the kernel). At most
+// n * grad_item_tiles(vol) items. `blocks` (grid size) changes no result.
+int grad_item_tiles(sfw_dims vol);
+hipError_t launch_grad_items(const AtomK* ak, int n, const float* q, sfw_dims vol, float* gpart,
+                             int* item_start, int blocks, hipStream_t st);
+// Sums partials in a fixed order (float64): over the ntiles tiles of the tile layout
+// (launch_grad_points), or over the atom's items when item_start is given (launch_grad_items).
+// For atom a:
 //   sums[a*6 + 0..5] = (S_g, S_u, S_l, S_mx, S_my, S_mz)
 // with S_g = sum q g, S_u = sum q g u', S_l = sum q g u' log2 r^2,
 // S_m = sum q g u' (s - m) / r^2 and u' = u log2(e). If loss_part != nullptr,
 // sums[6 n] = 1/2 sum of the nloss loss partials. If grad_out != nullptr, also writes the
 // gradient of C (float) using atoms and lambda, or with vjp the vector-Jacobian product
 // sum_s q df/d(w, m, sigma, d) of the forward model (lambda unused).
-hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const double* loss_part,
-                                int nloss, const sfw_atom* atoms, float lambda,
-                                double* sums, sfw_atom* grad_out, double* loss_out,
+hipError_t launch_grad_finalize(const float* gpart, int ntiles, const int* item_start, int n,
+                                const double* loss_part, int nloss, const sfw_atom* atoms,
+                                float lambda, double* sums, sfw_atom* grad_out, double* loss_out,
                                 hipStream_t st, bool vjp = false,
                                 const SigArgs& sig = kNoSig);
 // The maximum goes to best (device) and, when best_host is not null, to pinned host memory.

@@ -2,9 +2,11 @@
 // gradient reduction, grid certificate and its maximum, LASSO dot products).
 //
 // The paper computes the convolutions in the Fourier domain and parallelises C and grad C
-// across atoms (section 2). Here every operator is a direct, data-parallel kernel:
-// voxel columns for the atom sums, LDS-staged input tiles with register blocking along z
-// for the convolutions, and wavefront DPP reductions for the per-atom gradient sums.
+// across atoms (section 2). The Fourier-domain blur and certificate are in sfw_blur.hip and
+// sfw_fft*.hip; this file holds the data-parallel kernels beside them: voxel columns for the
+// atom sums, LDS-staged input tiles with register blocking along z for the direct
+// convolutions (the blur's second and third paths), and wavefront DPP reductions for the
+// per-atom gradient sums.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -316,10 +318,9 @@ __global__ __launch_bounds__(256) void k_render(const AtomK* __restrict__ ak, in
       const float dx = fx - k.mx;
       const float dy = fy - k.my;
       const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
-      const float dz0 = fz0 - k.mz;
 #pragma unroll
       for (int j = 0; j < VPT; ++j) {
-        const float dz = dz0 + (float)j;
+        const float dz = (fz0 + (float)j) - k.mz;  // z - m_z of this voxel, whatever VPT is
         const float r2 = fmaf(dz, dz, dxy2);
         const float l = fast_log2(r2);
         const float up = fast_exp2(fmaf(k.hd, l, k.c));  // u * log2(e)
@@ -718,30 +719,30 @@ __global__ __launch_bounds__(512) void k_conv_mfma(
   }
 }
 
-// ------------------------------------------------------------------ gradient sums
+// ------------------------------------------------------------------ gradient sums at points
 
-// Per-atom sums over a tile of voxels (block = 256 (y, x) columns x VPT z); grid.x = tiles,
-// grid.y = atom groups. Writes gpart[tile][atom][0..5] =
-// (S_g, S_u, S_l, S_mx, S_my, S_mz) of the tile (see launch_grad_finalize), zero for atoms whose
-// cut ball misses the tile. Each wave evaluates only the atoms whose cut ball meets its voxels
-// (wave_hits; the other terms are exact zeros).
-// With POINTS, the atoms come by value in `args` (at most kAtomArgs, one atom group) and the
-// last block to finish (ticket counter) sums the tile partials over tiles in a fixed order, in
-// float64, into sums_out[6 a + c]: one launch per evaluation of the certificate at a few
-// points, with nothing left for the host but one synchronisation. sums_out may be pinned host
-// memory: the kernel's writes to it are visible once the stream has been synchronised.
-template <int VPT, bool POINTS>
-__global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__ ak,
-                                                       AtomArgs args, int n, int apg,
-                                                       const float* __restrict__ q, int nx,
-                                                       int ny, int nz, int ntile_xy, int rx0,
-                                                       int ry0, int rtx, int rz0,
-                                                       float* __restrict__ gpart,
-                                                       int* __restrict__ ticket,
-                                                       double* __restrict__ sums_out,
-                                                       SigArgs sig) {
+// The per-atom sums of eta and its gradient at a few points (at most kAtomArgs unit-weight
+// atoms, by value in `args`) in one launch: block = 256 (y, x) columns x VPT z of the region
+// (ntile_xy tiles of 16 x 16 columns from tile (rx0, ry0), rtx per row, z tiles from rz0).
+// Each wave evaluates only the atoms whose cut ball meets its 16 x 4 x VPT voxels (the other
+// terms are exact zeros) and the tile partial gpart[tile][atom][0..5] = (S_g, S_u, S_l, S_mx,
+// S_my, S_mz) is the four wave sums added in wave order; the last block to finish (ticket
+// counter) sums the tile partials over tiles in a fixed order, in float64, into
+// sums_out[6 a + c]. Nothing is left for the host but one synchronisation; sums_out may be
+// pinned host memory: the kernel's writes to it are visible once the stream has been
+// synchronised.
+template <int VPT>
+__global__ __launch_bounds__(kGradThreads) void k_grad_points(AtomArgs args, int n,
+                                                              const float* __restrict__ q, int nx,
+                                                              int ny, int nz, int ntile_xy,
+                                                              int rx0, int ry0, int rtx, int rz0,
+                                                              float* __restrict__ gpart,
+                                                              int* __restrict__ ticket,
+                                                              double* __restrict__ sums_out,
+                                                              SigArgs sig) {
   constexpr int NW = kGradThreads / 64;
-  __shared__ float red[NW][64][6];
+  static_assert(kAtomArgs <= 64, "one atom list per wave");
+  __shared__ float red[NW][kAtomArgs][6];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int tile = blockIdx.x;
@@ -758,40 +759,19 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
   for (int j = 0; j < VPT; ++j)
     qv[j] = (pin && z0 + j < nz) ? q[(size_t)(z0 + j) * nxy + p] : 0.f;
   const float fx = (float)x, fy = (float)y, fz0 = (float)z0;
-  const int ga0 = blockIdx.y * apg;
-  const int ga1 = min(n, ga0 + apg);
   const int wave = tid / 64;
   const WaveBox wb = wave_box(t, nx, ny, z0, min(z0 + VPT, nz) - 1);
-  for (int a0 = ga0; a0 < ga1; a0 += 64) {
-    const int a1 = min(ga1, a0 + 64);
-    AtomK mine{};
-    unsigned long long m;
-    if (POINTS) {  // a handful of atoms straight from the arguments
-      m = 0;
-      for (int i = 0; i < a1 - a0; ++i) {
-        const AtomK k = args.a[a0 + i];
-        if (lane == i) mine = k;
-        if (!wb.misses(k)) m |= 1ull << i;
-      }
-    } else {
-      m = wave_hits(ak, a0, a1, wb, mine);
-    }
-    if (lane < a1 - a0 && !((m >> lane) & 1ull)) {  // this wave's terms of that atom are zero
-#pragma unroll
-      for (int c = 0; c < 6; ++c) red[wave][lane][c] = 0.f;
-    }
-    while (m) {
-      const int i = __builtin_ctzll(m);
-      m &= m - 1;
-      const AtomK k = lane_atom(mine, i);
+  for (int i = 0; i < n; ++i) {
+    const AtomK k = args.a[i];
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
+    if (!wb.misses(k)) {
       const float dx = fx - k.mx;
       const float dy = fy - k.my;
       const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
-      const float dz0 = fz0 - k.mz;
       float sg = 0.f, su = 0.f, sl = 0.f, sc = 0.f, scz = 0.f;
 #pragma unroll
       for (int j = 0; j < VPT; ++j) {
-        const float dz = dz0 + (float)j;
+        const float dz = (fz0 + (float)j) - k.mz;
         const float r2 = fmaf(dz, dz, dxy2);
         const float l = fast_log2(r2);
         const float vp = fast_exp2(fmaf(k.hdm1, l, k.c));  // u log2(e) / r^2
@@ -806,81 +786,248 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(const AtomK* __restrict__
         sc += c2;
         scz = fmaf(c2, dz, scz);
       }
-      const float s0 = wave_sum(sg);
-      const float s1 = wave_sum(su);
-      const float s2 = wave_sum(sl);
-      const float s3 = wave_sum(sc * dx);
-      const float s4 = wave_sum(sc * dy);
-      const float s5 = wave_sum(scz);
-      if (lane == 0) {
-        float* rr = red[wave][i];
-        rr[0] = s0;
-        rr[1] = s1;
-        rr[2] = s2;
-        rr[3] = s3;
-        rr[4] = s4;
-        rr[5] = s5;
-      }
+      s0 = wave_sum(sg);
+      s1 = wave_sum(su);
+      s2 = wave_sum(sl);
+      s3 = wave_sum(sc * dx);
+      s4 = wave_sum(sc * dy);
+      s5 = wave_sum(scz);
+    }
+    if (lane == 0) {
+      float* rr = red[wave][i];
+      rr[0] = s0;
+      rr[1] = s1;
+      rr[2] = s2;
+      rr[3] = s3;
+      rr[4] = s4;
+      rr[5] = s5;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < n * 6; e += kGradThreads) {
+    const int aa = e / 6, c = e - aa * 6;
+    float v = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v += red[w][aa][c];
+    gpart[(size_t)tile * n * 6 + e] = v;
+  }
+  __shared__ int is_last;
+  __shared__ double part[kGradThreads];
+  static_assert(kAtomArgs * 6 <= 64, "the sums must be written by the first wave");
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) is_last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    // the whole block sums the tiles: slice sl of (atom, component) pr takes the tiles
+    // tt = sl (mod nsl), then one thread per pr adds its slices in order (fixed order)
+    const int pairs = n * 6, ntiles = gridDim.x;
+    const int nsl = kGradThreads / pairs;
+    if (tid < pairs * nsl) {
+      const int pr = tid % pairs, sl = tid / pairs;
+      double acc = 0.0;
+#pragma unroll 4
+      for (int tt = sl; tt < ntiles; tt += nsl) acc += (double)gpart[(size_t)tt * pairs + pr];
+      part[sl * pairs + pr] = acc;
     }
     __syncthreads();
-    const int cnt = (a1 - a0) * 6;
-    for (int i = tid; i < cnt; i += kGradThreads) {
-      const int aa = i / 6, c = i - aa * 6;
+    if (tid < pairs) {
+      double S = 0.0;
+      for (int sl = 0; sl < nsl; ++sl) S += part[sl * pairs + tid];
+      sums_out[tid] = S;
+    }
+    if (tid == 0) *ticket = 0;  // ready for the next launch
+    signal_host(sig, 1);
+  }
+}
+
+// ------------------------------------------------------------------ gradient sums per item
+
+// The gradient sums of a (C, grad C) evaluation with the work spread evenly over the blocks:
+// an item is one atom on one 16 x 16 x 16 volume tile (the tiles of k_grad) that meets the
+// bounding box of the atom's cut ball, grown by a voxel; block b takes items b, b + gridDim.x,
+// ... (every item costs about the same, where the per-tile atom lists of k_grad leave a few
+// blocks with many atoms). Items go atom by atom (the atom's tiles with x fastest), so atom a
+// owns items [start[a], start[a + 1]); every block computes these offsets itself (the atom
+// constants are all it needs), keeping the atoms and their tile ranges in LDS (up to
+// kItemsLdsAtoms atoms; beyond, they are read again per item), and block 0 stores the offsets
+// in item_start for launch_grad_finalize.
+// Item i writes gpart[6 i + c] = (S_g, S_u, S_l, S_mx, S_my, S_mz) of its atom over its tile:
+// the four wave sums added in wave order, as k_grad's tile partial (a wave whose 16 x 4 x 16
+// box the cut ball misses adds exact zeros and skips them). No partial depends on gridDim.x.
+struct ItemBox {
+  int tx, ty, tz;  // first tile per axis
+  int cx, cy, cz;  // tiles per axis (0 when the cut ball misses the volume)
+};
+constexpr int kItemsLdsAtoms = 1024;
+__device__ __forceinline__ void item_axis(float m, float R, int n, int& t0, int& cnt) {
+  const float lo = fmaxf(0.f, floorf(m - R) - 1.f);
+  const float hi = fminf((float)(n - 1), ceilf(m + R) + 1.f);
+  if (lo <= hi) {
+    t0 = (int)lo / kTile;
+    cnt = (int)hi / kTile - t0 + 1;
+  } else {
+    t0 = 0;
+    cnt = 0;
+  }
+}
+__device__ __forceinline__ ItemBox item_box(const AtomK& k, int nx, int ny, int nz) {
+  const float R = sqrtf(k.rcut2);
+  ItemBox b;
+  item_axis(k.mx, R, nx, b.tx, b.cx);
+  item_axis(k.my, R, ny, b.ty, b.cy);
+  item_axis(k.mz, R, nz, b.tz, b.cz);
+  return b;
+}
+
+__global__ __launch_bounds__(kGradThreads) void k_grad_items(const AtomK* __restrict__ ak, int n,
+                                                             const float* __restrict__ q, int nx,
+                                                             int ny, int nz,
+                                                             float* __restrict__ gpart,
+                                                             int* __restrict__ item_start) {
+  constexpr int VPT = kTile, NW = kGradThreads / 64;
+  // dynamic LDS: item offsets [n + 1], then (cache) atoms [n] and their tile ranges [n]
+  extern __shared__ __align__(16) unsigned char items_lds[];
+  const bool cache = n <= kItemsLdsAtoms;
+  int* starts = reinterpret_cast<int*>(items_lds);
+  AtomK* atoms = reinterpret_cast<AtomK*>(items_lds + ((size_t)(n + 1) * sizeof(int) + 15) / 16 * 16);
+  ItemBox* boxes = reinterpret_cast<ItemBox*>(atoms + n);
+  __shared__ float red[NW][6];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid < 64) {  // item offsets: a scan of the per-atom tile counts, 64 atoms at a time
+    int carry = 0;
+    for (int a0 = 0; a0 < n; a0 += 64) {
+      const int a = a0 + lane;
+      int c = 0;
+      if (a < n) {
+        const AtomK k = ak[a];
+        const ItemBox b = item_box(k, nx, ny, nz);
+        if (cache) {
+          atoms[a] = k;
+          boxes[a] = b;
+        }
+        c = b.cx * b.cy * b.cz;
+      }
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(c, o, 64);
+        if (lane >= o) c += v;
+      }
+      if (a < n) starts[a + 1] = carry + c;
+      carry += __shfl(c, 63, 64);
+    }
+    if (lane == 0) starts[0] = 0;
+  }
+  __syncthreads();
+  const int total = starts[n];
+  if (blockIdx.x == 0)
+    for (int a = tid; a <= n; a += kGradThreads) item_start[a] = starts[a];
+  const int nxy = nx * ny;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    // its atom: the last a with starts[a] <= item (starts[n] = total > item)
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (starts[mid] <= item) lo = mid;
+      else hi = mid;
+    }
+    const AtomK k = cache ? atoms[lo] : ak[lo];
+    const ItemBox b = cache ? boxes[lo] : item_box(k, nx, ny, nz);
+    int local = item - starts[lo];
+    const int ix = local % b.cx;
+    local /= b.cx;
+    const int iy = local % b.cy, iz = local / b.cy;
+    const int x0 = (b.tx + ix) * kTile, y0 = (b.ty + iy) * kTile, z0 = (b.tz + iz) * VPT;
+    const int xx = x0 + (tid & (kTile - 1)), yy = y0 + tid / kTile;
+    const bool pin = xx < nx && yy < ny;
+    const int x = min(xx, nx - 1), y = min(yy, ny - 1);
+    const int y0w = y0 + wave * (64 / kTile);
+    const WaveBox wb{(float)x0,
+                     (float)min(x0 + kTile - 1, nx - 1),
+                     (float)min(y0w, ny - 1),
+                     (float)min(y0w + 64 / kTile - 1, ny - 1),
+                     (float)z0,
+                     (float)max(min(z0 + VPT, nz) - 1, z0)};
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
+    if (!wb.misses(k)) {
+      float qv[VPT];
+#pragma unroll
+      for (int j = 0; j < VPT; ++j)
+        qv[j] = (pin && z0 + j < nz) ? q[(size_t)(z0 + j) * nxy + (size_t)y * nx + x] : 0.f;
+      const float fx = (float)x, fy = (float)y, fz0 = (float)z0;
+      const float dx = fx - k.mx;
+      const float dy = fy - k.my;
+      const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
+      float sg = 0.f, su = 0.f, sl = 0.f, sc = 0.f, scz = 0.f;
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        const float dz = (fz0 + (float)j) - k.mz;
+        const float r2 = fmaf(dz, dz, dxy2);
+        const float l = fast_log2(r2);
+        const float vp = fast_exp2(fmaf(k.hdm1, l, k.c));  // u log2(e) / r^2
+        const float up = vp * r2;                           // u log2(e)
+        const float g = fast_exp2(-up);
+        const float qg = qv[j] * g;
+        sg += qg;
+        const float qgu = qg * up;
+        su += qgu;
+        sl = fmaf(qgu, l, sl);
+        const float c2 = qg * vp;
+        sc += c2;
+        scz = fmaf(c2, dz, scz);
+      }
+      s0 = wave_sum(sg);
+      s1 = wave_sum(su);
+      s2 = wave_sum(sl);
+      s3 = wave_sum(sc * dx);
+      s4 = wave_sum(sc * dy);
+      s5 = wave_sum(scz);
+    }
+    if (lane == 0) {
+      red[wave][0] = s0;
+      red[wave][1] = s1;
+      red[wave][2] = s2;
+      red[wave][3] = s3;
+      red[wave][4] = s4;
+      red[wave][5] = s5;
+    }
+    __syncthreads();
+    if (tid < 6) {
       float v = 0.f;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) v += red[w][aa][c];
-      gpart[((size_t)tile * n + a0 + aa) * 6 + c] = v;
+      for (int w = 0; w < NW; ++w) v += red[w][tid];
+      gpart[(size_t)item * 6 + tid] = v;
     }
-    __syncthreads();  // red is rewritten by the next batch
-  }
-  if (POINTS) {
-    __shared__ int is_last;
-    __shared__ double part[kGradThreads];
-    static_assert(kAtomArgs * 6 <= 64, "the sums must be written by the first wave");
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) is_last = atomicAdd(ticket, 1) == (int)(gridDim.x * gridDim.y) - 1;
-    __syncthreads();
-    if (is_last) {
-      __threadfence();
-      // the whole block sums the tiles: slice sl of (atom, component) pr takes the tiles
-      // tt = sl (mod nsl), then one thread per pr adds its slices in order (fixed order)
-      const int pairs = n * 6, ntiles = gridDim.x;
-      const int nsl = kGradThreads / pairs;
-      if (tid < pairs * nsl) {
-        const int pr = tid % pairs, sl = tid / pairs;
-        double acc = 0.0;
-#pragma unroll 4
-        for (int tt = sl; tt < ntiles; tt += nsl) acc += (double)gpart[(size_t)tt * pairs + pr];
-        part[sl * pairs + pr] = acc;
-      }
-      __syncthreads();
-      if (tid < pairs) {
-        double S = 0.0;
-        for (int sl = 0; sl < nsl; ++sl) S += part[sl * pairs + tid];
-        sums_out[tid] = S;
-      }
-      if (tid == 0) *ticket = 0;  // ready for the next launch
-      signal_host(sig, 1);
-    }
+    __syncthreads();  // red is rewritten by the next item
   }
 }
 
 // Block per atom (blockIdx.x < n) plus one block for the loss (blockIdx.x == n).
+// Partials in tile layout (gpart[(t n + a) 6 + c], t < ntiles) or, with item_start, in item
+// layout (atom a's partials at gpart[6 i + c], item_start[a] <= i < item_start[a + 1]).
 __global__ __launch_bounds__(256) void k_grad_finalize(
-    const float* __restrict__ gpart, int ntiles, int n, const double* __restrict__ loss_part,
-    int nloss, const sfw_atom* __restrict__ atoms, float lambda, double* __restrict__ sums,
-    sfw_atom* __restrict__ grad_out, double* __restrict__ loss_out, int vjp,
-    SigArgs sig) {
+    const float* __restrict__ gpart, int ntiles, const int* __restrict__ item_start, int n,
+    const double* __restrict__ loss_part, int nloss, const sfw_atom* __restrict__ atoms,
+    float lambda, double* __restrict__ sums, sfw_atom* __restrict__ grad_out,
+    double* __restrict__ loss_out, int vjp, SigArgs sig) {
   __shared__ double red[6][4];
   const int tid = threadIdx.x;
   const int a = blockIdx.x;
   if (a < n) {
     double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = tid; t < ntiles; t += 256) {
-      const float* g = gpart + ((size_t)t * n + a) * 6;
+    if (item_start) {
+      const int i1 = item_start[a + 1];
+      for (int i = item_start[a] + tid; i < i1; i += 256) {
+        const float* g = gpart + (size_t)i * 6;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) s[c] += (double)g[c];
+        for (int c = 0; c < 6; ++c) s[c] += (double)g[c];
+      }
+    } else {
+      for (int t = tid; t < ntiles; t += 256) {
+        const float* g = gpart + ((size_t)t * n + a) * 6;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s[c] += (double)g[c];
+      }
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -1214,31 +1361,11 @@ ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz) {
   return p;
 }
 
-GradPlan plan_grad(sfw_dims vol, int n_atoms, int target_blocks) {
+GradPlan plan_grad_box(sfw_dims vol, const int box[6]) {
   GradPlan p;
-  p.vpt = 16;  // a wave's box is 16 x 4 x 16 voxels: atoms are culled along z as well
-  p.rtx = (vol.nx + kTile - 1) / kTile;
-  p.ntile_xy = p.rtx * ((vol.ny + kTile - 1) / kTile);
-  p.ntile_z = (vol.nz + p.vpt - 1) / p.vpt;
-  p.ntiles = p.ntile_xy * p.ntile_z;
-  int groups = (target_blocks + p.ntiles - 1) / p.ntiles;
-  if (groups > n_atoms) groups = n_atoms;
-  if (groups < 1) groups = 1;
-  int apg = (n_atoms + groups - 1) / groups;
-  if (apg > kGradMaxAtomsPerGroup) apg = kGradMaxAtomsPerGroup;
-  if (apg < 1) apg = 1;
-  p.apg = apg;
-  p.groups = (n_atoms + apg - 1) / apg;
-  if (p.groups < 1) p.groups = 1;
-  return p;
-}
-
-GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6], bool deep) {
-  GradPlan p = plan_grad(vol, n_atoms);
-  // a few points (one launch, last-block sums): deep tiles keep the block count, and with it
-  // the per-block release fences and the last block's sum, small; a point's atom spans most
-  // of the depth anyway
-  if (deep) p.vpt = vol.nz >= 64 ? 64 : (vol.nz >= 32 ? 32 : 16);
+  // deep tiles keep the block count, and with it the per-block release fences and the last
+  // block's sum, small; a point's atom spans most of the depth anyway
+  p.vpt = vol.nz >= 64 ? 64 : (vol.nz >= 32 ? 32 : 16);
   p.rx0 = box[0] / kTile;
   p.rtx = std::max(1, (box[1] + kTile - 1) / kTile - p.rx0);
   p.ry0 = box[2] / kTile;
@@ -1247,11 +1374,6 @@ GradPlan plan_grad_box(sfw_dims vol, int n_atoms, const int box[6], bool deep) {
   p.rz0 = box[4] / p.vpt;
   p.ntile_z = std::max(1, (box[5] + p.vpt - 1) / p.vpt - p.rz0);
   p.ntiles = p.ntile_xy * p.ntile_z;
-  // atom groups for the smaller grid (same rule as plan_grad)
-  int groups = (512 + p.ntiles - 1) / p.ntiles;
-  groups = std::max(1, std::min(groups, n_atoms));
-  p.apg = std::max(1, std::min(kGradMaxAtomsPerGroup, (n_atoms + groups - 1) / groups));
-  p.groups = std::max(1, (n_atoms + p.apg - 1) / p.apg);
   return p;
 }
 
@@ -1608,23 +1730,27 @@ hipError_t launch_conv_mfma_region(const float* in, const float* amat, sfw_dims 
   return mfma_e<kEpiColumn>(in, amat, psf, vol, rg, out, nullptr, nullptr, st);
 }
 
-hipError_t launch_grad(const GradPlan& p, const AtomK* ak, int n, const float* q, sfw_dims vol,
-                       float* gpart, hipStream_t st) {
+int grad_item_tiles(sfw_dims vol) {
+  return ((vol.nx + kTile - 1) / kTile) * ((vol.ny + kTile - 1) / kTile) *
+         ((vol.nz + kTile - 1) / kTile);
+}
+
+hipError_t launch_grad_items(const AtomK* ak, int n, const float* q, sfw_dims vol, float* gpart,
+                             int* item_start, int blocks, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  dim3 grid(p.ntiles, p.groups);
-  AtomArgs none;
-  std::memset(&none, 0, sizeof(none));
-  if (p.vpt != 16) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_grad<16, false>), grid, dim3(kGradThreads), 0, st, ak, none, n, p.apg, q,
-                     vol.nx, vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart,
-                     nullptr, nullptr, kNoSig);
+  if (blocks < 1) return hipErrorInvalidValue;
+  size_t lds = ((size_t)(n + 1) * sizeof(int) + 15) / 16 * 16;
+  if (n <= kItemsLdsAtoms) lds += (size_t)n * (sizeof(AtomK) + sizeof(ItemBox));
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_grad_items, dim3(blocks), dim3(kGradThreads), lds, st, ak, n, q, vol.nx,
+                     vol.ny, vol.nz, gpart, item_start);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n, const float* q,
                               sfw_dims vol, float* gpart, int* ticket, double* sums_out,
                               const SigArgs& sig, hipStream_t st) {
-  if (n <= 0 || n > kAtomArgs || p.groups != 1) return hipErrorInvalidValue;
+  if (n <= 0 || n > kAtomArgs) return hipErrorInvalidValue;
   AtomArgs args;
   std::memset(&args, 0, sizeof(args));
   std::memcpy(args.a, host_atoms, sizeof(AtomK) * n);
@@ -1632,9 +1758,9 @@ hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n,
   switch (p.vpt) {
 #define SFW_GRAD_CASE(V)                                                                       \
   case V:                                                                                      \
-    hipLaunchKernelGGL((k_grad<V, true>), grid, dim3(kGradThreads), 0, st, nullptr, args, n, n, \
-                       q, vol.nx, vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0,       \
-                       gpart, ticket, sums_out, sig);                                           \
+    hipLaunchKernelGGL((k_grad_points<V>), grid, dim3(kGradThreads), 0, st, args, n, q, vol.nx, \
+                       vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart, ticket,  \
+                       sums_out, sig);                                                          \
     break;
     SFW_GRAD_CASE(64)
     SFW_GRAD_CASE(32)
@@ -1646,12 +1772,12 @@ hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n,
   return hipGetLastError();
 }
 
-hipError_t launch_grad_finalize(const float* gpart, int ntiles, int n, const double* loss_part,
-                                int nloss, const sfw_atom* atoms, float lambda, double* sums,
-                                sfw_atom* grad_out, double* loss_out, hipStream_t st,
-                                bool vjp, const SigArgs& sig) {
-  hipLaunchKernelGGL(k_grad_finalize, dim3(n + 1), dim3(256), 0, st, gpart, ntiles, n, loss_part,
-                     nloss, atoms, lambda, sums, grad_out, loss_out, vjp ? 1 : 0, sig);
+hipError_t launch_grad_finalize(const float* gpart, int ntiles, const int* item_start, int n,
+                                const double* loss_part, int nloss, const sfw_atom* atoms,
+                                float lambda, double* sums, sfw_atom* grad_out, double* loss_out,
+                                hipStream_t st, bool vjp, const SigArgs& sig) {
+  hipLaunchKernelGGL(k_grad_finalize, dim3(n + 1), dim3(256), 0, st, gpart, ntiles, item_start, n,
+                     loss_part, nloss, atoms, lambda, sums, grad_out, loss_out, vjp ? 1 : 0, sig);
   return hipGetLastError();
 }
 

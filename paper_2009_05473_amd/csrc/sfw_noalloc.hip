@@ -115,7 +115,7 @@ extern "C" int sfw_eta_points_noalloc(sfw_dims vol, const float* q, float lambda
       pa.sigma[i] = t[3];
       pa.d[i] = t[4];
     }
-    const GradPlan gp = plan_points(hk, n, vol, true);
+    const GradPlan gp = plan_points(hk, n, vol);
     const size_t part_bytes = (size_t)gp.ntiles * n * 6 * sizeof(float);
     if (part_bytes > SFW_NOALLOC_SCRATCH_BYTES - kPartOff)
       return fail(SFW_EINVAL, "the points' tiles need more than the fixed scratch "

@@ -63,9 +63,9 @@ int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
 // product of the forward model; ws->ak must hold the n atoms' constants.
 int op_vjp(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* gvol,
            const sfw_atom* atoms_dev, int n, sfw_atom* grad_out);
-// Tiles of the gradient-sum kernel that meet the cut ball of one of the n unit atoms hk (host
-// constants); one_group: all n atoms in one group (the one-launch path, n <= kAtomArgs).
-GradPlan plan_points(const AtomK* hk, int n, const sfw_dims& vol, bool one_group);
+// Tiles of the points kernel (the one-launch path, n <= kAtomArgs) that meet the cut ball of
+// one of the n unit atoms hk (host constants).
+GradPlan plan_points(const AtomK* hk, int n, const sfw_dims& vol);
 // eta and its gradient at n points theta = (mx, my, mz, sigma, d) (host, float64); syncs.
 int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double lambda,
                   const double* thetas, int n, double* eta_out, double* grad_out);

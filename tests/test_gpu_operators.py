@@ -133,8 +133,10 @@ def test_residual_grad_parity(L, ws_big, name, conv_path):
         assert rel_l2(gg[:, c], g[:, c]) <= 2e-4, c
 
 
-def test_residual_grad_edge(L, ws_big, conv_path):
-    shape = (23, 29, 37)
+@pytest.mark.parametrize("shape", [(23, 29, 37), (23, 29, 29)])
+def test_residual_grad_edge(L, ws_big, conv_path, shape):
+    """Ragged sizes; (23, 29, 29) gives square plane transforms, so the spectral blur runs its
+    fused plane passes on a plane that is not a multiple of any tile."""
     rng = np.random.default_rng(77)
     psf = f32(np.abs(rng.standard_normal((9, 5, 7))) + 0.05)
     psf /= psf.sum()
@@ -159,20 +161,23 @@ def test_residual_grad_edge(L, ws_big, conv_path):
     assert rel_err(loss0.cpu().numpy()[0], 0.5 * np.sum(y * y)) <= 1e-6
 
 
-def test_residual_grad_cut_atoms(L, ws_big):
+@pytest.mark.parametrize("shape,n", [((40, 96, 80), 30), ((40, 70, 70), 100)])
+def test_residual_grad_cut_atoms(L, ws_big, shape, n):
     """Atoms skipped where they are exactly zero: many narrow atoms (most tiles skip most of
     them), centres outside the volume, and wide long-tailed atoms (cut radius past the whole
-    volume, never skipped), against the oracle's dense sums."""
-    shape = (40, 96, 80)
+    volume, never skipped), against the oracle's dense sums. (40, 96, 80) runs the blur's five
+    separate passes, (40, 70, 70) its fused plane passes over ragged tiles, with more atoms
+    than one wave's atom list holds (two groups of 64)."""
     rng = np.random.default_rng(2024)
     psf = f32(synth.gaussian_psf(1.0, 2.0, (15, 9, 9)))
-    atoms = np.zeros((30, 6))
-    atoms[:, 0] = rng.uniform(0.5, 2.0, 30)
-    atoms[:, 1] = rng.uniform(-6, 86, 30)     # x, some outside [0, 79]
-    atoms[:, 2] = rng.uniform(-6, 102, 30)    # y
-    atoms[:, 3] = rng.uniform(-4, 44, 30)     # z
-    atoms[:, 4] = rng.uniform(0.5, 1.2, 30)   # narrow
-    atoms[:, 5] = rng.uniform(1.8, 3.0, 30)
+    nz, ny, nx = shape
+    atoms = np.zeros((n, 6))
+    atoms[:, 0] = rng.uniform(0.5, 2.0, n)
+    atoms[:, 1] = rng.uniform(-6, nx + 6, n)  # x, some outside [0, nx - 1]
+    atoms[:, 2] = rng.uniform(-6, ny + 6, n)  # y
+    atoms[:, 3] = rng.uniform(-4, nz + 4, n)  # z
+    atoms[:, 4] = rng.uniform(0.5, 1.2, n)    # narrow
+    atoms[:, 5] = rng.uniform(1.8, 3.0, n)
     atoms[:3, 4] = (3.5, 4.0, 3.8)            # wide and long-tailed
     atoms[:3, 5] = (1.2, 1.25, 1.3)
     atoms = f32(atoms)
@@ -180,9 +185,14 @@ def test_residual_grad_cut_atoms(L, ws_big):
     y = f32(oracle.blur(oracle.render(shape, truth), psf) + 0.01 * rng.standard_normal(shape))
     lam = 0.3
     say("sfw_residual_grad cut atoms", shape, len(atoms))
-    phi = L.sfw_forward(ws_big, dev(psf), dev(atoms), shape)
-    r, loss, grad = L.sfw_residual_grad(ws_big, dev(psf), dev(y), lam, dev(atoms))
-    torch.cuda.synchronize()
+    w = ws_big if n <= 64 else L.Workspace(shape, psf.shape, n)
+    try:
+        phi = L.sfw_forward(w, dev(psf), dev(atoms), shape)
+        r, loss, grad = L.sfw_residual_grad(w, dev(psf), dev(y), lam, dev(atoms))
+        torch.cuda.synchronize()
+    finally:
+        if w is not ws_big:
+            w.close()
     C, g, r_o, _ = oracle.criterion_and_grad(y, atoms, psf, lam)
     assert rel_l2(phi.cpu().numpy(), oracle.blur(oracle.render(shape, atoms), psf)) <= 1e-5
     assert rel_l2(r.cpu().numpy(), r_o) <= 1e-5
