@@ -365,16 +365,25 @@ def batch_run(L, synth, n_volumes, n_workspaces):
     many = L.sfw_solve_batch(wss, data, opts)
     t2 = time.perf_counter()
     print(f"[batch] {n_workspaces} workspaces: {t2 - t1:.3f} s", file=sys.stderr, flush=True)
+    # the same with every kernel launched eagerly (no graph replay, default launch shapes)
+    eager = L.default_options(mode="BSFW", sigma_grid=[float(np.float32(v)) for v in cfg0.sigma_grid],
+                              d_grid=cfg0.d_grid, graphs=0, autotune=0)
+    t3 = time.perf_counter()
+    plain = L.sfw_solve_batch(wss, data, eager)
+    t4 = time.perf_counter()
+    print(f"[batch] {n_workspaces} workspaces, eager: {t4 - t3:.3f} s", file=sys.stderr, flush=True)
     for w in wss:
         w.close()
     same = all(np.array_equal(a[0], b[0]) for a, b in zip(one, many))
     found = sum(len(r[0]) for r in many)
     true = sum(p.config.n_atoms for p in probs)
     return {"workload": f"{n_volumes} volumes of 48..96 x 48..96 x 48 voxels, 5..40 masses, "
-                        "own Gaussian PSF each (up to 15x15x29), from mu = 0",
+                        "own Gaussian PSF each (up to 17x17x33), from mu = 0",
             "mode": "BSFW", "workspaces": n_workspaces,
             "voxels": int(sum(np.prod(p.config.shape) for p in probs)),
             "seconds_one_workspace": t1 - t0, "seconds": t2 - t1,
+            "seconds_eager": t4 - t3,
+            "same_atoms_eager": bool(all(np.array_equal(a[0], b[0]) for a, b in zip(many, plain))),
             "volumes_per_s": n_volumes / (t2 - t1), "speedup": (t1 - t0) / (t2 - t1),
             "same_atoms": bool(same), "status_ok": int(sum(r[2] == L.SFW_OK for r in many)),
             "not_ok": {str(i): {"status": int(r[2]), "iterations": r[1]["iterations"],

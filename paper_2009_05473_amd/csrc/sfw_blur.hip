@@ -728,13 +728,14 @@ __global__ __launch_bounds__(kPlaneThreads) void k_bxy_inv_fwd(
 // 32 columns kx of row ky = blockIdx.y. S(tz, kx) = sum_{ty, tx} H w_y w_x goes through LDS.
 constexpr int kHhatCols = 32;
 constexpr int kHhatMaxPz = 33;
-constexpr int kHhatMaxTaps = 8192;  // PSF staged in LDS
+constexpr int kHhatLdsTaps = 8192;  // PSFs up to this many taps are staged in LDS
 
 // hcache holds the PSF and grid the stored spectrum was computed for: ints [0, 6) = (P_x, P_y,
 // P_z, N_x, N_y, N_z), taps from kHcacheHead on. One block compares the request with it and
 // sets *changed (updating the copy when it differs); the spectrum kernel then returns at once
 // when nothing changed, so an unchanged PSF costs no recomputation and no host round trip.
 constexpr int kHcacheHead = 16;
+constexpr int kHhatMaxTaps = kHcacheFloats - kHcacheHead;  // PSFs the spectral blur takes
 
 __global__ __launch_bounds__(1024) void k_psf_check(const float* __restrict__ H, int pxs, int pys,
                                                     int pzs, int Nx, int Ny, int Nz,
@@ -775,10 +776,14 @@ __global__ __launch_bounds__(256) void k_psf_spectrum(
   if (*changed == 0) return;
   __shared__ double2 wx[kFftMaxBlur], wy[kFftMaxBlur], wz[kFftMaxBlur];
   __shared__ double2 S[kHhatMaxPz * kHhatCols];
-  __shared__ float hs[kHhatMaxTaps];
+  __shared__ float hs[kHhatLdsTaps];
   const int t = threadIdx.x;
   const int ntaps = pxs * pys * pzs;
-  for (int i = t; i < ntaps; i += 256) hs[i] = H[i];
+  // larger PSFs are read through the caches (the spectrum is only made when H changes)
+  const bool staged = ntaps <= kHhatLdsTaps;
+  if (staged)
+    for (int i = t; i < ntaps; i += 256) hs[i] = H[i];
+  const float* taps = staged ? hs : H;
   // exp(-2 pi i m / N) = cospi(-2 m / N) + i sinpi(-2 m / N)
   for (int m = t; m < Nx; m += 256) {
     double s, c;
@@ -810,7 +815,7 @@ __global__ __launch_bounds__(256) void k_psf_spectrum(
       int my = first(ky, cy, Ny);
       const int mx0 = first(kx, cx, Nx);
       for (int ty = 0; ty < pys; ++ty) {
-        const float* row = hs + (tz * pys + ty) * pxs;
+        const float* row = taps + (tz * pys + ty) * pxs;
         double xr = 0.0, xi = 0.0;
         int mx = mx0;
 #pragma unroll 4

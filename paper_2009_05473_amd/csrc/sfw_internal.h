@@ -468,7 +468,7 @@ bool blur_plan(const sfw_dims& vol, const sfw_dims& psf, BlurPlan& bp);
 hipError_t launch_blur_twiddles(const BlurPlan& bp, float2* tw, hipStream_t st);
 // The spectrum is recomputed only when H or the grid differ from the copy in hcache
 // ([kHcacheFloats], zeroed at creation); changed: device int scratch.
-constexpr int kHcacheFloats = 16 + 8192;
+constexpr int kHcacheFloats = 16 + 32768;
 hipError_t launch_psf_spectrum(const BlurPlan& bp, const float* H, sfw_dims psf, float2* hhat,
                                float* hcache, int* changed, hipStream_t st);
 // Number of float64 loss partials the residual epilogue writes.

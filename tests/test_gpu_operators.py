@@ -202,6 +202,31 @@ def test_residual_grad_cut_atoms(L, ws_big, shape, n):
     assert rel_l2(gg, g) <= 1e-4
 
 
+@pytest.mark.parametrize("shape", [(40, 48, 56), (40, 52, 52)])
+def test_large_psf_spectral(L, shape, monkeypatch):
+    """A 17 x 17 x 33 PSF (9,537 taps: more than the spectrum kernel stages in LDS, the largest
+    of the batched-solve workload's 4-sigma PSFs) through the Fourier-domain blur, with the five
+    separate passes (48 x 56 planes) and with the fused plane passes (52 x 52): forward model,
+    residual, criterion and gradient against the oracle."""
+    monkeypatch.setenv("SFW_CONV", "fft")
+    rng = np.random.default_rng(33)
+    psf = f32(synth.gaussian_psf(2.0, 4.0, (33, 17, 17)))
+    truth = f32(synth.random_atoms(rng, 5, shape, margin=4))
+    atoms = f32(synth.random_atoms(rng, 5, shape, margin=4))
+    y = f32(oracle.blur(oracle.render(shape, truth), psf) + 0.01 * rng.standard_normal(shape))
+    lam = 0.25
+    with L.Workspace(shape, psf.shape, 8) as w:
+        say("sfw_forward / sfw_residual_grad, 17x17x33 PSF", shape)
+        phi = L.sfw_forward(w, dev(psf), dev(atoms), shape)
+        r, loss, grad = L.sfw_residual_grad(w, dev(psf), dev(y), lam, dev(atoms))
+        torch.cuda.synchronize()
+    assert rel_l2(phi.cpu().numpy(), oracle.blur(oracle.render(shape, atoms), psf)) <= 1e-5
+    C, g, r_o, _ = oracle.criterion_and_grad(y, atoms, psf, lam)
+    assert rel_l2(r.cpu().numpy(), r_o) <= 1e-5
+    assert rel_err(loss.cpu().numpy()[0], C) <= 1e-5
+    assert rel_l2(grad.cpu().numpy(), g) <= 1e-4
+
+
 def test_psf_spectrum_follows_h(L, ws_big, monkeypatch):
     """The spectral blur keeps the PSF spectrum between calls: overwriting H in place, and a
     PSF of another shape, must both be seen."""
