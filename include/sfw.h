@@ -110,11 +110,12 @@ typedef struct {
                                         of C) is taken on its slope (approximate Wolfe test)
                                         when it fails the sufficient-decrease test; default
                                         1e-6, 0 = sufficient decrease only */
-  int32_t graphs;                    /* 1 (default): the (C, grad C) evaluations of a solve whose
-                                        launch arguments repeat (the sliding descents) replay
-                                        one captured HIP graph; 0 = every kernel launched */
+  int32_t graphs;                    /* 1: the (C, grad C) evaluations of a solve whose launch
+                                        arguments repeat (the sliding descents) replay one
+                                        captured HIP graph; 0 (default): every kernel launched
+                                        (the same results bit for bit either way) */
   int32_t autotune;                  /* 1 (default): the render's z planes per thread and the
-                                        gradient sums' block count are timed once per volume
+                                        gradient sums' grid size are timed once per volume
                                         shape and power-of-two atom-count bucket on the
                                         workspace, which keeps the choice (every candidate
                                         gives the same results bit for bit); 0 = defaults */

@@ -960,7 +960,7 @@ int sfw_default_options(sfw_options* o) {
   o->check_finite = 1;
   o->verbose = 0;
   o->slide_slope_tol = 1e-6;
-  o->graphs = 1;
+  o->graphs = 0;
   o->autotune = 1;
   return SFW_OK;
 }

@@ -107,16 +107,19 @@ def test_batch_failing_item_is_named(L, batch):
 
 def test_batch_repeats_exactly_on_fresh_and_reused_workspaces(L, batch):
     """The same items solved again, on workspaces that just solved them (warm LASSO caches)
-    and on new ones, give the same atoms."""
+    and on new ones, give the same atoms; the repeats replay the evaluation chain from HIP
+    graphs, captured by several threads at once."""
     wss, probs, data = batch
     opts = _opts(L, probs[0])
-    say("sfw_solve_batch three times: reused workspaces, then new ones")
+    sg = [float(np.float32(v)) for v in probs[0].config.sigma_grid]
+    replay = L.default_options(mode="BSFW", sigma_grid=sg, d_grid=probs[0].config.d_grid, graphs=1)
+    say("sfw_solve_batch three times: reused workspaces, then new ones (graphs)")
     first = L.sfw_solve_batch(wss, data, opts)
-    again = L.sfw_solve_batch(wss, data, opts)
+    again = L.sfw_solve_batch(wss, data, replay)
     streams = [torch.cuda.Stream() for _ in range(2)]
     fresh_ws = [L.Workspace(VOL_MAX, PSF_MAX, MAX_ATOMS, stream=s) for s in streams]
     try:
-        fresh = L.sfw_solve_batch(fresh_ws, data, opts)
+        fresh = L.sfw_solve_batch(fresh_ws, data, replay)
     finally:
         for w in fresh_ws:
             w.close()
