@@ -891,15 +891,47 @@ int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
       SFW_HIP(hipMemcpyAsync(ws->lasso_slots, hs, sizeof(int) * nd, hipMemcpyHostToDevice,
                              ws->stream));
     }
-    // the rows' final sums go straight to pinned host memory
+    // the rows' final sums go straight to pinned host memory; rows over a support box go
+    // kDotsRows at a time through one launch (and one final reduction), the others one by one
     const size_t stride = (size_t)nd + 1;
     double* hr = ws->hpin + ws->hp_rows;
-    SigArgs sig = kNoSig;
+    std::vector<char> boxed(rows.size());
+    std::vector<GramRowBox> rb(rows.size());
     for (size_t r = 0; r < rows.size(); ++r) {
-      if (r + 1 == rows.size()) sig = sig_arm(ws);  // the last row's kernel signals
-      int rc = op_gram_row(ws, p, vol, y, rows[r], &ws->slot_theta[5 * (size_t)rows[r]], sa, nd,
-                           hr + r * stride, sig);
-      if (rc) return rc;
+      rb[r].a = ws->cols + (size_t)rows[r] * ws->vcap;
+      boxed[r] = vol.nx % 4 == 0 && ws->vcap % 4 == 0 &&
+                 column_box(&ws->slot_theta[5 * (size_t)rows[r]], p.psf, vol, rb[r].box);
+    }
+    // launch groups in row order: runs of consecutive boxed rows (their sums land in
+    // consecutive rows of the pinned block) whose partials fit the buffer together, and each
+    // other row alone; the last group signals
+    const int dcap = (int)std::min<size_t>(ws->dpart_cap, 1u << 30);
+    std::vector<std::pair<size_t, size_t>> groups;  // [first, last) rows
+    for (size_t r = 0; r < rows.size();) {
+      size_t e = r + 1;
+      if (boxed[r]) {
+        size_t parts = (size_t)dots_box_blocks(rb[r].box);
+        while (e < rows.size() && boxed[e] && e - r < (size_t)kDotsRows &&
+               (parts + dots_box_blocks(rb[e].box)) * (size_t)(nd + 1) <= (size_t)dcap)
+          parts += dots_box_blocks(rb[e++].box);
+      }
+      groups.emplace_back(r, e);
+      r = e;
+    }
+    SigArgs sig = kNoSig;
+    for (size_t g = 0; g < groups.size(); ++g) {
+      if (g + 1 == groups.size()) sig = sig_arm(ws);
+      const size_t r0 = groups[g].first, r1 = groups[g].second;
+      if (boxed[r0]) {
+        ProfScope ps(ws, kProfLassoDots);
+        SFW_HIP(launch_dots_box_rows(rb.data() + r0, (int)(r1 - r0), ws->cols, sa,
+                                     ws->lasso_slots, ws->slot_box, nd, ws->vcap, y, vol,
+                                     ws->dpart, dcap, hr + r0 * stride, stride, sig, ws->stream));
+      } else {
+        int rc = op_gram_row(ws, p, vol, y, rows[r0], &ws->slot_theta[5 * (size_t)rows[r0]], sa,
+                             nd, hr + r0 * stride, sig);
+        if (rc) return rc;
+      }
     }
     int rcw = sig_wait(ws, sig);
     if (rcw) return rcw;

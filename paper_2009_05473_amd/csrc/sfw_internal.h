@@ -447,6 +447,21 @@ hipError_t launch_dots_box(const float* a, const float* cols, const SlotArgs& sa
                            const int* slots, const int* slot_box, int k, size_t colstride,
                            const float* y, sfw_dims vol, const int box[6], double* dpart,
                            int dpart_cap, double* out, const SigArgs& sig, hipStream_t st);
+// The Gram rows of up to kDotsRows columns (each with its box, as for launch_dots_box) in one
+// launch and one final reduction: row r's sums to out + r out_stride, each row's sums the same
+// as launch_dots_box gives it alone.
+constexpr int kDotsRows = 8;
+struct GramRowBox {
+  const float* a;
+  int box[6];
+};
+// blocks (and float64 partials per column) of one row over box
+int dots_box_blocks(const int box[6]);
+hipError_t launch_dots_box_rows(const GramRowBox* rows, int nr, const float* cols,
+                                const SlotArgs& sa, const int* slots, const int* slot_box, int k,
+                                size_t colstride, const float* y, sfw_dims vol, double* dpart,
+                                int dpart_cap, double* out, size_t out_stride, const SigArgs& sig,
+                                hipStream_t st);
 // dst[0..6) = box (device)
 hipError_t launch_store_box(const int box[6], int* dst, hipStream_t st);
 hipError_t launch_any_nonfinite(const float* v, size_t n, int* flag, hipStream_t st);

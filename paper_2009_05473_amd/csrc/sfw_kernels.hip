@@ -1224,26 +1224,37 @@ __global__ __launch_bounds__(256) void k_dots(const float* __restrict__ a, Box6 
   }
 }
 
-// Gram row of column a over its box (a is valid there and stands for zero elsewhere): out
-// partials dpart[blockIdx.x][c] = sum over the box of a * col_c (c < k: cached column
+// Gram rows of up to kDotsRows columns in one launch (blockIdx.z = row r): for row r, column
+// a_r over its box (a_r is valid there and stands for zero elsewhere), partials
+// dpart[part0_r + blockIdx.x][c] = sum over the box of a_r * col_c (c < k: cached column
 // slot(c), counted only inside its own box; c = k: y) for the columns of chunk blockIdx.y (cpb
-// per chunk). The box is rows (y, z) of bw4 float4 starting at x0 (x0, nx, the column stride
-// and every column box's x bounds multiples of 4, so a float4 lies wholly inside or outside a
-// box); a thread keeps its kDotsHold float4 of a in registers across the columns.
-__global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
-                                                  const float* __restrict__ cols,
+// per chunk), blockIdx.x < nbx_r. The box is rows (y, z) of bw4 float4 starting at x0 (x0, nx,
+// the column stride and every column box's x bounds multiples of 4, so a float4 lies wholly
+// inside or outside a box); a thread keeps its kDotsHold float4 of a_r in registers across
+// the columns. A row's partials do not depend on the other rows of the launch.
+struct DotsRow {
+  const float* a;
+  int x0, bw4, y0, bh, z0, nrows;  // box: nrows = bh * depth rows of bw4 float4
+  int nbx, part0;                  // blocks of the row, its first partial
+};
+struct DotsRows {
+  DotsRow r[kDotsRows];
+};
+__global__ __launch_bounds__(256) void k_dots_box(DotsRows rows, const float* __restrict__ cols,
                                                   SlotArgs sa, const int* __restrict__ slots,
                                                   const int* __restrict__ slot_box,
                                                   int k, size_t colstride,
                                                   const float* __restrict__ y,
-                                                  int nx, int ny, int x0, int bw4, int y0,
-                                                  int bh, int z0, int nrows, int cpb,
+                                                  int nx, int ny, int cpb,
                                                   double* __restrict__ dpart) {
+  const DotsRow R = rows.r[blockIdx.z];
+  if ((int)blockIdx.x >= R.nbx) return;  // the whole block: the row needs fewer blocks
   __shared__ double red[kDotsCols][4];
   const int tid = threadIdx.x;
-  const int E = nrows * bw4;
-  const int stride = gridDim.x * 256;
+  const int E = R.nrows * R.bw4;
+  const int stride = R.nbx * 256;
   const int e0 = blockIdx.x * 256 + tid;
+  const float* a = R.a;
   float4 ah[kDotsHold];
   size_t vh[kDotsHold];
   int xh[kDotsHold], yh[kDotsHold], zh[kDotsHold];
@@ -1251,13 +1262,13 @@ __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
   for (int h = 0; h < kDotsHold; ++h) {
     const int e = e0 + h * stride;
     const bool ok = e < E;
-    const int row = ok ? e / bw4 : 0;
-    const int q = ok ? e - row * bw4 : 0;
-    const int yy = y0 + row % bh, zz = z0 + row / bh;
-    xh[h] = x0 + 4 * q;
+    const int row = ok ? e / R.bw4 : 0;
+    const int q = ok ? e - row * R.bw4 : 0;
+    const int yy = R.y0 + row % R.bh, zz = R.z0 + row / R.bh;
+    xh[h] = R.x0 + 4 * q;
     yh[h] = yy;
     zh[h] = zz;
-    vh[h] = ((size_t)zz * ny + yy) * nx + x0 + 4 * q;
+    vh[h] = ((size_t)zz * ny + yy) * nx + R.x0 + 4 * q;
     ah[h] = ok ? *reinterpret_cast<const float4*>(a + vh[h]) : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   const int cb = blockIdx.y * cpb, ce = min(k + 1, cb + cpb);
@@ -1293,10 +1304,37 @@ __global__ __launch_bounds__(256) void k_dots_box(const float* __restrict__ a,
     }
     __syncthreads();
     if (tid < nc)
-      dpart[(size_t)blockIdx.x * (k + 1) + c0 + tid] =
+      dpart[(size_t)(R.part0 + blockIdx.x) * (k + 1) + c0 + tid] =
           red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
     __syncthreads();
   }
+}
+
+// Row r = blockIdx.x of a k_dots_box launch: out[r out_stride + c] = the sum of its nbx_r
+// partials of column c, in float64, in partial order; the first wave stores (host memory is
+// fine: see signal_host).
+__global__ __launch_bounds__(256) void k_dots_rows_final(DotsRows rows, int k1,
+                                                         const double* __restrict__ dpart,
+                                                         double* __restrict__ out,
+                                                         size_t out_stride, SigArgs sig) {
+  __shared__ double res[256];
+  const DotsRow R = rows.r[blockIdx.x];
+  const int tid = threadIdx.x;
+  double* o = out + blockIdx.x * out_stride;
+  for (int c0 = 0; c0 < k1; c0 += 256) {
+    const int cn = min(256, k1 - c0);
+    if (tid < cn) {
+      double s = 0.0;
+#pragma unroll 8
+      for (int b = 0; b < R.nbx; ++b) s += dpart[(size_t)(R.part0 + b) * k1 + c0 + tid];
+      res[tid] = s;
+    }
+    __syncthreads();
+    if (tid < 64)
+      for (int cc = tid; cc < cn; cc += 64) o[c0 + cc] = res[cc];
+    __syncthreads();
+  }
+  signal_host(sig, gridDim.x);
 }
 
 // out[c] for c < k1: the sum over the nblocks partials dpart[b][c], in float64, in partial
@@ -1803,27 +1841,54 @@ hipError_t launch_dots(const float* a, const int abox[6], const float* cols, con
   return hipGetLastError();
 }
 
+int dots_box_blocks(const int box[6]) {
+  const int bw4 = (box[1] - box[0]) / 4, nrows = (box[3] - box[2]) * (box[5] - box[4]);
+  const int E = nrows * bw4;
+  return std::max(1, (E + 256 * kDotsHold - 1) / (256 * kDotsHold));
+}
+
+hipError_t launch_dots_box_rows(const GramRowBox* rows, int nr, const float* cols,
+                                const SlotArgs& sa, const int* slots, const int* slot_box, int k,
+                                size_t colstride, const float* y, sfw_dims vol, double* dpart,
+                                int dpart_cap, double* out, size_t out_stride, const SigArgs& sig,
+                                hipStream_t st) {
+  if (nr < 1 || nr > kDotsRows) return hipErrorInvalidValue;
+  DotsRows R;
+  std::memset(&R, 0, sizeof(R));
+  int part = 0, maxnbx = 0;
+  for (int r = 0; r < nr; ++r) {
+    const int* box = rows[r].box;
+    const int bw4 = (box[1] - box[0]) / 4, bh = box[3] - box[2], nrows = bh * (box[5] - box[4]);
+    if (nrows * bw4 <= 0) return hipErrorInvalidValue;
+    const int nbx = dots_box_blocks(box);
+    R.r[r] = DotsRow{rows[r].a, box[0], bw4, box[2], bh, box[4], nrows, nbx, part};
+    part += nbx;
+    maxnbx = std::max(maxnbx, nbx);
+  }
+  if ((size_t)part * (k + 1) > (size_t)dpart_cap) return hipErrorInvalidValue;
+  // column chunks: enough blocks to fill the chip, chunks of whole column groups
+  const int groups = (k + 1 + kDotsCols - 1) / kDotsCols;
+  int chunks = std::max(1, std::min(groups, (1024 + part - 1) / part));
+  const int cpb = (groups + chunks - 1) / chunks * kDotsCols;
+  chunks = (k + 1 + cpb - 1) / cpb;
+  hipLaunchKernelGGL(k_dots_box, dim3(maxnbx, chunks, nr), dim3(256), 0, st, R, cols, sa, slots,
+                     slot_box, k, colstride, y, vol.nx, vol.ny, cpb, dpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dots_rows_final, dim3(nr), dim3(256), 0, st, R, k + 1, dpart, out,
+                     out_stride, sig);
+  return hipGetLastError();
+}
+
 hipError_t launch_dots_box(const float* a, const float* cols, const SlotArgs& sa,
                            const int* slots, const int* slot_box, int k, size_t colstride,
                            const float* y, sfw_dims vol, const int box[6], double* dpart,
                            int dpart_cap, double* out, const SigArgs& sig, hipStream_t st) {
-  const int bw4 = (box[1] - box[0]) / 4, bh = box[3] - box[2], nrows = bh * (box[5] - box[4]);
-  const int E = nrows * bw4;
-  if (E <= 0) return hipErrorInvalidValue;
-  const int nbx = std::max(1, (E + 256 * kDotsHold - 1) / (256 * kDotsHold));
-  // column chunks: enough blocks to fill the chip, chunks of whole column groups
-  int chunks = std::max(1, std::min((k + 1 + kDotsCols - 1) / kDotsCols, (1024 + nbx - 1) / nbx));
-  const int groups = (k + 1 + kDotsCols - 1) / kDotsCols;
-  const int cpb = (groups + chunks - 1) / chunks * kDotsCols;
-  chunks = (k + 1 + cpb - 1) / cpb;
-  if ((size_t)nbx * (k + 1) > (size_t)dpart_cap) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dots_box, dim3(nbx, chunks), dim3(256), 0, st, a, cols, sa, slots,
-                     slot_box, k, colstride, y, vol.nx, vol.ny, box[0], bw4, box[2], bh, box[4], nrows, cpb,
-                     dpart);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, st, dpart, nbx, k + 1, out, sig);
-  return hipGetLastError();
+  GramRowBox row;
+  row.a = a;
+  std::memcpy(row.box, box, sizeof(row.box));
+  return launch_dots_box_rows(&row, 1, cols, sa, slots, slot_box, k, colstride, y, vol, dpart,
+                              dpart_cap, out, 0, sig, st);
 }
 
 hipError_t launch_any_nonfinite(const float* v, size_t n, int* flag, hipStream_t st) {
