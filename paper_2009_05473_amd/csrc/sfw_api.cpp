@@ -855,11 +855,35 @@ int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
       }
       SFW_HIP(hipMemcpyAsync(ws->ak, hk, sizeof(AtomK) * n, hipMemcpyHostToDevice, ws->stream));
     }
+    // columns over their support boxes go kBoxColumns at a time through one launch; the
+    // others (a box covering the volume, or a PSF the box kernel does not take) one by one
+    std::vector<ColumnBoxJob> jobs;
+    auto flush = [&]() -> int {
+      if (jobs.empty()) return SFW_OK;
+      ProfScope ps(ws, kProfLassoConv);
+      SFW_HIP(launch_column_boxes(jobs.data(), (int)jobs.size(), H, p.psf, vol, ws->stream));
+      jobs.clear();
+      return SFW_OK;
+    };
     for (const auto& f : fresh) {
-      int rc = op_columns(ws, p, vol, H, f.first, f.second, thetas + 5 * (size_t)f.first);
-      if (rc) return rc;
+      ColumnBoxJob job;
+      if (column_box(thetas + 5 * (size_t)f.first, p.psf, vol, job.box) && column_box_ok(p.psf)) {
+        job.atom = ws->ak + f.first;
+        job.out = ws->cols + (size_t)f.second * ws->vcap;
+        job.box_out = ws->slot_box + 6 * (size_t)f.second;
+        jobs.push_back(job);
+        if ((int)jobs.size() == kBoxColumns) {
+          int rc = flush();
+          if (rc) return rc;
+        }
+      } else {
+        int rc = op_columns(ws, p, vol, H, f.first, f.second, thetas + 5 * (size_t)f.first);
+        if (rc) return rc;
+      }
       ws->slot_ok[f.second] = 1;
     }
+    int rcf = flush();
+    if (rcf) return rcf;
   }
   // Gram rows for the entries missing between support slots: fresh slots first, each row
   // covering its slot's whole row and column, then any slot still missing an entry

@@ -400,6 +400,17 @@ bool column_box_ok(sfw_dims psf);
 // box_out (device int[6], may be null) receives the box.
 hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sfw_dims vol,
                              const int box[6], float* out, int* box_out, hipStream_t st);
+// Up to kBoxColumns such columns (one PSF, each with its atom, box, output and box record) in
+// one launch; each column the same as launch_column_box gives it alone.
+constexpr int kBoxColumns = 8;
+struct ColumnBoxJob {
+  const AtomK* atom;
+  float* out;
+  int* box_out;
+  int box[6];
+};
+hipError_t launch_column_boxes(const ColumnBoxJob* jobs, int n, const float* H, sfw_dims psf,
+                               sfw_dims vol, hipStream_t st);
 
 // The per-atom sums of at most kAtomArgs atoms given by their constants on the host, reduced
 // to sums_out[6 a + c] (float64; may be host memory) by the last block; ticket: device int that

@@ -1621,12 +1621,33 @@ hipError_t launch_conv_mfma(const float* in, const float* amat, sfw_dims psf, sf
 constexpr int kBoxTX = 16, kBoxTY = 4, kBoxZ = 4, kBoxMaxWaves = 16;
 static_assert(kBoxTX * kBoxTY == 64, "one output column per lane");
 
+// Up to kBoxColumns columns (one PSF) per launch: column c takes the blocks [first, first +
+// gx gy gz) of the flat grid, its block b as (b % gx, b / gx % gy, b / (gx gy)).
+struct BoxColumn {
+  const AtomK* atom;
+  float* out;
+  int* box_out;
+  int bx0, by0, bz0, bx1, by1, bz1;
+  int gx, gy, first;
+};
+struct BoxColumns {
+  BoxColumn c[kBoxColumns];
+};
+
 template <int PZ>
 __global__ __launch_bounds__(64 * kBoxMaxWaves) void k_column_box(
-    const AtomK* __restrict__ atom, const float* __restrict__ H, int pxs, int pys, int nx, int ny,
-    int nz, int bx0, int by0, int bz0, int bx1, int by1, int bz1, float* __restrict__ out,
-    int* __restrict__ box_out) {
-  if (box_out && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
+    BoxColumns cols, int ncols, const float* __restrict__ H, int pxs, int pys, int nx, int ny,
+    int nz) {
+  int ci = 0;
+  while (ci + 1 < ncols && (int)blockIdx.x >= cols.c[ci + 1].first) ++ci;
+  const BoxColumn& C = cols.c[ci];
+  const AtomK* __restrict__ atom = C.atom;
+  float* __restrict__ out = C.out;
+  int* __restrict__ box_out = C.box_out;
+  const int bx0 = C.bx0, by0 = C.by0, bz0 = C.bz0, bx1 = C.bx1, by1 = C.by1, bz1 = C.bz1;
+  const int b = (int)blockIdx.x - C.first;
+  const int bxi = b % C.gx, byi = (b / C.gx) % C.gy, bzi = b / (C.gx * C.gy);
+  if (box_out && b == 0 && threadIdx.x == 0) {
     box_out[0] = bx0;  // the box this column is valid on (read by the Gram-row kernels)
     box_out[1] = bx1;
     box_out[2] = by0;
@@ -1640,8 +1661,8 @@ __global__ __launch_bounds__(64 * kBoxMaxWaves) void k_column_box(
   extern __shared__ float4 lds4[];
   float* tile = reinterpret_cast<float*>(lds4);
   const int LX = kBoxTX + pxs - 1, LY = kBoxTY + pys - 1;
-  const int X0 = bx0 + blockIdx.x * kBoxTX, Y0 = by0 + blockIdx.y * kBoxTY;
-  const int Z0 = bz0 + blockIdx.z * kBoxZ;
+  const int X0 = bx0 + bxi * kBoxTX, Y0 = by0 + byi * kBoxTY;
+  const int Z0 = bz0 + bzi * kBoxZ;
   const int cx = (pxs - 1) / 2, cy = (pys - 1) / 2, cz = (PZ - 1) / 2;
   const int t = threadIdx.x;
   const int nwaves = (int)(blockDim.x >> 6);
@@ -1730,12 +1751,24 @@ bool column_box_ok(sfw_dims psf) {
          column_box_lds(psf) <= (size_t)kColumnBoxMaxLds;
 }
 
-hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sfw_dims vol,
-                             const int box[6], float* out, int* box_out, hipStream_t st) {
-  if (!column_box_ok(psf)) return hipErrorInvalidValue;
-  const int bw = box[1] - box[0], bh = box[3] - box[2], bd = box[5] - box[4];
-  if (bw <= 0 || bh <= 0 || bd <= 0) return hipSuccess;
-  const dim3 grid((bw + kBoxTX - 1) / kBoxTX, (bh + kBoxTY - 1) / kBoxTY, (bd + kBoxZ - 1) / kBoxZ);
+hipError_t launch_column_boxes(const ColumnBoxJob* jobs, int n, const float* H, sfw_dims psf,
+                               sfw_dims vol, hipStream_t st) {
+  if (!column_box_ok(psf) || n < 0 || n > kBoxColumns) return hipErrorInvalidValue;
+  BoxColumns bc;
+  std::memset(&bc, 0, sizeof(bc));
+  int nc = 0, blocks = 0;
+  for (int i = 0; i < n; ++i) {
+    const int* box = jobs[i].box;
+    const int bw = box[1] - box[0], bh = box[3] - box[2], bd = box[5] - box[4];
+    if (bw <= 0 || bh <= 0 || bd <= 0) continue;  // nothing to compute
+    const int gx = (bw + kBoxTX - 1) / kBoxTX, gy = (bh + kBoxTY - 1) / kBoxTY;
+    const int gz = (bd + kBoxZ - 1) / kBoxZ;
+    bc.c[nc++] = BoxColumn{jobs[i].atom, jobs[i].out, jobs[i].box_out, box[0], box[2], box[4],
+                           box[1], box[3], box[5], gx, gy, blocks};
+    blocks += gx * gy * gz;
+  }
+  if (nc == 0) return hipSuccess;
+  const dim3 grid(blocks);
   const size_t lds = column_box_lds(psf);
   switch (psf.nz) {
 #define SFW_BOX_CASE(P)                                                                        \
@@ -1744,10 +1777,8 @@ hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sf
         reinterpret_cast<const void*>(&k_column_box<P>),                                       \
         hipFuncAttributeMaxDynamicSharedMemorySize, kColumnBoxMaxLds);                         \
     if (attr != hipSuccess) return attr;                                                       \
-    hipLaunchKernelGGL(k_column_box<P>, grid, dim3(64 * column_box_waves(psf)), lds, st, atom, \
-                       H, psf.nx,                                                              \
-                       psf.ny, vol.nx, vol.ny, vol.nz, box[0], box[2], box[4], box[1], box[3], \
-                       box[5], out, box_out);                                                  \
+    hipLaunchKernelGGL(k_column_box<P>, grid, dim3(64 * column_box_waves(psf)), lds, st, bc,   \
+                       nc, H, psf.nx, psf.ny, vol.nx, vol.ny, vol.nz);                         \
     return hipGetLastError();                                                                  \
   }
     SFW_BOX_CASE(1) SFW_BOX_CASE(3) SFW_BOX_CASE(5) SFW_BOX_CASE(7) SFW_BOX_CASE(9)
@@ -1758,6 +1789,16 @@ hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sf
     default:
       return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_column_box(const AtomK* atom, const float* H, sfw_dims psf, sfw_dims vol,
+                             const int box[6], float* out, int* box_out, hipStream_t st) {
+  ColumnBoxJob job;
+  job.atom = atom;
+  job.out = out;
+  job.box_out = box_out;
+  std::memcpy(job.box, box, sizeof(job.box));
+  return launch_column_boxes(&job, 1, H, psf, vol, st);
 }
 
 hipError_t launch_conv_mfma_region(const float* in, const float* amat, sfw_dims psf, sfw_dims vol,
