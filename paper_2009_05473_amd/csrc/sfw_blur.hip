@@ -38,8 +38,11 @@ constexpr int bx_threads(int R1, int R2) {
   const int t = kBxPairs * (R1 > R2 ? R1 : R2);
   return (t + 63) / 64 * 64;
 }
+// columns per block of the z pass: 32 (each row read and written 256 bytes at a time) while its
+// two LDS buffers stay within 64 KiB, else 16
+constexpr int bz_lines(int L) { return L <= 120 ? 32 : 16; }
 constexpr int bz_threads(int R1, int R2) {
-  const int t = kFxLines * (R1 > R2 ? R1 : R2);
+  const int t = bz_lines(R1 * R2) * (R1 > R2 ? R1 : R2);
   return (t + 63) / 64 * 64;
 }
 
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(bx_threads(R1, R2)) void k_bx_r2c(
 
 // ---------------------------------------------------------------- z: forward, filter, inverse
 
-// Columns (x0 + c, y = blockIdx.y), c < kFxLines, x < ncols, along z (stride Ny px): planes
+// Columns (x0 + c, y = blockIdx.y), c < bz_lines(L), x < ncols, along z (stride Ny px): planes
 // z < nz in (zero beyond), DFT, times Hhat (conj(Hhat) when conj_h), conjugate, DFT again,
 // planes z < nz written back in place. What is stored is DFT_z(conj(X Hhat)), the z part of
 // the conjugated inverse.
@@ -118,7 +121,7 @@ template <int R1, int R2>
 __global__ __launch_bounds__(bz_threads(R1, R2)) void k_bz_filter(
     float2* __restrict__ spec, const float2* __restrict__ hhat, int conj_h, int ncols, int Ny,
     int px, int nz, const float2* __restrict__ twg) {
-  constexpr int L = R1 * R2, LS = L | 1, C = kFxLines, NT = bz_threads(R1, R2);
+  constexpr int L = R1 * R2, LS = L | 1, C = bz_lines(L), NT = bz_threads(R1, R2);
   __shared__ float2 bufa[C * LS];
   __shared__ float2 bufb[C * LS];
   __shared__ float2 tw[L];
@@ -980,7 +983,8 @@ static hipError_t bx_r2c(const BlurPlan& bp, const float* in, const sfw_dims& vo
 
 static hipError_t bz_filter(const BlurPlan& bp, float2* spec, const float2* hhat, bool conj_h,
                             int nz, const float2* tw, hipStream_t st) {
-  const dim3 grid((bp.hx + kFxLines - 1) / kFxLines, bp.N[1]);
+  const int lines = bz_lines(bp.N[2]);
+  const dim3 grid((bp.hx + lines - 1) / lines, bp.N[1]);
   switch (bp.N[2]) {
 #define SFW_BZ_CASE(n, a, b)                                                                 \
   case n:                                                                                    \
