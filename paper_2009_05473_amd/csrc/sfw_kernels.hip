@@ -845,17 +845,17 @@ __global__ __launch_bounds__(kGradThreads) void k_grad_points(AtomArgs args, int
 // ------------------------------------------------------------------ gradient sums per item
 
 // The gradient sums of a (C, grad C) evaluation with the work spread evenly over the blocks:
-// an item is one atom on one 16 x 16 x 16 volume tile (the tiles of k_grad) that meets the
-// bounding box of the atom's cut ball, grown by a voxel; block b takes items b, b + gridDim.x,
-// ... (every item costs about the same, where the per-tile atom lists of k_grad leave a few
-// blocks with many atoms). Items go atom by atom (the atom's tiles with x fastest), so atom a
-// owns items [start[a], start[a + 1]); every block computes these offsets itself (the atom
+// an item is one atom on one 16 x 16 x 16 volume tile that meets the bounding box of the atom's
+// cut ball, grown by a voxel; block b takes items b, b + gridDim.x, ... (every item costs
+// about the same, where per-tile atom lists would leave the blocks over dense regions with
+// many atoms each). Items go atom by atom (the atom's tiles with x fastest), so atom a owns
+// items [start[a], start[a + 1]); every block computes these offsets itself (the atom
 // constants are all it needs), keeping the atoms and their tile ranges in LDS (up to
 // kItemsLdsAtoms atoms; beyond, they are read again per item), and block 0 stores the offsets
-// in item_start for launch_grad_finalize.
-// Item i writes gpart[6 i + c] = (S_g, S_u, S_l, S_mx, S_my, S_mz) of its atom over its tile:
-// the four wave sums added in wave order, as k_grad's tile partial (a wave whose 16 x 4 x 16
-// box the cut ball misses adds exact zeros and skips them). No partial depends on gridDim.x.
+// in item_start for launch_grad_finalize. Item i writes gpart[6 i + c] = (S_g, S_u, S_l, S_mx,
+// S_my, S_mz) of its atom over its tile: the four wave sums added in wave order (a wave whose
+// 16 x 4 x 16 box the cut ball misses adds exact zeros and skips them). No partial depends on
+// gridDim.x.
 struct ItemBox {
   int tx, ty, tz;  // first tile per axis
   int cx, cy, cz;  // tiles per axis (0 when the cut ball misses the volume)

@@ -135,7 +135,7 @@ extern "C" int sfw_eta_points_noalloc(sfw_dims vol, const float* q, float lambda
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_noalloc_clear");
     e = launch_grad_points(gp, hk, n, q, vol, part, ticket, sums, kNoSig, stream);
-    if (e != hipSuccess) return hip_fail(e, "k_grad (points)");
+    if (e != hipSuccess) return hip_fail(e, "k_grad_points");
     hipLaunchKernelGGL(k_eta_finish, dim3(1), dim3(64), 0, stream, sums, n, (double)lambda, pa,
                        eta_out, grad_out);
     e = hipGetLastError();
