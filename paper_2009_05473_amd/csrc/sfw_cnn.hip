@@ -262,39 +262,50 @@ __global__ __launch_bounds__(256) void k_net_conv1(const float* __restrict__ xin
 // ---------------------------------------------------------------- weight gradients
 
 // part[g][t][co][ci] = sum over voxels v of group g of dy[v][co] * x[v + t - 1][ci] (stride 1,
-// zero outside): x bf16 [v][CIN], dy bf16 [v][COP]; block (t, g). Voxels are staged 64 at a
-// time in LDS as float32 (16-byte loads, coordinates once per voxel); thread (s, co quad, ci
-// quad) accumulates a 4 x 4 tile over the staged voxels j = s, s + S, ..., so each voxel costs
-// it two 16-byte LDS reads for 16 FMAs; the S voxel subsets are summed in order at the end.
-// The centre tap's blocks also leave the bias partial bpart[g][co] = sum over the group of
-// dy[v][co]. Voxel indices fit in int (checked by the launcher).
+// zero outside; x bf16 [v][CIN], dy bf16 [v][COP]; block (t, g), voxel indices fit in int,
+// checked by the launcher), on the matrix cores: for tap t the 16 x 16 tiles of the [COP][CIN]
+// product dY^T X_t, with K running over the group's voxels 32 at a time
+// (v_mfma_f32_16x16x32_bf16, bf16 products exact in float32, float32 accumulation). Voxels are
+// staged 64 at a time in LDS, transposed so that a lane's 8 consecutive voxels of one channel
+// are one 16-byte read: sdy[co][j] = dy[v0 + j][co], sx[ci][j] = x[v0 + j + t - 1][ci] (zero
+// outside). The T = COP CIN / 256 tiles go to the 4 waves, 4 / T waves per tile splitting the
+// K steps; their accumulators meet in LDS and are added in wave order. The centre tap's
+// blocks also leave the bias partial bpart[g][co] (float32 sums over the staged voxels).
 template <int CIN, int COP>
-__global__ __launch_bounds__(256) void k_net_wgrad(const uint16_t* __restrict__ x,
-                                                   const uint16_t* __restrict__ dy, int Z, int Y,
-                                                   int X, int vpg, float* __restrict__ part,
-                                                   float* __restrict__ bpart) {
-  constexpr int TC = COP / 4, TI = CIN / 4, NTILE = TC * TI, S = 256 / NTILE;
-  static_assert(256 % NTILE == 0 && S >= 1, "whole 4 x 4 tiles per block");
-  __shared__ __align__(16) float sdy[64][COP];
-  __shared__ __align__(16) float sx[64][CIN];
-  __shared__ float red[S][NTILE * 16];
-  __shared__ float bred[S][COP];
+__global__ __launch_bounds__(256) void k_net_wgrad_mfma(const uint16_t* __restrict__ x,
+                                                        const uint16_t* __restrict__ dy, int Z,
+                                                        int Y, int X, int vpg,
+                                                        float* __restrict__ part,
+                                                        float* __restrict__ bpart) {
+  constexpr int TI = CIN / 16, T = (COP / 16) * TI, KS = 4 / T;
+  static_assert(CIN % 16 == 0 && COP % 16 == 0 && (T == 1 || T == 2 || T == 4),
+                "whole 16 x 16 tiles, shared evenly by four waves");
+  constexpr int JP = 64 + 8;  // row pitch (bf16) of the transposed tiles
+  __shared__ __align__(16) uint16_t sdy[COP][JP];
+  __shared__ __align__(16) uint16_t sx[CIN][JP];
+  __shared__ float red[4][64][4];
   const int t = blockIdx.x, g = blockIdx.y;
   const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
   const int V = Z * Y * X;
   const int v0 = g * vpg, v1 = min(V, v0 + vpg);
-  const int tid = threadIdx.x;
-  const int s = tid / NTILE, ct = (tid % NTILE) / TI, it = tid % TI;
-  float acc[4][4] = {};
-  float bsum[4] = {0.f, 0.f, 0.f, 0.f};
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tile = wave % T, ks = wave / T;
+  const int co0 = (tile / TI) * 16, ci0 = (tile % TI) * 16;
+  const int m = lane & 15, q = lane >> 4;
+  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
   for (int vb = v0; vb < v1; vb += 64) {
     __syncthreads();
     for (int e = tid; e < 64 * COP / 8; e += 256) {
       const int j = e / (COP / 8), c8 = (e % (COP / 8)) * 8, v = vb + j;
       uint4 raw = make_uint4(0u, 0u, 0u, 0u);
       if (v < v1) raw = *reinterpret_cast<const uint4*>(dy + (size_t)v * COP + c8);
-      *reinterpret_cast<float4*>(&sdy[j][c8]) = bf4(raw.x, raw.y);
-      *reinterpret_cast<float4*>(&sdy[j][c8 + 4]) = bf4(raw.z, raw.w);
+      const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        sdy[c8 + 2 * i][j] = (uint16_t)(w4[i] & 0xffffu);
+        sdy[c8 + 2 * i + 1][j] = (uint16_t)(w4[i] >> 16);
+      }
     }
     for (int e = tid; e < 64 * CIN / 8; e += 256) {
       const int j = e / (CIN / 8), c8 = (e % (CIN / 8)) * 8, v = vb + j;
@@ -305,46 +316,38 @@ __global__ __launch_bounds__(256) void k_net_wgrad(const uint16_t* __restrict__ 
         if (xx >= 0 && xx < X && yy >= 0 && yy < Y && zz >= 0 && zz < Z)
           raw = *reinterpret_cast<const uint4*>(x + (((size_t)zz * Y + yy) * X + xx) * CIN + c8);
       }
-      *reinterpret_cast<float4*>(&sx[j][c8]) = bf4(raw.x, raw.y);
-      *reinterpret_cast<float4*>(&sx[j][c8 + 4]) = bf4(raw.z, raw.w);
-    }
-    __syncthreads();
-    for (int j = s; j < 64; j += S) {
-      const float4 d = *reinterpret_cast<const float4*>(&sdy[j][4 * ct]);
-      const float4 xv = *reinterpret_cast<const float4*>(&sx[j][4 * it]);
-      const float dd[4] = {d.x, d.y, d.z, d.w}, xa[4] = {xv.x, xv.y, xv.z, xv.w};
+      const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        bsum[a] += dd[a];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(dd[a], xa[b], acc[a][b]);
+      for (int i = 0; i < 4; ++i) {
+        sx[c8 + 2 * i][j] = (uint16_t)(w4[i] & 0xffffu);
+        sx[c8 + 2 * i + 1][j] = (uint16_t)(w4[i] >> 16);
       }
     }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {  // K steps of 32 voxels
+      if (s % KS != ks) continue;
+      const int j0 = 32 * s + 8 * q;
+      const v8s a = *reinterpret_cast<const v8s*>(&sdy[co0 + m][j0]);
+      const v8s b = *reinterpret_cast<const v8s*>(&sx[ci0 + m][j0]);
+      acc = mma(a, b, acc);
+    }
+    if (t == 13 && tid < COP)
+      for (int j = 0; j < 64; ++j) bsum += bf2f(sdy[tid][j]);
   }
+  // lane (m, q) holds the tile's rows co0 + 4 q + i, column ci0 + m
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) red[s][(tid % NTILE) * 16 + a * 4 + b] = acc[a][b];
-  if (it == 0)
-#pragma unroll
-    for (int a = 0; a < 4; ++a) bred[s][4 * ct + a] = bsum[a];
+  for (int i = 0; i < 4; ++i) red[wave][lane][i] = acc[i];
   __syncthreads();
-  if (s != 0) return;
+  if (ks == 0) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      float sum = 0.f;
-      for (int k = 0; k < S; ++k) sum += red[k][tid * 16 + a * 4 + b];
-      part[(((size_t)g * 27 + t) * COP + 4 * ct + a) * CIN + 4 * it + b] = sum;
+    for (int i = 0; i < 4; ++i) {
+      float sum = red[wave][lane][i];
+      for (int k = 1; k < KS; ++k) sum += red[wave + k * T][lane][i];
+      part[(((size_t)g * 27 + t) * COP + co0 + 4 * q + i) * CIN + ci0 + m] = sum;
     }
-  if (t == 13 && it == 0)
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      float sum = 0.f;
-      for (int k = 0; k < S; ++k) sum += bred[k][4 * ct + a];
-      bpart[(size_t)g * COP + 4 * ct + a] = sum;
-    }
+  }
+  if (t == 13 && tid < COP) bpart[(size_t)g * COP + tid] = bsum;
 }
 
 // The first layer's weight gradient: part[g][t][co] = sum over voxels v of group g of
@@ -720,8 +723,8 @@ int net_wgrad(sfw_net* n, const uint16_t* xin, const uint16_t* dy, const NetDims
   const int vpg = (int)((V + ng - 1) / ng);
   if ((size_t)ng * 27 * COP * CIN > n->part_cap) return fail(SFW_EINVAL, "gradient partials too small");
   if (V > INT_MAX - 64) return fail(SFW_EINVAL, "half-resolution volume too large");
-  hipLaunchKernelGGL((k_net_wgrad<CIN, COP>), dim3(27, ng), dim3(256), 0, n->stream, xin, dy, d.Z,
-                     d.Y, d.X, vpg, n->part, n->bpart);
+  hipLaunchKernelGGL((k_net_wgrad_mfma<CIN, COP>), dim3(27, ng), dim3(256), 0, n->stream, xin, dy,
+                     d.Z, d.Y, d.X, vpg, n->part, n->bpart);
   const int e = cout * CIN * 27;
   hipLaunchKernelGGL(k_net_wgrad_sum, dim3((e + 255) / 256), dim3(256), 0, n->stream, n->part, ng,
                      COP, CIN, cout, CIN, gw);
