@@ -320,6 +320,8 @@ def solve_run(L, ws, H, Y, lam, prob, sg, dg):
             "atoms_true": int(truth.shape[0]), "max_centre_error_voxels": err,
             "iterations": stats["iterations"], "criterion": stats["criterion"],
             "eta_evaluations": stats["n_eval_eta"], "cgrad_evaluations": stats["n_eval_cgrad"],
+            "ascent_iterations": stats["n_ascent_iterations"],
+            "slide_iterations": stats["n_slide_iterations"],
             "seconds_certificate": stats["seconds_certificate"],
             "seconds_ascent": stats["seconds_ascent"], "seconds_lasso": stats["seconds_lasso"],
             "seconds_slide": stats["seconds_slide"],

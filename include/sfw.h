@@ -137,6 +137,8 @@ typedef struct {
   int32_t n_fallbacks;       /* of which the grid maximum had to replace (0 or 1) */
   int32_t n_graph_replays;   /* (C, grad C) evaluations replayed from a captured graph */
   int32_t n_tunings;         /* launch shapes timed by the autotuner during this solve */
+  int32_t n_ascent_iterations; /* quasi-Newton iterations of all local ascents (step 1) */
+  int32_t n_slide_iterations;  /* quasi-Newton iterations of all sliding descents */
 } sfw_stats;
 
 /* ---------------------------------------------------------------- lifecycle */

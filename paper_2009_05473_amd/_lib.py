@@ -75,7 +75,8 @@ class SfwStats(ctypes.Structure):
         ("seconds_ascent", ctypes.c_double), ("seconds_lasso", ctypes.c_double),
         ("seconds_slide", ctypes.c_double), ("n_proposals", ctypes.c_int32),
         ("n_fallbacks", ctypes.c_int32), ("n_graph_replays", ctypes.c_int32),
-        ("n_tunings", ctypes.c_int32),
+        ("n_tunings", ctypes.c_int32), ("n_ascent_iterations", ctypes.c_int32),
+        ("n_slide_iterations", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -327,6 +327,7 @@ struct Solver {
     };
     MinResult r = minimize_box(fg, th, lo, hi, o.lbfgs_memory, o.ascent_gtol, o.ftol,
                                o.ascent_max_iter, true);
+    st.n_ascent_iterations += r.iterations;
     if (r.status) return r.status;
     eta_star = -r.f;  // the minimiser's last value is eta at the returned point
     return SFW_OK;
@@ -350,6 +351,7 @@ struct Solver {
     };
     MinResult r = minimize_box(fg, atoms, lo, hi, o.lbfgs_memory, o.slide_gtol, o.ftol,
                                o.slide_max_iter, false, o.slide_slope_tol);
+    st.n_slide_iterations += r.iterations;
     if (o.verbose)
       std::fprintf(stderr, "[sfw] slide n=%d it=%d evals=%d converged=%d (%s) C=%.12g\n", n,
                    r.iterations, r.evaluations, (int)r.converged, r.stop, r.f);
