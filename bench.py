@@ -58,6 +58,7 @@ SLOTS_PER_S = PEAK_FP32_TFLOPS * 1e12 / 2.0   # 256 CUs x 128 lanes x 2.4 GHz = 
 # box; every other pair is an exact zero that it skips.
 RENDER_WAVE_BOX = (16, 4, 8)
 GRAD_WAVE_BOX = (16, 4, 16)
+ETA_WAVE_BOX = (16, 4, 64)  # the one-launch eta kernel's 64-plane-deep tiles
 ATOM_CUT_U = 110.0
 
 
@@ -187,6 +188,44 @@ def zinv_bytes(shape, grid, npairs):
     hx, hy, hz = Nx // 2 + 1, Ny // 2 + 1, Nz // 2 + 1
     nz = shape[0]
     return 8 * (Nx * Ny * Nz + npairs * hx * hy * hz + npairs * nz * Ny * Nx)
+
+
+def cert_pass_bytes(shape, grid, npairs):
+    """HBM bytes the certificate's other passes must move, each reading its input and writing
+    its output once (the zinv_bytes convention): forward x (q in, full complex rows out), y and
+    z passes; after the inverse z pass, the inverse y pass over every pair's z < nz planes and
+    the x pass that reads them and keeps only block maxima."""
+    Nx, Ny, Nz = grid
+    nz, ny, nx = shape
+    fx = 4 * nx * ny * nz + 8 * Nx * ny * nz          # x: q in, rows y < ny, z < nz out
+    fy = 8 * Nx * ny * nz + 8 * Nx * Ny * nz          # y: all Ny rows out
+    fz = 8 * Nx * Ny * nz + 8 * Nx * Ny * Nz          # z: all Nz planes out
+    iy = npairs * 8 * (Nx * Ny * nz + Nx * ny * nz)   # inverse y: rows y < ny out
+    ix = npairs * 8 * Nx * ny * nz                     # inverse x: read, maxima only
+    return fx + fy + fz + iy + ix
+
+
+COLUMN_CUT_U = 28.0
+
+
+def column_box_voxels(shape, theta, psf_shape):
+    """Voxels of a LASSO column's support box (host replica of the library's column box: the
+    ball where the unit atom's u < 28, grown by one voxel and the PSF half-widths; x bounds
+    widened to multiples of 4)."""
+    m, sig, d = theta[:3], theta[3], theta[4]
+    R = sig * (2.0 * COLUMN_CUT_U) ** (1.0 / d) + 1.0
+    pz, py, px = psf_shape
+    c = ((px - 1) / 2.0, (py - 1) / 2.0, (pz - 1) / 2.0)
+    n = (shape[2], shape[1], shape[0])
+    ext = []
+    for a in range(3):
+        lo = int(max(0.0, min(n[a], np.floor(m[a] - R - c[a]))))
+        hi = int(max(0.0, min(n[a], np.ceil(m[a] + R + c[a]) + 1.0)))
+        if a == 0:
+            lo &= ~3
+            hi = min(n[a], (hi + 3) & ~3)
+        ext.append(max(hi - lo, 1))
+    return ext[0] * ext[1] * ext[2]
 
 
 def lut_taps(sigmas, ds, T=12.0):
@@ -464,10 +503,13 @@ def main():
     grad_buf = torch.empty((N, 6), dtype=torch.float32, device="cuda")
     w_buf = torch.empty(N, dtype=torch.float64, device="cuda")
 
+    last_point = []
+
     def step(k):
         L.sfw_residual_grad(ws, H, Y, lam, A, r_out=R, loss_out=loss_buf, grad_out=grad_buf)  # a1-a5
         _, best = L.sfw_certificate(ws, H, None, lam, sg, dg, vol_shape=shape)  # a6-a7
         th = [[best["x"], best["y"], best["z"], sg[best["i_sigma"]], dg[best["i_d"]]]]
+        last_point[:] = th
         L.sfw_eta_points(ws, shape, None, lam, th)                           # a8
         L.sfw_lasso_weights(ws, H, Y, lam, supports[k], w_out=w_buf)          # a9
 
@@ -507,12 +549,24 @@ def main():
     pairs_render = evaluated_pairs(shape, atoms_eval, RENDER_WAVE_BOX)
     pairs_grad = evaluated_pairs(shape, atoms_eval, GRAD_WAVE_BOX)
     vb = 4.0 * V  # one float32 volume
+    # the step's eta point (the certificate maximum's unit atom) and new LASSO column (the
+    # support's last atom, moved every step)
+    pairs_eta = evaluated_pairs(shape, [[1.0] + list(last_point[0])], ETA_WAVE_BOX)
+    col_vox = column_box_voxels(shape, [float(v) for v in atoms_eval[-1, 1:6]], psf.shape)
+    nd = N  # Gram row against the support's columns and y
     work = {  # class: (HBM bytes, ALU slots) per launch
         "render": (vb + 32.0 * N, float(pairs_render * RENDER_SLOTS_PER_PAIR)),
         "conv_residual": (3 * vb, 0.0),   # f and y in, r out (r stays in LDS for the adjoint)
         "conv_adjoint": (vb, 0.0),        # q out
         "grad": (vb, float(pairs_grad * GRAD_SLOTS_PER_PAIR)),  # q in
         "cert_zinv": (float(zbytes), 0.0),
+        "cert_fft": (cert_pass_bytes(shape, grid, npairs) / 2.0, 0.0),  # two launches a step
+        "eta_grad": (0.0, float(pairs_eta * GRAD_SLOTS_PER_PAIR)),
+        # the new column over its box: one FMA slot per tap per box voxel (the atom's own
+        # evaluation on the block tiles aside)
+        "lasso_conv": (4.0 * col_vox, float(col_vox * taps)),
+        # the Gram row: the new column and nd + 1 others (columns, y) over its box
+        "lasso_dots": (4.0 * col_vox * (nd + 2), 0.0),
     }
     ps = max(args.profile_steps, 1)
     breakdown = {}
