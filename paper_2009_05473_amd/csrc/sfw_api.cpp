@@ -1158,9 +1158,11 @@ int sfw_workspace_create(sfw_workspace** out, sfw_dims vol_max, sfw_dims psf_max
             break;
           }
       }
-      const size_t px = (size_t)((L[0] / 2 + 1 + 3) & ~3);
-      ws->blur_spec_cap = px * L[1] * vol_max.nz;
-      ws->blur_hhat_cap = px * L[1] * L[2];
+      // planes may take the longer of the two in-plane lengths for both axes (blur_plan)
+      const int Lp = std::max(L[0], L[1]);
+      const size_t px = (size_t)((Lp / 2 + 1 + 3) & ~3);
+      ws->blur_spec_cap = px * Lp * vol_max.nz;
+      ws->blur_hhat_cap = px * Lp * L[2];
       ALLOC(ws->blur_spec, ws->blur_spec_cap * sizeof(float2), "blur spectrum");
       ALLOC(ws->blur_hhat, ws->blur_hhat_cap * sizeof(float2), "PSF spectrum");
       ALLOC(ws->blur_tw, 3 * (size_t)kFftMaxBlur * sizeof(float2), "blur twiddles");

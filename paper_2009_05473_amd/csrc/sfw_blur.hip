@@ -887,13 +887,28 @@ bool blur_plan(const sfw_dims& vol, const sfw_dims& psf, BlurPlan& bp) {
       }
     if (!bp.N[a]) return false;
   }
+  // fused plane passes: square transforms in x and y, plane + exchange buffer in LDS. A plane
+  // whose two axes want different lengths takes the longer one for both (more zero padding
+  // changes nothing in the zero-padded linear convolution) when the plane still fits LDS: three
+  // launches per blur instead of five.
+  const size_t np = (size_t)(vol.ny + 1) / 2;
+  auto plane_lds = [&](int L) {
+    const size_t hx = (size_t)L / 2 + 1;
+    return ((size_t)vol.ny * hx + std::max(np, hx) * (size_t)(L | 1)) * sizeof(float2);
+  };
+  const bool passes = std::getenv("SFW_BLUR_PASSES") != nullptr;
+  if (!passes && bp.N[0] != bp.N[1]) {
+    const int a = bp.N[0] > bp.N[1] ? 0 : 1;
+    if (plane_lds(bp.N[a]) <= kPlaneLdsMax) {
+      bp.N[1 - a] = bp.N[a];
+      bp.r1[1 - a] = bp.r1[a];
+      bp.r2[1 - a] = bp.r2[a];
+    }
+  }
   bp.hx = bp.N[0] / 2 + 1;
   bp.px = (bp.hx + 3) & ~3;
-  // fused plane passes: square transforms in x and y, plane + exchange buffer in LDS
-  const size_t np = (size_t)(vol.ny + 1) / 2;
-  bp.lds = ((size_t)vol.ny * bp.hx + std::max(np, (size_t)bp.hx) * (size_t)(bp.N[0] | 1)) *
-           sizeof(float2);
-  bp.fused = bp.N[0] == bp.N[1] && bp.lds <= kPlaneLdsMax && std::getenv("SFW_BLUR_PASSES") == nullptr;
+  bp.lds = plane_lds(bp.N[0]);
+  bp.fused = bp.N[0] == bp.N[1] && bp.lds <= kPlaneLdsMax && !passes;
   const int rmax = std::max(bp.r1[0], bp.r2[0]);
   bp.chain = bp.fused && (int)np * rmax <= kPlaneThreads && bp.hx * rmax <= kPlaneThreads;
   return true;

@@ -135,8 +135,9 @@ def test_residual_grad_parity(L, ws_big, name, conv_path):
 
 @pytest.mark.parametrize("shape", [(23, 29, 37), (23, 29, 29)])
 def test_residual_grad_edge(L, ws_big, conv_path, shape):
-    """Ragged sizes; (23, 29, 29) gives square plane transforms, so the spectral blur runs its
-    fused plane passes on a plane that is not a multiple of any tile."""
+    """Ragged sizes, on planes that are not a multiple of any tile; on the spectral paths both
+    shapes run the fused plane passes (23 x 37 planes with one transform length for both axes),
+    and the five separate passes where forced."""
     rng = np.random.default_rng(77)
     psf = f32(np.abs(rng.standard_normal((9, 5, 7))) + 0.05)
     psf /= psf.sum()
@@ -161,13 +162,19 @@ def test_residual_grad_edge(L, ws_big, conv_path, shape):
     assert rel_err(loss0.cpu().numpy()[0], 0.5 * np.sum(y * y)) <= 1e-6
 
 
-@pytest.mark.parametrize("shape,n", [((40, 96, 80), 30), ((40, 70, 70), 100)])
-def test_residual_grad_cut_atoms(L, ws_big, shape, n):
+@pytest.mark.parametrize("shape,n,passes", [((40, 96, 80), 30, True), ((40, 96, 80), 30, False),
+                                            ((40, 70, 70), 100, False)])
+def test_residual_grad_cut_atoms(L, ws_big, shape, n, passes, monkeypatch):
     """Atoms skipped where they are exactly zero: many narrow atoms (most tiles skip most of
     them), centres outside the volume, and wide long-tailed atoms (cut radius past the whole
     volume, never skipped), against the oracle's dense sums. (40, 96, 80) runs the blur's five
-    separate passes, (40, 70, 70) its fused plane passes over ragged tiles, with more atoms
-    than one wave's atom list holds (two groups of 64)."""
+    separate passes (forced) and its fused plane passes with one transform length for both
+    axes; (40, 70, 70) the plane passes over ragged tiles, with more atoms than one wave's atom
+    list holds (two groups of 64)."""
+    if passes:
+        monkeypatch.setenv("SFW_BLUR_PASSES", "1")
+    else:
+        monkeypatch.delenv("SFW_BLUR_PASSES", raising=False)
     rng = np.random.default_rng(2024)
     psf = f32(synth.gaussian_psf(1.0, 2.0, (15, 9, 9)))
     nz, ny, nx = shape
@@ -202,13 +209,19 @@ def test_residual_grad_cut_atoms(L, ws_big, shape, n):
     assert rel_l2(gg, g) <= 1e-4
 
 
-@pytest.mark.parametrize("shape", [(40, 48, 56), (40, 52, 52)])
-def test_large_psf_spectral(L, shape, monkeypatch):
+@pytest.mark.parametrize("shape,passes", [((40, 48, 56), True), ((40, 48, 56), False),
+                                          ((40, 52, 52), False)])
+def test_large_psf_spectral(L, shape, passes, monkeypatch):
     """A 17 x 17 x 33 PSF (9,537 taps: more than the spectrum kernel stages in LDS, the largest
-    of the batched-solve workload's 4-sigma PSFs) through the Fourier-domain blur, with the five
-    separate passes (48 x 56 planes) and with the fused plane passes (52 x 52): forward model,
-    residual, criterion and gradient against the oracle."""
+    of the batched-solve workload's 4-sigma PSFs) through the Fourier-domain blur: the five
+    separate passes, the fused plane passes on 48 x 56 planes (both axes take the longer
+    transform) and on 52 x 52 planes. Forward model, residual, criterion and gradient against
+    the oracle."""
     monkeypatch.setenv("SFW_CONV", "fft")
+    if passes:
+        monkeypatch.setenv("SFW_BLUR_PASSES", "1")
+    else:
+        monkeypatch.delenv("SFW_BLUR_PASSES", raising=False)
     rng = np.random.default_rng(33)
     psf = f32(synth.gaussian_psf(2.0, 4.0, (33, 17, 17)))
     truth = f32(synth.random_atoms(rng, 5, shape, margin=4))
