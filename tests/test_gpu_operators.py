@@ -240,6 +240,33 @@ def test_large_psf_spectral(L, shape, passes, monkeypatch):
     assert rel_l2(grad.cpu().numpy(), g) <= 1e-4
 
 
+def test_residual_grad_many_atoms(L):
+    """1100 atoms: more than the gradient items' kernel keeps in LDS (1024), so every item
+    reads its atom again, and 18 groups of 64 in the render's atom lists; against the oracle."""
+    shape = (24, 40, 48)
+    n = 1100
+    rng = np.random.default_rng(1100)
+    psf = f32(synth.gaussian_psf(1.0, 1.5, (9, 7, 7)))
+    atoms = np.zeros((n, 6))
+    atoms[:, 0] = rng.uniform(0.2, 1.0, n)
+    atoms[:, 1] = rng.uniform(-2, shape[2] + 2, n)
+    atoms[:, 2] = rng.uniform(-2, shape[1] + 2, n)
+    atoms[:, 3] = rng.uniform(-2, shape[0] + 2, n)
+    atoms[:, 4] = rng.uniform(0.6, 1.6, n)
+    atoms[:, 5] = rng.uniform(1.5, 2.8, n)
+    atoms = f32(atoms)
+    y = f32(rng.standard_normal(shape))
+    lam = 0.3
+    say("sfw_residual_grad", shape, "atoms", n)
+    with L.Workspace(shape, psf.shape, n) as w:
+        r, loss, grad = L.sfw_residual_grad(w, dev(psf), dev(y), lam, dev(atoms))
+        torch.cuda.synchronize()
+    C, g, r_o, _ = oracle.criterion_and_grad(y, atoms, psf, lam)
+    assert rel_l2(r.cpu().numpy(), r_o) <= 1e-5
+    assert rel_err(loss.cpu().numpy()[0], C) <= 1e-5
+    assert rel_l2(grad.cpu().numpy(), g) <= 1e-4
+
+
 def test_psf_spectrum_follows_h(L, ws_big, monkeypatch):
     """The spectral blur keeps the PSF spectrum between calls: overwriting H in place, and a
     PSF of another shape, must both be seen."""
