@@ -56,7 +56,7 @@ SLOTS_PER_S = PEAK_FP32_TFLOPS * 1e12 / 2.0   # 256 CUs x 128 lanes x 2.4 GHz = 
 # Voxel boxes of one wave in the render and gradient kernels (x, y, z): a wave evaluates an atom
 # only where its cut ball (the radius beyond which the atom is exactly zero in float32) meets its
 # box; every other pair is an exact zero that it skips.
-RENDER_WAVE_BOX = (16, 4, 8)
+RENDER_WAVE_BOX = (16, 4, 4)
 GRAD_WAVE_BOX = (16, 4, 16)
 ETA_WAVE_BOX = (16, 4, 64)  # the one-launch eta kernel's 64-plane-deep tiles
 ATOM_CUT_U = 110.0

@@ -57,7 +57,7 @@ constexpr int kMfmaPatchMax = 512;
 
 // Voxel columns of the render kernel: 256 threads over the flattened (y, x) plane,
 // kRenderVPT consecutive z per thread by default (4, 8 or 16: the autotuner's candidates).
-constexpr int kRenderVPT = 8;
+constexpr int kRenderVPT = 4;
 // Gradient-sum kernels: 256 threads over a 16 x 16 tile of (y, x) columns, VPT z per thread.
 constexpr int kGradThreads = 256;
 
