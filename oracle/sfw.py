@@ -40,7 +40,7 @@ MERGE_TOL = 5e-2
 __all__ = [
     "T_TRUNC", "PRUNE_REL", "ETA_TOL", "MERGE_TOL", "merge_coincident", "coords", "atom_profile", "render", "blur", "adjoint",
     "criterion", "criterion_and_grad", "forward_vjp", "eta_point", "lut_radius", "lut_kernel",
-    "grid_certificate", "grid_argmax", "lasso_columns", "lasso_weights", "ascent",
+    "grid_certificate", "grid_argmax", "lasso_columns", "lasso_weights", "nnqp", "ascent",
     "slide", "prune", "solve", "SolveResult", "max_grid_certificate",
 ]
 
@@ -278,9 +278,8 @@ def lasso_columns(shape, thetas, psf):
 def lasso_weights(y, thetas, psf, lam):
     """argmin_{w >= 0} 1/2 ||y - sum_n w_n a_n||^2 + lam sum_n w_n (section 1.3, step 3).
 
-    With G = A^T A = L L^T and b = A^T y the objective is
-    1/2 ||L^T w - L^{-1}(b - lam 1)||^2 + const, a non-negative least-squares
-    problem handed to scipy.optimize.nnls. Returns (w, G, b).
+    With G = A^T A and b = A^T y the objective is 1/2 w^T G w - (b - lam 1)^T w + const,
+    minimised by nnqp. Returns (w, G, b).
     """
     y = np.asarray(y, dtype=np.float64)
     A = lasso_columns(y.shape, thetas, psf)
@@ -289,14 +288,29 @@ def lasso_weights(y, thetas, psf, lam):
         return np.zeros(0), np.zeros((0, 0)), np.zeros(0)
     G = A @ A.T
     b = A @ y.reshape(-1)
+    return nnqp(G, b - lam), G, b
+
+
+def nnqp(G, c):
+    """argmin_{w >= 0} 1/2 w^T G w - c^T w: the weights step of section 1.3 (step 3) once the
+    Gram matrix G = A^T A of the columns and c = A^T y - lam are formed.
+
+    With G = L L^T the objective is 1/2 ||L^T w - L^{-1} c||^2 + const, a non-negative
+    least-squares problem handed to scipy.optimize.nnls.
+    """
+    G = np.asarray(G, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    k = c.shape[0]
+    if k == 0:
+        return np.zeros(0)
     try:
         L = linalg.cholesky(G, lower=True)
     except linalg.LinAlgError:
         # duplicate atoms make G singular; any KKT point is then a minimiser
         L = linalg.cholesky(G + 1e-12 * np.trace(G) / k * np.eye(k), lower=True)
-    rhs = linalg.solve_triangular(L, b - lam, lower=True)
+    rhs = linalg.solve_triangular(L, c, lower=True)
     w, _ = optimize.nnls(L.T, rhs, maxiter=50 * k + 100)
-    return w, G, b
+    return w
 
 
 # ---------------------------------------------------------------- local ascent / descent

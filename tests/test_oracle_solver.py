@@ -178,3 +178,61 @@ def test_merge_coincident_pins():
     m = oracle.merge_coincident(np.vstack([a, far, c, e]))
     assert m.shape == (2, 6) and m[0, 0] == pytest.approx(3 * a[0])
     assert m[0, 1] == pytest.approx(a[1], abs=1e-12)
+
+
+def _qp_objective(G, c, w):
+    return 0.5 * w @ G @ w - c @ w
+
+
+def _qp_by_supports(G, c):
+    """Brute force: the KKT point among all 2^k supports (positive on S, non-negative
+    gradient off S); the objective's minimiser over w >= 0 for positive definite G."""
+    k = c.shape[0]
+    best = None
+    for bits in itertools.product([0, 1], repeat=k):
+        S = np.array(bits, dtype=bool)
+        w = np.zeros(k)
+        if S.any():
+            w[S] = np.linalg.solve(G[np.ix_(S, S)], c[S])
+            if np.any(w[S] <= 0):
+                continue
+        g = G @ w - c
+        if np.all(g[~S] >= -1e-10 * np.abs(c).max()):
+            assert best is None, "two KKT points of a strictly convex problem"
+            best = w
+    return best
+
+
+def test_nnqp_diagonal_closed_form():
+    d = np.array([2.0, 0.5, 4.0, 1.0, 3.0])
+    c = np.array([1.0, -2.0, 3.0, 0.0, -1e-9])
+    w = oracle.nnqp(np.diag(d), c)
+    np.testing.assert_allclose(w, np.maximum(c, 0.0) / d, rtol=1e-12, atol=1e-15)
+    assert oracle.nnqp(np.zeros((0, 0)), np.zeros(0)).shape == (0,)
+
+
+@pytest.mark.parametrize("seed,k", [(31, 4), (32, 6), (33, 7)])
+def test_nnqp_matches_support_enumeration(seed, k):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((2 * k + 3, k))
+    G = A.T @ A
+    c = rng.standard_normal(k) * 2.0
+    w = oracle.nnqp(G, c)
+    want = _qp_by_supports(G, c)
+    np.testing.assert_allclose(w, want, rtol=1e-9, atol=1e-12)
+    assert w.min() >= 0.0 and 0 < (w > 0).sum() < k  # a case with both kinds of coordinate
+
+
+def test_nnqp_singular_gram_reaches_the_minimum():
+    """Duplicate columns (the same atom twice) make G singular: the minimiser is not unique,
+    but the objective's minimum is, and it equals the one without the duplicate."""
+    rng = np.random.default_rng(34)
+    A = rng.standard_normal((12, 4))
+    c = rng.standard_normal(4) + 1.0
+    G = A.T @ A
+    A2 = np.concatenate([A, A[:, 1:2]], axis=1)
+    c2 = np.append(c, c[1])
+    w2 = oracle.nnqp(A2.T @ A2, c2)
+    w = _qp_by_supports(G, c)
+    assert _qp_objective(A2.T @ A2, c2, w2) == pytest.approx(_qp_objective(G, c, w), rel=1e-9)
+    assert w2[1] + w2[4] == pytest.approx(w[1], rel=1e-6, abs=1e-9)
