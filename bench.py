@@ -147,6 +147,9 @@ def parse():
                     help="train the proposal network for STEPS steps, then compare BSFW with "
                          "learned and with grid seeds on held-out volumes (0: skip)")
     ap.add_argument("--proposal-volumes", type=int, default=10)
+    ap.add_argument("--nnqp", type=int, default=4096, metavar="COUNT",
+                    help="time sfw_nnqp_batch on COUNT weights QPs of 50 atoms in one launch, "
+                         "and on one alone (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB on the device (the "
                          "known-size copy that scales the HBM counters of a --pmc run)")
@@ -369,6 +372,38 @@ def solve_run(L, ws, H, Y, lam, prob, sg, dg):
             "criterion_default_shapes": st_eager["criterion"],
             "seconds_graphs": dt_graph, "graph_replays": st_graph["n_graph_replays"],
             "criterion_graphs": st_graph["criterion"]}
+
+
+def nnqp_run(L, count, k=50, reps=20):
+    """Throughput of the batched weights QP (sfw_nnqp_batch): count problems of k atoms in one
+    launch, and one problem alone (its latency). Each problem is G = A'A, c = A'y - 0.5 of a
+    tall Gaussian A (2k + 8 rows) and y = A w + noise with a sparse non-negative w, 16 distinct
+    seeded problems repeated; HIP events on torch's current stream bracket reps launches."""
+    import torch
+    rng = np.random.default_rng(5150)
+    base = []
+    for _ in range(16):
+        A = rng.standard_normal((2 * k + 8, k))
+        w = rng.uniform(0.2, 1.5, size=k) * (rng.uniform(size=k) < 0.7)
+        y = A @ w + 0.3 * rng.standard_normal(A.shape[0])
+        base.append((A.T @ A, A.T @ y - 0.5))
+    rec = {"workload": f"weights QP, {k} atoms (Gram matrix of random columns)", "atoms": k}
+    for n in (count, 1):
+        G = torch.from_numpy(np.stack([base[i % 16][0] for i in range(n)])).cuda()
+        c = torch.from_numpy(np.stack([base[i % 16][1] for i in range(n)])).cuda()
+        w, info = L.sfw_nnqp_batch(G, c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            L.sfw_nnqp_batch(G, c, None, w, info)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        key = "batch" if n == count else "single"
+        rec[key] = {"problems": n, "us_per_launch": us, "problems_per_s": n / us * 1e6,
+                    "mean_passive_solves": float(info.float().mean().item())}
+    return rec
 
 
 def batch_run(L, synth, n_volumes, n_workspaces):
@@ -634,6 +669,8 @@ def main():
         out["batch"] = batch_run(L, synth, args.batch_volumes, args.batch)
     if args.proposal > 0:
         out["proposal"] = proposal_run(L, shape, args.proposal, args.proposal_volumes)
+    if args.nnqp > 0:
+        out["nnqp"] = nnqp_run(L, args.nnqp)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, atoms_eval.astype(np.float64),
                                            psf.astype(np.float64))

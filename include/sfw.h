@@ -231,6 +231,24 @@ int sfw_lasso_weights(sfw_workspace* ws, const float* H, sfw_dims psf, sfw_dims 
                       const float* y, float lambda, const sfw_atom* atoms, int n,
                       double* w_out);
 
+/* The weights step's quadratic program on the device, for many problems in one launch
+ * (algorithm 1 step 3 and algorithm 2 step 3: the criterion of section 1.1 restricted to the
+ * weights, whose Gram matrix and linear term sfw_lasso_weights builds): for p = 0..count-1,
+ * minimise 1/2 w'G_p w - c_p'w subject to w >= 0, in float64, by the active-set method of the
+ * host solver (one workgroup per problem, the Cholesky factor of the passive block in LDS).
+ * G: device double [count][kmax][kmax], problem p's matrix in the leading k_p x k_p block (row
+ * stride kmax), symmetric (both triangles stored and equal) and positive semi-definite;
+ * c: device double [count][kmax] (entries past k_p ignored); k: device int [count] with each
+ * k_p in [0, kmax], or NULL for k_p = kmax; kmax in [0, SFW_NNQP_MAX_K]; w: device double
+ * [count][kmax], written with the minimisers (zeros past k_p); info: device int [count] or
+ * NULL, per problem the number of passive-set solves it took, negated if an iteration cap
+ * (4 k_p + 20 steps of either loop) ended it. Enqueued on `stream` and returns without a
+ * synchronisation. SFW_EINVAL for count < 0, kmax outside its range or a NULL G, c or w
+ * (count = 0 or kmax = 0 is a no-op), SFW_EHIP if the launch fails. */
+#define SFW_NNQP_MAX_K 128
+int sfw_nnqp_batch(const double* G, const double* c, const int* k, int kmax, int count,
+                   double* w, int* info, hipStream_t stream);
+
 /* Certificate at points and its gradient, as sfw_eta_points, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): no workspace, no allocation and no synchronisation. Its scratch (per-tile

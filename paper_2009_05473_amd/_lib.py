@@ -28,9 +28,10 @@ EXPORTED = (
     "sfw_solve", "sfw_solve_batch", "sfw_profile_begin", "sfw_profile_end",
     "sfw_net_num_params", "sfw_net_create", "sfw_net_destroy", "sfw_net_set_params",
     "sfw_net_get_params", "sfw_net_forward", "sfw_net_gradients", "sfw_net_train_step",
-    "sfw_net_propose", "sfw_eta_points_noalloc",
+    "sfw_net_propose", "sfw_eta_points_noalloc", "sfw_nnqp_batch",
 )
 SFW_NOALLOC_SCRATCH_BYTES, SFW_NOALLOC_MAX_POINTS = 1 << 20, 8
+SFW_NNQP_MAX_K = 128
 SFW_PROF_KINDS = 16
 
 
@@ -121,6 +122,7 @@ def _load():
         "sfw_certificate": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp, i32, f32, vp, vp]),
         "sfw_eta_points": (i32, [vp, D, vp, f32, vp, i32, vp, vp]),
         "sfw_eta_points_noalloc": (i32, [D, vp, f32, vp, i32, vp, vp, vp]),
+        "sfw_nnqp_batch": (i32, [vp, vp, vp, i32, i32, vp, vp, vp]),
         "sfw_lasso_weights": (i32, [vp, vp, D, D, vp, f32, vp, i32, vp]),
         "sfw_solve": (i32, [vp, vp, D, vp, D, f32, ctypes.POINTER(SfwOptions), vp, i32,
                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SfwStats)]),
@@ -343,6 +345,30 @@ def sfw_eta_points_noalloc(vol_shape, q, lam, thetas, eta_out=None, grad_out=Non
                                      _dev_ptr(grad_out, "float64", "grad_out"),
                                      _stream_handle(stream)))
     return eta_out[:n], grad_out[:n]
+
+
+def sfw_nnqp_batch(G, c, k=None, w_out=None, info_out=None, stream=None):
+    """G: device float64 [count, kmax, kmax] (symmetric blocks), c: device float64
+    [count, kmax], k: device int32 [count] or None (every problem of size kmax). Enqueues the
+    batched weights QP on `stream` (torch's current stream by default); returns (w, info),
+    device tensors [count, kmax] float64 and [count] int32 (allocated here when None)."""
+    import torch
+    if G.dim() != 3 or G.shape[1] != G.shape[2]:
+        raise ValueError("G: expected [count, kmax, kmax]")
+    count, kmax = int(G.shape[0]), int(G.shape[1])
+    if tuple(c.shape) != (count, kmax):
+        raise ValueError("c: expected [count, kmax]")
+    if k is not None and tuple(k.shape) != (count,):
+        raise ValueError("k: expected [count]")
+    if w_out is None:
+        w_out = torch.empty((count, kmax), dtype=torch.float64, device=G.device)
+    if info_out is None:
+        info_out = torch.empty(count, dtype=torch.int32, device=G.device)
+    check(lib.sfw_nnqp_batch(_dev_ptr(G, "float64", "G"), _dev_ptr(c, "float64", "c"),
+                             _dev_ptr(k, "int32", "k"), kmax, count,
+                             _dev_ptr(w_out, "float64", "w_out"),
+                             _dev_ptr(info_out, "int32", "info_out"), _stream_handle(stream)))
+    return w_out, info_out
 
 
 def sfw_lasso_weights(ws: Workspace, H, y, lam, atoms, w_out=None):

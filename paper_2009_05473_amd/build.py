@@ -15,7 +15,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsfw.so")
 OBJ_DIR = os.path.join(PKG, "_build")
 SOURCES = ["sfw_kernels.hip", "sfw_fft.hip", "sfw_fft_fixed.hip", "sfw_blur.hip", "sfw_api.cpp",
-           "sfw_solver.cpp", "sfw_nnqp.cpp", "sfw_batch.cpp", "sfw_cnn.hip", "sfw_noalloc.hip"]
+           "sfw_solver.cpp", "sfw_nnqp.cpp", "sfw_batch.cpp", "sfw_cnn.hip", "sfw_noalloc.hip",
+           "sfw_nnqp_dev.hip"]
 ARCH = "gfx950"
 # hipcc's host pass does not know the packed-FP32 target feature; its warning is noise
 NOISE = "is not a recognized feature for this target"

@@ -127,3 +127,20 @@ def test_net_entry_points_validate_before_touching_the_gpu():
     assert L.sfw_net_train_step(None, None, D(8, 8, 8), 1.0, None, 0, 1e-3, None) == _lib.SFW_EINVAL
     assert L.sfw_net_propose(None, None, D(8, 8, 8), 1.0, None, None) == _lib.SFW_EINVAL
     L.sfw_net_destroy(None)  # no-op
+
+
+def test_nnqp_batch_validates_before_touching_the_gpu():
+    from paper_2009_05473_amd import _lib
+    L = _lib.lib
+    text = open(HEADER).read()
+    assert int(re.search(r"#define SFW_NNQP_MAX_K (\d+)", text).group(1)) == _lib.SFW_NNQP_MAX_K
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below fails its host checks
+    assert L.sfw_nnqp_batch(fake, fake, None, _lib.SFW_NNQP_MAX_K + 1, 1, fake, None, None) == _lib.SFW_EINVAL
+    assert "SFW_NNQP_MAX_K" in _lib.last_error()
+    assert L.sfw_nnqp_batch(fake, fake, None, 4, -1, fake, None, None) == _lib.SFW_EINVAL
+    assert L.sfw_nnqp_batch(fake, fake, None, -1, 1, fake, None, None) == _lib.SFW_EINVAL
+    assert L.sfw_nnqp_batch(None, fake, None, 4, 1, fake, None, None) == _lib.SFW_EINVAL
+    assert L.sfw_nnqp_batch(fake, fake, None, 4, 1, None, None, None) == _lib.SFW_EINVAL
+    assert "NULL" in _lib.last_error()
+    assert L.sfw_nnqp_batch(None, None, None, 4, 0, None, None, None) == _lib.SFW_OK  # no-op
+    assert L.sfw_nnqp_batch(None, None, None, 0, 3, None, None, None) == _lib.SFW_OK
