@@ -87,8 +87,8 @@ def evaluated_pairs(shape, atoms, box):
 
 # HBM traffic of one launch of the roofline kernel at this workload, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
-#   bench.py --steps 2 --warmup 1 --profile-steps 0 --no-cpu-baseline --no-solve
-#            --copy-probe-mib 256
+#   bench.py --steps 2 --warmup 1 --profile-steps 0 --no-cpu-baseline --no-solve --proposal 0
+#            --nnqp 0 --copy-probe-mib 256
 # each scaled by the same counter's reading for the known 256 MiB device copy at the end.
 # The record holds for the kernel source it was taken on: sha256 of the kernel's definition in
 # KERNEL_SOURCE (from its template line to the next section rule). None until measured.
@@ -97,9 +97,9 @@ KERNEL_START = ("template <int R1, int R2>\n__global__ __launch_bounds__(fx_thre
                 "void k_fx_z_inverse(")
 SECTION_RULE = "\n// ----"
 ROOF_TRAFFIC = {
-    "fetch_kib": 13912.9, "write_kib": 68400.0,          # k_fx_z_inverse<9, 9>, per dispatch
+    "fetch_kib": 13667.8, "write_kib": 68400.0,          # k_fx_z_inverse<9, 9>, per dispatch
     "copy_mib": 256, "copy_fetch_kib": 131087.8, "copy_write_kib": 262144.0,
-    "source_sha256": "f704e2e1e3aed9bcc307d2448205cd2e4cda3ac669b12996c99839e0aee76965",
+    "source_sha256": "cefa6576c1d802f039c77da37a12c84e78561ebd27905bb7d9ada049af72d829",
 }
 
 

@@ -95,9 +95,12 @@ __global__ __launch_bounds__(fx_threads(R1, R2)) void k_fx_strided(
 __device__ __forceinline__ int fold(int k, int N) { return 2 * k <= N ? k : N - k; }
 
 // First inverse pass, along z (L = Nz), for every pair: column (x0 + c, y) of Qhat is loaded
-// once, then for each pair p the input conj(Qhat * P_p) (P_p read from its octant) is
-// transformed and rows z < n_out are written to work + p * work_b. The next pair's spectrum
-// values are fetched while the current pair's second stage runs.
+// once into LDS (each task keeps its R1 elements there), then for each pair p the input
+// conj(Qhat * P_p) (P_p read from its octant) is transformed and rows z < n_out are written to
+// work + p * work_b. Keeping Qhat in LDS rather than registers, and fetching a pair's octant
+// values where they are used rather than one pair ahead, holds the kernel at 88 VGPRs at L = 81,
+// five waves per SIMD, so that the whole grid of the 128 x 128 x 64 workload is resident at once
+// (at 120 VGPRs a sixth of its blocks waited for a second round).
 //
 // Rows y and Ny - y read the same octant rows, as do all x groups of a row. Workgroups go to
 // the 8 XCDs round-robin by linear id and each XCD has its own L2, so the 1D grid is remapped:
@@ -109,9 +112,10 @@ __global__ __launch_bounds__(fx_threads(R1, R2)) void k_fx_z_inverse(
     const float2* __restrict__ qhat, const float2* __restrict__ oct, size_t oct_b, int hx, int hy,
     float2* __restrict__ work, size_t work_b, const float2* __restrict__ twg, int Nx, int Ny,
     int px, int n_out, int npairs, int gx, int chunk) {
-  constexpr int L = R1 * R2, LS = L | 1, C = kFxLines, NT = fx_threads(R1, R2);
+  constexpr int L = R1 * R2, LS = L | 1, C = kFxLines, NT = fx_threads(R1, R2), T1 = C * R2;
   __shared__ float2 buf[C * LS];
   __shared__ float2 tw[L];
+  __shared__ float2 qs[R1 * T1];  // the column of Qhat, element r of task t at qs[r T1 + t]
   const int lid = blockIdx.x;
   const int seq = (lid & 7) * chunk + (lid >> 3);
   if (seq >= gx * Ny) return;
@@ -123,27 +127,29 @@ __global__ __launch_bounds__(fx_threads(R1, R2)) void k_fx_z_inverse(
   const size_t obase = (size_t)y * px + x0;
   const int cols = min(C, Nx - x0);
   const int t = threadIdx.x;
-  const bool s1 = t < C * R2;
+  const bool s1 = t < T1;
   const int c1 = t % C, j1 = t / C;
   const bool cok = s1 && c1 < cols;
-  // octant offsets of this task's elements (pair 0)
+  // octant offset of this task's element r (any pair): (fold(i) hy + my) hx + mx
   const int mx = fold(min(x0 + c1, Nx - 1), Nx), my = fold(y, Ny);
-  int po[R1];
-  float2 q[R1], m[R1];
+  auto po = [&](int r) { return (fold(j1 + r * R2, L) * hy + my) * hx + mx; };
+  if (s1) {
 #pragma unroll
-  for (int r = 0; r < R1; ++r) {
-    const int i = j1 + r * R2;  // < L
-    po[r] = (fold(i, L) * hy + my) * hx + mx;
-    const float2 a = qhat[obase + (cok ? (size_t)i * istride + c1 : 0)];
-    q[r] = cok ? a : make_float2(0.f, 0.f);
-    m[r] = oct[s1 ? po[r] : 0];
+    for (int r = 0; r < R1; ++r) {
+      const int i = j1 + r * R2;  // < L
+      const float2 a = qhat[obase + (cok ? (size_t)i * istride + c1 : 0)];
+      qs[r * T1 + t] = cok ? a : make_float2(0.f, 0.f);
+    }
   }
   for (int p = 0; p < npairs; ++p) {
     if (s1) {
+      const float2* P = oct + (size_t)p * oct_b;
       float2 v[R1];
 #pragma unroll
+      for (int r = 0; r < R1; ++r) v[r] = P[po(r)];
+#pragma unroll
       for (int r = 0; r < R1; ++r) {
-        v[r] = cmul(q[r], m[r]);
+        v[r] = cmul(qs[r * T1 + t], v[r]);
         v[r].y = -v[r].y;
       }
       Dft<R1>::run(v);
@@ -151,11 +157,6 @@ __global__ __launch_bounds__(fx_threads(R1, R2)) void k_fx_z_inverse(
       for (int r = 0; r < R1; ++r) buf[c1 * LS + j1 * R1 + r] = v[r];
     }
     __syncthreads();
-    if (s1 && p + 1 < npairs) {
-      const float2* P = oct + (size_t)(p + 1) * oct_b;
-#pragma unroll
-      for (int r = 0; r < R1; ++r) m[r] = P[po[r]];
-    }
     if (t < C * R1) {
       const int c = t % C, j = t / C;
       float2 v[R2];
