@@ -58,7 +58,7 @@ SLOTS_PER_S = PEAK_FP32_TFLOPS * 1e12 / 2.0   # 256 CUs x 128 lanes x 2.4 GHz = 
 # box; every other pair is an exact zero that it skips.
 RENDER_WAVE_BOX = (16, 4, 4)
 GRAD_WAVE_BOX = (16, 4, 16)
-ETA_WAVE_BOX = (16, 4, 64)  # the one-launch eta kernel's 64-plane-deep tiles
+ETA_WAVE_BOX = (16, 4, 32)  # the one-launch eta kernel's 32-plane-deep tiles
 ATOM_CUT_U = 110.0
 
 

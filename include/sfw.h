@@ -260,7 +260,7 @@ int sfw_nnqp_batch(const double* G, const double* c, const int* k, int kmax, int
  * eta_out: device double [n]; grad_out: device double [n][5] or NULL; stream: where the
  * kernels are enqueued (results valid once it reaches them). SFW_EINVAL for invalid
  * arguments or when the tiles the points' atoms cover need more partials than the scratch
- * holds (about 43,000 tiles of 16 x 16 x 64 voxels at 1 point, 5,400 at 8 points). */
+ * holds (about 43,000 tiles of 16 x 16 x 32 voxels at 1 point, 5,400 at 8 points). */
 #define SFW_NOALLOC_SCRATCH_BYTES (1u << 20)
 #define SFW_NOALLOC_MAX_POINTS 8
 int sfw_eta_points_noalloc(sfw_dims vol, const float* q, float lambda, const float* thetas,

@@ -814,7 +814,9 @@ __global__ __launch_bounds__(kGradThreads) void k_grad_points(AtomArgs args, int
   __shared__ int is_last;
   __shared__ double part[kGradThreads];
   static_assert(kAtomArgs * 6 <= 64, "the sums must be written by the first wave");
-  __threadfence();
+  // only the first wave wrote partials, so only it releases them (a device-scope release
+  // writes back the L2; four per block cost more than the sums)
+  if (tid < 64) __threadfence();
   __syncthreads();
   if (tid == 0) is_last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
   __syncthreads();
@@ -1401,9 +1403,10 @@ ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz) {
 
 GradPlan plan_grad_box(sfw_dims vol, const int box[6]) {
   GradPlan p;
-  // deep tiles keep the block count, and with it the per-block release fences and the last
-  // block's sum, small; a point's atom spans most of the depth anyway
-  p.vpt = vol.nz >= 64 ? 64 : (vol.nz >= 32 ? 32 : 16);
+  // tiles 32 planes deep: shallower ones add blocks (each with its release fence and its
+  // partials for the last block to sum) faster than they shorten the per-thread chain, and
+  // 64 planes leave too few blocks for one point's box
+  p.vpt = vol.nz >= 32 ? 32 : 16;
   p.rx0 = box[0] / kTile;
   p.rtx = std::max(1, (box[1] + kTile - 1) / kTile - p.rx0);
   p.ry0 = box[2] / kTile;

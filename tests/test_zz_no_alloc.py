@@ -58,7 +58,7 @@ def test_noalloc_rejects_sizes_beyond_the_scratch(L):
     assert L.lib.sfw_eta_points_noalloc(*args(L.SFW_NOALLOC_MAX_POINTS + 1)) == L.SFW_EINVAL
     assert "SFW_NOALLOC_MAX_POINTS" in L.last_error()
     assert L.lib.sfw_eta_points_noalloc(*args(0)) == L.SFW_EINVAL
-    # a volume whose tiles need more partials than the scratch holds: one point per 16 x 16 x 64
+    # a volume whose tiles need more partials than the scratch holds: one point per 16 x 16 x 32
     # tile of a 4096 x 4096 x 64 volume with a very wide atom (no kernel is launched)
     wide = np.array([[2048, 2048, 32, 400.0, 1.2]], dtype=np.float32)
     assert L.lib.sfw_eta_points_noalloc(D(4096, 4096, 64), ctypes.c_void_p(q.data_ptr()), 1.0,
