@@ -1619,8 +1619,12 @@ hipError_t launch_conv_mfma(const float* in, const float* amat, sfw_dims psf, sf
 // the tap rows ky = wave, wave + nwaves, ... (nwaves = min(P_y, kBoxMaxWaves) waves per
 // block, so that a small box still gives the chip enough waves). For each tap (ky, kx) a lane
 // keeps the kBoxZ + PZ - 1 tile values of its column in registers and applies the PZ taps
-// along z, the same for the whole wave (scalar loads of H), to its kBoxZ outputs. The
-// partial sums of the waves meet in LDS and are added in wave order.
+// along z, the same for the whole wave, to its kBoxZ outputs. The PSF is staged in LDS beside
+// the tile, transposed so that a tap column's P_z values are a few float4 broadcasts (with
+// scalar loads of H instead, the waves of the one or two blocks a CU runs waited on a cold
+// scalar cache at every tap column); where it does not fit, H is read by scalar loads. The
+// tile is filled by (x, y) columns, so each thread takes its column's offsets once. The partial
+// sums of the waves meet in LDS and are added in wave order.
 constexpr int kBoxTX = 16, kBoxTY = 4, kBoxZ = 4, kBoxMaxWaves = 16;
 static_assert(kBoxTX * kBoxTY == 64, "one output column per lane");
 
@@ -1637,7 +1641,7 @@ struct BoxColumns {
   BoxColumn c[kBoxColumns];
 };
 
-template <int PZ>
+template <int PZ, bool HLDS>
 __global__ __launch_bounds__(64 * kBoxMaxWaves) void k_column_box(
     BoxColumns cols, int ncols, const float* __restrict__ H, int pxs, int pys, int nx, int ny,
     int nz) {
@@ -1659,8 +1663,8 @@ __global__ __launch_bounds__(64 * kBoxMaxWaves) void k_column_box(
     box_out[5] = bz1;
   }
   // tile [yy][xx][w] with the z window w innermost (WZP floats per column, 16-byte aligned),
-  // read as float4
-  constexpr int WZ = kBoxZ + PZ - 1, WZP = (WZ + 3) & ~3;
+  // read as float4; with HLDS, the PSF follows it as [ky][kx][kz] (PZP floats per tap column)
+  constexpr int WZ = kBoxZ + PZ - 1, WZP = (WZ + 3) & ~3, PZP = (PZ + 3) & ~3;
   extern __shared__ float4 lds4[];
   float* tile = reinterpret_cast<float*>(lds4);
   const int LX = kBoxTX + pxs - 1, LY = kBoxTY + pys - 1;
@@ -1669,28 +1673,47 @@ __global__ __launch_bounds__(64 * kBoxMaxWaves) void k_column_box(
   const int cx = (pxs - 1) / 2, cy = (pys - 1) / 2, cz = (PZ - 1) / 2;
   const int t = threadIdx.x;
   const int nwaves = (int)(blockDim.x >> 6);
-  const AtomK k = *atom;
-  // the tile, element e = (zz LY + yy) LX + xx, spread over all threads (several elements in
-  // flight per thread)
-  const int wave = t >> 6, lane = t & 63;
-  const int ntile = WZ * LY * LX, NT = (int)blockDim.x;
-#pragma unroll 4
-  for (int e = t; e < ntile; e += NT) {
-    const int xx = e % LX, r = e / LX;
-    const int yy = r % LY, zz = r / LY;
-    const int x = X0 - cx + xx, y = Y0 - cy + yy, z = Z0 - cz + zz;
-    float g = 0.f;
-    if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) {
-      const float dx = (float)x - k.mx, dy = (float)y - k.my, dz = (float)z - k.mz;
-      const float r2 = fmaf(dz, dz, fmaf(dx, dx, fmaf(dy, dy, kTinyR2)));
-      const float up = fast_exp2(fmaf(k.hd, fast_log2(r2), k.c));  // u * log2(e)
-      g = k.w * fast_exp2(-up);
+  const int NT = (int)blockDim.x;
+  const int ncol = LX * LY;
+  const int tile_floats = max(WZP * ncol, nwaves * kBoxZ * 64);
+  float* htile = tile + ((tile_floats + 3) & ~3);
+  if (HLDS) {  // the PSF, read once per block with consecutive threads on consecutive taps
+    const int plane = pxs * pys, ntap = plane * PZ;
+    for (int e = t; e < ntap; e += NT) {
+      const int kz = e / plane, r = e - kz * plane;
+      htile[r * PZP + kz] = H[e];
     }
-    tile[(yy * LX + xx) * WZP + zz] = g;
+  }
+  const AtomK k = *atom;
+  // the tile by (x, y) columns: G = NT / ncol thread groups (at least one) split the z window
+  {
+    const int G = max(1, NT / ncol), chunk = (WZ + G - 1) / G;
+    for (int c0 = t; c0 < ncol * G; c0 += NT) {
+      const int g = c0 / ncol, c = c0 - g * ncol;
+      const int xx = c % LX, yy = c / LX;
+      const int x = X0 - cx + xx, y = Y0 - cy + yy;
+      const bool inxy = x >= 0 && x < nx && y >= 0 && y < ny;
+      const float dx = (float)x - k.mx, dy = (float)y - k.my;
+      const float dxy2 = fmaf(dx, dx, fmaf(dy, dy, kTinyR2));
+      float* col = tile + c * WZP;
+      const int za = g * chunk, zb = min(WZ, za + chunk);
+      for (int zz = za; zz < zb; ++zz) {
+        const int z = Z0 - cz + zz;
+        float gv = 0.f;
+        if (inxy && z >= 0 && z < nz) {
+          const float dz = (float)z - k.mz;
+          const float r2 = fmaf(dz, dz, dxy2);
+          const float up = fast_exp2(fmaf(k.hd, fast_log2(r2), k.c));  // u * log2(e)
+          gv = k.w * fast_exp2(-up);
+        }
+        col[zz] = gv;
+      }
+    }
   }
   __syncthreads();
+  const int lane = t & 63;
   const int xl = lane % kBoxTX, yl = lane / kBoxTX;
-  const int part = __builtin_amdgcn_readfirstlane(wave);
+  const int part = __builtin_amdgcn_readfirstlane(t >> 6);
   const int hstride = pys * pxs;  // H is [kz][ky][kx]
   float acc[kBoxZ];
 #pragma unroll
@@ -1701,8 +1724,7 @@ __global__ __launch_bounds__(64 * kBoxMaxWaves) void k_column_box(
     for (int kx = 0; kx < pxs; ++kx) {
       const int xx = xl + pxs - 1 - kx;
       const float4* tv = reinterpret_cast<const float4*>(tile + (yy * LX + xx) * WZP);
-      const float* hp = H + ky * pxs + kx;
-      float v[WZP], h[PZ];
+      float v[WZP], h[PZP];
 #pragma unroll
       for (int q = 0; q < WZP / 4; ++q) {
         const float4 f = tv[q];
@@ -1711,8 +1733,21 @@ __global__ __launch_bounds__(64 * kBoxMaxWaves) void k_column_box(
         v[4 * q + 2] = f.z;
         v[4 * q + 3] = f.w;
       }
+      if (HLDS) {
+        const float4* hv = reinterpret_cast<const float4*>(htile + (ky * pxs + kx) * PZP);
 #pragma unroll
-      for (int kz = 0; kz < PZ; ++kz) h[kz] = hp[kz * hstride];
+        for (int q = 0; q < PZP / 4; ++q) {
+          const float4 f = hv[q];
+          h[4 * q] = f.x;
+          h[4 * q + 1] = f.y;
+          h[4 * q + 2] = f.z;
+          h[4 * q + 3] = f.w;
+        }
+      } else {
+        const float* hp = H + ky * pxs + kx;
+#pragma unroll
+        for (int kz = 0; kz < PZ; ++kz) h[kz] = hp[kz * hstride];
+      }
 #pragma unroll
       for (int kz = 0; kz < PZ; ++kz) {
 #pragma unroll
@@ -1748,6 +1783,13 @@ static size_t column_box_lds(sfw_dims psf) {
   return tile * sizeof(float);
 }
 
+// LDS with the PSF staged beside the tile ([ky][kx][kz], P_z padded to 4)
+static size_t column_box_lds_h(sfw_dims psf) {
+  const size_t tile = (column_box_lds(psf) / sizeof(float) + 3) & ~(size_t)3;
+  const size_t h = (size_t)psf.nx * psf.ny * ((psf.nz + 3) & ~3);
+  return (tile + h) * sizeof(float);
+}
+
 bool column_box_ok(sfw_dims psf) {
   // tile rows of at most one wave of x, P_z a supported template, the LDS of one CU
   return kBoxTX + psf.nx - 1 <= 64 && psf.nz <= 33 &&
@@ -1772,16 +1814,25 @@ hipError_t launch_column_boxes(const ColumnBoxJob* jobs, int n, const float* H, 
   }
   if (nc == 0) return hipSuccess;
   const dim3 grid(blocks);
-  const size_t lds = column_box_lds(psf);
+  const bool hlds = column_box_lds_h(psf) <= (size_t)kColumnBoxMaxLds;
+  const size_t lds = hlds ? column_box_lds_h(psf) : column_box_lds(psf);
   switch (psf.nz) {
 #define SFW_BOX_CASE(P)                                                                        \
   case P: {                                                                                    \
     static const hipError_t attr = hipFuncSetAttribute(                                        \
-        reinterpret_cast<const void*>(&k_column_box<P>),                                       \
+        reinterpret_cast<const void*>(&k_column_box<P, true>),                                 \
+        hipFuncAttributeMaxDynamicSharedMemorySize, kColumnBoxMaxLds);                         \
+    static const hipError_t attr2 = hipFuncSetAttribute(                                       \
+        reinterpret_cast<const void*>(&k_column_box<P, false>),                                \
         hipFuncAttributeMaxDynamicSharedMemorySize, kColumnBoxMaxLds);                         \
     if (attr != hipSuccess) return attr;                                                       \
-    hipLaunchKernelGGL(k_column_box<P>, grid, dim3(64 * column_box_waves(psf)), lds, st, bc,   \
-                       nc, H, psf.nx, psf.ny, vol.nx, vol.ny, vol.nz);                         \
+    if (attr2 != hipSuccess) return attr2;                                                     \
+    if (hlds)                                                                                  \
+      hipLaunchKernelGGL((k_column_box<P, true>), grid, dim3(64 * column_box_waves(psf)), lds, \
+                         st, bc, nc, H, psf.nx, psf.ny, vol.nx, vol.ny, vol.nz);               \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_column_box<P, false>), grid, dim3(64 * column_box_waves(psf)),     \
+                         lds, st, bc, nc, H, psf.nx, psf.ny, vol.nx, vol.ny, vol.nz);          \
     return hipGetLastError();                                                                  \
   }
     SFW_BOX_CASE(1) SFW_BOX_CASE(3) SFW_BOX_CASE(5) SFW_BOX_CASE(7) SFW_BOX_CASE(9)
