@@ -585,9 +585,9 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
       SFW_HIP(fft_forward_volume(pl, q, vol, ws->fft_qhat, ws->stream));
     }
     {
-      ProfScope ps(ws, kProfCertZinv);
+      ProfScope ps(ws, kProfCertZinv, true);  // timed by the kernel's own events
       SFW_HIP(fft_inverse_pairs_z(pl, ws->fft_qhat, ws->fft_pairs, ws->fft_work, ws->fft_cap,
-                                  ns * nd, vol, ws->stream));
+                                  ns * nd, vol, ws->stream, ps.start(), ps.stop()));
     }
     {
       ProfScope ps(ws, kProfCertFft);

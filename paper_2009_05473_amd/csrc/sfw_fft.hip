@@ -603,17 +603,23 @@ hipError_t fft_pack_octant(const FftPlan& pl, const float2* full, float2* oct, h
 // elements), with the block maxima of every slice: the z pass here, then y and x below.
 hipError_t fft_inverse_pairs_z(const FftPlan& pl, const float2* qhat, const float2* pairs,
                                float2* work, size_t bstride, int nslices, sfw_dims vol,
-                               hipStream_t st) {
+                               hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const unsigned np = (unsigned)((nslices + 1) / 2);
   if (pl.ax[2].r1 > 0)
     return fx_z_inverse(pl.nz, st, qhat, pairs, pl.oct, pl.hx, pl.hy, work, bstride,
-                        pl.ax[2].tw, pl.nx, pl.ny, pl.px, vol.nz, (int)np);
+                        pl.ax[2].tw, pl.nx, pl.ny, pl.px, vol.nz, (int)np, ev0, ev1);
+  if (ev0) {
+    const hipError_t e = hipEventRecord(ev0, st);
+    if (e != hipSuccess) return e;
+  }
   const int g = fft_lg_lines(pl.nz, true), B = 1 << g;
   hipLaunchKernelGGL(k_fft_strided<true>, dim3((pl.nx + B - 1) / B, pl.ny, np),
                      dim3(kFftThreads), fft_lds(pl.nz, g), st, qhat, (size_t)0, pairs, pl.oct,
                      work, bstride, pl.ax[2], pl.nx, (size_t)pl.px * pl.ny, (size_t)pl.px,
                      pl.nz, vol.nz, g, pl.hx, pl.hy, pl.ny);
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !ev1) return e;
+  return hipEventRecord(ev1, st);
 }
 
 hipError_t fft_inverse_pairs_yx(const FftPlan& pl, float2* work, size_t bstride, int nslices,

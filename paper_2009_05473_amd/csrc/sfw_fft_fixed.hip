@@ -7,6 +7,7 @@
 // maximum). With L, R1 and R2 known at compile time, every index and LDS offset folds, so
 // the passes cost little beyond the butterflies themselves. Lengths without a two-stage plan
 // use the generic runtime-length passes.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -380,15 +381,17 @@ hipError_t fx_strided(int L, dim3 grid, hipStream_t st, const float2* src, size_
 
 hipError_t fx_z_inverse(int L, hipStream_t st, const float2* qhat, const float2* oct,
                         size_t oct_b, int hx, int hy, float2* work, size_t work_b,
-                        const float2* tw, int Nx, int Ny, int px, int n_out, int npairs) {
+                        const float2* tw, int Nx, int Ny, int px, int n_out, int npairs,
+                        hipEvent_t ev0, hipEvent_t ev1) {
   const int gx = (Nx + kFxLines - 1) / kFxLines;
   const int chunk = (gx * Ny + 7) / 8;  // blocks per XCD
   const dim3 grid(8 * chunk);
   switch (L) {
 #define SFW_FX_CASE(n, a, b)                                                                  \
   case n:                                                                                     \
-    hipLaunchKernelGGL((k_fx_z_inverse<a, b>), grid, dim3(fx_threads(a, b)), 0, st, qhat, oct, \
-                       oct_b, hx, hy, work, work_b, tw, Nx, Ny, px, n_out, npairs, gx, chunk);\
+    hipExtLaunchKernelGGL((k_fx_z_inverse<a, b>), grid, dim3(fx_threads(a, b)), 0, st, ev0,   \
+                          ev1, 0, qhat, oct, oct_b, hx, hy, work, work_b, tw, Nx, Ny, px,      \
+                          n_out, npairs, gx, chunk);                                           \
     return hipGetLastError();
     SFW_FX_LENGTHS(SFW_FX_CASE)
 #undef SFW_FX_CASE

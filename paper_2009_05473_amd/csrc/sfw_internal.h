@@ -300,7 +300,12 @@ namespace sfw {
 struct ProfScope {
   sfw_workspace* ws;
   int slot = -1;
-  ProfScope(sfw_workspace* w, int kind) : ws(w) {
+  bool at_kernel = false;
+  // at_kernel: the scope covers one kernel launched with start() and stop() as its own
+  // start and stop events (hipExtLaunchKernelGGL), which time the kernel itself, without the
+  // dispatch latency that an event pair recorded around the launch also holds; the launch
+  // (or its caller) must record both
+  ProfScope(sfw_workspace* w, int kind, bool kernel_events = false) : ws(w) {
     if (!ws->prof_on || !((ws->prof_mask >> kind) & 1u)) return;
     if (ws->prof_used >= (int)ws->prof_start.size()) {
       ws->prof_overflow = true;
@@ -308,10 +313,13 @@ struct ProfScope {
     }
     slot = ws->prof_used++;
     ws->prof_kind[slot] = kind;
-    (void)hipEventRecord(ws->prof_start[slot], ws->stream);
+    at_kernel = kernel_events;
+    if (!at_kernel) (void)hipEventRecord(ws->prof_start[slot], ws->stream);
   }
+  hipEvent_t start() const { return slot >= 0 && at_kernel ? ws->prof_start[slot] : nullptr; }
+  hipEvent_t stop() const { return slot >= 0 && at_kernel ? ws->prof_stop[slot] : nullptr; }
   ~ProfScope() {
-    if (slot >= 0) (void)hipEventRecord(ws->prof_stop[slot], ws->stream);
+    if (slot >= 0 && !at_kernel) (void)hipEventRecord(ws->prof_stop[slot], ws->stream);
   }
 };
 }  // namespace sfw
@@ -517,9 +525,11 @@ hipError_t launch_blur_adjoint_chain(const BlurPlan& bp, const sfw_dims& vol, co
 hipError_t fx_strided(int L, dim3 grid, hipStream_t st, const float2* src, size_t src_b,
                       float2* dst, size_t dst_b, const float2* tw, int ncols, size_t istride,
                       size_t ostride, int n_in, int n_out);
+// ev0, ev1 (optional): the kernel's own start and stop events
 hipError_t fx_z_inverse(int L, hipStream_t st, const float2* qhat, const float2* oct,
                         size_t oct_b, int hx, int hy, float2* work, size_t work_b,
-                        const float2* tw, int Nx, int Ny, int px, int n_out, int npairs);
+                        const float2* tw, int Nx, int Ny, int px, int n_out, int npairs,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t fx_x_real(int L, dim3 grid, hipStream_t st, const float* q, int nx, int ny,
                      const float2* tw, int Ny, int px, float2* out);
 hipError_t fx_x_argmax(int L, dim3 grid, hipStream_t st, const float2* work, size_t work_b,
@@ -528,9 +538,12 @@ hipError_t fx_x_argmax(int L, dim3 grid, hipStream_t st, const float2* work, siz
 hipError_t fft_pack_octant(const FftPlan& pl, const float2* full, float2* oct, hipStream_t st);
 // The inverse side of the certificate in two launch groups: the z pass of every pair
 // (fft_inverse_pairs_z) and the y and x passes with the block maxima (fft_inverse_pairs_yx).
+// ev0, ev1 (optional): recorded at the start and the end of the z pass (the one kernel's own
+// events on the fixed-length path, an event pair around the launch otherwise).
 hipError_t fft_inverse_pairs_z(const FftPlan& pl, const float2* qhat, const float2* pairs,
                                float2* work, size_t bstride, int nslices, sfw_dims vol,
-                               hipStream_t st);
+                               hipStream_t st, hipEvent_t ev0 = nullptr,
+                               hipEvent_t ev1 = nullptr);
 hipError_t fft_inverse_pairs_yx(const FftPlan& pl, float2* work, size_t bstride, int nslices,
                                 sfw_dims vol, float scale, float* eta_out, ArgPart* apart,
                                 int nblk, hipStream_t st);
