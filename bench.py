@@ -571,6 +571,18 @@ def main():
     dt = t1 - t0
     ms_per_step = dt / args.steps * 1e3
     value = V * N * args.steps / dt / 1e9
+    # untimed: the (C, grad C) chain back to back, one event pair around 20 calls on the
+    # workspace's stream (torch's current one): its latency with the launch gaps, without the
+    # device idle that an event pair around every kernel class adds
+    chain_reps = 20
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    c0.record()
+    for _ in range(chain_reps):
+        L.sfw_residual_grad(ws, H, Y, lam, A, r_out=R, loss_out=loss_buf, grad_out=grad_buf)
+    c1.record()
+    torch.cuda.synchronize()
+    chain_b2b_us = c0.elapsed_time(c1) * 1e3 / chain_reps
 
     # algorithmic work per launch of each kernel class: HBM bytes that the operation must move
     # (its inputs and outputs, not the implementation's intermediate arrays) and ALU slots of
@@ -628,11 +640,14 @@ def main():
         breakdown["fwd_grad_GVoxel_atom_per_s"] = V * N / (fwd_grad_ms * 1e-3) / 1e9
         breakdown["fwd_grad_chain"] = {
             "us": fwd_grad_ms * 1e3, "roofline_us": roof_us, "frac": roof_us / (fwd_grad_ms * 1e3),
+            "us_back_to_back": chain_b2b_us, "frac_back_to_back": roof_us / chain_b2b_us,
+            "GVoxel_atom_per_s_back_to_back": V * N / (chain_b2b_us * 1e-6) / 1e9,
             "evaluated_pairs_render": pairs_render, "evaluated_pairs_grad": pairs_grad,
             "nominal_pairs": V * N,
             "definition": "sum over the chain's kernel classes of max(algorithmic HBM bytes / "
                           "8 TB/s, ALU slots of evaluated voxel-atom pairs / 78.6 T slots/s), "
-                          "over the measured chain time"}
+                          "over the measured chain time: us = the classes' event-timed sums, "
+                          "us_back_to_back = 20 chains between one event pair"}
 
     # roofline of the dominant kernel, timed live over the timed region
     launches, ms = roof_prof[ROOF_CLASS]
