@@ -558,7 +558,7 @@ def main():
         for k in range(args.profile_steps):
             step(args.warmup + k)
         prof = L.sfw_profile_end(ws)
-    # timed: only the roofline kernel's launches carry events (one pair per step)
+    # timed: only the roofline kernel carries events (its own start and stop, one launch a step)
     k0 = args.warmup + args.profile_steps
     torch.cuda.synchronize()
     L.sfw_profile_begin(ws, [ROOF_CLASS])

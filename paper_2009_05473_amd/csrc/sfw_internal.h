@@ -346,7 +346,7 @@ int sig_wait(sfw_workspace* ws, const SigArgs& s);
 
 // ---- launchers (sfw_kernels.hip); each returns a hipError_t from the launch
 ConvPlan plan_conv(sfw_dims vol, int px, int py, int pz);
-// Points-kernel tiles (16 x 16 columns, 16 to 64 planes deep) that meet box
+// Points-kernel tiles (16 x 16 columns, 32 planes deep, 16 in volumes under 32 planes) that meet box
 // {x0, x1, y0, y1, z0, z1} (voxels, half-open).
 GradPlan plan_grad_box(sfw_dims vol, const int box[6]);
 

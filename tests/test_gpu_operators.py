@@ -412,7 +412,7 @@ def test_certificate_argmax_only_matches_grid(L, ws_big, cert_path):
 @pytest.mark.parametrize("name,npts", [("c1", 1), ("c1", 6), ("c1", 8), ("c1", 11),
                                        ("c3", 1), ("c3", 8), ("c3", 11)])
 def test_eta_points_parity(L, ws_big, name, npts):
-    """Up to 8 points take the one-launch path (atoms as kernel arguments, 16 to 64 planes deep
+    """Up to 8 points take the one-launch path (atoms as kernel arguments, 16 or 32 planes deep
     tiles, sums reduced by the last block into host memory); more take the staged path. At
     128 x 128 x 64 the points sit within 3 voxels of true atoms anywhere in the volume (where
     eta is well above the noise)."""
