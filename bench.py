@@ -571,18 +571,20 @@ def main():
     dt = t1 - t0
     ms_per_step = dt / args.steps * 1e3
     value = V * N * args.steps / dt / 1e9
-    # untimed: the (C, grad C) chain back to back, one event pair around 20 calls on the
-    # workspace's stream (torch's current one): its latency with the launch gaps, without the
-    # device idle that an event pair around every kernel class adds
-    chain_reps = 20
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    c0.record()
-    for _ in range(chain_reps):
-        L.sfw_residual_grad(ws, H, Y, lam, A, r_out=R, loss_out=loss_buf, grad_out=grad_buf)
-    c1.record()
-    torch.cuda.synchronize()
-    chain_b2b_us = c0.elapsed_time(c1) * 1e3 / chain_reps
+    # untimed, with the breakdown: the (C, grad C) chain back to back, one event pair around 20
+    # calls on the workspace's stream (torch's current one): its latency with the launch gaps,
+    # without the device idle that an event pair around every kernel class adds
+    chain_b2b_us = None
+    if args.profile_steps > 0:
+        chain_reps = 20
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        c0.record()
+        for _ in range(chain_reps):
+            L.sfw_residual_grad(ws, H, Y, lam, A, r_out=R, loss_out=loss_buf, grad_out=grad_buf)
+        c1.record()
+        torch.cuda.synchronize()
+        chain_b2b_us = c0.elapsed_time(c1) * 1e3 / chain_reps
 
     # algorithmic work per launch of each kernel class: HBM bytes that the operation must move
     # (its inputs and outputs, not the implementation's intermediate arrays) and ALU slots of

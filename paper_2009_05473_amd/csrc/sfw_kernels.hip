@@ -1090,10 +1090,12 @@ __global__ __launch_bounds__(1024) void k_argmax_final(const ArgPart* __restrict
   const int tid = threadIdx.x;
   float bv = -INFINITY;
   long long bi = 0x7fffffffffffffffLL;
-  for (int i0 = tid; i0 < nparts; i0 += 4 * 1024) {
-    ArgPart ap[4];
+  // eight partials in flight per thread: the 128 x 128 x 64 certificate's 6,144 in one round
+  // (ties go to the lower index, so the order of the comparisons changes no result)
+  for (int i0 = tid; i0 < nparts; i0 += 8 * 1024) {
+    ArgPart ap[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int i = i0 + u * 1024;
       if (i < nparts) {
         ap[u] = apart[i];
@@ -1103,7 +1105,7 @@ __global__ __launch_bounds__(1024) void k_argmax_final(const ArgPart* __restrict
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
       if (arg_better(ap[u].val, ap[u].idx, bv, bi)) {
         bv = ap[u].val;
         bi = ap[u].idx;
