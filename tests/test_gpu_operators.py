@@ -563,6 +563,32 @@ def test_lasso_support_longer_than_inline_slot_list(L):
     assert np.all(np.abs(grad[got > 0]) <= 1e-4 * np.abs(b).max())
 
 
+@pytest.mark.parametrize("psf_shape", [(9, 9, 9), (33, 21, 21)])
+def test_lasso_column_psf_in_lds_or_not(L, psf_shape):
+    """The LASSO column kernel stages the PSF in LDS beside its tile where both fit (9 x 9 x 9)
+    and reads it by scalar loads where they do not (21 x 21 x 33: 124 KB of tile, 188 KB with
+    the PSF); both against the oracle's weights."""
+    shape = (40, 48, 48)
+    rng = np.random.default_rng(7200 + psf_shape[0])
+    psf = f32(synth.gaussian_psf(1.5, 3.0, psf_shape))
+    centres = np.array([[12, 12, 10], [34, 14, 28], [14, 35, 20], [33, 33, 12], [24, 24, 30],
+                        [8, 26, 22]], dtype=np.float64)
+    k = len(centres)
+    thetas = f32(np.hstack([centres + rng.uniform(-0.4, 0.4, centres.shape),
+                            rng.uniform(1.1, 1.6, (k, 1)), rng.uniform(1.6, 2.4, (k, 1))]))
+    truth = np.hstack([rng.uniform(0.5, 2.0, (k, 1)), thetas])
+    y = f32(oracle.blur(oracle.render(shape, truth), psf) + 0.01 * rng.standard_normal(shape))
+    lam = 0.02
+    atoms = np.hstack([np.zeros((k, 1)), thetas])
+    w_o, G, b = oracle.lasso_weights(y, thetas, psf, lam)
+    say("sfw_lasso_weights PSF", psf_shape)
+    with L.Workspace(shape, psf_shape, 8) as w:
+        got = L.sfw_lasso_weights(w, dev(psf), dev(y), lam, dev(atoms)).cpu().numpy()
+    assert rel_l2(got, w_o) <= 1e-4
+    grad = G @ got - b + lam
+    assert np.all(np.abs(grad[got > 0]) <= 1e-4 * np.abs(b).max())
+
+
 def test_reductions_are_deterministic(L, ws_big):
     prob, atoms, psf, y = _problem("c3")
     say("determinism c3")
