@@ -334,6 +334,36 @@ def cert_path(request, monkeypatch):
     return request.param
 
 
+@pytest.mark.parametrize("fft", ["fixed", "generic"])
+def test_profile_times_the_certificate_z_pass(L, fft, monkeypatch):
+    """The cert_zinv class is timed by the z pass kernel's own start and stop events on the
+    fixed-length path (128 x 128 x 64: lengths 150 x 150 x 81) and by an event pair around the
+    launch on the runtime-length path: one launch per certificate either way, a positive time,
+    and the same maximum."""
+    monkeypatch.delenv("SFW_CERT", raising=False)
+    if fft == "generic":
+        monkeypatch.setenv("SFW_FFT", "generic")
+    else:
+        monkeypatch.delenv("SFW_FFT", raising=False)
+    prob, atoms, psf, y = _problem("c3")
+    sg = [float(np.float32(v)) for v in prob.config.sigma_grid]
+    dg = list(prob.config.d_grid)
+    say("profiled certificate", fft)
+    with L.Workspace(prob.shape, psf.shape, 8) as w:
+        Hd, Yd = dev(psf), dev(y)
+        _, best0 = L.sfw_certificate(w, Hd, Yd, 0.9, sg, dg)
+        torch.cuda.synchronize()
+        L.sfw_profile_begin(w, ["cert_zinv", "cert_fft"])
+        for _ in range(3):
+            _, best = L.sfw_certificate(w, Hd, Yd, 0.9, sg, dg)
+        torch.cuda.synchronize()
+        prof = L.sfw_profile_end(w)
+    n, ms = prof["cert_zinv"]
+    assert n == 3 and 0.0 < ms / n < 10.0
+    assert prof["cert_fft"][0] == 6  # the forward transform and the inverse y, x passes
+    assert best == best0
+
+
 @pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_certificate_parity(L, ws_big, name, cert_path):
     prob, atoms, psf, y = _problem(name)
