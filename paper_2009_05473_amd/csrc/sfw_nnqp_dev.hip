@@ -6,10 +6,12 @@
 // The method is the host solver's active-set method: shrink the full set until the solution on
 // it is positive, then Lawson-Hanson steps from that feasible point, each solving G_PP z_P = c_P
 // on the passive set P by a Cholesky factor (with the same two ridge retries for a singular
-// G_PP). The s x s factor lives in LDS (row stride kmax + 1 doubles, so a column walk does not
-// hit one bank); G stays in global memory, read through the caches. Every decision (which
+// G_PP). G's upper triangle is staged once into LDS and the factor of G_PP is built beside it,
+// both packed by rows, so that both fit up to SFW_NNQP_MAX_K atoms. Every decision (which
 // coordinate to free, the step back to feasibility, which coordinates leave P) is taken from
-// values in LDS after a barrier, so the 256 threads follow one control flow.
+// values in LDS after a barrier, so the 256 threads follow one control flow. A single problem
+// is latency bound (each factor row is a chain of barriers, a square root and a divide); the
+// kernel is for batches.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
