@@ -1,7 +1,7 @@
 // The weights step's non-negative quadratic program on the device (algorithm 1 step 3,
 // algorithm 2 step 3: the criterion of section 1.1 restricted to the weights): minimise
-// 1/2 w'Gw - c'w over w >= 0 for many independent problems in one launch, one workgroup of
-// 256 threads per problem, in float64.
+// 1/2 w'Gw - c'w over w >= 0 for many independent problems in one launch, one workgroup per
+// problem (one wave for small problems in large batches, four waves otherwise), in float64.
 //
 // The method is the host solver's active-set method: shrink the full set until the solution on
 // it is positive, then Lawson-Hanson steps from that feasible point, each solving G_PP z_P = c_P
@@ -9,7 +9,7 @@
 // G_PP). G's upper triangle is staged once into LDS and the factor of G_PP is built beside it,
 // both packed by rows, so that both fit up to SFW_NNQP_MAX_K atoms. Every decision (which
 // coordinate to free, the step back to feasibility, which coordinates leave P) is taken from
-// values in LDS after a barrier, so the 256 threads follow one control flow. A single problem
+// values in LDS after a barrier, so the block's threads follow one control flow. A single problem
 // is latency bound (each factor row is a chain of barriers, a square root and a divide); the
 // kernel is for batches.
 #include <hip/hip_runtime.h>
@@ -26,8 +26,9 @@ int hip_fail(hipError_t e, const char* what);
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
+// NT threads per problem: 256 (four waves) in general, 64 (one wave, so the barriers cost next
+// to nothing) for small problems in large batches; the one-wave kernel needs k <= 64.
+constexpr int kMaxWaves = 4;
 constexpr int kLoadBatch = 16;  // loads of G in flight per thread while it is staged
 
 // Start of row a in the packed upper triangle of an m x m matrix (row a holds columns a..m-1).
@@ -40,9 +41,9 @@ __device__ inline int tri(int a, int m) { return a * (2 * m - a + 1) / 2; }
 struct Lds {
   double *Gp, *Up;
   double *w, *z, *c, *invd, *part;
-  double* redv;               // [kWaves]
-  unsigned long long* mask;   // [kWaves]
-  int* redi;                  // [kWaves]
+  double* redv;               // [kMaxWaves]
+  unsigned long long* mask;   // [kMaxWaves]
+  int* redi;                  // [kMaxWaves]
   int* P;
   int* passive;
   int kmax;
@@ -61,19 +62,19 @@ __device__ inline Lds carve(unsigned char* base, int kmax) {
   s.c = d + 2 * kmax;
   s.invd = d + 3 * kmax;
   s.part = d + 4 * kmax;
-  s.redv = d + (4 + kWaves) * kmax;
-  s.mask = reinterpret_cast<unsigned long long*>(s.redv + kWaves);
-  int* i = reinterpret_cast<int*>(s.mask + kWaves);
+  s.redv = d + (4 + kMaxWaves) * kmax;
+  s.mask = reinterpret_cast<unsigned long long*>(s.redv + kMaxWaves);
+  int* i = reinterpret_cast<int*>(s.mask + kMaxWaves);
   s.redi = i;
-  s.P = i + kWaves;
+  s.P = i + kMaxWaves;
   s.passive = s.P + kmax;
   return s;
 }
 
 size_t lds_bytes(int kmax) {
   const size_t T = (size_t)kmax * (kmax + 1) / 2;
-  return sizeof(double) * (2 * T + (4 + kWaves) * (size_t)kmax + 2 * kWaves) +
-         sizeof(int) * (kWaves + 2 * (size_t)kmax);
+  return sizeof(double) * (2 * T + (4 + kMaxWaves) * (size_t)kmax + 2 * kMaxWaves) +
+         sizeof(int) * (kMaxWaves + 2 * (size_t)kmax);
 }
 
 // Lane l's value of a double, on every lane (l uniform).
@@ -86,7 +87,9 @@ __device__ inline double readlane(double v, int l) {
 
 // Smallest value over the block with its index (ties: the smaller index; NaN never wins).
 // Every thread gets the result.
+template <int NT>
 __device__ void block_argmin(const Lds& s, double v, int idx, double* vout, int* iout) {
+  constexpr int kWaves = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (!(v == v)) {
     v = INFINITY;
@@ -117,9 +120,11 @@ __device__ void block_argmin(const Lds& s, double v, int idx, double* vout, int*
   *iout = bi;
 }
 
-// P = the passive coordinates in increasing order (thread i < k owns flag i: k <= 128 < 256);
-// returns |P| to every thread.
+// P = the passive coordinates in increasing order (thread i < k owns flag i: k <= NT); returns
+// |P| to every thread.
+template <int NT>
 __device__ int build_passive(const Lds& s, int k) {
+  constexpr int kWaves = NT / 64;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const bool on = t < k && s.passive[t];
   const unsigned long long m = __ballot(on);
@@ -141,33 +146,36 @@ __device__ int build_passive(const Lds& s, int k) {
 // Wave q sums the terms k = q, q + 4, ... of every column; the four sums are added after a
 // barrier. Row i overwrites A's row i except the pivot, whose reciprocal goes to invd.
 // False (on every thread) if a pivot is not positive.
+template <int NT>
 __device__ bool cholesky(const Lds& s, int n) {
+  constexpr int kWaves = NT / 64;
   const int t = threadIdx.x, lane = t & 63, q = t >> 6, km = s.kmax;
+  // the waves' sums of column jj, added in a fixed order
+  auto wave_sums = [&](int jj) {
+    if (kWaves == 4) return (s.part[jj] + s.part[km + jj]) + (s.part[2 * km + jj] + s.part[3 * km + jj]);
+    return s.part[jj];
+  };
   double* U = s.Up;
   for (int i = 0; i < n; ++i) {
     const int oi = tri(i, n) - i;  // U_ij at oi + j
     for (int jj = lane; jj < n - i; jj += 64) {
       const int j = i + jj;
       double acc = 0.0;
-      // U_kx at ok + x with ok = k (2n - k - 1) / 2, which grows by 4n - 4k - 10 from k to k + 4
-      int ok = q * (2 * n - q - 1) / 2, dk = 4 * n - 4 * q - 10;
+      // U_kx at ok + x with ok = k (2n - k - 1) / 2, which grows by W (2n - 2k - W - 1) / 2
+      // from k to k + W (W = kWaves), that step shrinking by W^2 each time
+      int ok = q * (2 * n - q - 1) / 2, dk = kWaves * (2 * n - 2 * q - kWaves - 1) / 2;
       for (int k = q; k < i; k += kWaves) {
         acc += U[ok + i] * U[ok + j];
         ok += dk;
-        dk -= 16;
+        dk -= kWaves * kWaves;
       }
       s.part[q * km + jj] = acc;
     }
     __syncthreads();
-    const double d =
-        U[oi + i] - ((s.part[0] + s.part[km]) + (s.part[2 * km] + s.part[3 * km]));
+    const double d = U[oi + i] - wave_sums(0);
     if (!(d > 0.0)) return false;
     const double inv = 1.0 / sqrt(d);
-    for (int jj = t + 1; jj < n - i; jj += kThreads) {
-      const double sum =
-          (s.part[jj] + s.part[km + jj]) + (s.part[2 * km + jj] + s.part[3 * km + jj]);
-      U[oi + i + jj] = (U[oi + i + jj] - sum) * inv;
-    }
+    for (int jj = t + 1; jj < n - i; jj += NT) U[oi + i + jj] = (U[oi + i + jj] - wave_sums(jj)) * inv;
     if (t == 0) s.invd[i] = inv;
     __syncthreads();
   }
@@ -176,9 +184,11 @@ __device__ bool cholesky(const Lds& s, int n) {
 
 // z_P = G_PP^{-1} c_P and z = 0 off P, with the ridges 1e-12 and 1e-6 times the mean diagonal
 // added when G_PP is not positive definite (duplicate atoms make it singular).
+template <int NT>
 __device__ void solve_passive(const Lds& s, int k, int n) {
+  constexpr int kWaves = NT / 64;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int i = t; i < k; i += kThreads) s.z[i] = 0.0;
+  for (int i = t; i < k; i += NT) s.z[i] = 0.0;
   for (int r = 0; r < 3; ++r) {
     double ridge = 0.0;
     if (r > 0) {  // mean diagonal of G_PP (only once a factorisation has failed)
@@ -192,7 +202,7 @@ __device__ void solve_passive(const Lds& s, int k, int n) {
         s.Up[oa + b] = s.Gp[ga + s.P[b]] + (b == a ? ridge : 0.0);
     }
     __syncthreads();
-    if (cholesky(s, n)) break;
+    if (cholesky<NT>(s, n)) break;
     __syncthreads();
   }
   // U' t = c_P, then U x = t, by wave 0 alone: lane l holds unknowns l and l + 64 in registers and
@@ -232,7 +242,8 @@ __device__ void solve_passive(const Lds& s, int k, int n) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Gall,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_nnqp(const double* __restrict__ Gall,
                                                    const double* __restrict__ Call,
                                                    const int* __restrict__ ks, int kmax,
                                                    double* __restrict__ Wall,
@@ -244,20 +255,20 @@ __global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Ga
   const double* G = Gall + (size_t)p * kmax * kmax;
   double* W = Wall + (size_t)p * kmax;
   // stage G's upper triangle, kLoadBatch loads in flight per thread
-  for (int base = 0; base < k * k; base += kThreads * kLoadBatch) {
+  for (int base = 0; base < k * k; base += NT * kLoadBatch) {
     double v[kLoadBatch];
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = base + u * kThreads + t, a = e / k, b = e - a * k;
+      const int e = base + u * NT + t, a = e / k, b = e - a * k;
       v[u] = e < k * k && b >= a ? G[(size_t)a * kmax + b] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = base + u * kThreads + t, a = e / k, b = e - a * k;
+      const int e = base + u * NT + t, a = e / k, b = e - a * k;
       if (e < k * k && b >= a) s.Gp[tri(a, k) + b - a] = v[u];
     }
   }
-  for (int i = t; i < kmax; i += kThreads) {
+  for (int i = t; i < kmax; i += NT) {
     s.w[i] = 0.0;
     s.passive[i] = i < k;
     s.c[i] = i < k ? Call[(size_t)p * kmax + i] : 0.0;
@@ -269,13 +280,13 @@ __global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Ga
   // solution on what remains is positive (a feasible point; with nothing dropped, the KKT
   // point of the strictly convex problem).
   for (int round = 0; round < k; ++round) {
-    const int n = build_passive(s, k);
+    const int n = build_passive<NT>(s, k);
     nP = n;
     if (n == 0) break;
-    solve_passive(s, k, n);
+    solve_passive<NT>(s, k, n);
     ++solves;
     int bad = 0;
-    for (int q = t; q < n; q += kThreads) {
+    for (int q = t; q < n; q += NT) {
       const int i = s.P[q];
       if (!(s.z[i] > 0.0)) {
         s.passive[i] = 0;
@@ -283,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Ga
       }
     }
     if (!__syncthreads_or(bad)) {
-      for (int i = t; i < k; i += kThreads) s.w[i] = s.z[i];
+      for (int i = t; i < k; i += NT) s.w[i] = s.z[i];
       __syncthreads();
       break;
     }
@@ -297,12 +308,15 @@ __global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Ga
   int outer = 0;
   for (; outer < cap; ++outer) {
     // gradient G w - c off P: w vanishes off the last passive set, so the sum runs over it;
-    // threads i and i + 128 take its two halves for coordinate i (k <= 128)
+    // with 256 threads, threads i and i + 128 take its two halves for coordinate i (k <= 128),
+    // with 64, thread i takes all of it (k <= 64)
+    constexpr int CH = NT >= 256 ? 128 : NT, HALVES = NT / CH;
     {
-      const int i = t & 127, h = t >> 7, mid = nP / 2;
+      const int i = t % CH, h = t / CH, mid = nP / 2;
       if (i < k && !s.passive[i]) {
         double acc = 0.0;
-        for (int q = h ? mid : 0; q < (h ? nP : mid); ++q) {
+        const int q0 = HALVES == 2 && h ? mid : 0, q1 = HALVES == 2 && !h ? mid : nP;
+        for (int q = q0; q < q1; ++q) {
           const int j = s.P[q], a = min(i, j), b = max(i, j);
           acc += s.Gp[tri(a, k) + b - a] * s.w[j];
         }
@@ -313,7 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Ga
     double g = INFINITY;
     int gi = 0x7fffffff;
     if (t < k && !s.passive[t]) {
-      const double acc = (s.part[t] + s.part[kmax + t]) - s.c[t];
+      const double acc = (HALVES == 2 ? s.part[t] + s.part[kmax + t] : s.part[t]) - s.c[t];
       if (acc < -tol) {
         g = acc;
         gi = t;
@@ -321,19 +335,19 @@ __global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Ga
     }
     double gbest;
     int jbest;
-    block_argmin(s, g, gi, &gbest, &jbest);
+    block_argmin<NT>(s, g, gi, &gbest, &jbest);
     if (jbest == 0x7fffffff) break;
     if (t == 0) s.passive[jbest] = 1;
     __syncthreads();
     int inner = 0;
     for (; inner < cap; ++inner) {
-      const int n = build_passive(s, k);
+      const int n = build_passive<NT>(s, k);
       nP = n;
-      solve_passive(s, k, n);
+      solve_passive<NT>(s, k, n);
       ++solves;
       int bad = 0;
       double a = 1.0;
-      for (int q = t; q < n; q += kThreads) {
+      for (int q = t; q < n; q += NT) {
         const int i = s.P[q];
         if (!(s.z[i] > 0.0)) {
           bad = 1;
@@ -342,17 +356,17 @@ __global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Ga
         }
       }
       if (!__syncthreads_or(bad)) {
-        for (int i = t; i < k; i += kThreads) s.w[i] = s.z[i];
+        for (int i = t; i < k; i += NT) s.w[i] = s.z[i];
         __syncthreads();
         break;
       }
       double alpha;
       int unused;
-      block_argmin(s, a, 0, &alpha, &unused);
-      for (int i = t; i < k; i += kThreads) s.w[i] += alpha * (s.z[i] - s.w[i]);
+      block_argmin<NT>(s, a, 0, &alpha, &unused);
+      for (int i = t; i < k; i += NT) s.w[i] += alpha * (s.z[i] - s.w[i]);
       __syncthreads();
       int moved = 0;
-      for (int q = t; q < n; q += kThreads) {
+      for (int q = t; q < n; q += NT) {
         const int i = s.P[q];
         if (s.w[i] <= 1e-15 * fmax(1.0, fabs(s.z[i]))) {
           s.passive[i] = 0;
@@ -363,7 +377,7 @@ __global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Ga
       if (!__syncthreads_or(moved)) {  // numerically stuck: drop the most negative member
         double zv = INFINITY;
         int zi = 0x7fffffff;
-        for (int q = t; q < n; q += kThreads) {
+        for (int q = t; q < n; q += NT) {
           const int i = s.P[q];
           if (s.z[i] < zv || (s.z[i] == zv && i < zi)) {
             zv = s.z[i];
@@ -372,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Ga
         }
         double zmin;
         int worst;
-        block_argmin(s, zv, zi, &zmin, &worst);
+        block_argmin<NT>(s, zv, zi, &zmin, &worst);
         if (worst == 0x7fffffff) worst = s.P[0];  // every z was NaN
         if (t == 0) {
           s.passive[worst] = 0;
@@ -384,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void k_nnqp(const double* __restrict__ Ga
     if (inner == cap) capped = true;
   }
   if (outer == cap) capped = true;
-  for (int i = t; i < kmax; i += kThreads) W[i] = i < k ? s.w[i] : 0.0;
+  for (int i = t; i < kmax; i += NT) W[i] = i < k ? s.w[i] : 0.0;
   if (info && t == 0) info[p] = capped ? -solves : solves;
 }
 
@@ -403,11 +417,23 @@ extern "C" int sfw_nnqp_batch(const double* G, const double* c, const int* k, in
     if (!G || !c || !w) return fail(SFW_EINVAL, "G, c or w is NULL");
     const size_t bytes = lds_bytes(kmax);
     static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_nnqp), hipFuncAttributeMaxDynamicSharedMemorySize,
+        reinterpret_cast<const void*>(&k_nnqp<256>), hipFuncAttributeMaxDynamicSharedMemorySize,
         (int)lds_bytes(SFW_NNQP_MAX_K));
     if (attr != hipSuccess) return hip_fail(attr, "hipFuncSetAttribute(k_nnqp)");
-    hipLaunchKernelGGL(k_nnqp, dim3((unsigned)count), dim3(kThreads), bytes, stream, G, c, k,
-                       kmax, w, info);
+    static const hipError_t attr64 = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_nnqp<64>), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)lds_bytes(64));
+    if (attr64 != hipSuccess) return hip_fail(attr64, "hipFuncSetAttribute(k_nnqp)");
+    // one wave per problem where it is faster (measured, 4,096 problems: 99 against 265 us at 16
+    // atoms, 773 against 1,019 at 40, 1,177 against 1,068 at 50; one problem alone: four waves
+    // from 24 atoms on)
+    const bool one_wave = kmax <= 16 || (kmax <= 40 && count >= 256);
+    if (one_wave)
+      hipLaunchKernelGGL(k_nnqp<64>, dim3((unsigned)count), dim3(64), bytes, stream, G, c, k,
+                         kmax, w, info);
+    else
+      hipLaunchKernelGGL(k_nnqp<256>, dim3((unsigned)count), dim3(256), bytes, stream, G, c, k,
+                         kmax, w, info);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_nnqp");
     return SFW_OK;

@@ -1,5 +1,6 @@
 """GPU parity of the batched weights QP (sfw_nnqp_batch) with the oracle's (oracle.nnqp).
 
+Both kernels run: one wave per problem (small problems in large batches) and four.
 Bars: w within 1e-9 (relative L2) of the oracle's (the problems' Gram matrices have condition
 numbers up to about 1e3, so two float64 solvers agree to about 1e-13); the objective within
 1e-12 (relative); the KKT conditions to 1e-9 of max |c|. The active-set path and the NNLS the
@@ -146,14 +147,15 @@ def test_duplicated_column(L):
     check_kkt(G, c, w[0], tol=1e-7)
 
 
-def test_large_batch_in_one_launch(L):
-    """4096 problems of 50 atoms (more workgroups than the chip holds at once) against the
-    oracle on a sample."""
-    rng = np.random.default_rng(4500)
-    base = [random_problem(rng, 50) for _ in range(16)]
+@pytest.mark.parametrize("k", [32, 50])
+def test_large_batch_in_one_launch(L, k):
+    """4096 problems of 32 atoms (one wave per problem) and of 50 (four waves), more workgroups
+    than the chip holds at once, against the oracle on a sample."""
+    rng = np.random.default_rng(4500 + k)
+    base = [random_problem(rng, k) for _ in range(16)]
     problems = [base[i % 16] for i in range(4096)]
-    say("sfw_nnqp_batch 4096 x 50")
-    w, info = run(L, problems, 50, with_k=False)
+    say("sfw_nnqp_batch 4096 x", k)
+    w, info = run(L, problems, k, with_k=False)
     for i in range(16):
         want = oracle.nnqp(*base[i])
         for p in (i, i + 16 * 100, i + 16 * 255):
