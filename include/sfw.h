@@ -272,10 +272,12 @@ int sfw_eta_points_noalloc(sfw_dims vol, const float* q, float lambda, const flo
  * sfw_profile_begin and sfw_profile_end. Classes: "prep", "render", "conv_residual",
  * "conv_adjoint", "conv_forward", "grad", "grad_finalize", "cert_conv", "cert_argmax",
  * "lasso_render", "lasso_conv", "lasso_dots", "hash", "eta_grad", "cert_fft" (the
- * certificate's transforms except the inverse z pass), "cert_zinv" (that pass, timed by its
- * kernel's own start and stop events, so without the dispatch latency). Each other timed
- * launch group costs an event pair on the stream (a few microseconds of device idle), so
- * time only the classes of interest when the surrounding throughput matters. */
+ * certificate's transforms except the inverse z pass), "cert_zinv" (that pass). A class that
+ * covers one kernel ("render", "grad", "grad_finalize", "eta_grad" at up to 8 points,
+ * "lasso_conv" for box columns, "cert_argmax", "cert_zinv") is timed by that kernel's own start
+ * and stop events, so without the dispatch latency; each other timed launch group costs an
+ * event pair on the stream (a few microseconds of device idle), so time only the classes of
+ * interest when the surrounding throughput matters. */
 #define SFW_PROF_KINDS 16
 typedef struct { char name[24]; int32_t launches; double ms; } sfw_prof_entry;
 

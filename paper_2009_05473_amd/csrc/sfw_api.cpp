@@ -191,8 +191,8 @@ int conv_direct(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, bool a
 
 int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, float* phi) {
   {
-    ProfScope ps(ws, kProfRender);
-    SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream));
+    ProfScope ps(ws, kProfRender, true);
+    SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream, kRenderVPT, ps.events()));
   }
   return conv_psf(ws, p, vol, false, ws->f, phi, kEpiPlain, nullptr, kProfConvForward);
 }
@@ -202,8 +202,8 @@ int op_forward(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, int n, 
 static int cgrad_chain(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float* y,
                        int n, float* r, const sfw_workspace::TuneChoice& shape) {
   {
-    ProfScope ps(ws, kProfRender);
-    SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream, shape.render_vpt));
+    ProfScope ps(ws, kProfRender, true);
+    SFW_HIP(launch_render(ws->ak, n, vol, ws->f, ws->stream, shape.render_vpt, ps.events()));
   }
   if (p.fft && p.blur.chain) {
     // residual and adjoint share the plane pass between them (see launch_blur_residual_chain)
@@ -221,9 +221,9 @@ static int cgrad_chain(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol,
     rc = conv_psf(ws, p, vol, true, r, ws->q, kEpiPlain, nullptr, kProfConvAdjoint);
     if (rc) return rc;
   }
-  ProfScope ps(ws, kProfGrad);
+  ProfScope ps(ws, kProfGrad, true);
   SFW_HIP(launch_grad_items(ws->ak, n, ws->q, vol, ws->gpart, ws->gitem, shape.grad_blocks,
-                            ws->stream));
+                            ws->stream, ps.events()));
   return SFW_OK;
 }
 
@@ -362,12 +362,12 @@ int op_cgrad(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
   rc = cgrad_enqueue(ws, p, vol, y, n, r, shape);
   if (rc) return rc;
   ws->q_valid = true;
-  ProfScope ps(ws, kProfGradFinalize);
+  ProfScope ps(ws, kProfGradFinalize, true);
   // sums for the host: the finalize kernel signals them (ws->sums_sig)
   ws->sums_sig = sums ? sig_arm(ws) : kNoSig;
   SFW_HIP(launch_grad_finalize(ws->gpart, 0, ws->gitem, n, ws->dpart, p.nres, atoms_dev, lambda,
                                sums ? sums : ws->dres, grad_out, loss_out, ws->stream, false,
-                               ws->sums_sig));
+                               ws->sums_sig, ps.events()));
   return SFW_OK;
 }
 
@@ -380,13 +380,13 @@ int op_vjp(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const float
   if ((size_t)grad_item_tiles(vol) * n * 6 > ws->gpart_cap)
     return fail(SFW_EINVAL, "gradient partial buffer too small");
   {
-    ProfScope ps(ws, kProfGrad);
+    ProfScope ps(ws, kProfGrad, true);
     SFW_HIP(launch_grad_items(ws->ak, n, ws->q, vol, ws->gpart, ws->gitem,
-                              sfw_workspace::TuneChoice().grad_blocks, ws->stream));
+                              sfw_workspace::TuneChoice().grad_blocks, ws->stream, ps.events()));
   }
-  ProfScope ps(ws, kProfGradFinalize);
+  ProfScope ps(ws, kProfGradFinalize, true);
   SFW_HIP(launch_grad_finalize(ws->gpart, 0, ws->gitem, n, nullptr, 0, atoms_dev, 0.f, ws->dres,
-                               grad_out, nullptr, ws->stream, true));
+                               grad_out, nullptr, ws->stream, true, kNoSig, ps.events()));
   return SFW_OK;
 }
 
@@ -432,11 +432,11 @@ int op_eta_points(sfw_workspace* ws, const sfw_dims& vol, const float* q, double
   double* hs = ws->hpin + ws->hp_sums;
   SigArgs sig = kNoSig;
   {
-    ProfScope ps(ws, kProfEtaGrad);
+    ProfScope ps(ws, kProfEtaGrad, one_launch);  // one kernel: timed by its own events
     if (one_launch) {
       sig = sig_arm(ws);
       SFW_HIP(launch_grad_points(gp, hk, n, q, vol, ws->gpart, ws->eta_ticket, hs, sig,
-                                 ws->stream));
+                                 ws->stream, ps.events()));
     } else {
       SFW_HIP(launch_grad_items(ws->ak, n, q, vol, ws->gpart, ws->gitem,
                                 sfw_workspace::TuneChoice().grad_blocks, ws->stream));
@@ -594,10 +594,10 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
       SFW_HIP(fft_inverse_pairs_yx(pl, ws->fft_work, ws->fft_cap, ns * nd, vol, 1.0f / lambda,
                                    eta_out, ws->apart, nblk, ws->stream));
     }
-    ProfScope ps(ws, kProfCertArgmax);
+    ProfScope ps(ws, kProfCertArgmax, true);
     ws->cert_sig = sig_arm(ws);
     SFW_HIP(launch_argmax_final(ws->apart, nblk * ns * nd, vol, nd, ws->best, pinned_best(ws),
-                                ws->cert_sig, ws->stream));
+                                ws->cert_sig, ws->stream, ps.events()));
     return SFW_OK;
   }
   int nb = 0;
@@ -615,10 +615,10 @@ int op_certificate(sfw_workspace* ws, const sfw_dims& vol, const float* q, float
                           1.0f / lambda, (long long)s * (long long)V, ws->apart + (size_t)s * nb,
                           ws->stream));
     }
-  ProfScope ps(ws, kProfCertArgmax);
+  ProfScope ps(ws, kProfCertArgmax, true);
   ws->cert_sig = sig_arm(ws);
   SFW_HIP(launch_argmax_final(ws->apart, nb * ns * nd, vol, nd, ws->best, pinned_best(ws),
-                              ws->cert_sig, ws->stream));
+                              ws->cert_sig, ws->stream, ps.events()));
   return SFW_OK;
 }
 
@@ -860,8 +860,9 @@ int op_lasso(sfw_workspace* ws, const PsfPlan& p, const sfw_dims& vol, const flo
     std::vector<ColumnBoxJob> jobs;
     auto flush = [&]() -> int {
       if (jobs.empty()) return SFW_OK;
-      ProfScope ps(ws, kProfLassoConv);
-      SFW_HIP(launch_column_boxes(jobs.data(), (int)jobs.size(), H, p.psf, vol, ws->stream));
+      ProfScope ps(ws, kProfLassoConv, true);
+      SFW_HIP(launch_column_boxes(jobs.data(), (int)jobs.size(), H, p.psf, vol, ws->stream,
+                                  ps.events()));
       jobs.clear();
       return SFW_OK;
     };

@@ -297,6 +297,29 @@ inline sfw_argmax* pinned_best(sfw_workspace* ws) {
 
 namespace sfw {
 // Records a start event on construction and a stop event on destruction when profiling is on.
+// Optional start and stop events of one kernel launch: a profiling class that covers a single
+// kernel hands them to the launch, which has them stamped with the kernel's own start and end
+// (hipExtLaunchKernelGGL, from <hip/hip_ext.h>, which the HIP sources that expand SFW_LAUNCH
+// include); without them the launch is an ordinary one (graph capture included).
+struct KernelEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+#define SFW_LAUNCH(ev, kernel, grid, block, lds, st, ...)                                   \
+  do {                                                                                       \
+    if ((ev).start || (ev).stop)                                                             \
+      hipExtLaunchKernelGGL(kernel, grid, block, lds, st, (ev).start, (ev).stop, 0,          \
+                            __VA_ARGS__);                                                    \
+    else                                                                                     \
+      hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);                         \
+  } while (0)
+// For a launcher that has nothing to launch: records the events, so that they stay valid.
+inline hipError_t record_events(const KernelEvents& ev, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (ev.start) e = hipEventRecord(ev.start, st);
+  if (e == hipSuccess && ev.stop) e = hipEventRecord(ev.stop, st);
+  return e;
+}
+
 struct ProfScope {
   sfw_workspace* ws;
   int slot = -1;
@@ -318,6 +341,7 @@ struct ProfScope {
   }
   hipEvent_t start() const { return slot >= 0 && at_kernel ? ws->prof_start[slot] : nullptr; }
   hipEvent_t stop() const { return slot >= 0 && at_kernel ? ws->prof_stop[slot] : nullptr; }
+  KernelEvents events() const { return KernelEvents{start(), stop()}; }
   ~ProfScope() {
     if (slot >= 0 && !at_kernel) (void)hipEventRecord(ws->prof_stop[slot], ws->stream);
   }
@@ -370,7 +394,7 @@ hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t
 // to the atom centres from its own coordinates and sums its nonzero atoms in index order,
 // whatever the tile).
 hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st,
-                         int vpt = kRenderVPT);
+                         int vpt = kRenderVPT, const KernelEvents& ev = {});
 
 enum ConvEpilogue { kEpiPlain = 0, kEpiResidual = 1, kEpiArgmax = 2, kEpiColumn = 3 };
 // out = conv(in, W) with W in [ky][kx][kzp] layout (already flipped for a correlation).
@@ -418,21 +442,22 @@ struct ColumnBoxJob {
   int box[6];
 };
 hipError_t launch_column_boxes(const ColumnBoxJob* jobs, int n, const float* H, sfw_dims psf,
-                               sfw_dims vol, hipStream_t st);
+                               sfw_dims vol, hipStream_t st, const KernelEvents& ev = {});
 
 // The per-atom sums of at most kAtomArgs atoms given by their constants on the host, reduced
 // to sums_out[6 a + c] (float64; may be host memory) by the last block; ticket: device int that
 // is 0 between launches.
 hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n, const float* q,
                               sfw_dims vol, float* gpart, int* ticket, double* sums_out,
-                              const SigArgs& sig, hipStream_t st);
+                              const SigArgs& sig, hipStream_t st, const KernelEvents& ev = {});
 // The gradient sums of the atoms ak[0, n) against q, one partial per item (an atom on one of
 // the 16 x 16 x 16 volume tiles its cut ball may reach) at gpart[6 i + c]; atom a's items are
 // item_start[a] .. item_start[a + 1] - 1 (device, n + 1 ints, written by the kernel). At most
 // n * grad_item_tiles(vol) items. `blocks` (grid size) changes no result.
 int grad_item_tiles(sfw_dims vol);
 hipError_t launch_grad_items(const AtomK* ak, int n, const float* q, sfw_dims vol, float* gpart,
-                             int* item_start, int blocks, hipStream_t st);
+                             int* item_start, int blocks, hipStream_t st,
+                             const KernelEvents& ev = {});
 // Sums partials in a fixed order (float64): over the ntiles tiles of the tile layout
 // (launch_grad_points), or over the atom's items when item_start is given (launch_grad_items).
 // For atom a:
@@ -446,11 +471,11 @@ hipError_t launch_grad_finalize(const float* gpart, int ntiles, const int* item_
                                 const double* loss_part, int nloss, const sfw_atom* atoms,
                                 float lambda, double* sums, sfw_atom* grad_out, double* loss_out,
                                 hipStream_t st, bool vjp = false,
-                                const SigArgs& sig = kNoSig);
+                                const SigArgs& sig = kNoSig, const KernelEvents& ev = {});
 // The maximum goes to best (device) and, when best_host is not null, to pinned host memory.
 hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
                                sfw_argmax* best, sfw_argmax* best_host, const SigArgs& sig,
-                               hipStream_t st);
+                               hipStream_t st, const KernelEvents& ev = {});
 // out[c] = sum_v a[v] * cols[c][v] for c < k, out[k] = sum_v a[v] * y[v] (float64).
 // dots of column a (valid on abox) with the k columns cols + slot(c) * colstride (each valid
 // on its box slot_box[6 slot(c)...], device) and with y (out[k]), a product counting only

@@ -7,6 +7,7 @@
 // atom sums, LDS-staged input tiles with register blocking along z for the direct
 // convolutions (the blur's second and third paths), and wavefront DPP reductions for the
 // per-atom gradient sums.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -1493,18 +1494,19 @@ hipError_t launch_fingerprints(const float* y, size_t ny, const float* H, size_t
   return hipGetLastError();
 }
 
-hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st, int vpt) {
+hipError_t launch_render(const AtomK* ak, int n, sfw_dims vol, float* f, hipStream_t st, int vpt,
+                         const KernelEvents& ev) {
   const int tiles = ((vol.nx + kTile - 1) / kTile) * ((vol.ny + kTile - 1) / kTile);
   dim3 grid(tiles, (vol.nz + vpt - 1) / vpt);
   switch (vpt) {
     case 4:
-      hipLaunchKernelGGL(k_render<4>, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
+      SFW_LAUNCH(ev, k_render<4>, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
       break;
     case 8:
-      hipLaunchKernelGGL(k_render<8>, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
+      SFW_LAUNCH(ev, k_render<8>, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
       break;
     case 16:
-      hipLaunchKernelGGL(k_render<16>, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
+      SFW_LAUNCH(ev, k_render<16>, grid, dim3(256), 0, st, ak, n, vol.nx, vol.ny, vol.nz, f);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1799,7 +1801,7 @@ bool column_box_ok(sfw_dims psf) {
 }
 
 hipError_t launch_column_boxes(const ColumnBoxJob* jobs, int n, const float* H, sfw_dims psf,
-                               sfw_dims vol, hipStream_t st) {
+                               sfw_dims vol, hipStream_t st, const KernelEvents& ev) {
   if (!column_box_ok(psf) || n < 0 || n > kBoxColumns) return hipErrorInvalidValue;
   BoxColumns bc;
   std::memset(&bc, 0, sizeof(bc));
@@ -1814,7 +1816,7 @@ hipError_t launch_column_boxes(const ColumnBoxJob* jobs, int n, const float* H, 
                            box[1], box[3], box[5], gx, gy, blocks};
     blocks += gx * gy * gz;
   }
-  if (nc == 0) return hipSuccess;
+  if (nc == 0) return record_events(ev, st);
   const dim3 grid(blocks);
   const bool hlds = column_box_lds_h(psf) <= (size_t)kColumnBoxMaxLds;
   const size_t lds = hlds ? column_box_lds_h(psf) : column_box_lds(psf);
@@ -1830,11 +1832,11 @@ hipError_t launch_column_boxes(const ColumnBoxJob* jobs, int n, const float* H, 
     if (attr != hipSuccess) return attr;                                                       \
     if (attr2 != hipSuccess) return attr2;                                                     \
     if (hlds)                                                                                  \
-      hipLaunchKernelGGL((k_column_box<P, true>), grid, dim3(64 * column_box_waves(psf)), lds, \
-                         st, bc, nc, H, psf.nx, psf.ny, vol.nx, vol.ny, vol.nz);               \
+      SFW_LAUNCH(ev, (k_column_box<P, true>), grid, dim3(64 * column_box_waves(psf)), lds, st, \
+                 bc, nc, H, psf.nx, psf.ny, vol.nx, vol.ny, vol.nz);                           \
     else                                                                                       \
-      hipLaunchKernelGGL((k_column_box<P, false>), grid, dim3(64 * column_box_waves(psf)),     \
-                         lds, st, bc, nc, H, psf.nx, psf.ny, vol.nx, vol.ny, vol.nz);          \
+      SFW_LAUNCH(ev, (k_column_box<P, false>), grid, dim3(64 * column_box_waves(psf)), lds,    \
+                 st, bc, nc, H, psf.nx, psf.ny, vol.nx, vol.ny, vol.nz);                       \
     return hipGetLastError();                                                                  \
   }
     SFW_BOX_CASE(1) SFW_BOX_CASE(3) SFW_BOX_CASE(5) SFW_BOX_CASE(7) SFW_BOX_CASE(9)
@@ -1871,20 +1873,21 @@ int grad_item_tiles(sfw_dims vol) {
 }
 
 hipError_t launch_grad_items(const AtomK* ak, int n, const float* q, sfw_dims vol, float* gpart,
-                             int* item_start, int blocks, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
+                             int* item_start, int blocks, hipStream_t st,
+                             const KernelEvents& ev) {
+  if (n <= 0) return record_events(ev, st);
   if (blocks < 1) return hipErrorInvalidValue;
   size_t lds = ((size_t)(n + 1) * sizeof(int) + 15) / 16 * 16;
   if (n <= kItemsLdsAtoms) lds += (size_t)n * (sizeof(AtomK) + sizeof(ItemBox));
   if (lds > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_grad_items, dim3(blocks), dim3(kGradThreads), lds, st, ak, n, q, vol.nx,
-                     vol.ny, vol.nz, gpart, item_start);
+  SFW_LAUNCH(ev, k_grad_items, dim3(blocks), dim3(kGradThreads), lds, st, ak, n, q, vol.nx,
+             vol.ny, vol.nz, gpart, item_start);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n, const float* q,
                               sfw_dims vol, float* gpart, int* ticket, double* sums_out,
-                              const SigArgs& sig, hipStream_t st) {
+                              const SigArgs& sig, hipStream_t st, const KernelEvents& ev) {
   if (n <= 0 || n > kAtomArgs) return hipErrorInvalidValue;
   AtomArgs args;
   std::memset(&args, 0, sizeof(args));
@@ -1893,9 +1896,9 @@ hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n,
   switch (p.vpt) {
 #define SFW_GRAD_CASE(V)                                                                       \
   case V:                                                                                      \
-    hipLaunchKernelGGL((k_grad_points<V>), grid, dim3(kGradThreads), 0, st, args, n, q, vol.nx, \
-                       vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart, ticket,  \
-                       sums_out, sig);                                                          \
+    SFW_LAUNCH(ev, (k_grad_points<V>), grid, dim3(kGradThreads), 0, st, args, n, q, vol.nx,     \
+               vol.ny, vol.nz, p.ntile_xy, p.rx0, p.ry0, p.rtx, p.rz0, gpart, ticket, sums_out, \
+               sig);                                                                            \
     break;
     SFW_GRAD_CASE(64)
     SFW_GRAD_CASE(32)
@@ -1910,17 +1913,18 @@ hipError_t launch_grad_points(const GradPlan& p, const AtomK* host_atoms, int n,
 hipError_t launch_grad_finalize(const float* gpart, int ntiles, const int* item_start, int n,
                                 const double* loss_part, int nloss, const sfw_atom* atoms,
                                 float lambda, double* sums, sfw_atom* grad_out, double* loss_out,
-                                hipStream_t st, bool vjp, const SigArgs& sig) {
-  hipLaunchKernelGGL(k_grad_finalize, dim3(n + 1), dim3(256), 0, st, gpart, ntiles, item_start, n,
-                     loss_part, nloss, atoms, lambda, sums, grad_out, loss_out, vjp ? 1 : 0, sig);
+                                hipStream_t st, bool vjp, const SigArgs& sig,
+                                const KernelEvents& ev) {
+  SFW_LAUNCH(ev, k_grad_finalize, dim3(n + 1), dim3(256), 0, st, gpart, ntiles, item_start, n,
+             loss_part, nloss, atoms, lambda, sums, grad_out, loss_out, vjp ? 1 : 0, sig);
   return hipGetLastError();
 }
 
 hipError_t launch_argmax_final(const ArgPart* apart, int nparts, sfw_dims vol, int nd,
                                sfw_argmax* best, sfw_argmax* best_host, const SigArgs& sig,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, st, apart, nparts, vol.nx, vol.ny,
-                     vol.nz, nd, best, best_host, sig);
+                               hipStream_t st, const KernelEvents& ev) {
+  SFW_LAUNCH(ev, k_argmax_final, dim3(1), dim3(1024), 0, st, apart, nparts, vol.nx, vol.ny,
+             vol.nz, nd, best, best_host, sig);
   return hipGetLastError();
 }
 
